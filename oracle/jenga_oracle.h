@@ -1,0 +1,125 @@
+/*
+ * FP64 CPU oracle for batched stepping of towers of oriented boxes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The product path (the HIP
+ * library) never links, includes or calls it, and shares no code with it.
+ *
+ * Everything is double precision and single threaded per tower.  A "tower" is an
+ * independent world: bodies indexed 0..nb-1, plus a static ground half-space z <= 0.
+ * Arrays are row-major: vec3 arrays are [nb][3], quaternions [nb][4] as [w,x,y,z].
+ */
+#ifndef JENGA_ORACLE_H
+#define JENGA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double gravity[3];     /* m/s^2, (0,0,-9.81) (Sec. Equations of Motion) */
+  double dt;             /* step length, 1/240 s */
+  double restitution;    /* e in Eq. (lambda_n), 0.10 */
+  double beta;           /* Baumgarte factor, Eq. (baumgarte), 0.35 */
+  double slop;           /* Baumgarte slop, 0.4 mm */
+  double margin;         /* AABB margin epsilon, Eq. (aabb), 2 mm */
+  int32_t n_sub;         /* substeps per step (each runs the whole pipeline with dt/n_sub) */
+  int32_t iters;         /* PGS iterations */
+  int32_t warm_start;    /* 0: zero initial impulses, 1: previous step's impulses by key */
+  int32_t _pad;
+} or_params;
+
+typedef struct {
+  int32_t body;          /* tower-local body index */
+  int32_t start;         /* first step on which the force acts */
+  int32_t steps;         /* number of steps it acts */
+  int32_t _pad;
+  double force[3];       /* world-frame force at the centre of mass [N] */
+  double withdraw;       /* displacement along the force that deactivates the body; 0 = never */
+  double x0[3];          /* position at the start of the push (written by the oracle) */
+} or_push;
+
+/* One contact manifold (a colliding pair) with up to four points. */
+typedef struct {
+  int32_t a, b;          /* bodies; b = -1 is the ground (then the normal is -z) */
+  int32_t colour, npts;
+  int32_t axis;          /* SAT axis 0..14 (A0..A2, B0..B2, Ai x Bj row-major); -1 for ground */
+  int32_t band;          /* precision-band flags (OR_BAND_*) */
+  int32_t slot[4];       /* diagonal slot 0..3 (box pairs) or vertex index 0..7 (ground) */
+  double normal[3], t1[3], t2[3];   /* normal points from a to b */
+  double depth;          /* penetration used by the position correction */
+  double sigma;          /* SAT separation -min_u delta_u (negative when overlapping) */
+  double point[4][3];    /* world contact points */
+  double lam[4][3];      /* accumulated impulses (normal, t1, t2) after the solve */
+  double k[4][3];        /* inverse effective masses (normal, t1, t2) */
+} or_manifold;
+
+enum {
+  OR_BAND_SEPARATION = 1,   /* |sigma| < 1e-6 m: the collide decision is precision sensitive */
+  OR_BAND_NORMAL = 2,       /* two best non-parallel axes within 1e-6 m */
+  OR_BAND_CROSS = 4,        /* a cross axis with |a x b| within 10% of the skip threshold */
+  OR_BAND_CLIP = 8,         /* a slot extreme tied within 1e-6 m, or a merge within 10% of 1e-6 m */
+  OR_BAND_GROUND = 16,      /* a vertex within 1e-6 m of the ground plane, or a depth tie at the cut */
+  OR_BAND_EMPTY = 32        /* empty clip: the single support-midpoint fallback was used */
+};
+
+typedef struct {
+  int64_t steps;
+  int64_t candidates;      /* broadphase candidates, summed over steps */
+  int64_t manifolds;       /* colliding pairs, summed over steps */
+  int64_t points;          /* contact points, summed over steps */
+  int64_t contact_iters;   /* points x iterations, summed over steps */
+  int32_t colours;         /* colours used in the last step */
+  int32_t error;           /* 1: colour cap exceeded (manifold dropped); 2: manifold capacity */
+  double res_rms;          /* natural-map residual of the last solve, RMS over rows [m/s] */
+  double res_max;          /* ... and max |r| */
+} or_stats;
+
+typedef struct {
+  int32_t collide, axis, band, _pad;
+  double depth, sigma;
+  double normal[3];
+} or_sat_result;
+
+/* Eq. (rotmat): rotation matrix of a unit quaternion [w,x,y,z]; R row-major. */
+void or_quat_to_rot(const double q[4], double R[9]);
+/* Eq. (inertia): diagonal body inertia of a uniform box of mass m and half extents he. */
+void or_box_inertia(double m, const double he[3], double I[3]);
+/* Sec. "Narrowphase: OBB SAT": 15-axis test of boxes A and B. */
+void or_sat(const double heA[3], const double xA[3], const double qA[4],
+            const double heB[3], const double xB[3], const double qB[4], or_sat_result* out);
+/* Sec. "Contact Manifold (Face Clipping)": manifold of a colliding box pair (normal from A to B). */
+int or_manifold_box(const double heA[3], const double xA[3], const double qA[4],
+                    const double heB[3], const double xB[3], const double qB[4],
+                    const double normal[3], double depth, or_manifold* out);
+/* Box against the ground half-space z <= 0; returns 1 if it collides. */
+int or_manifold_ground(const double he[3], const double x[3], const double q[4], or_manifold* out);
+
+/* Sec. "Contact Solver": PGS on explicit manifolds, processed in array order.
+ * Bodies: inverse mass, world inverse inertia (row-major 3x3), position, velocities (updated).
+ * Manifolds must have a, b, npts, normal, t1, t2, point set; lam holds the initial
+ * impulses (already applied to v, w by the caller if nonzero) and receives the result.
+ * Writes k.  Returns the residual (RMS and max) through res[2]. */
+void or_pgs(int nb, const double* invm, const double* Iinv, const double* x, double* v, double* w,
+            int nm, or_manifold* m, double mu, double restitution, int iters, double res[2]);
+
+/* Step one tower n_steps times (state arrays updated in place).
+ * prev/nprev: previous step's manifolds for the warm start (may be NULL/0).
+ * mout/mcap/nm_out: manifolds of the last substep, in colour-sorted processing order.
+ * step_counter: global step number of the first step (incremented by n_steps). */
+int or_step_tower(const or_params* p, int nb, const double* he, const double* mass,
+                  double* x, double* q, double* v, double* w, uint8_t* active,
+                  double mu, int npush, or_push* push, int64_t* step_counter, int n_steps,
+                  const or_manifold* prev, int nprev,
+                  or_manifold* mout, int mcap, int* nm_out, or_stats* st);
+
+/* Broadphase candidates of one tower (pairs a<b, b = -1 ground), canonical order. */
+int or_broadphase(int nb, const double* he, const double* mass, const double* x, const double* q,
+                  const uint8_t* active, double margin, int32_t* pairs, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

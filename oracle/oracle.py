@@ -1,0 +1,272 @@
+"""ctypes wrapper of the FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it.  The product path never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("JENGA_ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
+SRC = os.path.join(HERE, "jenga_oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, -O2, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                               "-fno-fast-math", "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [("gravity", C.c_double * 3), ("dt", C.c_double), ("restitution", C.c_double),
+                ("beta", C.c_double), ("slop", C.c_double), ("margin", C.c_double),
+                ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("_pad", C.c_int32)]
+
+
+class Push(C.Structure):
+    _fields_ = [("body", C.c_int32), ("start", C.c_int32), ("steps", C.c_int32), ("_pad", C.c_int32),
+                ("force", C.c_double * 3), ("withdraw", C.c_double), ("x0", C.c_double * 3)]
+
+
+class Manifold(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("colour", C.c_int32), ("npts", C.c_int32),
+                ("axis", C.c_int32), ("band", C.c_int32), ("slot", C.c_int32 * 4),
+                ("normal", C.c_double * 3), ("t1", C.c_double * 3), ("t2", C.c_double * 3),
+                ("depth", C.c_double), ("sigma", C.c_double),
+                ("point", (C.c_double * 3) * 4), ("lam", (C.c_double * 3) * 4), ("k", (C.c_double * 3) * 4)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("candidates", C.c_int64), ("manifolds", C.c_int64),
+                ("points", C.c_int64), ("contact_iters", C.c_int64), ("colours", C.c_int32),
+                ("error", C.c_int32), ("res_rms", C.c_double), ("res_max", C.c_double)]
+
+
+class SatResult(C.Structure):
+    _fields_ = [("collide", C.c_int32), ("axis", C.c_int32), ("band", C.c_int32), ("_pad", C.c_int32),
+                ("depth", C.c_double), ("sigma", C.c_double), ("normal", C.c_double * 3)]
+
+
+BAND_SEPARATION, BAND_NORMAL, BAND_CROSS, BAND_CLIP, BAND_GROUND, BAND_EMPTY = 1, 2, 4, 8, 16, 32
+
+_lib = None
+_lock = threading.Lock()
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                build()
+            L = C.CDLL(LIB_PATH)
+            L.or_quat_to_rot.argtypes = [_dp, _dp]
+            L.or_box_inertia.argtypes = [C.c_double, _dp, _dp]
+            L.or_sat.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.POINTER(SatResult)]
+            L.or_manifold_box.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.POINTER(Manifold)]
+            L.or_manifold_box.restype = C.c_int
+            L.or_manifold_ground.argtypes = [_dp, _dp, _dp, C.POINTER(Manifold)]
+            L.or_manifold_ground.restype = C.c_int
+            L.or_pgs.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_int, C.POINTER(Manifold), C.c_double,
+                                 C.c_double, C.c_int, _dp]
+            L.or_step_tower.argtypes = [C.POINTER(Params), C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _u8p, C.c_double,
+                                        C.c_int, C.POINTER(Push), C.POINTER(C.c_int64), C.c_int,
+                                        C.POINTER(Manifold), C.c_int, C.POINTER(Manifold), C.c_int,
+                                        C.POINTER(C.c_int), C.POINTER(Stats)]
+            L.or_step_tower.restype = C.c_int
+            L.or_broadphase.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _u8p, C.c_double, _i32p, C.c_int]
+            L.or_broadphase.restype = C.c_int
+            _lib = L
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a.reshape(shape) if shape is not None else a
+
+
+def make_params(p: dict, warm_start: int = 0) -> Params:
+    P = Params()
+    P.gravity[:] = [float(g) for g in p["gravity"]]
+    P.dt = float(p["dt"])
+    P.restitution = float(p["restitution"])
+    P.beta = float(p["beta"])
+    P.slop = float(p["slop"])
+    P.margin = float(p["margin"])
+    P.n_sub = int(p["n_sub"])
+    P.iters = int(p["iters"])
+    P.warm_start = int(warm_start)
+    return P
+
+
+# ---------------------------------------------------------------------------------------------
+# stage functions
+# ---------------------------------------------------------------------------------------------
+
+def quat_to_rot(q) -> np.ndarray:
+    R = np.zeros(9)
+    lib().or_quat_to_rot(_f64(q, 4), R)
+    return R.reshape(3, 3)
+
+
+def box_inertia(m, he) -> np.ndarray:
+    I = np.zeros(3)
+    lib().or_box_inertia(float(m), _f64(he, 3), I)
+    return I
+
+
+def sat(heA, xA, qA, heB, xB, qB) -> SatResult:
+    r = SatResult()
+    lib().or_sat(_f64(heA, 3), _f64(xA, 3), _f64(qA, 4), _f64(heB, 3), _f64(xB, 3), _f64(qB, 4), C.byref(r))
+    return r
+
+
+def manifold_box(heA, xA, qA, heB, xB, qB, normal, depth) -> Manifold:
+    m = Manifold()
+    lib().or_manifold_box(_f64(heA, 3), _f64(xA, 3), _f64(qA, 4), _f64(heB, 3), _f64(xB, 3), _f64(qB, 4),
+                          _f64(normal, 3), float(depth), C.byref(m))
+    return m
+
+
+def manifold_ground(he, x, q):
+    m = Manifold()
+    hit = lib().or_manifold_ground(_f64(he, 3), _f64(x, 3), _f64(q, 4), C.byref(m))
+    return m if hit else None
+
+
+def pgs(invm, Iinv, x, v, w, manifolds, mu, restitution, iters):
+    """PGS on explicit manifolds (processed in list order). Returns (v, w, manifolds, residual)."""
+    nb = len(invm)
+    v = _f64(v, (nb, 3)).copy()
+    w = _f64(w, (nb, 3)).copy()
+    arr = (Manifold * max(1, len(manifolds)))()
+    for i, m in enumerate(manifolds):
+        arr[i] = m
+    res = np.zeros(2)
+    lib().or_pgs(nb, _f64(invm, nb), _f64(Iinv, (nb, 9)), _f64(x, (nb, 3)), v, w, len(manifolds), arr,
+                 float(mu), float(restitution), int(iters), res)
+    return v, w, [arr[i] for i in range(len(manifolds))], res
+
+
+def broadphase(he, mass, x, q, active, margin):
+    nb = len(mass)
+    cap = nb * (nb + 1) // 2 + 1
+    pairs = np.zeros(2 * cap, np.int32)
+    n = lib().or_broadphase(nb, _f64(he, (nb, 3)), _f64(mass, nb), _f64(x, (nb, 3)), _f64(q, (nb, 4)),
+                            np.ascontiguousarray(active, np.uint8), float(margin), pairs, cap)
+    return pairs[:2 * n].reshape(n, 2)
+
+
+def manifold_dict(m: Manifold) -> dict:
+    n = m.npts
+    return dict(a=m.a, b=m.b, colour=m.colour, npts=n, axis=m.axis, band=m.band,
+                slot=np.array(m.slot[:n], np.int32),
+                normal=np.array(m.normal[:]), t1=np.array(m.t1[:]), t2=np.array(m.t2[:]),
+                depth=m.depth, sigma=m.sigma,
+                point=np.array([m.point[i][:] for i in range(n)]).reshape(n, 3),
+                lam=np.array([m.lam[i][:] for i in range(n)]).reshape(n, 3),
+                k=np.array([m.k[i][:] for i in range(n)]).reshape(n, 3))
+
+
+# ---------------------------------------------------------------------------------------------
+# scene stepping
+# ---------------------------------------------------------------------------------------------
+
+class OracleWorld:
+    """All towers of a scene, stepped tower by tower in FP64."""
+
+    def __init__(self, scene: dict, warm_start: int = 0, params: dict | None = None):
+        self.scene = scene
+        self.params = make_params(params or scene["params"], warm_start)
+        self.ptr = np.asarray(scene["tower_ptr"], np.int64)
+        self.T = int(scene["n_towers"])
+        self.he = _f64(scene["half_extents"]).reshape(-1, 3).copy()
+        self.mass = _f64(scene["mass"]).copy()
+        self.x = _f64(scene["pos"]).reshape(-1, 3).copy()
+        self.q = _f64(scene["quat"]).reshape(-1, 4).copy()
+        self.v = _f64(scene["linvel"]).reshape(-1, 3).copy()
+        self.w = _f64(scene["angvel"]).reshape(-1, 3).copy()
+        self.active = np.ascontiguousarray(scene["active"], np.uint8).copy()
+        self.mu = _f64(scene["mu"]).copy()
+        self.step_counter = [C.c_int64(0) for _ in range(self.T)]
+        self.stats = [Stats() for _ in range(self.T)]
+        self.contacts = [None] * self.T
+        self.ncontacts = [0] * self.T
+        self.pushes = [[] for _ in range(self.T)]
+        tower = np.repeat(np.arange(self.T), np.diff(self.ptr))
+        for i in range(len(scene["push_body"])):
+            b = int(scene["push_body"][i])
+            t = int(tower[b])
+            p = Push()
+            p.body = b - int(self.ptr[t])
+            p.start = int(scene["push_start"][i])
+            p.steps = int(scene["push_steps"][i])
+            p.force[:] = [float(f) for f in scene["push_force"][i]]
+            p.withdraw = float(scene["push_withdraw"][i])
+            self.pushes[t].append(p)
+        self.push_arrays = []
+        for t in range(self.T):
+            arr = (Push * max(1, len(self.pushes[t])))()
+            for i, p in enumerate(self.pushes[t]):
+                arr[i] = p
+            self.push_arrays.append(arr)
+
+    def set_state(self, pos, quat, linvel, angvel):
+        self.x[:] = np.asarray(pos, np.float64).reshape(-1, 3)
+        self.q[:] = np.asarray(quat, np.float64).reshape(-1, 4)
+        self.v[:] = np.asarray(linvel, np.float64).reshape(-1, 3)
+        self.w[:] = np.asarray(angvel, np.float64).reshape(-1, 3)
+
+    def step_tower(self, t: int, n_steps: int):
+        a, b = int(self.ptr[t]), int(self.ptr[t + 1])
+        nb = b - a
+        if nb == 0:
+            self.step_counter[t].value += n_steps
+            return
+        # views into the global arrays (contiguous slices of C-contiguous arrays)
+        x = self.x[a:b]; q = self.q[a:b]; v = self.v[a:b]; w = self.w[a:b]
+        act = self.active[a:b]
+        cap = 6 * nb + 8
+        out = (Manifold * cap)()
+        nout = C.c_int(0)
+        prev = self.contacts[t]
+        nprev = self.ncontacts[t]
+        lib().or_step_tower(C.byref(self.params), nb, self.he[a:b], self.mass[a:b], x, q, v, w, act,
+                            float(self.mu[t]), len(self.pushes[t]), self.push_arrays[t],
+                            C.byref(self.step_counter[t]), int(n_steps),
+                            prev if prev is not None else None, int(nprev), out, cap, C.byref(nout),
+                            C.byref(self.stats[t]))
+        self.contacts[t] = out
+        self.ncontacts[t] = min(nout.value, cap)
+
+    def step(self, n_steps: int = 1, towers=None, threads: int = 1):
+        towers = range(self.T) if towers is None else towers
+        if threads <= 1:
+            for t in towers:
+                self.step_tower(t, n_steps)
+        else:
+            with ThreadPoolExecutor(threads) as ex:
+                list(ex.map(lambda t: self.step_tower(t, n_steps), towers))
+
+    def manifolds(self, t: int):
+        arr = self.contacts[t]
+        if arr is None:
+            return []
+        return [manifold_dict(arr[i]) for i in range(self.ncontacts[t])]
+
+    def tower_stats(self, t: int) -> Stats:
+        return self.stats[t]

@@ -1,0 +1,365 @@
+"""Seeded synthetic workloads: towers of oriented boxes, as plain input arrays.
+
+This module only builds inputs (geometry, masses, initial state, friction per
+tower, push schedules).  It holds none of the stepping arithmetic, so both the
+FP64 oracle and the HIP path read exactly the same scene.
+
+Tower construction follows the paper's structural constraints (Sec. "Structural
+Constraints": three blocks per layer, alternating perpendicular layers, block
+ratios L = 3W, T = 0.6W) with the block size and density of the benchmark
+configurations (75 x 25 x 15 mm, 600 kg/m^3).  Push magnitudes are multiples of
+Ziglar's thresholds F = k mu m g (Eq. 4, k = 3; Eq. 8, k = 4).
+
+Every random draw comes from ``numpy.random.default_rng([260628394, config_id,
+tower_index])`` so that any tower of any configuration can be regenerated alone.
+
+A scene is a dict of numpy arrays:
+  n_towers            int
+  tower_ptr  (T+1,)   int64   bodies of tower t are [tower_ptr[t], tower_ptr[t+1])
+  half_extents (N,3)  f64     body-frame half sizes (x = length, y = width, z = thickness)
+  mass       (N,)     f64     0 => static body
+  pos (N,3), quat (N,4) [w,x,y,z], linvel (N,3), angvel (N,3) (world frame)
+  active     (N,)     u8
+  mu         (T,)     f64     static friction coefficient of each tower
+  push_body  (K,)     int32   global body index
+  push_force (K,3)    f64     constant world-frame force [N]
+  push_start (K,)     int32   first step the force acts
+  push_steps (K,)     int32   number of steps it acts
+  push_withdraw (K,)  f64     displacement along the force that deactivates the body (0 = never)
+  params     dict     dt, iters, n_sub, restitution, beta, slop, margin, gravity
+  n_steps    int      steps the configuration runs
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_ROOT = 260628394
+
+# Benchmark block: 75 x 25 x 15 mm, density 600 kg/m^3 -> 16.875 g.
+BLOCK_HALF = np.array([0.0375, 0.0125, 0.0075])
+BLOCK_DENSITY = 600.0
+BLOCK_MASS = BLOCK_DENSITY * float(np.prod(2.0 * BLOCK_HALF))
+# The paper's block (appendix table): 81 x 26 x 18 mm, 19.6 g.
+PAPER_BLOCK_HALF = np.array([0.0405, 0.013, 0.009])
+PAPER_BLOCK_MASS = 0.0196
+
+G = 9.81
+MU_LEVELS = (0.25, 0.40, 0.60)
+LAYER_GAP = 1e-3        # in-layer gap between neighbouring blocks
+BED_OVERLAP = 1e-4      # initial vertical overlap (keeps resting contacts active)
+JITTER = 5e-4           # horizontal placement jitter (uniform +-)
+
+
+def default_params(**over):
+    p = dict(dt=1.0 / 240.0, iters=20, n_sub=1, restitution=0.10, beta=0.35,
+             slop=4e-4, margin=2e-3, gravity=(0.0, 0.0, -G))
+    p.update(over)
+    return p
+
+
+def rng_for(config_id: int, index: int) -> np.random.Generator:
+    return np.random.default_rng([SEED_ROOT, int(config_id), int(index)])
+
+
+def quat_z(angle: float) -> np.ndarray:
+    return np.array([math.cos(angle / 2), 0.0, 0.0, math.sin(angle / 2)])
+
+
+def quat_axis_angle(axis, angle: float) -> np.ndarray:
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    s = math.sin(angle / 2)
+    return np.array([math.cos(angle / 2), a[0] * s, a[1] * s, a[2] * s])
+
+
+def quat_mul(a, b) -> np.ndarray:
+    """Hamilton product (placement helper only: used to build initial poses)."""
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.array([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw])
+
+
+def _rotate(q, v) -> np.ndarray:
+    """Rotate vector v by unit quaternion q (placement helper only)."""
+    w, x, y, z = q
+    u = np.array([x, y, z])
+    v = np.asarray(v, dtype=np.float64)
+    return v + 2.0 * np.cross(u, np.cross(u, v) + w * v)
+
+
+def jenga_tower(levels: int, rng: np.random.Generator | None, half=BLOCK_HALF,
+                mass=None, jitter=JITTER):
+    """One upright tower: ``levels`` layers of 3 blocks, alternating 90 deg.
+
+    Level l has its long axis along world x when l is even, y when odd; the
+    three slots sit at -(w+gap), 0, +(w+gap) across the long axis.  Layers
+    overlap by 0.1 mm so resting contacts are active from step 0.
+    Returns (half_extents, mass, pos, quat, level, slot).
+    """
+    half = np.asarray(half, dtype=np.float64)
+    if mass is None:
+        mass = BLOCK_DENSITY * float(np.prod(2.0 * half))
+    width = 2.0 * half[1]
+    thick = 2.0 * half[2]
+    n = 3 * levels
+    he = np.tile(half, (n, 1))
+    m = np.full(n, float(mass))
+    pos = np.zeros((n, 3))
+    quat = np.zeros((n, 4))
+    lev = np.zeros(n, dtype=np.int32)
+    slot = np.zeros(n, dtype=np.int32)
+    for l in range(levels):
+        z = half[2] - BED_OVERLAP + l * (thick - BED_OVERLAP)
+        along_x = (l % 2 == 0)
+        q = np.array([1.0, 0.0, 0.0, 0.0]) if along_x else quat_z(math.pi / 2)
+        for s in range(3):
+            k = 3 * l + s
+            off = (s - 1) * (width + LAYER_GAP)
+            if rng is not None and jitter > 0:
+                jx, jy = rng.uniform(-jitter, jitter, size=2)
+            else:
+                jx = jy = 0.0
+            if along_x:
+                pos[k] = (jx, off + jy, z)
+            else:
+                pos[k] = (off + jx, jy, z)
+            quat[k] = q
+            lev[k] = l
+            slot[k] = s
+    return he, m, pos, quat, lev, slot
+
+
+def tilt_about_edge(pos, quat, he, theta: float, edge: int):
+    """Rigidly rotate a tower by ``theta`` about one bottom edge of its footprint.
+
+    edge in {0: +x, 1: -x, 2: +y, 3: -y} picks the footprint side the tower
+    tips towards.  Returns new (pos, quat).
+    """
+    d = [np.array([1.0, 0, 0]), np.array([-1.0, 0, 0]),
+         np.array([0, 1.0, 0]), np.array([0, -1.0, 0])][edge]
+    # footprint extent along d and the lowest corner height
+    ext = -np.inf
+    zmin = np.inf
+    for k in range(len(pos)):
+        for c in range(8):
+            sgn = np.array([1 if c & 1 else -1, 1 if c & 2 else -1, 1 if c & 4 else -1])
+            p = pos[k] + _rotate(quat[k], sgn * he[k])
+            ext = max(ext, float(d @ p))
+            zmin = min(zmin, float(p[2]))
+    pivot = d * ext + np.array([0.0, 0.0, zmin])
+    axis = np.cross(np.array([0.0, 0.0, 1.0]), d)
+    qr = quat_axis_angle(axis, theta)
+    npos = np.array([pivot + _rotate(qr, p - pivot) for p in pos])
+    nquat = np.array([quat_mul(qr, q) for q in quat])
+    return npos, nquat
+
+
+def critical_tilt(pos, quat, he, edge: int) -> float:
+    """Tilt at which the tower's centre of mass sits above the pivot edge."""
+    d = [np.array([1.0, 0, 0]), np.array([-1.0, 0, 0]),
+         np.array([0, 1.0, 0]), np.array([0, -1.0, 0])][edge]
+    ext = -np.inf
+    zmin = np.inf
+    for k in range(len(pos)):
+        for c in range(8):
+            sgn = np.array([1 if c & 1 else -1, 1 if c & 2 else -1, 1 if c & 4 else -1])
+            p = pos[k] + _rotate(quat[k], sgn * he[k])
+            ext = max(ext, float(d @ p))
+            zmin = min(zmin, float(p[2]))
+    com = pos.mean(axis=0)
+    return math.atan2(ext - float(d @ com), float(com[2]) - zmin)
+
+
+class SceneBuilder:
+    """Accumulates towers and pushes into one scene dict."""
+
+    def __init__(self, params=None, n_steps=1):
+        self.params = params or default_params()
+        self.n_steps = n_steps
+        self.towers = []     # list of dicts of body arrays
+        self.mu = []
+        self.pushes = []     # (global body, force, start, steps, withdraw)
+        self.n_bodies = 0
+
+    def add_tower(self, he, m, pos, quat, mu, linvel=None, angvel=None, active=None):
+        n = len(m)
+        t = dict(he=np.asarray(he, np.float64).reshape(n, 3),
+                 m=np.asarray(m, np.float64).reshape(n),
+                 pos=np.asarray(pos, np.float64).reshape(n, 3),
+                 quat=np.asarray(quat, np.float64).reshape(n, 4),
+                 v=np.zeros((n, 3)) if linvel is None else np.asarray(linvel, np.float64).reshape(n, 3),
+                 w=np.zeros((n, 3)) if angvel is None else np.asarray(angvel, np.float64).reshape(n, 3),
+                 active=np.ones(n, np.uint8) if active is None else np.asarray(active, np.uint8).reshape(n))
+        first = self.n_bodies
+        self.towers.append(t)
+        self.mu.append(float(mu))
+        self.n_bodies += n
+        return first
+
+    def add_push(self, body, force, start, steps, withdraw=0.0):
+        self.pushes.append((int(body), np.asarray(force, np.float64).reshape(3), int(start), int(steps),
+                            float(withdraw)))
+
+    def build(self):
+        T = len(self.towers)
+        ptr = np.zeros(T + 1, np.int64)
+        for i, t in enumerate(self.towers):
+            ptr[i + 1] = ptr[i] + len(t["m"])
+        cat = lambda k: np.concatenate([t[k] for t in self.towers]) if T else np.zeros(0)
+        K = len(self.pushes)
+        sc = dict(
+            n_towers=T, tower_ptr=ptr,
+            half_extents=cat("he").reshape(-1, 3), mass=cat("m"), pos=cat("pos").reshape(-1, 3),
+            quat=cat("quat").reshape(-1, 4), linvel=cat("v").reshape(-1, 3), angvel=cat("w").reshape(-1, 3),
+            active=cat("active").astype(np.uint8), mu=np.asarray(self.mu, np.float64),
+            push_body=np.array([p[0] for p in self.pushes], np.int32).reshape(K),
+            push_force=np.array([p[1] for p in self.pushes], np.float64).reshape(K, 3),
+            push_start=np.array([p[2] for p in self.pushes], np.int32).reshape(K),
+            push_steps=np.array([p[3] for p in self.pushes], np.int32).reshape(K),
+            push_withdraw=np.array([p[4] for p in self.pushes], np.float64).reshape(K),
+            params=dict(self.params), n_steps=int(self.n_steps))
+        return sc
+
+
+def tower_of(scene) -> np.ndarray:
+    ptr = scene["tower_ptr"]
+    return np.repeat(np.arange(scene["n_towers"], dtype=np.int32), np.diff(ptr))
+
+
+def subset(scene, towers) -> dict:
+    """Scene restricted to the listed towers (pushes re-indexed)."""
+    towers = list(towers)
+    ptr = scene["tower_ptr"]
+    sb = SceneBuilder(scene["params"], scene["n_steps"])
+    remap = {}
+    for t in towers:
+        a, b = int(ptr[t]), int(ptr[t + 1])
+        first = sb.add_tower(scene["half_extents"][a:b], scene["mass"][a:b], scene["pos"][a:b],
+                             scene["quat"][a:b], scene["mu"][t], scene["linvel"][a:b],
+                             scene["angvel"][a:b], scene["active"][a:b])
+        for k in range(a, b):
+            remap[k] = first + (k - a)
+    for i in range(len(scene["push_body"])):
+        b = int(scene["push_body"][i])
+        if b in remap:
+            sb.add_push(remap[b], scene["push_force"][i], scene["push_start"][i], scene["push_steps"][i],
+                        scene["push_withdraw"][i])
+    return sb.build()
+
+
+# ----------------------------------------------------------------------------------------------
+# Benchmark configurations
+# ----------------------------------------------------------------------------------------------
+
+def cfg1(seed: int = 0):
+    """One 18-level tower (54 blocks), one seeded middle block removed at t = 0.
+
+    mu = 0.40, 20 iterations, dt = 1/240 s, 240 steps.
+    """
+    rng = rng_for(1, seed)
+    he, m, pos, quat, lev, slot = jenga_tower(18, rng)
+    active = np.ones(len(m), np.uint8)
+    level = int(rng.integers(8, 10))
+    s = int(rng.integers(0, 3))
+    active[3 * level + s] = 0
+    sb = SceneBuilder(default_params(), n_steps=240)
+    sb.add_tower(he, m, pos, quat, 0.40, active=active)
+    return sb.build()
+
+
+def _tower_push_schedule(rng, levels, mu, first_body, sb, n_removals):
+    """Seeded removals: at step 60 + 240 r push one block (levels 1..L-3) for 180 steps."""
+    chosen = set()
+    for r in range(n_removals):
+        while True:
+            l = int(rng.integers(1, levels - 2))
+            s = int(rng.integers(0, 3))
+            if (l, s) not in chosen:
+                chosen.add((l, s))
+                break
+        along_x = (l % 2 == 0)
+        long_axis = np.array([1.0, 0, 0]) if along_x else np.array([0, 1.0, 0])
+        short_axis = np.array([0, 1.0, 0]) if along_x else np.array([1.0, 0, 0])
+        if s == 1 or rng.random() < 0.5:
+            k, direction, extent = 3, long_axis * (1 if rng.random() < 0.5 else -1), 2 * BLOCK_HALF[0]
+        else:
+            k, direction, extent = 4, short_axis * (1 if s == 2 else -1), 2 * BLOCK_HALF[1]
+        scale = rng.uniform(0.9, 1.3)
+        f = scale * k * mu * BLOCK_MASS * G
+        sb.add_push(first_body + 3 * l + s, f * direction, 60 + 240 * r, 180, extent)
+
+
+def cfg2(seed: int = 0, n_per_mu: int = 150, n_steps: int = 2000):
+    """450 towers (150 per mu level), 12-24 levels, 1-8 seeded push removals each."""
+    sb = SceneBuilder(default_params(), n_steps=n_steps)
+    idx = 0
+    for mu in MU_LEVELS:
+        for _ in range(n_per_mu):
+            rng = rng_for(2, seed * 100000 + idx)
+            levels = int(rng.integers(12, 25))
+            he, m, pos, quat, lev, slot = jenga_tower(levels, rng)
+            first = sb.add_tower(he, m, pos, quat, mu)
+            _tower_push_schedule(rng, levels, mu, first, sb, int(rng.integers(1, 9)))
+            idx += 1
+    return sb.build()
+
+
+def cfg3(seed: int = 0, n_towers: int = 16384, n_steps: int = 500, literal_tilt: bool = False,
+         min_levels: int = 8, max_levels: int = 40):
+    """Throughput batch: towers of 8-40 levels, each tilted past its critical angle.
+
+    The tilt is theta_crit(L) + U(0, 3 deg) about a seeded bottom edge, so every
+    tower collapses fully (dense, dynamic contacts).  ``literal_tilt`` draws the
+    tilt from U(0, 3 deg) alone (towers keep standing).
+    """
+    sb = SceneBuilder(default_params(), n_steps=n_steps)
+    for t in range(n_towers):
+        rng = rng_for(3, seed * 1000000 + t)
+        levels = int(rng.integers(min_levels, max_levels + 1))
+        mu = MU_LEVELS[int(rng.integers(0, 3))]
+        he, m, pos, quat, lev, slot = jenga_tower(levels, rng)
+        edge = int(rng.integers(0, 4))
+        extra = math.radians(rng.uniform(0.0, 3.0))
+        theta = extra if literal_tilt else critical_tilt(pos, quat, he, edge) + extra
+        pos, quat = tilt_about_edge(pos, quat, he, theta, edge)
+        sb.add_tower(he, m, pos, quat, mu)
+    return sb.build()
+
+
+def tilted_towers(config_id: int, n_towers: int, levels_range=(8, 40), seed: int = 0, n_steps: int = 1,
+                  literal_tilt: bool = False):
+    """Smaller batches with the same recipe as the throughput batch (for parity tests)."""
+    sb = SceneBuilder(default_params(), n_steps=n_steps)
+    for t in range(n_towers):
+        rng = rng_for(config_id, seed * 1000000 + t)
+        levels = int(rng.integers(levels_range[0], levels_range[1] + 1))
+        mu = MU_LEVELS[int(rng.integers(0, 3))]
+        he, m, pos, quat, lev, slot = jenga_tower(levels, rng)
+        edge = int(rng.integers(0, 4))
+        extra = math.radians(rng.uniform(0.0, 3.0))
+        theta = extra if literal_tilt else critical_tilt(pos, quat, he, edge) + extra
+        pos, quat = tilt_about_edge(pos, quat, he, theta, edge)
+        sb.add_tower(he, m, pos, quat, mu)
+    return sb.build()
+
+
+def random_box_pairs(n: int, seed: int = 0, size=(0.1, 1.0), spread=1.5):
+    """Random box pairs (for separating-axis checks): half extents, centres, unit quaternions."""
+    rng = rng_for(90, seed)
+    he = rng.uniform(size[0], size[1], size=(n, 2, 3)) / 2.0
+    x = rng.uniform(-spread / 2, spread / 2, size=(n, 2, 3))
+    q = rng.normal(size=(n, 2, 4))
+    q /= np.linalg.norm(q, axis=-1, keepdims=True)
+    return he, x, q
+
+
+def single_box(pos, quat=(1.0, 0, 0, 0), linvel=(0, 0, 0), angvel=(0, 0, 0), half=BLOCK_HALF,
+               mass=BLOCK_MASS, mu=0.4, params=None, n_steps=1):
+    sb = SceneBuilder(params or default_params(), n_steps=n_steps)
+    sb.add_tower([half], [mass], [pos], [quat], mu, [linvel], [angvel])
+    return sb.build()

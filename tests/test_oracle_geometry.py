@@ -1,0 +1,278 @@
+"""Pins of the oracle's geometry: rotations, inertia, SAT, manifolds.
+
+Each check compares the oracle with something other than itself: values the
+paper prints, a library routine, numerical integration, or brute force.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from paper_2606_28394_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------------------------------------
+# P3: Eq. (rotmat) against scipy's quaternion -> matrix conversion, orthonormality, det = 1
+# ---------------------------------------------------------------------------------------------
+
+def test_rotation_matches_library_and_is_proper(oracle):
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        R = oracle.quat_to_rot(q)
+        ref = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()   # scipy is scalar-last
+        np.testing.assert_allclose(R, ref, atol=1e-14)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-14
+
+
+def test_rotation_axis_angle_rodrigues(oracle):
+    # q = [cos(t/2), sin(t/2) n] rotates by t about n (Sec. "Quaternions and Rotations")
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        t = rng.uniform(-math.pi, math.pi)
+        q = np.concatenate([[math.cos(t / 2)], math.sin(t / 2) * n])
+        K = np.array([[0, -n[2], n[1]], [n[2], 0, -n[0]], [-n[1], n[0], 0]])
+        rod = np.eye(3) + math.sin(t) * K + (1 - math.cos(t)) * K @ K
+        np.testing.assert_allclose(oracle.quat_to_rot(q), rod, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------------------------
+# P2: Eq. (inertia): hand-evaluated values for the paper's block, and a volume integral
+# ---------------------------------------------------------------------------------------------
+
+def test_inertia_paper_block_golden(oracle):
+    vals = [float(v) for v in _golden_rows("inertia_paper_block.txt")[0]]
+    I = oracle.box_inertia(W.PAPER_BLOCK_MASS, W.PAPER_BLOCK_HALF)
+    np.testing.assert_allclose(I, vals, rtol=1e-6)
+    # the printed I_xx (1.18e-5) is the formula's I_zz, not I_xx
+    assert abs(I[2] - 1.18e-5) / 1.18e-5 < 0.01 and abs(I[0] - 1.18e-5) / 1.18e-5 > 0.5
+
+
+def test_inertia_matches_volume_integral(oracle):
+    he = np.array([0.0375, 0.0125, 0.0075])
+    m = 0.016875
+    n = 120
+    axes = [(np.arange(n) + 0.5) / n * 2 * h - h for h in he]   # midpoint rule
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    ref = m * np.array([np.mean(Y ** 2 + Z ** 2), np.mean(X ** 2 + Z ** 2), np.mean(X ** 2 + Y ** 2)])
+    np.testing.assert_allclose(oracle.box_inertia(m, he), ref, rtol=1e-4)
+
+
+# ---------------------------------------------------------------------------------------------
+# P6: SAT against brute-force box-box distance and intersection
+# ---------------------------------------------------------------------------------------------
+
+_CORNER_SIGNS = np.array([[1 if k & 1 else -1, 1 if k & 2 else -1, 1 if k & 4 else -1] for k in range(8)], float)
+_EDGES = [(a, b) for a in range(8) for b in range(a + 1, 8) if bin(a ^ b).count("1") == 1]
+
+
+def _corners(he, x, R):
+    return x + (_CORNER_SIGNS * he) @ R.T
+
+
+def _point_box_dist(p, he, x, R):
+    loc = (p - x) @ R
+    cl = np.clip(loc, -he, he)
+    return np.linalg.norm(loc - cl, axis=-1)
+
+
+def _seg_seg_dist(p1, q1, p2, q2):
+    d1, d2, r = q1 - p1, q2 - p2, p1 - p2
+    a, e, f = d1 @ d1, d2 @ d2, d2 @ r
+    c, b = d1 @ r, d1 @ d2
+    den = a * e - b * b
+    s = np.clip((b * f - c * e) / den, 0.0, 1.0) if den > 1e-300 else 0.0
+    t = (b * s + f) / e
+    if t < 0.0:
+        t, s = 0.0, np.clip(-c / a, 0.0, 1.0)
+    elif t > 1.0:
+        t, s = 1.0, np.clip((b - c) / a, 0.0, 1.0)
+    return np.linalg.norm((p1 + d1 * s) - (p2 + d2 * t))
+
+
+def _seg_hits_box(p, q, he, x, R):
+    """Liang-Barsky: does segment pq meet the closed box?"""
+    a = (p - x) @ R
+    d = (q - x) @ R - a
+    t0, t1 = 0.0, 1.0
+    for k in range(3):
+        if abs(d[k]) < 1e-300:
+            if abs(a[k]) > he[k]:
+                return False
+            continue
+        ta, tb = (-he[k] - a[k]) / d[k], (he[k] - a[k]) / d[k]
+        t0, t1 = max(t0, min(ta, tb)), min(t1, max(ta, tb))
+        if t0 > t1:
+            return False
+    return True
+
+
+def _brute(heA, xA, RA, heB, xB, RB):
+    cA, cB = _corners(heA, xA, RA), _corners(heB, xB, RB)
+    for i, j in _EDGES:
+        if _seg_hits_box(cA[i], cA[j], heB, xB, RB) or _seg_hits_box(cB[i], cB[j], heA, xA, RA):
+            return True, 0.0
+    d = min(_point_box_dist(cA, heB, xB, RB).min(), _point_box_dist(cB, heA, xA, RA).min())
+    for i, j in _EDGES:
+        for k, l in _EDGES:
+            d = min(d, _seg_seg_dist(cA[i], cA[j], cB[k], cB[l]))
+    return False, d
+
+
+def _fib_dirs(n):
+    i = np.arange(n) + 0.5
+    phi = np.arccos(1 - 2 * i / n)
+    th = math.pi * (1 + 5 ** 0.5) * i
+    return np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+
+
+def test_sat_agrees_with_brute_force(oracle):
+    he, x, q = W.random_box_pairs(1500, seed=1)
+    dirs = _fib_dirs(10000)
+    n_overlap = n_sep = 0
+    for p in range(len(he)):
+        RA, RB = oracle.quat_to_rot(q[p, 0]), oracle.quat_to_rot(q[p, 1])
+        s = oracle.sat(he[p, 0], x[p, 0], q[p, 0], he[p, 1], x[p, 1], q[p, 1])
+        hit, dist = _brute(he[p, 0], x[p, 0], RA, he[p, 1], x[p, 1], RB)
+        if abs(s.sigma) < 1e-9:
+            continue
+        assert bool(s.collide) == hit, (p, s.sigma, dist)
+        if hit:
+            n_overlap += 1
+            # the least overlap over all directions is reached on one of the 15 axes
+            d = x[p, 1] - x[p, 0]
+            ov = (np.abs(dirs @ RA) @ he[p, 0] + np.abs(dirs @ RB) @ he[p, 1] - np.abs(dirs @ d))
+            assert s.depth <= ov.min() + 1e-12
+            assert s.depth > 0
+            # normal from A to B
+            assert np.dot(np.array(s.normal[:]), d) >= 0
+        else:
+            n_sep += 1
+            # the largest axis gap is a lower bound of the distance
+            assert s.sigma <= dist + 1e-12
+            assert dist > 0
+    assert n_overlap > 100 and n_sep > 100
+
+
+def test_sat_aligned_stack_normal_and_depth(oracle):
+    he = W.BLOCK_HALF
+    ident = [1.0, 0, 0, 0]
+    top = W.quat_z(math.pi / 2)
+    s = oracle.sat(he, [0, 0, 0.0075], ident, he, [0.001, -0.002, 0.0075 + 0.015 - 1e-4], top)
+    assert s.collide
+    np.testing.assert_allclose(s.normal[:], [0, 0, 1], atol=1e-12)
+    assert abs(s.depth - 1e-4) < 1e-12
+    # in-layer neighbours 1 mm apart are separated by exactly 1 mm along the width axis
+    s = oracle.sat(he, [0, 0, 0.0075], ident, he, [0, 0.026, 0.0075], ident)
+    assert not s.collide and abs(s.sigma - 1e-3) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------------
+# P7: manifolds with closed-form answers
+# ---------------------------------------------------------------------------------------------
+
+def _pts(m):
+    return np.array([m.point[i][:] for i in range(m.npts)])
+
+
+def test_manifold_crossed_blocks_square(oracle):
+    he = W.BLOCK_HALF
+    dx, dy = 0.0004, -0.0003
+    zb = 0.0075 + 0.015 - 1e-4
+    m = oracle.manifold_box(he, [0, 0, 0.0075], [1, 0, 0, 0], he, [dx, dy, zb], W.quat_z(math.pi / 2),
+                            [0, 0, 1], 1e-4)
+    assert m.npts == 4
+    # overlap square: x within B's width, y within A's width
+    xs = [dx - 0.0125, dx + 0.0125]
+    ys = [-0.0125, 0.0125]
+    zmid = 0.5 * ((0.0075 + 0.0075) + (zb - 0.0075))
+    expect = {(xs[1], ys[1]): 0, (xs[0], ys[1]): 1, (xs[0], ys[0]): 2, (xs[1], ys[0]): 3}
+    pts = _pts(m)
+    for i in range(4):
+        key = min(expect, key=lambda k: (k[0] - pts[i, 0]) ** 2 + (k[1] - pts[i, 1]) ** 2)
+        np.testing.assert_allclose(pts[i, :2], key, atol=1e-12)
+        assert abs(pts[i, 2] - zmid) < 1e-12
+        assert m.slot[i] == expect[key]
+
+
+def test_manifold_offset_parallel_stack_rectangle(oracle):
+    he = W.BLOCK_HALF
+    dx, dy = 0.02, 0.005
+    zb = 0.0075 + 0.015 - 1e-4
+    m = oracle.manifold_box(he, [0, 0, 0.0075], [1, 0, 0, 0], he, [dx, dy, zb], [1, 0, 0, 0], [0, 0, 1], 1e-4)
+    pts = _pts(m)
+    x_lo, x_hi = max(-he[0], dx - he[0]), min(he[0], dx + he[0])
+    y_lo, y_hi = max(-he[1], dy - he[1]), min(he[1], dy + he[1])
+    corners = sorted([(x_lo, y_lo), (x_lo, y_hi), (x_hi, y_lo), (x_hi, y_hi)])
+    got = sorted([tuple(p[:2]) for p in pts])
+    np.testing.assert_allclose(np.array(got), np.array(corners), atol=1e-12)
+
+
+def test_manifold_ground_face_down(oracle):
+    he = W.BLOCK_HALF
+    z = he[2] - 1e-4
+    m = oracle.manifold_ground(he, [0.01, 0.02, z], [1, 0, 0, 0])
+    assert m is not None and m.npts == 4
+    assert list(m.slot[:4]) == [0, 1, 2, 3]          # bottom vertices (z sign bit clear)
+    pts = _pts(m)
+    for i in range(4):
+        sx = 1 if (m.slot[i] & 1) else -1
+        sy = 1 if (m.slot[i] & 2) else -1
+        np.testing.assert_allclose(pts[i], [0.01 + sx * he[0], 0.02 + sy * he[1], -0.5e-4], atol=1e-15)
+    np.testing.assert_allclose(m.normal[:], [0, 0, -1])
+    assert abs(m.depth - 1e-4) < 1e-15
+
+
+def test_manifold_ground_edge_and_corner(oracle):
+    he = W.BLOCK_HALF
+    # resting on an edge: rotated about x by 30 deg, lowest edge 0.1 mm below ground
+    q = W.quat_axis_angle([1, 0, 0], math.radians(30))
+    R = oracle.quat_to_rot(q)
+    zlow = min((R @ (s * he))[2] for s in _CORNER_SIGNS)
+    m = oracle.manifold_ground(he, [0, 0, -zlow - 1e-4], q)
+    assert m.npts == 2
+    # tilted about two axes: a single corner
+    q = W.quat_mul(W.quat_axis_angle([1, 0, 0], 0.3), W.quat_axis_angle([0, 1, 0], 0.2))
+    R = oracle.quat_to_rot(q)
+    zlow = min((R @ (s * he))[2] for s in _CORNER_SIGNS)
+    m = oracle.manifold_ground(he, [0, 0, -zlow - 1e-4], q)
+    assert m.npts == 1 and abs(m.depth - 1e-4) < 1e-15
+
+
+def test_manifold_points_lie_in_both_silhouettes(oracle):
+    """Every manifold point projects inside both boxes' shadows along the normal."""
+    he, x, q = W.random_box_pairs(400, seed=2, spread=0.6)
+    checked = 0
+    for p in range(len(he)):
+        s = oracle.sat(he[p, 0], x[p, 0], q[p, 0], he[p, 1], x[p, 1], q[p, 1])
+        if not s.collide or s.band:
+            continue
+        m = oracle.manifold_box(he[p, 0], x[p, 0], q[p, 0], he[p, 1], x[p, 1], q[p, 1], s.normal[:], s.depth)
+        n = np.array(s.normal[:])
+        for i in range(m.npts):
+            pt = np.array(m.point[i][:])
+            for b in range(2):
+                R = oracle.quat_to_rot(q[p, b])
+                # a point lies in the shadow of box b along n iff the line pt + t n meets the box
+                far = 10.0
+                assert _seg_hits_box(pt - far * n, pt + far * n, he[p, b] * (1 + 1e-9) + 1e-12, x[p, b], R)
+        checked += 1
+    assert checked > 50
