@@ -174,8 +174,19 @@ static int cmp_pt2(const void* pa, const void* pb) {
 }
 
 /* Convex hull, counter-clockwise, collinear and repeated points dropped (the hull is a
- * set: any hull algorithm, QuickHull included, returns these vertices). Returns count. */
+ * set: any hull algorithm, QuickHull included, returns these vertices). Returns count.
+ * Corners that project onto the same point (a box seen along one of its axes shows each
+ * corner of the silhouette twice, equal up to rounding) count once: points within 1e-12 m
+ * of an earlier point are removed before the chain is built. */
 static int convex_hull(pt2* p, int n, pt2* h) {
+  int nd = 0;
+  for (int i = 0; i < n; ++i) {
+    int dup = 0;
+    for (int j = 0; j < nd; ++j)
+      if (hypot(p[i].u - p[j].u, p[i].v - p[j].v) < 1e-12) { dup = 1; break; }
+    if (!dup) p[nd++] = p[i];
+  }
+  n = nd;
   qsort(p, (size_t)n, sizeof(pt2), cmp_pt2);
   int k = 0;
   for (int i = 0; i < n; ++i) {                       /* lower chain */

@@ -226,10 +226,13 @@ class OracleWorld:
             self.push_arrays.append(arr)
 
     def set_state(self, pos, quat, linvel, angvel):
+        """Overwrite the body state and forget the previous step's impulses."""
         self.x[:] = np.asarray(pos, np.float64).reshape(-1, 3)
         self.q[:] = np.asarray(quat, np.float64).reshape(-1, 4)
         self.v[:] = np.asarray(linvel, np.float64).reshape(-1, 3)
         self.w[:] = np.asarray(angvel, np.float64).reshape(-1, 3)
+        self.contacts = [None] * self.T
+        self.ncontacts = [0] * self.T
 
     def step_tower(self, t: int, n_steps: int):
         a, b = int(self.ptr[t]), int(self.ptr[t + 1])

@@ -276,3 +276,69 @@ def test_manifold_points_lie_in_both_silhouettes(oracle):
                 assert _seg_hits_box(pt - far * n, pt + far * n, he[p, b] * (1 + 1e-9) + 1e-12, x[p, b], R)
         checked += 1
     assert checked > 50
+
+
+def test_manifold_crossed_blocks_any_orientation(oracle):
+    """A rigid rotation of a crossed pair moves the overlap square with it: the manifold is the
+    square's four corners (one per diagonal slot) lifted to the mid-plane, for any rotation."""
+    he = W.BLOCK_HALF
+    rng = np.random.default_rng(12)
+    zb = 0.0075 + 0.015 - 1e-4
+    xa0, xb0 = np.array([0.0, 0.0, 0.0075]), np.array([0.0003, -0.0002, zb])
+    sq = np.array([[xb0[0] + sx * 0.0125, sy * 0.0125, 0.5 * (0.015 + zb - 0.0075)]
+                   for sx in (-1, 1) for sy in (-1, 1)])
+    checked = 0
+    for trial in range(200):
+        qr = rng.normal(size=4)
+        qr /= np.linalg.norm(qr)
+        if trial < 4:                      # tilts about a single world axis (the tilted-tower case)
+            qr = W.quat_axis_angle(np.eye(3)[trial % 3], 0.3 + 0.2 * trial)
+        R = oracle.quat_to_rot(qr)
+        qa = qr
+        qb = W.quat_mul(qr, W.quat_z(math.pi / 2))
+        xa, xb = R @ xa0, R @ xb0
+        s = oracle.sat(he, xa, qa, he, xb, qb)
+        assert s.collide
+        m = oracle.manifold_box(he, xa, qa, he, xb, qb, s.normal[:], s.depth)
+        if m.band & oracle.BAND_CLIP:
+            continue                       # a square edge along a diagonal: slots tie
+        pts = _pts(m)
+        expect = (R @ sq.T).T
+        assert m.npts == 4, (trial, m.npts)
+        d = np.linalg.norm(pts[:, None, :] - expect[None, :, :], axis=2)
+        assert d.min(axis=1).max() < 1e-12 and sorted(d.argmin(axis=1)) == [0, 1, 2, 3]
+        checked += 1
+    assert checked > 150
+
+
+def test_manifold_tilted_tower_crossings_are_rectangles(oracle):
+    """In a rigidly tilted intact tower every crossing of two consecutive layers overlaps in the
+    intersection of the two blocks' footprints, a rectangle in the lower block's frame: the
+    manifold is its four corners on the mid-plane, whatever the tilt."""
+    sc = W.tilted_towers(35, 12, levels_range=(8, 24))
+    checked = 0
+    for t in range(sc["n_towers"]):
+        a0, a1 = int(sc["tower_ptr"][t]), int(sc["tower_ptr"][t + 1])
+        he, x, q = sc["half_extents"], sc["pos"], sc["quat"]
+        for i in range(a0, a1 - 3):
+            for j in range(i + 1, a1):
+                if (j - a0) // 3 != (i - a0) // 3 + 1:
+                    continue
+                s = oracle.sat(he[i], x[i], q[i], he[j], x[j], q[j])
+                assert s.collide
+                m = oracle.manifold_box(he[i], x[i], q[i], he[j], x[j], q[j], s.normal[:], s.depth)
+                if m.band & oracle.BAND_CLIP:
+                    continue
+                assert m.npts == 4, (t, i - a0, j - a0, m.npts)
+                RA = oracle.quat_to_rot(q[i])
+                d = RA.T @ (x[j] - x[i])                 # B's centre in A's frame; B turned 90 deg
+                xs = [max(-he[i][0], d[0] - he[j][1]), min(he[i][0], d[0] + he[j][1])]
+                ys = [max(-he[i][1], d[1] - he[j][0]), min(he[i][1], d[1] + he[j][0])]
+                zmid = 0.5 * (he[i][2] + d[2] - he[j][2])
+                loc = (_pts(m) - x[i]) @ RA
+                want = np.array([(cx, cy) for cx in xs for cy in ys])
+                dd = np.linalg.norm(loc[:, None, :2] - want[None, :, :], axis=2)
+                assert dd.min(axis=1).max() < 1e-12 and sorted(dd.argmin(axis=1)) == [0, 1, 2, 3]
+                np.testing.assert_allclose(loc[:, 2], zmid, atol=1e-12)
+                checked += 1
+    assert checked > 500
