@@ -1,0 +1,1123 @@
+// Batched block stepping on gfx950: one workgroup (one 64-lane wave) owns a
+// "pack" of whole towers and keeps their bodies, contacts and colours in LDS
+// for every step of a launch.  HBM is touched only when the launch starts and
+// ends, so the step is bound by the vector ALUs and LDS latency, not by HBM.
+//
+// Per step (Secs. "Rigid-Body Foundations", "Physics Engine --- Collision
+// Detection", "Contact Solver --- Projected Gauss-Seidel (PGS)"):
+//   1 external forces: v += dt g + dt F/m (semi-implicit Euler)
+//   2 frames: R(q) (Eq. (rotmat)), world AABB half sizes, I_w^-1 = R I_b^-1 R^T
+//   3 broadphase (Eq. (aabb)): all same-tower pairs i<j plus the ground; ballot
+//     compaction keeps the canonical (i, j) order
+//   4 narrowphase: 15-axis SAT, normal = first least-penetration axis
+//   5 greedy first-fit colouring over the canonical list (bit masks per body)
+//   6 manifolds, written straight into colour-sorted slots: the silhouettes of
+//     both boxes along n are zonogons (three projected half-edges); the clipped
+//     polygon's extremes along the four diagonals are found among (a) corners of
+//     one silhouette inside the other and (b) silhouette edge crossings; points
+//     are lifted to the mid-plane of the overlap slab
+//   7 PGS: colour by colour, one lane per manifold, its points and rows in
+//     order (Eq. (lambda_n) then Eq. (coulomb_pgs) on t1, t2); manifolds of one
+//     colour share no dynamic body, so each colour is an exact Gauss-Seidel sweep
+//   8 residual of the solve (natural map)
+//   9 integration: x += dt v, q from Eq. (quat_int) with world-frame omega,
+//     omega re-derived from the angular momentum (Eq. (newton_euler), torque free)
+//  10 Baumgarte correction (Eq. (baumgarte)), colour by colour
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "jenga_device.h"
+
+namespace jg {
+namespace {
+
+constexpr uint32_t kGround = 0xffffu;
+constexpr uint32_t kErrCand = 1u, kErrMan = 2u, kErrCol = 4u, kErrNan = 8u;
+
+struct Lds {
+  // bodies [comp * nbp + i]
+  float *x, *q, *v, *w, *he, *invm, *invI, *R, *Iw, *h;
+  uint32_t *flag, *mask;
+  int32_t* tw;
+  // towers
+  int32_t *tb0, *tb1;
+  float* mu;
+  uint32_t* tcnt;   // [t*4 + k]
+  float* tres;      // [t*2 + k]
+  // pushes
+  int32_t *pb, *ps, *pn;
+  float *pf, *pwd, *px0;
+  // colours and scalars
+  int32_t *coloff, *colcnt, *scal;
+  // broadphase candidates
+  uint32_t* cand;
+  // canonical colliding pairs
+  uint32_t* cab;
+  float *cn, *cdepth;
+  int32_t* cpos;
+  // colour-sorted manifolds
+  uint32_t *mab, *mmeta;
+  float *mn, *mt1, *mdepth;
+  int32_t* mcanon;
+  float *mr, *ml;   // [(j*3 + k) * pc + m]
+  // previous step (warm start), canonical order
+  uint32_t *pkey, *pslot;
+  float *pnrm, *plam;
+  int nbp, pc, cc, tpc, ppc;
+};
+
+__device__ inline Lds carve(float* base, const StepArgs& a) {
+  Lds L;
+  L.nbp = a.nbp; L.pc = a.pc; L.cc = a.cc; L.tpc = a.tpc; L.ppc = a.ppc;
+  float* p = base;
+  auto take = [&](int n) { float* r = p; p += n; return r; };
+  const int nb = a.nbp, pc = a.pc;
+  L.x = take(3 * nb); L.q = take(4 * nb); L.v = take(3 * nb); L.w = take(3 * nb);
+  L.he = take(3 * nb); L.invm = take(nb); L.invI = take(3 * nb);
+  L.flag = (uint32_t*)take(nb); L.tw = (int32_t*)take(nb);
+  L.R = take(9 * nb); L.Iw = take(6 * nb); L.h = take(3 * nb);
+  L.mask = (uint32_t*)take(2 * nb);
+  L.tb0 = (int32_t*)take(a.tpc); L.tb1 = (int32_t*)take(a.tpc); L.mu = take(a.tpc);
+  L.tcnt = (uint32_t*)take(4 * a.tpc); L.tres = take(2 * a.tpc); take(a.tpc);
+  L.pb = (int32_t*)take(a.ppc); L.ps = (int32_t*)take(a.ppc); L.pn = (int32_t*)take(a.ppc);
+  L.pf = take(3 * a.ppc); L.pwd = take(a.ppc); L.px0 = take(3 * a.ppc);
+  L.coloff = (int32_t*)take(kMaxColours + 1); L.colcnt = (int32_t*)take(kMaxColours + 1);
+  L.scal = (int32_t*)take(16);
+  L.cand = (uint32_t*)take(a.cc);
+  L.cab = (uint32_t*)take(pc); L.cn = take(3 * pc); L.cdepth = take(pc); L.cpos = (int32_t*)take(pc);
+  L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc); L.mn = take(3 * pc); L.mt1 = take(3 * pc);
+  L.mdepth = take(pc); L.mcanon = (int32_t*)take(pc); L.mr = take(12 * pc); L.ml = take(12 * pc);
+  if (a.warm_start) {
+    L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
+  } else {
+    L.pkey = L.pslot = nullptr; L.pnrm = L.plam = nullptr;
+  }
+  return L;
+}
+
+__device__ inline float dot3(const float a[3], const float b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ inline void cross3(const float a[3], const float b[3], float c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+// symmetric 3x3 (xx, yy, zz, xy, xz, yz) times vector
+__device__ inline void sym_mul(const float I[6], const float c[3], float o[3]) {
+  o[0] = I[0] * c[0] + I[3] * c[1] + I[4] * c[2];
+  o[1] = I[3] * c[0] + I[1] * c[1] + I[5] * c[2];
+  o[2] = I[4] * c[0] + I[5] * c[1] + I[2] * c[2];
+}
+
+// Eq. (rotmat), row-major
+__device__ inline void quat_rot(float w, float x, float y, float z, float R[9]) {
+  R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - z * w);       R[2] = 2.f * (x * z + y * w);
+  R[3] = 2.f * (x * y + z * w);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - x * w);
+  R[6] = 2.f * (x * z - y * w);       R[7] = 2.f * (y * z + x * w);       R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+__device__ inline void load_R(const Lds& L, int i, float R[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = L.R[k * L.nbp + i];
+}
+__device__ inline void load3(const float* a, int stride, int i, float o[3]) {
+  o[0] = a[i]; o[1] = a[stride + i]; o[2] = a[2 * stride + i];
+}
+__device__ inline void store3(float* a, int stride, int i, const float o[3]) {
+  a[i] = o[0]; a[stride + i] = o[1]; a[2 * stride + i] = o[2];
+}
+
+__device__ inline void tangent_basis(const float n[3], float t1[3], float t2[3]) {
+  float e[3] = {0.f, 0.f, 0.f};
+  if (fabsf(n[0]) < 0.9f) e[0] = 1.f; else e[1] = 1.f;
+  const float en = dot3(e, n);
+  float t[3] = {e[0] - en * n[0], e[1] - en * n[1], e[2] - en * n[2]};
+  const float il = rsqrtf(dot3(t, t));
+  t1[0] = t[0] * il; t1[1] = t[1] * il; t1[2] = t[2] * il;
+  cross3(n, t1, t2);
+}
+
+// ------------------------------------------------------------------------------------------------
+// narrowphase: 15-axis SAT in coordinates relative to A's centre (d = xB - xA)
+// ------------------------------------------------------------------------------------------------
+__device__ bool sat_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
+                          const float d[3], float n[3], float& depth) {
+  float A[3][3], B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { A[i][k] = RA[3 * k + i]; B[i][k] = RB[3 * k + i]; }
+  float best = INFINITY;
+  float bu[3] = {0.f, 0.f, 1.f};
+  auto axis = [&](const float u[3]) -> bool {
+    const float ra = heA[0] * fabsf(dot3(A[0], u)) + heA[1] * fabsf(dot3(A[1], u)) + heA[2] * fabsf(dot3(A[2], u));
+    const float rb = heB[0] * fabsf(dot3(B[0], u)) + heB[1] * fabsf(dot3(B[1], u)) + heB[2] * fabsf(dot3(B[2], u));
+    const float dd = ra + rb - fabsf(dot3(d, u));
+    if (!(dd > 0.f)) return false;
+    if (dd < best) { best = dd; bu[0] = u[0]; bu[1] = u[1]; bu[2] = u[2]; }
+    return true;
+  };
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (!axis(A[i])) return false;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (!axis(B[j])) return false;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float c[3];
+      cross3(A[i], B[j], c);
+      const float len = sqrtf(dot3(c, c));
+      if (len < 1e-5f) continue;
+      const float il = 1.f / len;
+      c[0] *= il; c[1] *= il; c[2] *= il;
+      if (!axis(c)) return false;
+    }
+  const float s = dot3(d, bu) < 0.f ? -1.f : 1.f;
+  n[0] = s * bu[0]; n[1] = s * bu[1]; n[2] = s * bu[2];
+  depth = best;
+  return true;
+}
+
+// ------------------------------------------------------------------------------------------------
+// manifold of a colliding box pair (relative to A's centre)
+// ------------------------------------------------------------------------------------------------
+struct V2 { float x, y; };
+__device__ inline float cr2(V2 a, V2 b) { return a.x * b.y - a.y * b.x; }
+
+struct Zono {        // silhouette of a box along n: centre + sum_i s_i g_i, |s_i| <= 1
+  V2 c, g[3];
+  V2 m[3];           // slab normals perp(g_i)
+  float h[3];        // slab half widths
+  float tol[3];
+  bool use[3];
+};
+
+__device__ inline void zono_build(Zono& Z) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Z.m[k].x = -Z.g[k].y; Z.m[k].y = Z.g[k].x;
+    float hk = 0.f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) hk += fabsf(Z.m[k].x * Z.g[j].x + Z.m[k].y * Z.g[j].y);
+    Z.h[k] = hk;
+    const float len = sqrtf(Z.g[k].x * Z.g[k].x + Z.g[k].y * Z.g[k].y);
+    Z.use[k] = len > 1e-9f;
+    Z.tol[k] = 2e-7f * len;
+  }
+}
+
+__device__ inline bool zono_inside(const Zono& Z, V2 p) {
+  const float px = p.x - Z.c.x, py = p.y - Z.c.y;
+  bool in = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    in = in && (!Z.use[k] || fabsf(Z.m[k].x * px + Z.m[k].y * py) <= Z.h[k] + Z.tol[k]);
+  return in;
+}
+
+// CCW hexagon (possibly with repeated or collinear vertices) of the zonogon
+__device__ inline void zono_hexagon(const Zono& Z, V2 v[6]) {
+  V2 g[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g[k] = Z.g[k];
+    if (g[k].y < 0.f || (g[k].y == 0.f && g[k].x < 0.f)) { g[k].x = -g[k].x; g[k].y = -g[k].y; }
+  }
+  // sort by polar angle in [0, pi): a before b when cross(a, b) > 0
+  auto cswap = [](V2& a, V2& b) { if (cr2(a, b) < 0.f) { V2 t = a; a = b; b = t; } };
+  cswap(g[0], g[1]); cswap(g[1], g[2]); cswap(g[0], g[1]);
+  v[0].x = Z.c.x - (g[0].x + g[1].x + g[2].x); v[0].y = Z.c.y - (g[0].y + g[1].y + g[2].y);
+  v[1].x = v[0].x + 2.f * g[0].x; v[1].y = v[0].y + 2.f * g[0].y;
+  v[2].x = v[1].x + 2.f * g[1].x; v[2].y = v[1].y + 2.f * g[1].y;
+  v[3].x = v[2].x + 2.f * g[2].x; v[3].y = v[2].y + 2.f * g[2].y;
+  v[4].x = v[3].x - 2.f * g[0].x; v[4].y = v[3].y - 2.f * g[0].y;
+  v[5].x = v[4].x - 2.f * g[1].x; v[5].y = v[4].y - 2.f * g[1].y;
+}
+
+struct Extremes {
+  float best[4];
+  V2 p[4];
+  __device__ inline void init() {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { best[s] = -INFINITY; p[s].x = p[s].y = 0.f; }
+  }
+  // diagonals (+,+), (-,+), (-,-), (+,-); the first candidate wins ties
+  __device__ inline void consider(V2 q) {
+    const float a = q.x + q.y, b = q.y - q.x;
+    if (a > best[0]) { best[0] = a; p[0] = q; }
+    if (b > best[1]) { best[1] = b; p[1] = q; }
+    if (-a > best[2]) { best[2] = -a; p[2] = q; }
+    if (-b > best[3]) { best[3] = -b; p[3] = q; }
+  }
+};
+
+// returns number of points; rA[j] relative to A's centre, slot[j] in 0..3
+__device__ int manifold_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
+                              const float d[3], const float n[3], float t1[3], float t2[3], float rA[4][3],
+                              int slot[4]) {
+  tangent_basis(n, t1, t2);
+  Zono ZA, ZB;
+  float zA = 0.f, zB = dot3(d, n);
+  ZA.c.x = 0.f; ZA.c.y = 0.f;
+  ZB.c.x = dot3(d, t1); ZB.c.y = dot3(d, t2);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float a[3] = {RA[i], RA[3 + i], RA[6 + i]};
+    const float b[3] = {RB[i], RB[3 + i], RB[6 + i]};
+    ZA.g[i].x = heA[i] * dot3(a, t1); ZA.g[i].y = heA[i] * dot3(a, t2);
+    ZB.g[i].x = heB[i] * dot3(b, t1); ZB.g[i].y = heB[i] * dot3(b, t2);
+    zA += heA[i] * fabsf(dot3(a, n));
+    zB -= heB[i] * fabsf(dot3(b, n));
+  }
+  zono_build(ZA);
+  zono_build(ZB);
+  Extremes E;
+  E.init();
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float s0 = (k & 1) ? 1.f : -1.f, s1 = (k & 2) ? 1.f : -1.f, s2 = (k & 4) ? 1.f : -1.f;
+    V2 pa, pb;
+    pa.x = s0 * ZA.g[0].x + s1 * ZA.g[1].x + s2 * ZA.g[2].x;
+    pa.y = s0 * ZA.g[0].y + s1 * ZA.g[1].y + s2 * ZA.g[2].y;
+    pb.x = ZB.c.x + s0 * ZB.g[0].x + s1 * ZB.g[1].x + s2 * ZB.g[2].x;
+    pb.y = ZB.c.y + s0 * ZB.g[0].y + s1 * ZB.g[1].y + s2 * ZB.g[2].y;
+    if (zono_inside(ZB, pa)) { E.consider(pa); any = true; }
+    if (zono_inside(ZA, pb)) { E.consider(pb); any = true; }
+  }
+  V2 ha[6], hb[6];
+  zono_hexagon(ZA, ha);
+  zono_hexagon(ZB, hb);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const V2 p0 = ha[i], p1 = ha[(i + 1) % 6];
+    const V2 u = {p1.x - p0.x, p1.y - p0.y};
+    const float lu = u.x * u.x + u.y * u.y;
+    if (lu < 1e-18f) continue;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const V2 q0 = hb[j], q1 = hb[(j + 1) % 6];
+      const V2 w = {q1.x - q0.x, q1.y - q0.y};
+      const float den = cr2(u, w);
+      const float lw = w.x * w.x + w.y * w.y;
+      if (den * den <= 1e-12f * lu * lw) continue;   // parallel edges
+      const V2 r = {q0.x - p0.x, q0.y - p0.y};
+      const float t = cr2(r, w) / den, s = cr2(r, u) / den;
+      if (t >= -1e-6f && t <= 1.f + 1e-6f && s >= -1e-6f && s <= 1.f + 1e-6f) {
+        V2 pt = {p0.x + t * u.x, p0.y + t * u.y};
+        E.consider(pt);
+        any = true;
+      }
+    }
+  }
+  const float zmid = 0.5f * (zA + zB);
+  if (!any) {
+    // empty clip: halfway between the support corners of A (max along n) and B (min)
+    int ka = 0, kb = 0;
+    float ba = -INFINITY, bb = INFINITY;
+    float ca[3] = {0, 0, 0}, cb[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float s[3] = {(k & 1) ? heA[0] : -heA[0], (k & 2) ? heA[1] : -heA[1], (k & 4) ? heA[2] : -heA[2]};
+      const float sb[3] = {(k & 1) ? heB[0] : -heB[0], (k & 2) ? heB[1] : -heB[1], (k & 4) ? heB[2] : -heB[2]};
+      float pa[3], pb[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        pa[r] = RA[3 * r] * s[0] + RA[3 * r + 1] * s[1] + RA[3 * r + 2] * s[2];
+        pb[r] = d[r] + RB[3 * r] * sb[0] + RB[3 * r + 1] * sb[1] + RB[3 * r + 2] * sb[2];
+      }
+      const float da = dot3(pa, n), db = dot3(pb, n);
+      if (da > ba) { ba = da; ka = k; ca[0] = pa[0]; ca[1] = pa[1]; ca[2] = pa[2]; }
+      if (db < bb) { bb = db; kb = k; cb[0] = pb[0]; cb[1] = pb[1]; cb[2] = pb[2]; }
+    }
+    (void)ka; (void)kb;
+    rA[0][0] = 0.5f * (ca[0] + cb[0]); rA[0][1] = 0.5f * (ca[1] + cb[1]); rA[0][2] = 0.5f * (ca[2] + cb[2]);
+    slot[0] = 0;
+    return 1;
+  }
+  int np = 0;
+  V2 kept[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (E.best[s] == -INFINITY) continue;
+    bool dup = false;
+    for (int c = 0; c < np; ++c) {
+      const float dx = E.p[s].x - kept[c].x, dy = E.p[s].y - kept[c].y;
+      dup = dup || (dx * dx + dy * dy < 1e-12f);
+    }
+    if (dup) continue;
+    kept[np] = E.p[s];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) rA[np][r] = E.p[s].x * t1[r] + E.p[s].y * t2[r] + zmid * n[r];
+    slot[np] = s;
+    ++np;
+  }
+  return np;
+}
+
+// ------------------------------------------------------------------------------------------------
+// one contact point's three rows (Eq. (lambda_n), Eq. (coulomb_pgs)); A gets -P, B gets +P
+// ------------------------------------------------------------------------------------------------
+struct BodyRegs {
+  float v[3], w[3], I[6], im;
+  bool dyn;
+};
+
+__device__ inline void apply_row(BodyRegs& A, BodyRegs& B, const float rA[3], const float rB[3], const float d[3],
+                                 float dl) {
+  float cA[3], cB[3], iA[3], iB[3];
+  cross3(rA, d, cA);
+  cross3(rB, d, cB);
+  sym_mul(A.I, cA, iA);
+  sym_mul(B.I, cB, iB);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A.v[k] -= A.im * dl * d[k]; A.w[k] -= dl * iA[k];
+    B.v[k] += B.im * dl * d[k]; B.w[k] += dl * iB[k];
+  }
+}
+
+// solves row d: normal (bound < 0 means the non-negative clamp with restitution) or tangent
+template <bool kNormal>
+__device__ inline float solve_row(BodyRegs& A, BodyRegs& B, const float rA[3], const float rB[3], const float d[3],
+                                  float lam, float bound, float e) {
+  float cA[3], cB[3], iA[3], iB[3];
+  cross3(rA, d, cA);
+  cross3(rB, d, cB);
+  const float vrel = d[0] * (B.v[0] - A.v[0]) + d[1] * (B.v[1] - A.v[1]) + d[2] * (B.v[2] - A.v[2]) +
+                     dot3(cB, B.w) - dot3(cA, A.w);
+  sym_mul(A.I, cA, iA);
+  sym_mul(B.I, cB, iB);
+  const float k = A.im + B.im + dot3(cA, iA) + dot3(cB, iB);
+  float nl;
+  if (kNormal) {
+    nl = fmaxf(lam - (1.f + e) * vrel / k, 0.f);
+  } else {
+    nl = fminf(fmaxf(lam - vrel / k, -bound), bound);
+  }
+  const float dl = nl - lam;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    A.v[q] -= A.im * dl * d[q]; A.w[q] -= dl * iA[q];
+    B.v[q] += B.im * dl * d[q]; B.w[q] += dl * iB[q];
+  }
+  return nl;
+}
+
+__device__ inline void load_body(const Lds& L, int i, BodyRegs& b) {
+  if (i == (int)kGround || !(L.flag[i] & kDynamic)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { b.v[k] = 0.f; b.w[k] = 0.f; }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) b.I[k] = 0.f;
+    b.im = 0.f;
+    b.dyn = false;
+    return;
+  }
+  const int nb = L.nbp;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { b.v[k] = L.v[k * nb + i]; b.w[k] = L.w[k * nb + i]; }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) b.I[k] = L.Iw[k * nb + i];
+  b.im = L.invm[i];
+  b.dyn = true;
+}
+
+__device__ inline void store_body(const Lds& L, int i, const BodyRegs& b) {
+  if (!b.dyn) return;
+  const int nb = L.nbp;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { L.v[k * nb + i] = b.v[k]; L.w[k * nb + i] = b.w[k]; }
+}
+
+__device__ inline void manifold_bodies(const Lds& L, int m, int& a, int& b, BodyRegs& A, BodyRegs& B,
+                                       float dAB[3]) {
+  const uint32_t ab = L.mab[m];
+  a = (int)(ab >> 16);
+  b = (int)(ab & 0xffffu);
+  load_body(L, a, A);
+  load_body(L, b, B);
+  if (b != (int)kGround) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dAB[k] = L.x[k * L.nbp + a] - L.x[k * L.nbp + b];
+  } else {
+    dAB[0] = dAB[1] = dAB[2] = 0.f;
+  }
+}
+
+__device__ inline void manifold_frame(const Lds& L, int m, float n[3], float t1[3], float t2[3]) {
+  const int pc = L.pc;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { n[k] = L.mn[k * pc + m]; t1[k] = L.mt1[k * pc + m]; }
+  cross3(n, t1, t2);
+}
+
+__device__ void solve_manifold(const Lds& L, int m, float mu, float e) {
+  const int pc = L.pc;
+  int a, b;
+  BodyRegs A, B;
+  float dAB[3], n[3], t1[3], t2[3];
+  manifold_bodies(L, m, a, b, A, B, dAB);
+  manifold_frame(L, m, n, t1, t2);
+  const int np = (int)(L.mmeta[m] & 15u);
+  for (int j = 0; j < np; ++j) {
+    float rA[3], rB[3], lam[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rA[k] = L.mr[(j * 3 + k) * pc + m];
+      rB[k] = rA[k] + dAB[k];
+      lam[k] = L.ml[(j * 3 + k) * pc + m];
+    }
+    lam[0] = solve_row<true>(A, B, rA, rB, n, lam[0], 0.f, e);
+    const float bound = mu * lam[0];
+    lam[1] = solve_row<false>(A, B, rA, rB, t1, lam[1], bound, e);
+    lam[2] = solve_row<false>(A, B, rA, rB, t2, lam[2], bound, e);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) L.ml[(j * 3 + k) * pc + m] = lam[k];
+  }
+  store_body(L, a, A);
+  if (b != (int)kGround) store_body(L, b, B);
+}
+
+__device__ void warm_apply_manifold(const Lds& L, int m) {
+  const int pc = L.pc;
+  int a, b;
+  BodyRegs A, B;
+  float dAB[3], n[3], t1[3], t2[3];
+  manifold_bodies(L, m, a, b, A, B, dAB);
+  manifold_frame(L, m, n, t1, t2);
+  const int np = (int)(L.mmeta[m] & 15u);
+  for (int j = 0; j < np; ++j) {
+    float rA[3], rB[3], lam[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rA[k] = L.mr[(j * 3 + k) * pc + m];
+      rB[k] = rA[k] + dAB[k];
+      lam[k] = L.ml[(j * 3 + k) * pc + m];
+    }
+    apply_row(A, B, rA, rB, n, lam[0]);
+    apply_row(A, B, rA, rB, t1, lam[1]);
+    apply_row(A, B, rA, rB, t2, lam[2]);
+  }
+  store_body(L, a, A);
+  if (b != (int)kGround) store_body(L, b, B);
+}
+
+// natural-map residual of one manifold: returns sum of squares, max |r|
+__device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, float& mx) {
+  const int pc = L.pc;
+  int a, b;
+  BodyRegs A, B;
+  float dAB[3], n[3], t1[3], t2[3];
+  manifold_bodies(L, m, a, b, A, B, dAB);
+  manifold_frame(L, m, n, t1, t2);
+  const int np = (int)(L.mmeta[m] & 15u);
+  sum = 0.f;
+  mx = 0.f;
+  for (int j = 0; j < np; ++j) {
+    float rA[3], rB[3], lam[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rA[k] = L.mr[(j * 3 + k) * pc + m];
+      rB[k] = rA[k] + dAB[k];
+      lam[k] = L.ml[(j * 3 + k) * pc + m];
+    }
+    const float* dirs[3] = {n, t1, t2};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float* d = dirs[r];
+      float cA[3], cB[3], iA[3], iB[3];
+      cross3(rA, d, cA);
+      cross3(rB, d, cB);
+      const float vrel = d[0] * (B.v[0] - A.v[0]) + d[1] * (B.v[1] - A.v[1]) + d[2] * (B.v[2] - A.v[2]) +
+                         dot3(cB, B.w) - dot3(cA, A.w);
+      sym_mul(A.I, cA, iA);
+      sym_mul(B.I, cB, iB);
+      const float k = A.im + B.im + dot3(cA, iA) + dot3(cB, iB);
+      float res;
+      if (r == 0) {
+        res = fminf(k * lam[0], vrel);
+      } else {
+        const float bound = mu * lam[0];
+        const float cl = fminf(fmaxf(lam[r] - vrel / k, -bound), bound);
+        res = k * (lam[r] - cl);
+      }
+      sum += res * res;
+      mx = fmaxf(mx, fabsf(res));
+    }
+  }
+}
+
+__device__ inline uint64_t lane_lt_mask(int lane) { return lane ? ((~0ull) >> (64 - lane)) : 0ull; }
+
+// ------------------------------------------------------------------------------------------------
+// the kernel
+// ------------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
+  extern __shared__ float smem[];
+  const Lds L = carve(smem, a);
+  const int lane = threadIdx.x;
+  const int pk = blockIdx.x;
+  const int gb0 = a.pack_body0[pk], nb = a.pack_body0[pk + 1] - gb0;
+  const int gt0 = a.pack_tower0[pk], nt = a.pack_tower0[pk + 1] - gt0;
+  const int gp0 = a.pack_push0[pk], np = a.pack_push0[pk + 1] - gp0;
+  const int NB = L.nbp, PC = L.pc, CAP = a.cap;
+
+  // ---- load the pack ----
+  for (int i = lane; i < nb; i += kWave) {
+    const int g = gb0 + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      L.x[k * NB + i] = a.x[k * CAP + g];
+      L.v[k * NB + i] = a.v[k * CAP + g];
+      L.w[k * NB + i] = a.w[k * CAP + g];
+      L.he[k * NB + i] = a.he[k * CAP + g];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.q[k * NB + i] = a.q[k * CAP + g];
+    // inverse mass and inverse body inertia, Eq. (inertia) with l, w, h the full sizes
+    const float m = a.mass[g];
+    const float l = 2.f * a.he[g], wd = 2.f * a.he[CAP + g], hh = 2.f * a.he[2 * CAP + g];
+    const bool dyn = m > 0.f;
+    L.invm[i] = dyn ? 1.f / m : 0.f;
+    L.invI[i] = dyn ? 1.f / (m / 12.f * (wd * wd + hh * hh)) : 0.f;
+    L.invI[NB + i] = dyn ? 1.f / (m / 12.f * (l * l + hh * hh)) : 0.f;
+    L.invI[2 * NB + i] = dyn ? 1.f / (m / 12.f * (l * l + wd * wd)) : 0.f;
+    L.flag[i] = a.flags[g];
+    L.tw[i] = a.body_tower[g] - gt0;
+  }
+  for (int t = lane; t < nt; t += kWave) {
+    L.tb0[t] = a.tower_body0[gt0 + t] - gb0;
+    L.tb1[t] = a.tower_body0[gt0 + t + 1] - gb0;
+    L.mu[t] = a.tower_mu[gt0 + t];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.tcnt[t * 4 + k] = 0u;
+    L.tres[2 * t] = 0.f;
+    L.tres[2 * t + 1] = 0.f;
+  }
+  for (int r = lane; r < np; r += kWave) {
+    const int g = gp0 + r;
+    L.pb[r] = a.push_body[g] - gb0;
+    L.ps[r] = a.push_start[g];
+    L.pn[r] = a.push_steps[g];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { L.pf[3 * r + k] = a.push_force[3 * g + k]; L.px0[3 * r + k] = a.push_x0[3 * g + k]; }
+    L.pwd[r] = a.push_withdraw[g];
+  }
+  if (lane == 0) {
+    L.scal[3] = 0;                                   // error bits
+    L.scal[4] = a.warm_start ? a.prev_count[pk] : 0; // previous-step manifolds
+  }
+  if (a.warm_start) {
+    const int npv = a.prev_count[pk];
+    for (int p = lane; p < npv; p += kWave) {
+      const int g = pk * PC + p;
+      L.pkey[p] = a.prev_key[g];
+      L.pslot[p] = __float_as_uint(a.prev_data[16 * g + 3]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) L.pnrm[k * PC + p] = a.prev_data[16 * g + k];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) L.plam[k * PC + p] = a.prev_data[16 * g + 4 + k];
+    }
+  }
+  __syncthreads();
+
+  const float dt = a.dt, e = a.restitution;
+  for (int s = 0; s < a.n_steps; ++s) {
+    const int64_t step = a.step0 + s;
+    for (int r = lane; r < np; r += kWave)
+      if ((int64_t)L.ps[r] == step) {
+        const int b = L.pb[r];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L.px0[3 * r + k] = L.x[k * NB + b];
+      }
+    __syncthreads();
+    for (int sub = 0; sub < a.n_sub; ++sub) {
+      const bool last = (s == a.n_steps - 1) && (sub == a.n_sub - 1);
+      // ---- 1. external forces; 2. frames ----
+      for (int i = lane; i < nb; i += kWave) {
+        const uint32_t f = L.flag[i];
+        if ((f & (kActive | kDynamic)) == (kActive | kDynamic)) {
+          float vv[3];
+          load3(L.v, NB, i, vv);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) vv[k] += dt * a.g[k];
+          const float im = L.invm[i];
+          for (int r = 0; r < np; ++r)
+            if (L.pb[r] == i && step >= (int64_t)L.ps[r] && step < (int64_t)L.ps[r] + L.pn[r]) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) vv[k] += dt * L.pf[3 * r + k] * im;
+            }
+          store3(L.v, NB, i, vv);
+        }
+        float R[9];
+        quat_rot(L.q[i], L.q[NB + i], L.q[2 * NB + i], L.q[3 * NB + i], R);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) L.R[k * NB + i] = R[k];
+        const float he0 = L.he[i], he1 = L.he[NB + i], he2 = L.he[2 * NB + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          L.h[k * NB + i] = fabsf(R[3 * k]) * he0 + fabsf(R[3 * k + 1]) * he1 + fabsf(R[3 * k + 2]) * he2;
+        float d[3];
+        if ((f & (kActive | kDynamic)) == (kActive | kDynamic)) load3(L.invI, NB, i, d);
+        else d[0] = d[1] = d[2] = 0.f;
+        // R diag(d) R^T
+        float I6[6];
+        I6[0] = R[0] * d[0] * R[0] + R[1] * d[1] * R[1] + R[2] * d[2] * R[2];
+        I6[1] = R[3] * d[0] * R[3] + R[4] * d[1] * R[4] + R[5] * d[2] * R[5];
+        I6[2] = R[6] * d[0] * R[6] + R[7] * d[1] * R[7] + R[8] * d[2] * R[8];
+        I6[3] = R[0] * d[0] * R[3] + R[1] * d[1] * R[4] + R[2] * d[2] * R[5];
+        I6[4] = R[0] * d[0] * R[6] + R[1] * d[1] * R[7] + R[2] * d[2] * R[8];
+        I6[5] = R[3] * d[0] * R[6] + R[4] * d[1] * R[7] + R[5] * d[2] * R[8];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) L.Iw[k * NB + i] = I6[k];
+        L.mask[2 * i] = 0u;
+        L.mask[2 * i + 1] = 0u;
+      }
+      for (int c = lane; c <= kMaxColours; c += kWave) L.colcnt[c] = 0;
+      for (int t = lane; t < nt; t += kWave) L.tcnt[t * 4 + 3] = 0u;
+      __syncthreads();
+
+      // ---- 3. broadphase: same-tower pairs i<j, then the ground, in canonical order ----
+      int ncand = 0;
+      for (int i = 0; i < nb; ++i) {
+        const uint32_t fi = L.flag[i];
+        if (!(fi & kActive)) continue;
+        const bool dyni = (fi & kDynamic) != 0;
+        const int ti = L.tw[i];
+        const int npair = L.tb1[ti] - i - 1;
+        const float xi0 = L.x[i], xi1 = L.x[NB + i], xi2 = L.x[2 * NB + i];
+        const float hi0 = L.h[i], hi1 = L.h[NB + i], hi2 = L.h[2 * NB + i];
+        for (int c0 = 0; c0 <= npair; c0 += kWave) {
+          const int jj = c0 + lane;
+          bool hit = false;
+          uint32_t code = 0;
+          if (jj < npair) {
+            const int j = i + 1 + jj;
+            const uint32_t fj = L.flag[j];
+            if ((fj & kActive) && (dyni || (fj & kDynamic))) {
+              hit = fabsf(xi0 - L.x[j]) <= hi0 + L.h[j] + a.margin &&
+                    fabsf(xi1 - L.x[NB + j]) <= hi1 + L.h[NB + j] + a.margin &&
+                    fabsf(xi2 - L.x[2 * NB + j]) <= hi2 + L.h[2 * NB + j] + a.margin;
+            }
+            code = ((uint32_t)i << 16) | (uint32_t)j;
+          } else if (jj == npair) {
+            hit = dyni && (xi2 - hi2 <= a.margin);
+            code = ((uint32_t)i << 16) | kGround;
+          }
+          const uint64_t bal = __ballot(hit);
+          if (hit) {
+            const int idx = ncand + __popcll(bal & lane_lt_mask(lane));
+            if (idx < L.cc) L.cand[idx] = code;
+          }
+          if (lane == 0) L.tcnt[ti * 4 + 0] += (uint32_t)__popcll(bal);
+          ncand += __popcll(bal);
+        }
+      }
+      if (ncand > L.cc) {
+        if (lane == 0) L.scal[3] |= kErrCand;
+        ncand = L.cc;
+      }
+      __syncthreads();
+
+      // ---- 4. narrowphase (canonical order kept by stable compaction) ----
+      int nman = 0;
+      for (int c0 = 0; c0 < ncand; c0 += kWave) {
+        const int c = c0 + lane;
+        bool hit = false;
+        uint32_t code = 0;
+        float n[3] = {0.f, 0.f, -1.f}, depth = 0.f;
+        if (c < ncand) {
+          code = L.cand[c];
+          const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
+          if (j == (int)kGround) {
+            const float zlow = L.x[2 * NB + i] - L.h[2 * NB + i];
+            hit = zlow < 0.f;
+            depth = -zlow;
+          } else {
+            float RA[9], RB[9], heA[3], heB[3], d[3];
+            load_R(L, i, RA);
+            load_R(L, j, RB);
+            load3(L.he, NB, i, heA);
+            load3(L.he, NB, j, heB);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
+            hit = sat_boxes(RA, heA, RB, heB, d, n, depth);
+          }
+        }
+        const uint64_t bal = __ballot(hit);
+        if (hit) {
+          const int idx = nman + __popcll(bal & lane_lt_mask(lane));
+          if (idx < PC) {
+            L.cab[idx] = code;
+            L.cn[idx] = n[0]; L.cn[PC + idx] = n[1]; L.cn[2 * PC + idx] = n[2];
+            L.cdepth[idx] = depth;
+          }
+        }
+        nman += __popcll(bal);
+      }
+      if (nman > PC) {
+        if (lane == 0) L.scal[3] |= kErrMan;
+        nman = PC;
+      }
+      __syncthreads();
+
+      // ---- 5. greedy first-fit colouring over the canonical list ----
+      if (lane == 0) {
+        for (int p = 0; p < nman; ++p) {
+          const uint32_t code = L.cab[p];
+          const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
+          const bool di = (L.flag[i] & kDynamic) != 0;
+          const bool dj = j != (int)kGround && (L.flag[j] & kDynamic);
+          uint64_t u = 0;
+          if (di) u |= (uint64_t)L.mask[2 * i] | ((uint64_t)L.mask[2 * i + 1] << 32);
+          if (dj) u |= (uint64_t)L.mask[2 * j] | ((uint64_t)L.mask[2 * j + 1] << 32);
+          if (u == ~0ull) {
+            L.scal[3] |= kErrCol;
+            L.cpos[p] = -1;
+            continue;
+          }
+          const int col = __ffsll((unsigned long long)~u) - 1;
+          const uint64_t bit = 1ull << col;
+          if (di) { L.mask[2 * i] |= (uint32_t)bit; L.mask[2 * i + 1] |= (uint32_t)(bit >> 32); }
+          if (dj) { L.mask[2 * j] |= (uint32_t)bit; L.mask[2 * j + 1] |= (uint32_t)(bit >> 32); }
+          L.colcnt[col] += 1;
+          L.cpos[p] = col;
+          const int ti = L.tw[i];
+          if ((uint32_t)(col + 1) > L.tcnt[ti * 4 + 3]) L.tcnt[ti * 4 + 3] = (uint32_t)(col + 1);
+        }
+        int ncol = 0;
+        L.coloff[0] = 0;
+        for (int c = 0; c < kMaxColours; ++c) {
+          L.coloff[c + 1] = L.coloff[c] + L.colcnt[c];
+          if (L.colcnt[c]) ncol = c + 1;
+          L.colcnt[c] = L.coloff[c];
+        }
+        for (int p = 0; p < nman; ++p) {
+          const int col = L.cpos[p];
+          if (col >= 0) L.cpos[p] = L.colcnt[col]++;
+        }
+        L.scal[2] = ncol;
+      }
+      __syncthreads();
+      const int ncol = L.scal[2];
+      const int nkept = L.coloff[ncol];
+
+      // ---- 6. manifolds into colour-sorted slots (+ warm start lookup) ----
+      const int nprev = L.scal[4];
+      for (int p = lane; p < nman; p += kWave) {
+        const int sidx = L.cpos[p];
+        if (sidx < 0) continue;
+        const uint32_t code = L.cab[p];
+        const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
+        float n[3] = {L.cn[p], L.cn[PC + p], L.cn[2 * PC + p]};
+        float t1[3], t2[3], rA[4][3];
+        int slot[4];
+        int npts = 0;
+        float depth = L.cdepth[p];
+        if (j == (int)kGround) {
+          float R[9], he[3];
+          load_R(L, i, R);
+          load3(L.he, NB, i, he);
+          const float xz = L.x[2 * NB + i];
+          float vz[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
+            vz[k] = xz + (R[6] * s0 + R[7] * s1 + R[8] * s2);
+          }
+          depth = 0.f;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (!(vz[k] < 0.f)) continue;
+            int rank = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rank += (vz[q] < 0.f) && (vz[q] < vz[k] || (vz[q] == vz[k] && q < k));
+            if (rank >= 4) continue;
+            const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
+            rA[npts][0] = R[0] * s0 + R[1] * s1 + R[2] * s2;
+            rA[npts][1] = R[3] * s0 + R[4] * s1 + R[5] * s2;
+            const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
+            rA[npts][2] = 0.5f * (rz - xz);
+            slot[npts] = k;
+            depth = fmaxf(depth, -vz[k]);
+            ++npts;
+          }
+          n[0] = 0.f; n[1] = 0.f; n[2] = -1.f;
+          t1[0] = 1.f; t1[1] = 0.f; t1[2] = 0.f;
+        } else {
+          float RA[9], RB[9], heA[3], heB[3], d[3];
+          load_R(L, i, RA);
+          load_R(L, j, RB);
+          load3(L.he, NB, i, heA);
+          load3(L.he, NB, j, heB);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
+          npts = manifold_boxes(RA, heA, RB, heB, d, n, t1, t2, rA, slot);
+        }
+        // warm start: previous step's impulses of the same (pair, slot) if the normal barely turned
+        float lam0[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lam0[q][0] = lam0[q][1] = lam0[q][2] = 0.f;
+        if (a.warm_start && nprev > 0) {
+          int lo = 0, hi = nprev - 1, found = -1;
+          while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const uint32_t kk = L.pkey[mid];
+            if (kk == code) { found = mid; break; }
+            if (kk < code) lo = mid + 1; else hi = mid - 1;
+          }
+          if (found >= 0) {
+            const float pn[3] = {L.pnrm[found], L.pnrm[PC + found], L.pnrm[2 * PC + found]};
+            if (dot3(pn, n) > 0.95f) {
+              const uint32_t ps = L.pslot[found];
+              const int pnp = (int)(ps & 15u);
+              for (int q = 0; q < npts; ++q)
+                for (int r = 0; r < pnp; ++r)
+                  if ((int)((ps >> (4 + 4 * r)) & 15u) == slot[q]) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) lam0[q][k] = L.plam[(r * 3 + k) * PC + found];
+                  }
+            }
+          }
+        }
+        uint32_t meta = (uint32_t)npts;
+        for (int q = 0; q < npts; ++q) meta |= (uint32_t)slot[q] << (12 + 4 * q);
+        L.mab[sidx] = code;
+        L.mmeta[sidx] = meta;
+        L.mcanon[sidx] = p;
+        L.mdepth[sidx] = depth;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { L.mn[k * PC + sidx] = n[k]; L.mt1[k * PC + sidx] = t1[k]; }
+        for (int q = 0; q < npts; ++q)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            L.mr[(q * 3 + k) * PC + sidx] = rA[q][k];
+            L.ml[(q * 3 + k) * PC + sidx] = lam0[q][k];
+          }
+        const int ti = L.tw[i];
+        atomicAdd(&L.tcnt[ti * 4 + 1], 1u);
+        atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
+      }
+      __syncthreads();
+
+      // ---- 7. warm-start impulses, then PGS sweeps, colour by colour ----
+      if (a.warm_start) {
+        for (int col = 0; col < ncol; ++col) {
+          for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) warm_apply_manifold(L, m);
+          __syncthreads();
+        }
+      }
+      for (int it = 0; it < a.iters; ++it) {
+        for (int col = 0; col < ncol; ++col) {
+          for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
+            const float mu = L.mu[L.tw[L.mab[m] >> 16]];
+            solve_manifold(L, m, mu, e);
+          }
+          __syncthreads();
+        }
+      }
+
+      // ---- 8. residual: per manifold partials, then per tower in solve order ----
+      for (int m = lane; m < nkept; m += kWave) {
+        float sum, mx;
+        const float mu = L.mu[L.tw[L.mab[m] >> 16]];
+        residual_manifold(L, m, mu, sum, mx);
+        L.cn[m] = sum;
+        L.cn[PC + m] = mx;
+      }
+      __syncthreads();
+      for (int t = lane; t < nt; t += kWave) {
+        float sum = 0.f, mx = 0.f;
+        int rows = 0;
+        for (int m = 0; m < nkept; ++m) {
+          if (L.tw[L.mab[m] >> 16] != t) continue;
+          sum += L.cn[m];
+          mx = fmaxf(mx, L.cn[PC + m]);
+          rows += 3 * (int)(L.mmeta[m] & 15u);
+        }
+        L.tres[2 * t] = rows ? sqrtf(sum / (float)rows) : 0.f;
+        L.tres[2 * t + 1] = mx;
+      }
+      // contacts of the final step, and the warm-start store
+      if (last) {
+        for (int m = lane; m < nkept; m += kWave) {
+          const int a_ = (int)(L.mab[m] >> 16);
+          const int g = pk * PC + m;
+          int col = 0;
+          while (col + 1 < ncol && L.coloff[col + 1] <= m) ++col;
+          a.out_ab[g] = L.mab[m];
+          a.out_meta[g] = (L.mmeta[m] & 0x0ffff00fu) | ((uint32_t)col << 4);
+          a.out_tower[g] = L.tw[a_];
+          for (int k = 0; k < 3; ++k) {
+            a.out_geo[8 * g + k] = L.mn[k * PC + m];
+            a.out_geo[8 * g + 3 + k] = L.mt1[k * PC + m];
+          }
+          a.out_geo[8 * g + 6] = L.mdepth[m];
+          a.out_geo[8 * g + 7] = 0.f;
+          const int npts = (int)(L.mmeta[m] & 15u);
+          for (int q = 0; q < 4; ++q)
+            for (int k = 0; k < 3; ++k) {
+              const float r = q < npts ? L.mr[(q * 3 + k) * PC + m] : 0.f;
+              a.out_pts[24 * g + 6 * q + k] = L.x[k * NB + a_] + r;
+              a.out_pts[24 * g + 6 * q + 3 + k] = q < npts ? L.ml[(q * 3 + k) * PC + m] : 0.f;
+            }
+        }
+        if (lane == 0) a.out_count[pk] = nkept;
+      }
+      if (a.warm_start) {
+        // canonical-order store of this step's impulses (dropped pairs keep their key, no points)
+        for (int p = lane; p < nman; p += kWave) { L.pkey[p] = L.cab[p]; L.pslot[p] = 0u; }
+        __syncthreads();
+        for (int m = lane; m < nkept; m += kWave) {
+          const int p = L.mcanon[m];
+          const uint32_t meta = L.mmeta[m];
+          const int npts = (int)(meta & 15u);
+          uint32_t ps = (uint32_t)npts;
+          for (int q = 0; q < npts; ++q) ps |= ((meta >> (12 + 4 * q)) & 15u) << (4 + 4 * q);
+          L.pslot[p] = ps;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) L.pnrm[k * PC + p] = L.mn[k * PC + m];
+          for (int k = 0; k < 12; ++k) L.plam[k * PC + p] = L.ml[k * PC + m];
+        }
+        if (lane == 0) L.scal[4] = nman;
+      }
+      __syncthreads();
+
+      // ---- 9. integrate ----
+      for (int i = lane; i < nb; i += kWave) {
+        const uint32_t f = L.flag[i];
+        if ((f & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
+        float xv[3], vv[3], wv[3], R[9], Ib[3], iIb[3];
+        load3(L.x, NB, i, xv);
+        load3(L.v, NB, i, vv);
+        load3(L.w, NB, i, wv);
+        load_R(L, i, R);
+        load3(L.invI, NB, i, iIb);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { xv[k] += dt * vv[k]; Ib[k] = 1.f / iIb[k]; }
+        // L = R Ib R^T w
+        float bw[3], Lw[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bw[k] = (R[k] * wv[0] + R[3 + k] * wv[1] + R[6 + k] * wv[2]) * Ib[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Lw[r] = R[3 * r] * bw[0] + R[3 * r + 1] * bw[1] + R[3 * r + 2] * bw[2];
+        float qw = L.q[i], qx = L.q[NB + i], qy = L.q[2 * NB + i], qz = L.q[3 * NB + i];
+        const float hd = 0.5f * dt;
+        const float dw = -(wv[0] * qx + wv[1] * qy + wv[2] * qz);
+        const float dx = wv[0] * qw + (wv[1] * qz - wv[2] * qy);
+        const float dy = wv[1] * qw + (wv[2] * qx - wv[0] * qz);
+        const float dz = wv[2] * qw + (wv[0] * qy - wv[1] * qx);
+        qw += hd * dw; qx += hd * dx; qy += hd * dy; qz += hd * dz;
+        const float il = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw *= il; qx *= il; qy *= il; qz *= il;
+        quat_rot(qw, qx, qy, qz, R);
+        float bl[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bl[k] = (R[k] * Lw[0] + R[3 + k] * Lw[1] + R[6 + k] * Lw[2]) * iIb[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) wv[r] = R[3 * r] * bl[0] + R[3 * r + 1] * bl[1] + R[3 * r + 2] * bl[2];
+        bool finite = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) finite = finite && isfinite(xv[k]) && isfinite(vv[k]) && isfinite(wv[k]);
+        finite = finite && isfinite(qw);
+        if (!finite) atomicOr((uint32_t*)&L.scal[3], kErrNan);
+        store3(L.x, NB, i, xv);
+        store3(L.w, NB, i, wv);
+        L.q[i] = qw; L.q[NB + i] = qx; L.q[2 * NB + i] = qy; L.q[3 * NB + i] = qz;
+      }
+      __syncthreads();
+      // ---- 10. Baumgarte position correction, colour by colour ----
+      for (int col = 0; col < ncol; ++col) {
+        for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
+          const uint32_t ab = L.mab[m];
+          const int i = (int)(ab >> 16), j = (int)(ab & 0xffffu);
+          const bool di = (L.flag[i] & kDynamic) != 0;
+          const bool dj = j != (int)kGround && (L.flag[j] & kDynamic);
+          const float ia = di ? L.invm[i] : 0.f, ib = dj ? L.invm[j] : 0.f;
+          float corr = L.mdepth[m] - a.slop;
+          if (ia + ib <= 0.f || corr <= 0.f) continue;
+          corr /= (ia + ib);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const float nk = L.mn[k * PC + m];
+            if (di) L.x[k * NB + i] -= a.beta * ia * corr * nk;
+            if (dj) L.x[k * NB + j] += a.beta * ib * corr * nk;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // ---- withdrawal of pushed bodies ----
+    for (int r = lane; r < np; r += kWave) {
+      const int b = L.pb[r];
+      if (!(L.pwd[r] > 0.f) || step < (int64_t)L.ps[r] || !(L.flag[b] & kActive)) continue;
+      float dx[3], f[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { dx[k] = L.x[k * NB + b] - L.px0[3 * r + k]; f[k] = L.pf[3 * r + k]; }
+      if (dot3(dx, f) >= L.pwd[r] * sqrtf(dot3(f, f))) {
+        atomicAnd(&L.flag[b], ~kActive);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { L.v[k * NB + b] = 0.f; L.w[k * NB + b] = 0.f; }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write the pack back ----
+  for (int i = lane; i < nb; i += kWave) {
+    const int g = gb0 + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a.x[k * CAP + g] = L.x[k * NB + i];
+      a.v[k * CAP + g] = L.v[k * NB + i];
+      a.w[k * CAP + g] = L.w[k * NB + i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.q[k * CAP + g] = L.q[k * NB + i];
+    a.flags[g] = L.flag[i];
+  }
+  for (int t = lane; t < nt; t += kWave) {
+    const int g = gt0 + t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.tower_count[4 * g + k] += L.tcnt[4 * t + k];
+    a.tower_count[4 * g + 3] = L.tcnt[4 * t + 3];
+    a.tower_res[2 * g] = L.tres[2 * t];
+    a.tower_res[2 * g + 1] = L.tres[2 * t + 1];
+  }
+  for (int r = lane; r < np; r += kWave) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.push_x0[3 * (gp0 + r) + k] = L.px0[3 * r + k];
+  }
+  if (a.warm_start) {
+    const int npv = L.scal[4];
+    for (int p = lane; p < npv; p += kWave) {
+      const int g = pk * PC + p;
+      a.prev_key[g] = L.pkey[p];
+      a.prev_data[16 * g + 3] = __uint_as_float(L.pslot[p]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a.prev_data[16 * g + k] = L.pnrm[k * PC + p];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) a.prev_data[16 * g + 4 + k] = L.plam[k * PC + p];
+    }
+    if (lane == 0) a.prev_count[pk] = npv;
+  }
+  if (lane == 0) a.pack_error[pk] |= (uint32_t)L.scal[3];
+}
+
+}  // namespace
+
+void launch_step(const StepArgs& a, int threads, size_t lds_bytes, void* stream) {
+  (void)threads;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(step_kernel, dim3(a.n_packs), dim3(kWave), lds_bytes, (hipStream_t)stream, a);
+}
+
+}  // namespace jg

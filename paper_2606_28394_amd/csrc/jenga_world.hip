@@ -1,0 +1,718 @@
+// Host side of the C ABI (include/jenga.h): world bookkeeping, packing towers
+// into on-chip packs, host <-> device transfers, launches and queries.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/jenga.h"
+#include "jenga_device.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(JG_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t count) {
+    if (count <= n && p) return hipSuccess;
+    if (p) { hipFree(p); p = nullptr; n = 0; }
+    size_t c = count ? count : 1;
+    hipError_t e = hipMalloc((void**)&p, c * sizeof(T));
+    if (e == hipSuccess) n = c;
+    return e;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct PushRow {
+  int body;
+  double force[3];
+  int start, steps;
+  double withdraw;
+  double x0[3];
+};
+
+}  // namespace
+
+struct jg_world {
+  jg_params prm;
+  int max_towers = 0, max_bodies = 0;
+  hipStream_t stream = nullptr;
+  // host mirror, indexed by body id
+  std::vector<double> he, mass, x, q, v, w;
+  std::vector<uint8_t> active;
+  std::vector<int> body_tower;
+  std::vector<std::vector<int>> tower_bodies;
+  std::vector<double> mu;
+  std::vector<PushRow> pushes;
+  // state flags
+  bool layout_dirty = true;   // bodies, towers or pushes changed
+  bool host_dirty = true;     // host mirror newer than the device
+  bool device_newer = false;  // device newer than the host mirror
+  bool clear_warm = true;     // forget the previous step's impulses before the next launch
+  // layout (internal order)
+  std::vector<int> int_of_body, body_of_int;
+  std::vector<int> tower_order;      // internal tower slot -> tower id
+  std::vector<int> tower_slot;       // tower id -> internal slot
+  std::vector<int> pack_body0, pack_tower0, pack_push0;
+  std::vector<int> push_order;       // internal push row -> pushes index
+  std::vector<int> pack_of_tower;    // tower id -> pack
+  int n_packs = 0, nbp = 0, pc = 0, cc = 0, tpc = 0, ppc = 0;
+  size_t lds_bytes = 0;
+  // device buffers
+  DevBuf<float> d_x, d_q, d_v, d_w, d_he, d_mass;
+  DevBuf<uint32_t> d_flags;
+  DevBuf<int32_t> d_body_tower, d_pack_body0, d_pack_tower0, d_pack_push0, d_tower_body0;
+  DevBuf<float> d_tower_mu;
+  DevBuf<int32_t> d_push_body, d_push_start, d_push_steps;
+  DevBuf<float> d_push_force, d_push_withdraw, d_push_x0;
+  DevBuf<uint32_t> d_tower_count;
+  DevBuf<float> d_tower_res;
+  DevBuf<uint32_t> d_pack_error;
+  DevBuf<uint32_t> d_out_ab, d_out_meta;
+  DevBuf<float> d_out_geo, d_out_pts;
+  DevBuf<int32_t> d_out_count, d_out_tower;
+  DevBuf<uint32_t> d_prev_key;
+  DevBuf<float> d_prev_data;
+  DevBuf<int32_t> d_prev_count;
+  // statistics (per tower id)
+  std::vector<int64_t> st_cand, st_man, st_pts, st_ci;
+  std::vector<int32_t> st_col;
+  std::vector<uint32_t> st_err;
+  std::vector<double> st_rms, st_max;
+  std::vector<uint32_t> pack_err_acc;
+  int64_t step = 0;
+  int64_t launched_points_iters = 0;
+  bool stats_pending = false;
+  int last_launch_steps = 0;
+};
+
+namespace {
+
+int32_t check_world(jg_world* w) {
+  if (!w) return fail(JG_EINVAL, "null world");
+  return JG_OK;
+}
+
+int32_t set_device(jg_world* w) {
+  HIP_TRY(hipSetDevice(w->prm.device));
+  return JG_OK;
+}
+
+// device -> host mirror
+int32_t download_state(jg_world* w) {
+  if (!w->device_newer) return JG_OK;
+  const int n = (int)w->body_of_int.size();
+  const int cap = w->max_bodies;
+  std::vector<float> buf((size_t)4 * cap);
+  std::vector<uint32_t> fl(cap);
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  auto get = [&](DevBuf<float>& d, int comps, std::vector<double>& dst) -> int32_t {
+    HIP_TRY(hipMemcpy(buf.data(), d.p, sizeof(float) * comps * cap, hipMemcpyDeviceToHost));
+    for (int k = 0; k < comps; ++k)
+      for (int i = 0; i < n; ++i) dst[(size_t)comps * w->body_of_int[i] + k] = buf[(size_t)k * cap + i];
+    return JG_OK;
+  };
+  int32_t r;
+  if ((r = get(w->d_x, 3, w->x))) return r;
+  if ((r = get(w->d_q, 4, w->q))) return r;
+  if ((r = get(w->d_v, 3, w->v))) return r;
+  if ((r = get(w->d_w, 3, w->w))) return r;
+  HIP_TRY(hipMemcpy(fl.data(), w->d_flags.p, sizeof(uint32_t) * cap, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) w->active[w->body_of_int[i]] = (fl[i] & jg::kActive) ? 1 : 0;
+  if (!w->pushes.empty()) {
+    std::vector<float> x0(3 * w->push_order.size());
+    HIP_TRY(hipMemcpy(x0.data(), w->d_push_x0.p, sizeof(float) * x0.size(), hipMemcpyDeviceToHost));
+    for (size_t r2 = 0; r2 < w->push_order.size(); ++r2)
+      for (int k = 0; k < 3; ++k) w->pushes[w->push_order[r2]].x0[k] = x0[3 * r2 + k];
+  }
+  w->device_newer = false;
+  return JG_OK;
+}
+
+// pack towers (first fit, largest first) and size the on-chip capacities
+int32_t build_layout(jg_world* w) {
+  const int T = (int)w->tower_bodies.size();
+  std::vector<int> order;
+  int max_tower = 1;
+  for (int t = 0; t < T; ++t) {
+    if (!w->tower_bodies[t].empty()) order.push_back(t);
+    max_tower = std::max(max_tower, (int)w->tower_bodies[t].size());
+  }
+  if (max_tower > 4000) return fail(JG_ECAPACITY, "a tower has more bodies than one pack can index");
+  int target = w->prm.pack_bodies > 0 ? w->prm.pack_bodies : std::max(64, max_tower);
+  if (target < max_tower) target = max_tower;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return w->tower_bodies[a].size() > w->tower_bodies[b].size();
+  });
+  struct Bin { int bodies = 0; std::vector<int> towers; };
+  std::vector<Bin> bins;
+  for (int t : order) {
+    const int n = (int)w->tower_bodies[t].size();
+    bool placed = false;
+    for (auto& b : bins)
+      if (b.bodies + n <= target && (int)b.towers.size() < 255) { b.towers.push_back(t); b.bodies += n; placed = true; break; }
+    if (!placed) { Bin b; b.bodies = n; b.towers.push_back(t); bins.push_back(b); }
+  }
+  std::stable_sort(bins.begin(), bins.end(), [](const Bin& a, const Bin& b) { return a.bodies > b.bodies; });
+  // internal order
+  const int N = (int)w->he.size() / 3;
+  w->int_of_body.assign(N, -1);
+  w->body_of_int.clear();
+  w->tower_order.clear();
+  w->tower_slot.assign(T, -1);
+  w->pack_of_tower.assign(T, -1);
+  w->pack_body0.assign(1, 0);
+  w->pack_tower0.assign(1, 0);
+  w->pack_push0.assign(1, 0);
+  w->push_order.clear();
+  std::vector<std::vector<int>> push_of_body(N);
+  for (size_t r = 0; r < w->pushes.size(); ++r) push_of_body[w->pushes[r].body].push_back((int)r);
+  int nbp = 1, tpc = 1, ppc = 1;
+  for (size_t b = 0; b < bins.size(); ++b) {
+    int pushes = 0;
+    for (int t : bins[b].towers) {
+      w->tower_slot[t] = (int)w->tower_order.size();
+      w->tower_order.push_back(t);
+      w->pack_of_tower[t] = (int)b;
+      for (int id : w->tower_bodies[t]) {
+        w->int_of_body[id] = (int)w->body_of_int.size();
+        w->body_of_int.push_back(id);
+      }
+    }
+    for (int t : bins[b].towers)
+      for (int id : w->tower_bodies[t])
+        for (int r : push_of_body[id]) { w->push_order.push_back(r); ++pushes; }
+    w->pack_body0.push_back((int)w->body_of_int.size());
+    w->pack_tower0.push_back((int)w->tower_order.size());
+    w->pack_push0.push_back((int)w->push_order.size());
+    nbp = std::max(nbp, bins[b].bodies);
+    tpc = std::max(tpc, (int)bins[b].towers.size());
+    ppc = std::max(ppc, pushes);
+  }
+  w->n_packs = (int)bins.size();
+  const float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 4.0f;
+  w->nbp = nbp;
+  w->pc = std::max(64, (int)std::ceil(mpb * nbp));
+  w->cc = std::max(128, 8 * nbp);
+  w->tpc = tpc;
+  w->ppc = ppc;
+  const int64_t words = jg::lds_words(w->nbp, w->pc, w->cc, w->tpc, w->ppc, w->prm.warm_start == 1);
+  w->lds_bytes = (size_t)words * 4;
+  if (w->lds_bytes > 160 * 1024)
+    return fail(JG_ECAPACITY, "pack needs " + std::to_string(w->lds_bytes) + " bytes of LDS (max 163840); "
+                              "use smaller towers or fewer manifolds per body");
+  // device buffers sized by the layout
+  const size_t np = (size_t)std::max(1, w->n_packs);
+  const size_t nt = (size_t)std::max(1, T);
+  const size_t npush = std::max<size_t>(1, w->push_order.size());
+  HIP_TRY(w->d_pack_body0.ensure(np + 1));
+  HIP_TRY(w->d_pack_tower0.ensure(np + 1));
+  HIP_TRY(w->d_pack_push0.ensure(np + 1));
+  HIP_TRY(w->d_tower_body0.ensure(nt + 1));
+  HIP_TRY(w->d_tower_mu.ensure(nt));
+  HIP_TRY(w->d_tower_count.ensure(4 * nt));
+  HIP_TRY(w->d_tower_res.ensure(2 * nt));
+  HIP_TRY(w->d_pack_error.ensure(np));
+  HIP_TRY(w->d_push_body.ensure(npush));
+  HIP_TRY(w->d_push_start.ensure(npush));
+  HIP_TRY(w->d_push_steps.ensure(npush));
+  HIP_TRY(w->d_push_force.ensure(3 * npush));
+  HIP_TRY(w->d_push_withdraw.ensure(npush));
+  HIP_TRY(w->d_push_x0.ensure(3 * npush));
+  const size_t slots = np * (size_t)w->pc;
+  HIP_TRY(w->d_out_ab.ensure(slots));
+  HIP_TRY(w->d_out_meta.ensure(slots));
+  HIP_TRY(w->d_out_geo.ensure(8 * slots));
+  HIP_TRY(w->d_out_pts.ensure(24 * slots));
+  HIP_TRY(w->d_out_count.ensure(np));
+  HIP_TRY(w->d_out_tower.ensure(slots));
+  HIP_TRY(w->d_prev_key.ensure(slots));
+  HIP_TRY(w->d_prev_data.ensure(16 * slots));
+  HIP_TRY(w->d_prev_count.ensure(np));
+  HIP_TRY(hipMemsetAsync(w->d_tower_count.p, 0, sizeof(uint32_t) * 4 * nt, w->stream));
+  HIP_TRY(hipMemsetAsync(w->d_tower_res.p, 0, sizeof(float) * 2 * nt, w->stream));
+  HIP_TRY(hipMemsetAsync(w->d_pack_error.p, 0, sizeof(uint32_t) * np, w->stream));
+  HIP_TRY(hipMemsetAsync(w->d_out_count.p, 0, sizeof(int32_t) * np, w->stream));
+  HIP_TRY(hipMemsetAsync(w->d_prev_count.p, 0, sizeof(int32_t) * np, w->stream));
+  std::vector<int32_t> tb0(T + 1, 0);
+  for (int s = 0; s < (int)w->tower_order.size(); ++s)
+    tb0[s + 1] = tb0[s] + (int)w->tower_bodies[w->tower_order[s]].size();
+  HIP_TRY(hipMemcpy(w->d_pack_body0.p, w->pack_body0.data(), sizeof(int32_t) * w->pack_body0.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w->d_pack_tower0.p, w->pack_tower0.data(), sizeof(int32_t) * w->pack_tower0.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w->d_pack_push0.p, w->pack_push0.data(), sizeof(int32_t) * w->pack_push0.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w->d_tower_body0.p, tb0.data(), sizeof(int32_t) * (w->tower_order.size() + 1), hipMemcpyHostToDevice));
+  std::vector<int32_t> btw(w->max_bodies, 0);
+  for (int s = 0; s < (int)w->tower_order.size(); ++s)
+    for (int k = tb0[s]; k < tb0[s + 1]; ++k) btw[k] = s;
+  HIP_TRY(hipMemcpy(w->d_body_tower.p, btw.data(), sizeof(int32_t) * w->max_bodies, hipMemcpyHostToDevice));
+  w->layout_dirty = false;
+  w->clear_warm = true;
+  return JG_OK;
+}
+
+// host mirror -> device (state, statics, towers, pushes)
+int32_t upload_all(jg_world* w) {
+  const int n = (int)w->body_of_int.size();
+  const int cap = w->max_bodies;
+  std::vector<float> buf((size_t)4 * cap, 0.f);
+  auto put = [&](DevBuf<float>& d, int comps, const std::vector<double>& src) -> int32_t {
+    std::fill(buf.begin(), buf.end(), 0.f);
+    for (int k = 0; k < comps; ++k)
+      for (int i = 0; i < n; ++i) buf[(size_t)k * cap + i] = (float)src[(size_t)comps * w->body_of_int[i] + k];
+    HIP_TRY(hipMemcpy(d.p, buf.data(), sizeof(float) * comps * cap, hipMemcpyHostToDevice));
+    return JG_OK;
+  };
+  int32_t r;
+  if ((r = put(w->d_x, 3, w->x))) return r;
+  if ((r = put(w->d_q, 4, w->q))) return r;
+  if ((r = put(w->d_v, 3, w->v))) return r;
+  if ((r = put(w->d_w, 3, w->w))) return r;
+  if ((r = put(w->d_he, 3, w->he))) return r;
+  std::vector<float> ms(cap, 0.f);
+  std::vector<uint32_t> fl(cap, 0u);
+  for (int i = 0; i < n; ++i) {
+    const int id = w->body_of_int[i];
+    ms[i] = (float)w->mass[id];
+    fl[i] = (w->active[id] ? jg::kActive : 0u) | (w->mass[id] > 0.0 ? jg::kDynamic : 0u);
+  }
+  HIP_TRY(hipMemcpy(w->d_mass.p, ms.data(), sizeof(float) * cap, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w->d_flags.p, fl.data(), sizeof(uint32_t) * cap, hipMemcpyHostToDevice));
+  std::vector<float> mu(std::max<size_t>(1, w->tower_order.size()));
+  for (size_t s = 0; s < w->tower_order.size(); ++s) mu[s] = (float)w->mu[w->tower_order[s]];
+  HIP_TRY(hipMemcpy(w->d_tower_mu.p, mu.data(), sizeof(float) * mu.size(), hipMemcpyHostToDevice));
+  const size_t P = w->push_order.size();
+  if (P) {
+    std::vector<int32_t> pb(P), ps(P), pn(P);
+    std::vector<float> pf(3 * P), pw(P), px(3 * P);
+    for (size_t r2 = 0; r2 < P; ++r2) {
+      const PushRow& pr = w->pushes[w->push_order[r2]];
+      pb[r2] = w->int_of_body[pr.body];
+      ps[r2] = pr.start;
+      pn[r2] = pr.steps;
+      pw[r2] = (float)pr.withdraw;
+      for (int k = 0; k < 3; ++k) { pf[3 * r2 + k] = (float)pr.force[k]; px[3 * r2 + k] = (float)pr.x0[k]; }
+    }
+    HIP_TRY(hipMemcpy(w->d_push_body.p, pb.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_push_start.p, ps.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_push_steps.p, pn.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_push_force.p, pf.data(), sizeof(float) * 3 * P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_push_withdraw.p, pw.data(), sizeof(float) * P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_push_x0.p, px.data(), sizeof(float) * 3 * P, hipMemcpyHostToDevice));
+  }
+  w->host_dirty = false;
+  return JG_OK;
+}
+
+// fold device counters into the host statistics and clear them
+int32_t collect_stats(jg_world* w) {
+  if (!w->stats_pending) return JG_OK;
+  const int T = (int)w->tower_order.size();
+  if (T == 0) { w->stats_pending = false; return JG_OK; }
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  std::vector<uint32_t> cnt(4 * T);
+  std::vector<float> res(2 * T);
+  std::vector<uint32_t> perr(w->n_packs);
+  HIP_TRY(hipMemcpy(cnt.data(), w->d_tower_count.p, sizeof(uint32_t) * 4 * T, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(res.data(), w->d_tower_res.p, sizeof(float) * 2 * T, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(perr.data(), w->d_pack_error.p, sizeof(uint32_t) * w->n_packs, hipMemcpyDeviceToHost));
+  for (int s = 0; s < T; ++s) {
+    const int t = w->tower_order[s];
+    w->st_cand[t] += cnt[4 * s];
+    w->st_man[t] += cnt[4 * s + 1];
+    w->st_pts[t] += cnt[4 * s + 2];
+    w->st_ci[t] += (int64_t)cnt[4 * s + 2] * w->prm.iters;
+    w->st_col[t] = (int32_t)cnt[4 * s + 3];
+    w->st_rms[t] = res[2 * s];
+    w->st_max[t] = res[2 * s + 1];
+    w->st_err[t] |= perr[w->pack_of_tower[t]];
+  }
+  for (int k = 0; k < 4 * T; k += 4) { cnt[k] = cnt[k + 1] = cnt[k + 2] = 0; }
+  HIP_TRY(hipMemcpy(w->d_tower_count.p, cnt.data(), sizeof(uint32_t) * 4 * T, hipMemcpyHostToDevice));
+  w->stats_pending = false;
+  return JG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void jg_default_params(jg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->gravity[0] = 0.0; p->gravity[1] = 0.0; p->gravity[2] = -9.81;
+  p->dt = 1.0 / 240.0;
+  p->restitution = 0.10;
+  p->beta = 0.35;
+  p->slop = 4e-4;
+  p->margin = 2e-3;
+  p->n_sub = 1;
+  p->iters = 20;
+  p->warm_start = 0;
+  p->device = 0;
+  p->stream = nullptr;
+  p->pack_bodies = 0;
+  p->manifolds_per_body = 0.f;
+}
+
+const char* jg_last_error(void) { return g_err.c_str(); }
+
+int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodies, jg_world** out) {
+  if (!out) return fail(JG_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!p) return fail(JG_EINVAL, "null params");
+  if (max_towers <= 0 || max_bodies <= 0) return fail(JG_EINVAL, "max_towers and max_bodies must be positive");
+  if (p->iters < 0 || p->n_sub < 1 || !(p->dt > 0.0)) return fail(JG_EINVAL, "bad iters, n_sub or dt");
+  if (p->warm_start < 0 || p->warm_start > 1) return fail(JG_EINVAL, "warm_start must be 0 or 1");
+  jg_world* w = new (std::nothrow) jg_world();
+  if (!w) return fail(JG_ENOMEM, "host allocation failed");
+  w->prm = *p;
+  w->max_towers = max_towers;
+  w->max_bodies = max_bodies;
+  w->stream = (hipStream_t)p->stream;
+  int32_t r = set_device(w);
+  if (r) { delete w; return r; }
+  const size_t cap = (size_t)max_bodies;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = w->d_x.ensure(3 * cap);
+  if (e == hipSuccess) e = w->d_q.ensure(4 * cap);
+  if (e == hipSuccess) e = w->d_v.ensure(3 * cap);
+  if (e == hipSuccess) e = w->d_w.ensure(3 * cap);
+  if (e == hipSuccess) e = w->d_he.ensure(3 * cap);
+  if (e == hipSuccess) e = w->d_mass.ensure(cap);
+  if (e == hipSuccess) e = w->d_flags.ensure(cap);
+  if (e == hipSuccess) e = w->d_body_tower.ensure(cap);
+  if (e != hipSuccess) {
+    jg_destroy_world(w);
+    return fail(JG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+  }
+  *out = w;
+  return JG_OK;
+}
+
+int32_t jg_destroy_world(jg_world* w) {
+  if (!w) return JG_OK;
+  hipSetDevice(w->prm.device);
+  hipStreamSynchronize(w->stream);
+  w->d_x.release(); w->d_q.release(); w->d_v.release(); w->d_w.release(); w->d_he.release();
+  w->d_mass.release(); w->d_flags.release(); w->d_body_tower.release();
+  w->d_pack_body0.release(); w->d_pack_tower0.release(); w->d_pack_push0.release(); w->d_tower_body0.release();
+  w->d_tower_mu.release(); w->d_push_body.release(); w->d_push_start.release(); w->d_push_steps.release();
+  w->d_push_force.release(); w->d_push_withdraw.release(); w->d_push_x0.release();
+  w->d_tower_count.release(); w->d_tower_res.release(); w->d_pack_error.release();
+  w->d_out_ab.release(); w->d_out_meta.release(); w->d_out_geo.release(); w->d_out_pts.release();
+  w->d_out_count.release(); w->d_out_tower.release();
+  w->d_prev_key.release(); w->d_prev_data.release(); w->d_prev_count.release();
+  delete w;
+  return JG_OK;
+}
+
+int32_t jg_add_boxes(jg_world* w, int32_t tower, int32_t n, const double* half_extents, const double* mass,
+                     const double* pos, const double* quat, const double* linvel, const double* angvel,
+                     int32_t* body_ids_out) {
+  if (int32_t r = check_world(w)) return r;
+  if (n < 0) return fail(JG_EINVAL, "negative body count");
+  if (tower < 0 || tower >= w->max_towers) return fail(JG_EINVAL, "tower index out of range");
+  if (tower > (int)w->tower_bodies.size()) return fail(JG_EINVAL, "towers must be numbered densely by first use");
+  if (n == 0) return JG_OK;
+  if (!half_extents || !mass || !pos || !quat) return fail(JG_EINVAL, "null geometry array");
+  const int N = (int)w->mass.size();
+  if (N + n > w->max_bodies) return fail(JG_ECAPACITY, "max_bodies exceeded");
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k)
+      if (!(half_extents[3 * i + k] > 0.0)) return fail(JG_EINVAL, "half extents must be positive");
+    if (!(mass[i] >= 0.0)) return fail(JG_EINVAL, "mass must be >= 0");
+    double qq = 0.0;
+    for (int k = 0; k < 4; ++k) qq += quat[4 * i + k] * quat[4 * i + k];
+    if (!(qq > 0.0) || !std::isfinite(qq)) return fail(JG_EINVAL, "quaternion must be non-zero and finite");
+  }
+  if (int32_t r = download_state(w)) return r;
+  if (tower == (int)w->tower_bodies.size()) {
+    w->tower_bodies.emplace_back();
+    w->mu.push_back(0.4);
+    w->st_cand.push_back(0); w->st_man.push_back(0); w->st_pts.push_back(0); w->st_ci.push_back(0);
+    w->st_col.push_back(0); w->st_err.push_back(0); w->st_rms.push_back(0.0); w->st_max.push_back(0.0);
+  }
+  for (int i = 0; i < n; ++i) {
+    const int id = N + i;
+    for (int k = 0; k < 3; ++k) {
+      w->he.push_back(half_extents[3 * i + k]);
+      w->x.push_back(pos[3 * i + k]);
+      w->v.push_back(linvel ? linvel[3 * i + k] : 0.0);
+      w->w.push_back(angvel ? angvel[3 * i + k] : 0.0);
+    }
+    double qq = 0.0;
+    for (int k = 0; k < 4; ++k) qq += quat[4 * i + k] * quat[4 * i + k];
+    const double il = 1.0 / std::sqrt(qq);
+    for (int k = 0; k < 4; ++k) w->q.push_back(quat[4 * i + k] * il);
+    w->mass.push_back(mass[i]);
+    w->active.push_back(1);
+    w->body_tower.push_back(tower);
+    w->tower_bodies[tower].push_back(id);
+    if (body_ids_out) body_ids_out[i] = id;
+  }
+  w->layout_dirty = true;
+  w->host_dirty = true;
+  return JG_OK;
+}
+
+int32_t jg_set_friction(jg_world* w, int32_t tower, double mu) {
+  if (int32_t r = check_world(w)) return r;
+  if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(JG_EINVAL, "friction must be finite and >= 0");
+  if (tower < -1 || tower >= (int)w->tower_bodies.size()) return fail(JG_EINVAL, "tower index out of range");
+  if (int32_t r = download_state(w)) return r;
+  if (tower == -1) std::fill(w->mu.begin(), w->mu.end(), mu);
+  else w->mu[tower] = mu;
+  w->host_dirty = true;
+  return JG_OK;
+}
+
+int32_t jg_set_push(jg_world* w, int32_t body, const double force[3], int32_t start_step, int32_t n_steps,
+                    double withdraw) {
+  if (int32_t r = check_world(w)) return r;
+  if (body < 0 || body >= (int)w->mass.size()) return fail(JG_EINVAL, "body index out of range");
+  if (!force || n_steps < 0 || !(withdraw >= 0.0)) return fail(JG_EINVAL, "bad push arguments");
+  if (int32_t r = download_state(w)) return r;
+  PushRow pr;
+  pr.body = body;
+  for (int k = 0; k < 3; ++k) { pr.force[k] = force[k]; pr.x0[k] = w->x[3 * body + k]; }
+  pr.start = start_step;
+  pr.steps = n_steps;
+  pr.withdraw = withdraw;
+  w->pushes.push_back(pr);
+  w->layout_dirty = true;
+  w->host_dirty = true;
+  return JG_OK;
+}
+
+int32_t jg_set_active(jg_world* w, int32_t body, int32_t active) {
+  if (int32_t r = check_world(w)) return r;
+  if (body < 0 || body >= (int)w->mass.size()) return fail(JG_EINVAL, "body index out of range");
+  if (int32_t r = download_state(w)) return r;
+  w->active[body] = active ? 1 : 0;
+  if (!active) for (int k = 0; k < 3; ++k) { w->v[3 * body + k] = 0.0; w->w[3 * body + k] = 0.0; }
+  w->host_dirty = true;
+  return JG_OK;
+}
+
+int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
+  if (int32_t r = check_world(w)) return r;
+  if (n_steps < 0) return fail(JG_EINVAL, "negative step count");
+  if (n_steps == 0) return JG_OK;
+  if (int32_t r = set_device(w)) return r;
+  if (w->layout_dirty || w->host_dirty) {
+    if (int32_t r = download_state(w)) return r;
+    if (int32_t r = collect_stats(w)) return r;
+    if (w->layout_dirty)
+      if (int32_t r = build_layout(w)) return r;
+    if (int32_t r = upload_all(w)) return r;
+  }
+  if (w->clear_warm) {
+    HIP_TRY(hipMemsetAsync(w->d_prev_count.p, 0, sizeof(int32_t) * std::max(1, w->n_packs), w->stream));
+    w->clear_warm = false;
+  }
+  if (w->n_packs == 0) { w->step += n_steps; return JG_OK; }
+  jg::StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = w->d_x.p; a.q = w->d_q.p; a.v = w->d_v.p; a.w = w->d_w.p;
+  a.he = w->d_he.p; a.mass = w->d_mass.p; a.flags = w->d_flags.p;
+  a.body_tower = w->d_body_tower.p; a.cap = w->max_bodies;
+  a.pack_body0 = w->d_pack_body0.p; a.pack_tower0 = w->d_pack_tower0.p; a.pack_push0 = w->d_pack_push0.p;
+  a.tower_body0 = w->d_tower_body0.p; a.tower_mu = w->d_tower_mu.p; a.n_packs = w->n_packs;
+  a.push_body = w->d_push_body.p; a.push_start = w->d_push_start.p; a.push_steps = w->d_push_steps.p;
+  a.push_force = w->d_push_force.p; a.push_withdraw = w->d_push_withdraw.p; a.push_x0 = w->d_push_x0.p;
+  a.tower_count = w->d_tower_count.p; a.tower_res = w->d_tower_res.p; a.pack_error = w->d_pack_error.p;
+  a.out_ab = w->d_out_ab.p; a.out_meta = w->d_out_meta.p; a.out_geo = w->d_out_geo.p; a.out_pts = w->d_out_pts.p;
+  a.out_count = w->d_out_count.p; a.out_tower = w->d_out_tower.p;
+  a.prev_key = w->d_prev_key.p; a.prev_data = w->d_prev_data.p; a.prev_count = w->d_prev_count.p;
+  for (int k = 0; k < 3; ++k) a.g[k] = (float)w->prm.gravity[k];
+  a.dt = (float)(w->prm.dt / w->prm.n_sub);
+  a.restitution = (float)w->prm.restitution;
+  a.beta = (float)w->prm.beta;
+  a.slop = (float)w->prm.slop;
+  a.margin = (float)w->prm.margin;
+  a.iters = w->prm.iters;
+  a.n_sub = w->prm.n_sub;
+  a.n_steps = n_steps;
+  a.warm_start = w->prm.warm_start;
+  a.step0 = w->step;
+  a.nbp = w->nbp; a.pc = w->pc; a.cc = w->cc; a.tpc = w->tpc; a.ppc = w->ppc;
+  jg::launch_step(a, jg::kWave, w->lds_bytes, w->stream);
+  HIP_TRY(hipGetLastError());
+  w->step += n_steps;
+  w->device_newer = true;
+  w->stats_pending = true;
+  w->last_launch_steps = n_steps;
+  return JG_OK;
+}
+
+int32_t jg_query_state(jg_world* w, int32_t first_body, int32_t n, double* pos, double* quat, double* linvel,
+                       double* angvel) {
+  if (int32_t r = check_world(w)) return r;
+  if (first_body < 0 || n < 0 || first_body + n > (int)w->mass.size()) return fail(JG_EINVAL, "body range out of range");
+  if (int32_t r = set_device(w)) return r;
+  if (int32_t r = download_state(w)) return r;
+  for (int i = 0; i < n; ++i) {
+    const int id = first_body + i;
+    for (int k = 0; k < 3; ++k) {
+      if (pos) pos[3 * i + k] = w->x[3 * id + k];
+      if (linvel) linvel[3 * i + k] = w->v[3 * id + k];
+      if (angvel) angvel[3 * i + k] = w->w[3 * id + k];
+    }
+    if (quat) for (int k = 0; k < 4; ++k) quat[4 * i + k] = w->q[4 * id + k];
+  }
+  return JG_OK;
+}
+
+int32_t jg_set_state(jg_world* w, int32_t first_body, int32_t n, const double* pos, const double* quat,
+                     const double* linvel, const double* angvel) {
+  if (int32_t r = check_world(w)) return r;
+  if (first_body < 0 || n < 0 || first_body + n > (int)w->mass.size()) return fail(JG_EINVAL, "body range out of range");
+  if (int32_t r = set_device(w)) return r;
+  if (int32_t r = download_state(w)) return r;
+  for (int i = 0; i < n; ++i) {
+    const int id = first_body + i;
+    for (int k = 0; k < 3; ++k) {
+      if (pos) w->x[3 * id + k] = pos[3 * i + k];
+      if (linvel) w->v[3 * id + k] = linvel[3 * i + k];
+      if (angvel) w->w[3 * id + k] = angvel[3 * i + k];
+    }
+    if (quat) {
+      double qq = 0.0;
+      for (int k = 0; k < 4; ++k) qq += quat[4 * i + k] * quat[4 * i + k];
+      if (!(qq > 0.0)) return fail(JG_EINVAL, "zero quaternion");
+      const double il = 1.0 / std::sqrt(qq);
+      for (int k = 0; k < 4; ++k) w->q[4 * id + k] = quat[4 * i + k] * il;
+    }
+  }
+  w->host_dirty = true;
+  w->clear_warm = true;
+  return JG_OK;
+}
+
+int32_t jg_query_active(jg_world* w, int32_t first_body, int32_t n, uint8_t* active) {
+  if (int32_t r = check_world(w)) return r;
+  if (!active || first_body < 0 || n < 0 || first_body + n > (int)w->mass.size())
+    return fail(JG_EINVAL, "bad body range or null output");
+  if (int32_t r = set_device(w)) return r;
+  if (int32_t r = download_state(w)) return r;
+  for (int i = 0; i < n; ++i) active[i] = w->active[first_body + i];
+  return JG_OK;
+}
+
+int32_t jg_query_contacts(jg_world* w, int32_t tower, jg_contact* out, int32_t capacity, int32_t* n_out) {
+  if (int32_t r = check_world(w)) return r;
+  if (!n_out || capacity < 0 || (capacity > 0 && !out)) return fail(JG_EINVAL, "bad output buffer");
+  if (tower < 0 || tower >= (int)w->tower_bodies.size()) return fail(JG_EINVAL, "tower index out of range");
+  *n_out = 0;
+  if (w->layout_dirty || w->n_packs == 0) return JG_OK;
+  if (int32_t r = set_device(w)) return r;
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  const int pk = w->pack_of_tower[tower];
+  if (pk < 0) return JG_OK;
+  int32_t cnt = 0;
+  HIP_TRY(hipMemcpy(&cnt, w->d_out_count.p + pk, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (cnt <= 0) return JG_OK;
+  const size_t base = (size_t)pk * w->pc;
+  std::vector<uint32_t> ab(cnt), meta(cnt);
+  std::vector<int32_t> tw(cnt);
+  std::vector<float> geo(8 * (size_t)cnt), pts(24 * (size_t)cnt);
+  HIP_TRY(hipMemcpy(ab.data(), w->d_out_ab.p + base, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(meta.data(), w->d_out_meta.p + base, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(tw.data(), w->d_out_tower.p + base, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(geo.data(), w->d_out_geo.p + 8 * base, sizeof(float) * 8 * cnt, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(pts.data(), w->d_out_pts.p + 24 * base, sizeof(float) * 24 * cnt, hipMemcpyDeviceToHost));
+  const int local = w->tower_slot[tower] - w->pack_tower0[pk];
+  const int b0 = w->pack_body0[pk];
+  int total = 0, order = 0;
+  for (int m = 0; m < cnt; ++m) {
+    if (tw[m] != local) continue;
+    const int a = (int)(ab[m] >> 16), b = (int)(ab[m] & 0xffffu);
+    const int npts = (int)(meta[m] & 15u);
+    const int colour = (int)((meta[m] >> 4) & 255u);
+    for (int q = 0; q < npts; ++q) {
+      if (total < capacity) {
+        jg_contact& c = out[total];
+        c.tower = tower;
+        c.body_a = w->body_of_int[b0 + a];
+        c.body_b = (b == 0xffff) ? -1 : w->body_of_int[b0 + b];
+        c.slot = (int)((meta[m] >> (12 + 4 * q)) & 15u);
+        c.colour = colour;
+        c.order = order;
+        for (int k = 0; k < 3; ++k) {
+          c.point[k] = pts[24 * (size_t)m + 6 * q + k];
+          c.normal[k] = geo[8 * (size_t)m + k];
+          c.t1[k] = geo[8 * (size_t)m + 3 + k];
+        }
+        c.depth = geo[8 * (size_t)m + 6];
+        c.lambda_n = pts[24 * (size_t)m + 6 * q + 3];
+        c.lambda_t1 = pts[24 * (size_t)m + 6 * q + 4];
+        c.lambda_t2 = pts[24 * (size_t)m + 6 * q + 5];
+      }
+      ++total;
+    }
+    ++order;
+  }
+  *n_out = total;
+  return JG_OK;
+}
+
+int32_t jg_query_stats(jg_world* w, int32_t tower, jg_stats* out) {
+  if (int32_t r = check_world(w)) return r;
+  if (!out) return fail(JG_EINVAL, "null output");
+  if (tower < -1 || tower >= (int)w->tower_bodies.size()) return fail(JG_EINVAL, "tower index out of range");
+  if (int32_t r = set_device(w)) return r;
+  if (int32_t r = collect_stats(w)) return r;
+  std::memset(out, 0, sizeof(*out));
+  out->steps = w->step;
+  auto add = [&](int t) {
+    out->candidates += w->st_cand[t];
+    out->manifolds += w->st_man[t];
+    out->points += w->st_pts[t];
+    out->contact_iters += w->st_ci[t];
+    out->colours = std::max(out->colours, w->st_col[t]);
+    out->error_word |= w->st_err[t];
+    out->residual_rms = std::max(out->residual_rms, w->st_rms[t]);
+    out->residual_max = std::max(out->residual_max, w->st_max[t]);
+  };
+  if (tower >= 0) add(tower);
+  else for (int t = 0; t < (int)w->tower_bodies.size(); ++t) add(t);
+  return JG_OK;
+}
+
+int32_t jg_world_size(jg_world* w, int32_t* n_towers, int32_t* n_bodies) {
+  if (int32_t r = check_world(w)) return r;
+  if (n_towers) *n_towers = (int32_t)w->tower_bodies.size();
+  if (n_bodies) *n_bodies = (int32_t)w->mass.size();
+  return JG_OK;
+}
+
+int32_t jg_sync(jg_world* w) {
+  if (int32_t r = check_world(w)) return r;
+  if (int32_t r = set_device(w)) return r;
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  return JG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,302 @@
+"""Python binding of the C ABI in include/jenga.h (argument marshalling only).
+
+Every step of the simulation runs in ``libjenga.so`` on the GPU.  The functions
+keep the C names (``jg_create_world``, ``jg_step_batch``, ...); ``World`` wraps a
+handle for convenience.  PyTorch is only used to pick the HIP stream.
+
+Importing this module does not need a GPU; loading the library does, and fails
+loudly when ``libjenga.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjenga.so")
+
+JG_OK, JG_EINVAL, JG_ENOMEM, JG_EDEVICE, JG_ECAPACITY, JG_ESTATE, JG_ENAN = 0, -1, -2, -3, -4, -5, -6
+ERR_CANDIDATES, ERR_MANIFOLDS, ERR_COLOURS, ERR_NAN = 1, 2, 4, 8
+
+EXPORTS = ["jg_default_params", "jg_create_world", "jg_destroy_world", "jg_add_boxes", "jg_set_friction",
+           "jg_set_push", "jg_set_active", "jg_step_batch", "jg_query_state", "jg_set_state", "jg_query_active",
+           "jg_query_contacts", "jg_query_stats", "jg_world_size", "jg_sync", "jg_last_error"]
+
+
+class jg_params(C.Structure):
+    _fields_ = [("gravity", C.c_double * 3), ("dt", C.c_double), ("restitution", C.c_double),
+                ("beta", C.c_double), ("slop", C.c_double), ("margin", C.c_double),
+                ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("device", C.c_int32),
+                ("stream", C.c_void_p), ("pack_bodies", C.c_int32), ("manifolds_per_body", C.c_float)]
+
+
+class jg_contact(C.Structure):
+    _fields_ = [("tower", C.c_int32), ("body_a", C.c_int32), ("body_b", C.c_int32), ("slot", C.c_int32),
+                ("colour", C.c_int32), ("order", C.c_int32), ("point", C.c_float * 3), ("normal", C.c_float * 3),
+                ("t1", C.c_float * 3), ("depth", C.c_float), ("lambda_n", C.c_float), ("lambda_t1", C.c_float),
+                ("lambda_t2", C.c_float)]
+
+
+class jg_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("candidates", C.c_int64), ("manifolds", C.c_int64), ("points", C.c_int64),
+                ("contact_iters", C.c_int64), ("colours", C.c_int32), ("error_word", C.c_uint32),
+                ("residual_rms", C.c_double), ("residual_max", C.c_double)]
+
+
+CONTACT_DTYPE = np.dtype([("tower", np.int32), ("body_a", np.int32), ("body_b", np.int32), ("slot", np.int32),
+                          ("colour", np.int32), ("order", np.int32), ("point", np.float32, 3),
+                          ("normal", np.float32, 3), ("t1", np.float32, 3), ("depth", np.float32),
+                          ("lambda_n", np.float32), ("lambda_t1", np.float32), ("lambda_t2", np.float32)])
+assert CONTACT_DTYPE.itemsize == C.sizeof(jg_contact)
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libjenga.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python paper_2606_28394_amd/build.py` "
+                          "(or __graft_entry__.build())")
+    # Load torch first: libjenga.so then binds to the same HIP runtime (same soname), so the
+    # streams torch hands out are valid inside the library and one runtime owns the device.
+    import torch  # noqa: F401
+    L = C.CDLL(path)
+    L.jg_default_params.argtypes = [C.POINTER(jg_params)]
+    L.jg_default_params.restype = None
+    L.jg_create_world.argtypes = [C.POINTER(jg_params), C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+    L.jg_destroy_world.argtypes = [C.c_void_p]
+    L.jg_add_boxes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
+                               C.POINTER(C.c_int32)]
+    L.jg_set_friction.argtypes = [C.c_void_p, C.c_int32, C.c_double]
+    L.jg_set_push.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, C.c_int32, C.c_double]
+    L.jg_set_active.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    L.jg_step_batch.argtypes = [C.c_void_p, C.c_int32]
+    L.jg_query_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
+    L.jg_set_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
+    L.jg_query_active.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_uint8)]
+    L.jg_query_contacts.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+    L.jg_query_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(jg_stats)]
+    L.jg_world_size.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.jg_sync.argtypes = [C.c_void_p]
+    L.jg_last_error.argtypes = []
+    L.jg_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("jg_default_params", "jg_last_error"):
+            getattr(L, name).restype = C.c_int32
+    _lib = L
+    return L
+
+
+class JengaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"jenga error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != JG_OK:
+        raise JengaError(code, load_library().jg_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _arr(a, shape):
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+
+
+# ------------------------------------------------------------------------------------------------
+# thin wrappers with the C names
+# ------------------------------------------------------------------------------------------------
+
+def jg_default_params() -> jg_params:
+    p = jg_params()
+    load_library().jg_default_params(C.byref(p))
+    return p
+
+
+def jg_create_world(params: jg_params, max_towers: int, max_bodies: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(load_library().jg_create_world(C.byref(params), int(max_towers), int(max_bodies), C.byref(h)))
+    return h
+
+
+def jg_destroy_world(h):
+    _check(load_library().jg_destroy_world(h))
+
+
+def jg_add_boxes(h, tower, half_extents, mass, pos, quat, linvel=None, angvel=None) -> np.ndarray:
+    n = len(np.atleast_1d(mass))
+    he = _arr(half_extents, (n, 3)); m = _arr(mass, (n,)); x = _arr(pos, (n, 3)); q = _arr(quat, (n, 4))
+    v = _arr(linvel, (n, 3)); w = _arr(angvel, (n, 3))
+    ids = np.zeros(n, np.int32)
+    _check(load_library().jg_add_boxes(h, int(tower), n, _ptr(he), _ptr(m), _ptr(x), _ptr(q), _ptr(v), _ptr(w),
+                                       ids.ctypes.data_as(C.POINTER(C.c_int32))))
+    return ids
+
+
+def jg_set_friction(h, tower, mu):
+    _check(load_library().jg_set_friction(h, int(tower), float(mu)))
+
+
+def jg_set_push(h, body, force, start_step, n_steps, withdraw=0.0):
+    f = _arr(force, (3,))
+    _check(load_library().jg_set_push(h, int(body), _ptr(f), int(start_step), int(n_steps), float(withdraw)))
+
+
+def jg_set_active(h, body, active):
+    _check(load_library().jg_set_active(h, int(body), int(bool(active))))
+
+
+def jg_step_batch(h, n_steps):
+    _check(load_library().jg_step_batch(h, int(n_steps)))
+
+
+def jg_query_state(h, first, n):
+    pos = np.zeros((n, 3)); quat = np.zeros((n, 4)); v = np.zeros((n, 3)); w = np.zeros((n, 3))
+    _check(load_library().jg_query_state(h, int(first), int(n), _ptr(pos), _ptr(quat), _ptr(v), _ptr(w)))
+    return pos, quat, v, w
+
+
+def jg_set_state(h, first, pos=None, quat=None, linvel=None, angvel=None):
+    n = None
+    for a, c in ((pos, 3), (quat, 4), (linvel, 3), (angvel, 3)):
+        if a is not None:
+            n = np.asarray(a).size // c
+    if n is None:
+        return
+    _check(load_library().jg_set_state(h, int(first), int(n), _ptr(_arr(pos, (n, 3))), _ptr(_arr(quat, (n, 4))),
+                                       _ptr(_arr(linvel, (n, 3))), _ptr(_arr(angvel, (n, 3)))))
+
+
+def jg_query_active(h, first, n):
+    out = np.zeros(n, np.uint8)
+    _check(load_library().jg_query_active(h, int(first), int(n), out.ctypes.data_as(C.POINTER(C.c_uint8))))
+    return out
+
+
+def jg_query_contacts(h, tower, capacity=None) -> np.ndarray:
+    L = load_library()
+    n = C.c_int32(0)
+    if capacity is None:
+        _check(L.jg_query_contacts(h, int(tower), None, 0, C.byref(n)))
+        capacity = n.value
+    out = np.zeros(max(1, capacity), CONTACT_DTYPE)
+    _check(L.jg_query_contacts(h, int(tower), out.ctypes.data_as(C.c_void_p), int(capacity), C.byref(n)))
+    return out[:min(n.value, capacity)]
+
+
+def jg_query_stats(h, tower=-1) -> jg_stats:
+    s = jg_stats()
+    _check(load_library().jg_query_stats(h, int(tower), C.byref(s)))
+    return s
+
+
+def jg_world_size(h):
+    t = C.c_int32(0); b = C.c_int32(0)
+    _check(load_library().jg_world_size(h, C.byref(t), C.byref(b)))
+    return t.value, b.value
+
+
+def jg_sync(h):
+    _check(load_library().jg_sync(h))
+
+
+def jg_last_error() -> str:
+    return load_library().jg_last_error().decode()
+
+
+# ------------------------------------------------------------------------------------------------
+# convenience handle
+# ------------------------------------------------------------------------------------------------
+
+def current_stream_handle():
+    """The raw hipStream_t of torch's current stream (None without a GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:   # torch is optional for the binding
+        pass
+    return None
+
+
+class World:
+    """A world built from a scene dict (see workloads.py); bodies keep the scene's order."""
+
+    def __init__(self, scene: dict, warm_start: int = 0, stream=None, device: int = 0, pack_bodies: int = 0,
+                 manifolds_per_body: float = 0.0, params: dict | None = None):
+        pr = params or scene["params"]
+        p = jg_default_params()
+        p.gravity[:] = [float(g) for g in pr["gravity"]]
+        p.dt = float(pr["dt"])
+        p.restitution = float(pr["restitution"])
+        p.beta = float(pr["beta"])
+        p.slop = float(pr["slop"])
+        p.margin = float(pr["margin"])
+        p.n_sub = int(pr["n_sub"])
+        p.iters = int(pr["iters"])
+        p.warm_start = int(warm_start)
+        p.device = int(device)
+        p.stream = stream if stream is not None else current_stream_handle()
+        p.pack_bodies = int(pack_bodies)
+        p.manifolds_per_body = float(manifolds_per_body)
+        self.params = p
+        T = int(scene["n_towers"])
+        ptr = np.asarray(scene["tower_ptr"])
+        N = int(ptr[-1])
+        self.n_towers, self.n_bodies = T, N
+        self.h = jg_create_world(p, max(1, T), max(1, N))
+        for t in range(T):
+            a, b = int(ptr[t]), int(ptr[t + 1])
+            if b > a:
+                jg_add_boxes(self.h, t, scene["half_extents"][a:b], scene["mass"][a:b], scene["pos"][a:b],
+                             scene["quat"][a:b], scene["linvel"][a:b], scene["angvel"][a:b])
+            jg_set_friction(self.h, t, float(scene["mu"][t]))
+        act = np.asarray(scene["active"])
+        for i in np.nonzero(act == 0)[0]:
+            jg_set_active(self.h, int(i), 0)
+        for i in range(len(scene["push_body"])):
+            jg_set_push(self.h, int(scene["push_body"][i]), scene["push_force"][i], int(scene["push_start"][i]),
+                        int(scene["push_steps"][i]), float(scene["push_withdraw"][i]))
+
+    def step(self, n_steps: int = 1):
+        jg_step_batch(self.h, n_steps)
+
+    def state(self):
+        return jg_query_state(self.h, 0, self.n_bodies)
+
+    def set_state(self, pos=None, quat=None, linvel=None, angvel=None):
+        jg_set_state(self.h, 0, pos, quat, linvel, angvel)
+
+    def active(self):
+        return jg_query_active(self.h, 0, self.n_bodies)
+
+    def contacts(self, tower: int) -> np.ndarray:
+        return jg_query_contacts(self.h, tower)
+
+    def stats(self, tower: int = -1) -> jg_stats:
+        return jg_query_stats(self.h, tower)
+
+    def sync(self):
+        jg_sync(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            jg_destroy_world(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

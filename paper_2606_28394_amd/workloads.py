@@ -134,44 +134,51 @@ def jenga_tower(levels: int, rng: np.random.Generator | None, half=BLOCK_HALF,
     return he, m, pos, quat, lev, slot
 
 
+_EDGE_DIRS = np.array([[1.0, 0, 0], [-1.0, 0, 0], [0, 1.0, 0], [0, -1.0, 0]])
+_SIGNS = np.array([[1 if c & 1 else -1, 1 if c & 2 else -1, 1 if c & 4 else -1] for c in range(8)], float)
+
+
+def _rot_matrices(quat) -> np.ndarray:
+    """Rotation matrices of unit quaternions (placement helper only)."""
+    w, x, y, z = (np.asarray(quat, np.float64)[:, k] for k in range(4))
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def _all_corners(pos, quat, he) -> np.ndarray:
+    R = _rot_matrices(quat)
+    local = _SIGNS[None, :, :] * np.asarray(he)[:, None, :]
+    return np.asarray(pos)[:, None, :] + np.einsum("nij,nkj->nki", R, local)
+
+
+def _pivot(pos, quat, he, edge):
+    d = _EDGE_DIRS[edge]
+    c = _all_corners(pos, quat, he).reshape(-1, 3)
+    return d, float((c @ d).max()), float(c[:, 2].min())
+
+
 def tilt_about_edge(pos, quat, he, theta: float, edge: int):
     """Rigidly rotate a tower by ``theta`` about one bottom edge of its footprint.
 
     edge in {0: +x, 1: -x, 2: +y, 3: -y} picks the footprint side the tower
     tips towards.  Returns new (pos, quat).
     """
-    d = [np.array([1.0, 0, 0]), np.array([-1.0, 0, 0]),
-         np.array([0, 1.0, 0]), np.array([0, -1.0, 0])][edge]
-    # footprint extent along d and the lowest corner height
-    ext = -np.inf
-    zmin = np.inf
-    for k in range(len(pos)):
-        for c in range(8):
-            sgn = np.array([1 if c & 1 else -1, 1 if c & 2 else -1, 1 if c & 4 else -1])
-            p = pos[k] + _rotate(quat[k], sgn * he[k])
-            ext = max(ext, float(d @ p))
-            zmin = min(zmin, float(p[2]))
+    d, ext, zmin = _pivot(pos, quat, he, edge)
     pivot = d * ext + np.array([0.0, 0.0, zmin])
     axis = np.cross(np.array([0.0, 0.0, 1.0]), d)
     qr = quat_axis_angle(axis, theta)
-    npos = np.array([pivot + _rotate(qr, p - pivot) for p in pos])
+    Rr = _rot_matrices(qr[None, :])[0]
+    npos = pivot + (np.asarray(pos) - pivot) @ Rr.T
     nquat = np.array([quat_mul(qr, q) for q in quat])
     return npos, nquat
 
 
 def critical_tilt(pos, quat, he, edge: int) -> float:
     """Tilt at which the tower's centre of mass sits above the pivot edge."""
-    d = [np.array([1.0, 0, 0]), np.array([-1.0, 0, 0]),
-         np.array([0, 1.0, 0]), np.array([0, -1.0, 0])][edge]
-    ext = -np.inf
-    zmin = np.inf
-    for k in range(len(pos)):
-        for c in range(8):
-            sgn = np.array([1 if c & 1 else -1, 1 if c & 2 else -1, 1 if c & 4 else -1])
-            p = pos[k] + _rotate(quat[k], sgn * he[k])
-            ext = max(ext, float(d @ p))
-            zmin = min(zmin, float(p[2]))
-    com = pos.mean(axis=0)
+    d, ext, zmin = _pivot(pos, quat, he, edge)
+    com = np.asarray(pos).mean(axis=0)
     return math.atan2(ext - float(d @ com), float(com[2]) - zmin)
 
 

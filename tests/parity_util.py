@@ -1,0 +1,93 @@
+"""Helpers that compare the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (one step, FP32 GPU against FP64 oracle):
+  positions    |dx| <= 1e-5 * max(|x|, 0.075 m)
+  quaternions  |dq| <= 1e-5
+  velocities   |dv| <= 1e-4 * max(|v|, g dt)        angular: 1e-4 * max(|w|, 1 rad/s)
+  impulses     |dl| <= 1e-4 * max(|l|, m g dt / 4)  (m g dt / 4 = 1.72e-4 N s for the benchmark block)
+  points       |dp| <= 1e-5 * max(|p|, 0.075 m)
+Contact-pair sets must agree exactly outside the oracle's precision bands;
+colours must agree exactly for towers without a banded pair.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+G_DT = 9.81 / 240.0
+LAM_FLOOR = 0.016875 * 9.81 / 240.0 / 4.0
+BAND_MASK = O.BAND_SEPARATION | O.BAND_NORMAL | O.BAND_CROSS | O.BAND_CLIP | O.BAND_GROUND | O.BAND_EMPTY
+
+
+def gpu_manifolds(contacts, first_body: int) -> dict:
+    """Group GPU contact points by (a, b) with tower-local body indices (ground = -1)."""
+    out = {}
+    for c in contacts:
+        a = int(c["body_a"]) - first_body
+        b = int(c["body_b"])
+        b = -1 if b < 0 else b - first_body
+        m = out.setdefault((a, b), dict(colour=int(c["colour"]), order=int(c["order"]), slot=[], point=[], lam=[],
+                                       normal=np.array(c["normal"], np.float64), t1=np.array(c["t1"], np.float64),
+                                       depth=float(c["depth"])))
+        m["slot"].append(int(c["slot"]))
+        m["point"].append(np.array(c["point"], np.float64))
+        m["lam"].append([float(c["lambda_n"]), float(c["lambda_t1"]), float(c["lambda_t2"])])
+    for m in out.values():
+        m["point"] = np.array(m["point"]).reshape(-1, 3)
+        m["lam"] = np.array(m["lam"]).reshape(-1, 3)
+    return out
+
+
+def oracle_manifolds(ow, t: int) -> dict:
+    return {(m["a"], m["b"]): m for m in ow.manifolds(t)}
+
+
+def compare_contacts(om: dict, gm: dict) -> dict:
+    """Returns a report; 'ok' is True when every check inside the tolerances passes."""
+    rep = dict(pairs=len(om), banded=0, missing=[], extra=[], colour_mismatch=[], slot_mismatch=[],
+               point_err=0.0, lam_err=0.0, normal_err=0.0, colours_checked=False)
+    banded = {k for k, m in om.items() if m["band"] & BAND_MASK}
+    rep["banded"] = len(banded)
+    okeys = set(om) - banded
+    gkeys = set(gm) - banded
+    rep["missing"] = sorted(okeys - gkeys)
+    rep["extra"] = sorted(gkeys - okeys)
+    # colours are a function of the whole pair set; compare them when the sets agree exactly
+    if set(om) == set(gm):
+        rep["colours_checked"] = True
+        for k in om:
+            if om[k]["colour"] != gm[k]["colour"]:
+                rep["colour_mismatch"].append(k)
+    for k in okeys & gkeys:
+        o, g = om[k], gm[k]
+        rep["normal_err"] = max(rep["normal_err"], float(np.abs(o["normal"] - g["normal"]).max()))
+        if list(o["slot"]) != list(g["slot"]):
+            rep["slot_mismatch"].append((k, list(o["slot"]), list(g["slot"])))
+            continue
+        scale = np.maximum(np.linalg.norm(o["point"], axis=1), 0.075)
+        rep["point_err"] = max(rep["point_err"], float((np.linalg.norm(o["point"] - g["point"], axis=1) / scale).max()))
+        lam_scale = np.maximum(np.abs(o["lam"]), LAM_FLOOR)
+        rep["lam_err"] = max(rep["lam_err"], float((np.abs(o["lam"] - g["lam"]) / lam_scale).max()))
+    rep["ok"] = (not rep["missing"] and not rep["extra"] and not rep["colour_mismatch"] and not rep["slot_mismatch"]
+                 and rep["point_err"] <= 1e-5 and rep["lam_err"] <= 1e-4)
+    return rep
+
+
+def compare_state(ow, gpos, gquat, gv, gw, idx=None) -> dict:
+    idx = slice(None) if idx is None else idx
+    x, q, v, w = ow.x[idx], ow.q[idx], ow.v[idx], ow.w[idx]
+    gx, gq, gvv, gww = gpos[idx], gquat[idx], gv[idx], gw[idx]
+    # quaternions q and -q are the same rotation
+    sgn = np.sign(np.sum(q * gq, axis=1, keepdims=True))
+    sgn[sgn == 0] = 1
+    ex = float((np.linalg.norm(x - gx, axis=1) / np.maximum(np.linalg.norm(x, axis=1), 0.075)).max(initial=0))
+    eq = float(np.abs(q - sgn * gq).max(initial=0))
+    ev = float((np.linalg.norm(v - gvv, axis=1) / np.maximum(np.linalg.norm(v, axis=1), G_DT)).max(initial=0))
+    ew = float((np.linalg.norm(w - gww, axis=1) / np.maximum(np.linalg.norm(w, axis=1), 1.0)).max(initial=0))
+    return dict(x=ex, q=eq, v=ev, w=ew, ok=(ex <= 1e-5 and eq <= 1e-5 and ev <= 1e-4 and ew <= 1e-4))
+
+
+def fmt(rep: dict) -> str:
+    keys = [k for k in rep if k not in ("ok",)]
+    return ", ".join(f"{k}={rep[k] if not isinstance(rep[k], list) else rep[k][:4]}" for k in keys)
