@@ -1,0 +1,189 @@
+"""Throughput benchmark of batched tower stepping on one MI355X.
+
+Workload (default): the throughput batch -- 16384 towers of 8-40 levels x 3 boxes
+(75 x 25 x 15 mm, 600 kg/m^3), each tilted past its critical angle about a seeded
+bottom edge so it collapses fully; mu_s drawn from {0.25, 0.40, 0.60}; dt = 1/240 s,
+20 PGS iterations, FP32 on the GPU.  One bench "step" advances every tower by one
+time step through the whole path (broadphase, SAT, manifolds, colouring, PGS,
+residual, integration, position correction).
+
+The K timed steps run as one persistent launch (jg_step_batch(world, K)) from the
+batch's initial state, with every input already resident in HBM; W warm-up steps run
+first and the initial state is then restored.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2606_28394_amd/csrc/jenga_step.hip", "paper_2606_28394_amd/csrc/jenga_device.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_flops(n_bodies_per_tower, steps, candidates, manifolds, points, iters):
+    """FP32 operations the method needs (not what the kernel executes), summed over a launch:
+    per tower-step 250 N (frames, integration) + 12 N(N-1)/2 (AABB tests) + 350 per candidate
+    (SAT) + 1200 per manifold (projection, clipping) + 210 per point (prep) + 156 per point and
+    iteration (three PGS rows) + 90 per point (residual)."""
+    pair_tests = sum(12.0 * n * (n - 1) / 2 + 250.0 * n for n in n_bodies_per_tower) * steps
+    return pair_tests + 350.0 * candidates + 1200.0 * manifolds + (210.0 + 156.0 * iters + 90.0) * points
+
+
+def algorithmic_bytes(n_bodies_total, n_points_launch_end):
+    """HBM bytes one launch must move: body state in and out (13 floats each way + 5 static
+    words read) and the final contacts written (32 B per point)."""
+    return n_bodies_total * (13 * 4 * 2 + 5 * 4) + 32.0 * n_points_launch_end
+
+
+def traffic_from_profile(khash: str, workload: str):
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != khash or rec.get("workload") != workload:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scene, n_towers=1024, n_steps=50, threads=None):
+    """The FP64 oracle on the host cores over a bounded sample of the same batch."""
+    from oracle import oracle as O
+    from paper_2606_28394_amd import workloads as W
+    threads = threads or min(16, os.cpu_count() or 1)
+    sub = W.subset(scene, range(min(n_towers, scene["n_towers"])))
+    ow = O.OracleWorld(sub)
+    t0 = time.perf_counter()
+    ow.step(n_steps, threads=threads)
+    dt = time.perf_counter() - t0
+    ci = sum(ow.tower_stats(t).contact_iters for t in range(sub["n_towers"]))
+    return dict(value=sub["n_towers"] * n_steps / dt, unit="tower-steps/s", cores=threads, kind="oracle",
+                sample=f"first {sub['n_towers']} towers x {n_steps} steps of the same batch, FP64, "
+                       f"{threads} threads, {dt:.1f} s",
+                contact_iters_per_s=ci / dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--towers", type=int, default=16384)
+    ap.add_argument("--warm-start", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-towers", type=int, default=1024)
+    ap.add_argument("--cpu-steps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); towers shard across GPUs with no "
+              "exchange, so a multi-GPU run would be N independent copies of this one", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_28394_amd import jenga as J
+    from paper_2606_28394_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    J.load_library()
+    log("generating the batch ...")
+    t0 = time.perf_counter()
+    scene = W.cfg3(0, n_towers=args.towers, n_steps=args.steps)
+    log(f"  {scene['n_towers']} towers, {int(scene['tower_ptr'][-1])} bodies in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+    world = J.World(scene, warm_start=args.warm_start, stream=stream.cuda_stream)
+    sizes = np.diff(scene["tower_ptr"]).tolist()
+    init = world.state()
+
+    if args.warmup > 0:
+        world.step(args.warmup)
+        world.sync()
+        log(f"warm-up {args.warmup} steps done")
+        world.set_state(*init)
+    world.step(0)          # make the restored state resident before the timed region
+    world.sync()
+    s0 = world.stats()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    world.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1)
+    s1 = world.stats()
+    log(f"timed {args.steps} steps: wall {wall * 1e3:.1f} ms, kernel (events) {kernel_ms:.1f} ms")
+
+    T = scene["n_towers"]
+    cand = s1.candidates - s0.candidates
+    man = s1.manifolds - s0.manifolds
+    pts = s1.points - s0.points
+    ci = s1.contact_iters - s0.contact_iters
+    tower_steps = T * args.steps
+    value = tower_steps / wall
+    flops = algorithmic_flops(sizes, args.steps, cand, man, pts, 20)
+    achieved_tflops = flops / (kernel_ms * 1e-3) / 1e12
+    workload = f"throughput batch: {T} tilted towers, 8-40 levels x 3 boxes, {args.steps} steps"
+    traffic = traffic_from_profile(kernel_hash(), workload)
+    last_points = pts / max(1, args.steps)
+    bytes_launch = algorithmic_bytes(int(scene["tower_ptr"][-1]), last_points)
+    out = {
+        "metric": "tower-steps/s",
+        "value": value,
+        "unit": "tower-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "towers": T, "bodies": int(scene["tower_ptr"][-1]),
+                   "pgs_iters": 20, "dt": 1 / 240, "warm_start": "previous step" if args.warm_start else "zero",
+                   "launch": "one persistent launch of all steps, one 64-lane workgroup per pack of towers"},
+        "contact_iters_per_s": ci / wall,
+        "kernel_ms": kernel_ms,
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "hbm_algorithmic_gbs": bytes_launch / (kernel_ms * 1e-3) / 1e9},
+        "error_word": int(s1.error_word),
+        "residual_rms_max": s1.residual_rms,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_towers, args.cpu_steps)
+    world.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

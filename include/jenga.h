@@ -132,7 +132,10 @@ int32_t jg_set_push(jg_world* w, int32_t body, const double force[3], int32_t st
 /* Activate (1) or remove (0) a body; inactive bodies neither move nor collide. */
 int32_t jg_set_active(jg_world* w, int32_t body, int32_t active);
 
-/* Queue n_steps steps of every tower on the world's stream (one kernel launch). */
+/* Queue n_steps steps of every tower on the world's stream (one kernel launch).  Changes made
+ * on the host since the last call (bodies, pushes, state, friction) are copied to the device
+ * first; n_steps = 0 only does that copy.  The on-chip packing is recomputed (and per-pack
+ * buffers reallocated) after towers or pushes were added. */
 int32_t jg_step_batch(jg_world* w, int32_t n_steps);
 
 /* Copy bodies [first_body, first_body + n) to host arrays (any may be NULL).  Waits. */

@@ -215,7 +215,8 @@ int32_t build_layout(jg_world* w) {
   const float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 4.0f;
   w->nbp = nbp;
   w->pc = std::max(64, (int)std::ceil(mpb * nbp));
-  w->cc = std::max(128, 8 * nbp);
+  // broadphase candidates reach ~9 per body while a tilted tower falls apart
+  w->cc = std::max(256, 16 * nbp);
   w->tpc = tpc;
   w->ppc = ppc;
   const int64_t words = jg::lds_words(w->nbp, w->pc, w->cc, w->tpc, w->ppc, w->prm.warm_start == 1);
@@ -519,7 +520,6 @@ int32_t jg_set_active(jg_world* w, int32_t body, int32_t active) {
 int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   if (int32_t r = check_world(w)) return r;
   if (n_steps < 0) return fail(JG_EINVAL, "negative step count");
-  if (n_steps == 0) return JG_OK;
   if (int32_t r = set_device(w)) return r;
   if (w->layout_dirty || w->host_dirty) {
     if (int32_t r = download_state(w)) return r;
@@ -528,10 +528,11 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
       if (int32_t r = build_layout(w)) return r;
     if (int32_t r = upload_all(w)) return r;
   }
-  if (w->clear_warm) {
-    HIP_TRY(hipMemsetAsync(w->d_prev_count.p, 0, sizeof(int32_t) * std::max(1, w->n_packs), w->stream));
+  if (w->clear_warm && w->n_packs > 0) {
+    HIP_TRY(hipMemsetAsync(w->d_prev_count.p, 0, sizeof(int32_t) * w->n_packs, w->stream));
     w->clear_warm = false;
   }
+  if (n_steps == 0) return JG_OK;   // host changes are now resident on the device
   if (w->n_packs == 0) { w->step += n_steps; return JG_OK; }
   jg::StepArgs a;
   std::memset(&a, 0, sizeof(a));

@@ -109,28 +109,19 @@ def jenga_tower(levels: int, rng: np.random.Generator | None, half=BLOCK_HALF,
     n = 3 * levels
     he = np.tile(half, (n, 1))
     m = np.full(n, float(mass))
-    pos = np.zeros((n, 3))
-    quat = np.zeros((n, 4))
-    lev = np.zeros(n, dtype=np.int32)
-    slot = np.zeros(n, dtype=np.int32)
-    for l in range(levels):
-        z = half[2] - BED_OVERLAP + l * (thick - BED_OVERLAP)
-        along_x = (l % 2 == 0)
-        q = np.array([1.0, 0.0, 0.0, 0.0]) if along_x else quat_z(math.pi / 2)
-        for s in range(3):
-            k = 3 * l + s
-            off = (s - 1) * (width + LAYER_GAP)
-            if rng is not None and jitter > 0:
-                jx, jy = rng.uniform(-jitter, jitter, size=2)
-            else:
-                jx = jy = 0.0
-            if along_x:
-                pos[k] = (jx, off + jy, z)
-            else:
-                pos[k] = (off + jx, jy, z)
-            quat[k] = q
-            lev[k] = l
-            slot[k] = s
+    lev = np.repeat(np.arange(levels, dtype=np.int32), 3)
+    slot = np.tile(np.arange(3, dtype=np.int32), levels)
+    if rng is not None and jitter > 0:
+        jit = rng.uniform(-jitter, jitter, size=(n, 2))    # drawn per block in tower order
+    else:
+        jit = np.zeros((n, 2))
+    along_x = (lev % 2 == 0)
+    off = (slot - 1) * (width + LAYER_GAP)
+    z = half[2] - BED_OVERLAP + lev * (thick - BED_OVERLAP)
+    pos = np.stack([np.where(along_x, jit[:, 0], off + jit[:, 0]),
+                    np.where(along_x, off + jit[:, 1], jit[:, 1]), z], 1)
+    q90 = quat_z(math.pi / 2)
+    quat = np.where(along_x[:, None], np.array([1.0, 0.0, 0.0, 0.0]), q90)
     return he, m, pos, quat, lev, slot
 
 
@@ -171,7 +162,10 @@ def tilt_about_edge(pos, quat, he, theta: float, edge: int):
     qr = quat_axis_angle(axis, theta)
     Rr = _rot_matrices(qr[None, :])[0]
     npos = pivot + (np.asarray(pos) - pivot) @ Rr.T
-    nquat = np.array([quat_mul(qr, q) for q in quat])
+    aw, ax, ay, az = qr
+    bw, bx, by, bz = (np.asarray(quat)[:, k] for k in range(4))
+    nquat = np.stack([aw * bw - ax * bx - ay * by - az * bz, aw * bx + ax * bw + ay * bz - az * by,
+                      aw * by - ax * bz + ay * bw + az * bx, aw * bz + ax * by - ay * bx + az * bw], 1)
     return npos, nquat
 
 

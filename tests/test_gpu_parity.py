@@ -39,6 +39,7 @@ def _one_step_compare(J, oracle, scene, states, warm_start=0, n_check_towers=Non
                 J.jg_set_active(gw.h, i, 0)
         ow.step(1)
         gw.step(1)
+        assert gw.stats().error_word == 0, f"{label}: device error word {gw.stats().error_word}"
         gx, gq, gv, gww = gw.state()
         st = compare_state(ow, gx, gq, gv, gww)
         for t in towers:
