@@ -138,10 +138,11 @@ static void sat_R(const double heA[3], const double xA[3], const double RA[9],
   double s = dot3(d, axes[best]) < 0.0 ? -1.0 : 1.0;
   for (int k = 0; k < 3; ++k) out->normal[k] = s * axes[best][k];
   if (fabs(out->sigma) < BAND) band |= OR_BAND_SEPARATION;
-  /* second best axis that is not parallel to the chosen one */
+  /* second best axis that is not parallel to the chosen one (axes closer than ~4e-7 rad give
+   * the same normal to single precision; anything further apart changes the contact frame) */
   for (int a = 0; a < 15; ++a) {
     if (!tested[a] || a == best) continue;
-    if (fabs(dot3(axes[a], axes[best])) > 1.0 - 1e-9) continue;
+    if (fabs(dot3(axes[a], axes[best])) > 1.0 - 1e-13) continue;
     if (delta[a] - dmin < BAND) band |= OR_BAND_NORMAL;
   }
   out->band = band;

@@ -6,10 +6,10 @@
 // Per step (Secs. "Rigid-Body Foundations", "Physics Engine --- Collision
 // Detection", "Contact Solver --- Projected Gauss-Seidel (PGS)"):
 //   1 external forces: v += dt g + dt F/m (semi-implicit Euler)
-//   2 frames: R(q) (Eq. (rotmat)), world AABB half sizes, I_w^-1 = R I_b^-1 R^T
-//   3 broadphase (Eq. (aabb)): all same-tower pairs i<j plus the ground; ballot
-//     compaction keeps the canonical (i, j) order
-//   4 narrowphase: 15-axis SAT, normal = first least-penetration axis
+//   2 frames: world AABB half sizes, I_w^-1 = R I_b^-1 R^T with R from Eq. (rotmat)
+//   3 broadphase (Eq. (aabb)): all same-tower pairs i<j plus the ground, ballot
+//     compaction into a small ring that keeps the canonical (i, j) order
+//   4 narrowphase: 15-axis SAT on each 64 candidates as soon as the ring holds them
 //   5 greedy first-fit colouring over the canonical list (bit masks per body)
 //   6 manifolds, written straight into colour-sorted slots: the silhouettes of
 //     both boxes along n are zonogons (three projected half-edges); the clipped
@@ -19,7 +19,8 @@
 //   7 PGS: colour by colour, one lane per manifold, its points and rows in
 //     order (Eq. (lambda_n) then Eq. (coulomb_pgs) on t1, t2); manifolds of one
 //     colour share no dynamic body, so each colour is an exact Gauss-Seidel sweep
-//   8 residual of the solve (natural map)
+//   8 residual of the solve (natural map), reduced per tower over its contiguous
+//     canonical range
 //   9 integration: x += dt v, q from Eq. (quat_int) with world-frame omega,
 //     omega re-derived from the angular momentum (Eq. (newton_euler), torque free)
 //  10 Baumgarte correction (Eq. (baumgarte)), colour by colour
@@ -37,61 +38,65 @@ constexpr uint32_t kErrCand = 1u, kErrMan = 2u, kErrCol = 4u, kErrNan = 8u;
 
 struct Lds {
   // bodies [comp * nbp + i]
-  float *x, *q, *v, *w, *he, *invm, *invI, *R, *Iw, *h;
-  uint32_t *flag, *mask;
+  float *x, *q, *v, *w, *he, *invm, *invI, *Iw;
+  float* hm;          // AABB half sizes during the broadphase, then colour masks (2 words)
+  uint32_t* flag;
   int32_t* tw;
   // towers
   int32_t *tb0, *tb1;
   float* mu;
-  uint32_t* tcnt;   // [t*4 + k]
-  float* tres;      // [t*2 + k]
+  uint32_t* tcnt;     // [t*4 + k]: candidates, manifolds, points (launch totals), colours (last step)
+  float* tres;        // [t*2 + k]
+  int32_t *tc0, *tc1, *tpts;   // canonical range and points of the current step
   // pushes
   int32_t *pb, *ps, *pn;
   float *pf, *pwd, *px0;
   // colours and scalars
   int32_t *coloff, *colcnt, *scal;
-  // broadphase candidates
-  uint32_t* cand;
-  // canonical colliding pairs
+  uint32_t* ring;
+  // canonical colliding pairs (code, colour-sorted position); residual partials afterwards
   uint32_t* cab;
-  float *cn, *cdepth;
   int32_t* cpos;
   // colour-sorted manifolds
   uint32_t *mab, *mmeta;
   float *mn, *mt1, *mdepth;
+  float *mr, *ml;     // [(j*3 + k) * pc + m]
+  // warm start: sorted -> canonical, previous step store (canonical order)
   int32_t* mcanon;
-  float *mr, *ml;   // [(j*3 + k) * pc + m]
-  // previous step (warm start), canonical order
   uint32_t *pkey, *pslot;
   float *pnrm, *plam;
-  int nbp, pc, cc, tpc, ppc;
+  int nbp, pc;
 };
 
 __device__ inline Lds carve(float* base, const StepArgs& a) {
   Lds L;
-  L.nbp = a.nbp; L.pc = a.pc; L.cc = a.cc; L.tpc = a.tpc; L.ppc = a.ppc;
+  L.nbp = a.nbp;
+  L.pc = a.pc;
   float* p = base;
   auto take = [&](int n) { float* r = p; p += n; return r; };
-  const int nb = a.nbp, pc = a.pc;
+  const int nb = a.nbp, pc = a.pc, nt = a.tpc, np = a.ppc;
   L.x = take(3 * nb); L.q = take(4 * nb); L.v = take(3 * nb); L.w = take(3 * nb);
   L.he = take(3 * nb); L.invm = take(nb); L.invI = take(3 * nb);
   L.flag = (uint32_t*)take(nb); L.tw = (int32_t*)take(nb);
-  L.R = take(9 * nb); L.Iw = take(6 * nb); L.h = take(3 * nb);
-  L.mask = (uint32_t*)take(2 * nb);
-  L.tb0 = (int32_t*)take(a.tpc); L.tb1 = (int32_t*)take(a.tpc); L.mu = take(a.tpc);
-  L.tcnt = (uint32_t*)take(4 * a.tpc); L.tres = take(2 * a.tpc); take(a.tpc);
-  L.pb = (int32_t*)take(a.ppc); L.ps = (int32_t*)take(a.ppc); L.pn = (int32_t*)take(a.ppc);
-  L.pf = take(3 * a.ppc); L.pwd = take(a.ppc); L.px0 = take(3 * a.ppc);
+  L.Iw = take(6 * nb); L.hm = take(3 * nb);
+  L.tb0 = (int32_t*)take(nt); L.tb1 = (int32_t*)take(nt); L.mu = take(nt);
+  L.tcnt = (uint32_t*)take(4 * nt); L.tres = take(2 * nt);
+  L.tc0 = (int32_t*)take(nt); L.tc1 = (int32_t*)take(nt); L.tpts = (int32_t*)take(nt);
+  L.pb = (int32_t*)take(np); L.ps = (int32_t*)take(np); L.pn = (int32_t*)take(np);
+  L.pf = take(3 * np); L.pwd = take(np); L.px0 = take(3 * np);
   L.coloff = (int32_t*)take(kMaxColours + 1); L.colcnt = (int32_t*)take(kMaxColours + 1);
   L.scal = (int32_t*)take(16);
-  L.cand = (uint32_t*)take(a.cc);
-  L.cab = (uint32_t*)take(pc); L.cn = take(3 * pc); L.cdepth = take(pc); L.cpos = (int32_t*)take(pc);
+  L.ring = (uint32_t*)take(kRing);
+  L.cab = (uint32_t*)take(pc); L.cpos = (int32_t*)take(pc);
   L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc); L.mn = take(3 * pc); L.mt1 = take(3 * pc);
-  L.mdepth = take(pc); L.mcanon = (int32_t*)take(pc); L.mr = take(12 * pc); L.ml = take(12 * pc);
+  L.mdepth = take(pc); L.mr = take(12 * pc); L.ml = take(12 * pc);
   if (a.warm_start) {
+    L.mcanon = (int32_t*)take(pc);
     L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
   } else {
-    L.pkey = L.pslot = nullptr; L.pnrm = L.plam = nullptr;
+    L.mcanon = nullptr;
+    L.pkey = L.pslot = nullptr;
+    L.pnrm = L.plam = nullptr;
   }
   return L;
 }
@@ -116,9 +121,9 @@ __device__ inline void quat_rot(float w, float x, float y, float z, float R[9]) 
   R[6] = 2.f * (x * z - y * w);       R[7] = 2.f * (y * z + x * w);       R[8] = 1.f - 2.f * (x * x + y * y);
 }
 
-__device__ inline void load_R(const Lds& L, int i, float R[9]) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) R[k] = L.R[k * L.nbp + i];
+__device__ inline void body_R(const Lds& L, int i, float R[9]) {
+  const int nb = L.nbp;
+  quat_rot(L.q[i], L.q[nb + i], L.q[2 * nb + i], L.q[3 * nb + i], R);
 }
 __device__ inline void load3(const float* a, int stride, int i, float o[3]) {
   o[0] = a[i]; o[1] = a[stride + i]; o[2] = a[2 * stride + i];
@@ -149,32 +154,32 @@ __device__ bool sat_boxes(const float RA[9], const float heA[3], const float RB[
     for (int k = 0; k < 3; ++k) { A[i][k] = RA[3 * k + i]; B[i][k] = RB[3 * k + i]; }
   float best = INFINITY;
   float bu[3] = {0.f, 0.f, 1.f};
-  auto axis = [&](const float u[3]) -> bool {
+  bool sep = false;
+  auto axis = [&](const float u[3]) {
     const float ra = heA[0] * fabsf(dot3(A[0], u)) + heA[1] * fabsf(dot3(A[1], u)) + heA[2] * fabsf(dot3(A[2], u));
     const float rb = heB[0] * fabsf(dot3(B[0], u)) + heB[1] * fabsf(dot3(B[1], u)) + heB[2] * fabsf(dot3(B[2], u));
     const float dd = ra + rb - fabsf(dot3(d, u));
-    if (!(dd > 0.f)) return false;
+    sep = sep || !(dd > 0.f);
     if (dd < best) { best = dd; bu[0] = u[0]; bu[1] = u[1]; bu[2] = u[2]; }
-    return true;
   };
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-    if (!axis(A[i])) return false;
+  for (int i = 0; i < 3; ++i) axis(A[i]);
 #pragma unroll
-  for (int j = 0; j < 3; ++j)
-    if (!axis(B[j])) return false;
+  for (int j = 0; j < 3; ++j) axis(B[j]);
+  if (sep) return false;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       float c[3];
       cross3(A[i], B[j], c);
-      const float len = sqrtf(dot3(c, c));
-      if (len < 1e-5f) continue;
-      const float il = 1.f / len;
+      const float len2 = dot3(c, c);
+      if (len2 < 1e-10f) continue;          // |a x b| < 1e-5: not tested
+      const float il = rsqrtf(len2);
       c[0] *= il; c[1] *= il; c[2] *= il;
-      if (!axis(c)) return false;
+      axis(c);
     }
+  if (sep) return false;
   const float s = dot3(d, bu) < 0.f ? -1.f : 1.f;
   n[0] = s * bu[0]; n[1] = s * bu[1]; n[2] = s * bu[2];
   depth = best;
@@ -254,10 +259,10 @@ struct Extremes {
   }
 };
 
-// returns number of points; rA[j] relative to A's centre, slot[j] in 0..3
-__device__ int manifold_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
-                              const float d[3], const float n[3], float t1[3], float t2[3], float rA[4][3],
-                              int slot[4]) {
+// Points relative to A's centre in slot order; bit s of the result marks slot s as used.
+__device__ uint32_t manifold_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
+                                   const float d[3], const float n[3], float t1[3], float rA[4][3]) {
+  float t2[3];
   tangent_basis(n, t1, t2);
   Zono ZA, ZB;
   float zA = 0.f, zB = dot3(d, n);
@@ -296,16 +301,16 @@ __device__ int manifold_boxes(const float RA[9], const float heA[3], const float
     const V2 p0 = ha[i], p1 = ha[(i + 1) % 6];
     const V2 u = {p1.x - p0.x, p1.y - p0.y};
     const float lu = u.x * u.x + u.y * u.y;
-    if (lu < 1e-18f) continue;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const V2 q0 = hb[j], q1 = hb[(j + 1) % 6];
       const V2 w = {q1.x - q0.x, q1.y - q0.y};
       const float den = cr2(u, w);
       const float lw = w.x * w.x + w.y * w.y;
-      if (den * den <= 1e-12f * lu * lw) continue;   // parallel edges
+      if (lu < 1e-18f || den * den <= 1e-12f * lu * lw) continue;   // empty or parallel edges
       const V2 r = {q0.x - p0.x, q0.y - p0.y};
-      const float t = cr2(r, w) / den, s = cr2(r, u) / den;
+      const float id = 1.f / den;
+      const float t = cr2(r, w) * id, s = cr2(r, u) * id;
       if (t >= -1e-6f && t <= 1.f + 1e-6f && s >= -1e-6f && s <= 1.f + 1e-6f) {
         V2 pt = {p0.x + t * u.x, p0.y + t * u.y};
         E.consider(pt);
@@ -316,7 +321,6 @@ __device__ int manifold_boxes(const float RA[9], const float heA[3], const float
   const float zmid = 0.5f * (zA + zB);
   if (!any) {
     // empty clip: halfway between the support corners of A (max along n) and B (min)
-    int ka = 0, kb = 0;
     float ba = -INFINITY, bb = INFINITY;
     float ca[3] = {0, 0, 0}, cb[3] = {0, 0, 0};
 #pragma unroll
@@ -330,32 +334,27 @@ __device__ int manifold_boxes(const float RA[9], const float heA[3], const float
         pb[r] = d[r] + RB[3 * r] * sb[0] + RB[3 * r + 1] * sb[1] + RB[3 * r + 2] * sb[2];
       }
       const float da = dot3(pa, n), db = dot3(pb, n);
-      if (da > ba) { ba = da; ka = k; ca[0] = pa[0]; ca[1] = pa[1]; ca[2] = pa[2]; }
-      if (db < bb) { bb = db; kb = k; cb[0] = pb[0]; cb[1] = pb[1]; cb[2] = pb[2]; }
+      if (da > ba) { ba = da; ca[0] = pa[0]; ca[1] = pa[1]; ca[2] = pa[2]; }
+      if (db < bb) { bb = db; cb[0] = pb[0]; cb[1] = pb[1]; cb[2] = pb[2]; }
     }
-    (void)ka; (void)kb;
-    rA[0][0] = 0.5f * (ca[0] + cb[0]); rA[0][1] = 0.5f * (ca[1] + cb[1]); rA[0][2] = 0.5f * (ca[2] + cb[2]);
-    slot[0] = 0;
-    return 1;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) rA[0][r] = 0.5f * (ca[r] + cb[r]);
+    return 1u;
   }
-  int np = 0;
-  V2 kept[4];
+  uint32_t used = 0u;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    if (E.best[s] == -INFINITY) continue;
-    bool dup = false;
-    for (int c = 0; c < np; ++c) {
-      const float dx = E.p[s].x - kept[c].x, dy = E.p[s].y - kept[c].y;
-      dup = dup || (dx * dx + dy * dy < 1e-12f);
-    }
-    if (dup) continue;
-    kept[np] = E.p[s];
+    bool ok = E.best[s] != -INFINITY;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) rA[np][r] = E.p[s].x * t1[r] + E.p[s].y * t2[r] + zmid * n[r];
-    slot[np] = s;
-    ++np;
+    for (int c = 0; c < s; ++c) {
+      const float dx = E.p[s].x - E.p[c].x, dy = E.p[s].y - E.p[c].y;
+      ok = ok && !(((used >> c) & 1u) && (dx * dx + dy * dy < 1e-12f));
+    }
+    if (ok) used |= 1u << s;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) rA[s][r] = E.p[s].x * t1[r] + E.p[s].y * t2[r] + zmid * n[r];
   }
-  return np;
+  return used;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -380,7 +379,6 @@ __device__ inline void apply_row(BodyRegs& A, BodyRegs& B, const float rA[3], co
   }
 }
 
-// solves row d: normal (bound < 0 means the non-negative clamp with restitution) or tangent
 template <bool kNormal>
 __device__ inline float solve_row(BodyRegs& A, BodyRegs& B, const float rA[3], const float rB[3], const float d[3],
                                   float lam, float bound, float e) {
@@ -506,7 +504,7 @@ __device__ void warm_apply_manifold(const Lds& L, int m) {
   if (b != (int)kGround) store_body(L, b, B);
 }
 
-// natural-map residual of one manifold: returns sum of squares, max |r|
+// natural-map residual of one manifold: sum of squares and max |r| over its rows
 __device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, float& mx) {
   const int pc = L.pc;
   int a, b;
@@ -553,6 +551,36 @@ __device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, flo
 
 __device__ inline uint64_t lane_lt_mask(int lane) { return lane ? ((~0ull) >> (64 - lane)) : 0ull; }
 
+// SAT on up to 64 ring entries starting at `head`; colliding pairs are appended (in order)
+// to the canonical list.  Returns the new list length.
+__device__ int narrow_chunk(const Lds& L, int head, int count, int nman, int lane) {
+  const int NB = L.nbp;
+  bool hit = false;
+  uint32_t code = 0;
+  if (lane < count) {
+    code = L.ring[(head + lane) & (kRing - 1)];
+    const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
+    if (j == (int)kGround) {
+      hit = L.x[2 * NB + i] - L.hm[2 * NB + i] < 0.f;
+    } else {
+      float RA[9], RB[9], heA[3], heB[3], d[3], n[3], depth;
+      body_R(L, i, RA);
+      body_R(L, j, RB);
+      load3(L.he, NB, i, heA);
+      load3(L.he, NB, j, heB);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
+      hit = sat_boxes(RA, heA, RB, heB, d, n, depth);
+    }
+  }
+  const uint64_t bal = __ballot(hit);
+  if (hit) {
+    const int idx = nman + __popcll(bal & lane_lt_mask(lane));
+    if (idx < L.pc) L.cab[idx] = code;
+  }
+  return nman + __popcll(bal);
+}
+
 // ------------------------------------------------------------------------------------------------
 // the kernel
 // ------------------------------------------------------------------------------------------------
@@ -560,10 +588,11 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   extern __shared__ float smem[];
   const Lds L = carve(smem, a);
   const int lane = threadIdx.x;
-  const int pk = blockIdx.x;
+  const int pk = a.pack_first + blockIdx.x;
   const int gb0 = a.pack_body0[pk], nb = a.pack_body0[pk + 1] - gb0;
   const int gt0 = a.pack_tower0[pk], nt = a.pack_tower0[pk + 1] - gt0;
   const int gp0 = a.pack_push0[pk], np = a.pack_push0[pk + 1] - gp0;
+  const int slot0 = a.pack_slot0[pk];
   const int NB = L.nbp, PC = L.pc, CAP = a.cap;
 
   // ---- load the pack ----
@@ -614,7 +643,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   if (a.warm_start) {
     const int npv = a.prev_count[pk];
     for (int p = lane; p < npv; p += kWave) {
-      const int g = pk * PC + p;
+      const int g = slot0 + p;
       L.pkey[p] = a.prev_key[g];
       L.pslot[p] = __float_as_uint(a.prev_data[16 * g + 3]);
 #pragma unroll
@@ -640,7 +669,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       // ---- 1. external forces; 2. frames ----
       for (int i = lane; i < nb; i += kWave) {
         const uint32_t f = L.flag[i];
-        if ((f & (kActive | kDynamic)) == (kActive | kDynamic)) {
+        const bool moving = (f & (kActive | kDynamic)) == (kActive | kDynamic);
+        if (moving) {
           float vv[3];
           load3(L.v, NB, i, vv);
 #pragma unroll
@@ -654,35 +684,33 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           store3(L.v, NB, i, vv);
         }
         float R[9];
-        quat_rot(L.q[i], L.q[NB + i], L.q[2 * NB + i], L.q[3 * NB + i], R);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) L.R[k * NB + i] = R[k];
+        body_R(L, i, R);
         const float he0 = L.he[i], he1 = L.he[NB + i], he2 = L.he[2 * NB + i];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          L.h[k * NB + i] = fabsf(R[3 * k]) * he0 + fabsf(R[3 * k + 1]) * he1 + fabsf(R[3 * k + 2]) * he2;
+          L.hm[k * NB + i] = fabsf(R[3 * k]) * he0 + fabsf(R[3 * k + 1]) * he1 + fabsf(R[3 * k + 2]) * he2;
         float d[3];
-        if ((f & (kActive | kDynamic)) == (kActive | kDynamic)) load3(L.invI, NB, i, d);
+        if (moving) load3(L.invI, NB, i, d);
         else d[0] = d[1] = d[2] = 0.f;
         // R diag(d) R^T
-        float I6[6];
-        I6[0] = R[0] * d[0] * R[0] + R[1] * d[1] * R[1] + R[2] * d[2] * R[2];
-        I6[1] = R[3] * d[0] * R[3] + R[4] * d[1] * R[4] + R[5] * d[2] * R[5];
-        I6[2] = R[6] * d[0] * R[6] + R[7] * d[1] * R[7] + R[8] * d[2] * R[8];
-        I6[3] = R[0] * d[0] * R[3] + R[1] * d[1] * R[4] + R[2] * d[2] * R[5];
-        I6[4] = R[0] * d[0] * R[6] + R[1] * d[1] * R[7] + R[2] * d[2] * R[8];
-        I6[5] = R[3] * d[0] * R[6] + R[4] * d[1] * R[7] + R[5] * d[2] * R[8];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) L.Iw[k * NB + i] = I6[k];
-        L.mask[2 * i] = 0u;
-        L.mask[2 * i + 1] = 0u;
+        L.Iw[i] = R[0] * d[0] * R[0] + R[1] * d[1] * R[1] + R[2] * d[2] * R[2];
+        L.Iw[NB + i] = R[3] * d[0] * R[3] + R[4] * d[1] * R[4] + R[5] * d[2] * R[5];
+        L.Iw[2 * NB + i] = R[6] * d[0] * R[6] + R[7] * d[1] * R[7] + R[8] * d[2] * R[8];
+        L.Iw[3 * NB + i] = R[0] * d[0] * R[3] + R[1] * d[1] * R[4] + R[2] * d[2] * R[5];
+        L.Iw[4 * NB + i] = R[0] * d[0] * R[6] + R[1] * d[1] * R[7] + R[2] * d[2] * R[8];
+        L.Iw[5 * NB + i] = R[3] * d[0] * R[6] + R[4] * d[1] * R[7] + R[5] * d[2] * R[8];
       }
       for (int c = lane; c <= kMaxColours; c += kWave) L.colcnt[c] = 0;
-      for (int t = lane; t < nt; t += kWave) L.tcnt[t * 4 + 3] = 0u;
+      for (int t = lane; t < nt; t += kWave) {
+        L.tcnt[t * 4 + 3] = 0u;
+        L.tc0[t] = 0;
+        L.tc1[t] = 0;
+        L.tpts[t] = 0;
+      }
       __syncthreads();
 
-      // ---- 3. broadphase: same-tower pairs i<j, then the ground, in canonical order ----
-      int ncand = 0;
+      // ---- 3 + 4. broadphase in canonical order, narrowphase on every 64 candidates ----
+      int head = 0, tail = 0, nman = 0;
       for (int i = 0; i < nb; ++i) {
         const uint32_t fi = L.flag[i];
         if (!(fi & kActive)) continue;
@@ -690,7 +718,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         const int ti = L.tw[i];
         const int npair = L.tb1[ti] - i - 1;
         const float xi0 = L.x[i], xi1 = L.x[NB + i], xi2 = L.x[2 * NB + i];
-        const float hi0 = L.h[i], hi1 = L.h[NB + i], hi2 = L.h[2 * NB + i];
+        const float hi0 = L.hm[i], hi1 = L.hm[NB + i], hi2 = L.hm[2 * NB + i];
         for (int c0 = 0; c0 <= npair; c0 += kWave) {
           const int jj = c0 + lane;
           bool hit = false;
@@ -699,9 +727,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             const int j = i + 1 + jj;
             const uint32_t fj = L.flag[j];
             if ((fj & kActive) && (dyni || (fj & kDynamic))) {
-              hit = fabsf(xi0 - L.x[j]) <= hi0 + L.h[j] + a.margin &&
-                    fabsf(xi1 - L.x[NB + j]) <= hi1 + L.h[NB + j] + a.margin &&
-                    fabsf(xi2 - L.x[2 * NB + j]) <= hi2 + L.h[2 * NB + j] + a.margin;
+              hit = fabsf(xi0 - L.x[j]) <= hi0 + L.hm[j] + a.margin &&
+                    fabsf(xi1 - L.x[NB + j]) <= hi1 + L.hm[NB + j] + a.margin &&
+                    fabsf(xi2 - L.x[2 * NB + j]) <= hi2 + L.hm[2 * NB + j] + a.margin;
             }
             code = ((uint32_t)i << 16) | (uint32_t)j;
           } else if (jj == npair) {
@@ -709,55 +737,22 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             code = ((uint32_t)i << 16) | kGround;
           }
           const uint64_t bal = __ballot(hit);
-          if (hit) {
-            const int idx = ncand + __popcll(bal & lane_lt_mask(lane));
-            if (idx < L.cc) L.cand[idx] = code;
+          if (hit) L.ring[(tail + __popcll(bal & lane_lt_mask(lane))) & (kRing - 1)] = code;
+          const int cnt = __popcll(bal);
+          if (lane == 0 && cnt) L.tcnt[ti * 4 + 0] += (uint32_t)cnt;
+          tail += cnt;
+          if (tail - head >= kWave) {
+            __syncthreads();
+            nman = narrow_chunk(L, head, kWave, nman, lane);
+            head += kWave;
           }
-          if (lane == 0) L.tcnt[ti * 4 + 0] += (uint32_t)__popcll(bal);
-          ncand += __popcll(bal);
         }
-      }
-      if (ncand > L.cc) {
-        if (lane == 0) L.scal[3] |= kErrCand;
-        ncand = L.cc;
       }
       __syncthreads();
-
-      // ---- 4. narrowphase (canonical order kept by stable compaction) ----
-      int nman = 0;
-      for (int c0 = 0; c0 < ncand; c0 += kWave) {
-        const int c = c0 + lane;
-        bool hit = false;
-        uint32_t code = 0;
-        float n[3] = {0.f, 0.f, -1.f}, depth = 0.f;
-        if (c < ncand) {
-          code = L.cand[c];
-          const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
-          if (j == (int)kGround) {
-            const float zlow = L.x[2 * NB + i] - L.h[2 * NB + i];
-            hit = zlow < 0.f;
-            depth = -zlow;
-          } else {
-            float RA[9], RB[9], heA[3], heB[3], d[3];
-            load_R(L, i, RA);
-            load_R(L, j, RB);
-            load3(L.he, NB, i, heA);
-            load3(L.he, NB, j, heB);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
-            hit = sat_boxes(RA, heA, RB, heB, d, n, depth);
-          }
-        }
-        const uint64_t bal = __ballot(hit);
-        if (hit) {
-          const int idx = nman + __popcll(bal & lane_lt_mask(lane));
-          if (idx < PC) {
-            L.cab[idx] = code;
-            L.cn[idx] = n[0]; L.cn[PC + idx] = n[1]; L.cn[2 * PC + idx] = n[2];
-            L.cdepth[idx] = depth;
-          }
-        }
-        nman += __popcll(bal);
+      while (head < tail) {
+        const int cnt = min(kWave, tail - head);
+        nman = narrow_chunk(L, head, cnt, nman, lane);
+        head += cnt;
       }
       if (nman > PC) {
         if (lane == 0) L.scal[3] |= kErrMan;
@@ -765,7 +760,15 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       }
       __syncthreads();
 
-      // ---- 5. greedy first-fit colouring over the canonical list ----
+      // ---- 5. tower ranges of the canonical list; greedy first-fit colouring ----
+      for (int p = lane; p < nman; p += kWave) {
+        const int t = L.tw[L.cab[p] >> 16];
+        if (p == 0 || L.tw[L.cab[p - 1] >> 16] != t) L.tc0[t] = p;
+        if (p == nman - 1 || L.tw[L.cab[p + 1] >> 16] != t) L.tc1[t] = p + 1;
+      }
+      for (int i = lane; i < nb; i += kWave) { L.hm[i] = 0.f; L.hm[NB + i] = 0.f; }
+      __syncthreads();
+      uint32_t* mask = (uint32_t*)L.hm;   // [word * nbp + body]
       if (lane == 0) {
         for (int p = 0; p < nman; ++p) {
           const uint32_t code = L.cab[p];
@@ -773,8 +776,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           const bool di = (L.flag[i] & kDynamic) != 0;
           const bool dj = j != (int)kGround && (L.flag[j] & kDynamic);
           uint64_t u = 0;
-          if (di) u |= (uint64_t)L.mask[2 * i] | ((uint64_t)L.mask[2 * i + 1] << 32);
-          if (dj) u |= (uint64_t)L.mask[2 * j] | ((uint64_t)L.mask[2 * j + 1] << 32);
+          if (di) u |= (uint64_t)mask[i] | ((uint64_t)mask[NB + i] << 32);
+          if (dj) u |= (uint64_t)mask[j] | ((uint64_t)mask[NB + j] << 32);
           if (u == ~0ull) {
             L.scal[3] |= kErrCol;
             L.cpos[p] = -1;
@@ -782,8 +785,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           }
           const int col = __ffsll((unsigned long long)~u) - 1;
           const uint64_t bit = 1ull << col;
-          if (di) { L.mask[2 * i] |= (uint32_t)bit; L.mask[2 * i + 1] |= (uint32_t)(bit >> 32); }
-          if (dj) { L.mask[2 * j] |= (uint32_t)bit; L.mask[2 * j + 1] |= (uint32_t)(bit >> 32); }
+          if (di) { mask[i] |= (uint32_t)bit; mask[NB + i] |= (uint32_t)(bit >> 32); }
+          if (dj) { mask[j] |= (uint32_t)bit; mask[NB + j] |= (uint32_t)(bit >> 32); }
           L.colcnt[col] += 1;
           L.cpos[p] = col;
           const int ti = L.tw[i];
@@ -813,15 +816,14 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         if (sidx < 0) continue;
         const uint32_t code = L.cab[p];
         const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
-        float n[3] = {L.cn[p], L.cn[PC + p], L.cn[2 * PC + p]};
-        float t1[3], t2[3], rA[4][3];
-        int slot[4];
+        float n[3], t1[3], rA[4][3], depth = 0.f;
+        uint32_t used = 0u, slots = 0u;
         int npts = 0;
-        float depth = L.cdepth[p];
+        float R[9], he[3];
+        body_R(L, i, R);
+        load3(L.he, NB, i, he);
         if (j == (int)kGround) {
-          float R[9], he[3];
-          load_R(L, i, R);
-          load3(L.he, NB, i, he);
+          // vertices below the ground: the four deepest (ties: lower vertex index), in index order
           const float xz = L.x[2 * NB + i];
           float vz[8];
 #pragma unroll
@@ -829,41 +831,47 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
             vz[k] = xz + (R[6] * s0 + R[7] * s1 + R[8] * s2);
           }
-          depth = 0.f;
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            if (!(vz[k] < 0.f)) continue;
             int rank = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) rank += (vz[q] < 0.f) && (vz[q] < vz[k] || (vz[q] == vz[k] && q < k));
-            if (rank >= 4) continue;
-            const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
-            rA[npts][0] = R[0] * s0 + R[1] * s1 + R[2] * s2;
-            rA[npts][1] = R[3] * s0 + R[4] * s1 + R[5] * s2;
-            const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
-            rA[npts][2] = 0.5f * (rz - xz);
-            slot[npts] = k;
-            depth = fmaxf(depth, -vz[k]);
-            ++npts;
+            if ((vz[k] < 0.f) && rank < 4) {
+              const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
+              const float rx = R[0] * s0 + R[1] * s1 + R[2] * s2;
+              const float ry = R[3] * s0 + R[4] * s1 + R[5] * s2;
+              const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
+              L.mr[(npts * 3 + 0) * PC + sidx] = rx;
+              L.mr[(npts * 3 + 1) * PC + sidx] = ry;
+              L.mr[(npts * 3 + 2) * PC + sidx] = 0.5f * (rz - xz);
+              slots |= (uint32_t)k << (4 * npts);
+              depth = fmaxf(depth, -vz[k]);
+              ++npts;
+            }
           }
           n[0] = 0.f; n[1] = 0.f; n[2] = -1.f;
           t1[0] = 1.f; t1[1] = 0.f; t1[2] = 0.f;
         } else {
-          float RA[9], RB[9], heA[3], heB[3], d[3];
-          load_R(L, i, RA);
-          load_R(L, j, RB);
-          load3(L.he, NB, i, heA);
+          float RB[9], heB[3], d[3];
+          body_R(L, j, RB);
           load3(L.he, NB, j, heB);
 #pragma unroll
           for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
-          npts = manifold_boxes(RA, heA, RB, heB, d, n, t1, t2, rA, slot);
+          sat_boxes(R, he, RB, heB, d, n, depth);   // same inputs as the narrowphase: same normal
+          used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2)
+            if ((used >> s2) & 1u) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) L.mr[(npts * 3 + k) * PC + sidx] = rA[s2][k];
+              slots |= (uint32_t)s2 << (4 * npts);
+              ++npts;
+            }
         }
         // warm start: previous step's impulses of the same (pair, slot) if the normal barely turned
-        float lam0[4][3];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) lam0[q][0] = lam0[q][1] = lam0[q][2] = 0.f;
+        int found = -1;
         if (a.warm_start && nprev > 0) {
-          int lo = 0, hi = nprev - 1, found = -1;
+          int lo = 0, hi = nprev - 1;
           while (lo <= hi) {
             const int mid = (lo + hi) >> 1;
             const uint32_t kk = L.pkey[mid];
@@ -872,35 +880,36 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           }
           if (found >= 0) {
             const float pn[3] = {L.pnrm[found], L.pnrm[PC + found], L.pnrm[2 * PC + found]};
-            if (dot3(pn, n) > 0.95f) {
-              const uint32_t ps = L.pslot[found];
-              const int pnp = (int)(ps & 15u);
-              for (int q = 0; q < npts; ++q)
-                for (int r = 0; r < pnp; ++r)
-                  if ((int)((ps >> (4 + 4 * r)) & 15u) == slot[q]) {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) lam0[q][k] = L.plam[(r * 3 + k) * PC + found];
-                  }
-            }
+            if (!(dot3(pn, n) > 0.95f)) found = -1;
           }
         }
-        uint32_t meta = (uint32_t)npts;
-        for (int q = 0; q < npts; ++q) meta |= (uint32_t)slot[q] << (12 + 4 * q);
+        for (int q = 0; q < npts; ++q) {
+          float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+          if (found >= 0) {
+            const uint32_t ps = L.pslot[found];
+            const int pnp = (int)(ps & 15u);
+            const uint32_t sq = (slots >> (4 * q)) & 15u;
+            for (int r = 0; r < pnp; ++r)
+              if (((ps >> (4 + 4 * r)) & 15u) == sq) {
+                l0 = L.plam[(r * 3 + 0) * PC + found];
+                l1 = L.plam[(r * 3 + 1) * PC + found];
+                l2 = L.plam[(r * 3 + 2) * PC + found];
+              }
+          }
+          L.ml[(q * 3 + 0) * PC + sidx] = l0;
+          L.ml[(q * 3 + 1) * PC + sidx] = l1;
+          L.ml[(q * 3 + 2) * PC + sidx] = l2;
+        }
         L.mab[sidx] = code;
-        L.mmeta[sidx] = meta;
-        L.mcanon[sidx] = p;
+        L.mmeta[sidx] = (uint32_t)npts | (slots << 12);
         L.mdepth[sidx] = depth;
+        if (a.warm_start) L.mcanon[sidx] = p;
 #pragma unroll
         for (int k = 0; k < 3; ++k) { L.mn[k * PC + sidx] = n[k]; L.mt1[k * PC + sidx] = t1[k]; }
-        for (int q = 0; q < npts; ++q)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            L.mr[(q * 3 + k) * PC + sidx] = rA[q][k];
-            L.ml[(q * 3 + k) * PC + sidx] = lam0[q][k];
-          }
         const int ti = L.tw[i];
         atomicAdd(&L.tcnt[ti * 4 + 1], 1u);
         atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
+        atomicAdd(&L.tpts[ti], npts);
       }
       __syncthreads();
 
@@ -921,34 +930,13 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         }
       }
 
-      // ---- 8. residual: per manifold partials, then per tower in solve order ----
-      for (int m = lane; m < nkept; m += kWave) {
-        float sum, mx;
-        const float mu = L.mu[L.tw[L.mab[m] >> 16]];
-        residual_manifold(L, m, mu, sum, mx);
-        L.cn[m] = sum;
-        L.cn[PC + m] = mx;
-      }
-      __syncthreads();
-      for (int t = lane; t < nt; t += kWave) {
-        float sum = 0.f, mx = 0.f;
-        int rows = 0;
-        for (int m = 0; m < nkept; ++m) {
-          if (L.tw[L.mab[m] >> 16] != t) continue;
-          sum += L.cn[m];
-          mx = fmaxf(mx, L.cn[PC + m]);
-          rows += 3 * (int)(L.mmeta[m] & 15u);
-        }
-        L.tres[2 * t] = rows ? sqrtf(sum / (float)rows) : 0.f;
-        L.tres[2 * t + 1] = mx;
-      }
-      // contacts of the final step, and the warm-start store
+      // ---- contacts of the final step; warm-start store ----
       if (last) {
         for (int m = lane; m < nkept; m += kWave) {
-          const int a_ = (int)(L.mab[m] >> 16);
-          const int g = pk * PC + m;
           int col = 0;
           while (col + 1 < ncol && L.coloff[col + 1] <= m) ++col;
+          const int a_ = (int)(L.mab[m] >> 16);
+          const int g = slot0 + m;
           a.out_ab[g] = L.mab[m];
           a.out_meta[g] = (L.mmeta[m] & 0x0ffff00fu) | ((uint32_t)col << 4);
           a.out_tower[g] = L.tw[a_];
@@ -976,9 +964,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           const int p = L.mcanon[m];
           const uint32_t meta = L.mmeta[m];
           const int npts = (int)(meta & 15u);
-          uint32_t ps = (uint32_t)npts;
-          for (int q = 0; q < npts; ++q) ps |= ((meta >> (12 + 4 * q)) & 15u) << (4 + 4 * q);
-          L.pslot[p] = ps;
+          L.pslot[p] = (uint32_t)npts | (((meta >> 12) & 0xffffu) << 4);
 #pragma unroll
           for (int k = 0; k < 3; ++k) L.pnrm[k * PC + p] = L.mn[k * PC + m];
           for (int k = 0; k < 12; ++k) L.plam[k * PC + p] = L.ml[k * PC + m];
@@ -986,6 +972,26 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         if (lane == 0) L.scal[4] = nman;
       }
       __syncthreads();
+
+      // ---- 8. residual: partials per canonical pair, then each tower's contiguous range ----
+      for (int p = lane; p < nman; p += kWave) {
+        const int m = L.cpos[p];
+        float sum = 0.f, mx = 0.f;
+        if (m >= 0) residual_manifold(L, m, L.mu[L.tw[L.mab[m] >> 16]], sum, mx);
+        L.cab[p] = __float_as_uint(sum);
+        L.cpos[p] = __float_as_int(mx);
+      }
+      __syncthreads();
+      for (int t = lane; t < nt; t += kWave) {
+        float sum = 0.f, mx = 0.f;
+        for (int p = L.tc0[t]; p < L.tc1[t]; ++p) {
+          sum += __uint_as_float(L.cab[p]);
+          mx = fmaxf(mx, __int_as_float(L.cpos[p]));
+        }
+        const int rows = 3 * L.tpts[t];
+        L.tres[2 * t] = rows ? sqrtf(sum / (float)rows) : 0.f;
+        L.tres[2 * t + 1] = mx;
+      }
 
       // ---- 9. integrate ----
       for (int i = lane; i < nb; i += kWave) {
@@ -995,7 +1001,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         load3(L.x, NB, i, xv);
         load3(L.v, NB, i, vv);
         load3(L.w, NB, i, wv);
-        load_R(L, i, R);
+        body_R(L, i, R);
         load3(L.invI, NB, i, iIb);
 #pragma unroll
         for (int k = 0; k < 3; ++k) { xv[k] += dt * vv[k]; Ib[k] = 1.f / iIb[k]; }
@@ -1020,10 +1026,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         for (int k = 0; k < 3; ++k) bl[k] = (R[k] * Lw[0] + R[3 + k] * Lw[1] + R[6 + k] * Lw[2]) * iIb[k];
 #pragma unroll
         for (int r = 0; r < 3; ++r) wv[r] = R[3 * r] * bl[0] + R[3 * r + 1] * bl[1] + R[3 * r + 2] * bl[2];
-        bool finite = true;
+        bool finite = isfinite(qw);
 #pragma unroll
         for (int k = 0; k < 3; ++k) finite = finite && isfinite(xv[k]) && isfinite(vv[k]) && isfinite(wv[k]);
-        finite = finite && isfinite(qw);
         if (!finite) atomicOr((uint32_t*)&L.scal[3], kErrNan);
         store3(L.x, NB, i, xv);
         store3(L.w, NB, i, wv);
@@ -1095,7 +1100,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   if (a.warm_start) {
     const int npv = L.scal[4];
     for (int p = lane; p < npv; p += kWave) {
-      const int g = pk * PC + p;
+      const int g = slot0 + p;
       a.prev_key[g] = L.pkey[p];
       a.prev_data[16 * g + 3] = __uint_as_float(L.pslot[p]);
 #pragma unroll
@@ -1110,8 +1115,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
 
 }  // namespace
 
-void launch_step(const StepArgs& a, int threads, size_t lds_bytes, void* stream) {
-  (void)threads;
+void launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   static bool attr_set = false;
   if (!attr_set) {
     hipFuncSetAttribute((const void*)step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

@@ -75,15 +75,19 @@ struct jg_world {
   std::vector<int> int_of_body, body_of_int;
   std::vector<int> tower_order;      // internal tower slot -> tower id
   std::vector<int> tower_slot;       // tower id -> internal slot
-  std::vector<int> pack_body0, pack_tower0, pack_push0;
+  std::vector<int> pack_body0, pack_tower0, pack_push0, pack_slot0;
+  struct PackClass {
+    int first = 0, count = 0, per_cu = 0, nbp = 1, pc = 16, tpc = 1, ppc = 1;
+    size_t lds = 0;
+  };
+  std::vector<PackClass> classes;   // launch classes, in pack order
   std::vector<int> push_order;       // internal push row -> pushes index
   std::vector<int> pack_of_tower;    // tower id -> pack
-  int n_packs = 0, nbp = 0, pc = 0, cc = 0, tpc = 0, ppc = 0;
-  size_t lds_bytes = 0;
+  int n_packs = 0;
   // device buffers
   DevBuf<float> d_x, d_q, d_v, d_w, d_he, d_mass;
   DevBuf<uint32_t> d_flags;
-  DevBuf<int32_t> d_body_tower, d_pack_body0, d_pack_tower0, d_pack_push0, d_tower_body0;
+  DevBuf<int32_t> d_body_tower, d_pack_body0, d_pack_tower0, d_pack_push0, d_pack_slot0, d_tower_body0;
   DevBuf<float> d_tower_mu;
   DevBuf<int32_t> d_push_body, d_push_start, d_push_steps;
   DevBuf<float> d_push_force, d_push_withdraw, d_push_x0;
@@ -151,7 +155,10 @@ int32_t download_state(jg_world* w) {
   return JG_OK;
 }
 
-// pack towers (first fit, largest first) and size the on-chip capacities
+// Pack towers into workgroups (first fit, largest first).  A pack holds whole towers and at
+// most `target` bodies, where `target` is the largest pack whose LDS fits four workgroups on a
+// CU; a tower larger than that gets a pack of its own.  Packs are then grouped into launch
+// classes of equal workgroups-per-CU, each launched with the LDS its largest pack needs.
 int32_t build_layout(jg_world* w) {
   const int T = (int)w->tower_bodies.size();
   std::vector<int> order;
@@ -161,19 +168,28 @@ int32_t build_layout(jg_world* w) {
     max_tower = std::max(max_tower, (int)w->tower_bodies[t].size());
   }
   if (max_tower > 4000) return fail(JG_ECAPACITY, "a tower has more bodies than one pack can index");
-  int target = w->prm.pack_bodies > 0 ? w->prm.pack_bodies : std::max(64, max_tower);
-  if (target < max_tower) target = max_tower;
+  const float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 3.5f;
+  const int warm = w->prm.warm_start == 1;
+  auto pc_of = [&](int nb) { return std::max(16, (int)std::ceil(mpb * nb)); };
+  auto lds_of = [&](int nb, int towers, int pushes) -> size_t {
+    return (size_t)jg::lds_words(nb, pc_of(nb), std::max(1, towers), std::max(1, pushes), warm) * 4;
+  };
+  int target = w->prm.pack_bodies;
+  if (target <= 0) {
+    target = 8;
+    while (lds_of(target + 1, 4, 8) <= 40 * 1024) ++target;
+  }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return w->tower_bodies[a].size() > w->tower_bodies[b].size();
   });
-  struct Bin { int bodies = 0; std::vector<int> towers; };
+  struct Bin { int bodies = 0, cap = 0; std::vector<int> towers; };
   std::vector<Bin> bins;
   for (int t : order) {
     const int n = (int)w->tower_bodies[t].size();
     bool placed = false;
     for (auto& b : bins)
-      if (b.bodies + n <= target && (int)b.towers.size() < 255) { b.towers.push_back(t); b.bodies += n; placed = true; break; }
-    if (!placed) { Bin b; b.bodies = n; b.towers.push_back(t); bins.push_back(b); }
+      if (b.bodies + n <= b.cap && (int)b.towers.size() < 255) { b.towers.push_back(t); b.bodies += n; placed = true; break; }
+    if (!placed) { Bin b; b.bodies = n; b.cap = std::max(target, n); b.towers.push_back(t); bins.push_back(b); }
   }
   std::stable_sort(bins.begin(), bins.end(), [](const Bin& a, const Bin& b) { return a.bodies > b.bodies; });
   // internal order
@@ -186,10 +202,11 @@ int32_t build_layout(jg_world* w) {
   w->pack_body0.assign(1, 0);
   w->pack_tower0.assign(1, 0);
   w->pack_push0.assign(1, 0);
+  w->pack_slot0.assign(1, 0);
   w->push_order.clear();
+  w->classes.clear();
   std::vector<std::vector<int>> push_of_body(N);
   for (size_t r = 0; r < w->pushes.size(); ++r) push_of_body[w->pushes[r].body].push_back((int)r);
-  int nbp = 1, tpc = 1, ppc = 1;
   for (size_t b = 0; b < bins.size(); ++b) {
     int pushes = 0;
     for (int t : bins[b].towers) {
@@ -207,23 +224,33 @@ int32_t build_layout(jg_world* w) {
     w->pack_body0.push_back((int)w->body_of_int.size());
     w->pack_tower0.push_back((int)w->tower_order.size());
     w->pack_push0.push_back((int)w->push_order.size());
-    nbp = std::max(nbp, bins[b].bodies);
-    tpc = std::max(tpc, (int)bins[b].towers.size());
-    ppc = std::max(ppc, pushes);
+    // launch class: packs that fit the same number of workgroups per CU
+    const size_t lds = lds_of(bins[b].bodies, (int)bins[b].towers.size(), pushes);
+    const int per_cu = (int)((160 * 1024) / lds);
+    if (per_cu == 0)
+      return fail(JG_ECAPACITY, "a pack needs " + std::to_string(lds) + " bytes of LDS (max 163840); "
+                                "use smaller towers or fewer manifolds per body");
+    if (w->classes.empty() || w->classes.back().per_cu != per_cu) {
+      jg_world::PackClass c;
+      c.first = (int)b;
+      c.per_cu = per_cu;
+      w->classes.push_back(c);
+    }
+    jg_world::PackClass& c = w->classes.back();
+    c.count += 1;
+    c.nbp = std::max(c.nbp, bins[b].bodies);
+    c.tpc = std::max(c.tpc, (int)bins[b].towers.size());
+    c.ppc = std::max(c.ppc, std::max(1, pushes));
+  }
+  // class capacities; every pack of a class gets the class's contact slots
+  for (auto& c : w->classes) {
+    c.pc = pc_of(c.nbp);
+    c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, warm) * 4;
+    if (c.lds > 160 * 1024)
+      return fail(JG_ECAPACITY, "a launch class needs " + std::to_string(c.lds) + " bytes of LDS (max 163840)");
+    for (int k = 0; k < c.count; ++k) w->pack_slot0.push_back(w->pack_slot0.back() + c.pc);
   }
   w->n_packs = (int)bins.size();
-  const float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 4.0f;
-  w->nbp = nbp;
-  w->pc = std::max(64, (int)std::ceil(mpb * nbp));
-  // broadphase candidates reach ~9 per body while a tilted tower falls apart
-  w->cc = std::max(256, 16 * nbp);
-  w->tpc = tpc;
-  w->ppc = ppc;
-  const int64_t words = jg::lds_words(w->nbp, w->pc, w->cc, w->tpc, w->ppc, w->prm.warm_start == 1);
-  w->lds_bytes = (size_t)words * 4;
-  if (w->lds_bytes > 160 * 1024)
-    return fail(JG_ECAPACITY, "pack needs " + std::to_string(w->lds_bytes) + " bytes of LDS (max 163840); "
-                              "use smaller towers or fewer manifolds per body");
   // device buffers sized by the layout
   const size_t np = (size_t)std::max(1, w->n_packs);
   const size_t nt = (size_t)std::max(1, T);
@@ -231,6 +258,7 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(w->d_pack_body0.ensure(np + 1));
   HIP_TRY(w->d_pack_tower0.ensure(np + 1));
   HIP_TRY(w->d_pack_push0.ensure(np + 1));
+  HIP_TRY(w->d_pack_slot0.ensure(np + 1));
   HIP_TRY(w->d_tower_body0.ensure(nt + 1));
   HIP_TRY(w->d_tower_mu.ensure(nt));
   HIP_TRY(w->d_tower_count.ensure(4 * nt));
@@ -242,7 +270,7 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(w->d_push_force.ensure(3 * npush));
   HIP_TRY(w->d_push_withdraw.ensure(npush));
   HIP_TRY(w->d_push_x0.ensure(3 * npush));
-  const size_t slots = np * (size_t)w->pc;
+  const size_t slots = std::max<size_t>(1, (size_t)w->pack_slot0.back());
   HIP_TRY(w->d_out_ab.ensure(slots));
   HIP_TRY(w->d_out_meta.ensure(slots));
   HIP_TRY(w->d_out_geo.ensure(8 * slots));
@@ -263,6 +291,7 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(hipMemcpy(w->d_pack_body0.p, w->pack_body0.data(), sizeof(int32_t) * w->pack_body0.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w->d_pack_tower0.p, w->pack_tower0.data(), sizeof(int32_t) * w->pack_tower0.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w->d_pack_push0.p, w->pack_push0.data(), sizeof(int32_t) * w->pack_push0.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w->d_pack_slot0.p, w->pack_slot0.data(), sizeof(int32_t) * w->pack_slot0.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w->d_tower_body0.p, tb0.data(), sizeof(int32_t) * (w->tower_order.size() + 1), hipMemcpyHostToDevice));
   std::vector<int32_t> btw(w->max_bodies, 0);
   for (int s = 0; s < (int)w->tower_order.size(); ++s)
@@ -418,7 +447,8 @@ int32_t jg_destroy_world(jg_world* w) {
   hipStreamSynchronize(w->stream);
   w->d_x.release(); w->d_q.release(); w->d_v.release(); w->d_w.release(); w->d_he.release();
   w->d_mass.release(); w->d_flags.release(); w->d_body_tower.release();
-  w->d_pack_body0.release(); w->d_pack_tower0.release(); w->d_pack_push0.release(); w->d_tower_body0.release();
+  w->d_pack_body0.release(); w->d_pack_tower0.release(); w->d_pack_push0.release(); w->d_pack_slot0.release();
+  w->d_tower_body0.release();
   w->d_tower_mu.release(); w->d_push_body.release(); w->d_push_start.release(); w->d_push_steps.release();
   w->d_push_force.release(); w->d_push_withdraw.release(); w->d_push_x0.release();
   w->d_tower_count.release(); w->d_tower_res.release(); w->d_pack_error.release();
@@ -540,7 +570,8 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.he = w->d_he.p; a.mass = w->d_mass.p; a.flags = w->d_flags.p;
   a.body_tower = w->d_body_tower.p; a.cap = w->max_bodies;
   a.pack_body0 = w->d_pack_body0.p; a.pack_tower0 = w->d_pack_tower0.p; a.pack_push0 = w->d_pack_push0.p;
-  a.tower_body0 = w->d_tower_body0.p; a.tower_mu = w->d_tower_mu.p; a.n_packs = w->n_packs;
+  a.pack_slot0 = w->d_pack_slot0.p;
+  a.tower_body0 = w->d_tower_body0.p; a.tower_mu = w->d_tower_mu.p;
   a.push_body = w->d_push_body.p; a.push_start = w->d_push_start.p; a.push_steps = w->d_push_steps.p;
   a.push_force = w->d_push_force.p; a.push_withdraw = w->d_push_withdraw.p; a.push_x0 = w->d_push_x0.p;
   a.tower_count = w->d_tower_count.p; a.tower_res = w->d_tower_res.p; a.pack_error = w->d_pack_error.p;
@@ -558,9 +589,13 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.n_steps = n_steps;
   a.warm_start = w->prm.warm_start;
   a.step0 = w->step;
-  a.nbp = w->nbp; a.pc = w->pc; a.cc = w->cc; a.tpc = w->tpc; a.ppc = w->ppc;
-  jg::launch_step(a, jg::kWave, w->lds_bytes, w->stream);
-  HIP_TRY(hipGetLastError());
+  for (const auto& c : w->classes) {
+    a.pack_first = c.first;
+    a.n_packs = c.count;
+    a.nbp = c.nbp; a.pc = c.pc; a.tpc = c.tpc; a.ppc = c.ppc;
+    jg::launch_step(a, c.lds, w->stream);
+    HIP_TRY(hipGetLastError());
+  }
   w->step += n_steps;
   w->device_newer = true;
   w->stats_pending = true;
@@ -635,7 +670,7 @@ int32_t jg_query_contacts(jg_world* w, int32_t tower, jg_contact* out, int32_t c
   int32_t cnt = 0;
   HIP_TRY(hipMemcpy(&cnt, w->d_out_count.p + pk, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (cnt <= 0) return JG_OK;
-  const size_t base = (size_t)pk * w->pc;
+  const size_t base = (size_t)w->pack_slot0[pk];
   std::vector<uint32_t> ab(cnt), meta(cnt);
   std::vector<int32_t> tw(cnt);
   std::vector<float> geo(8 * (size_t)cnt), pts(24 * (size_t)cnt);
