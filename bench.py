@@ -127,6 +127,7 @@ def main():
     world.step(0)          # make the restored state resident before the timed region
     world.sync()
     s0 = world.stats()
+    J.jg_query_phase_cycles(world.h)   # reset the per-phase counters
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -139,7 +140,10 @@ def main():
     wall = time.perf_counter() - t0
     kernel_ms = ev0.elapsed_time(ev1)
     s1 = world.stats()
+    phases = J.jg_query_phase_cycles(world.h)
+    total_cyc = max(1, sum(phases.values()))
     log(f"timed {args.steps} steps: wall {wall * 1e3:.1f} ms, kernel (events) {kernel_ms:.1f} ms")
+    log("phase share of workgroup cycles: " + ", ".join(f"{k} {100.0 * v / total_cyc:.1f}%" for k, v in phases.items()))
 
     T = scene["n_towers"]
     cand = s1.candidates - s0.candidates
@@ -175,6 +179,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "hbm_algorithmic_gbs": bytes_launch / (kernel_ms * 1e-3) / 1e9},
+        "phase_cycle_share": {k: round(v / total_cyc, 4) for k, v in phases.items()},
         "error_word": int(s1.error_word),
         "residual_rms_max": s1.residual_rms,
     }

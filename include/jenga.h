@@ -51,7 +51,7 @@ typedef enum {
 } jg_status;
 
 /* Device error-word bits reported by jg_query_stats. */
-#define JG_ERR_CANDIDATES 1u   /* broadphase candidates exceeded the pack capacity */
+#define JG_ERR_CANDIDATES 1u   /* reserved (broadphase candidates are consumed as produced) */
 #define JG_ERR_MANIFOLDS 2u    /* colliding pairs exceeded the pack capacity */
 #define JG_ERR_COLOURS 4u      /* a manifold needed more than 64 colours (dropped) */
 #define JG_ERR_NAN 8u          /* non-finite body state */
@@ -69,7 +69,7 @@ typedef struct {
   int32_t device;        /* HIP device ordinal */
   void* stream;          /* hipStream_t for all GPU work; NULL = default stream */
   int32_t pack_bodies;   /* bodies per on-chip pack; 0 = automatic */
-  float manifolds_per_body;  /* manifold capacity per body in a pack; 0 = automatic (4.0) */
+  float manifolds_per_body;  /* manifold capacity per body in a pack; 0 = automatic (3.5) */
 } jg_params;
 
 /* One contact point of the last solved step. */
@@ -156,6 +156,13 @@ int32_t jg_query_contacts(jg_world* w, int32_t tower, jg_contact* out, int32_t c
 /* Counters of one tower, or the sum over towers when tower = -1 (then colours is the
  * max, the residuals are the max over towers, error_word the OR).  Waits. */
 int32_t jg_query_stats(jg_world* w, int32_t tower, jg_stats* out);
+
+/* Diagnostics: GPU cycles spent per phase of the step kernel since the last call, summed
+ * over all workgroups, in this order: 0 load/store and push bookkeeping, 1 forces and frames,
+ * 2 broadphase + narrowphase, 3 colouring, 4 manifolds, 5 PGS (with warm start), 6 contact
+ * output and warm-start store, 7 residual, 8 integration, 9 position correction.  Writes
+ * min(n, 10) counters (further entries 0) and resets them.  Waits. */
+int32_t jg_query_phase_cycles(jg_world* w, uint64_t* cycles, int32_t n);
 
 /* Number of towers and bodies added so far. */
 int32_t jg_world_size(jg_world* w, int32_t* n_towers, int32_t* n_bodies);

@@ -21,6 +21,9 @@ constexpr uint32_t kDynamic = 2u;   // mass > 0 (written by the solver)
 constexpr int kMaxColours = 64;
 constexpr int kWave = 64;
 constexpr int kRing = 128;          // broadphase -> narrowphase candidate ring
+// phases timed by the step kernel: load/store, forces+frames, broad+narrow, colouring,
+// manifolds, PGS (with warm start), outputs, residual, integration, position correction
+constexpr int kPhases = 10;
 
 struct StepArgs {
   // bodies
@@ -64,6 +67,8 @@ struct StepArgs {
   uint32_t* prev_key;          // [slot]
   float* prev_data;            // [slot][16]: n[3], slots(as bits), lambda[4][3]
   int32_t* prev_count;         // [pack]
+  // cycles spent per phase, summed over packs (kPhases counters)
+  unsigned long long* phase_cycles;
   // parameters
   float g[3];
   float dt;                    // substep length
@@ -89,7 +94,7 @@ inline int64_t lds_words(int nbp, int pc, int tpc, int ppc, int warm) {
   w += (int64_t)nbp * kBodyWords;
   w += (int64_t)tpc * kTowerWords;
   w += (int64_t)ppc * kPushWords;
-  w += 2 * (kMaxColours + 1) + 16 + kRing;
+  w += 2 * (kMaxColours + 1) + 16 + kRing + 2 * kPhases;
   w += (int64_t)pc * kManWords;
   if (warm) w += (int64_t)pc * kWarmWords;
   return w;

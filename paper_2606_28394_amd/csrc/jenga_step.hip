@@ -54,6 +54,7 @@ struct Lds {
   // colours and scalars
   int32_t *coloff, *colcnt, *scal;
   uint32_t* ring;
+  unsigned long long* cyc;   // per-phase cycle counters of this pack
   // canonical colliding pairs (code, colour-sorted position); residual partials afterwards
   uint32_t* cab;
   int32_t* cpos;
@@ -75,6 +76,7 @@ __device__ inline Lds carve(float* base, const StepArgs& a) {
   float* p = base;
   auto take = [&](int n) { float* r = p; p += n; return r; };
   const int nb = a.nbp, pc = a.pc, nt = a.tpc, np = a.ppc;
+  L.cyc = (unsigned long long*)take(2 * kPhases);   // first: 8-byte aligned
   L.x = take(3 * nb); L.q = take(4 * nb); L.v = take(3 * nb); L.w = take(3 * nb);
   L.he = take(3 * nb); L.invm = take(nb); L.invI = take(3 * nb);
   L.flag = (uint32_t*)take(nb); L.tw = (int32_t*)take(nb);
@@ -389,12 +391,12 @@ __device__ inline float solve_row(BodyRegs& A, BodyRegs& B, const float rA[3], c
                      dot3(cB, B.w) - dot3(cA, A.w);
   sym_mul(A.I, cA, iA);
   sym_mul(B.I, cB, iB);
-  const float k = A.im + B.im + dot3(cA, iA) + dot3(cB, iB);
+  const float ik = __builtin_amdgcn_rcpf(A.im + B.im + dot3(cA, iA) + dot3(cB, iB));
   float nl;
   if (kNormal) {
-    nl = fmaxf(lam - (1.f + e) * vrel / k, 0.f);
+    nl = fmaxf(lam - (1.f + e) * vrel * ik, 0.f);
   } else {
-    nl = fminf(fmaxf(lam - vrel / k, -bound), bound);
+    nl = fminf(fmaxf(lam - vrel * ik, -bound), bound);
   }
   const float dl = nl - lam;
 #pragma unroll
@@ -540,7 +542,7 @@ __device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, flo
         res = fminf(k * lam[0], vrel);
       } else {
         const float bound = mu * lam[0];
-        const float cl = fminf(fmaxf(lam[r] - vrel / k, -bound), bound);
+        const float cl = fminf(fmaxf(lam[r] - vrel * __builtin_amdgcn_rcpf(k), -bound), bound);
         res = k * (lam[r] - cl);
       }
       sum += res * res;
@@ -548,6 +550,16 @@ __device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, flo
     }
   }
 }
+
+// wave-uniform phase timer: adds the cycles since the previous mark to counter k
+struct PhaseTimer {
+  unsigned long long last;
+  __device__ inline void mark(const Lds& L, int lane, int k) {
+    const unsigned long long t = (unsigned long long)clock64();
+    if (lane == 0) L.cyc[k] += t - last;
+    last = t;
+  }
+};
 
 __device__ inline uint64_t lane_lt_mask(int lane) { return lane ? ((~0ull) >> (64 - lane)) : 0ull; }
 
@@ -594,6 +606,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   const int gp0 = a.pack_push0[pk], np = a.pack_push0[pk + 1] - gp0;
   const int slot0 = a.pack_slot0[pk];
   const int NB = L.nbp, PC = L.pc, CAP = a.cap;
+  PhaseTimer timer;
+  timer.last = (unsigned long long)clock64();
+  if (lane < kPhases) L.cyc[lane] = 0ull;
 
   // ---- load the pack ----
   for (int i = lane; i < nb; i += kWave) {
@@ -653,6 +668,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
     }
   }
   __syncthreads();
+  timer.mark(L, lane, 0);
 
   const float dt = a.dt, e = a.restitution;
   for (int s = 0; s < a.n_steps; ++s) {
@@ -708,6 +724,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         L.tpts[t] = 0;
       }
       __syncthreads();
+      timer.mark(L, lane, 1);
 
       // ---- 3 + 4. broadphase in canonical order, narrowphase on every 64 candidates ----
       int head = 0, tail = 0, nman = 0;
@@ -759,6 +776,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         nman = PC;
       }
       __syncthreads();
+      timer.mark(L, lane, 2);
 
       // ---- 5. tower ranges of the canonical list; greedy first-fit colouring ----
       for (int p = lane; p < nman; p += kWave) {
@@ -769,43 +787,90 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       for (int i = lane; i < nb; i += kWave) { L.hm[i] = 0.f; L.hm[NB + i] = 0.f; }
       __syncthreads();
       uint32_t* mask = (uint32_t*)L.hm;   // [word * nbp + body]
-      if (lane == 0) {
-        for (int p = 0; p < nman; ++p) {
-          const uint32_t code = L.cab[p];
-          const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
-          const bool di = (L.flag[i] & kDynamic) != 0;
-          const bool dj = j != (int)kGround && (L.flag[j] & kDynamic);
-          uint64_t u = 0;
-          if (di) u |= (uint64_t)mask[i] | ((uint64_t)mask[NB + i] << 32);
-          if (dj) u |= (uint64_t)mask[j] | ((uint64_t)mask[NB + j] << 32);
-          if (u == ~0ull) {
-            L.scal[3] |= kErrCol;
-            L.cpos[p] = -1;
-            continue;
+      // Greedy first fit in canonical order, 64 manifolds at a time: a lane is coloured once
+      // every earlier manifold of its chunk that shares a dynamic body is coloured.  Lanes
+      // coloured in one round share no body, and each sees exactly the colours of all its
+      // earlier neighbours, so the result equals the sequential greedy colouring.
+      for (int c0 = 0; c0 < nman; c0 += kWave) {
+        const int p = c0 + lane;
+        const bool valid = p < nman;
+        const uint32_t code = valid ? L.cab[p] : 0u;
+        const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
+        const bool di = valid && (L.flag[i] & kDynamic);
+        const bool dj = valid && j != (int)kGround && (L.flag[j] & kDynamic);
+        const int ki = di ? i : 0x10000 + lane;       // lane-unique keys never match a body
+        const int kj = dj ? j : 0x20000 + lane;
+        uint64_t dep = 0ull;
+        for (int k = 0; k < kWave; ++k) {
+          const int ak = __builtin_amdgcn_readlane(ki, k), bk = __builtin_amdgcn_readlane(kj, k);
+          const bool hit = (k < lane) && (ak == ki || ak == kj || bk == ki || bk == kj);
+          dep |= (uint64_t)hit << k;
+        }
+        bool done = !valid;
+        int col = -1;
+        while (true) {
+          const uint64_t donem = __ballot(done);
+          if (donem == ~0ull) break;
+          if (!done && (dep & ~donem) == 0ull) {
+            uint64_t u = 0ull;
+            if (di) u |= (uint64_t)mask[i] | ((uint64_t)mask[NB + i] << 32);
+            if (dj) u |= (uint64_t)mask[j] | ((uint64_t)mask[NB + j] << 32);
+            if (u != ~0ull) {
+              col = __ffsll((unsigned long long)~u) - 1;
+              const uint64_t bit = 1ull << col;
+              if (di) { mask[i] |= (uint32_t)bit; mask[NB + i] |= (uint32_t)(bit >> 32); }
+              if (dj) { mask[j] |= (uint32_t)bit; mask[NB + j] |= (uint32_t)(bit >> 32); }
+            }
+            done = true;
           }
-          const int col = __ffsll((unsigned long long)~u) - 1;
-          const uint64_t bit = 1ull << col;
-          if (di) { mask[i] |= (uint32_t)bit; mask[NB + i] |= (uint32_t)(bit >> 32); }
-          if (dj) { mask[j] |= (uint32_t)bit; mask[NB + j] |= (uint32_t)(bit >> 32); }
-          L.colcnt[col] += 1;
+          __syncthreads();
+        }
+        if (valid) {
           L.cpos[p] = col;
-          const int ti = L.tw[i];
-          if ((uint32_t)(col + 1) > L.tcnt[ti * 4 + 3]) L.tcnt[ti * 4 + 3] = (uint32_t)(col + 1);
+          if (col >= 0) atomicAdd(&L.colcnt[col], 1);
+          else atomicOr((uint32_t*)&L.scal[3], kErrCol);
         }
-        int ncol = 0;
-        L.coloff[0] = 0;
-        for (int c = 0; c < kMaxColours; ++c) {
-          L.coloff[c + 1] = L.coloff[c] + L.colcnt[c];
-          if (L.colcnt[c]) ncol = c + 1;
-          L.colcnt[c] = L.coloff[c];
-        }
-        for (int p = 0; p < nman; ++p) {
-          const int col = L.cpos[p];
-          if (col >= 0) L.cpos[p] = L.colcnt[col]++;
-        }
-        L.scal[2] = ncol;
       }
       __syncthreads();
+      // colour offsets (wave prefix sum over the 64 colour counts)
+      {
+        const int cnt = L.colcnt[lane];
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+          const int t = __shfl_up(incl, d);
+          if (lane >= d) incl += t;
+        }
+        L.coloff[lane + 1] = incl;
+        L.colcnt[lane] = incl - cnt;       // running position of each colour
+        if (lane == 0) L.coloff[0] = 0;
+        const uint64_t used = __ballot(cnt > 0);
+        if (lane == 0) L.scal[2] = used ? 64 - __clzll((long long)used) : 0;
+      }
+      __syncthreads();
+      // colour-sorted positions, canonical order inside each colour
+      for (int c0 = 0; c0 < nman; c0 += kWave) {
+        const int p = c0 + lane;
+        const int col = p < nman ? L.cpos[p] : -1;
+        int pos = -1;
+        uint64_t pending = __ballot(col >= 0);
+        while (pending) {
+          const int c = __builtin_amdgcn_readlane(col, __ffsll((unsigned long long)pending) - 1);
+          const uint64_t m = __ballot(col == c);
+          const int base = L.colcnt[c];
+          if (col == c) pos = base + __popcll(m & lane_lt_mask(lane));
+          __syncthreads();
+          if (lane == 0) L.colcnt[c] = base + __popcll(m);
+          __syncthreads();
+          pending &= ~m;
+        }
+        if (p < nman) {
+          L.cpos[p] = pos;
+          if (col >= 0) atomicMax(&L.tcnt[L.tw[L.cab[p] >> 16] * 4 + 3], (uint32_t)(col + 1));
+        }
+      }
+      __syncthreads();
+      timer.mark(L, lane, 3);
       const int ncol = L.scal[2];
       const int nkept = L.coloff[ncol];
 
@@ -912,6 +977,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         atomicAdd(&L.tpts[ti], npts);
       }
       __syncthreads();
+      timer.mark(L, lane, 4);
 
       // ---- 7. warm-start impulses, then PGS sweeps, colour by colour ----
       if (a.warm_start) {
@@ -929,6 +995,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           __syncthreads();
         }
       }
+      timer.mark(L, lane, 5);
 
       // ---- contacts of the final step; warm-start store ----
       if (last) {
@@ -972,6 +1039,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         if (lane == 0) L.scal[4] = nman;
       }
       __syncthreads();
+      timer.mark(L, lane, 6);
 
       // ---- 8. residual: partials per canonical pair, then each tower's contiguous range ----
       for (int p = lane; p < nman; p += kWave) {
@@ -992,6 +1060,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         L.tres[2 * t] = rows ? sqrtf(sum / (float)rows) : 0.f;
         L.tres[2 * t + 1] = mx;
       }
+      timer.mark(L, lane, 7);
 
       // ---- 9. integrate ----
       for (int i = lane; i < nb; i += kWave) {
@@ -1035,6 +1104,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         L.q[i] = qw; L.q[NB + i] = qx; L.q[2 * NB + i] = qy; L.q[3 * NB + i] = qz;
       }
       __syncthreads();
+      timer.mark(L, lane, 8);
       // ---- 10. Baumgarte position correction, colour by colour ----
       for (int col = 0; col < ncol; ++col) {
         for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
@@ -1055,6 +1125,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         }
         __syncthreads();
       }
+      timer.mark(L, lane, 9);
     }
     // ---- withdrawal of pushed bodies ----
     for (int r = lane; r < np; r += kWave) {
@@ -1111,6 +1182,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
     if (lane == 0) a.prev_count[pk] = npv;
   }
   if (lane == 0) a.pack_error[pk] |= (uint32_t)L.scal[3];
+  timer.mark(L, lane, 0);
+  __syncthreads();
+  if (a.phase_cycles && lane < kPhases) atomicAdd(&a.phase_cycles[lane], L.cyc[lane]);
 }
 
 }  // namespace

@@ -100,6 +100,7 @@ struct jg_world {
   DevBuf<uint32_t> d_prev_key;
   DevBuf<float> d_prev_data;
   DevBuf<int32_t> d_prev_count;
+  DevBuf<unsigned long long> d_phase_cycles;
   // statistics (per tower id)
   std::vector<int64_t> st_cand, st_man, st_pts, st_ci;
   std::vector<int32_t> st_col;
@@ -433,6 +434,8 @@ int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodi
   if (e == hipSuccess) e = w->d_mass.ensure(cap);
   if (e == hipSuccess) e = w->d_flags.ensure(cap);
   if (e == hipSuccess) e = w->d_body_tower.ensure(cap);
+  if (e == hipSuccess) e = w->d_phase_cycles.ensure(jg::kPhases);
+  if (e == hipSuccess) e = hipMemset(w->d_phase_cycles.p, 0, sizeof(unsigned long long) * jg::kPhases);
   if (e != hipSuccess) {
     jg_destroy_world(w);
     return fail(JG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
@@ -455,6 +458,7 @@ int32_t jg_destroy_world(jg_world* w) {
   w->d_out_ab.release(); w->d_out_meta.release(); w->d_out_geo.release(); w->d_out_pts.release();
   w->d_out_count.release(); w->d_out_tower.release();
   w->d_prev_key.release(); w->d_prev_data.release(); w->d_prev_count.release();
+  w->d_phase_cycles.release();
   delete w;
   return JG_OK;
 }
@@ -578,6 +582,7 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.out_ab = w->d_out_ab.p; a.out_meta = w->d_out_meta.p; a.out_geo = w->d_out_geo.p; a.out_pts = w->d_out_pts.p;
   a.out_count = w->d_out_count.p; a.out_tower = w->d_out_tower.p;
   a.prev_key = w->d_prev_key.p; a.prev_data = w->d_prev_data.p; a.prev_count = w->d_prev_count.p;
+  a.phase_cycles = w->d_phase_cycles.p;
   for (int k = 0; k < 3; ++k) a.g[k] = (float)w->prm.gravity[k];
   a.dt = (float)(w->prm.dt / w->prm.n_sub);
   a.restitution = (float)w->prm.restitution;
@@ -741,6 +746,18 @@ int32_t jg_world_size(jg_world* w, int32_t* n_towers, int32_t* n_bodies) {
   if (int32_t r = check_world(w)) return r;
   if (n_towers) *n_towers = (int32_t)w->tower_bodies.size();
   if (n_bodies) *n_bodies = (int32_t)w->mass.size();
+  return JG_OK;
+}
+
+int32_t jg_query_phase_cycles(jg_world* w, uint64_t* cycles, int32_t n) {
+  if (int32_t r = check_world(w)) return r;
+  if (!cycles || n < 0) return fail(JG_EINVAL, "bad output buffer");
+  if (int32_t r = set_device(w)) return r;
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  unsigned long long c[jg::kPhases];
+  HIP_TRY(hipMemcpy(c, w->d_phase_cycles.p, sizeof(c), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(w->d_phase_cycles.p, 0, sizeof(c)));
+  for (int k = 0; k < n; ++k) cycles[k] = k < jg::kPhases ? (uint64_t)c[k] : 0u;
   return JG_OK;
 }
 

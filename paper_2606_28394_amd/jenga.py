@@ -22,7 +22,10 @@ ERR_CANDIDATES, ERR_MANIFOLDS, ERR_COLOURS, ERR_NAN = 1, 2, 4, 8
 
 EXPORTS = ["jg_default_params", "jg_create_world", "jg_destroy_world", "jg_add_boxes", "jg_set_friction",
            "jg_set_push", "jg_set_active", "jg_step_batch", "jg_query_state", "jg_set_state", "jg_query_active",
-           "jg_query_contacts", "jg_query_stats", "jg_world_size", "jg_sync", "jg_last_error"]
+           "jg_query_contacts", "jg_query_stats", "jg_query_phase_cycles", "jg_world_size", "jg_sync",
+           "jg_last_error"]
+PHASES = ["load/store", "forces+frames", "broad+narrow", "colouring", "manifolds", "pgs", "outputs",
+          "residual", "integrate", "baumgarte"]
 
 
 class jg_params(C.Structure):
@@ -82,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.jg_query_active.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_uint8)]
     L.jg_query_contacts.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
     L.jg_query_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(jg_stats)]
+    L.jg_query_phase_cycles.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_int32]
     L.jg_world_size.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.jg_sync.argtypes = [C.c_void_p]
     L.jg_last_error.argtypes = []
@@ -199,6 +203,12 @@ def jg_query_stats(h, tower=-1) -> jg_stats:
     s = jg_stats()
     _check(load_library().jg_query_stats(h, int(tower), C.byref(s)))
     return s
+
+
+def jg_query_phase_cycles(h) -> dict:
+    out = (C.c_uint64 * len(PHASES))()
+    _check(load_library().jg_query_phase_cycles(h, out, len(PHASES)))
+    return dict(zip(PHASES, [int(v) for v in out]))
 
 
 def jg_world_size(h):
