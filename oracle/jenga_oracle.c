@@ -617,6 +617,102 @@ int or_broadphase(int nb, const double* he, const double* mass, const double* x,
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* learned warm start: features and the per-contact MLP                                        */
+/* ------------------------------------------------------------------------------------------ */
+
+double or_bf16(double x) {
+  /* to single precision, then to bfloat16 with round-to-nearest-even on the float's bits */
+  float f = (float)x;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (double)f;   /* inf / nan unchanged */
+  u += 0x7fffu + ((u >> 16) & 1u);
+  u &= 0xffff0000u;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+static double gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
+
+void or_mlp_forward(const double* mlp, const double f[OR_NFEAT], double y[3]) {
+  const double* W1 = mlp;
+  const double* b1 = W1 + OR_NFEAT * OR_HIDDEN;
+  const double* W2 = b1 + OR_HIDDEN;
+  const double* b2 = W2 + OR_HIDDEN * OR_HIDDEN;
+  const double* W3 = b2 + OR_HIDDEN;
+  const double* b3 = W3 + OR_HIDDEN * 3;
+  const double* mean = b3 + 3;
+  const double* sd = mean + OR_NFEAT;
+  double x0[OR_NFEAT], h1[OR_HIDDEN], h2[OR_HIDDEN];
+  for (int i = 0; i < OR_NFEAT; ++i) x0[i] = or_bf16((f[i] - mean[i]) / sd[i]);
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = b1[j];
+    for (int i = 0; i < OR_NFEAT; ++i) s += x0[i] * W1[i * OR_HIDDEN + j];
+    h1[j] = or_bf16(gelu(s));
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = b2[j];
+    for (int i = 0; i < OR_HIDDEN; ++i) s += h1[i] * W2[i * OR_HIDDEN + j];
+    h2[j] = or_bf16(gelu(s));
+  }
+  for (int j = 0; j < 3; ++j) {
+    double s = b3[j];
+    for (int i = 0; i < OR_HIDDEN; ++i) s += h2[i] * W3[i * 3 + j];
+    y[j] = s;
+  }
+}
+
+/* the 24 features of point i of manifold m, at the pre-solve velocities:
+ * contact-frame x_B - x_A (3), q_A^-1 q_B with w >= 0 (4), world normal (3), depth (1), mu (1),
+ * previous-step impulses of the same key (3, zero if new), contact-frame r_A and r_B (6),
+ * contact-frame relative velocity of the contact point (3).  The ground stands in as a body at
+ * (x_A, y_A, 0) with the identity orientation. */
+static void point_features(const or_manifold* m, int i, const double* x, const double* q, const double* v,
+                           const double* w, const uint8_t* dyn, double mu, const double prev_lam[3],
+                           double f[OR_NFEAT]) {
+  const double* F[3] = {m->normal, m->t1, m->t2};
+  const double* xa = x + 3 * m->a;
+  double xb[3] = {xa[0], xa[1], 0.0};
+  double qb[4] = {1.0, 0.0, 0.0, 0.0};
+  if (m->b >= 0) {
+    for (int k = 0; k < 3; ++k) xb[k] = x[3 * m->b + k];
+    for (int k = 0; k < 4; ++k) qb[k] = q[4 * m->b + k];
+  }
+  const double* qa = q + 4 * m->a;
+  double d[3] = {xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]};
+  int o = 0;
+  for (int k = 0; k < 3; ++k) f[o++] = dot3(F[k], d);
+  /* conj(qa) (x) qb */
+  double aw = qa[0], ax = -qa[1], ay = -qa[2], az = -qa[3];
+  double bw = qb[0], bx = qb[1], by = qb[2], bz = qb[3];
+  double r[4] = {aw * bw - ax * bx - ay * by - az * bz, aw * bx + ax * bw + ay * bz - az * by,
+                 aw * by - ax * bz + ay * bw + az * bx, aw * bz + ax * by - ay * bx + az * bw};
+  double sg = r[0] < 0.0 ? -1.0 : 1.0;
+  for (int k = 0; k < 4; ++k) f[o++] = sg * r[k];
+  for (int k = 0; k < 3; ++k) f[o++] = m->normal[k];
+  f[o++] = m->depth;
+  f[o++] = mu;
+  for (int k = 0; k < 3; ++k) f[o++] = prev_lam[k];
+  double rA[3], rB[3];
+  for (int k = 0; k < 3; ++k) {
+    rA[k] = m->point[i][k] - xa[k];
+    rB[k] = m->point[i][k] - xb[k];
+  }
+  for (int k = 0; k < 3; ++k) f[o++] = dot3(F[k], rA);
+  for (int k = 0; k < 3; ++k) f[o++] = dot3(F[k], rB);
+  const double z[3] = {0.0, 0.0, 0.0};
+  const double* vA = dyn[m->a] ? v + 3 * m->a : z;
+  const double* wA = dyn[m->a] ? w + 3 * m->a : z;
+  const double* vB = (m->b >= 0 && dyn[m->b]) ? v + 3 * m->b : z;
+  const double* wB = (m->b >= 0 && dyn[m->b]) ? w + 3 * m->b : z;
+  double ua[3], ub[3], rel[3];
+  cross3(wA, rA, ua);
+  cross3(wB, rB, ub);
+  for (int k = 0; k < 3; ++k) rel[k] = (vB[k] + ub[k]) - (vA[k] + ua[k]);
+  for (int k = 0; k < 3; ++k) f[o++] = dot3(F[k], rel);
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* one tower step                                                                              */
 /* ------------------------------------------------------------------------------------------ */
 
@@ -640,7 +736,8 @@ static int find_prev(const or_manifold* prev, int nprev, const or_manifold* m, i
 static int substep(const or_params* P, double dt, int nb, const double* he, const double* mass,
                    double* x, double* q, double* v, double* w, uint8_t* active, double mu,
                    int npush, const or_push* push, int64_t step,
-                   const or_manifold* prev, int nprev, or_manifold** ms_out, int* nm_out, or_stats* st) {
+                   const or_manifold* prev, int nprev, or_manifold** ms_out, int* nm_out, or_stats* st,
+                   double* feat_out, int feat_cap, int* nfeat_out) {
   const size_t NB = (size_t)(nb > 0 ? nb : 1);
   double* R = (double*)malloc(sizeof(double) * 9 * NB);
   double* Iinv = (double*)malloc(sizeof(double) * 9 * NB);
@@ -742,18 +839,56 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
   body_view bv = {invm, Iinv, x, v, w, dyn};
   prep_k(&bv, ord, nm);
   long npts = 0;
-  for (int c = 0; c < nm; ++c) {
-    or_manifold* m = &ord[c];
-    npts += m->npts;
-    for (int i = 0; i < m->npts; ++i) {
-      m->lam[i][0] = m->lam[i][1] = m->lam[i][2] = 0.0;
-      if (P->warm_start == 1 && prev) {
-        double l[3];
-        if (find_prev(prev, nprev, m, m->slot[i], l)) { m->lam[i][0] = l[0]; m->lam[i][1] = l[1]; m->lam[i][2] = l[2]; }
+  for (int c = 0; c < nm; ++c) npts += ord[c].npts;
+  const int learned = P->warm_start == 2 && P->mlp != NULL;
+  double* feats = NULL;
+  if (learned || feat_out) {
+    feats = (double*)malloc(sizeof(double) * OR_NFEAT * (size_t)(npts > 0 ? npts : 1));
+    long o = 0;
+    for (int c = 0; c < nm; ++c) {
+      const or_manifold* m = &ord[c];
+      for (int i = 0; i < m->npts; ++i, ++o) {
+        double l[3] = {0.0, 0.0, 0.0};
+        if (prev) find_prev(prev, nprev, m, m->slot[i], l);
+        point_features(m, i, x, q, v, w, dyn, mu, l, feats + OR_NFEAT * o);
       }
     }
   }
-  if (P->warm_start == 1) {
+  const double gdt = norm3(P->gravity) * dt;
+  {
+    long o = 0;
+    for (int c = 0; c < nm; ++c) {
+      or_manifold* m = &ord[c];
+      for (int i = 0; i < m->npts; ++i, ++o) {
+        m->lam[i][0] = m->lam[i][1] = m->lam[i][2] = 0.0;
+        if (P->warm_start == 1 && prev) {
+          double l[3];
+          if (find_prev(prev, nprev, m, m->slot[i], l)) { m->lam[i][0] = l[0]; m->lam[i][1] = l[1]; m->lam[i][2] = l[2]; }
+        } else if (learned) {
+          /* the network predicts impulses in units of |g| dt / k (dimensionless) */
+          double y[3];
+          or_mlp_forward(P->mlp, feats + OR_NFEAT * o, y);
+          double ln = (y[0] > 0.0 ? y[0] : 0.0) * gdt / m->k[i][0];
+          double b = mu * ln;
+          double l1 = y[1] * gdt / m->k[i][1], l2 = y[2] * gdt / m->k[i][2];
+          if (l1 < -b) l1 = -b;
+          if (l1 > b) l1 = b;
+          if (l2 < -b) l2 = -b;
+          if (l2 > b) l2 = b;
+          m->lam[i][0] = ln; m->lam[i][1] = l1; m->lam[i][2] = l2;
+        }
+      }
+    }
+  }
+  double* v_save = NULL;
+  double* w_save = NULL;
+  if (learned) {
+    v_save = (double*)malloc(sizeof(double) * 3 * NB);
+    w_save = (double*)malloc(sizeof(double) * 3 * NB);
+    memcpy(v_save, v, sizeof(double) * 3 * (size_t)nb);
+    memcpy(w_save, w, sizeof(double) * 3 * (size_t)nb);
+  }
+  if (P->warm_start == 1 || learned) {
     /* apply the initial impulses like solver impulses, in processing order */
     for (int c = 0; c < nm; ++c) {
       or_manifold* m = &ord[c];
@@ -769,15 +904,42 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
     }
   }
   st->points += npts;
-  st->contact_iters += npts * (int64_t)P->iters;
 
-  /* 8. PGS */
-  for (int it = 0; it < P->iters; ++it) pgs_sweep(&bv, ord, nm, mu, P->restitution);
-  /* 9. residual */
+  /* 8. PGS; 9. residual.  A learned start runs mlp_iters sweeps; if the residual is still above
+   * fallback_tau the solve is redone plainly (pre-solve velocities, zero impulses, iters sweeps). */
+  const int iters = learned ? P->mlp_iters : P->iters;
+  for (int it = 0; it < iters; ++it) pgs_sweep(&bv, ord, nm, mu, P->restitution);
+  st->contact_iters += npts * (int64_t)iters;
   double res[2];
   residual(&bv, ord, nm, mu, res);
+  if (learned && res[0] > P->fallback_tau) {
+    memcpy(v, v_save, sizeof(double) * 3 * (size_t)nb);
+    memcpy(w, w_save, sizeof(double) * 3 * (size_t)nb);
+    for (int c = 0; c < nm; ++c)
+      for (int i = 0; i < ord[c].npts; ++i) ord[c].lam[i][0] = ord[c].lam[i][1] = ord[c].lam[i][2] = 0.0;
+    for (int it = 0; it < P->iters; ++it) pgs_sweep(&bv, ord, nm, mu, P->restitution);
+    st->contact_iters += npts * (int64_t)P->iters;
+    st->fallbacks += 1;
+    residual(&bv, ord, nm, mu, res);
+  }
+  free(v_save);
+  free(w_save);
   st->res_rms = res[0];
   st->res_max = res[1];
+  if (feat_out) {
+    long o = 0;
+    for (int c = 0; c < nm; ++c) {
+      const or_manifold* m = &ord[c];
+      for (int i = 0; i < m->npts; ++i, ++o) {
+        if (o >= feat_cap) continue;
+        double* r = feat_out + (size_t)OR_FEAT_RECORD * o;
+        memcpy(r, feats + OR_NFEAT * o, sizeof(double) * OR_NFEAT);
+        for (int k = 0; k < 3; ++k) { r[OR_NFEAT + k] = m->k[i][k]; r[OR_NFEAT + 3 + k] = m->lam[i][k]; }
+      }
+    }
+    *nfeat_out = (int)(npts < feat_cap ? npts : feat_cap);
+  }
+  free(feats);
 
   /* 10. integrate: x += dt v; q' = normalise(q + dt/2 [0,w] (x) q); keep L = I_w w */
   for (int i = 0; i < nb; ++i) {
@@ -838,8 +1000,12 @@ int or_step_tower(const or_params* p, int nb, const double* he, const double* ma
                   double* x, double* q, double* v, double* w, uint8_t* active,
                   double mu, int npush, or_push* push, int64_t* step_counter, int n_steps,
                   const or_manifold* prev, int nprev,
-                  or_manifold* mout, int mcap, int* nm_out, or_stats* st) {
+                  or_manifold* mout, int mcap, int* nm_out, or_stats* st,
+                  double* feat_out, int feat_cap, int* nfeat_out) {
   or_manifold* cur = NULL;
+  int nfeat_dummy = 0;
+  if (!nfeat_out) nfeat_out = &nfeat_dummy;
+  *nfeat_out = 0;
   int ncur = 0;
   or_manifold* last = NULL;
   int nlast = 0;
@@ -853,7 +1019,9 @@ int or_step_tower(const or_params* p, int nb, const double* he, const double* ma
     for (int sub = 0; sub < nsub; ++sub) {
       const or_manifold* pv = last ? last : prev;
       int npv = last ? nlast : nprev;
-      substep(p, dt, nb, he, mass, x, q, v, w, active, mu, npush, push, step, pv, npv, &cur, &ncur, st);
+      const int final_sub = (s == n_steps - 1) && (sub == nsub - 1);
+      substep(p, dt, nb, he, mass, x, q, v, w, active, mu, npush, push, step, pv, npv, &cur, &ncur, st,
+              final_sub ? feat_out : NULL, feat_cap, nfeat_out);
       free(last);
       last = cur; nlast = ncur;
       cur = NULL;

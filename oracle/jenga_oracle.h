@@ -27,9 +27,22 @@ typedef struct {
   double margin;         /* AABB margin epsilon, Eq. (aabb), 2 mm */
   int32_t n_sub;         /* substeps per step (each runs the whole pipeline with dt/n_sub) */
   int32_t iters;         /* PGS iterations */
-  int32_t warm_start;    /* 0: zero initial impulses, 1: previous step's impulses by key */
-  int32_t _pad;
+  int32_t warm_start;    /* 0: zero initial impulses, 1: previous step's impulses by key,
+                            2: learned (MLP) initial impulses, plain solve as the fallback */
+  int32_t mlp_iters;     /* PGS iterations after the learned warm start */
+  double fallback_tau;   /* tower residual [m/s] above which the plain solve is redone */
+  const double* mlp;     /* MLP parameters (layout OR_MLP_*), used when warm_start == 2 */
 } or_params;
+
+/* Learned warm start: per-contact MLP 24 -> 128 -> 128 -> 3 with GELU (erf form), parameters
+ * as doubles (already rounded to bfloat16 by the caller) in this order:
+ * W1[24][128], b1[128], W2[128][128], b2[128], W3[128][3], b3[3], mean[24], std[24].
+ * Each layer's input is rounded to bfloat16, as the GPU feeds its matrix cores. */
+#define OR_NFEAT 24
+#define OR_HIDDEN 128
+#define OR_MLP_SIZE (24 * 128 + 128 + 128 * 128 + 128 + 128 * 3 + 3 + 24 + 24)
+/* Per-point record written when feature output is requested: 24 features, k[3], lambda[3]. */
+#define OR_FEAT_RECORD 30
 
 typedef struct {
   int32_t body;          /* tower-local body index */
@@ -71,6 +84,7 @@ typedef struct {
   int64_t manifolds;       /* colliding pairs, summed over steps */
   int64_t points;          /* contact points, summed over steps */
   int64_t contact_iters;   /* points x iterations, summed over steps */
+  int64_t fallbacks;       /* learned solves redone by the plain solver */
   int32_t colours;         /* colours used in the last step */
   int32_t error;           /* 1: colour cap exceeded (manifold dropped); 2: manifold capacity */
   double res_rms;          /* natural-map residual of the last solve, RMS over rows [m/s] */
@@ -107,13 +121,21 @@ void or_pgs(int nb, const double* invm, const double* Iinv, const double* x, dou
 
 /* Step one tower n_steps times (state arrays updated in place).
  * prev/nprev: previous step's manifolds for the warm start (may be NULL/0).
+ * feat_out (may be NULL): OR_FEAT_RECORD doubles per contact point of the last substep, in
+ * processing order (features before the solve, k and the solved impulses after it).
  * mout/mcap/nm_out: manifolds of the last substep, in colour-sorted processing order.
  * step_counter: global step number of the first step (incremented by n_steps). */
 int or_step_tower(const or_params* p, int nb, const double* he, const double* mass,
                   double* x, double* q, double* v, double* w, uint8_t* active,
                   double mu, int npush, or_push* push, int64_t* step_counter, int n_steps,
                   const or_manifold* prev, int nprev,
-                  or_manifold* mout, int mcap, int* nm_out, or_stats* st);
+                  or_manifold* mout, int mcap, int* nm_out, or_stats* st,
+                  double* feat_out, int feat_cap, int* nfeat_out);
+
+/* bfloat16 rounding (round to nearest even) of a double, returned as a double. */
+double or_bf16(double x);
+/* MLP forward of one feature vector (normalisation, three layers); y[3] out. */
+void or_mlp_forward(const double* mlp, const double f[OR_NFEAT], double y[3]);
 
 /* Broadphase candidates of one tower (pairs a<b, b = -1 ground), canonical order. */
 int or_broadphase(int nb, const double* he, const double* mass, const double* x, const double* q,

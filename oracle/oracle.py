@@ -31,7 +31,12 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("dt", C.c_double), ("restitution", C.c_double),
                 ("beta", C.c_double), ("slop", C.c_double), ("margin", C.c_double),
-                ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("_pad", C.c_int32)]
+                ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("mlp_iters", C.c_int32),
+                ("fallback_tau", C.c_double), ("mlp", C.POINTER(C.c_double))]
+
+
+NFEAT, HIDDEN, FEAT_RECORD = 24, 128, 30
+MLP_SIZE = 24 * 128 + 128 + 128 * 128 + 128 + 128 * 3 + 3 + 24 + 24
 
 
 class Push(C.Structure):
@@ -49,7 +54,7 @@ class Manifold(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("candidates", C.c_int64), ("manifolds", C.c_int64),
-                ("points", C.c_int64), ("contact_iters", C.c_int64), ("colours", C.c_int32),
+                ("points", C.c_int64), ("contact_iters", C.c_int64), ("fallbacks", C.c_int64), ("colours", C.c_int32),
                 ("error", C.c_int32), ("res_rms", C.c_double), ("res_max", C.c_double)]
 
 
@@ -86,8 +91,12 @@ def lib():
             L.or_step_tower.argtypes = [C.POINTER(Params), C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _u8p, C.c_double,
                                         C.c_int, C.POINTER(Push), C.POINTER(C.c_int64), C.c_int,
                                         C.POINTER(Manifold), C.c_int, C.POINTER(Manifold), C.c_int,
-                                        C.POINTER(C.c_int), C.POINTER(Stats)]
+                                        C.POINTER(C.c_int), C.POINTER(Stats), C.c_void_p, C.c_int,
+                                        C.POINTER(C.c_int)]
             L.or_step_tower.restype = C.c_int
+            L.or_bf16.argtypes = [C.c_double]
+            L.or_bf16.restype = C.c_double
+            L.or_mlp_forward.argtypes = [_dp, _dp, _dp]
             L.or_broadphase.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _u8p, C.c_double, _i32p, C.c_int]
             L.or_broadphase.restype = C.c_int
             _lib = L
@@ -99,7 +108,10 @@ def _f64(a, shape=None):
     return a.reshape(shape) if shape is not None else a
 
 
-def make_params(p: dict, warm_start: int = 0) -> Params:
+def make_params(p: dict, warm_start: int = 0, mlp=None, mlp_iters: int = 0,
+                fallback_tau: float = float("inf")) -> Params:
+    """Solver parameters.  ``mlp`` (flat float64, MLP_SIZE, bf16-rounded) is kept alive by the
+    caller; warm_start 2 uses it with ``mlp_iters`` sweeps and the residual fallback."""
     P = Params()
     P.gravity[:] = [float(g) for g in p["gravity"]]
     P.dt = float(p["dt"])
@@ -110,7 +122,23 @@ def make_params(p: dict, warm_start: int = 0) -> Params:
     P.n_sub = int(p["n_sub"])
     P.iters = int(p["iters"])
     P.warm_start = int(warm_start)
+    P.mlp_iters = int(mlp_iters)
+    P.fallback_tau = float(fallback_tau)
+    if mlp is not None:
+        assert mlp.dtype == np.float64 and mlp.flags.c_contiguous and mlp.size == MLP_SIZE
+        P.mlp = mlp.ctypes.data_as(C.POINTER(C.c_double))
     return P
+
+
+def bf16(x: float) -> float:
+    return lib().or_bf16(float(x))
+
+
+def mlp_forward(mlp, f) -> np.ndarray:
+    """Network output (3,) for one feature vector (24,), FP64 with bf16-rounded layer inputs."""
+    y = np.zeros(3)
+    lib().or_mlp_forward(_f64(mlp), _f64(f, NFEAT), y)
+    return y
 
 
 # ---------------------------------------------------------------------------------------------
@@ -189,9 +217,12 @@ def manifold_dict(m: Manifold) -> dict:
 class OracleWorld:
     """All towers of a scene, stepped tower by tower in FP64."""
 
-    def __init__(self, scene: dict, warm_start: int = 0, params: dict | None = None):
+    def __init__(self, scene: dict, warm_start: int = 0, params: dict | None = None, mlp=None,
+                 mlp_iters: int = 0, fallback_tau: float = float("inf")):
         self.scene = scene
-        self.params = make_params(params or scene["params"], warm_start)
+        self.mlp = None if mlp is None else _f64(mlp).copy()
+        self.params = make_params(params or scene["params"], warm_start, self.mlp, mlp_iters, fallback_tau)
+        self.features = {}
         self.ptr = np.asarray(scene["tower_ptr"], np.int64)
         self.T = int(scene["n_towers"])
         self.he = _f64(scene["half_extents"]).reshape(-1, 3).copy()
@@ -234,7 +265,7 @@ class OracleWorld:
         self.contacts = [None] * self.T
         self.ncontacts = [0] * self.T
 
-    def step_tower(self, t: int, n_steps: int):
+    def step_tower(self, t: int, n_steps: int, record: bool = False):
         a, b = int(self.ptr[t]), int(self.ptr[t + 1])
         nb = b - a
         if nb == 0:
@@ -248,22 +279,32 @@ class OracleWorld:
         nout = C.c_int(0)
         prev = self.contacts[t]
         nprev = self.ncontacts[t]
+        feat = None
+        nfeat = C.c_int(0)
+        if record:
+            fcap = 4 * cap
+            feat = np.zeros((fcap, FEAT_RECORD))
         lib().or_step_tower(C.byref(self.params), nb, self.he[a:b], self.mass[a:b], x, q, v, w, act,
                             float(self.mu[t]), len(self.pushes[t]), self.push_arrays[t],
                             C.byref(self.step_counter[t]), int(n_steps),
                             prev if prev is not None else None, int(nprev), out, cap, C.byref(nout),
-                            C.byref(self.stats[t]))
+                            C.byref(self.stats[t]), None if feat is None else feat.ctypes.data,
+                            0 if feat is None else fcap, C.byref(nfeat))
+        if record:
+            self.features[t] = feat[:nfeat.value].copy()
         self.contacts[t] = out
         self.ncontacts[t] = min(nout.value, cap)
 
-    def step(self, n_steps: int = 1, towers=None, threads: int = 1):
+    def step(self, n_steps: int = 1, towers=None, threads: int = 1, record: bool = False):
+        """Step towers; with ``record`` keep the last step's per-point feature records
+        (features, k, solved impulses) in ``self.features[t]``."""
         towers = range(self.T) if towers is None else towers
         if threads <= 1:
             for t in towers:
-                self.step_tower(t, n_steps)
+                self.step_tower(t, n_steps, record)
         else:
             with ThreadPoolExecutor(threads) as ex:
-                list(ex.map(lambda t: self.step_tower(t, n_steps), towers))
+                list(ex.map(lambda t: self.step_tower(t, n_steps, record), towers))
 
     def manifolds(self, t: int):
         arr = self.contacts[t]

@@ -364,3 +364,23 @@ def single_box(pos, quat=(1.0, 0, 0, 0), linvel=(0, 0, 0), angvel=(0, 0, 0), hal
     sb = SceneBuilder(params or default_params(), n_steps=n_steps)
     sb.add_tower([half], [mass], [pos], [quat], mu, [linvel], [angvel])
     return sb.build()
+
+
+def mlp_init(seed: int = 0, n_feat: int = 24, hidden: int = 128, n_out: int = 3) -> np.ndarray:
+    """Initial parameters of the per-contact warm-start network, flat float64 in the order
+    W1[n_feat][hidden], b1, W2[hidden][hidden], b2, W3[hidden][n_out], b3, mean[n_feat], std[n_feat].
+    Weights and biases are uniform in +-1/sqrt(fan_in); mean 0 and std 1 (identity normalisation)."""
+    rng = rng_for(41, seed)
+    parts = []
+    for fan_in, fan_out in ((n_feat, hidden), (hidden, hidden), (hidden, n_out)):
+        bound = 1.0 / math.sqrt(fan_in)
+        parts.append(rng.uniform(-bound, bound, fan_in * fan_out))
+        parts.append(rng.uniform(-bound, bound, fan_out))
+    parts.append(np.zeros(n_feat))
+    parts.append(np.ones(n_feat))
+    return np.concatenate(parts)
+
+
+def random_features(n: int, seed: int = 0, n_feat: int = 24) -> np.ndarray:
+    """Feature-shaped random rows (standard normal), for network tests."""
+    return rng_for(42, seed).standard_normal((n, n_feat))
