@@ -14,6 +14,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <string>
+
 namespace jg {
 
 constexpr uint32_t kActive = 1u;    // body takes part in the simulation
@@ -85,7 +87,7 @@ struct StepArgs {
 constexpr int kBodyWords = 31;     // x3 q4 v3 w3 he3 invm invI3 flag tower Iw6 aabb/mask3
 constexpr int kTowerWords = 13;    // body range, mu, counters4, residual2, canonical range2, points
 constexpr int kPushWords = 10;
-constexpr int kManWords = 35;      // canonical (code, pos) + sorted (33)
+constexpr int kManWords = 32;      // canonical (code, pos) + sorted (code, meta, n3, depth, r_A 12, lambda 12)
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
 
 // LDS words needed by one pack with these capacities.
@@ -101,5 +103,8 @@ inline int64_t lds_words(int nbp, int pc, int tpc, int ppc, int warm) {
 }
 
 void launch_step(const StepArgs& a, size_t lds_bytes, void* stream);
+
+// records the message returned by jg_last_error on this thread; returns code
+int32_t set_error(int32_t code, const std::string& msg);
 
 }  // namespace jg

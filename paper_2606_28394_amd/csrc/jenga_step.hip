@@ -34,6 +34,7 @@ namespace jg {
 namespace {
 
 constexpr uint32_t kGround = 0xffffu;
+constexpr int kWindows = 4;      // broadphase register windows: packs of up to 256 bodies
 constexpr uint32_t kErrCand = 1u, kErrMan = 2u, kErrCol = 4u, kErrNan = 8u;
 
 struct Lds {
@@ -60,8 +61,8 @@ struct Lds {
   int32_t* cpos;
   // colour-sorted manifolds
   uint32_t *mab, *mmeta;
-  float *mn, *mt1, *mdepth;
-  float *mr, *ml;     // [(j*3 + k) * pc + m]
+  float *mn, *mdepth;
+  float *mr, *ml;     // [(j*3 + k) * pc + m]; mr holds r_A in the contact frame (n, t1, t2)
   // warm start: sorted -> canonical, previous step store (canonical order)
   int32_t* mcanon;
   uint32_t *pkey, *pslot;
@@ -90,7 +91,7 @@ __device__ inline Lds carve(float* base, const StepArgs& a) {
   L.scal = (int32_t*)take(16);
   L.ring = (uint32_t*)take(kRing);
   L.cab = (uint32_t*)take(pc); L.cpos = (int32_t*)take(pc);
-  L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc); L.mn = take(3 * pc); L.mt1 = take(3 * pc);
+  L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc); L.mn = take(3 * pc);
   L.mdepth = take(pc); L.mr = take(12 * pc); L.ml = take(12 * pc);
   if (a.warm_start) {
     L.mcanon = (int32_t*)take(pc);
@@ -261,7 +262,8 @@ struct Extremes {
   }
 };
 
-// Points relative to A's centre in slot order; bit s of the result marks slot s as used.
+// Points relative to A's centre, in contact-frame coordinates (along n, t1, t2), in slot
+// order; bit s of the result marks slot s as used.
 __device__ uint32_t manifold_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
                                    const float d[3], const float n[3], float t1[3], float rA[4][3]) {
   float t2[3];
@@ -339,8 +341,10 @@ __device__ uint32_t manifold_boxes(const float RA[9], const float heA[3], const 
       if (da > ba) { ba = da; ca[0] = pa[0]; ca[1] = pa[1]; ca[2] = pa[2]; }
       if (db < bb) { bb = db; cb[0] = pb[0]; cb[1] = pb[1]; cb[2] = pb[2]; }
     }
+    float mid[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) rA[0][r] = 0.5f * (ca[r] + cb[r]);
+    for (int r = 0; r < 3; ++r) mid[r] = 0.5f * (ca[r] + cb[r]);
+    rA[0][0] = dot3(mid, n); rA[0][1] = dot3(mid, t1); rA[0][2] = dot3(mid, t2);
     return 1u;
   }
   uint32_t used = 0u;
@@ -353,64 +357,46 @@ __device__ uint32_t manifold_boxes(const float RA[9], const float heA[3], const 
       ok = ok && !(((used >> c) & 1u) && (dx * dx + dy * dy < 1e-12f));
     }
     if (ok) used |= 1u << s;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) rA[s][r] = E.p[s].x * t1[r] + E.p[s].y * t2[r] + zmid * n[r];
+    rA[s][0] = zmid; rA[s][1] = E.p[s].x; rA[s][2] = E.p[s].y;
   }
   return used;
 }
 
 // ------------------------------------------------------------------------------------------------
-// one contact point's three rows (Eq. (lambda_n), Eq. (coulomb_pgs)); A gets -P, B gets +P
+// PGS rows (Eq. (lambda_n), Eq. (coulomb_pgs)), worked in the contact frame F = (n, t1, t2).
+// In that frame a row's direction is a unit axis e_K, so r x e_K has two non-zero components
+// and an impulse changes one linear-velocity component; A gets -P, B gets +P.
 // ------------------------------------------------------------------------------------------------
-struct BodyRegs {
-  float v[3], w[3], I[6], im;
+struct Frame { float f[3][3]; };   // rows n, t1, t2 (right handed: t2 = n x t1)
+
+__device__ inline void make_frame(const float n[3], Frame& F) {
+  F.f[0][0] = n[0]; F.f[0][1] = n[1]; F.f[0][2] = n[2];
+  tangent_basis(n, F.f[1], F.f[2]);
+}
+__device__ inline void to_local(const Frame& F, const float v[3], float o[3]) {
+  o[0] = dot3(F.f[0], v); o[1] = dot3(F.f[1], v); o[2] = dot3(F.f[2], v);
+}
+__device__ inline void to_world(const Frame& F, const float o[3], float v[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) v[r] = F.f[0][r] * o[0] + F.f[1][r] * o[1] + F.f[2][r] * o[2];
+}
+
+// body velocities and inverse inertia in the contact frame.  v0, w0 keep the velocities as
+// loaded: only the change is rotated back, so the frame's rounding (F^T F = I + O(eps)) touches
+// the impulses' effect and not the whole velocity on every visit.
+struct LBody {
+  float v[3], w[3], v0[3], w0[3], I[6], im;   // I: (00, 11, 22, 01, 02, 12)
   bool dyn;
 };
 
-__device__ inline void apply_row(BodyRegs& A, BodyRegs& B, const float rA[3], const float rB[3], const float d[3],
-                                 float dl) {
-  float cA[3], cB[3], iA[3], iB[3];
-  cross3(rA, d, cA);
-  cross3(rB, d, cB);
-  sym_mul(A.I, cA, iA);
-  sym_mul(B.I, cB, iB);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    A.v[k] -= A.im * dl * d[k]; A.w[k] -= dl * iA[k];
-    B.v[k] += B.im * dl * d[k]; B.w[k] += dl * iB[k];
-  }
+__device__ constexpr int sym_index(int r, int c) {
+  return r == c ? r : ((r + c == 1) ? 3 : ((r + c == 2) ? 4 : 5));
 }
 
-template <bool kNormal>
-__device__ inline float solve_row(BodyRegs& A, BodyRegs& B, const float rA[3], const float rB[3], const float d[3],
-                                  float lam, float bound, float e) {
-  float cA[3], cB[3], iA[3], iB[3];
-  cross3(rA, d, cA);
-  cross3(rB, d, cB);
-  const float vrel = d[0] * (B.v[0] - A.v[0]) + d[1] * (B.v[1] - A.v[1]) + d[2] * (B.v[2] - A.v[2]) +
-                     dot3(cB, B.w) - dot3(cA, A.w);
-  sym_mul(A.I, cA, iA);
-  sym_mul(B.I, cB, iB);
-  const float ik = __builtin_amdgcn_rcpf(A.im + B.im + dot3(cA, iA) + dot3(cB, iB));
-  float nl;
-  if (kNormal) {
-    nl = fmaxf(lam - (1.f + e) * vrel * ik, 0.f);
-  } else {
-    nl = fminf(fmaxf(lam - vrel * ik, -bound), bound);
-  }
-  const float dl = nl - lam;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    A.v[q] -= A.im * dl * d[q]; A.w[q] -= dl * iA[q];
-    B.v[q] += B.im * dl * d[q]; B.w[q] += dl * iB[q];
-  }
-  return nl;
-}
-
-__device__ inline void load_body(const Lds& L, int i, BodyRegs& b) {
+__device__ inline void load_local(const Lds& L, int i, const Frame& F, LBody& b) {
   if (i == (int)kGround || !(L.flag[i] & kDynamic)) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { b.v[k] = 0.f; b.w[k] = 0.f; }
+    for (int k = 0; k < 3; ++k) { b.v[k] = 0.f; b.w[k] = 0.f; b.v0[k] = 0.f; b.w0[k] = 0.f; }
 #pragma unroll
     for (int k = 0; k < 6; ++k) b.I[k] = 0.f;
     b.im = 0.f;
@@ -418,136 +404,194 @@ __device__ inline void load_body(const Lds& L, int i, BodyRegs& b) {
     return;
   }
   const int nb = L.nbp;
+  float v[3], w[3], Iw[6];
+  load3(L.v, nb, i, v);
+  load3(L.w, nb, i, w);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) { b.v[k] = L.v[k * nb + i]; b.w[k] = L.w[k * nb + i]; }
+  for (int k = 0; k < 6; ++k) Iw[k] = L.Iw[k * nb + i];
+  to_local(F, v, b.v);
+  to_local(F, w, b.w);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) b.I[k] = L.Iw[k * nb + i];
+  for (int k = 0; k < 3; ++k) { b.v0[k] = b.v[k]; b.w0[k] = b.w[k]; }
+  // F Iw F^T
+  float g[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) sym_mul(Iw, F.f[j], g[j]);
+  b.I[0] = dot3(F.f[0], g[0]); b.I[1] = dot3(F.f[1], g[1]); b.I[2] = dot3(F.f[2], g[2]);
+  b.I[3] = dot3(F.f[0], g[1]); b.I[4] = dot3(F.f[0], g[2]); b.I[5] = dot3(F.f[1], g[2]);
   b.im = L.invm[i];
   b.dyn = true;
 }
 
-__device__ inline void store_body(const Lds& L, int i, const BodyRegs& b) {
+__device__ inline void store_local(const Lds& L, int i, const Frame& F, const LBody& b) {
   if (!b.dyn) return;
-  const int nb = L.nbp;
+  float dv[3], dw[3], v[3], w[3], gv[3], gw[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) { L.v[k * nb + i] = b.v[k]; L.w[k * nb + i] = b.w[k]; }
+  for (int k = 0; k < 3; ++k) { dv[k] = b.v[k] - b.v0[k]; dw[k] = b.w[k] - b.w0[k]; }
+  to_world(F, dv, gv);
+  to_world(F, dw, gw);
+  load3(L.v, L.nbp, i, v);
+  load3(L.w, L.nbp, i, w);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { v[k] += gv[k]; w[k] += gw[k]; }
+  store3(L.v, L.nbp, i, v);
+  store3(L.w, L.nbp, i, w);
 }
 
-__device__ inline void manifold_bodies(const Lds& L, int m, int& a, int& b, BodyRegs& A, BodyRegs& B,
-                                       float dAB[3]) {
+// the two non-zero components (at i1 < i2) of a x e_K
+template <int K>
+__device__ inline void axis_cross(const float a[3], float& c1, float& c2) {
+  if constexpr (K == 0) { c1 = a[2]; c2 = -a[1]; }        // (0, a2, -a1)
+  else if constexpr (K == 1) { c1 = -a[2]; c2 = a[0]; }   // (-a2, 0, a0)
+  else { c1 = a[1]; c2 = -a[0]; }                         // (a1, -a0, 0)
+}
+
+template <int K>
+struct RowTerms {
+  static constexpr int i1 = (K == 0) ? 1 : 0;
+  static constexpr int i2 = (K == 2) ? 1 : 2;
+  float a1, a2, b1, b2;   // r_A x e_K, r_B x e_K
+  float iA[3], iB[3];     // I_A^-1 (r_A x e_K), I_B^-1 (r_B x e_K)
+  float k;                // inverse effective mass, Eq. (keff)
+  __device__ inline void build(const LBody& A, const LBody& B, const float rA[3], const float rB[3]) {
+    axis_cross<K>(rA, a1, a2);
+    axis_cross<K>(rB, b1, b2);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      iA[r] = A.I[sym_index(r, i1)] * a1 + A.I[sym_index(r, i2)] * a2;
+      iB[r] = B.I[sym_index(r, i1)] * b1 + B.I[sym_index(r, i2)] * b2;
+    }
+    k = A.im + B.im + (a1 * iA[i1] + a2 * iA[i2]) + (b1 * iB[i1] + b2 * iB[i2]);
+  }
+  __device__ inline float vrel(const LBody& A, const LBody& B) const {
+    return (B.v[K] - A.v[K]) + (b1 * B.w[i1] + b2 * B.w[i2]) - (a1 * A.w[i1] + a2 * A.w[i2]);
+  }
+  __device__ inline void apply(LBody& A, LBody& B, float dl) const {
+    A.v[K] -= A.im * dl;
+    B.v[K] += B.im * dl;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) { A.w[q] -= dl * iA[q]; B.w[q] += dl * iB[q]; }
+  }
+};
+
+__device__ inline void manifold_open(const Lds& L, int m, int& a, int& b, Frame& F, LBody& A, LBody& B,
+                                     float dAB[3]) {
   const uint32_t ab = L.mab[m];
   a = (int)(ab >> 16);
   b = (int)(ab & 0xffffu);
-  load_body(L, a, A);
-  load_body(L, b, B);
+  const float n[3] = {L.mn[m], L.mn[L.pc + m], L.mn[2 * L.pc + m]};
+  make_frame(n, F);
+  load_local(L, a, F, A);
+  load_local(L, b, F, B);
   if (b != (int)kGround) {
+    float d[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dAB[k] = L.x[k * L.nbp + a] - L.x[k * L.nbp + b];
+    for (int k = 0; k < 3; ++k) d[k] = L.x[k * L.nbp + a] - L.x[k * L.nbp + b];
+    to_local(F, d, dAB);
   } else {
     dAB[0] = dAB[1] = dAB[2] = 0.f;
   }
 }
 
-__device__ inline void manifold_frame(const Lds& L, int m, float n[3], float t1[3], float t2[3]) {
+__device__ inline void load_point(const Lds& L, int m, int j, const float dAB[3], float rA[3], float rB[3],
+                                  float lam[3]) {
   const int pc = L.pc;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) { n[k] = L.mn[k * pc + m]; t1[k] = L.mt1[k * pc + m]; }
-  cross3(n, t1, t2);
+  for (int k = 0; k < 3; ++k) {
+    rA[k] = L.mr[(j * 3 + k) * pc + m];
+    rB[k] = rA[k] + dAB[k];
+    lam[k] = L.ml[(j * 3 + k) * pc + m];
+  }
 }
 
 __device__ void solve_manifold(const Lds& L, int m, float mu, float e) {
   const int pc = L.pc;
   int a, b;
-  BodyRegs A, B;
-  float dAB[3], n[3], t1[3], t2[3];
-  manifold_bodies(L, m, a, b, A, B, dAB);
-  manifold_frame(L, m, n, t1, t2);
+  Frame F;
+  LBody A, B;
+  float dAB[3];
+  manifold_open(L, m, a, b, F, A, B, dAB);
   const int np = (int)(L.mmeta[m] & 15u);
   for (int j = 0; j < np; ++j) {
     float rA[3], rB[3], lam[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      rA[k] = L.mr[(j * 3 + k) * pc + m];
-      rB[k] = rA[k] + dAB[k];
-      lam[k] = L.ml[(j * 3 + k) * pc + m];
+    load_point(L, m, j, dAB, rA, rB, lam);
+    {
+      RowTerms<0> t;
+      t.build(A, B, rA, rB);
+      const float nl = fmaxf(lam[0] - (1.f + e) * t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), 0.f);
+      t.apply(A, B, nl - lam[0]);
+      lam[0] = nl;
     }
-    lam[0] = solve_row<true>(A, B, rA, rB, n, lam[0], 0.f, e);
     const float bound = mu * lam[0];
-    lam[1] = solve_row<false>(A, B, rA, rB, t1, lam[1], bound, e);
-    lam[2] = solve_row<false>(A, B, rA, rB, t2, lam[2], bound, e);
+    {
+      RowTerms<1> t;
+      t.build(A, B, rA, rB);
+      const float nl = fminf(fmaxf(lam[1] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
+      t.apply(A, B, nl - lam[1]);
+      lam[1] = nl;
+    }
+    {
+      RowTerms<2> t;
+      t.build(A, B, rA, rB);
+      const float nl = fminf(fmaxf(lam[2] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
+      t.apply(A, B, nl - lam[2]);
+      lam[2] = nl;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) L.ml[(j * 3 + k) * pc + m] = lam[k];
   }
-  store_body(L, a, A);
-  if (b != (int)kGround) store_body(L, b, B);
+  store_local(L, a, F, A);
+  if (b != (int)kGround) store_local(L, b, F, B);
 }
 
 __device__ void warm_apply_manifold(const Lds& L, int m) {
-  const int pc = L.pc;
   int a, b;
-  BodyRegs A, B;
-  float dAB[3], n[3], t1[3], t2[3];
-  manifold_bodies(L, m, a, b, A, B, dAB);
-  manifold_frame(L, m, n, t1, t2);
+  Frame F;
+  LBody A, B;
+  float dAB[3];
+  manifold_open(L, m, a, b, F, A, B, dAB);
   const int np = (int)(L.mmeta[m] & 15u);
   for (int j = 0; j < np; ++j) {
     float rA[3], rB[3], lam[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      rA[k] = L.mr[(j * 3 + k) * pc + m];
-      rB[k] = rA[k] + dAB[k];
-      lam[k] = L.ml[(j * 3 + k) * pc + m];
-    }
-    apply_row(A, B, rA, rB, n, lam[0]);
-    apply_row(A, B, rA, rB, t1, lam[1]);
-    apply_row(A, B, rA, rB, t2, lam[2]);
+    load_point(L, m, j, dAB, rA, rB, lam);
+    { RowTerms<0> t; t.build(A, B, rA, rB); t.apply(A, B, lam[0]); }
+    { RowTerms<1> t; t.build(A, B, rA, rB); t.apply(A, B, lam[1]); }
+    { RowTerms<2> t; t.build(A, B, rA, rB); t.apply(A, B, lam[2]); }
   }
-  store_body(L, a, A);
-  if (b != (int)kGround) store_body(L, b, B);
+  store_local(L, a, F, A);
+  if (b != (int)kGround) store_local(L, b, F, B);
 }
 
 // natural-map residual of one manifold: sum of squares and max |r| over its rows
 __device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, float& mx) {
-  const int pc = L.pc;
   int a, b;
-  BodyRegs A, B;
-  float dAB[3], n[3], t1[3], t2[3];
-  manifold_bodies(L, m, a, b, A, B, dAB);
-  manifold_frame(L, m, n, t1, t2);
+  Frame F;
+  LBody A, B;
+  float dAB[3];
+  manifold_open(L, m, a, b, F, A, B, dAB);
   const int np = (int)(L.mmeta[m] & 15u);
   sum = 0.f;
   mx = 0.f;
   for (int j = 0; j < np; ++j) {
     float rA[3], rB[3], lam[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      rA[k] = L.mr[(j * 3 + k) * pc + m];
-      rB[k] = rA[k] + dAB[k];
-      lam[k] = L.ml[(j * 3 + k) * pc + m];
+    load_point(L, m, j, dAB, rA, rB, lam);
+    const float bound = mu * lam[0];
+    float res[3];
+    { RowTerms<0> t; t.build(A, B, rA, rB); res[0] = fminf(t.k * lam[0], t.vrel(A, B)); }
+    {
+      RowTerms<1> t;
+      t.build(A, B, rA, rB);
+      const float cl = fminf(fmaxf(lam[1] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
+      res[1] = t.k * (lam[1] - cl);
     }
-    const float* dirs[3] = {n, t1, t2};
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const float* d = dirs[r];
-      float cA[3], cB[3], iA[3], iB[3];
-      cross3(rA, d, cA);
-      cross3(rB, d, cB);
-      const float vrel = d[0] * (B.v[0] - A.v[0]) + d[1] * (B.v[1] - A.v[1]) + d[2] * (B.v[2] - A.v[2]) +
-                         dot3(cB, B.w) - dot3(cA, A.w);
-      sym_mul(A.I, cA, iA);
-      sym_mul(B.I, cB, iB);
-      const float k = A.im + B.im + dot3(cA, iA) + dot3(cB, iB);
-      float res;
-      if (r == 0) {
-        res = fminf(k * lam[0], vrel);
-      } else {
-        const float bound = mu * lam[0];
-        const float cl = fminf(fmaxf(lam[r] - vrel * __builtin_amdgcn_rcpf(k), -bound), bound);
-        res = k * (lam[r] - cl);
-      }
-      sum += res * res;
-      mx = fmaxf(mx, fabsf(res));
+    {
+      RowTerms<2> t;
+      t.build(A, B, rA, rB);
+      const float cl = fminf(fmaxf(lam[2] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
+      res[2] = t.k * (lam[2] - cl);
     }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) { sum += res[r] * res[r]; mx = fmaxf(mx, fabsf(res[r])); }
   }
 }
 
@@ -727,43 +771,83 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       timer.mark(L, lane, 1);
 
       // ---- 3 + 4. broadphase in canonical order, narrowphase on every 64 candidates ----
+      // Lane l holds body 64 w + l of window w in registers (position, AABB, flags, tower);
+      // body i is broadcast from its window with readlane, so the pair loop touches LDS only
+      // to append candidates to the ring.
       int head = 0, tail = 0, nman = 0;
-      for (int i = 0; i < nb; ++i) {
-        const uint32_t fi = L.flag[i];
-        if (!(fi & kActive)) continue;
-        const bool dyni = (fi & kDynamic) != 0;
-        const int ti = L.tw[i];
-        const int npair = L.tb1[ti] - i - 1;
-        const float xi0 = L.x[i], xi1 = L.x[NB + i], xi2 = L.x[2 * NB + i];
-        const float hi0 = L.hm[i], hi1 = L.hm[NB + i], hi2 = L.hm[2 * NB + i];
-        for (int c0 = 0; c0 <= npair; c0 += kWave) {
-          const int jj = c0 + lane;
-          bool hit = false;
-          uint32_t code = 0;
-          if (jj < npair) {
-            const int j = i + 1 + jj;
-            const uint32_t fj = L.flag[j];
-            if ((fj & kActive) && (dyni || (fj & kDynamic))) {
-              hit = fabsf(xi0 - L.x[j]) <= hi0 + L.hm[j] + a.margin &&
-                    fabsf(xi1 - L.x[NB + j]) <= hi1 + L.hm[NB + j] + a.margin &&
-                    fabsf(xi2 - L.x[2 * NB + j]) <= hi2 + L.hm[2 * NB + j] + a.margin;
-            }
-            code = ((uint32_t)i << 16) | (uint32_t)j;
-          } else if (jj == npair) {
-            hit = dyni && (xi2 - hi2 <= a.margin);
-            code = ((uint32_t)i << 16) | kGround;
+      {
+        float wx[kWindows][3], wh[kWindows][3];
+        uint32_t wf[kWindows];
+        int wt[kWindows];
+#pragma unroll
+        for (int w = 0; w < kWindows; ++w) {
+          const int j = w * kWave + lane;
+          const bool in = j < nb;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            wx[w][k] = in ? L.x[k * NB + j] : 0.f;
+            wh[w][k] = in ? L.hm[k * NB + j] : 0.f;
           }
-          const uint64_t bal = __ballot(hit);
-          if (hit) L.ring[(tail + __popcll(bal & lane_lt_mask(lane))) & (kRing - 1)] = code;
-          const int cnt = __popcll(bal);
-          if (lane == 0 && cnt) L.tcnt[ti * 4 + 0] += (uint32_t)cnt;
-          tail += cnt;
-          if (tail - head >= kWave) {
-            __syncthreads();
-            nman = narrow_chunk(L, head, kWave, nman, lane);
-            head += kWave;
+          wf[w] = in ? L.flag[j] : 0u;
+          wt[w] = in ? L.tw[j] : -1;
+        }
+        const int nwin = (nb + kWave - 1) / kWave;
+        int cur_t = -1, cand_acc = 0;
+        for (int i = 0; i < nb; ++i) {
+          const int wi = i / kWave, li = i % kWave;
+          float xi[3], hi[3];
+          uint32_t fi = 0u;
+          int ti = 0;
+#pragma unroll
+          for (int w = 0; w < kWindows; ++w)
+            if (w == wi) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                xi[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wx[w][k]), li));
+                hi[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wh[w][k]), li));
+              }
+              fi = __builtin_amdgcn_readlane(wf[w], li);
+              ti = __builtin_amdgcn_readlane(wt[w], li);
+            }
+          if (!(fi & kActive)) continue;
+          if (ti != cur_t) {
+            if (lane == 0 && cur_t >= 0 && cand_acc) L.tcnt[cur_t * 4 + 0] += (uint32_t)cand_acc;
+            cur_t = ti;
+            cand_acc = 0;
+          }
+          const bool dyni = (fi & kDynamic) != 0;
+#pragma unroll
+          for (int w = 0; w < kWindows; ++w) {
+            if (w < wi || w >= nwin) continue;
+            const int j = w * kWave + lane;
+            const bool hit = j > i && wt[w] == ti && (wf[w] & kActive) && (dyni || (wf[w] & kDynamic)) &&
+                             fabsf(xi[0] - wx[w][0]) <= hi[0] + wh[w][0] + a.margin &&
+                             fabsf(xi[1] - wx[w][1]) <= hi[1] + wh[w][1] + a.margin &&
+                             fabsf(xi[2] - wx[w][2]) <= hi[2] + wh[w][2] + a.margin;
+            const uint64_t bal = __ballot(hit);
+            if (hit) L.ring[(tail + __popcll(bal & lane_lt_mask(lane))) & (kRing - 1)] = ((uint32_t)i << 16) | (uint32_t)j;
+            const int cnt = __popcll(bal);
+            cand_acc += cnt;
+            tail += cnt;
+            if (tail - head >= kWave) {
+              __syncthreads();
+              nman = narrow_chunk(L, head, kWave, nman, lane);
+              head += kWave;
+            }
+          }
+          // the ground comes last in body i's canonical row
+          if (dyni && (xi[2] - hi[2] <= a.margin)) {
+            if (lane == 0) L.ring[tail & (kRing - 1)] = ((uint32_t)i << 16) | kGround;
+            cand_acc += 1;
+            tail += 1;
+            if (tail - head >= kWave) {
+              __syncthreads();
+              nman = narrow_chunk(L, head, kWave, nman, lane);
+              head += kWave;
+            }
           }
         }
+        if (lane == 0 && cur_t >= 0 && cand_acc) L.tcnt[cur_t * 4 + 0] += (uint32_t)cand_acc;
       }
       __syncthreads();
       while (head < tail) {
@@ -906,9 +990,10 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
               const float rx = R[0] * s0 + R[1] * s1 + R[2] * s2;
               const float ry = R[3] * s0 + R[4] * s1 + R[5] * s2;
               const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
-              L.mr[(npts * 3 + 0) * PC + sidx] = rx;
-              L.mr[(npts * 3 + 1) * PC + sidx] = ry;
-              L.mr[(npts * 3 + 2) * PC + sidx] = 0.5f * (rz - xz);
+              // r_A = (rx, ry, (rz - xz)/2) in the frame n = -z, t1 = x, t2 = -y
+              L.mr[(npts * 3 + 0) * PC + sidx] = 0.5f * (xz - rz);
+              L.mr[(npts * 3 + 1) * PC + sidx] = rx;
+              L.mr[(npts * 3 + 2) * PC + sidx] = -ry;
               slots |= (uint32_t)k << (4 * npts);
               depth = fmaxf(depth, -vz[k]);
               ++npts;
@@ -970,7 +1055,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         L.mdepth[sidx] = depth;
         if (a.warm_start) L.mcanon[sidx] = p;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { L.mn[k * PC + sidx] = n[k]; L.mt1[k * PC + sidx] = t1[k]; }
+        for (int k = 0; k < 3; ++k) L.mn[k * PC + sidx] = n[k];
         const int ti = L.tw[i];
         atomicAdd(&L.tcnt[ti * 4 + 1], 1u);
         atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
@@ -1007,19 +1092,26 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           a.out_ab[g] = L.mab[m];
           a.out_meta[g] = (L.mmeta[m] & 0x0ffff00fu) | ((uint32_t)col << 4);
           a.out_tower[g] = L.tw[a_];
+          const float nn[3] = {L.mn[m], L.mn[PC + m], L.mn[2 * PC + m]};
+          Frame F;
+          make_frame(nn, F);
           for (int k = 0; k < 3; ++k) {
-            a.out_geo[8 * g + k] = L.mn[k * PC + m];
-            a.out_geo[8 * g + 3 + k] = L.mt1[k * PC + m];
+            a.out_geo[8 * g + k] = nn[k];
+            a.out_geo[8 * g + 3 + k] = F.f[1][k];
           }
           a.out_geo[8 * g + 6] = L.mdepth[m];
           a.out_geo[8 * g + 7] = 0.f;
           const int npts = (int)(L.mmeta[m] & 15u);
-          for (int q = 0; q < 4; ++q)
+          for (int q = 0; q < 4; ++q) {
+            float rl[3] = {0.f, 0.f, 0.f}, rw[3];
+            if (q < npts)
+              for (int k = 0; k < 3; ++k) rl[k] = L.mr[(q * 3 + k) * PC + m];
+            to_world(F, rl, rw);
             for (int k = 0; k < 3; ++k) {
-              const float r = q < npts ? L.mr[(q * 3 + k) * PC + m] : 0.f;
-              a.out_pts[24 * g + 6 * q + k] = L.x[k * NB + a_] + r;
+              a.out_pts[24 * g + 6 * q + k] = L.x[k * NB + a_] + rw[k];
               a.out_pts[24 * g + 6 * q + 3 + k] = q < npts ? L.ml[(q * 3 + k) * PC + m] : 0.f;
             }
+          }
         }
         if (lane == 0) a.out_count[pk] = nkept;
       }

@@ -55,6 +55,8 @@ struct PushRow {
 
 }  // namespace
 
+int32_t jg::set_error(int32_t code, const std::string& msg) { return fail(code, msg); }
+
 struct jg_world {
   jg_params prm;
   int max_towers = 0, max_bodies = 0;
@@ -228,6 +230,8 @@ int32_t build_layout(jg_world* w) {
     // launch class: packs that fit the same number of workgroups per CU
     const size_t lds = lds_of(bins[b].bodies, (int)bins[b].towers.size(), pushes);
     const int per_cu = (int)((160 * 1024) / lds);
+    if (bins[b].bodies > 4 * jg::kWave)
+      return fail(JG_ECAPACITY, "a pack of " + std::to_string(bins[b].bodies) + " bodies exceeds 256");
     if (per_cu == 0)
       return fail(JG_ECAPACITY, "a pack needs " + std::to_string(lds) + " bytes of LDS (max 163840); "
                                 "use smaller towers or fewer manifolds per body");
