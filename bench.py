@@ -85,6 +85,82 @@ def cpu_baseline(scene, n_towers=1024, n_steps=50, threads=None):
                 contact_iters_per_s=ci / dt)
 
 
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2606_28394_amd", "data", "warmstart_mlp.npy")
+
+
+def _run_residuals(J, scene, steps, chunk, **kw):
+    """Step a fresh world `steps` steps in launches of `chunk`; median and mean of the per-tower
+    residual (RMS over rows) at each launch end, and the counters."""
+    import numpy as np
+    world = J.World(scene, **kw)
+    res = []
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        world.step(n)
+        done += n
+        res.extend(world.stats(t).residual_rms for t in range(scene["n_towers"]))
+    st = world.stats()
+    world.close()
+    res = np.asarray(res)
+    return float(np.median(res)), float(res.mean()), st
+
+
+def _run_timed(J, torch, scene, steps, **kw):
+    """One persistent launch of `steps` steps from the initial state; tower-steps/s from HIP events."""
+    stream = torch.cuda.current_stream()
+    world = J.World(scene, stream=stream.cuda_stream, **kw)
+    world.step(0)
+    world.sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    world.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    st = world.stats()
+    world.close()
+    return scene["n_towers"] * steps / (ms * 1e-3), ms, st
+
+
+def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(4, 8, 12)):
+    """The learned warm start against plain PGS at 20 iterations at equal residual, on the
+    450-tower removal batch: R20 = median tower residual of plain-20; each k runs with the
+    fallback threshold tau = R20; the smallest k whose median residual is <= R20 is the
+    equal-residual point.  Rates include inference, residual passes and fallbacks."""
+    import numpy as np
+    from paper_2606_28394_amd import workloads as W
+    net = np.load(weights)
+    scene = W.cfg2(0, n_steps=steps)
+    r20, m20, st20 = _run_residuals(J, scene, steps, chunk)
+    v20, ms20, _ = _run_timed(J, torch, scene, steps)
+    log(f"plain-20: median residual {r20:.3e} m/s, {v20:.4g} tower-steps/s")
+    rows = []
+    for k in ks:
+        rk, mk, stk = _run_residuals(J, scene, steps, chunk, warm_start=2, mlp=net, mlp_iters=k, fallback_tau=r20)
+        vk, msk, stt = _run_timed(J, torch, scene, steps, warm_start=2, mlp=net, mlp_iters=k, fallback_tau=r20)
+        rows.append(dict(k=k, median_residual=rk, mean_residual=mk, value=vk, kernel_ms=msk,
+                         fallback_rate=stt.fallbacks / (scene["n_towers"] * steps),
+                         contact_iters_per_point=stt.contact_iters / max(1, stt.points)))
+        log(f"learned k={k}: median residual {rk:.3e}, {vk:.4g} tower-steps/s, fallbacks "
+            f"{100 * rows[-1]['fallback_rate']:.1f}%")
+    # zero-start and previous-step plain solves at the same k, for context
+    ctx = {}
+    for k in ks:
+        p = dict(scene["params"])
+        p["iters"] = k
+        ctx[f"zero_k{k}"] = _run_residuals(J, scene, steps, chunk, params=p)[0]
+        ctx[f"previous_k{k}"] = _run_residuals(J, scene, steps, chunk, params=p, warm_start=1)[0]
+    ok = [r for r in rows if r["median_residual"] <= r20]
+    best = min(ok, key=lambda r: r["k"]) if ok else None
+    return dict(workload=f"removal batch: {scene['n_towers']} towers, 12-24 levels, 1-8 push removals each, "
+                         f"{steps} steps",
+                plain20=dict(median_residual=r20, mean_residual=m20, value=v20, kernel_ms=ms20),
+                learned=rows, median_residual_other_starts=ctx,
+                equal_residual_k=best["k"] if best else None,
+                learned_vs_plain20=(best["value"] / v20) if best else None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +171,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-towers", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=50)
+    ap.add_argument("--learned-weights", default=DEFAULT_WEIGHTS,
+                    help="trained warm-start network (.npy); the equal-residual leg runs when it exists")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); towers shard across GPUs with no "
@@ -183,10 +262,13 @@ def main():
         "error_word": int(s1.error_word),
         "residual_rms_max": s1.residual_rms,
     }
+    world.close()
+    if not args.no_learned and os.path.exists(args.learned_weights):
+        log("equal-residual leg (learned warm start vs plain-20) ...")
+        out["equal_residual"] = equal_residual(J, torch, args.learned_weights)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_towers, args.cpu_steps)
-    world.close()
     print(json.dumps(out), flush=True)
 
 

@@ -65,11 +65,19 @@ typedef struct {
   double margin;         /* AABB margin epsilon, Eq. (aabb); default 2e-3 m */
   int32_t n_sub;         /* substeps per step, each a full pipeline with dt/n_sub; default 1 */
   int32_t iters;         /* PGS iterations; default 20 */
-  int32_t warm_start;    /* 0: zero initial impulses; 1: previous step's impulses by key */
+  int32_t warm_start;    /* 0: zero initial impulses; 1: previous step's impulses by key (same pair
+                            and slot, normals within 0.95); 2: learned (network set by jg_set_mlp),
+                            mlp_iters sweeps, plain re-solve of towers whose residual exceeds
+                            fallback_tau */
   int32_t device;        /* HIP device ordinal */
   void* stream;          /* hipStream_t for all GPU work; NULL = default stream */
   int32_t pack_bodies;   /* bodies per on-chip pack; 0 = automatic */
   float manifolds_per_body;  /* manifold capacity per body in a pack; 0 = automatic (3.5) */
+  int32_t mlp_iters;     /* PGS iterations after a learned warm start; default 8 */
+  double fallback_tau;   /* tower residual [m/s] above which a learned solve is redone plainly
+                            (pre-solve velocities, zero impulses, iters sweeps); default 1e30 */
+  int32_t record_features;   /* 1: keep per-point feature records of each launch's last step
+                                (jg_query_features); default 0 */
 } jg_params;
 
 /* One contact point of the last solved step. */
@@ -97,6 +105,7 @@ typedef struct {
   uint32_t error_word;     /* JG_ERR_* bits */
   double residual_rms;     /* natural-map residual of the last solve, RMS over rows [m/s] */
   double residual_max;     /* largest |row residual| of the last solve [m/s] */
+  int64_t fallbacks;       /* learned solves redone plainly, summed over steps */
 } jg_stats;
 
 /* Fill *p with the defaults listed above. */
@@ -164,6 +173,17 @@ int32_t jg_query_stats(jg_world* w, int32_t tower, jg_stats* out);
  * min(n, 10) counters (further entries 0) and resets them.  Waits. */
 int32_t jg_query_phase_cycles(jg_world* w, uint64_t* cycles, int32_t n);
 
+/* Per-point records of the last step of the last launch (needs record_features = 1), in the
+ * order of jg_query_contacts: JG_FEAT_RECORD floats each, the 24 network features taken before
+ * the solve (layout described with jg_set_mlp), then k_n, k_t1, k_t2 (Eq. (keff)) and the solved
+ * impulses.  tower = -1 returns every tower's records, grouped by on-chip pack.  Writes at most
+ * `capacity` records and the total count to *n_out.  Waits. */
+int32_t jg_query_features(jg_world* w, int32_t tower, float* out, int32_t capacity, int32_t* n_out);
+
+/* Network for warm_start = 2: host FP32 parameter vector (JG_MLP_PARAMS values, layout below).
+ * The world keeps a device copy and its packed form; call again to replace it. */
+int32_t jg_set_mlp(jg_world* w, const float* params);
+
 /* Number of towers and bodies added so far. */
 int32_t jg_world_size(jg_world* w, int32_t* n_towers, int32_t* n_bodies);
 
@@ -172,6 +192,63 @@ int32_t jg_sync(jg_world* w);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* jg_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Learned warm start: a per-contact network predicts each contact point's initial impulses
+ * (normal, t1, t2) before the PGS sweeps of Sec. "Contact Solver --- Projected Gauss-Seidel".
+ * The network is 24 features -> 128 -> GELU -> 128 -> GELU -> 3 on bfloat16 matrix-core
+ * operands with FP32 accumulation.
+ *
+ * Parameters are one FP32 vector of JG_MLP_PARAMS values, in this order:
+ *   W1[24][128], b1[128], W2[128][128], b2[128], W3[128][3], b3[3], mean[24], sd[24]
+ * W[i][j] multiplies input i into output j; the first JG_MLP_TRAINABLE values are trained,
+ * mean and sd z-score the features.  Every weight and bias is rounded to bfloat16 (nearest
+ * even) when packed; layer inputs are rounded to bfloat16 before each product.
+ *
+ * Features of a contact point (in the contact frame F = (n, t1, t2) unless noted), at the
+ * velocities before the solve: F (x_B - x_A) [3]; q_A^-1 q_B with w >= 0 [4]; world normal [3];
+ * depth [1]; mu [1]; previous step's impulses of the same (pair, slot) in the outputs' units,
+ * lambda_d k_d / (|g| dt) with this step's k, zero if new [3];
+ * F r_A [3]; F r_B [3]; F (relative velocity of B with respect to A at the point) [3].  The
+ * ground acts as a body at (x_A, y_A, 0) with the identity orientation.
+ * Outputs y are the change of the dimensionless impulses lambda_d k_d / (|g| dt) (k_d of
+ * Eq. (keff)) from the previous step's (features 12..14): with s = y + those features, the
+ * initial impulses are lambda_n = max(0, s_n) |g| dt / k_n and
+ * lambda_t = clip(s_t |g| dt / k_t, -mu lambda_n, mu lambda_n).  A zero network is therefore the
+ * previous-step warm start (with the tangents clipped to the friction box).
+ *
+ * The jg_mlp_* calls take DEVICE pointers owned by the caller, queue work on `stream`
+ * (NULL = default stream) and return without waiting.
+ * ------------------------------------------------------------------------------------------- */
+#define JG_MLP_PARAMS 20147
+#define JG_MLP_TRAINABLE 20099
+#define JG_MLP_FEATURES 24
+#define JG_FEAT_RECORD 30      /* per contact point: 24 features, k[3], solved impulses[3] */
+
+/* Size of the packed (bfloat16 operand layout) copy of the parameters. */
+int32_t jg_mlp_packed_bytes(size_t* bytes);
+
+/* Pack params (JG_MLP_PARAMS floats) into packed (jg_mlp_packed_bytes bytes, 16-byte aligned). */
+int32_t jg_mlp_pack(const float* params, void* packed, void* stream);
+
+/* Network outputs y (n x 3) for feature rows feats (n x 24), with packed parameters. */
+int32_t jg_mlp_forward(const void* packed, const float* feats, int32_t n, float* y, void* stream);
+
+/* Workspace needed by jg_mlp_grad for a batch of n rows. */
+int32_t jg_mlp_grad_workspace_bytes(int32_t n, size_t* bytes);
+
+/* Mean squared error over the n x 3 outputs against targets (n x 3), and its gradient with
+ * respect to the JG_MLP_TRAINABLE trainable parameters (grad: JG_MLP_TRAINABLE floats; loss:
+ * one float, may be NULL).  packed must hold jg_mlp_pack(params).  The forward pass is the one
+ * jg_mlp_forward runs; the backward pass treats the bfloat16 roundings as the identity. */
+int32_t jg_mlp_grad(const float* params, const void* packed, const float* feats, const float* targets, int32_t n,
+                    float* grad, float* loss, void* workspace, size_t workspace_bytes, void* stream);
+
+/* One AdamW step (decoupled weight decay, bias-corrected moments; step counts from 1) on the
+ * trainable parameters: p *= 1 - lr wd; m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  m, v: JG_MLP_TRAINABLE floats. */
+int32_t jg_mlp_adamw(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                     float beta2, float eps, float weight_decay, void* stream);
 
 #ifdef __cplusplus
 }

@@ -664,12 +664,13 @@ void or_mlp_forward(const double* mlp, const double f[OR_NFEAT], double y[3]) {
 
 /* the 24 features of point i of manifold m, at the pre-solve velocities:
  * contact-frame x_B - x_A (3), q_A^-1 q_B with w >= 0 (4), world normal (3), depth (1), mu (1),
- * previous-step impulses of the same key (3, zero if new), contact-frame r_A and r_B (6),
- * contact-frame relative velocity of the contact point (3).  The ground stands in as a body at
- * (x_A, y_A, 0) with the identity orientation. */
+ * previous-step impulses of the same key in the outputs' units, lambda_d k_d / (|g| dt) with
+ * this step's k (3, zero if new), contact-frame r_A and r_B (6), contact-frame relative velocity
+ * of the contact point (3).  The ground stands in as a body at (x_A, y_A, 0) with the identity
+ * orientation.  m->k must hold this step's inverse effective masses. */
 static void point_features(const or_manifold* m, int i, const double* x, const double* q, const double* v,
                            const double* w, const uint8_t* dyn, double mu, const double prev_lam[3],
-                           double f[OR_NFEAT]) {
+                           double gdt, double f[OR_NFEAT]) {
   const double* F[3] = {m->normal, m->t1, m->t2};
   const double* xa = x + 3 * m->a;
   double xb[3] = {xa[0], xa[1], 0.0};
@@ -692,7 +693,7 @@ static void point_features(const or_manifold* m, int i, const double* x, const d
   for (int k = 0; k < 3; ++k) f[o++] = m->normal[k];
   f[o++] = m->depth;
   f[o++] = mu;
-  for (int k = 0; k < 3; ++k) f[o++] = prev_lam[k];
+  for (int k = 0; k < 3; ++k) f[o++] = prev_lam[k] * m->k[i][k] / gdt;
   double rA[3], rB[3];
   for (int k = 0; k < 3; ++k) {
     rA[k] = m->point[i][k] - xa[k];
@@ -842,6 +843,7 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
   for (int c = 0; c < nm; ++c) npts += ord[c].npts;
   const int learned = P->warm_start == 2 && P->mlp != NULL;
   double* feats = NULL;
+  const double gdt = norm3(P->gravity) * dt;
   if (learned || feat_out) {
     feats = (double*)malloc(sizeof(double) * OR_NFEAT * (size_t)(npts > 0 ? npts : 1));
     long o = 0;
@@ -850,11 +852,10 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
       for (int i = 0; i < m->npts; ++i, ++o) {
         double l[3] = {0.0, 0.0, 0.0};
         if (prev) find_prev(prev, nprev, m, m->slot[i], l);
-        point_features(m, i, x, q, v, w, dyn, mu, l, feats + OR_NFEAT * o);
+        point_features(m, i, x, q, v, w, dyn, mu, l, gdt, feats + OR_NFEAT * o);
       }
     }
   }
-  const double gdt = norm3(P->gravity) * dt;
   {
     long o = 0;
     for (int c = 0; c < nm; ++c) {
@@ -865,9 +866,12 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
           double l[3];
           if (find_prev(prev, nprev, m, m->slot[i], l)) { m->lam[i][0] = l[0]; m->lam[i][1] = l[1]; m->lam[i][2] = l[2]; }
         } else if (learned) {
-          /* the network predicts impulses in units of |g| dt / k (dimensionless) */
+          /* the network predicts the change of the dimensionless impulses lambda k / (|g| dt)
+           * from the previous step's (input features 12..14) */
           double y[3];
-          or_mlp_forward(P->mlp, feats + OR_NFEAT * o, y);
+          const double* f = feats + OR_NFEAT * o;
+          or_mlp_forward(P->mlp, f, y);
+          for (int d = 0; d < 3; ++d) y[d] += f[12 + d];
           double ln = (y[0] > 0.0 ? y[0] : 0.0) * gdt / m->k[i][0];
           double b = mu * ln;
           double l1 = y[1] * gdt / m->k[i][1], l2 = y[2] * gdt / m->k[i][2];

@@ -34,7 +34,9 @@ typedef struct {
   const double* mlp;     /* MLP parameters (layout OR_MLP_*), used when warm_start == 2 */
 } or_params;
 
-/* Learned warm start: per-contact MLP 24 -> 128 -> 128 -> 3 with GELU (erf form), parameters
+/* Learned warm start: per-contact MLP 24 -> 128 -> 128 -> 3 with GELU (erf form).  Its outputs
+ * are added to the previous step's dimensionless impulses (features 12..14) and the sum y maps to
+ * lambda_n = max(0, y_n) |g| dt / k_n, lambda_t = clip(y_t |g| dt / k_t, +-mu lambda_n).  Parameters
  * as doubles (already rounded to bfloat16 by the caller) in this order:
  * W1[24][128], b1[128], W2[128][128], b2[128], W3[128][3], b3[3], mean[24], std[24].
  * Each layer's input is rounded to bfloat16, as the GPU feeds its matrix cores. */

@@ -5,11 +5,11 @@ CPU-baseline leg.  The product path never imports this module.
 
 Network (learned warm start of the contact solver): 24 contact features, z-scored
 with training-set statistics, then Linear(24, 128) -> GELU -> Linear(128, 128) -> GELU
--> Linear(128, 3).  GELU is the exact form x * Phi(x).  The three outputs are the
-dimensionless impulses lambda_d * k_d / (|g| dt) for d = normal, t1, t2, where k_d is
-the row's inverse effective mass (Eq. (keff)); training minimises their mean squared
-error against a converged plain solve, with AdamW (the paper's optimiser defaults:
-learning rate 3e-4, weight decay 1e-4).
+-> Linear(128, 3).  GELU is the exact form x * Phi(x).  The three outputs are the change
+of the dimensionless impulses lambda_d * k_d / (|g| dt) (d = normal, t1, t2; k_d the row's
+inverse effective mass, Eq. (keff)) from the previous step's, which are input features
+12..14; training minimises their mean squared error against a converged plain solve, with
+AdamW (the paper's optimiser defaults: learning rate 3e-4, weight decay 1e-4).
 
 Parameters live in one flat float64 vector, in this order (the same as the C oracle's
 ``or_mlp_forward``): W1[24][128], b1[128], W2[128][128], b2[128], W3[128][3], b3[3],
@@ -135,14 +135,18 @@ def normalisation(feats: np.ndarray, floor: float = 1e-12):
     return mean, np.where(std > floor, std, 1.0)
 
 
-def targets(k: np.ndarray, lam: np.ndarray, gravity_norm: float, dt: float) -> np.ndarray:
-    """Dimensionless training targets lambda_d k_d / (|g| dt)."""
-    return lam * k / (gravity_norm * dt)
+def targets(k: np.ndarray, lam: np.ndarray, prev: np.ndarray, gravity_norm: float, dt: float) -> np.ndarray:
+    """Training targets: the change lambda_d k_d / (|g| dt) - prev_d of the dimensionless impulses
+    from the previous step's (prev = features 12..14)."""
+    return lam * k / (gravity_norm * dt) - prev
 
 
-def warm_start(y: np.ndarray, k: np.ndarray, mu: float, gravity_norm: float, dt: float) -> np.ndarray:
-    """Initial impulses from network outputs: lambda_n = max(0, y_n) |g| dt / k_n and
-    lambda_t = clip(y_t |g| dt / k_t, -mu lambda_n, mu lambda_n)."""
+def warm_start(y: np.ndarray, k: np.ndarray, prev: np.ndarray, mu: float, gravity_norm: float,
+               dt: float) -> np.ndarray:
+    """Initial impulses from network outputs y and the previous dimensionless impulses prev:
+    with s = y + prev, lambda_n = max(0, s_n) |g| dt / k_n and
+    lambda_t = clip(s_t |g| dt / k_t, -mu lambda_n, mu lambda_n)."""
+    y = y + prev
     gdt = gravity_norm * dt
     ln = np.maximum(0.0, y[..., 0]) * gdt / k[..., 0]
     b = mu * ln

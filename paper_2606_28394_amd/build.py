@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjenga.so")
-SOURCES = ["jenga_step.hip", "jenga_world.hip"]
+SOURCES = ["jenga_step.hip", "jenga_world.hip", "jenga_mlp.hip"]
 ARCH = os.environ.get("JENGA_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -71,6 +71,12 @@ struct StepArgs {
   int32_t* prev_count;         // [pack]
   // cycles spent per phase, summed over packs (kPhases counters)
   unsigned long long* phase_cycles;
+  // learned warm start (warm_start == 2) and per-point feature records
+  const void* mlp;             // packed network (16-byte aligned, jg_mlp_pack layout)
+  float* feat_out;             // [slot][4][30]: features, k, impulses of the last step; or null
+  uint32_t* tower_fallback;    // [tower][2]: fallbacks, fallback points (accumulated per launch)
+  int32_t mlp_iters;
+  float fallback_tau;
   // parameters
   float g[3];
   float dt;                    // substep length
@@ -89,20 +95,27 @@ constexpr int kTowerWords = 13;    // body range, mu, counters4, residual2, cano
 constexpr int kPushWords = 10;
 constexpr int kManWords = 32;      // canonical (code, pos) + sorted (code, meta, n3, depth, r_A 12, lambda 12)
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
+constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
+                                                // and the chunk's previous dimensionless impulses
+constexpr int kFeatRecord = 30;
 
-// LDS words needed by one pack with these capacities.
-inline int64_t lds_words(int nbp, int pc, int tpc, int ppc, int warm) {
+// LDS layout modes: 0 plain; 1 previous-step store (warm start from the previous step, or
+// feature records); 2 learned warm start: the store plus network input staging, saved
+// velocities (6 per body), residual partials (2 per manifold), fallback state (3 per tower).
+inline int64_t lds_words(int nbp, int pc, int tpc, int ppc, int mode) {
   int64_t w = 0;
   w += (int64_t)nbp * kBodyWords;
   w += (int64_t)tpc * kTowerWords;
   w += (int64_t)ppc * kPushWords;
   w += 2 * (kMaxColours + 1) + 16 + kRing + 2 * kPhases;
   w += (int64_t)pc * kManWords;
-  if (warm) w += (int64_t)pc * kWarmWords;
+  if (mode >= 1) w += (int64_t)pc * kWarmWords;
+  if (mode == 2) w += kStageWords + 6 * (int64_t)nbp + 2 * (int64_t)pc + 3 * (int64_t)tpc;
   return w;
 }
 
-void launch_step(const StepArgs& a, size_t lds_bytes, void* stream);
+// queues one launch of the step kernel; returns the hipError_t of the launch (0 = success)
+int launch_step(const StepArgs& a, size_t lds_bytes, void* stream);
 
 // records the message returned by jg_last_error on this thread; returns code
 int32_t set_error(int32_t code, const std::string& msg);

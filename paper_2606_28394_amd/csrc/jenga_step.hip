@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include "jenga_device.h"
+#include "mlp_device.h"
 
 namespace jg {
 namespace {
@@ -67,8 +68,18 @@ struct Lds {
   int32_t* mcanon;
   uint32_t *pkey, *pslot;
   float *pnrm, *plam;
+  // learned warm start: network input rows, pre-solve velocities, residual partials,
+  // per-tower fallback flag and counters (fallbacks, fallback points)
+  uint32_t* xs;
+  float *vsave, *rpart;
+  uint32_t *tfb, *tfc;
   int nbp, pc;
 };
+
+// LDS layout mode of a launch (see lds_words)
+__device__ inline int lds_mode(const StepArgs& a) {
+  return a.warm_start == 2 ? 2 : ((a.warm_start == 1 || a.feat_out) ? 1 : 0);
+}
 
 __device__ inline Lds carve(float* base, const StepArgs& a) {
   Lds L;
@@ -77,7 +88,9 @@ __device__ inline Lds carve(float* base, const StepArgs& a) {
   float* p = base;
   auto take = [&](int n) { float* r = p; p += n; return r; };
   const int nb = a.nbp, pc = a.pc, nt = a.tpc, np = a.ppc;
+  const int mode = lds_mode(a);
   L.cyc = (unsigned long long*)take(2 * kPhases);   // first: 8-byte aligned
+  L.xs = mode == 2 ? (uint32_t*)take(kStageWords) : nullptr;   // 16-byte aligned (80-byte offset)
   L.x = take(3 * nb); L.q = take(4 * nb); L.v = take(3 * nb); L.w = take(3 * nb);
   L.he = take(3 * nb); L.invm = take(nb); L.invI = take(3 * nb);
   L.flag = (uint32_t*)take(nb); L.tw = (int32_t*)take(nb);
@@ -93,13 +106,20 @@ __device__ inline Lds carve(float* base, const StepArgs& a) {
   L.cab = (uint32_t*)take(pc); L.cpos = (int32_t*)take(pc);
   L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc); L.mn = take(3 * pc);
   L.mdepth = take(pc); L.mr = take(12 * pc); L.ml = take(12 * pc);
-  if (a.warm_start) {
+  if (mode >= 1) {
     L.mcanon = (int32_t*)take(pc);
     L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
   } else {
     L.mcanon = nullptr;
     L.pkey = L.pslot = nullptr;
     L.pnrm = L.plam = nullptr;
+  }
+  if (mode == 2) {
+    L.vsave = take(6 * nb); L.rpart = take(2 * pc);
+    L.tfb = (uint32_t*)take(nt); L.tfc = (uint32_t*)take(2 * nt);
+  } else {
+    L.vsave = L.rpart = nullptr;
+    L.tfb = L.tfc = nullptr;
   }
   return L;
 }
@@ -595,6 +615,160 @@ __device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, flo
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// learned warm start: contact features, initial impulses from the network's outputs
+// ------------------------------------------------------------------------------------------------
+// The 24 network inputs of point j of colour-sorted manifold m, before the solve:
+// F (x_B - x_A), q_A^-1 q_B (w >= 0), world normal, depth, mu, previous impulses (ml holds them
+// after the key lookup) in the outputs' units lambda_d k_d / (|g| dt) with this step's k,
+// F r_A, F r_B, F (relative velocity of B with respect to A at the point).  The ground is a
+// body at (x_A, y_A, 0) with the identity orientation.
+__device__ void point_features(const Lds& L, int m, int j, float gdt, float f[mlp::kFeat]) {
+  const int nb = L.nbp, pc = L.pc;
+  const uint32_t ab = L.mab[m];
+  const int ia = (int)(ab >> 16), ib = (int)(ab & 0xffffu);
+  const bool ground = ib == (int)kGround;
+  const float n[3] = {L.mn[m], L.mn[pc + m], L.mn[2 * pc + m]};
+  Frame F;
+  make_frame(n, F);
+  float xa[3], xb[3], d[3], dl[3];
+  load3(L.x, nb, ia, xa);
+  if (ground) { xb[0] = xa[0]; xb[1] = xa[1]; xb[2] = 0.f; }
+  else load3(L.x, nb, ib, xb);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d[k] = xb[k] - xa[k];
+  to_local(F, d, dl);
+  f[0] = dl[0]; f[1] = dl[1]; f[2] = dl[2];
+  const float aw = L.q[ia], ax = -L.q[nb + ia], ay = -L.q[2 * nb + ia], az = -L.q[3 * nb + ia];
+  float bw = 1.f, bx = 0.f, by = 0.f, bz = 0.f;
+  if (!ground) { bw = L.q[ib]; bx = L.q[nb + ib]; by = L.q[2 * nb + ib]; bz = L.q[3 * nb + ib]; }
+  const float rw = aw * bw - ax * bx - ay * by - az * bz;
+  const float rx = aw * bx + ax * bw + ay * bz - az * by;
+  const float ry = aw * by - ax * bz + ay * bw + az * bx;
+  const float rz = aw * bz + ax * by - ay * bx + az * bw;
+  const float sg = rw < 0.f ? -1.f : 1.f;
+  f[3] = sg * rw; f[4] = sg * rx; f[5] = sg * ry; f[6] = sg * rz;
+  f[7] = n[0]; f[8] = n[1]; f[9] = n[2];
+  f[10] = L.mdepth[m];
+  f[11] = L.mu[L.tw[ia]];
+  float rA[3], rB[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    rA[k] = L.mr[(j * 3 + k) * pc + m];
+    rB[k] = rA[k] - dl[k];
+    f[15 + k] = rA[k];
+    f[18 + k] = rB[k];
+  }
+  LBody A, B;
+  load_local(L, ia, F, A);
+  load_local(L, ib, F, B);
+  {
+    // the solver's own rows (rB for the ground only matters through the ground's zero terms)
+    float kk[3];
+    RowTerms<0> t0;
+    RowTerms<1> t1;
+    RowTerms<2> t2;
+    t0.build(A, B, rA, rB);
+    t1.build(A, B, rA, rB);
+    t2.build(A, B, rA, rB);
+    kk[0] = t0.k; kk[1] = t1.k; kk[2] = t2.k;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[12 + k] = L.ml[(j * 3 + k) * pc + m] * kk[k] / gdt;
+  }
+  float ua[3], ub[3];
+  cross3(A.w, rA, ua);
+  cross3(B.w, rB, ub);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[21 + k] = (B.v[k] + ub[k]) - (A.v[k] + ua[k]);
+}
+
+// Initial impulses of manifold m from s = network output + previous dimensionless impulses (held
+// in ml), applied like solver impulses: lambda_n = max(0, s_n) |g| dt / k_n,
+// lambda_t = clip(s_t |g| dt / k_t, +-mu lambda_n).
+__device__ void learned_apply_manifold(const Lds& L, int m, float mu, float gdt) {
+  int a, b;
+  Frame F;
+  LBody A, B;
+  float dAB[3];
+  manifold_open(L, m, a, b, F, A, B, dAB);
+  const int np = (int)(L.mmeta[m] & 15u);
+  for (int j = 0; j < np; ++j) {
+    float rA[3], rB[3], y[3];
+    load_point(L, m, j, dAB, rA, rB, y);
+    RowTerms<0> t0;
+    RowTerms<1> t1;
+    RowTerms<2> t2;
+    t0.build(A, B, rA, rB);
+    t1.build(A, B, rA, rB);
+    t2.build(A, B, rA, rB);
+    const float ln = fmaxf(y[0], 0.f) * gdt / t0.k;
+    const float bound = mu * ln;
+    const float l1 = fminf(fmaxf(y[1] * gdt / t1.k, -bound), bound);
+    const float l2 = fminf(fmaxf(y[2] * gdt / t2.k, -bound), bound);
+    t0.apply(A, B, ln);
+    t1.apply(A, B, l1);
+    t2.apply(A, B, l2);
+    L.ml[(j * 3 + 0) * L.pc + m] = ln;
+    L.ml[(j * 3 + 1) * L.pc + m] = l1;
+    L.ml[(j * 3 + 2) * L.pc + m] = l2;
+  }
+  store_local(L, a, F, A);
+  if (b != (int)kGround) store_local(L, b, F, B);
+}
+
+// k and the solved impulses of manifold m into its points' feature records
+__device__ void record_solution(const Lds& L, int m, float* rec) {
+  int a, b;
+  Frame F;
+  LBody A, B;
+  float dAB[3];
+  manifold_open(L, m, a, b, F, A, B, dAB);
+  const int np = (int)(L.mmeta[m] & 15u);
+  for (int j = 0; j < np; ++j) {
+    float rA[3], rB[3], lam[3];
+    load_point(L, m, j, dAB, rA, rB, lam);
+    RowTerms<0> t0;
+    RowTerms<1> t1;
+    RowTerms<2> t2;
+    t0.build(A, B, rA, rB);
+    t1.build(A, B, rA, rB);
+    t2.build(A, B, rA, rB);
+    float* r = rec + j * kFeatRecord;
+    r[24] = t0.k; r[25] = t1.k; r[26] = t2.k;
+    r[27] = lam[0]; r[28] = lam[1]; r[29] = lam[2];
+  }
+}
+
+// Natural-map residual of each tower (RMS over its rows and max |r|) into tres: partial sums per
+// canonical pair in psum / pmax (which may alias cab / cpos: each entry is read before it is
+// written), then each tower's contiguous canonical range.  With `only`, towers whose flag is
+// clear keep their residual.
+__device__ void tower_residuals(const Lds& L, int nman, int nt, int lane, float* psum, float* pmax,
+                                const uint32_t* only) {
+  for (int p = lane; p < nman; p += kWave) {
+    const int m = L.cpos[p];
+    float sum = 0.f, mx = 0.f;
+    if (m >= 0) {
+      const int t = L.tw[L.mab[m] >> 16];
+      if (!only || only[t]) residual_manifold(L, m, L.mu[t], sum, mx);
+    }
+    psum[p] = sum;
+    pmax[p] = mx;
+  }
+  __syncthreads();
+  for (int t = lane; t < nt; t += kWave) {
+    if (only && !only[t]) continue;
+    float sum = 0.f, mx = 0.f;
+    for (int p = L.tc0[t]; p < L.tc1[t]; ++p) {
+      sum += psum[p];
+      mx = fmaxf(mx, pmax[p]);
+    }
+    const int rows = 3 * L.tpts[t];
+    L.tres[2 * t] = rows ? sqrtf(sum / (float)rows) : 0.f;
+    L.tres[2 * t + 1] = mx;
+  }
+}
+
 // wave-uniform phase timer: adds the cycles since the previous mark to counter k
 struct PhaseTimer {
   unsigned long long last;
@@ -640,9 +814,13 @@ __device__ int narrow_chunk(const Lds& L, int head, int count, int nman, int lan
 // ------------------------------------------------------------------------------------------------
 // the kernel
 // ------------------------------------------------------------------------------------------------
+// kLearned: the variant with contact features (learned warm start, feature records); the plain
+// variant does not carry the network's registers.
+template <bool kLearned>
 __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) float smem[];
   const Lds L = carve(smem, a);
+  const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   const int lane = threadIdx.x;
   const int pk = a.pack_first + blockIdx.x;
   const int gb0 = a.pack_body0[pk], nb = a.pack_body0[pk + 1] - gb0;
@@ -697,9 +875,13 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   }
   if (lane == 0) {
     L.scal[3] = 0;                                   // error bits
-    L.scal[4] = a.warm_start ? a.prev_count[pk] : 0; // previous-step manifolds
+    L.scal[4] = keep_prev ? a.prev_count[pk] : 0;    // previous-step manifolds
   }
-  if (a.warm_start) {
+  if constexpr (kLearned) {
+    if (a.warm_start == 2)
+      for (int t = lane; t < nt; t += kWave) { L.tfc[2 * t] = 0u; L.tfc[2 * t + 1] = 0u; }
+  }
+  if (keep_prev) {
     const int npv = a.prev_count[pk];
     for (int p = lane; p < npv; p += kWave) {
       const int g = slot0 + p;
@@ -1020,7 +1202,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         }
         // warm start: previous step's impulses of the same (pair, slot) if the normal barely turned
         int found = -1;
-        if (a.warm_start && nprev > 0) {
+        if (keep_prev && nprev > 0) {
           int lo = 0, hi = nprev - 1;
           while (lo <= hi) {
             const int mid = (lo + hi) >> 1;
@@ -1053,7 +1235,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         L.mab[sidx] = code;
         L.mmeta[sidx] = (uint32_t)npts | (slots << 12);
         L.mdepth[sidx] = depth;
-        if (a.warm_start) L.mcanon[sidx] = p;
+        if (keep_prev) L.mcanon[sidx] = p;
 #pragma unroll
         for (int k = 0; k < 3; ++k) L.mn[k * PC + sidx] = n[k];
         const int ti = L.tw[i];
@@ -1064,14 +1246,85 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       __syncthreads();
       timer.mark(L, lane, 4);
 
+      // ---- learned warm start: features, network, initial impulses; feature records ----
+      bool learned = false;
+      if constexpr (kLearned) {
+        learned = a.warm_start == 2;
+        const bool rec = a.feat_out != nullptr && last;
+        if (learned)
+          for (int i = lane; i < nb; i += kWave)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              L.vsave[k * NB + i] = L.v[k * NB + i];
+              L.vsave[(3 + k) * NB + i] = L.w[k * NB + i];
+            }
+        if (learned || rec) {
+          const uint4* net = (const uint4*)a.mlp;
+          const float gdt = sqrtf(a.g[0] * a.g[0] + a.g[1] * a.g[1] + a.g[2] * a.g[2]) * dt;
+          // 16 manifolds x 4 point slots per pass: lane = 4 (m - m0) + j
+          for (int m0 = 0; m0 < nkept; m0 += kWave / 4) {
+            const int m = m0 + (lane >> 2), j = lane & 3;
+            const bool valid = m < nkept && j < (int)(L.mmeta[m] & 15u);
+            float f[mlp::kFeat];
+            if (valid) point_features(L, m, j, gdt, f);
+            else
+#pragma unroll
+              for (int k = 0; k < mlp::kFeat; ++k) f[k] = 0.f;
+            if (rec && valid) {
+              float* o = a.feat_out + ((size_t)(slot0 + m) * 4 + j) * kFeatRecord;
+#pragma unroll
+              for (int k = 0; k < mlp::kFeat; ++k) o[k] = f[k];
+            }
+            if (learned) {
+              // the network predicts the change from the previous dimensionless impulses
+              float* prevd = reinterpret_cast<float*>(L.xs + kWave * mlp::kRowWords);
+              mlp::stage_row(net, f, L.xs + lane * mlp::kRowWords);
+#pragma unroll
+              for (int k = 0; k < 3; ++k) prevd[3 * lane + k] = f[12 + k];
+              __syncthreads();
+              mlp::f32x4 y[4];
+              mlp::infer_chunk(net, L.xs, lane, y);
+              if (lane < 16) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                  const int row = 16 * t + lane, mm = m0 + (row >> 2), jj = row & 3;
+                  if (mm < nkept && jj < (int)(L.mmeta[mm] & 15u))
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) L.ml[(jj * 3 + k) * PC + mm] = y[t][k] + prevd[3 * row + k];
+                }
+              }
+              __syncthreads();
+            }
+          }
+          __syncthreads();
+          if (a.warm_start == 0)   // the previous impulses only fed the features
+            for (int m = lane; m < nkept; m += kWave)
+#pragma unroll
+              for (int k = 0; k < 12; ++k) L.ml[k * PC + m] = 0.f;
+          __syncthreads();
+        }
+      }
+
       // ---- 7. warm-start impulses, then PGS sweeps, colour by colour ----
-      if (a.warm_start) {
+      if (a.warm_start == 1) {
         for (int col = 0; col < ncol; ++col) {
           for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) warm_apply_manifold(L, m);
           __syncthreads();
         }
       }
-      for (int it = 0; it < a.iters; ++it) {
+      int sweeps = a.iters;
+      if constexpr (kLearned) {
+        if (learned) {
+          const float gdt = sqrtf(a.g[0] * a.g[0] + a.g[1] * a.g[1] + a.g[2] * a.g[2]) * dt;
+          for (int col = 0; col < ncol; ++col) {
+            for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave)
+              learned_apply_manifold(L, m, L.mu[L.tw[L.mab[m] >> 16]], gdt);
+            __syncthreads();
+          }
+          sweeps = a.mlp_iters;
+        }
+      }
+      for (int it = 0; it < sweeps; ++it) {
         for (int col = 0; col < ncol; ++col) {
           for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
             const float mu = L.mu[L.tw[L.mab[m] >> 16]];
@@ -1081,6 +1334,50 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         }
       }
       timer.mark(L, lane, 5);
+
+      // ---- learned warm start: residual, and the plain solve again for towers above tau ----
+      if constexpr (kLearned) {
+        if (learned) {
+          tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, nullptr);
+          __syncthreads();
+          int any = 0;
+          for (int t = lane; t < nt; t += kWave) {
+            const uint32_t fb = L.tres[2 * t] > a.fallback_tau ? 1u : 0u;
+            L.tfb[t] = fb;
+            any |= (int)fb;
+          }
+          __syncthreads();
+          any = __any(any);   // one wave per workgroup: a wave vote is the workgroup's
+          if (any) {
+            for (int i = lane; i < nb; i += kWave)
+              if (L.tfb[L.tw[i]])
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                  L.v[k * NB + i] = L.vsave[k * NB + i];
+                  L.w[k * NB + i] = L.vsave[(3 + k) * NB + i];
+                }
+            for (int m = lane; m < nkept; m += kWave)
+              if (L.tfb[L.tw[L.mab[m] >> 16]])
+#pragma unroll
+                for (int k = 0; k < 12; ++k) L.ml[k * PC + m] = 0.f;
+            __syncthreads();
+            for (int it = 0; it < a.iters; ++it) {
+              for (int col = 0; col < ncol; ++col) {
+                for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
+                  const int t = L.tw[L.mab[m] >> 16];
+                  if (L.tfb[t]) solve_manifold(L, m, L.mu[t], e);
+                }
+                __syncthreads();
+              }
+            }
+            for (int t = lane; t < nt; t += kWave)
+              if (L.tfb[t]) { L.tfc[2 * t] += 1u; L.tfc[2 * t + 1] += (uint32_t)L.tpts[t]; }
+            tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, L.tfb);
+          }
+          __syncthreads();
+          timer.mark(L, lane, 7);
+        }
+      }
 
       // ---- contacts of the final step; warm-start store ----
       if (last) {
@@ -1102,6 +1399,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           a.out_geo[8 * g + 6] = L.mdepth[m];
           a.out_geo[8 * g + 7] = 0.f;
           const int npts = (int)(L.mmeta[m] & 15u);
+          if constexpr (kLearned) {
+            if (a.feat_out) record_solution(L, m, a.feat_out + (size_t)g * 4 * kFeatRecord);
+          }
           for (int q = 0; q < 4; ++q) {
             float rl[3] = {0.f, 0.f, 0.f}, rw[3];
             if (q < npts)
@@ -1115,7 +1415,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         }
         if (lane == 0) a.out_count[pk] = nkept;
       }
-      if (a.warm_start) {
+      if (keep_prev) {
         // canonical-order store of this step's impulses (dropped pairs keep their key, no points)
         for (int p = lane; p < nman; p += kWave) { L.pkey[p] = L.cab[p]; L.pslot[p] = 0u; }
         __syncthreads();
@@ -1133,26 +1433,12 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       __syncthreads();
       timer.mark(L, lane, 6);
 
-      // ---- 8. residual: partials per canonical pair, then each tower's contiguous range ----
-      for (int p = lane; p < nman; p += kWave) {
-        const int m = L.cpos[p];
-        float sum = 0.f, mx = 0.f;
-        if (m >= 0) residual_manifold(L, m, L.mu[L.tw[L.mab[m] >> 16]], sum, mx);
-        L.cab[p] = __float_as_uint(sum);
-        L.cpos[p] = __float_as_int(mx);
+      // ---- 8. residual (the learned variant took it before the outputs) ----
+      if (!learned) {
+        tower_residuals(L, nman, nt, lane, reinterpret_cast<float*>(L.cab), reinterpret_cast<float*>(L.cpos),
+                        nullptr);
+        timer.mark(L, lane, 7);
       }
-      __syncthreads();
-      for (int t = lane; t < nt; t += kWave) {
-        float sum = 0.f, mx = 0.f;
-        for (int p = L.tc0[t]; p < L.tc1[t]; ++p) {
-          sum += __uint_as_float(L.cab[p]);
-          mx = fmaxf(mx, __int_as_float(L.cpos[p]));
-        }
-        const int rows = 3 * L.tpts[t];
-        L.tres[2 * t] = rows ? sqrtf(sum / (float)rows) : 0.f;
-        L.tres[2 * t + 1] = mx;
-      }
-      timer.mark(L, lane, 7);
 
       // ---- 9. integrate ----
       for (int i = lane; i < nb; i += kWave) {
@@ -1260,7 +1546,14 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) a.push_x0[3 * (gp0 + r) + k] = L.px0[3 * r + k];
   }
-  if (a.warm_start) {
+  if constexpr (kLearned) {
+    if (a.warm_start == 2)
+      for (int t = lane; t < nt; t += kWave) {
+        a.tower_fallback[2 * (gt0 + t)] += L.tfc[2 * t];
+        a.tower_fallback[2 * (gt0 + t) + 1] += L.tfc[2 * t + 1];
+      }
+  }
+  if (keep_prev) {
     const int npv = L.scal[4];
     for (int p = lane; p < npv; p += kWave) {
       const int g = slot0 + p;
@@ -1281,13 +1574,22 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
 
 }  // namespace
 
-void launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
+int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void*)step_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)step_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    if (e != hipSuccess) return (int)e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(step_kernel, dim3(a.n_packs), dim3(kWave), lds_bytes, (hipStream_t)stream, a);
+  if (a.warm_start == 2 || a.feat_out)
+    hipLaunchKernelGGL(step_kernel<true>, dim3(a.n_packs), dim3(kWave), lds_bytes, (hipStream_t)stream, a);
+  else
+    hipLaunchKernelGGL(step_kernel<false>, dim3(a.n_packs), dim3(kWave), lds_bytes, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
 }
 
 }  // namespace jg

@@ -103,8 +103,14 @@ struct jg_world {
   DevBuf<float> d_prev_data;
   DevBuf<int32_t> d_prev_count;
   DevBuf<unsigned long long> d_phase_cycles;
+  // learned warm start and feature records
+  DevBuf<float> d_mlp_params;
+  DevBuf<uint8_t> d_mlp_packed;
+  bool mlp_set = false;
+  DevBuf<float> d_feat;
+  DevBuf<uint32_t> d_tower_fallback;
   // statistics (per tower id)
-  std::vector<int64_t> st_cand, st_man, st_pts, st_ci;
+  std::vector<int64_t> st_cand, st_man, st_pts, st_ci, st_fb;
   std::vector<int32_t> st_col;
   std::vector<uint32_t> st_err;
   std::vector<double> st_rms, st_max;
@@ -172,10 +178,10 @@ int32_t build_layout(jg_world* w) {
   }
   if (max_tower > 4000) return fail(JG_ECAPACITY, "a tower has more bodies than one pack can index");
   const float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 3.5f;
-  const int warm = w->prm.warm_start == 1;
+  const int mode = w->prm.warm_start == 2 ? 2 : ((w->prm.warm_start == 1 || w->prm.record_features) ? 1 : 0);
   auto pc_of = [&](int nb) { return std::max(16, (int)std::ceil(mpb * nb)); };
   auto lds_of = [&](int nb, int towers, int pushes) -> size_t {
-    return (size_t)jg::lds_words(nb, pc_of(nb), std::max(1, towers), std::max(1, pushes), warm) * 4;
+    return (size_t)jg::lds_words(nb, pc_of(nb), std::max(1, towers), std::max(1, pushes), mode) * 4;
   };
   int target = w->prm.pack_bodies;
   if (target <= 0) {
@@ -250,7 +256,7 @@ int32_t build_layout(jg_world* w) {
   // class capacities; every pack of a class gets the class's contact slots
   for (auto& c : w->classes) {
     c.pc = pc_of(c.nbp);
-    c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, warm) * 4;
+    c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
     if (c.lds > 160 * 1024)
       return fail(JG_ECAPACITY, "a launch class needs " + std::to_string(c.lds) + " bytes of LDS (max 163840)");
     for (int k = 0; k < c.count; ++k) w->pack_slot0.push_back(w->pack_slot0.back() + c.pc);
@@ -285,6 +291,9 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(w->d_prev_key.ensure(slots));
   HIP_TRY(w->d_prev_data.ensure(16 * slots));
   HIP_TRY(w->d_prev_count.ensure(np));
+  HIP_TRY(w->d_tower_fallback.ensure(2 * nt));
+  HIP_TRY(hipMemsetAsync(w->d_tower_fallback.p, 0, sizeof(uint32_t) * 2 * nt, w->stream));
+  if (w->prm.record_features) HIP_TRY(w->d_feat.ensure((size_t)4 * jg::kFeatRecord * slots));
   HIP_TRY(hipMemsetAsync(w->d_tower_count.p, 0, sizeof(uint32_t) * 4 * nt, w->stream));
   HIP_TRY(hipMemsetAsync(w->d_tower_res.p, 0, sizeof(float) * 2 * nt, w->stream));
   HIP_TRY(hipMemsetAsync(w->d_pack_error.p, 0, sizeof(uint32_t) * np, w->stream));
@@ -369,6 +378,10 @@ int32_t collect_stats(jg_world* w) {
   std::vector<uint32_t> cnt(4 * T);
   std::vector<float> res(2 * T);
   std::vector<uint32_t> perr(w->n_packs);
+  std::vector<uint32_t> fb(2 * T, 0u);
+  const bool learned = w->prm.warm_start == 2;
+  if (learned)
+    HIP_TRY(hipMemcpy(fb.data(), w->d_tower_fallback.p, sizeof(uint32_t) * 2 * T, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(cnt.data(), w->d_tower_count.p, sizeof(uint32_t) * 4 * T, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(res.data(), w->d_tower_res.p, sizeof(float) * 2 * T, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(perr.data(), w->d_pack_error.p, sizeof(uint32_t) * w->n_packs, hipMemcpyDeviceToHost));
@@ -377,7 +390,9 @@ int32_t collect_stats(jg_world* w) {
     w->st_cand[t] += cnt[4 * s];
     w->st_man[t] += cnt[4 * s + 1];
     w->st_pts[t] += cnt[4 * s + 2];
-    w->st_ci[t] += (int64_t)cnt[4 * s + 2] * w->prm.iters;
+    w->st_ci[t] += (int64_t)cnt[4 * s + 2] * (learned ? w->prm.mlp_iters : w->prm.iters) +
+                   (int64_t)fb[2 * s + 1] * w->prm.iters;
+    w->st_fb[t] += fb[2 * s];
     w->st_col[t] = (int32_t)cnt[4 * s + 3];
     w->st_rms[t] = res[2 * s];
     w->st_max[t] = res[2 * s + 1];
@@ -385,6 +400,7 @@ int32_t collect_stats(jg_world* w) {
   }
   for (int k = 0; k < 4 * T; k += 4) { cnt[k] = cnt[k + 1] = cnt[k + 2] = 0; }
   HIP_TRY(hipMemcpy(w->d_tower_count.p, cnt.data(), sizeof(uint32_t) * 4 * T, hipMemcpyHostToDevice));
+  if (learned) HIP_TRY(hipMemset(w->d_tower_fallback.p, 0, sizeof(uint32_t) * 2 * T));
   w->stats_pending = false;
   return JG_OK;
 }
@@ -409,6 +425,9 @@ void jg_default_params(jg_params* p) {
   p->stream = nullptr;
   p->pack_bodies = 0;
   p->manifolds_per_body = 0.f;
+  p->mlp_iters = 8;
+  p->fallback_tau = 1e30;
+  p->record_features = 0;
 }
 
 const char* jg_last_error(void) { return g_err.c_str(); }
@@ -419,7 +438,8 @@ int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodi
   if (!p) return fail(JG_EINVAL, "null params");
   if (max_towers <= 0 || max_bodies <= 0) return fail(JG_EINVAL, "max_towers and max_bodies must be positive");
   if (p->iters < 0 || p->n_sub < 1 || !(p->dt > 0.0)) return fail(JG_EINVAL, "bad iters, n_sub or dt");
-  if (p->warm_start < 0 || p->warm_start > 1) return fail(JG_EINVAL, "warm_start must be 0 or 1");
+  if (p->warm_start < 0 || p->warm_start > 2) return fail(JG_EINVAL, "warm_start must be 0, 1 or 2");
+  if (p->mlp_iters < 0) return fail(JG_EINVAL, "mlp_iters must not be negative");
   jg_world* w = new (std::nothrow) jg_world();
   if (!w) return fail(JG_ENOMEM, "host allocation failed");
   w->prm = *p;
@@ -463,6 +483,7 @@ int32_t jg_destroy_world(jg_world* w) {
   w->d_out_count.release(); w->d_out_tower.release();
   w->d_prev_key.release(); w->d_prev_data.release(); w->d_prev_count.release();
   w->d_phase_cycles.release();
+  w->d_mlp_params.release(); w->d_mlp_packed.release(); w->d_feat.release(); w->d_tower_fallback.release();
   delete w;
   return JG_OK;
 }
@@ -491,6 +512,7 @@ int32_t jg_add_boxes(jg_world* w, int32_t tower, int32_t n, const double* half_e
     w->tower_bodies.emplace_back();
     w->mu.push_back(0.4);
     w->st_cand.push_back(0); w->st_man.push_back(0); w->st_pts.push_back(0); w->st_ci.push_back(0);
+    w->st_fb.push_back(0);
     w->st_col.push_back(0); w->st_err.push_back(0); w->st_rms.push_back(0.0); w->st_max.push_back(0.0);
   }
   for (int i = 0; i < n; ++i) {
@@ -571,6 +593,7 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
     w->clear_warm = false;
   }
   if (n_steps == 0) return JG_OK;   // host changes are now resident on the device
+  if (w->prm.warm_start == 2 && !w->mlp_set) return fail(JG_ESTATE, "warm_start 2 needs jg_set_mlp first");
   if (w->n_packs == 0) { w->step += n_steps; return JG_OK; }
   jg::StepArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -598,12 +621,17 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.n_steps = n_steps;
   a.warm_start = w->prm.warm_start;
   a.step0 = w->step;
+  a.mlp = w->mlp_set ? (const void*)w->d_mlp_packed.p : nullptr;
+  a.feat_out = w->prm.record_features ? w->d_feat.p : nullptr;
+  a.tower_fallback = w->d_tower_fallback.p;
+  a.mlp_iters = w->prm.mlp_iters;
+  a.fallback_tau = (float)std::min(w->prm.fallback_tau, 3.0e38);
   for (const auto& c : w->classes) {
     a.pack_first = c.first;
     a.n_packs = c.count;
     a.nbp = c.nbp; a.pc = c.pc; a.tpc = c.tpc; a.ppc = c.ppc;
-    jg::launch_step(a, c.lds, w->stream);
-    HIP_TRY(hipGetLastError());
+    if (int e = jg::launch_step(a, c.lds, w->stream))
+      return fail(JG_EDEVICE, std::string("step kernel launch: ") + hipGetErrorString((hipError_t)e));
   }
   w->step += n_steps;
   w->device_newer = true;
@@ -740,9 +768,66 @@ int32_t jg_query_stats(jg_world* w, int32_t tower, jg_stats* out) {
     out->error_word |= w->st_err[t];
     out->residual_rms = std::max(out->residual_rms, w->st_rms[t]);
     out->residual_max = std::max(out->residual_max, w->st_max[t]);
+    out->fallbacks += w->st_fb[t];
   };
   if (tower >= 0) add(tower);
   else for (int t = 0; t < (int)w->tower_bodies.size(); ++t) add(t);
+  return JG_OK;
+}
+
+int32_t jg_query_features(jg_world* w, int32_t tower, float* out, int32_t capacity, int32_t* n_out) {
+  if (int32_t r = check_world(w)) return r;
+  if (!n_out || capacity < 0 || (capacity > 0 && !out)) return fail(JG_EINVAL, "bad output buffer");
+  if (tower < -1 || tower >= (int)w->tower_bodies.size()) return fail(JG_EINVAL, "tower index out of range");
+  if (!w->prm.record_features) return fail(JG_ESTATE, "the world was created without record_features");
+  *n_out = 0;
+  if (w->layout_dirty || w->n_packs == 0) return JG_OK;
+  if (int32_t r = set_device(w)) return r;
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  const int p0 = tower >= 0 ? w->pack_of_tower[tower] : 0;
+  const int p1 = tower >= 0 ? p0 + 1 : w->n_packs;
+  if (p0 < 0) return JG_OK;
+  std::vector<int32_t> cnt(p1 - p0);
+  HIP_TRY(hipMemcpy(cnt.data(), w->d_out_count.p + p0, sizeof(int32_t) * (p1 - p0), hipMemcpyDeviceToHost));
+  const size_t s0 = (size_t)w->pack_slot0[p0], s1 = (size_t)w->pack_slot0[p1];
+  std::vector<uint32_t> meta(s1 - s0);
+  std::vector<int32_t> tw(s1 - s0);
+  std::vector<float> rec((s1 - s0) * 4 * jg::kFeatRecord);
+  HIP_TRY(hipMemcpy(meta.data(), w->d_out_meta.p + s0, sizeof(uint32_t) * (s1 - s0), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(tw.data(), w->d_out_tower.p + s0, sizeof(int32_t) * (s1 - s0), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(rec.data(), w->d_feat.p + s0 * 4 * jg::kFeatRecord, sizeof(float) * rec.size(),
+                    hipMemcpyDeviceToHost));
+  const int local = tower >= 0 ? w->tower_slot[tower] - w->pack_tower0[p0] : -1;
+  int total = 0;
+  for (int pk = p0; pk < p1; ++pk) {
+    const size_t base = (size_t)w->pack_slot0[pk] - s0;
+    for (int m = 0; m < cnt[pk - p0]; ++m) {
+      if (tower >= 0 && tw[base + m] != local) continue;
+      const int npts = (int)(meta[base + m] & 15u);
+      for (int q = 0; q < npts; ++q) {
+        if (total < capacity)
+          std::memcpy(out + (size_t)total * jg::kFeatRecord, &rec[((base + m) * 4 + q) * jg::kFeatRecord],
+                      sizeof(float) * jg::kFeatRecord);
+        ++total;
+      }
+    }
+  }
+  *n_out = total;
+  return JG_OK;
+}
+
+int32_t jg_set_mlp(jg_world* w, const float* params) {
+  if (int32_t r = check_world(w)) return r;
+  if (!params) return fail(JG_EINVAL, "null parameters");
+  if (int32_t r = set_device(w)) return r;
+  size_t bytes = 0;
+  if (int32_t r = jg_mlp_packed_bytes(&bytes)) return r;
+  HIP_TRY(w->d_mlp_params.ensure(JG_MLP_PARAMS));
+  HIP_TRY(w->d_mlp_packed.ensure(bytes));
+  HIP_TRY(hipMemcpyAsync(w->d_mlp_params.p, params, sizeof(float) * JG_MLP_PARAMS, hipMemcpyHostToDevice, w->stream));
+  if (int32_t r = jg_mlp_pack(w->d_mlp_params.p, w->d_mlp_packed.p, w->stream)) return r;
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  w->mlp_set = true;
   return JG_OK;
 }
 

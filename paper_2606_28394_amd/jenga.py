@@ -22,8 +22,11 @@ ERR_CANDIDATES, ERR_MANIFOLDS, ERR_COLOURS, ERR_NAN = 1, 2, 4, 8
 
 EXPORTS = ["jg_default_params", "jg_create_world", "jg_destroy_world", "jg_add_boxes", "jg_set_friction",
            "jg_set_push", "jg_set_active", "jg_step_batch", "jg_query_state", "jg_set_state", "jg_query_active",
-           "jg_query_contacts", "jg_query_stats", "jg_query_phase_cycles", "jg_world_size", "jg_sync",
-           "jg_last_error"]
+           "jg_query_contacts", "jg_query_stats", "jg_query_phase_cycles", "jg_query_features", "jg_set_mlp",
+           "jg_world_size", "jg_sync",
+           "jg_last_error", "jg_mlp_packed_bytes", "jg_mlp_pack", "jg_mlp_forward", "jg_mlp_grad_workspace_bytes",
+           "jg_mlp_grad", "jg_mlp_adamw"]
+MLP_PARAMS, MLP_TRAINABLE, MLP_FEATURES, FEAT_RECORD = 20147, 20099, 24, 30
 PHASES = ["load/store", "forces+frames", "broad+narrow", "colouring", "manifolds", "pgs", "outputs",
           "residual", "integrate", "baumgarte"]
 
@@ -32,7 +35,8 @@ class jg_params(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("dt", C.c_double), ("restitution", C.c_double),
                 ("beta", C.c_double), ("slop", C.c_double), ("margin", C.c_double),
                 ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("pack_bodies", C.c_int32), ("manifolds_per_body", C.c_float)]
+                ("stream", C.c_void_p), ("pack_bodies", C.c_int32), ("manifolds_per_body", C.c_float),
+                ("mlp_iters", C.c_int32), ("fallback_tau", C.c_double), ("record_features", C.c_int32)]
 
 
 class jg_contact(C.Structure):
@@ -45,7 +49,7 @@ class jg_contact(C.Structure):
 class jg_stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("candidates", C.c_int64), ("manifolds", C.c_int64), ("points", C.c_int64),
                 ("contact_iters", C.c_int64), ("colours", C.c_int32), ("error_word", C.c_uint32),
-                ("residual_rms", C.c_double), ("residual_max", C.c_double)]
+                ("residual_rms", C.c_double), ("residual_max", C.c_double), ("fallbacks", C.c_int64)]
 
 
 CONTACT_DTYPE = np.dtype([("tower", np.int32), ("body_a", np.int32), ("body_b", np.int32), ("slot", np.int32),
@@ -86,10 +90,19 @@ def load_library(path: str = LIB_PATH):
     L.jg_query_contacts.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
     L.jg_query_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(jg_stats)]
     L.jg_query_phase_cycles.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_int32]
+    L.jg_query_features.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
+    L.jg_set_mlp.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
     L.jg_world_size.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.jg_sync.argtypes = [C.c_void_p]
     L.jg_last_error.argtypes = []
     L.jg_last_error.restype = C.c_char_p
+    vp, sz = C.c_void_p, C.c_size_t
+    L.jg_mlp_packed_bytes.argtypes = [C.POINTER(sz)]
+    L.jg_mlp_pack.argtypes = [vp, vp, vp]
+    L.jg_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp]
+    L.jg_mlp_grad_workspace_bytes.argtypes = [C.c_int32, C.POINTER(sz)]
+    L.jg_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, sz, vp]
+    L.jg_mlp_adamw.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     for name in EXPORTS:
         if name not in ("jg_default_params", "jg_last_error"):
             getattr(L, name).restype = C.c_int32
@@ -211,6 +224,21 @@ def jg_query_phase_cycles(h) -> dict:
     return dict(zip(PHASES, [int(v) for v in out]))
 
 
+def jg_query_features(h, tower=-1) -> np.ndarray:
+    """Feature records (n x 30: 24 features, k[3], impulses[3]) of the last step, in contact order."""
+    L = load_library()
+    n = C.c_int32(0)
+    _check(L.jg_query_features(h, int(tower), None, 0, C.byref(n)))
+    out = np.zeros((max(1, n.value), FEAT_RECORD), np.float32)
+    _check(L.jg_query_features(h, int(tower), out.ctypes.data_as(C.POINTER(C.c_float)), n.value, C.byref(n)))
+    return out[:n.value]
+
+
+def jg_set_mlp(h, params):
+    p = np.ascontiguousarray(np.asarray(params, np.float32).reshape(MLP_PARAMS))
+    _check(load_library().jg_set_mlp(h, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+
 def jg_world_size(h):
     t = C.c_int32(0); b = C.c_int32(0)
     _check(load_library().jg_world_size(h, C.byref(t), C.byref(b)))
@@ -225,9 +253,94 @@ def jg_last_error() -> str:
     return load_library().jg_last_error().decode()
 
 
+# network entry points: device pointers (ints) and a raw stream handle
+
+def jg_mlp_packed_bytes() -> int:
+    n = C.c_size_t(0)
+    _check(load_library().jg_mlp_packed_bytes(C.byref(n)))
+    return n.value
+
+
+def jg_mlp_pack(params_ptr, packed_ptr, stream=None):
+    _check(load_library().jg_mlp_pack(params_ptr, packed_ptr, stream))
+
+
+def jg_mlp_forward(packed_ptr, feats_ptr, n, y_ptr, stream=None):
+    _check(load_library().jg_mlp_forward(packed_ptr, feats_ptr, int(n), y_ptr, stream))
+
+
+def jg_mlp_grad_workspace_bytes(n) -> int:
+    b = C.c_size_t(0)
+    _check(load_library().jg_mlp_grad_workspace_bytes(int(n), C.byref(b)))
+    return b.value
+
+
+def jg_mlp_grad(params_ptr, packed_ptr, feats_ptr, targets_ptr, n, grad_ptr, loss_ptr, ws_ptr, ws_bytes,
+                stream=None):
+    _check(load_library().jg_mlp_grad(params_ptr, packed_ptr, feats_ptr, targets_ptr, int(n), grad_ptr, loss_ptr,
+                                      ws_ptr, int(ws_bytes), stream))
+
+
+def jg_mlp_adamw(params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, weight_decay, stream=None):
+    _check(load_library().jg_mlp_adamw(params_ptr, grad_ptr, m_ptr, v_ptr, int(step), float(lr), float(beta1),
+                                       float(beta2), float(eps), float(weight_decay), stream))
+
+
 # ------------------------------------------------------------------------------------------------
-# convenience handle
+# convenience handles
 # ------------------------------------------------------------------------------------------------
+
+class Mlp:
+    """Device copies of the warm-start network (torch tensors as memory): FP32 parameters,
+    their packed bfloat16 form, AdamW moments and a gradient workspace."""
+
+    def __init__(self, params, device: str = "cuda"):
+        import torch
+        p = torch.as_tensor(np.asarray(params, np.float32).reshape(MLP_PARAMS))
+        self.torch = torch
+        self.params = p.to(device).contiguous()
+        self.packed = torch.zeros(jg_mlp_packed_bytes(), dtype=torch.uint8, device=device)
+        self.m = torch.zeros(MLP_TRAINABLE, dtype=torch.float32, device=device)
+        self.v = torch.zeros(MLP_TRAINABLE, dtype=torch.float32, device=device)
+        self.grad = torch.zeros(MLP_TRAINABLE, dtype=torch.float32, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.ws = torch.zeros(0, dtype=torch.uint8, device=device)
+        self.step_count = 0
+        self.pack()
+
+    def _stream(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def pack(self):
+        jg_mlp_pack(self.params.data_ptr(), self.packed.data_ptr(), self._stream())
+
+    def forward(self, feats):
+        f = feats.contiguous()
+        y = self.torch.empty((f.shape[0], 3), dtype=self.torch.float32, device=f.device)
+        jg_mlp_forward(self.packed.data_ptr(), f.data_ptr(), f.shape[0], y.data_ptr(), self._stream())
+        return y
+
+    def compute_grad(self, feats, targets):
+        """Gradient (JG_MLP_TRAINABLE) and loss of the mean squared error on one batch."""
+        f, t = feats.contiguous(), targets.contiguous()
+        need = jg_mlp_grad_workspace_bytes(f.shape[0])
+        if self.ws.numel() < need:
+            self.ws = self.torch.zeros(need, dtype=self.torch.uint8, device=f.device)
+        jg_mlp_grad(self.params.data_ptr(), self.packed.data_ptr(), f.data_ptr(), t.data_ptr(), f.shape[0],
+                    self.grad.data_ptr(), self.loss.data_ptr(), self.ws.data_ptr(), self.ws.numel(), self._stream())
+        return self.grad, self.loss
+
+    def adamw(self, lr=3e-4, betas=(0.9, 0.999), eps=1e-8, weight_decay=1e-4):
+        self.step_count += 1
+        jg_mlp_adamw(self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                     self.step_count, lr, betas[0], betas[1], eps, weight_decay, self._stream())
+        self.pack()
+
+    def train_step(self, feats, targets, **opt):
+        _, loss = self.compute_grad(feats, targets)
+        self.adamw(**opt)
+        return loss
+
 
 def current_stream_handle():
     """The raw hipStream_t of torch's current stream (None without a GPU)."""
@@ -244,7 +357,8 @@ class World:
     """A world built from a scene dict (see workloads.py); bodies keep the scene's order."""
 
     def __init__(self, scene: dict, warm_start: int = 0, stream=None, device: int = 0, pack_bodies: int = 0,
-                 manifolds_per_body: float = 0.0, params: dict | None = None):
+                 manifolds_per_body: float = 0.0, params: dict | None = None, mlp=None, mlp_iters: int = 8,
+                 fallback_tau: float = 1e30, record_features: bool = False):
         pr = params or scene["params"]
         p = jg_default_params()
         p.gravity[:] = [float(g) for g in pr["gravity"]]
@@ -260,6 +374,9 @@ class World:
         p.stream = stream if stream is not None else current_stream_handle()
         p.pack_bodies = int(pack_bodies)
         p.manifolds_per_body = float(manifolds_per_body)
+        p.mlp_iters = int(mlp_iters)
+        p.fallback_tau = float(fallback_tau)
+        p.record_features = int(bool(record_features))
         self.params = p
         T = int(scene["n_towers"])
         ptr = np.asarray(scene["tower_ptr"])
@@ -278,6 +395,8 @@ class World:
         for i in range(len(scene["push_body"])):
             jg_set_push(self.h, int(scene["push_body"][i]), scene["push_force"][i], int(scene["push_start"][i]),
                         int(scene["push_steps"][i]), float(scene["push_withdraw"][i]))
+        if mlp is not None:
+            jg_set_mlp(self.h, mlp)
 
     def step(self, n_steps: int = 1):
         jg_step_batch(self.h, n_steps)
@@ -296,6 +415,9 @@ class World:
 
     def stats(self, tower: int = -1) -> jg_stats:
         return jg_query_stats(self.h, tower)
+
+    def features(self, tower: int = -1) -> np.ndarray:
+        return jg_query_features(self.h, tower)
 
     def sync(self):
         jg_sync(self.h)

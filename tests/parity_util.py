@@ -91,3 +91,58 @@ def compare_state(ow, gpos, gquat, gv, gw, idx=None) -> dict:
 def fmt(rep: dict) -> str:
     keys = [k for k in rep if k not in ("ok",)]
     return ", ".join(f"{k}={rep[k] if not isinstance(rep[k], list) else rep[k][:4]}" for k in keys)
+
+
+# ---------------------------------------------------------------------------------------------
+# per-point feature records (24 features, k[3], impulses[3])
+# ---------------------------------------------------------------------------------------------
+
+def oracle_records(ow, t: int) -> dict:
+    """(a, b, slot) -> (record, band) from the oracle's last recorded step of tower t."""
+    recs = ow.features[t]
+    out, o = {}, 0
+    for m in ow.manifolds(t):
+        for i in range(m["npts"]):
+            out[(m["a"], m["b"], int(m["slot"][i]))] = (recs[o], m["band"])
+            o += 1
+    assert o == len(recs)
+    return out
+
+
+def gpu_records(contacts, records, first_body: int) -> dict:
+    assert len(contacts) == len(records)
+    out = {}
+    for c, r in zip(contacts, records):
+        a = int(c["body_a"]) - first_body
+        b = int(c["body_b"])
+        b = -1 if b < 0 else b - first_body
+        out[(a, b, int(c["slot"]))] = np.asarray(r, np.float64)
+    return out
+
+
+def compare_records(om: dict, gm: dict, lam_tol: float = 1e-4) -> dict:
+    """Largest scaled error per record group over the points outside the precision bands.
+    Each group's error is already divided by its tolerance: ok means every value <= 1."""
+    keys = [k for k, (_, band) in om.items() if not band & BAND_MASK]
+    rep = dict(points=len(keys), missing=[k for k in keys if k not in gm])
+    groups = dict(pos=0.0, quat=0.0, normal=0.0, depth=0.0, mu=0.0, prev=0.0, lever=0.0, vel=0.0, k=0.0, lam=0.0)
+    for key in keys:
+        if key not in gm:
+            continue
+        o, g = om[key][0], gm[key]
+        d = np.abs(o - g)
+        groups["pos"] = max(groups["pos"], float((d[0:3] / np.maximum(np.abs(o[0:3]), 0.075)).max() / 1e-5))
+        groups["quat"] = max(groups["quat"], float(d[3:7].max() / 1e-5))
+        groups["normal"] = max(groups["normal"], float(d[7:10].max() / 1e-5))
+        groups["depth"] = max(groups["depth"], float(d[10] / (1e-5 * 0.075)))
+        groups["mu"] = max(groups["mu"], float(d[11] / 1e-7))
+        # previous impulses in the outputs' units lambda k / (|g| dt): the impulse tolerance scaled alike
+        prev_floor = LAM_FLOOR * np.abs(o[24:27]) / G_DT
+        groups["prev"] = max(groups["prev"], float((d[12:15] / np.maximum(np.abs(o[12:15]), prev_floor)).max() / 1e-4))
+        groups["lever"] = max(groups["lever"], float(d[15:21].max() / (1e-5 * 0.075)))
+        groups["vel"] = max(groups["vel"], float((d[21:24] / np.maximum(np.abs(o[21:24]), G_DT)).max() / 1e-4))
+        groups["k"] = max(groups["k"], float((d[24:27] / np.abs(o[24:27])).max() / 1e-5))
+        groups["lam"] = max(groups["lam"], float((d[27:30] / np.maximum(np.abs(o[27:30]), LAM_FLOOR)).max() / lam_tol))
+    rep.update(groups)
+    rep["ok"] = not rep["missing"] and all(v <= 1.0 for v in groups.values())
+    return rep

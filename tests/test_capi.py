@@ -35,12 +35,34 @@ def test_header_declarations_are_exported(lib):
     assert sorted(jenga.EXPORTS) == names
 
 
-def test_struct_sizes_match_header_layout():
+def _c_layout(struct, fields):
+    """sizeof and offsetof as the C compiler lays out the header's struct."""
+    import subprocess
+    import tempfile
+    body = "\n".join(f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields)
+    src = f"""#include <stdio.h>
+#include <stddef.h>
+#include "jenga.h"
+int main(void) {{ printf("%zu\\n", sizeof({struct})); {body} return 0; }}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "t.c"), os.path.join(d, "t")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        vals = [int(v) for v in subprocess.check_output([exe]).split()]
+    return vals[0], dict(zip(fields, vals[1:]))
+
+
+@pytest.mark.parametrize("name", ["jg_params", "jg_contact", "jg_stats"])
+def test_struct_layout_matches_header(name):
     from paper_2606_28394_amd import jenga as J
-    # jg_params: gravity[3] + 5 doubles, 4 int32, a pointer, int32 + float
-    assert ctypes.sizeof(J.jg_params) == 8 * 8 + 4 * 4 + 8 + 4 + 4
-    assert ctypes.sizeof(J.jg_contact) == 6 * 4 + 9 * 4 + 4 * 4
-    assert ctypes.sizeof(J.jg_stats) == 5 * 8 + 2 * 4 + 2 * 8
+    cls = getattr(J, name)
+    fields = [f for f, _ in cls._fields_]
+    size, offs = _c_layout(name, fields)
+    assert ctypes.sizeof(cls) == size
+    for f in fields:
+        assert getattr(cls, f).offset == offs[f], f
 
 
 def test_default_params(lib):

@@ -1,0 +1,60 @@
+"""What the trained warm-start network gains: it is trained here on the GPU (own kernels) on
+converged impulses of removal episodes, then the residual after k sweeps is compared with the
+zero start (and, for context, the previous-step start) on held-out towers."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_28394_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    from paper_2606_28394_amd import jenga as J
+    from paper_2606_28394_amd import warmstart as WS
+    J.load_library()
+    rec = WS.generate(300_000, iters=100, episodes_seed=1, every=10, n_per_mu=4, max_steps=400, log=_say)
+    g = math.sqrt(sum(x * x for x in W.default_params()["gravity"]))
+    tg = WS.targets_of(rec, g, W.default_params()["dt"])
+    params, losses = WS.fit(rec[:, :24].astype(np.float64), tg, epochs=10, batch=4096, lr=1e-3, log=_say)
+    assert losses[-1] < 0.5 * losses[0]
+    return params
+
+
+def _median_residual(sc, steps, **kw):
+    from paper_2606_28394_amd import jenga as J
+    world = J.World(sc, **kw)
+    res = []
+    for _ in range(steps):
+        world.step(1)
+        res.extend(world.stats(t).residual_rms for t in range(sc["n_towers"]))
+    st = world.stats()
+    world.close()
+    res = np.asarray(res)
+    _say(f"  {kw.get('warm_start', 0)}: mean {res.mean():.3e}, zero entries {np.mean(res == 0):.3f}")
+    return float(np.median(res)), st
+
+
+def test_learned_start_beats_zero_start(trained):
+    sc = W.cfg2(seed=0, n_per_mu=4, n_steps=120)
+    k = 4
+    p = dict(sc["params"])
+    p["iters"] = k
+    r_zero, _ = _median_residual(sc, 120, params=p)
+    r_prev, _ = _median_residual(sc, 120, params=p, warm_start=1)
+    r_learn, st = _median_residual(sc, 120, warm_start=2, mlp=trained, mlp_iters=k)
+    p20 = dict(sc["params"])
+    r20, _ = _median_residual(sc, 120, params=p20)
+    _say(f"median tower residual after {k} sweeps: zero {r_zero:.3e}, previous step {r_prev:.3e}, "
+         f"learned {r_learn:.3e}; plain 20 sweeps {r20:.3e}; fallbacks {st.fallbacks}")
+    assert st.fallbacks == 0 and st.error_word == 0
+    assert r_learn < r_zero

@@ -185,11 +185,13 @@ def test_training_reduces_loss():
 
 
 def test_warm_start_mapping():
-    k = np.array([[200.0, 400.0, 500.0], [100.0, 100.0, 100.0]])
-    y = np.array([[2.0, 10.0, -0.5], [-1.0, 3.0, 3.0]])
+    k = np.array([[200.0, 400.0, 500.0], [100.0, 100.0, 100.0], [100.0, 100.0, 100.0]])
+    y = np.array([[2.0, 10.0, -0.5], [-1.0, 3.0, 3.0], [-1.0, 0.5, 0.0]])
+    prev = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [3.0, -0.5, 0.25]])
     g, dt, mu = 9.81, 1 / 240, 0.4
-    lam = M.warm_start(y, k, mu, g, dt)
+    lam = M.warm_start(y, k, prev, mu, g, dt)
     gdt = g * dt
     np.testing.assert_allclose(lam[0], [2 * gdt / 200, mu * 2 * gdt / 200, -0.5 * gdt / 500])
     np.testing.assert_array_equal(lam[1], [0.0, 0.0, 0.0])   # a pulling normal clamps all three
-    np.testing.assert_allclose(M.targets(k, lam, g, dt)[0, 0], 2.0)
+    np.testing.assert_allclose(lam[2], [2 * gdt / 100, 0.0, 0.25 * gdt / 100])   # outputs add to prev
+    np.testing.assert_allclose(M.targets(k, lam, prev, g, dt)[2], [-1.0, 0.5, 0.0], atol=1e-12)
