@@ -1297,10 +1297,13 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             }
           }
           __syncthreads();
-          if (a.warm_start == 0)   // the previous impulses only fed the features
-            for (int m = lane; m < nkept; m += kWave)
+        }
+        if (keep_prev && a.warm_start == 0) {
+          // records without a warm start: the key lookup filled ml only to feed the features
+          // (on every step, so the solve starts from zero whether or not this step records)
+          for (int m = lane; m < nkept; m += kWave)
 #pragma unroll
-              for (int k = 0; k < 12; ++k) L.ml[k * PC + m] = 0.f;
+            for (int k = 0; k < 12; ++k) L.ml[k * PC + m] = 0.f;
           __syncthreads();
         }
       }

@@ -25,11 +25,14 @@ from . import workloads as W
 N_FEAT = 24
 
 
-def targets_of(records: np.ndarray, gravity_norm: float, dt: float) -> np.ndarray:
+def targets_of(records: np.ndarray, gravity_norm: float, dt: float, clip: float | None = 10.0) -> np.ndarray:
     """Network targets from records (n x 30: features, k[3], impulses[3]): the change of the
-    dimensionless impulses lambda_d k_d / (|g| dt) from the previous step's (features 12..14)."""
+    dimensionless impulses lambda_d k_d / (|g| dt) from the previous step's (features 12..14),
+    clipped to +-clip: impact transients, which no warm start can anticipate, would otherwise
+    dominate the squared error."""
     r = records.astype(np.float64)
-    return r[:, 27:30] * r[:, 24:27] / (gravity_norm * dt) - r[:, 12:15]
+    t = r[:, 27:30] * r[:, 24:27] / (gravity_norm * dt) - r[:, 12:15]
+    return t if clip is None else np.clip(t, -clip, clip)
 
 
 def generate(n_records: int, iters: int = 100, episodes_seed: int = 1, every: int = 8, n_per_mu: int = 50,
@@ -103,24 +106,26 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--records", type=float, default=2e6)
     ap.add_argument("--iters", type=int, default=100)
-    ap.add_argument("--epochs", type=int, default=6)
-    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--weight-decay", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--clip", type=float, default=10.0)
     args = ap.parse_args()
     J.load_library()
     t0 = time.time()
     rec = generate(int(args.records), iters=args.iters)
     g = math.sqrt(sum(x * x for x in W.default_params()["gravity"]))
     dt = W.default_params()["dt"]
-    feats, tg = rec[:, :N_FEAT].astype(np.float64), targets_of(rec, g, dt)
+    feats, tg = rec[:, :N_FEAT].astype(np.float64), targets_of(rec, g, dt, args.clip)
     print(f"data: {len(rec)} records in {time.time() - t0:.1f} s", flush=True)
     t0 = time.time()
     params, losses = fit(feats, tg, epochs=args.epochs, batch=args.batch, lr=args.lr,
                          weight_decay=args.weight_decay, seed=args.seed)
     print(f"training: {time.time() - t0:.1f} s, mse {losses[0]:.5f} -> {losses[-1]:.5f}", flush=True)
     np.save(args.out, params.astype(np.float32))
+    print(f"saved {args.out}", flush=True)
 
 
 if __name__ == "__main__":

@@ -93,6 +93,20 @@ def test_feature_records_plain(J, oracle):
     gw.close()
 
 
+@pytest.mark.parametrize("warm", [0, 1])
+def test_feature_records_multi_step_launch(J, oracle, warm):
+    """Records and state after one launch of several steps (the previous impulses carried on
+    chip between steps); without a warm start they only feed the features."""
+    sc = _scene(seed=12)
+    ow = oracle.OracleWorld(sc, warm_start=warm)
+    gw = J.World(sc, record_features=True, warm_start=warm)
+    ow.step(4, record=True)
+    gw.step(4)
+    _check_records(sc, ow, gw, label=f"launch4 warm{warm}")
+    _check_step(sc, ow, gw, label=f"launch4 warm{warm}")
+    gw.close()
+
+
 def test_feature_records_warm_start(J, oracle):
     sc = _scene(seed=2)
     ow, gw = _pair(J, oracle, sc, dict(warm_start=1), dict(warm_start=1), steps=3)
