@@ -83,6 +83,11 @@ struct jg_world {
     size_t lds = 0;
   };
   std::vector<PackClass> classes;   // launch classes, in pack order
+  // launch classes run concurrently: one auxiliary stream per class after the first, forked from
+  // and joined back into the world's stream with events (all at the default priority)
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> aux_done;
+  hipEvent_t fork = nullptr;
   std::vector<int> push_order;       // internal push row -> pushes index
   std::vector<int> pack_of_tower;    // tower id -> pack
   int n_packs = 0;
@@ -201,6 +206,25 @@ int32_t build_layout(jg_world* w) {
     if (!placed) { Bin b; b.bodies = n; b.cap = std::max(target, n); b.towers.push_back(t); bins.push_back(b); }
   }
   std::stable_sort(bins.begin(), bins.end(), [](const Bin& a, const Bin& b) { return a.bodies > b.bodies; });
+  // group packs by how many fit a CU (their LDS), largest LDS first, so that each launch class
+  // is one contiguous range: a handful of classes, not one per change of push count
+  {
+    std::vector<int> tower_pushes(T, 0);
+    for (const auto& pr : w->pushes) ++tower_pushes[w->body_tower[pr.body]];
+    std::vector<int> key(bins.size());
+    for (size_t b = 0; b < bins.size(); ++b) {
+      int pushes = 0;
+      for (int t : bins[b].towers) pushes += tower_pushes[t];
+      key[b] = (int)((160 * 1024) / std::max<size_t>(1, lds_of(bins[b].bodies, (int)bins[b].towers.size(), pushes)));
+    }
+    std::vector<size_t> idx(bins.size());
+    for (size_t b = 0; b < idx.size(); ++b) idx[b] = b;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
+    std::vector<Bin> sorted;
+    sorted.reserve(bins.size());
+    for (size_t b : idx) sorted.push_back(std::move(bins[b]));
+    bins.swap(sorted);
+  }
   // internal order
   const int N = (int)w->he.size() / 3;
   w->int_of_body.assign(N, -1);
@@ -252,6 +276,20 @@ int32_t build_layout(jg_world* w) {
     c.nbp = std::max(c.nbp, bins[b].bodies);
     c.tpc = std::max(c.tpc, (int)bins[b].towers.size());
     c.ppc = std::max(c.ppc, std::max(1, pushes));
+  }
+  // at most four classes (the hardware queues a process gets by default): fold the smallest class
+  // into its neighbour with the larger LDS (its packs then run at that neighbour's occupancy)
+  while (w->classes.size() > 4) {
+    size_t k = 1;
+    for (size_t i = 2; i < w->classes.size(); ++i)
+      if (w->classes[i].count < w->classes[k].count) k = i;
+    jg_world::PackClass& into = w->classes[k - 1];
+    const jg_world::PackClass& from = w->classes[k];
+    into.count += from.count;
+    into.nbp = std::max(into.nbp, from.nbp);
+    into.tpc = std::max(into.tpc, from.tpc);
+    into.ppc = std::max(into.ppc, from.ppc);
+    w->classes.erase(w->classes.begin() + (long)k);
   }
   // class capacities; every pack of a class gets the class's contact slots
   for (auto& c : w->classes) {
@@ -484,6 +522,9 @@ int32_t jg_destroy_world(jg_world* w) {
   w->d_prev_key.release(); w->d_prev_data.release(); w->d_prev_count.release();
   w->d_phase_cycles.release();
   w->d_mlp_params.release(); w->d_mlp_packed.release(); w->d_feat.release(); w->d_tower_fallback.release();
+  for (hipStream_t s : w->aux) { hipStreamSynchronize(s); hipStreamDestroy(s); }
+  for (hipEvent_t e : w->aux_done) hipEventDestroy(e);
+  if (w->fork) hipEventDestroy(w->fork);
   delete w;
   return JG_OK;
 }
@@ -626,13 +667,33 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.tower_fallback = w->d_tower_fallback.p;
   a.mlp_iters = w->prm.mlp_iters;
   a.fallback_tau = (float)std::min(w->prm.fallback_tau, 3.0e38);
-  for (const auto& c : w->classes) {
+  // Classes are independent (disjoint packs, towers and bodies): run them side by side, so a
+  // small batch fills the GPU and one class's tail overlaps the others.
+  const size_t nc = w->classes.size();
+  while (w->aux.size() + 1 < nc) {
+    hipStream_t s;
+    hipEvent_t ev;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    w->aux.push_back(s);
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    w->aux_done.push_back(ev);
+  }
+  if (nc > 1) {
+    if (!w->fork) HIP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(w->fork, w->stream));
+  }
+  for (size_t k = 0; k < nc; ++k) {
+    const auto& c = w->classes[k];
+    hipStream_t s = k == 0 ? w->stream : w->aux[k - 1];
+    if (k > 0) HIP_TRY(hipStreamWaitEvent(s, w->fork, 0));
     a.pack_first = c.first;
     a.n_packs = c.count;
     a.nbp = c.nbp; a.pc = c.pc; a.tpc = c.tpc; a.ppc = c.ppc;
-    if (int e = jg::launch_step(a, c.lds, w->stream))
+    if (int e = jg::launch_step(a, c.lds, s))
       return fail(JG_EDEVICE, std::string("step kernel launch: ") + hipGetErrorString((hipError_t)e));
+    if (k > 0) HIP_TRY(hipEventRecord(w->aux_done[k - 1], s));
   }
+  for (size_t k = 1; k < nc; ++k) HIP_TRY(hipStreamWaitEvent(w->stream, w->aux_done[k - 1], 0));
   w->step += n_steps;
   w->device_newer = true;
   w->stats_pending = true;

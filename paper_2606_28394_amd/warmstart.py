@@ -25,17 +25,20 @@ from . import workloads as W
 N_FEAT = 24
 
 
-def targets_of(records: np.ndarray, gravity_norm: float, dt: float, clip: float | None = 10.0) -> np.ndarray:
+def targets_of(records: np.ndarray, gravity_norm: float, dt: float, clip: float | None = 0.5) -> np.ndarray:
     """Network targets from records (n x 30: features, k[3], impulses[3]): the change of the
     dimensionless impulses lambda_d k_d / (|g| dt) from the previous step's (features 12..14),
-    clipped to +-clip: impact transients, which no warm start can anticipate, would otherwise
-    dominate the squared error."""
+    clipped to +-clip.  Impact transients, which no warm start can anticipate, would otherwise
+    dominate the squared error.  The clip also keeps the network's corrections small: the
+    previous impulses are already a good start, and the corrections are added to every contact.
+    On the removal batch, the median residual after 4 sweeps was lowest at clip 0.5 among
+    10, 2, 1 and 0.5."""
     r = records.astype(np.float64)
     t = r[:, 27:30] * r[:, 24:27] / (gravity_norm * dt) - r[:, 12:15]
     return t if clip is None else np.clip(t, -clip, clip)
 
 
-def generate(n_records: int, iters: int = 100, episodes_seed: int = 1, every: int = 8, n_per_mu: int = 50,
+def generate(n_records: int, iters: int = 100, episodes_seed: int = 1, every: int = 50, n_per_mu: int = 50,
              max_steps: int = 2000, log=print) -> np.ndarray:
     """Records from plain solves at `iters` iterations over removal episodes, one snapshot of
     every tower every `every` steps, until n_records are collected."""
@@ -104,14 +107,14 @@ def fit(features: np.ndarray, targets: np.ndarray, epochs: int = 4, batch: int =
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", required=True)
-    ap.add_argument("--records", type=float, default=2e6)
+    ap.add_argument("--records", type=float, default=3e6)
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--weight-decay", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--clip", type=float, default=10.0)
+    ap.add_argument("--clip", type=float, default=0.5)
     args = ap.parse_args()
     J.load_library()
     t0 = time.time()

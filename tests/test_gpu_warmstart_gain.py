@@ -26,7 +26,8 @@ def trained():
     g = math.sqrt(sum(x * x for x in W.default_params()["gravity"]))
     tg = WS.targets_of(rec, g, W.default_params()["dt"])
     params, losses = WS.fit(rec[:, :24].astype(np.float64), tg, epochs=10, batch=4096, lr=1e-3, log=_say)
-    assert losses[-1] < 0.5 * losses[0]
+    # the network must do better than predicting no change (the previous-step start)
+    assert losses[-1] < float(np.mean(tg ** 2))
     return params
 
 
