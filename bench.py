@@ -174,6 +174,9 @@ def main():
     ap.add_argument("--learned-weights", default=DEFAULT_WEIGHTS,
                     help="trained warm-start network (.npy); the equal-residual leg runs when it exists")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="first copy MB megabytes device to device once (a known-size reference for "
+                         "profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); towers shard across GPUs with no "
@@ -189,6 +192,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     J.load_library()
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 4} bytes read and written once")
+        del src, dst
     log("generating the batch ...")
     t0 = time.perf_counter()
     scene = W.cfg3(0, n_towers=args.towers, n_steps=args.steps)

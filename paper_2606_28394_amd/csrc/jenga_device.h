@@ -10,7 +10,8 @@
 //   contacts    per pack, slots [pack_slot0[p], pack_slot0[p+1]) of the output / warm-start arrays
 // A pack is the unit of one workgroup: its bodies, contacts and colours live in
 // LDS for every step of a launch.  Packs are launched in size classes, each with
-// the LDS its largest pack needs.
+// the LDS its largest pack needs.  An island too large for LDS (more than 256 bodies) is a
+// "global" pack: the same layout lives in a per-pack region of device memory instead.
 #pragma once
 #include <stdint.h>
 
@@ -43,6 +44,8 @@ struct StepArgs {
   const int32_t* pack_tower0;
   const int32_t* pack_push0;
   const int32_t* pack_slot0;
+  const int64_t* pack_goff;    // [pack] word offset of a global pack's region in gmem
+  float* gmem;                 // non-null: this launch's packs keep their state in gmem
   const int32_t* tower_body0;
   const float* tower_mu;
   int32_t pack_first;          // first pack of this launch
@@ -98,6 +101,11 @@ constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step st
 constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
                                                 // and the chunk's previous dimensionless impulses
 constexpr int kFeatRecord = 30;
+
+constexpr int kRegBodies = 256;    // largest pack the LDS path takes (register broadphase windows)
+
+// words of the window bounding boxes a global pack's broadphase keeps (6 per 64 bodies)
+__host__ __device__ inline int64_t window_words(int nbp) { return 6 * (int64_t)((nbp + 63) / 64); }
 
 // LDS layout modes: 0 plain; 1 previous-step store (warm start from the previous step, or
 // feature records); 2 learned warm start: the store plus network input staging, saved

@@ -73,6 +73,7 @@ struct Lds {
   uint32_t* xs;
   float *vsave, *rpart;
   uint32_t *tfb, *tfc;
+  float* wbox;        // global packs: per 64-body window, AABB lo[3], hi[3] (broadphase)
   int nbp, pc;
 };
 
@@ -121,6 +122,7 @@ __device__ inline Lds carve(float* base, const StepArgs& a) {
     L.vsave = L.rpart = nullptr;
     L.tfb = L.tfc = nullptr;
   }
+  L.wbox = a.gmem ? take((int)window_words(nb)) : nullptr;
   return L;
 }
 
@@ -819,7 +821,8 @@ __device__ int narrow_chunk(const Lds& L, int head, int count, int nman, int lan
 template <bool kLearned>
 __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   extern __shared__ __align__(16) float smem[];
-  const Lds L = carve(smem, a);
+  // a global pack keeps the same layout in its region of device memory
+  const Lds L = carve(a.gmem ? a.gmem + a.pack_goff[a.pack_first + blockIdx.x] : smem, a);
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   const int lane = threadIdx.x;
   const int pk = a.pack_first + blockIdx.x;
@@ -957,7 +960,85 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       // body i is broadcast from its window with readlane, so the pair loop touches LDS only
       // to append candidates to the ring.
       int head = 0, tail = 0, nman = 0;
-      {
+      if (nb > kWindows * kWave) {
+        // global packs: bounding boxes of 64-body windows let body i skip the windows it cannot
+        // touch (lane = window), then the surviving windows are tested body by body as above,
+        // in ascending order, so candidates still come out in canonical order
+        const int nwin = (nb + kWave - 1) / kWave;
+        for (int w = lane; w < nwin; w += kWave) {
+          float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+          for (int j = w * kWave; j < min(nb, (w + 1) * kWave); ++j) {
+            if (!(L.flag[j] & kActive)) continue;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              lo[k] = fminf(lo[k], L.x[k * NB + j] - L.hm[k * NB + j]);
+              hi[k] = fmaxf(hi[k], L.x[k * NB + j] + L.hm[k * NB + j]);
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) { L.wbox[6 * w + k] = lo[k]; L.wbox[6 * w + 3 + k] = hi[k]; }
+        }
+        __syncthreads();
+        const float slack = a.margin * 1.01f + 1e-6f;   // a filter: wider than the pair test
+        int cur_t = -1, cand_acc = 0;
+        for (int i = 0; i < nb; ++i) {
+          const uint32_t fi = L.flag[i];
+          if (!(fi & kActive)) continue;
+          const int ti = L.tw[i];
+          float xi[3], hi[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) { xi[k] = L.x[k * NB + i]; hi[k] = L.hm[k * NB + i]; }
+          if (ti != cur_t) {
+            if (lane == 0 && cur_t >= 0 && cand_acc) L.tcnt[cur_t * 4 + 0] += (uint32_t)cand_acc;
+            cur_t = ti;
+            cand_acc = 0;
+          }
+          const bool dyni = (fi & kDynamic) != 0;
+          for (int g0 = i / kWave; g0 < nwin; g0 += kWave) {
+            const int w = g0 + lane;
+            bool near = w < nwin;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+              near = near && xi[k] - hi[k] <= L.wbox[6 * w + 3 + k] + slack &&
+                     xi[k] + hi[k] + slack >= L.wbox[6 * w + k];
+            uint64_t wb = __ballot(near);
+            while (wb) {
+              const int ww = g0 + __ffsll((unsigned long long)wb) - 1;
+              wb &= wb - 1;
+              const int j = ww * kWave + lane;
+              bool hit = j > i && j < nb;
+              if (hit) {
+                const uint32_t fj = L.flag[j];
+                hit = L.tw[j] == ti && (fj & kActive) && (dyni || (fj & kDynamic)) &&
+                      fabsf(xi[0] - L.x[j]) <= hi[0] + L.hm[j] + a.margin &&
+                      fabsf(xi[1] - L.x[NB + j]) <= hi[1] + L.hm[NB + j] + a.margin &&
+                      fabsf(xi[2] - L.x[2 * NB + j]) <= hi[2] + L.hm[2 * NB + j] + a.margin;
+              }
+              const uint64_t bal = __ballot(hit);
+              if (hit) L.ring[(tail + __popcll(bal & lane_lt_mask(lane))) & (kRing - 1)] = ((uint32_t)i << 16) | (uint32_t)j;
+              const int cnt = __popcll(bal);
+              cand_acc += cnt;
+              tail += cnt;
+              if (tail - head >= kWave) {
+                __syncthreads();
+                nman = narrow_chunk(L, head, kWave, nman, lane);
+                head += kWave;
+              }
+            }
+          }
+          if (dyni && (xi[2] - hi[2] <= a.margin)) {
+            if (lane == 0) L.ring[tail & (kRing - 1)] = ((uint32_t)i << 16) | kGround;
+            cand_acc += 1;
+            tail += 1;
+            if (tail - head >= kWave) {
+              __syncthreads();
+              nman = narrow_chunk(L, head, kWave, nman, lane);
+              head += kWave;
+            }
+          }
+        }
+        if (lane == 0 && cur_t >= 0 && cand_acc) L.tcnt[cur_t * 4 + 0] += (uint32_t)cand_acc;
+      } else {
         float wx[kWindows][3], wh[kWindows][3];
         uint32_t wf[kWindows];
         int wt[kWindows];

@@ -81,6 +81,8 @@ struct jg_world {
   struct PackClass {
     int first = 0, count = 0, per_cu = 0, nbp = 1, pc = 16, tpc = 1, ppc = 1;
     size_t lds = 0;
+    bool global = false;     // packs keep their state in device memory (islands too large for LDS)
+    int64_t gwords = 0;      // words of one such pack's region
   };
   std::vector<PackClass> classes;   // launch classes, in pack order
   // launch classes run concurrently: one auxiliary stream per class after the first, forked from
@@ -95,6 +97,8 @@ struct jg_world {
   DevBuf<float> d_x, d_q, d_v, d_w, d_he, d_mass;
   DevBuf<uint32_t> d_flags;
   DevBuf<int32_t> d_body_tower, d_pack_body0, d_pack_tower0, d_pack_push0, d_pack_slot0, d_tower_body0;
+  DevBuf<int64_t> d_pack_goff;
+  DevBuf<float> d_gmem;           // regions of the global packs
   DevBuf<float> d_tower_mu;
   DevBuf<int32_t> d_push_body, d_push_start, d_push_steps;
   DevBuf<float> d_push_force, d_push_withdraw, d_push_x0;
@@ -181,14 +185,14 @@ int32_t build_layout(jg_world* w) {
     if (!w->tower_bodies[t].empty()) order.push_back(t);
     max_tower = std::max(max_tower, (int)w->tower_bodies[t].size());
   }
-  if (max_tower > 4000) return fail(JG_ECAPACITY, "a tower has more bodies than one pack can index");
+  if (max_tower > 65534) return fail(JG_ECAPACITY, "a tower has more bodies than one pack can index (65534)");
   const float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 3.5f;
   const int mode = w->prm.warm_start == 2 ? 2 : ((w->prm.warm_start == 1 || w->prm.record_features) ? 1 : 0);
   auto pc_of = [&](int nb) { return std::max(16, (int)std::ceil(mpb * nb)); };
   auto lds_of = [&](int nb, int towers, int pushes) -> size_t {
     return (size_t)jg::lds_words(nb, pc_of(nb), std::max(1, towers), std::max(1, pushes), mode) * 4;
   };
-  int target = w->prm.pack_bodies;
+  int target = w->prm.pack_bodies > 0 ? w->prm.pack_bodies : 0;
   if (target <= 0) {
     target = 8;
     while (lds_of(target + 1, 4, 8) <= 40 * 1024) ++target;
@@ -196,26 +200,36 @@ int32_t build_layout(jg_world* w) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return w->tower_bodies[a].size() > w->tower_bodies[b].size();
   });
-  struct Bin { int bodies = 0, cap = 0; std::vector<int> towers; };
+  struct Bin { int bodies = 0, cap = 0; std::vector<int> towers; bool global = false; };
   std::vector<Bin> bins;
+  std::vector<int> tower_pushes(T, 0);
+  for (const auto& pr : w->pushes) ++tower_pushes[w->body_tower[pr.body]];
   for (int t : order) {
     const int n = (int)w->tower_bodies[t].size();
+    // an island beyond the LDS path (register broadphase windows, or LDS) is a global pack
+    if (n > jg::kRegBodies || lds_of(n, 1, tower_pushes[t]) > 160 * 1024 || w->prm.pack_bodies < 0) {
+      Bin b;
+      b.bodies = n; b.cap = n; b.towers.push_back(t); b.global = true;
+      bins.push_back(b);
+      continue;
+    }
     bool placed = false;
     for (auto& b : bins)
-      if (b.bodies + n <= b.cap && (int)b.towers.size() < 255) { b.towers.push_back(t); b.bodies += n; placed = true; break; }
+      if (!b.global && b.bodies + n <= b.cap && (int)b.towers.size() < 255) {
+        b.towers.push_back(t); b.bodies += n; placed = true; break;
+      }
     if (!placed) { Bin b; b.bodies = n; b.cap = std::max(target, n); b.towers.push_back(t); bins.push_back(b); }
   }
   std::stable_sort(bins.begin(), bins.end(), [](const Bin& a, const Bin& b) { return a.bodies > b.bodies; });
   // group packs by how many fit a CU (their LDS), largest LDS first, so that each launch class
   // is one contiguous range: a handful of classes, not one per change of push count
   {
-    std::vector<int> tower_pushes(T, 0);
-    for (const auto& pr : w->pushes) ++tower_pushes[w->body_tower[pr.body]];
     std::vector<int> key(bins.size());
     for (size_t b = 0; b < bins.size(); ++b) {
       int pushes = 0;
       for (int t : bins[b].towers) pushes += tower_pushes[t];
-      key[b] = (int)((160 * 1024) / std::max<size_t>(1, lds_of(bins[b].bodies, (int)bins[b].towers.size(), pushes)));
+      key[b] = bins[b].global ? (1 << 30)   // global packs last, one class of their own
+                              : (int)((160 * 1024) / std::max<size_t>(1, lds_of(bins[b].bodies, (int)bins[b].towers.size(), pushes)));
     }
     std::vector<size_t> idx(bins.size());
     for (size_t b = 0; b < idx.size(); ++b) idx[b] = b;
@@ -257,18 +271,17 @@ int32_t build_layout(jg_world* w) {
     w->pack_body0.push_back((int)w->body_of_int.size());
     w->pack_tower0.push_back((int)w->tower_order.size());
     w->pack_push0.push_back((int)w->push_order.size());
-    // launch class: packs that fit the same number of workgroups per CU
+    // launch class: packs that fit the same number of workgroups per CU (global packs: one class)
     const size_t lds = lds_of(bins[b].bodies, (int)bins[b].towers.size(), pushes);
-    const int per_cu = (int)((160 * 1024) / lds);
-    if (bins[b].bodies > 4 * jg::kWave)
-      return fail(JG_ECAPACITY, "a pack of " + std::to_string(bins[b].bodies) + " bodies exceeds 256");
-    if (per_cu == 0)
+    const int per_cu = bins[b].global ? 0 : (int)((160 * 1024) / lds);
+    if (!bins[b].global && per_cu == 0)
       return fail(JG_ECAPACITY, "a pack needs " + std::to_string(lds) + " bytes of LDS (max 163840); "
                                 "use smaller towers or fewer manifolds per body");
-    if (w->classes.empty() || w->classes.back().per_cu != per_cu) {
+    if (w->classes.empty() || w->classes.back().per_cu != per_cu || w->classes.back().global != bins[b].global) {
       jg_world::PackClass c;
       c.first = (int)b;
       c.per_cu = per_cu;
+      c.global = bins[b].global;
       w->classes.push_back(c);
     }
     jg_world::PackClass& c = w->classes.back();
@@ -279,10 +292,15 @@ int32_t build_layout(jg_world* w) {
   }
   // at most four classes (the hardware queues a process gets by default): fold the smallest class
   // into its neighbour with the larger LDS (its packs then run at that neighbour's occupancy)
-  while (w->classes.size() > 4) {
+  auto lds_classes = [&]() {
+    size_t n = 0;
+    for (const auto& c : w->classes) n += c.global ? 0 : 1;
+    return n;
+  };
+  while (lds_classes() > 4) {
     size_t k = 1;
     for (size_t i = 2; i < w->classes.size(); ++i)
-      if (w->classes[i].count < w->classes[k].count) k = i;
+      if (!w->classes[i].global && w->classes[i].count < w->classes[k].count) k = i;
     jg_world::PackClass& into = w->classes[k - 1];
     const jg_world::PackClass& from = w->classes[k];
     into.count += from.count;
@@ -292,11 +310,20 @@ int32_t build_layout(jg_world* w) {
     w->classes.erase(w->classes.begin() + (long)k);
   }
   // class capacities; every pack of a class gets the class's contact slots
+  std::vector<int64_t> goff;
+  int64_t gtotal = 0;
   for (auto& c : w->classes) {
     c.pc = pc_of(c.nbp);
-    c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
-    if (c.lds > 160 * 1024)
-      return fail(JG_ECAPACITY, "a launch class needs " + std::to_string(c.lds) + " bytes of LDS (max 163840)");
+    if (c.global) {
+      c.lds = 0;
+      c.gwords = (jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) + jg::window_words(c.nbp) + 3) & ~(int64_t)3;
+      for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
+    } else {
+      c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
+      if (c.lds > 160 * 1024)
+        return fail(JG_ECAPACITY, "a launch class needs " + std::to_string(c.lds) + " bytes of LDS (max 163840)");
+      for (int k = 0; k < c.count; ++k) goff.push_back(0);
+    }
     for (int k = 0; k < c.count; ++k) w->pack_slot0.push_back(w->pack_slot0.back() + c.pc);
   }
   w->n_packs = (int)bins.size();
@@ -308,6 +335,8 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(w->d_pack_tower0.ensure(np + 1));
   HIP_TRY(w->d_pack_push0.ensure(np + 1));
   HIP_TRY(w->d_pack_slot0.ensure(np + 1));
+  HIP_TRY(w->d_pack_goff.ensure(np));
+  HIP_TRY(w->d_gmem.ensure((size_t)std::max<int64_t>(4, gtotal)));
   HIP_TRY(w->d_tower_body0.ensure(nt + 1));
   HIP_TRY(w->d_tower_mu.ensure(nt));
   HIP_TRY(w->d_tower_count.ensure(4 * nt));
@@ -344,6 +373,8 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(hipMemcpy(w->d_pack_tower0.p, w->pack_tower0.data(), sizeof(int32_t) * w->pack_tower0.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w->d_pack_push0.p, w->pack_push0.data(), sizeof(int32_t) * w->pack_push0.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w->d_pack_slot0.p, w->pack_slot0.data(), sizeof(int32_t) * w->pack_slot0.size(), hipMemcpyHostToDevice));
+  if (!goff.empty())
+    HIP_TRY(hipMemcpy(w->d_pack_goff.p, goff.data(), sizeof(int64_t) * goff.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(w->d_tower_body0.p, tb0.data(), sizeof(int32_t) * (w->tower_order.size() + 1), hipMemcpyHostToDevice));
   std::vector<int32_t> btw(w->max_bodies, 0);
   for (int s = 0; s < (int)w->tower_order.size(); ++s)
@@ -514,6 +545,7 @@ int32_t jg_destroy_world(jg_world* w) {
   w->d_mass.release(); w->d_flags.release(); w->d_body_tower.release();
   w->d_pack_body0.release(); w->d_pack_tower0.release(); w->d_pack_push0.release(); w->d_pack_slot0.release();
   w->d_tower_body0.release();
+  w->d_pack_goff.release(); w->d_gmem.release();
   w->d_tower_mu.release(); w->d_push_body.release(); w->d_push_start.release(); w->d_push_steps.release();
   w->d_push_force.release(); w->d_push_withdraw.release(); w->d_push_x0.release();
   w->d_tower_count.release(); w->d_tower_res.release(); w->d_pack_error.release();
@@ -689,6 +721,8 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
     a.pack_first = c.first;
     a.n_packs = c.count;
     a.nbp = c.nbp; a.pc = c.pc; a.tpc = c.tpc; a.ppc = c.ppc;
+    a.gmem = c.global ? w->d_gmem.p : nullptr;
+    a.pack_goff = w->d_pack_goff.p;
     if (int e = jg::launch_step(a, c.lds, s))
       return fail(JG_EDEVICE, std::string("step kernel launch: ") + hipGetErrorString((hipError_t)e));
     if (k > 0) HIP_TRY(hipEventRecord(w->aux_done[k - 1], s));

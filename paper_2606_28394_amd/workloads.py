@@ -384,3 +384,46 @@ def mlp_init(seed: int = 0, n_feat: int = 24, hidden: int = 128, n_out: int = 3)
 def random_features(n: int, seed: int = 0, n_feat: int = 24) -> np.ndarray:
     """Feature-shaped random rows (standard normal), for network tests."""
     return rng_for(42, seed).standard_normal((n, n_feat))
+
+
+STONE_DENSITY = 2400.0
+
+
+def masonry_wall(courses: int = 64, per_course: int = 64, seed: int = 0, n_steps: int = 3000,
+                 shear: float = 0.5, mu: float = 0.60, params=None) -> dict:
+    """One wall of stones in running bond, as one island (one tower of the scene).
+
+    Stone length ~ LogNormal(ln 0.3, 0.25) [m]; each course draws an aspect a_c ~ U(1, 3) and
+    has height 0.3 / a_c; depth (through the wall) 0.3 m; 1 mm head joints; odd courses start
+    0.15 m further along x (running bond); courses overlap by 0.1 mm so the bed contacts are
+    active from the first step; density 2400 kg/m^3.  The bottom course starts with velocity
+    `shear` m/s along x (an in-plane base shear)."""
+    rng = rng_for(5, seed)
+    depth = 0.3
+    he, m, pos, vel = [], [], [], []
+    z = 0.0
+    for c in range(courses):
+        a_c = rng.uniform(1.0, 3.0)
+        h = 0.3 / a_c
+        lengths = np.exp(rng.normal(math.log(0.3), 0.25, per_course))
+        x = 0.15 if c % 2 else 0.0
+        zc = z + h / 2 - BED_OVERLAP
+        for k in range(per_course):
+            L = float(lengths[k])
+            half = np.array([L / 2, depth / 2, h / 2])
+            he.append(half)
+            m.append(STONE_DENSITY * L * depth * h)
+            pos.append([x + L / 2, 0.0, zc])
+            vel.append([shear if c == 0 else 0.0, 0.0, 0.0])
+            x += L + LAYER_GAP
+        z = zc + h / 2
+    n = len(m)
+    sb = SceneBuilder(params or default_params(), n_steps=n_steps)
+    sb.add_tower(np.array(he), np.array(m), np.array(pos), np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)), mu,
+                 np.array(vel), np.zeros((n, 3)))
+    return sb.build()
+
+
+def cfg5(seed: int = 0, n_steps: int = 3000):
+    """The masonry collapse: one wall of 64 courses x 64 stones (4096 bodies, one island)."""
+    return masonry_wall(64, 64, seed=seed, n_steps=n_steps)

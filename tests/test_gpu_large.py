@@ -1,0 +1,149 @@
+"""Islands too large for one workgroup's LDS (global packs): masonry walls against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_28394_amd import workloads as W
+from parity_util import compare_contacts, compare_state, fmt, gpu_manifolds, impulses_feasible, oracle_manifolds
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def J():
+    from paper_2606_28394_amd import jenga
+    jenga.load_library()
+    return jenga
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare(J, oracle, sc, states, warm_start=0, label=""):
+    """One step from each state.  Impulses are compared on the first step from the scene's
+    initial state; once a wall has settled its contact impulses are statically indeterminate
+    (the per-point split after 20 sweeps moves by about 1e-2 between FP32 and FP64 rounding),
+    so later steps compare pair sets, points, normals and colours exactly, positions at 1e-5,
+    and velocities at 1e-3: the 20-sweep iterates of a settled wall differ by ~3e-4 (relative,
+    floor g dt) between FP32 and FP64, the same on the LDS path (224 stones) as in device memory
+    (288 stones); 60 sweeps bring it to ~2e-4.  Every impulse must be feasible."""
+    ow = oracle.OracleWorld(sc, warm_start=warm_start)
+    gw = J.World(sc, warm_start=warm_start)
+    ptr = sc["tower_ptr"]
+    for si, (x, q, v, w) in enumerate(states):
+        ow.set_state(x, q, v, w)
+        gw.set_state(x, q, v, w)
+        ow.step(1)
+        gw.step(1)
+        assert gw.stats().error_word == 0, f"{label}: device error word {gw.stats().error_word}"
+        for t in range(sc["n_towers"]):
+            a, b = int(ptr[t]), int(ptr[t + 1])
+            gc = gw.contacts(t)
+            rep = compare_contacts(oracle_manifolds(ow, t), gpu_manifolds(gc, a), sc["mass"][a:b],
+                                   impulses=(si == 0))
+            assert rep["ok"], f"{label} tower {t}: {fmt(rep)}"
+            assert impulses_feasible(gc, float(sc["mu"][t])), f"{label} tower {t}: infeasible impulse"
+        st = compare_state(ow, *gw.state(), vtol=1e-4 if si == 0 else 1e-3)
+        _say(label, "pairs", rep["pairs"], "banded", rep["banded"], "lam_err", rep["lam_err"], "state", st)
+        assert st["ok"], f"{label}: {st}"
+    gw.close()
+
+
+def _states(oracle, sc, steps):
+    ow = oracle.OracleWorld(sc)
+    out, done = [], 0
+    for s in steps:
+        if s > done:
+            ow.step(s - done)
+            done = s
+        out.append((ow.x.copy(), ow.q.copy(), ow.v.copy(), ow.w.copy()))
+    return out
+
+
+def test_wall_above_lds_size_parity(J, oracle):
+    """A 12 x 24 wall (288 stones, beyond the 256-body LDS path) along its first shear steps."""
+    sc = W.masonry_wall(12, 24, seed=1)
+    _compare(J, oracle, sc, _states(oracle, sc, [0, 20, 60]), label="wall288")
+
+
+def test_wall_previous_step_warm_start(J, oracle):
+    """Previous-step warm start on a wall: the first step's impulses, then the unique quantities."""
+    sc = W.masonry_wall(10, 32, seed=2, n_steps=3)
+    ow = oracle.OracleWorld(sc, warm_start=1)
+    gw = J.World(sc, warm_start=1)
+    for k in range(3):
+        ow.step(1)
+        gw.step(1)
+        gc = gw.contacts(0)
+        rep = compare_contacts(oracle_manifolds(ow, 0), gpu_manifolds(gc, 0), sc["mass"], impulses=(k == 0))
+        st = compare_state(ow, *gw.state(), vtol=1e-4 if k == 0 else 1e-3)
+        _say("wall warm step", k, st, fmt(rep))
+        assert rep["ok"] and st["ok"] and impulses_feasible(gc, float(sc["mu"][0]))
+    gw.close()
+
+
+def test_wall_multi_step_launch(J):
+    """Several steps in one launch keep the island's state in its device-memory region: the
+    result equals stepping one launch per step, bitwise."""
+    sc = W.masonry_wall(10, 30, seed=3, n_steps=5)
+    one = J.World(sc)
+    many = J.World(sc)
+    one.step(5)
+    for _ in range(5):
+        many.step(1)
+    for a, b in zip(one.state(), many.state()):
+        np.testing.assert_array_equal(a, b)
+    assert one.stats().points == many.stats().points
+    one.close()
+    many.close()
+
+
+def test_wall_with_small_towers(J, oracle):
+    """A global pack next to LDS packs in one world: all classes run side by side."""
+    wall = W.masonry_wall(9, 32, seed=4)
+    towers = W.tilted_towers(34, 6, levels_range=(8, 20))
+    sb = W.SceneBuilder(W.default_params(), 1)
+    for sc in (wall, towers):
+        ptr = sc["tower_ptr"]
+        for t in range(sc["n_towers"]):
+            a, b = int(ptr[t]), int(ptr[t + 1])
+            sb.add_tower(sc["half_extents"][a:b], sc["mass"][a:b], sc["pos"][a:b], sc["quat"][a:b], sc["mu"][t],
+                         sc["linvel"][a:b], sc["angvel"][a:b])
+    sc = sb.build()
+    _compare(J, oracle, sc, _states(oracle, sc, [0, 30]), label="mixed")
+
+
+def test_full_masonry_wall_one_step(J, oracle):
+    """The 64 x 64 wall (4096 stones, one island): one step from rest with the base shear."""
+    sc = W.cfg5(0, n_steps=1)
+    _compare(J, oracle, sc, _states(oracle, sc, [0]), label="cfg5")
+
+
+def test_device_memory_path_equals_lds_path(J):
+    """The same towers stepped with their state in LDS and in device memory: bitwise equal (the
+    code is the same, only where the arrays live differs)."""
+    wall = W.masonry_wall(8, 28, seed=6)            # 224 stones: still on the LDS path by default
+    towers = W.tilted_towers(35, 5, levels_range=(8, 30))
+    sb = W.SceneBuilder(W.default_params(), 1)
+    for sc in (wall, towers):
+        ptr = sc["tower_ptr"]
+        for t in range(sc["n_towers"]):
+            a, b = int(ptr[t]), int(ptr[t + 1])
+            sb.add_tower(sc["half_extents"][a:b], sc["mass"][a:b], sc["pos"][a:b], sc["quat"][a:b], sc["mu"][t],
+                         sc["linvel"][a:b], sc["angvel"][a:b])
+    sc = sb.build()
+    for warm in (0, 1):
+        lds = J.World(sc, warm_start=warm)
+        dev = J.World(sc, warm_start=warm, pack_bodies=-1)
+        lds.step(40)
+        dev.step(40)
+        for a, b in zip(lds.state(), dev.state()):
+            np.testing.assert_array_equal(a, b)
+        for t in range(sc["n_towers"]):
+            ca, cb = lds.contacts(t), dev.contacts(t)
+            assert len(ca) == len(cb) and (ca == cb).all()
+        lds.close()
+        dev.close()
