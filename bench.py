@@ -63,7 +63,9 @@ def traffic_from_profile(khash: str, workload: str):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != khash or rec.get("workload") != workload:
+    # the record is per launch (state loaded once, contacts written at the end), so it holds
+    # for any step count of the same batch; a changed kernel invalidates it
+    if rec.get("kernel_hash") != khash or not workload.startswith(rec.get("workload", "\0")):
         return None
     return rec.get("hbm_bytes_per_launch")
 
