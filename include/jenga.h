@@ -45,7 +45,7 @@ typedef enum {
   JG_EINVAL = -1,      /* bad argument (null pointer, index or size out of range) */
   JG_ENOMEM = -2,      /* device or host allocation failed */
   JG_EDEVICE = -3,     /* a HIP call failed (message in jg_last_error) */
-  JG_ECAPACITY = -4,   /* a tower does not fit the on-chip island capacity */
+  JG_ECAPACITY = -4,   /* a size limit was exceeded (the world's max_bodies, 65534 bodies per tower) */
   JG_ESTATE = -5,      /* call not valid in the world's current state */
   JG_ENAN = -6         /* a tower's state became non-finite */
 } jg_status;

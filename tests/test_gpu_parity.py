@@ -211,14 +211,18 @@ def test_edge_cases(J, oracle):
     with pytest.raises(J.JengaError):
         J.jg_add_boxes(h, 1, [[-1, 1, 1]], [m], [[0, 0, 0]], [[1, 0, 0, 0]])
     J.jg_destroy_world(h)
-    # a pack that cannot fit on chip is refused with JG_ECAPACITY
+    # a 300-body tower does not fit on chip: it is stepped with its state in device memory
     p = J.jg_default_params()
     p.pack_bodies = 600
-    h = J.jg_create_world(p, 2, 1200)
+    h = J.jg_create_world(p, 2, 300)
     he6, m6, pos6, q6, _, _ = W.jenga_tower(100, None)
     J.jg_add_boxes(h, 0, he6, m6, pos6, q6)
+    J.jg_step_batch(h, 2)
+    s = J.jg_query_stats(h)
+    assert s.error_word == 0 and s.steps == 2 and s.points > 0
+    # more bodies than the world was created for are refused with JG_ECAPACITY
     with pytest.raises(J.JengaError) as ei:
-        J.jg_step_batch(h, 1)
+        J.jg_add_boxes(h, 1, [he], [m], [[1, 0, 0.2]], [[1, 0, 0, 0]])
     assert ei.value.code == J.JG_ECAPACITY
     J.jg_destroy_world(h)
 
