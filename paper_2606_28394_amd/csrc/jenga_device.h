@@ -44,8 +44,11 @@ struct StepArgs {
   const int32_t* pack_tower0;
   const int32_t* pack_push0;
   const int32_t* pack_slot0;
-  const int64_t* pack_goff;    // [pack] word offset of a global pack's region in gmem
-  float* gmem;                 // non-null: this launch's packs keep their state in gmem
+  const int64_t* pack_goff;    // [pack] word offset of the pack's region in gmem
+  float* gmem;                 // per-pack regions: the contact points' lever arms and impulses
+                               // (kManDevWords per manifold slot), then, for a pack whose layout
+                               // lives in device memory, the whole layout
+  int32_t in_gmem;             // 1: this launch's packs keep their whole layout in gmem
   const int32_t* tower_body0;
   const float* tower_mu;
   int32_t pack_first;          // first pack of this launch
@@ -96,7 +99,8 @@ struct StepArgs {
 constexpr int kBodyWords = 31;     // x3 q4 v3 w3 he3 invm invI3 flag tower Iw6 aabb/mask3
 constexpr int kTowerWords = 13;    // body range, mu, counters4, residual2, canonical range2, points
 constexpr int kPushWords = 10;
-constexpr int kManWords = 32;      // canonical (code, pos) + sorted (code, meta, n3, depth, r_A 12, lambda 12)
+constexpr int kManWords = 8;       // canonical (code, pos) + sorted (code, meta, n3, depth)
+constexpr int kManDevWords = 24;   // r_A 12, lambda 12 per sorted manifold, in the pack's device region
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
 constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
                                                 // and the chunk's previous dimensionless impulses

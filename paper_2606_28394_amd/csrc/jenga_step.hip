@@ -78,11 +78,13 @@ struct Lds {
 };
 
 // LDS layout mode of a launch (see lds_words)
-__device__ inline int lds_mode(const StepArgs& a) {
+__device__ __forceinline__ int lds_mode(const StepArgs& a) {
   return a.warm_start == 2 ? 2 : ((a.warm_start == 1 || a.feat_out) ? 1 : 0);
 }
 
-__device__ inline Lds carve(float* base, const StepArgs& a) {
+// base: the layout (LDS, or device memory for a pack kept there); dev: the pack's block of
+// lever arms and impulses in device memory
+__device__ __forceinline__ Lds carve(float* base, float* dev, const StepArgs& a) {
   Lds L;
   L.nbp = a.nbp;
   L.pc = a.pc;
@@ -106,7 +108,7 @@ __device__ inline Lds carve(float* base, const StepArgs& a) {
   L.ring = (uint32_t*)take(kRing);
   L.cab = (uint32_t*)take(pc); L.cpos = (int32_t*)take(pc);
   L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc); L.mn = take(3 * pc);
-  L.mdepth = take(pc); L.mr = take(12 * pc); L.ml = take(12 * pc);
+  L.mdepth = take(pc); L.mr = dev; L.ml = dev + 12 * pc;
   if (mode >= 1) {
     L.mcanon = (int32_t*)take(pc);
     L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
@@ -122,42 +124,42 @@ __device__ inline Lds carve(float* base, const StepArgs& a) {
     L.vsave = L.rpart = nullptr;
     L.tfb = L.tfc = nullptr;
   }
-  L.wbox = a.gmem ? take((int)window_words(nb)) : nullptr;
+  L.wbox = a.in_gmem ? take((int)window_words(nb)) : nullptr;
   return L;
 }
 
-__device__ inline float dot3(const float a[3], const float b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
-__device__ inline void cross3(const float a[3], const float b[3], float c[3]) {
+__device__ __forceinline__ float dot3(const float a[3], const float b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ __forceinline__ void cross3(const float a[3], const float b[3], float c[3]) {
   c[0] = a[1] * b[2] - a[2] * b[1];
   c[1] = a[2] * b[0] - a[0] * b[2];
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 // symmetric 3x3 (xx, yy, zz, xy, xz, yz) times vector
-__device__ inline void sym_mul(const float I[6], const float c[3], float o[3]) {
+__device__ __forceinline__ void sym_mul(const float I[6], const float c[3], float o[3]) {
   o[0] = I[0] * c[0] + I[3] * c[1] + I[4] * c[2];
   o[1] = I[3] * c[0] + I[1] * c[1] + I[5] * c[2];
   o[2] = I[4] * c[0] + I[5] * c[1] + I[2] * c[2];
 }
 
 // Eq. (rotmat), row-major
-__device__ inline void quat_rot(float w, float x, float y, float z, float R[9]) {
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float R[9]) {
   R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - z * w);       R[2] = 2.f * (x * z + y * w);
   R[3] = 2.f * (x * y + z * w);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - x * w);
   R[6] = 2.f * (x * z - y * w);       R[7] = 2.f * (y * z + x * w);       R[8] = 1.f - 2.f * (x * x + y * y);
 }
 
-__device__ inline void body_R(const Lds& L, int i, float R[9]) {
+__device__ __forceinline__ void body_R(const Lds& L, int i, float R[9]) {
   const int nb = L.nbp;
   quat_rot(L.q[i], L.q[nb + i], L.q[2 * nb + i], L.q[3 * nb + i], R);
 }
-__device__ inline void load3(const float* a, int stride, int i, float o[3]) {
+__device__ __forceinline__ void load3(const float* a, int stride, int i, float o[3]) {
   o[0] = a[i]; o[1] = a[stride + i]; o[2] = a[2 * stride + i];
 }
-__device__ inline void store3(float* a, int stride, int i, const float o[3]) {
+__device__ __forceinline__ void store3(float* a, int stride, int i, const float o[3]) {
   a[i] = o[0]; a[stride + i] = o[1]; a[2 * stride + i] = o[2];
 }
 
-__device__ inline void tangent_basis(const float n[3], float t1[3], float t2[3]) {
+__device__ __forceinline__ void tangent_basis(const float n[3], float t1[3], float t2[3]) {
   float e[3] = {0.f, 0.f, 0.f};
   if (fabsf(n[0]) < 0.9f) e[0] = 1.f; else e[1] = 1.f;
   const float en = dot3(e, n);
@@ -170,7 +172,7 @@ __device__ inline void tangent_basis(const float n[3], float t1[3], float t2[3])
 // ------------------------------------------------------------------------------------------------
 // narrowphase: 15-axis SAT in coordinates relative to A's centre (d = xB - xA)
 // ------------------------------------------------------------------------------------------------
-__device__ bool sat_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
+__device__ __forceinline__ bool sat_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
                           const float d[3], float n[3], float& depth) {
   float A[3][3], B[3][3];
 #pragma unroll
@@ -215,7 +217,7 @@ __device__ bool sat_boxes(const float RA[9], const float heA[3], const float RB[
 // manifold of a colliding box pair (relative to A's centre)
 // ------------------------------------------------------------------------------------------------
 struct V2 { float x, y; };
-__device__ inline float cr2(V2 a, V2 b) { return a.x * b.y - a.y * b.x; }
+__device__ __forceinline__ float cr2(V2 a, V2 b) { return a.x * b.y - a.y * b.x; }
 
 struct Zono {        // silhouette of a box along n: centre + sum_i s_i g_i, |s_i| <= 1
   V2 c, g[3];
@@ -225,7 +227,7 @@ struct Zono {        // silhouette of a box along n: centre + sum_i s_i g_i, |s_
   bool use[3];
 };
 
-__device__ inline void zono_build(Zono& Z) {
+__device__ __forceinline__ void zono_build(Zono& Z) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     Z.m[k].x = -Z.g[k].y; Z.m[k].y = Z.g[k].x;
@@ -239,7 +241,7 @@ __device__ inline void zono_build(Zono& Z) {
   }
 }
 
-__device__ inline bool zono_inside(const Zono& Z, V2 p) {
+__device__ __forceinline__ bool zono_inside(const Zono& Z, V2 p) {
   const float px = p.x - Z.c.x, py = p.y - Z.c.y;
   bool in = true;
 #pragma unroll
@@ -249,7 +251,7 @@ __device__ inline bool zono_inside(const Zono& Z, V2 p) {
 }
 
 // CCW hexagon (possibly with repeated or collinear vertices) of the zonogon
-__device__ inline void zono_hexagon(const Zono& Z, V2 v[6]) {
+__device__ __forceinline__ void zono_hexagon(const Zono& Z, V2 v[6]) {
   V2 g[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -270,12 +272,12 @@ __device__ inline void zono_hexagon(const Zono& Z, V2 v[6]) {
 struct Extremes {
   float best[4];
   V2 p[4];
-  __device__ inline void init() {
+  __device__ __forceinline__ void init() {
 #pragma unroll
     for (int s = 0; s < 4; ++s) { best[s] = -INFINITY; p[s].x = p[s].y = 0.f; }
   }
   // diagonals (+,+), (-,+), (-,-), (+,-); the first candidate wins ties
-  __device__ inline void consider(V2 q) {
+  __device__ __forceinline__ void consider(V2 q) {
     const float a = q.x + q.y, b = q.y - q.x;
     if (a > best[0]) { best[0] = a; p[0] = q; }
     if (b > best[1]) { best[1] = b; p[1] = q; }
@@ -286,7 +288,7 @@ struct Extremes {
 
 // Points relative to A's centre, in contact-frame coordinates (along n, t1, t2), in slot
 // order; bit s of the result marks slot s as used.
-__device__ uint32_t manifold_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
+__device__ __forceinline__ uint32_t manifold_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
                                    const float d[3], const float n[3], float t1[3], float rA[4][3]) {
   float t2[3];
   tangent_basis(n, t1, t2);
@@ -391,14 +393,14 @@ __device__ uint32_t manifold_boxes(const float RA[9], const float heA[3], const 
 // ------------------------------------------------------------------------------------------------
 struct Frame { float f[3][3]; };   // rows n, t1, t2 (right handed: t2 = n x t1)
 
-__device__ inline void make_frame(const float n[3], Frame& F) {
+__device__ __forceinline__ void make_frame(const float n[3], Frame& F) {
   F.f[0][0] = n[0]; F.f[0][1] = n[1]; F.f[0][2] = n[2];
   tangent_basis(n, F.f[1], F.f[2]);
 }
-__device__ inline void to_local(const Frame& F, const float v[3], float o[3]) {
+__device__ __forceinline__ void to_local(const Frame& F, const float v[3], float o[3]) {
   o[0] = dot3(F.f[0], v); o[1] = dot3(F.f[1], v); o[2] = dot3(F.f[2], v);
 }
-__device__ inline void to_world(const Frame& F, const float o[3], float v[3]) {
+__device__ __forceinline__ void to_world(const Frame& F, const float o[3], float v[3]) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) v[r] = F.f[0][r] * o[0] + F.f[1][r] * o[1] + F.f[2][r] * o[2];
 }
@@ -415,7 +417,7 @@ __device__ constexpr int sym_index(int r, int c) {
   return r == c ? r : ((r + c == 1) ? 3 : ((r + c == 2) ? 4 : 5));
 }
 
-__device__ inline void load_local(const Lds& L, int i, const Frame& F, LBody& b) {
+__device__ __forceinline__ void load_local(const Lds& L, int i, const Frame& F, LBody& b) {
   if (i == (int)kGround || !(L.flag[i] & kDynamic)) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) { b.v[k] = 0.f; b.w[k] = 0.f; b.v0[k] = 0.f; b.w0[k] = 0.f; }
@@ -445,7 +447,7 @@ __device__ inline void load_local(const Lds& L, int i, const Frame& F, LBody& b)
   b.dyn = true;
 }
 
-__device__ inline void store_local(const Lds& L, int i, const Frame& F, const LBody& b) {
+__device__ __forceinline__ void store_local(const Lds& L, int i, const Frame& F, const LBody& b) {
   if (!b.dyn) return;
   float dv[3], dw[3], v[3], w[3], gv[3], gw[3];
 #pragma unroll
@@ -462,7 +464,7 @@ __device__ inline void store_local(const Lds& L, int i, const Frame& F, const LB
 
 // the two non-zero components (at i1 < i2) of a x e_K
 template <int K>
-__device__ inline void axis_cross(const float a[3], float& c1, float& c2) {
+__device__ __forceinline__ void axis_cross(const float a[3], float& c1, float& c2) {
   if constexpr (K == 0) { c1 = a[2]; c2 = -a[1]; }        // (0, a2, -a1)
   else if constexpr (K == 1) { c1 = -a[2]; c2 = a[0]; }   // (-a2, 0, a0)
   else { c1 = a[1]; c2 = -a[0]; }                         // (a1, -a0, 0)
@@ -475,7 +477,7 @@ struct RowTerms {
   float a1, a2, b1, b2;   // r_A x e_K, r_B x e_K
   float iA[3], iB[3];     // I_A^-1 (r_A x e_K), I_B^-1 (r_B x e_K)
   float k;                // inverse effective mass, Eq. (keff)
-  __device__ inline void build(const LBody& A, const LBody& B, const float rA[3], const float rB[3]) {
+  __device__ __forceinline__ void build(const LBody& A, const LBody& B, const float rA[3], const float rB[3]) {
     axis_cross<K>(rA, a1, a2);
     axis_cross<K>(rB, b1, b2);
 #pragma unroll
@@ -485,10 +487,10 @@ struct RowTerms {
     }
     k = A.im + B.im + (a1 * iA[i1] + a2 * iA[i2]) + (b1 * iB[i1] + b2 * iB[i2]);
   }
-  __device__ inline float vrel(const LBody& A, const LBody& B) const {
+  __device__ __forceinline__ float vrel(const LBody& A, const LBody& B) const {
     return (B.v[K] - A.v[K]) + (b1 * B.w[i1] + b2 * B.w[i2]) - (a1 * A.w[i1] + a2 * A.w[i2]);
   }
-  __device__ inline void apply(LBody& A, LBody& B, float dl) const {
+  __device__ __forceinline__ void apply(LBody& A, LBody& B, float dl) const {
     A.v[K] -= A.im * dl;
     B.v[K] += B.im * dl;
 #pragma unroll
@@ -496,7 +498,7 @@ struct RowTerms {
   }
 };
 
-__device__ inline void manifold_open(const Lds& L, int m, int& a, int& b, Frame& F, LBody& A, LBody& B,
+__device__ __forceinline__ void manifold_open(const Lds& L, int m, int& a, int& b, Frame& F, LBody& A, LBody& B,
                                      float dAB[3]) {
   const uint32_t ab = L.mab[m];
   a = (int)(ab >> 16);
@@ -515,7 +517,7 @@ __device__ inline void manifold_open(const Lds& L, int m, int& a, int& b, Frame&
   }
 }
 
-__device__ inline void load_point(const Lds& L, int m, int j, const float dAB[3], float rA[3], float rB[3],
+__device__ __forceinline__ void load_point(const Lds& L, int m, int j, const float dAB[3], float rA[3], float rB[3],
                                   float lam[3]) {
   const int pc = L.pc;
 #pragma unroll
@@ -526,47 +528,100 @@ __device__ inline void load_point(const Lds& L, int m, int j, const float dAB[3]
   }
 }
 
-__device__ void solve_manifold(const Lds& L, int m, float mu, float e) {
-  const int pc = L.pc;
+// one point's rows in order: Eq. (lambda_n), then Eq. (coulomb_pgs) on t1 and t2
+__device__ __forceinline__ void solve_point(LBody& A, LBody& B, const float rA[3], const float rB[3], float lam[3],
+                                            float mu, float e) {
+  {
+    RowTerms<0> t;
+    t.build(A, B, rA, rB);
+    const float nl = fmaxf(lam[0] - (1.f + e) * t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), 0.f);
+    t.apply(A, B, nl - lam[0]);
+    lam[0] = nl;
+  }
+  const float bound = mu * lam[0];
+  {
+    RowTerms<1> t;
+    t.build(A, B, rA, rB);
+    const float nl = fminf(fmaxf(lam[1] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
+    t.apply(A, B, nl - lam[1]);
+    lam[1] = nl;
+  }
+  {
+    RowTerms<2> t;
+    t.build(A, B, rA, rB);
+    const float nl = fminf(fmaxf(lam[2] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
+    t.apply(A, B, nl - lam[2]);
+    lam[2] = nl;
+  }
+}
+
+// lever arms and impulses of a manifold's points, [j * 3 + k]; slots past its points are unused
+struct ManPoints { float r[12], l[12]; };
+
+__device__ __forceinline__ void fetch_points(const Lds& L, int m, ManPoints& d) {
+  const int n3 = 3 * (int)(L.mmeta[m] & 15u);
+#pragma unroll
+  for (int q = 0; q < 12; ++q)
+    if (q < n3) { d.r[q] = L.mr[q * L.pc + m]; d.l[q] = L.ml[q * L.pc + m]; }
+}
+
+// one PGS visit of manifold m with its points already in registers; stores the new impulses
+__device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float mu, float e, ManPoints& d) {
   int a, b;
   Frame F;
   LBody A, B;
   float dAB[3];
   manifold_open(L, m, a, b, F, A, B, dAB);
   const int np = (int)(L.mmeta[m] & 15u);
-  for (int j = 0; j < np; ++j) {
-    float rA[3], rB[3], lam[3];
-    load_point(L, m, j, dAB, rA, rB, lam);
-    {
-      RowTerms<0> t;
-      t.build(A, B, rA, rB);
-      const float nl = fmaxf(lam[0] - (1.f + e) * t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), 0.f);
-      t.apply(A, B, nl - lam[0]);
-      lam[0] = nl;
-    }
-    const float bound = mu * lam[0];
-    {
-      RowTerms<1> t;
-      t.build(A, B, rA, rB);
-      const float nl = fminf(fmaxf(lam[1] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
-      t.apply(A, B, nl - lam[1]);
-      lam[1] = nl;
-    }
-    {
-      RowTerms<2> t;
-      t.build(A, B, rA, rB);
-      const float nl = fminf(fmaxf(lam[2] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
-      t.apply(A, B, nl - lam[2]);
-      lam[2] = nl;
-    }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) L.ml[(j * 3 + k) * pc + m] = lam[k];
+  for (int j = 0; j < 4; ++j) {
+    if (j < np) {
+      const float rA[3] = {d.r[3 * j], d.r[3 * j + 1], d.r[3 * j + 2]};
+      const float rB[3] = {rA[0] + dAB[0], rA[1] + dAB[1], rA[2] + dAB[2]};
+      solve_point(A, B, rA, rB, &d.l[3 * j], mu, e);
+    }
   }
   store_local(L, a, F, A);
   if (b != (int)kGround) store_local(L, b, F, B);
+#pragma unroll
+  for (int q = 0; q < 12; ++q)
+    if (q < 3 * np) L.ml[q * L.pc + m] = d.l[q];
 }
 
-__device__ void warm_apply_manifold(const Lds& L, int m) {
+__device__ __forceinline__ void solve_manifold(const Lds& L, int m, float mu, float e) {
+  ManPoints d;
+  fetch_points(L, m, d);
+  solve_manifold_pts(L, m, mu, e, d);
+}
+
+// `sweeps` PGS sweeps over the colours.  A lane visits the same manifolds in the same order on
+// every sweep (colour by colour, m = coloff[col] + lane + 64 k), so the points of its next
+// manifold are fetched from device memory while it solves the current one.  A lane with a
+// single manifold keeps its points in registers.
+__device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, int lane, float e) {
+  int first = 0;   // the lane's first colour with a manifold (ncol: none)
+  while (first < ncol && L.coloff[first] + lane >= L.coloff[first + 1]) ++first;
+  ManPoints cur, nxt;
+  if (first < ncol) fetch_points(L, L.coloff[first] + lane, cur);
+  for (int it = 0; it < sweeps; ++it) {
+    for (int col = 0; col < ncol; ++col) {
+      for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
+        int n2 = m + kWave, c2 = col;
+        while (n2 >= L.coloff[c2 + 1]) {
+          if (++c2 == ncol) { c2 = first; n2 = L.coloff[first] + lane; break; }
+          n2 = L.coloff[c2] + lane;
+        }
+        const bool other = n2 != m;
+        if (other) fetch_points(L, n2, nxt);
+        solve_manifold_pts(L, m, L.mu[L.tw[L.mab[m] >> 16]], e, cur);
+        if (other) cur = nxt;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ void warm_apply_manifold(const Lds& L, int m) {
   int a, b;
   Frame F;
   LBody A, B;
@@ -585,7 +640,7 @@ __device__ void warm_apply_manifold(const Lds& L, int m) {
 }
 
 // natural-map residual of one manifold: sum of squares and max |r| over its rows
-__device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, float& mx) {
+__device__ __forceinline__ void residual_manifold(const Lds& L, int m, float mu, float& sum, float& mx) {
   int a, b;
   Frame F;
   LBody A, B;
@@ -625,7 +680,7 @@ __device__ void residual_manifold(const Lds& L, int m, float mu, float& sum, flo
 // after the key lookup) in the outputs' units lambda_d k_d / (|g| dt) with this step's k,
 // F r_A, F r_B, F (relative velocity of B with respect to A at the point).  The ground is a
 // body at (x_A, y_A, 0) with the identity orientation.
-__device__ void point_features(const Lds& L, int m, int j, float gdt, float f[mlp::kFeat]) {
+__device__ __forceinline__ void point_features(const Lds& L, int m, int j, float gdt, float f[mlp::kFeat]) {
   const int nb = L.nbp, pc = L.pc;
   const uint32_t ab = L.mab[m];
   const int ia = (int)(ab >> 16), ib = (int)(ab & 0xffffu);
@@ -687,7 +742,7 @@ __device__ void point_features(const Lds& L, int m, int j, float gdt, float f[ml
 // Initial impulses of manifold m from s = network output + previous dimensionless impulses (held
 // in ml), applied like solver impulses: lambda_n = max(0, s_n) |g| dt / k_n,
 // lambda_t = clip(s_t |g| dt / k_t, +-mu lambda_n).
-__device__ void learned_apply_manifold(const Lds& L, int m, float mu, float gdt) {
+__device__ __forceinline__ void learned_apply_manifold(const Lds& L, int m, float mu, float gdt) {
   int a, b;
   Frame F;
   LBody A, B;
@@ -719,7 +774,7 @@ __device__ void learned_apply_manifold(const Lds& L, int m, float mu, float gdt)
 }
 
 // k and the solved impulses of manifold m into its points' feature records
-__device__ void record_solution(const Lds& L, int m, float* rec) {
+__device__ __forceinline__ void record_solution(const Lds& L, int m, float* rec) {
   int a, b;
   Frame F;
   LBody A, B;
@@ -745,7 +800,7 @@ __device__ void record_solution(const Lds& L, int m, float* rec) {
 // canonical pair in psum / pmax (which may alias cab / cpos: each entry is read before it is
 // written), then each tower's contiguous canonical range.  With `only`, towers whose flag is
 // clear keep their residual.
-__device__ void tower_residuals(const Lds& L, int nman, int nt, int lane, float* psum, float* pmax,
+__device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, int lane, float* psum, float* pmax,
                                 const uint32_t* only) {
   for (int p = lane; p < nman; p += kWave) {
     const int m = L.cpos[p];
@@ -774,18 +829,18 @@ __device__ void tower_residuals(const Lds& L, int nman, int nt, int lane, float*
 // wave-uniform phase timer: adds the cycles since the previous mark to counter k
 struct PhaseTimer {
   unsigned long long last;
-  __device__ inline void mark(const Lds& L, int lane, int k) {
+  __device__ __forceinline__ void mark(const Lds& L, int lane, int k) {
     const unsigned long long t = (unsigned long long)clock64();
     if (lane == 0) L.cyc[k] += t - last;
     last = t;
   }
 };
 
-__device__ inline uint64_t lane_lt_mask(int lane) { return lane ? ((~0ull) >> (64 - lane)) : 0ull; }
+__device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane ? ((~0ull) >> (64 - lane)) : 0ull; }
 
 // SAT on up to 64 ring entries starting at `head`; colliding pairs are appended (in order)
 // to the canonical list.  Returns the new list length.
-__device__ int narrow_chunk(const Lds& L, int head, int count, int nman, int lane) {
+__device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, int nman, int lane) {
   const int NB = L.nbp;
   bool hit = false;
   uint32_t code = 0;
@@ -818,11 +873,13 @@ __device__ int narrow_chunk(const Lds& L, int head, int count, int nman, int lan
 // ------------------------------------------------------------------------------------------------
 // kLearned: the variant with contact features (learned warm start, feature records); the plain
 // variant does not carry the network's registers.
-template <bool kLearned>
+// kGlobal: the pack's layout lives in its region of device memory instead of LDS.  The two are
+// separate instantiations so that the LDS variant's accesses compile to LDS instructions.
+template <bool kLearned, bool kGlobal>
 __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   extern __shared__ __align__(16) float smem[];
-  // a global pack keeps the same layout in its region of device memory
-  const Lds L = carve(a.gmem ? a.gmem + a.pack_goff[a.pack_first + blockIdx.x] : smem, a);
+  float* const dev = a.gmem + a.pack_goff[a.pack_first + blockIdx.x];
+  const Lds L = carve(kGlobal ? dev + kManDevWords * a.pc : smem, dev, a);
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   const int lane = threadIdx.x;
   const int pk = a.pack_first + blockIdx.x;
@@ -1408,15 +1465,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           sweeps = a.mlp_iters;
         }
       }
-      for (int it = 0; it < sweeps; ++it) {
-        for (int col = 0; col < ncol; ++col) {
-          for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
-            const float mu = L.mu[L.tw[L.mab[m] >> 16]];
-            solve_manifold(L, m, mu, e);
-          }
-          __syncthreads();
-        }
-      }
+      pgs_sweeps(L, sweeps, ncol, lane, e);
       timer.mark(L, lane, 5);
 
       // ---- learned warm start: residual, and the plain solve again for towers above tau ----
@@ -1661,18 +1710,22 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
 int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)step_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)step_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    if (e != hipSuccess) return (int)e;
+    const void* lds_variants[2] = {(const void*)step_kernel<false, false>, (const void*)step_kernel<true, false>};
+    for (const void* f : lds_variants)
+      if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
+        return (int)e;
     attr_set = true;
   }
-  if (a.warm_start == 2 || a.feat_out)
-    hipLaunchKernelGGL(step_kernel<true>, dim3(a.n_packs), dim3(kWave), lds_bytes, (hipStream_t)stream, a);
-  else
-    hipLaunchKernelGGL(step_kernel<false>, dim3(a.n_packs), dim3(kWave), lds_bytes, (hipStream_t)stream, a);
+  const bool learned = a.warm_start == 2 || a.feat_out;
+  const dim3 grid(a.n_packs), block(kWave);
+  hipStream_t s = (hipStream_t)stream;
+  if (a.in_gmem) {
+    if (learned) hipLaunchKernelGGL((step_kernel<true, true>), grid, block, lds_bytes, s, a);
+    else hipLaunchKernelGGL((step_kernel<false, true>), grid, block, lds_bytes, s, a);
+  } else {
+    if (learned) hipLaunchKernelGGL((step_kernel<true, false>), grid, block, lds_bytes, s, a);
+    else hipLaunchKernelGGL((step_kernel<false, false>), grid, block, lds_bytes, s, a);
+  }
   return (int)hipGetLastError();
 }
 

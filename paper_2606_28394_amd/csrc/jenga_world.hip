@@ -82,7 +82,7 @@ struct jg_world {
     int first = 0, count = 0, per_cu = 0, nbp = 1, pc = 16, tpc = 1, ppc = 1;
     size_t lds = 0;
     bool global = false;     // packs keep their state in device memory (islands too large for LDS)
-    int64_t gwords = 0;      // words of one such pack's region
+    int64_t gwords = 0;      // words of one pack's device region
   };
   std::vector<PackClass> classes;   // launch classes, in pack order
   // launch classes run concurrently: one auxiliary stream per class after the first, forked from
@@ -98,7 +98,7 @@ struct jg_world {
   DevBuf<uint32_t> d_flags;
   DevBuf<int32_t> d_body_tower, d_pack_body0, d_pack_tower0, d_pack_push0, d_pack_slot0, d_tower_body0;
   DevBuf<int64_t> d_pack_goff;
-  DevBuf<float> d_gmem;           // regions of the global packs
+  DevBuf<float> d_gmem;           // per-pack device regions (lever arms, impulses; global packs: all)
   DevBuf<float> d_tower_mu;
   DevBuf<int32_t> d_push_body, d_push_start, d_push_steps;
   DevBuf<float> d_push_force, d_push_withdraw, d_push_x0;
@@ -316,13 +316,15 @@ int32_t build_layout(jg_world* w) {
     c.pc = pc_of(c.nbp);
     if (c.global) {
       c.lds = 0;
-      c.gwords = (jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) + jg::window_words(c.nbp) + 3) & ~(int64_t)3;
+      c.gwords = ((int64_t)jg::kManDevWords * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
+                  jg::window_words(c.nbp) + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
     } else {
       c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
       if (c.lds > 160 * 1024)
         return fail(JG_ECAPACITY, "a launch class needs " + std::to_string(c.lds) + " bytes of LDS (max 163840)");
-      for (int k = 0; k < c.count; ++k) goff.push_back(0);
+      c.gwords = ((int64_t)jg::kManDevWords * c.pc + 3) & ~(int64_t)3;
+      for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
     }
     for (int k = 0; k < c.count; ++k) w->pack_slot0.push_back(w->pack_slot0.back() + c.pc);
   }
@@ -721,7 +723,8 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
     a.pack_first = c.first;
     a.n_packs = c.count;
     a.nbp = c.nbp; a.pc = c.pc; a.tpc = c.tpc; a.ppc = c.ppc;
-    a.gmem = c.global ? w->d_gmem.p : nullptr;
+    a.gmem = w->d_gmem.p;
+    a.in_gmem = c.global ? 1 : 0;
     a.pack_goff = w->d_pack_goff.p;
     if (int e = jg::launch_step(a, c.lds, s))
       return fail(JG_EDEVICE, std::string("step kernel launch: ") + hipGetErrorString((hipError_t)e));
