@@ -174,8 +174,9 @@ int32_t download_state(jg_world* w) {
 }
 
 // Pack towers into workgroups (first fit, largest first).  A pack holds whole towers and at
-// most `target` bodies, where `target` is the largest pack whose LDS fits four workgroups on a
-// CU; a tower larger than that gets a pack of its own.  Packs are then grouped into launch
+// most `target` bodies, where `target` is the largest pack whose LDS fits eight workgroups on a
+// CU (two waves per SIMD, as many as the step kernel's registers allow); a tower larger than
+// that gets a pack of its own.  Packs are then grouped into launch
 // classes of equal workgroups-per-CU, each launched with the LDS its largest pack needs.
 int32_t build_layout(jg_world* w) {
   const int T = (int)w->tower_bodies.size();
@@ -195,7 +196,7 @@ int32_t build_layout(jg_world* w) {
   int target = w->prm.pack_bodies > 0 ? w->prm.pack_bodies : 0;
   if (target <= 0) {
     target = 8;
-    while (lds_of(target + 1, 4, 8) <= 40 * 1024) ++target;
+    while (lds_of(target + 1, 4, 8) <= 20 * 1024) ++target;
   }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return w->tower_bodies[a].size() > w->tower_bodies[b].size();
