@@ -99,8 +99,9 @@ struct StepArgs {
 constexpr int kBodyWords = 31;     // x3 q4 v3 w3 he3 invm invI3 flag tower Iw6 aabb/mask3
 constexpr int kTowerWords = 13;    // body range, mu, counters4, residual2, canonical range2, points
 constexpr int kPushWords = 10;
-constexpr int kManWords = 8;       // canonical (code, pos) + sorted (code, meta, n3, depth)
-constexpr int kManDevWords = 24;   // r_A 12, lambda 12 per sorted manifold, in the pack's device region
+constexpr int kManWords = 4;       // canonical (code, pos) + sorted (code, meta)
+constexpr int kManDevWords = 28;   // r_A 12, lambda 12, n 3, depth per sorted manifold, in the
+                                   // pack's device region
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
 constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
                                                 // and the chunk's previous dimensionless impulses

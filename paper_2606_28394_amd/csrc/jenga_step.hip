@@ -107,8 +107,8 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, const StepArgs& a)
   L.scal = (int32_t*)take(16);
   L.ring = (uint32_t*)take(kRing);
   L.cab = (uint32_t*)take(pc); L.cpos = (int32_t*)take(pc);
-  L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc); L.mn = take(3 * pc);
-  L.mdepth = take(pc); L.mr = dev; L.ml = dev + 12 * pc;
+  L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc);
+  L.mr = dev; L.ml = dev + 12 * pc; L.mn = dev + 24 * pc; L.mdepth = dev + 27 * pc;
   if (mode >= 1) {
     L.mcanon = (int32_t*)take(pc);
     L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
@@ -498,12 +498,10 @@ struct RowTerms {
   }
 };
 
-__device__ __forceinline__ void manifold_open(const Lds& L, int m, int& a, int& b, Frame& F, LBody& A, LBody& B,
-                                     float dAB[3]) {
-  const uint32_t ab = L.mab[m];
+__device__ __forceinline__ void manifold_open(const Lds& L, uint32_t ab, const float n[3], int& a, int& b, Frame& F,
+                                              LBody& A, LBody& B, float dAB[3]) {
   a = (int)(ab >> 16);
   b = (int)(ab & 0xffffu);
-  const float n[3] = {L.mn[m], L.mn[L.pc + m], L.mn[2 * L.pc + m]};
   make_frame(n, F);
   load_local(L, a, F, A);
   load_local(L, b, F, B);
@@ -515,6 +513,12 @@ __device__ __forceinline__ void manifold_open(const Lds& L, int m, int& a, int& 
   } else {
     dAB[0] = dAB[1] = dAB[2] = 0.f;
   }
+}
+
+__device__ __forceinline__ void manifold_open(const Lds& L, int m, int& a, int& b, Frame& F, LBody& A, LBody& B,
+                                              float dAB[3]) {
+  const float n[3] = {L.mn[m], L.mn[L.pc + m], L.mn[2 * L.pc + m]};
+  manifold_open(L, L.mab[m], n, a, b, F, A, B, dAB);
 }
 
 __device__ __forceinline__ void load_point(const Lds& L, int m, int j, const float dAB[3], float rA[3], float rB[3],
@@ -555,43 +559,53 @@ __device__ __forceinline__ void solve_point(LBody& A, LBody& B, const float rA[3
   }
 }
 
-// lever arms and impulses of a manifold's points, [j * 3 + k]; slots past its points are unused
-struct ManPoints { float r[12], l[12]; };
+// what one PGS visit of a manifold reads besides the bodies: its pair, point count, friction
+// coefficient and normal, and its points' lever arms and impulses, [j * 3 + k] (slots past its
+// points are unused)
+struct ManPoints {
+  float r[12], l[12], n[3], mu;
+  uint32_t ab;
+  int np;
+};
 
 __device__ __forceinline__ void fetch_points(const Lds& L, int m, ManPoints& d) {
-  const int n3 = 3 * (int)(L.mmeta[m] & 15u);
+  d.ab = L.mab[m];
+  d.np = (int)(L.mmeta[m] & 15u);
+  d.mu = L.mu[L.tw[d.ab >> 16]];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d.n[k] = L.mn[k * L.pc + m];
+  const int n3 = 3 * d.np;
 #pragma unroll
   for (int q = 0; q < 12; ++q)
     if (q < n3) { d.r[q] = L.mr[q * L.pc + m]; d.l[q] = L.ml[q * L.pc + m]; }
 }
 
-// one PGS visit of manifold m with its points already in registers; stores the new impulses
-__device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float mu, float e, ManPoints& d) {
+// one PGS visit of manifold m with its data already in registers; stores the new impulses
+__device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float e, ManPoints& d) {
   int a, b;
   Frame F;
   LBody A, B;
   float dAB[3];
-  manifold_open(L, m, a, b, F, A, B, dAB);
-  const int np = (int)(L.mmeta[m] & 15u);
+  manifold_open(L, d.ab, d.n, a, b, F, A, B, dAB);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (j < np) {
+    if (j < d.np) {
       const float rA[3] = {d.r[3 * j], d.r[3 * j + 1], d.r[3 * j + 2]};
       const float rB[3] = {rA[0] + dAB[0], rA[1] + dAB[1], rA[2] + dAB[2]};
-      solve_point(A, B, rA, rB, &d.l[3 * j], mu, e);
+      solve_point(A, B, rA, rB, &d.l[3 * j], d.mu, e);
     }
   }
   store_local(L, a, F, A);
   if (b != (int)kGround) store_local(L, b, F, B);
 #pragma unroll
   for (int q = 0; q < 12; ++q)
-    if (q < 3 * np) L.ml[q * L.pc + m] = d.l[q];
+    if (q < 3 * d.np) L.ml[q * L.pc + m] = d.l[q];
 }
 
-__device__ __forceinline__ void solve_manifold(const Lds& L, int m, float mu, float e) {
+__device__ __forceinline__ void solve_manifold(const Lds& L, int m, float e) {
   ManPoints d;
   fetch_points(L, m, d);
-  solve_manifold_pts(L, m, mu, e, d);
+  solve_manifold_pts(L, m, e, d);
 }
 
 // `sweeps` PGS sweeps over the colours.  A lane visits the same manifolds in the same order on
@@ -613,7 +627,7 @@ __device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, i
         }
         const bool other = n2 != m;
         if (other) fetch_points(L, n2, nxt);
-        solve_manifold_pts(L, m, L.mu[L.tw[L.mab[m] >> 16]], e, cur);
+        solve_manifold_pts(L, m, e, cur);
         if (other) cur = nxt;
       }
       __syncthreads();
@@ -1498,7 +1512,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
               for (int col = 0; col < ncol; ++col) {
                 for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
                   const int t = L.tw[L.mab[m] >> 16];
-                  if (L.tfb[t]) solve_manifold(L, m, L.mu[t], e);
+                  if (L.tfb[t]) solve_manifold(L, m, e);
                 }
                 __syncthreads();
               }
