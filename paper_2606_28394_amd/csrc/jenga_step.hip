@@ -62,8 +62,8 @@ struct Lds {
   int32_t* cpos;
   // colour-sorted manifolds
   uint32_t *mab, *mmeta;
-  float *mn, *mdepth;
-  float *mr, *ml;     // [(j*3 + k) * pc + m]; mr holds r_A in the contact frame (n, t1, t2)
+  float* md;          // device block, kManDevWords per sorted manifold: r_A [12] (contact frame
+                      // (n, t1, t2)), lambda [12], n [3], depth (see mdev)
   // warm start: sorted -> canonical, previous step store (canonical order)
   int32_t* mcanon;
   uint32_t *pkey, *pslot;
@@ -76,6 +76,9 @@ struct Lds {
   float* wbox;        // global packs: per 64-body window, AABB lo[3], hi[3] (broadphase)
   int nbp, pc;
 };
+
+// the device-block record of sorted manifold m (16-byte aligned: kManDevWords is a multiple of 4)
+__device__ __forceinline__ float* mdev(const Lds& L, int m) { return L.md + (size_t)m * kManDevWords; }
 
 // LDS layout mode of a launch (see lds_words)
 __device__ __forceinline__ int lds_mode(const StepArgs& a) {
@@ -108,7 +111,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, const StepArgs& a)
   L.ring = (uint32_t*)take(kRing);
   L.cab = (uint32_t*)take(pc); L.cpos = (int32_t*)take(pc);
   L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc);
-  L.mr = dev; L.ml = dev + 12 * pc; L.mn = dev + 24 * pc; L.mdepth = dev + 27 * pc;
+  L.md = dev;
   if (mode >= 1) {
     L.mcanon = (int32_t*)take(pc);
     L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
@@ -164,7 +167,7 @@ __device__ __forceinline__ void tangent_basis(const float n[3], float t1[3], flo
   if (fabsf(n[0]) < 0.9f) e[0] = 1.f; else e[1] = 1.f;
   const float en = dot3(e, n);
   float t[3] = {e[0] - en * n[0], e[1] - en * n[1], e[2] - en * n[2]};
-  const float il = rsqrtf(dot3(t, t));
+  const float il = __builtin_amdgcn_rsqf(dot3(t, t));   // |t|^2 >= 0.19: no denormal scaling
   t1[0] = t[0] * il; t1[1] = t[1] * il; t1[2] = t[2] * il;
   cross3(n, t1, t2);
 }
@@ -417,22 +420,27 @@ __device__ constexpr int sym_index(int r, int c) {
   return r == c ? r : ((r + c == 1) ? 3 : ((r + c == 2) ? 4 : 5));
 }
 
+// A body without mass holds zero velocity, inverse mass and inverse inertia in the pack (its
+// stored velocity is left as given), so it needs no case of its own; the ground (i = kGround,
+// only ever the second body of a pair) reads slot 0 and takes zeros.
+template <bool kMayBeGround>
 __device__ __forceinline__ void load_local(const Lds& L, int i, const Frame& F, LBody& b) {
-  if (i == (int)kGround || !(L.flag[i] & kDynamic)) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) { b.v[k] = 0.f; b.w[k] = 0.f; b.v0[k] = 0.f; b.w0[k] = 0.f; }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) b.I[k] = 0.f;
-    b.im = 0.f;
-    b.dyn = false;
-    return;
-  }
   const int nb = L.nbp;
+  const bool ground = kMayBeGround && i == (int)kGround;
+  const int j = ground ? 0 : i;
   float v[3], w[3], Iw[6];
-  load3(L.v, nb, i, v);
-  load3(L.w, nb, i, w);
+  load3(L.v, nb, j, v);
+  load3(L.w, nb, j, w);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) Iw[k] = L.Iw[k * nb + i];
+  for (int k = 0; k < 6; ++k) Iw[k] = L.Iw[k * nb + j];
+  float im = L.invm[j];
+  if (ground) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { v[k] = 0.f; w[k] = 0.f; }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Iw[k] = 0.f;
+    im = 0.f;
+  }
   to_local(F, v, b.v);
   to_local(F, w, b.w);
 #pragma unroll
@@ -443,8 +451,8 @@ __device__ __forceinline__ void load_local(const Lds& L, int i, const Frame& F, 
   for (int j = 0; j < 3; ++j) sym_mul(Iw, F.f[j], g[j]);
   b.I[0] = dot3(F.f[0], g[0]); b.I[1] = dot3(F.f[1], g[1]); b.I[2] = dot3(F.f[2], g[2]);
   b.I[3] = dot3(F.f[0], g[1]); b.I[4] = dot3(F.f[0], g[2]); b.I[5] = dot3(F.f[1], g[2]);
-  b.im = L.invm[i];
-  b.dyn = true;
+  b.im = im;
+  b.dyn = im > 0.f;
 }
 
 __device__ __forceinline__ void store_local(const Lds& L, int i, const Frame& F, const LBody& b) {
@@ -503,8 +511,8 @@ __device__ __forceinline__ void manifold_open(const Lds& L, uint32_t ab, const f
   a = (int)(ab >> 16);
   b = (int)(ab & 0xffffu);
   make_frame(n, F);
-  load_local(L, a, F, A);
-  load_local(L, b, F, B);
+  load_local<false>(L, a, F, A);
+  load_local<true>(L, b, F, B);
   if (b != (int)kGround) {
     float d[3];
 #pragma unroll
@@ -517,7 +525,7 @@ __device__ __forceinline__ void manifold_open(const Lds& L, uint32_t ab, const f
 
 __device__ __forceinline__ void manifold_open(const Lds& L, int m, int& a, int& b, Frame& F, LBody& A, LBody& B,
                                               float dAB[3]) {
-  const float n[3] = {L.mn[m], L.mn[L.pc + m], L.mn[2 * L.pc + m]};
+  const float n[3] = {mdev(L, m)[24], mdev(L, m)[25], mdev(L, m)[26]};
   manifold_open(L, L.mab[m], n, a, b, F, A, B, dAB);
 }
 
@@ -526,9 +534,9 @@ __device__ __forceinline__ void load_point(const Lds& L, int m, int j, const flo
   const int pc = L.pc;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    rA[k] = L.mr[(j * 3 + k) * pc + m];
+    rA[k] = mdev(L, m)[j * 3 + k];
     rB[k] = rA[k] + dAB[k];
-    lam[k] = L.ml[(j * 3 + k) * pc + m];
+    lam[k] = mdev(L, m)[12 + j * 3 + k];
   }
 }
 
@@ -572,12 +580,16 @@ __device__ __forceinline__ void fetch_points(const Lds& L, int m, ManPoints& d) 
   d.ab = L.mab[m];
   d.np = (int)(L.mmeta[m] & 15u);
   d.mu = L.mu[L.tw[d.ab >> 16]];
+  // the whole record in seven 16-byte loads (slots past the manifold's points come along unused)
+  const float4* rec = reinterpret_cast<const float4*>(mdev(L, m));
 #pragma unroll
-  for (int k = 0; k < 3; ++k) d.n[k] = L.mn[k * L.pc + m];
-  const int n3 = 3 * d.np;
-#pragma unroll
-  for (int q = 0; q < 12; ++q)
-    if (q < n3) { d.r[q] = L.mr[q * L.pc + m]; d.l[q] = L.ml[q * L.pc + m]; }
+  for (int c = 0; c < 3; ++c) {
+    const float4 r = rec[c], l = rec[3 + c];
+    d.r[4 * c] = r.x; d.r[4 * c + 1] = r.y; d.r[4 * c + 2] = r.z; d.r[4 * c + 3] = r.w;
+    d.l[4 * c] = l.x; d.l[4 * c + 1] = l.y; d.l[4 * c + 2] = l.z; d.l[4 * c + 3] = l.w;
+  }
+  const float4 nd = rec[6];
+  d.n[0] = nd.x; d.n[1] = nd.y; d.n[2] = nd.z;
 }
 
 // one PGS visit of manifold m with its data already in registers; stores the new impulses
@@ -597,9 +609,9 @@ __device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float e,
   }
   store_local(L, a, F, A);
   if (b != (int)kGround) store_local(L, b, F, B);
+  float4* rec = reinterpret_cast<float4*>(mdev(L, m));
 #pragma unroll
-  for (int q = 0; q < 12; ++q)
-    if (q < 3 * d.np) L.ml[q * L.pc + m] = d.l[q];
+  for (int c = 0; c < 3; ++c) rec[3 + c] = make_float4(d.l[4 * c], d.l[4 * c + 1], d.l[4 * c + 2], d.l[4 * c + 3]);
 }
 
 __device__ __forceinline__ void solve_manifold(const Lds& L, int m, float e) {
@@ -699,7 +711,7 @@ __device__ __forceinline__ void point_features(const Lds& L, int m, int j, float
   const uint32_t ab = L.mab[m];
   const int ia = (int)(ab >> 16), ib = (int)(ab & 0xffffu);
   const bool ground = ib == (int)kGround;
-  const float n[3] = {L.mn[m], L.mn[pc + m], L.mn[2 * pc + m]};
+  const float n[3] = {mdev(L, m)[24], mdev(L, m)[25], mdev(L, m)[26]};
   Frame F;
   make_frame(n, F);
   float xa[3], xb[3], d[3], dl[3];
@@ -720,19 +732,19 @@ __device__ __forceinline__ void point_features(const Lds& L, int m, int j, float
   const float sg = rw < 0.f ? -1.f : 1.f;
   f[3] = sg * rw; f[4] = sg * rx; f[5] = sg * ry; f[6] = sg * rz;
   f[7] = n[0]; f[8] = n[1]; f[9] = n[2];
-  f[10] = L.mdepth[m];
+  f[10] = mdev(L, m)[27];
   f[11] = L.mu[L.tw[ia]];
   float rA[3], rB[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    rA[k] = L.mr[(j * 3 + k) * pc + m];
+    rA[k] = mdev(L, m)[j * 3 + k];
     rB[k] = rA[k] - dl[k];
     f[15 + k] = rA[k];
     f[18 + k] = rB[k];
   }
   LBody A, B;
-  load_local(L, ia, F, A);
-  load_local(L, ib, F, B);
+  load_local<false>(L, ia, F, A);
+  load_local<true>(L, ib, F, B);
   {
     // the solver's own rows (rB for the ground only matters through the ground's zero terms)
     float kk[3];
@@ -744,7 +756,7 @@ __device__ __forceinline__ void point_features(const Lds& L, int m, int j, float
     t2.build(A, B, rA, rB);
     kk[0] = t0.k; kk[1] = t1.k; kk[2] = t2.k;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f[12 + k] = L.ml[(j * 3 + k) * pc + m] * kk[k] / gdt;
+    for (int k = 0; k < 3; ++k) f[12 + k] = mdev(L, m)[12 + j * 3 + k] * kk[k] / gdt;
   }
   float ua[3], ub[3];
   cross3(A.w, rA, ua);
@@ -779,9 +791,9 @@ __device__ __forceinline__ void learned_apply_manifold(const Lds& L, int m, floa
     t0.apply(A, B, ln);
     t1.apply(A, B, l1);
     t2.apply(A, B, l2);
-    L.ml[(j * 3 + 0) * L.pc + m] = ln;
-    L.ml[(j * 3 + 1) * L.pc + m] = l1;
-    L.ml[(j * 3 + 2) * L.pc + m] = l2;
+    mdev(L, m)[12 + j * 3 + 0] = ln;
+    mdev(L, m)[12 + j * 3 + 1] = l1;
+    mdev(L, m)[12 + j * 3 + 2] = l2;
   }
   store_local(L, a, F, A);
   if (b != (int)kGround) store_local(L, b, F, B);
@@ -928,6 +940,10 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
     L.invI[2 * NB + i] = dyn ? 1.f / (m / 12.f * (l * l + wd * wd)) : 0.f;
     L.flag[i] = a.flags[g];
     L.tw[i] = a.body_tower[g] - gt0;
+    if (!dyn) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { L.v[k * NB + i] = 0.f; L.w[k * NB + i] = 0.f; }
+    }
   }
   for (int t = lane; t < nt; t += kWave) {
     L.tb0[t] = a.tower_body0[gt0 + t] - gb0;
@@ -1325,9 +1341,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
               const float ry = R[3] * s0 + R[4] * s1 + R[5] * s2;
               const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
               // r_A = (rx, ry, (rz - xz)/2) in the frame n = -z, t1 = x, t2 = -y
-              L.mr[(npts * 3 + 0) * PC + sidx] = 0.5f * (xz - rz);
-              L.mr[(npts * 3 + 1) * PC + sidx] = rx;
-              L.mr[(npts * 3 + 2) * PC + sidx] = -ry;
+              mdev(L, sidx)[npts * 3 + 0] = 0.5f * (xz - rz);
+              mdev(L, sidx)[npts * 3 + 1] = rx;
+              mdev(L, sidx)[npts * 3 + 2] = -ry;
               slots |= (uint32_t)k << (4 * npts);
               depth = fmaxf(depth, -vz[k]);
               ++npts;
@@ -1347,7 +1363,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           for (int s2 = 0; s2 < 4; ++s2)
             if ((used >> s2) & 1u) {
 #pragma unroll
-              for (int k = 0; k < 3; ++k) L.mr[(npts * 3 + k) * PC + sidx] = rA[s2][k];
+              for (int k = 0; k < 3; ++k) mdev(L, sidx)[npts * 3 + k] = rA[s2][k];
               slots |= (uint32_t)s2 << (4 * npts);
               ++npts;
             }
@@ -1380,16 +1396,16 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
                 l2 = L.plam[(r * 3 + 2) * PC + found];
               }
           }
-          L.ml[(q * 3 + 0) * PC + sidx] = l0;
-          L.ml[(q * 3 + 1) * PC + sidx] = l1;
-          L.ml[(q * 3 + 2) * PC + sidx] = l2;
+          mdev(L, sidx)[12 + q * 3 + 0] = l0;
+          mdev(L, sidx)[12 + q * 3 + 1] = l1;
+          mdev(L, sidx)[12 + q * 3 + 2] = l2;
         }
         L.mab[sidx] = code;
         L.mmeta[sidx] = (uint32_t)npts | (slots << 12);
-        L.mdepth[sidx] = depth;
+        mdev(L, sidx)[27] = depth;
         if (keep_prev) L.mcanon[sidx] = p;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) L.mn[k * PC + sidx] = n[k];
+        for (int k = 0; k < 3; ++k) mdev(L, sidx)[24 + k] = n[k];
         const int ti = L.tw[i];
         atomicAdd(&L.tcnt[ti * 4 + 1], 1u);
         atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
@@ -1442,7 +1458,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
                   const int row = 16 * t + lane, mm = m0 + (row >> 2), jj = row & 3;
                   if (mm < nkept && jj < (int)(L.mmeta[mm] & 15u))
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) L.ml[(jj * 3 + k) * PC + mm] = y[t][k] + prevd[3 * row + k];
+                    for (int k = 0; k < 3; ++k) mdev(L, mm)[12 + jj * 3 + k] = y[t][k] + prevd[3 * row + k];
                 }
               }
               __syncthreads();
@@ -1455,7 +1471,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           // (on every step, so the solve starts from zero whether or not this step records)
           for (int m = lane; m < nkept; m += kWave)
 #pragma unroll
-            for (int k = 0; k < 12; ++k) L.ml[k * PC + m] = 0.f;
+            for (int k = 0; k < 12; ++k) mdev(L, m)[12 + k] = 0.f;
           __syncthreads();
         }
       }
@@ -1506,7 +1522,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             for (int m = lane; m < nkept; m += kWave)
               if (L.tfb[L.tw[L.mab[m] >> 16]])
 #pragma unroll
-                for (int k = 0; k < 12; ++k) L.ml[k * PC + m] = 0.f;
+                for (int k = 0; k < 12; ++k) mdev(L, m)[12 + k] = 0.f;
             __syncthreads();
             for (int it = 0; it < a.iters; ++it) {
               for (int col = 0; col < ncol; ++col) {
@@ -1536,14 +1552,14 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           a.out_ab[g] = L.mab[m];
           a.out_meta[g] = (L.mmeta[m] & 0x0ffff00fu) | ((uint32_t)col << 4);
           a.out_tower[g] = L.tw[a_];
-          const float nn[3] = {L.mn[m], L.mn[PC + m], L.mn[2 * PC + m]};
+          const float nn[3] = {mdev(L, m)[24], mdev(L, m)[25], mdev(L, m)[26]};
           Frame F;
           make_frame(nn, F);
           for (int k = 0; k < 3; ++k) {
             a.out_geo[8 * g + k] = nn[k];
             a.out_geo[8 * g + 3 + k] = F.f[1][k];
           }
-          a.out_geo[8 * g + 6] = L.mdepth[m];
+          a.out_geo[8 * g + 6] = mdev(L, m)[27];
           a.out_geo[8 * g + 7] = 0.f;
           const int npts = (int)(L.mmeta[m] & 15u);
           if constexpr (kLearned) {
@@ -1552,11 +1568,11 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           for (int q = 0; q < 4; ++q) {
             float rl[3] = {0.f, 0.f, 0.f}, rw[3];
             if (q < npts)
-              for (int k = 0; k < 3; ++k) rl[k] = L.mr[(q * 3 + k) * PC + m];
+              for (int k = 0; k < 3; ++k) rl[k] = mdev(L, m)[q * 3 + k];
             to_world(F, rl, rw);
             for (int k = 0; k < 3; ++k) {
               a.out_pts[24 * g + 6 * q + k] = L.x[k * NB + a_] + rw[k];
-              a.out_pts[24 * g + 6 * q + 3 + k] = q < npts ? L.ml[(q * 3 + k) * PC + m] : 0.f;
+              a.out_pts[24 * g + 6 * q + 3 + k] = q < npts ? mdev(L, m)[12 + q * 3 + k] : 0.f;
             }
           }
         }
@@ -1572,8 +1588,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           const int npts = (int)(meta & 15u);
           L.pslot[p] = (uint32_t)npts | (((meta >> 12) & 0xffffu) << 4);
 #pragma unroll
-          for (int k = 0; k < 3; ++k) L.pnrm[k * PC + p] = L.mn[k * PC + m];
-          for (int k = 0; k < 12; ++k) L.plam[k * PC + p] = L.ml[k * PC + m];
+          for (int k = 0; k < 3; ++k) L.pnrm[k * PC + p] = mdev(L, m)[24 + k];
+          for (int k = 0; k < 12; ++k) L.plam[k * PC + p] = mdev(L, m)[12 + k];
         }
         if (lane == 0) L.scal[4] = nman;
       }
@@ -1638,12 +1654,12 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           const bool di = (L.flag[i] & kDynamic) != 0;
           const bool dj = j != (int)kGround && (L.flag[j] & kDynamic);
           const float ia = di ? L.invm[i] : 0.f, ib = dj ? L.invm[j] : 0.f;
-          float corr = L.mdepth[m] - a.slop;
+          float corr = mdev(L, m)[27] - a.slop;
           if (ia + ib <= 0.f || corr <= 0.f) continue;
           corr /= (ia + ib);
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            const float nk = L.mn[k * PC + m];
+            const float nk = mdev(L, m)[24 + k];
             if (di) L.x[k * NB + i] -= a.beta * ia * corr * nk;
             if (dj) L.x[k * NB + j] += a.beta * ib * corr * nk;
           }
@@ -1668,14 +1684,17 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
     __syncthreads();
   }
 
-  // ---- write the pack back ----
+  // ---- write the pack back (a body without mass keeps its stored velocity) ----
   for (int i = lane; i < nb; i += kWave) {
     const int g = gb0 + i;
+    const bool dyn = (L.flag[i] & kDynamic) != 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       a.x[k * CAP + g] = L.x[k * NB + i];
-      a.v[k * CAP + g] = L.v[k * NB + i];
-      a.w[k * CAP + g] = L.w[k * NB + i];
+      if (dyn) {
+        a.v[k * CAP + g] = L.v[k * NB + i];
+        a.w[k * CAP + g] = L.w[k * NB + i];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) a.q[k * CAP + g] = L.q[k * NB + i];

@@ -174,9 +174,10 @@ int32_t download_state(jg_world* w) {
 }
 
 // Pack towers into workgroups (first fit, largest first).  A pack holds whole towers and at
-// most `target` bodies, where `target` is the largest pack whose LDS fits eight workgroups on a
-// CU (two waves per SIMD, as many as the step kernel's registers allow); a tower larger than
-// that gets a pack of its own.  Packs are then grouped into launch
+// most `target` bodies, where `target` is the largest pack whose LDS fits as many workgroups on
+// a CU as the step kernel's registers allow: eight (two waves per SIMD) for the plain variant,
+// four for the variant with contact features (learned warm start, feature records).  A tower
+// larger than that gets a pack of its own.  Packs are then grouped into launch
 // classes of equal workgroups-per-CU, each launched with the LDS its largest pack needs.
 int32_t build_layout(jg_world* w) {
   const int T = (int)w->tower_bodies.size();
@@ -196,7 +197,8 @@ int32_t build_layout(jg_world* w) {
   int target = w->prm.pack_bodies > 0 ? w->prm.pack_bodies : 0;
   if (target <= 0) {
     target = 8;
-    while (lds_of(target + 1, 4, 8) <= 20 * 1024) ++target;
+    const size_t budget = (w->prm.warm_start == 2 || w->prm.record_features) ? 40 * 1024 : 20 * 1024;
+    while (lds_of(target + 1, 4, 8) <= budget) ++target;
   }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return w->tower_bodies[a].size() > w->tower_bodies[b].size();
