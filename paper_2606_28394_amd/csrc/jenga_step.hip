@@ -1218,7 +1218,11 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         if (p == 0 || L.tw[L.cab[p - 1] >> 16] != t) L.tc0[t] = p;
         if (p == nman - 1 || L.tw[L.cab[p + 1] >> 16] != t) L.tc1[t] = p + 1;
       }
-      for (int i = lane; i < nb; i += kWave) { L.hm[i] = 0.f; L.hm[NB + i] = 0.f; }
+      // per-body lane masks of the current chunk (the sorted-manifold words are free until the
+      // manifolds are written): lanes that touch body i, low and high 32 lanes
+      uint32_t* const lmlo = L.mab;
+      uint32_t* const lmhi = L.mmeta;
+      for (int i = lane; i < nb; i += kWave) { L.hm[i] = 0.f; L.hm[NB + i] = 0.f; lmlo[i] = 0u; lmhi[i] = 0u; }
       __syncthreads();
       uint32_t* mask = (uint32_t*)L.hm;   // [word * nbp + body]
       // Greedy first fit in canonical order, 64 manifolds at a time: a lane is coloured once
@@ -1232,14 +1236,19 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
         const bool di = valid && (L.flag[i] & kDynamic);
         const bool dj = valid && j != (int)kGround && (L.flag[j] & kDynamic);
-        const int ki = di ? i : 0x10000 + lane;       // lane-unique keys never match a body
-        const int kj = dj ? j : 0x20000 + lane;
+        // earlier lanes of the chunk that share a dynamic body with this one
+        uint32_t* const lmw = lane < 32 ? lmlo : lmhi;
+        const uint32_t lbit = 1u << (lane & 31);
+        if (di) atomicOr(&lmw[i], lbit);
+        if (dj) atomicOr(&lmw[j], lbit);
+        __syncthreads();
         uint64_t dep = 0ull;
-        for (int k = 0; k < kWave; ++k) {
-          const int ak = __builtin_amdgcn_readlane(ki, k), bk = __builtin_amdgcn_readlane(kj, k);
-          const bool hit = (k < lane) && (ak == ki || ak == kj || bk == ki || bk == kj);
-          dep |= (uint64_t)hit << k;
-        }
+        if (di) dep |= ((uint64_t)lmhi[i] << 32) | lmlo[i];
+        if (dj) dep |= ((uint64_t)lmhi[j] << 32) | lmlo[j];
+        dep &= lane_lt_mask(lane);
+        __syncthreads();
+        if (di) { lmlo[i] = 0u; lmhi[i] = 0u; }
+        if (dj) { lmlo[j] = 0u; lmhi[j] = 0u; }
         bool done = !valid;
         int col = -1;
         while (true) {
