@@ -56,18 +56,20 @@ def algorithmic_bytes(n_bodies_total, n_points_launch_end):
     return n_bodies_total * (13 * 4 * 2 + 5 * 4) + 32.0 * n_points_launch_end
 
 
-def traffic_from_profile(khash: str, workload: str):
+def traffic_from_profile(khash: str, workload: str, steps: int):
+    """HBM bytes of one launch of `steps` steps from the committed counter record (FETCH_SIZE +
+    WRITE_SIZE of a launch of the same batch).  Nearly all of it is per step (the contact points'
+    lever arms and impulses stream through device memory on every sweep), so the record scales
+    with the step count; a changed kernel invalidates it."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    # the record is per launch (state loaded once, contacts written at the end), so it holds
-    # for any step count of the same batch; a changed kernel invalidates it
     if rec.get("kernel_hash") != khash or not workload.startswith(rec.get("workload", "\0")):
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec["hbm_bytes_per_launch"] * steps / rec["steps"]
 
 
 def cpu_baseline(scene, n_towers=1024, n_steps=50, threads=None):
@@ -247,7 +249,7 @@ def main():
     flops = algorithmic_flops(sizes, args.steps, cand, man, pts, 20)
     achieved_tflops = flops / (kernel_ms * 1e-3) / 1e12
     workload = f"throughput batch: {T} tilted towers, 8-40 levels x 3 boxes, {args.steps} steps"
-    traffic = traffic_from_profile(kernel_hash(), workload)
+    traffic = traffic_from_profile(kernel_hash(), workload, args.steps)
     last_points = pts / max(1, args.steps)
     bytes_launch = algorithmic_bytes(int(scene["tower_ptr"][-1]), last_points)
     out = {
@@ -270,7 +272,8 @@ def main():
         "kernel_ms": kernel_ms,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "hbm_algorithmic_gbs": bytes_launch / (kernel_ms * 1e-3) / 1e9},
+                     "hbm_algorithmic_gbs": bytes_launch / (kernel_ms * 1e-3) / 1e9,
+                     "hbm_measured_gbs": None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e9},
         "phase_cycle_share": {k: round(v / total_cyc, 4) for k, v in phases.items()},
         "error_word": int(s1.error_word),
         "residual_rms_max": s1.residual_rms,

@@ -1,7 +1,10 @@
 // Batched block stepping on gfx950: one workgroup (one 64-lane wave) owns a
-// "pack" of whole towers and keeps their bodies, contacts and colours in LDS
-// for every step of a launch.  HBM is touched only when the launch starts and
-// ends, so the step is bound by the vector ALUs and LDS latency, not by HBM.
+// "pack" of whole towers for every step of a launch.  Bodies, contact pairs and
+// colours stay in LDS; each contact manifold's lever arms, impulses, normal and
+// depth live in a per-pack block of device memory, read on every PGS visit with
+// the next manifold's record in flight while the current one is solved (this
+// keeps LDS per body small, so more waves share a CU).  The step is bound by
+// the vector ALUs.
 //
 // Per step (Secs. "Rigid-Body Foundations", "Physics Engine --- Collision
 // Detection", "Contact Solver --- Projected Gauss-Seidel (PGS)"):
