@@ -89,6 +89,34 @@ def cpu_baseline(scene, n_towers=1024, n_steps=50, threads=None):
                 contact_iters_per_s=ci / dt)
 
 
+def cpu_report(threads=None):
+    """The FP64 oracle on one host thread and on all of them, over bounded samples of the four
+    workloads: the 18-level removal tower (240 steps), the removal batch (450 towers x 200 steps),
+    the throughput batch (first 1024 towers x 50 steps) and the 64 x 64 wall (100 steps; one
+    island, so one thread does the work either way)."""
+    from oracle import oracle as O
+    from paper_2606_28394_amd import workloads as W
+    threads = threads or min(16, os.cpu_count() or 1)
+    samples = [("removal tower, 240 steps", W.cfg1(0), 240),
+               ("removal batch, 450 towers x 200 steps", W.cfg2(0, n_steps=200), 200),
+               ("throughput batch, first 1024 towers x 50 steps", W.subset(W.cfg3(0, n_steps=50), range(1024)), 50),
+               ("masonry wall, 100 steps", W.cfg5(0, n_steps=100), 100)]
+    out = []
+    for name, sc, n in samples:
+        row = dict(sample=name, towers=sc["n_towers"], bodies=int(sc["tower_ptr"][-1]), steps=n)
+        for th in (1, threads):
+            ow = O.OracleWorld(sc)
+            t0 = time.perf_counter()
+            ow.step(n, threads=th)
+            dt = time.perf_counter() - t0
+            ci = sum(ow.tower_stats(t).contact_iters for t in range(sc["n_towers"]))
+            row[f"threads_{th}"] = dict(tower_steps_per_s=sc["n_towers"] * n / dt, contact_iters_per_s=ci / dt,
+                                        seconds=dt)
+            log(f"  oracle {name}, {th} thread(s): {sc['n_towers'] * n / dt:.4g} tower-steps/s ({dt:.1f} s)")
+        out.append(row)
+    return dict(cores=threads, samples=out)
+
+
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2606_28394_amd", "data", "warmstart_mlp.npy")
 
 
@@ -148,21 +176,60 @@ def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(4, 8, 12)):
                          contact_iters_per_point=stt.contact_iters / max(1, stt.points)))
         log(f"learned k={k}: median residual {rk:.3e}, {vk:.4g} tower-steps/s, fallbacks "
             f"{100 * rows[-1]['fallback_rate']:.1f}%")
-    # zero-start and previous-step plain solves at the same k, for context
-    ctx = {}
+    # zero-start solves at the same k (residual only), and the previous-step start (the impulses
+    # of the previous step, matched by key) with its rate: the warm start without the network
+    ctx, prev_rows = {}, []
     for k in ks:
         p = dict(scene["params"])
         p["iters"] = k
         ctx[f"zero_k{k}"] = _run_residuals(J, scene, steps, chunk, params=p)[0]
-        ctx[f"previous_k{k}"] = _run_residuals(J, scene, steps, chunk, params=p, warm_start=1)[0]
+        rk, mk, _ = _run_residuals(J, scene, steps, chunk, params=p, warm_start=1)
+        vk, msk, _ = _run_timed(J, torch, scene, steps, params=p, warm_start=1)
+        ctx[f"previous_k{k}"] = rk
+        prev_rows.append(dict(k=k, median_residual=rk, mean_residual=mk, value=vk, kernel_ms=msk))
+        log(f"previous-step k={k}: median residual {rk:.3e}, {vk:.4g} tower-steps/s")
     ok = [r for r in rows if r["median_residual"] <= r20]
     best = min(ok, key=lambda r: r["k"]) if ok else None
+    okp = [r for r in prev_rows if r["median_residual"] <= r20]
+    bestp = min(okp, key=lambda r: r["k"]) if okp else None
     return dict(workload=f"removal batch: {scene['n_towers']} towers, 12-24 levels, 1-8 push removals each, "
                          f"{steps} steps",
                 plain20=dict(median_residual=r20, mean_residual=m20, value=v20, kernel_ms=ms20),
-                learned=rows, median_residual_other_starts=ctx,
+                learned=rows, median_residual_other_starts=ctx, previous_step=prev_rows,
                 equal_residual_k=best["k"] if best else None,
-                learned_vs_plain20=(best["value"] / v20) if best else None)
+                learned_vs_plain20=(best["value"] / v20) if best else None,
+                previous_step_equal_residual_k=bestp["k"] if bestp else None,
+                previous_step_vs_plain20=(bestp["value"] / v20) if bestp else None)
+
+
+def large_island(J, torch, W, steps):
+    """One 4,096-stone wall (a single island, kept in device memory), plain PGS-20: time per step
+    from HIP events over one launch of `steps` steps after 5 warm-up steps."""
+    scene = W.cfg5(0, n_steps=steps + 5)
+    stream = torch.cuda.current_stream()
+    world = J.World(scene, stream=stream.cuda_stream)
+    world.step(5)
+    world.sync()
+    s0 = world.stats()
+    J.jg_query_phase_cycles(world.h)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    world.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    s1 = world.stats()
+    phases = J.jg_query_phase_cycles(world.h)
+    tot = max(1, sum(phases.values()))
+    n = int(scene["tower_ptr"][-1])
+    world.close()
+    log(f"  {steps} steps: {ms / steps:.2f} ms per step")
+    return {"workload": f"one masonry wall, 64 courses x 64 stones ({n} bodies), steps 6-{5 + steps}",
+            "steps": steps, "ms_per_step": ms / steps, "body_steps_per_s": n * steps / (ms * 1e-3),
+            "manifolds_per_step": (s1.manifolds - s0.manifolds) / steps,
+            "points_per_step": (s1.points - s0.points) / steps,
+            "phase_cycle_share": {k: round(v / tot, 4) for k, v in phases.items()},
+            "error_word": int(s1.error_word)}
 
 
 def main():
@@ -178,6 +245,11 @@ def main():
     ap.add_argument("--learned-weights", default=DEFAULT_WEIGHTS,
                     help="trained warm-start network (.npy); the equal-residual leg runs when it exists")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--cpu-report", action="store_true",
+                    help="also time the oracle single-threaded and on all host threads over samples of "
+                         "every workload (a few minutes)")
+    ap.add_argument("--island-steps", type=int, default=100,
+                    help="steps of the large-island leg (one 64 x 64 masonry wall); 0 skips it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="first copy MB megabytes device to device once (a known-size reference for "
                          "profiler byte counters)")
@@ -273,18 +345,28 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "hbm_algorithmic_gbs": bytes_launch / (kernel_ms * 1e-3) / 1e9,
-                     "hbm_measured_gbs": None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e9},
+                     "hbm_measured_gbs": None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e9,
+                     # both components of max(B / 8 TB/s, F / 157.3 TF) / time
+                     "alu_frac": achieved_tflops / PEAK_FP32_TFLOPS,
+                     "hbm_frac_algorithmic": bytes_launch / (kernel_ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
+                     "hbm_frac_measured": None if traffic is None else traffic / (kernel_ms * 1e-3) / (PEAK_HBM_GBS * 1e9)},
         "phase_cycle_share": {k: round(v / total_cyc, 4) for k, v in phases.items()},
         "error_word": int(s1.error_word),
         "residual_rms_max": s1.residual_rms,
     }
     world.close()
+    if args.island_steps > 0:
+        log("large-island leg (64 x 64 masonry wall) ...")
+        out["large_island"] = large_island(J, torch, W, args.island_steps)
     if not args.no_learned and os.path.exists(args.learned_weights):
         log("equal-residual leg (learned warm start vs plain-20) ...")
         out["equal_residual"] = equal_residual(J, torch, args.learned_weights)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_towers, args.cpu_steps)
+    if args.cpu_report:
+        log("oracle timing report ...")
+        out["cpu_report"] = cpu_report()
     print(json.dumps(out), flush=True)
 
 
