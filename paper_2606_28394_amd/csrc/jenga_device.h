@@ -49,6 +49,7 @@ struct StepArgs {
                                // (kManDevWords per manifold slot), then, for a pack whose layout
                                // lives in device memory, the whole layout
   int32_t in_gmem;             // 1: this launch's packs keep their whole layout in gmem
+  int32_t hot_bodies;          // in_gmem packs: 1 = the arrays of the serial walks also in LDS
   const int32_t* tower_body0;
   const float* tower_mu;
   int32_t pack_first;          // first pack of this launch
@@ -111,6 +112,18 @@ constexpr int kRegBodies = 256;    // largest pack the LDS path takes (register 
 
 // words of the window bounding boxes a global pack's broadphase keeps (6 per 64 bodies)
 __host__ __device__ inline int64_t window_words(int nbp) { return 6 * (int64_t)((nbp + 63) / 64); }
+
+// LDS words of a pack kept in device memory: its small arrays (phase counters, colour offsets,
+// the candidate ring, towers, pushes, broadphase windows) and, with `bodies`, the body arrays
+// that the serial walks (broadphase, colouring) read: positions, AABB half sizes and colour
+// masks, flags, colouring lane masks (9 words per body)
+constexpr int kHotBodyWords = 9;
+__host__ __device__ inline int64_t hot_words(int nbp, int tpc, int ppc, bool bodies) {
+  int64_t w = 2 * kPhases + 2 * (kMaxColours + 1) + 16 + kRing + (int64_t)tpc * kTowerWords +
+              (int64_t)ppc * kPushWords + window_words(nbp);
+  if (bodies) w += (int64_t)kHotBodyWords * nbp;
+  return w;
+}
 
 // LDS layout modes: 0 plain; 1 previous-step store (warm start from the previous step, or
 // feature records); 2 learned warm start: the store plus network input staging, saved

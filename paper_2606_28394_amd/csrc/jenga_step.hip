@@ -38,6 +38,17 @@ namespace jg {
 namespace {
 
 constexpr uint32_t kGround = 0xffffu;
+constexpr int kIslandWaves = 8;   // waves of a workgroup that steps an island in device memory
+
+// A barrier among the lanes of one wave.  Every phase runs on one wave (the workgroup's first),
+// so this is all its steps need: LDS and device-memory accesses of one wave are performed in
+// order.  Only the PGS sweeps of an island in device memory use the whole workgroup and its
+// barrier (__syncthreads).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 constexpr int kWindows = 4;      // broadphase register windows: packs of up to 256 bodies
 constexpr uint32_t kErrCand = 1u, kErrMan = 2u, kErrCol = 4u, kErrNan = 8u;
 
@@ -65,6 +76,7 @@ struct Lds {
   int32_t* cpos;
   // colour-sorted manifolds
   uint32_t *mab, *mmeta;
+  uint32_t *lmlo, *lmhi;   // colouring: per-body lane masks of the current chunk (low, high lanes)
   float* md;          // device block, kManDevWords per sorted manifold: r_A [12] (contact frame
                       // (n, t1, t2)), lambda [12], n [3], depth (see mdev)
   // warm start: sorted -> canonical, previous step store (canonical order)
@@ -89,8 +101,9 @@ __device__ __forceinline__ int lds_mode(const StepArgs& a) {
 }
 
 // base: the layout (LDS, or device memory for a pack kept there); dev: the pack's block of
-// lever arms and impulses in device memory
-__device__ __forceinline__ Lds carve(float* base, float* dev, const StepArgs& a) {
+// lever arms and impulses in device memory; hot (packs kept in device memory only): LDS for the
+// arrays listed in hot_words
+__device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, const StepArgs& a) {
   Lds L;
   L.nbp = a.nbp;
   L.pc = a.pc;
@@ -131,6 +144,30 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, const StepArgs& a)
     L.tfb = L.tfc = nullptr;
   }
   L.wbox = a.in_gmem ? take((int)window_words(nb)) : nullptr;
+  // the colouring's lane masks reuse the sorted-manifold words (free until the manifolds are
+  // written)
+  L.lmlo = L.mab;
+  L.lmhi = L.mmeta;
+  if (hot) {
+    // a pack in device memory keeps its small arrays, and if they fit the arrays its serial
+    // walks read, in LDS (the copies in its region stay unused)
+    float* h = hot;
+    auto htake = [&](int n) { float* r = h; h += n; return r; };
+    L.cyc = (unsigned long long*)htake(2 * kPhases);   // first: 8-byte aligned
+    L.coloff = (int32_t*)htake(kMaxColours + 1); L.colcnt = (int32_t*)htake(kMaxColours + 1);
+    L.scal = (int32_t*)htake(16);
+    L.ring = (uint32_t*)htake(kRing);
+    L.tb0 = (int32_t*)htake(nt); L.tb1 = (int32_t*)htake(nt); L.mu = htake(nt);
+    L.tcnt = (uint32_t*)htake(4 * nt); L.tres = htake(2 * nt);
+    L.tc0 = (int32_t*)htake(nt); L.tc1 = (int32_t*)htake(nt); L.tpts = (int32_t*)htake(nt);
+    L.pb = (int32_t*)htake(np); L.ps = (int32_t*)htake(np); L.pn = (int32_t*)htake(np);
+    L.pf = htake(3 * np); L.pwd = htake(np); L.px0 = htake(3 * np);
+    L.wbox = htake((int)window_words(nb));
+    if (a.hot_bodies) {
+      L.x = htake(3 * nb); L.hm = htake(3 * nb); L.flag = (uint32_t*)htake(nb);
+      L.lmlo = (uint32_t*)htake(nb); L.lmhi = (uint32_t*)htake(nb);
+    }
+  }
   return L;
 }
 
@@ -623,22 +660,23 @@ __device__ __forceinline__ void solve_manifold(const Lds& L, int m, float e) {
   solve_manifold_pts(L, m, e, d);
 }
 
-// `sweeps` PGS sweeps over the colours.  A lane visits the same manifolds in the same order on
-// every sweep (colour by colour, m = coloff[col] + lane + 64 k), so the points of its next
-// manifold are fetched from device memory while it solves the current one.  A lane with a
-// single manifold keeps its points in registers.
-__device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, int lane, float e) {
-  int first = 0;   // the lane's first colour with a manifold (ncol: none)
-  while (first < ncol && L.coloff[first] + lane >= L.coloff[first + 1]) ++first;
+// `sweeps` PGS sweeps over the colours by the workgroup's `nthr` threads (thread `tid`).  A
+// thread visits the same manifolds in the same order on every sweep (colour by colour,
+// m = coloff[col] + tid + nthr k), so the points of its next manifold are fetched from device
+// memory while it solves the current one; one with a single manifold keeps it in registers.
+// Every thread passes the same sweeps x ncol barriers.
+__device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, int tid, int nthr, float e) {
+  int first = 0;   // the thread's first colour with a manifold (ncol: none)
+  while (first < ncol && L.coloff[first] + tid >= L.coloff[first + 1]) ++first;
   ManPoints cur, nxt;
-  if (first < ncol) fetch_points(L, L.coloff[first] + lane, cur);
+  if (first < ncol) fetch_points(L, L.coloff[first] + tid, cur);
   for (int it = 0; it < sweeps; ++it) {
     for (int col = 0; col < ncol; ++col) {
-      for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
-        int n2 = m + kWave, c2 = col;
+      for (int m = L.coloff[col] + tid; m < L.coloff[col + 1]; m += nthr) {
+        int n2 = m + nthr, c2 = col;
         while (n2 >= L.coloff[c2 + 1]) {
-          if (++c2 == ncol) { c2 = first; n2 = L.coloff[first] + lane; break; }
-          n2 = L.coloff[c2] + lane;
+          if (++c2 == ncol) { c2 = first; n2 = L.coloff[first] + tid; break; }
+          n2 = L.coloff[c2] + tid;
         }
         const bool other = n2 != m;
         if (other) fetch_points(L, n2, nxt);
@@ -841,7 +879,7 @@ __device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, 
     psum[p] = sum;
     pmax[p] = mx;
   }
-  __syncthreads();
+  wave_sync();
   for (int t = lane; t < nt; t += kWave) {
     if (only && !only[t]) continue;
     float sum = 0.f, mx = 0.f;
@@ -904,12 +942,31 @@ __device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, i
 // variant does not carry the network's registers.
 // kGlobal: the pack's layout lives in its region of device memory instead of LDS.  The two are
 // separate instantiations so that the LDS variant's accesses compile to LDS instructions.
+// The plain device-memory variant runs kIslandWaves waves: the first runs every phase, and the
+// others join it for the PGS sweeps only (an island's colours hold hundreds of manifolds).
 template <bool kLearned, bool kGlobal>
-__global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
+constexpr int step_threads() { return (kGlobal && !kLearned) ? kIslandWaves * kWave : kWave; }
+
+template <bool kLearned, bool kGlobal>
+__global__ void __launch_bounds__((step_threads<kLearned, kGlobal>())) step_kernel(StepArgs a) {
+  constexpr int kThreads = step_threads<kLearned, kGlobal>();
   extern __shared__ __align__(16) float smem[];
   float* const dev = a.gmem + a.pack_goff[a.pack_first + blockIdx.x];
-  const Lds L = carve(kGlobal ? dev + kManDevWords * a.pc : smem, dev, a);
+  const Lds L = carve(kGlobal ? dev + kManDevWords * a.pc : smem, dev, kGlobal ? smem : nullptr, a);
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
+  if constexpr (kThreads > kWave) {
+    if (threadIdx.x >= kWave) {
+      // helper waves: per substep, the barrier where the first wave enters the sweeps, the
+      // sweeps, the barrier where it leaves them (the same count as the first wave's)
+      for (int s = 0; s < a.n_steps; ++s)
+        for (int sub = 0; sub < a.n_sub; ++sub) {
+          __syncthreads();
+          pgs_sweeps(L, a.iters, L.scal[2], threadIdx.x, kThreads, a.restitution);
+          __syncthreads();
+        }
+      return;
+    }
+  }
   const int lane = threadIdx.x;
   const int pk = a.pack_first + blockIdx.x;
   const int gb0 = a.pack_body0[pk], nb = a.pack_body0[pk + 1] - gb0;
@@ -986,7 +1043,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       for (int k = 0; k < 12; ++k) L.plam[k * PC + p] = a.prev_data[16 * g + 4 + k];
     }
   }
-  __syncthreads();
+  wave_sync();
   timer.mark(L, lane, 0);
 
   const float dt = a.dt, e = a.restitution;
@@ -998,7 +1055,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) L.px0[3 * r + k] = L.x[k * NB + b];
       }
-    __syncthreads();
+    wave_sync();
     for (int sub = 0; sub < a.n_sub; ++sub) {
       const bool last = (s == a.n_steps - 1) && (sub == a.n_sub - 1);
       // ---- 1. external forces; 2. frames ----
@@ -1042,7 +1099,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         L.tc1[t] = 0;
         L.tpts[t] = 0;
       }
-      __syncthreads();
+      wave_sync();
       timer.mark(L, lane, 1);
 
       // ---- 3 + 4. broadphase in canonical order, narrowphase on every 64 candidates ----
@@ -1053,7 +1110,8 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       if (nb > kWindows * kWave) {
         // global packs: bounding boxes of 64-body windows let body i skip the windows it cannot
         // touch (lane = window), then the surviving windows are tested body by body as above,
-        // in ascending order, so candidates still come out in canonical order
+        // in ascending order, so candidates still come out in canonical order.  A pack of one tower
+        // (every island in device memory) skips the tower index.
         const int nwin = (nb + kWave - 1) / kWave;
         for (int w = lane; w < nwin; w += kWave) {
           float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
@@ -1068,13 +1126,13 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) { L.wbox[6 * w + k] = lo[k]; L.wbox[6 * w + 3 + k] = hi[k]; }
         }
-        __syncthreads();
+        wave_sync();
         const float slack = a.margin * 1.01f + 1e-6f;   // a filter: wider than the pair test
         int cur_t = -1, cand_acc = 0;
         for (int i = 0; i < nb; ++i) {
           const uint32_t fi = L.flag[i];
           if (!(fi & kActive)) continue;
-          const int ti = L.tw[i];
+          const int ti = nt == 1 ? 0 : L.tw[i];
           float xi[3], hi[3];
 #pragma unroll
           for (int k = 0; k < 3; ++k) { xi[k] = L.x[k * NB + i]; hi[k] = L.hm[k * NB + i]; }
@@ -1099,7 +1157,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
               bool hit = j > i && j < nb;
               if (hit) {
                 const uint32_t fj = L.flag[j];
-                hit = L.tw[j] == ti && (fj & kActive) && (dyni || (fj & kDynamic)) &&
+                hit = (nt == 1 || L.tw[j] == ti) && (fj & kActive) && (dyni || (fj & kDynamic)) &&
                       fabsf(xi[0] - L.x[j]) <= hi[0] + L.hm[j] + a.margin &&
                       fabsf(xi[1] - L.x[NB + j]) <= hi[1] + L.hm[NB + j] + a.margin &&
                       fabsf(xi[2] - L.x[2 * NB + j]) <= hi[2] + L.hm[2 * NB + j] + a.margin;
@@ -1110,7 +1168,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
               cand_acc += cnt;
               tail += cnt;
               if (tail - head >= kWave) {
-                __syncthreads();
+                wave_sync();
                 nman = narrow_chunk(L, head, kWave, nman, lane);
                 head += kWave;
               }
@@ -1121,7 +1179,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             cand_acc += 1;
             tail += 1;
             if (tail - head >= kWave) {
-              __syncthreads();
+              wave_sync();
               nman = narrow_chunk(L, head, kWave, nman, lane);
               head += kWave;
             }
@@ -1183,7 +1241,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             cand_acc += cnt;
             tail += cnt;
             if (tail - head >= kWave) {
-              __syncthreads();
+              wave_sync();
               nman = narrow_chunk(L, head, kWave, nman, lane);
               head += kWave;
             }
@@ -1194,7 +1252,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             cand_acc += 1;
             tail += 1;
             if (tail - head >= kWave) {
-              __syncthreads();
+              wave_sync();
               nman = narrow_chunk(L, head, kWave, nman, lane);
               head += kWave;
             }
@@ -1202,7 +1260,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         }
         if (lane == 0 && cur_t >= 0 && cand_acc) L.tcnt[cur_t * 4 + 0] += (uint32_t)cand_acc;
       }
-      __syncthreads();
+      wave_sync();
       while (head < tail) {
         const int cnt = min(kWave, tail - head);
         nman = narrow_chunk(L, head, cnt, nman, lane);
@@ -1212,7 +1270,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         if (lane == 0) L.scal[3] |= kErrMan;
         nman = PC;
       }
-      __syncthreads();
+      wave_sync();
       timer.mark(L, lane, 2);
 
       // ---- 5. tower ranges of the canonical list; greedy first-fit colouring ----
@@ -1223,10 +1281,10 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       }
       // per-body lane masks of the current chunk (the sorted-manifold words are free until the
       // manifolds are written): lanes that touch body i, low and high 32 lanes
-      uint32_t* const lmlo = L.mab;
-      uint32_t* const lmhi = L.mmeta;
+      uint32_t* const lmlo = L.lmlo;
+      uint32_t* const lmhi = L.lmhi;
       for (int i = lane; i < nb; i += kWave) { L.hm[i] = 0.f; L.hm[NB + i] = 0.f; lmlo[i] = 0u; lmhi[i] = 0u; }
-      __syncthreads();
+      wave_sync();
       uint32_t* mask = (uint32_t*)L.hm;   // [word * nbp + body]
       // Greedy first fit in canonical order, 64 manifolds at a time: a lane is coloured once
       // every earlier manifold of its chunk that shares a dynamic body is coloured.  Lanes
@@ -1244,12 +1302,12 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         const uint32_t lbit = 1u << (lane & 31);
         if (di) atomicOr(&lmw[i], lbit);
         if (dj) atomicOr(&lmw[j], lbit);
-        __syncthreads();
+        wave_sync();
         uint64_t dep = 0ull;
         if (di) dep |= ((uint64_t)lmhi[i] << 32) | lmlo[i];
         if (dj) dep |= ((uint64_t)lmhi[j] << 32) | lmlo[j];
         dep &= lane_lt_mask(lane);
-        __syncthreads();
+        wave_sync();
         if (di) { lmlo[i] = 0u; lmhi[i] = 0u; }
         if (dj) { lmlo[j] = 0u; lmhi[j] = 0u; }
         bool done = !valid;
@@ -1269,7 +1327,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             }
             done = true;
           }
-          __syncthreads();
+          wave_sync();
         }
         if (valid) {
           L.cpos[p] = col;
@@ -1277,7 +1335,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           else atomicOr((uint32_t*)&L.scal[3], kErrCol);
         }
       }
-      __syncthreads();
+      wave_sync();
       // colour offsets (wave prefix sum over the 64 colour counts)
       {
         const int cnt = L.colcnt[lane];
@@ -1293,7 +1351,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         const uint64_t used = __ballot(cnt > 0);
         if (lane == 0) L.scal[2] = used ? 64 - __clzll((long long)used) : 0;
       }
-      __syncthreads();
+      wave_sync();
       // colour-sorted positions, canonical order inside each colour
       for (int c0 = 0; c0 < nman; c0 += kWave) {
         const int p = c0 + lane;
@@ -1305,9 +1363,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           const uint64_t m = __ballot(col == c);
           const int base = L.colcnt[c];
           if (col == c) pos = base + __popcll(m & lane_lt_mask(lane));
-          __syncthreads();
+          wave_sync();
           if (lane == 0) L.colcnt[c] = base + __popcll(m);
-          __syncthreads();
+          wave_sync();
           pending &= ~m;
         }
         if (p < nman) {
@@ -1315,7 +1373,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           if (col >= 0) atomicMax(&L.tcnt[L.tw[L.cab[p] >> 16] * 4 + 3], (uint32_t)(col + 1));
         }
       }
-      __syncthreads();
+      wave_sync();
       timer.mark(L, lane, 3);
       const int ncol = L.scal[2];
       const int nkept = L.coloff[ncol];
@@ -1423,7 +1481,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
         atomicAdd(&L.tpts[ti], npts);
       }
-      __syncthreads();
+      wave_sync();
       timer.mark(L, lane, 4);
 
       // ---- learned warm start: features, network, initial impulses; feature records ----
@@ -1461,7 +1519,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
               mlp::stage_row(net, f, L.xs + lane * mlp::kRowWords);
 #pragma unroll
               for (int k = 0; k < 3; ++k) prevd[3 * lane + k] = f[12 + k];
-              __syncthreads();
+              wave_sync();
               mlp::f32x4 y[4];
               mlp::infer_chunk(net, L.xs, lane, y);
               if (lane < 16) {
@@ -1473,10 +1531,10 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
                     for (int k = 0; k < 3; ++k) mdev(L, mm)[12 + jj * 3 + k] = y[t][k] + prevd[3 * row + k];
                 }
               }
-              __syncthreads();
+              wave_sync();
             }
           }
-          __syncthreads();
+          wave_sync();
         }
         if (keep_prev && a.warm_start == 0) {
           // records without a warm start: the key lookup filled ml only to feed the features
@@ -1484,7 +1542,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           for (int m = lane; m < nkept; m += kWave)
 #pragma unroll
             for (int k = 0; k < 12; ++k) mdev(L, m)[12 + k] = 0.f;
-          __syncthreads();
+          wave_sync();
         }
       }
 
@@ -1492,7 +1550,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       if (a.warm_start == 1) {
         for (int col = 0; col < ncol; ++col) {
           for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) warm_apply_manifold(L, m);
-          __syncthreads();
+          wave_sync();
         }
       }
       int sweeps = a.iters;
@@ -1502,26 +1560,28 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
           for (int col = 0; col < ncol; ++col) {
             for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave)
               learned_apply_manifold(L, m, L.mu[L.tw[L.mab[m] >> 16]], gdt);
-            __syncthreads();
+            wave_sync();
           }
           sweeps = a.mlp_iters;
         }
       }
-      pgs_sweeps(L, sweeps, ncol, lane, e);
+      __syncthreads();   // the helper waves (if any) enter the sweeps with this wave
+      pgs_sweeps(L, sweeps, ncol, threadIdx.x, kThreads, e);
+      __syncthreads();
       timer.mark(L, lane, 5);
 
       // ---- learned warm start: residual, and the plain solve again for towers above tau ----
       if constexpr (kLearned) {
         if (learned) {
           tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, nullptr);
-          __syncthreads();
+          wave_sync();
           int any = 0;
           for (int t = lane; t < nt; t += kWave) {
             const uint32_t fb = L.tres[2 * t] > a.fallback_tau ? 1u : 0u;
             L.tfb[t] = fb;
             any |= (int)fb;
           }
-          __syncthreads();
+          wave_sync();
           any = __any(any);   // one wave per workgroup: a wave vote is the workgroup's
           if (any) {
             for (int i = lane; i < nb; i += kWave)
@@ -1535,21 +1595,21 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
               if (L.tfb[L.tw[L.mab[m] >> 16]])
 #pragma unroll
                 for (int k = 0; k < 12; ++k) mdev(L, m)[12 + k] = 0.f;
-            __syncthreads();
+            wave_sync();
             for (int it = 0; it < a.iters; ++it) {
               for (int col = 0; col < ncol; ++col) {
                 for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
                   const int t = L.tw[L.mab[m] >> 16];
                   if (L.tfb[t]) solve_manifold(L, m, e);
                 }
-                __syncthreads();
+                wave_sync();
               }
             }
             for (int t = lane; t < nt; t += kWave)
               if (L.tfb[t]) { L.tfc[2 * t] += 1u; L.tfc[2 * t + 1] += (uint32_t)L.tpts[t]; }
             tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, L.tfb);
           }
-          __syncthreads();
+          wave_sync();
           timer.mark(L, lane, 7);
         }
       }
@@ -1593,7 +1653,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
       if (keep_prev) {
         // canonical-order store of this step's impulses (dropped pairs keep their key, no points)
         for (int p = lane; p < nman; p += kWave) { L.pkey[p] = L.cab[p]; L.pslot[p] = 0u; }
-        __syncthreads();
+        wave_sync();
         for (int m = lane; m < nkept; m += kWave) {
           const int p = L.mcanon[m];
           const uint32_t meta = L.mmeta[m];
@@ -1605,7 +1665,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         }
         if (lane == 0) L.scal[4] = nman;
       }
-      __syncthreads();
+      wave_sync();
       timer.mark(L, lane, 6);
 
       // ---- 8. residual (the learned variant took it before the outputs) ----
@@ -1656,7 +1716,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         store3(L.w, NB, i, wv);
         L.q[i] = qw; L.q[NB + i] = qx; L.q[2 * NB + i] = qy; L.q[3 * NB + i] = qz;
       }
-      __syncthreads();
+      wave_sync();
       timer.mark(L, lane, 8);
       // ---- 10. Baumgarte position correction, colour by colour ----
       for (int col = 0; col < ncol; ++col) {
@@ -1676,7 +1736,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
             if (dj) L.x[k * NB + j] += a.beta * ib * corr * nk;
           }
         }
-        __syncthreads();
+        wave_sync();
       }
       timer.mark(L, lane, 9);
     }
@@ -1693,7 +1753,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
         for (int k = 0; k < 3; ++k) { L.v[k * NB + b] = 0.f; L.w[k * NB + b] = 0.f; }
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 
   // ---- write the pack back (a body without mass keeps its stored velocity) ----
@@ -1746,7 +1806,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
   }
   if (lane == 0) a.pack_error[pk] |= (uint32_t)L.scal[3];
   timer.mark(L, lane, 0);
-  __syncthreads();
+  wave_sync();
   if (a.phase_cycles && lane < kPhases) atomicAdd(&a.phase_cycles[lane], L.cyc[lane]);
 }
 
@@ -1755,8 +1815,9 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepArgs a) {
 int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    const void* lds_variants[2] = {(const void*)step_kernel<false, false>, (const void*)step_kernel<true, false>};
-    for (const void* f : lds_variants)
+    const void* variants[4] = {(const void*)step_kernel<false, false>, (const void*)step_kernel<true, false>,
+                               (const void*)step_kernel<false, true>, (const void*)step_kernel<true, true>};
+    for (const void* f : variants)
       if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
         return (int)e;
     attr_set = true;
@@ -1766,7 +1827,7 @@ int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (a.in_gmem) {
     if (learned) hipLaunchKernelGGL((step_kernel<true, true>), grid, block, lds_bytes, s, a);
-    else hipLaunchKernelGGL((step_kernel<false, true>), grid, block, lds_bytes, s, a);
+    else hipLaunchKernelGGL((step_kernel<false, true>), grid, dim3(step_threads<false, true>()), lds_bytes, s, a);
   } else {
     if (learned) hipLaunchKernelGGL((step_kernel<true, false>), grid, block, lds_bytes, s, a);
     else hipLaunchKernelGGL((step_kernel<false, false>), grid, block, lds_bytes, s, a);

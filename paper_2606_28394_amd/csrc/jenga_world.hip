@@ -82,6 +82,7 @@ struct jg_world {
     int first = 0, count = 0, per_cu = 0, nbp = 1, pc = 16, tpc = 1, ppc = 1;
     size_t lds = 0;
     bool global = false;     // packs keep their state in device memory (islands too large for LDS)
+    bool hot_bodies = false; // global packs: the serial walks' body arrays in LDS
     int64_t gwords = 0;      // words of one pack's device region
   };
   std::vector<PackClass> classes;   // launch classes, in pack order
@@ -318,7 +319,12 @@ int32_t build_layout(jg_world* w) {
   for (auto& c : w->classes) {
     c.pc = pc_of(c.nbp);
     if (c.global) {
-      c.lds = 0;
+      // small arrays in LDS always; the serial walks' body arrays too when they fit
+      c.hot_bodies = jg::hot_words(c.nbp, c.tpc, c.ppc, true) * 4 <= 160 * 1024;
+      c.lds = (size_t)jg::hot_words(c.nbp, c.tpc, c.ppc, c.hot_bodies) * 4;
+      if (c.lds > 160 * 1024)
+        return fail(JG_ECAPACITY, "a pack kept in device memory needs " + std::to_string(c.lds) +
+                                  " bytes of LDS for its towers and pushes (max 163840)");
       c.gwords = ((int64_t)jg::kManDevWords * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
                   jg::window_words(c.nbp) + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
@@ -728,6 +734,7 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
     a.nbp = c.nbp; a.pc = c.pc; a.tpc = c.tpc; a.ppc = c.ppc;
     a.gmem = w->d_gmem.p;
     a.in_gmem = c.global ? 1 : 0;
+    a.hot_bodies = c.hot_bodies ? 1 : 0;
     a.pack_goff = w->d_pack_goff.p;
     if (int e = jg::launch_step(a, c.lds, s))
       return fail(JG_EDEVICE, std::string("step kernel launch: ") + hipGetErrorString((hipError_t)e));
