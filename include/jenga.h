@@ -51,7 +51,7 @@ typedef enum {
 } jg_status;
 
 /* Device error-word bits reported by jg_query_stats. */
-#define JG_ERR_CANDIDATES 1u   /* reserved (broadphase candidates are consumed as produced) */
+#define JG_ERR_CANDIDATES 1u   /* an island in device memory had more than 16 broadphase candidates per body */
 #define JG_ERR_MANIFOLDS 2u    /* colliding pairs exceeded the pack capacity */
 #define JG_ERR_COLOURS 4u      /* a manifold needed more than 64 colours (dropped) */
 #define JG_ERR_NAN 8u          /* non-finite body state */
@@ -71,7 +71,7 @@ typedef struct {
                             fallback_tau */
   int32_t device;        /* HIP device ordinal */
   void* stream;          /* hipStream_t for all GPU work; NULL = default stream */
-  int32_t pack_bodies;   /* bodies per on-chip pack; 0 = automatic; -1 = every tower keeps its
+  int32_t pack_bodies;   /* bodies per on-chip pack (at most 256); 0 = automatic; -1 = every tower keeps its
                             state in device memory (the path of islands over 256 bodies) */
   float manifolds_per_body;  /* manifold capacity per body in a pack; 0 = automatic (3.5) */
   int32_t mlp_iters;     /* PGS iterations after a learned warm start; default 8 */

@@ -113,6 +113,10 @@ constexpr int kRegBodies = 256;    // largest pack the LDS path takes (register 
 // words of the window bounding boxes a global pack's broadphase keeps (6 per 64 bodies)
 __host__ __device__ inline int64_t window_words(int nbp) { return 6 * (int64_t)((nbp + 63) / 64); }
 
+// an island in device memory lists its broadphase candidates of a step: at most this many per
+// body (more sets JG_ERR_CANDIDATES)
+constexpr int kCandPerBody = 16;
+
 // LDS words of a pack kept in device memory: its small arrays (phase counters, colour offsets,
 // the candidate ring, towers, pushes, broadphase windows) and, with `bodies`, the body arrays
 // that the serial walks (broadphase, colouring) read: positions, AABB half sizes and colour

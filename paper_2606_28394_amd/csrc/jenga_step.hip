@@ -89,6 +89,7 @@ struct Lds {
   float *vsave, *rpart;
   uint32_t *tfb, *tfc;
   float* wbox;        // global packs: per 64-body window, AABB lo[3], hi[3] (broadphase)
+  uint32_t* cand;     // global packs: the broadphase candidates of a step, canonical order
   int nbp, pc;
 };
 
@@ -101,9 +102,11 @@ __device__ __forceinline__ int lds_mode(const StepArgs& a) {
 }
 
 // base: the layout (LDS, or device memory for a pack kept there); dev: the pack's block of
-// lever arms and impulses in device memory; hot (packs kept in device memory only): LDS for the
-// arrays listed in hot_words
-__device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, const StepArgs& a) {
+// lever arms and impulses in device memory; with use_hot (packs kept in device memory), hot is
+// LDS for the small arrays listed in hot_words, and with hot_bodies for the walks' body arrays.
+// The flags are compile-time constants at the call, so every array has one address space.
+__device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool use_hot, bool hot_bodies,
+                                     const StepArgs& a) {
   Lds L;
   L.nbp = a.nbp;
   L.pc = a.pc;
@@ -144,11 +147,12 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, const 
     L.tfb = L.tfc = nullptr;
   }
   L.wbox = a.in_gmem ? take((int)window_words(nb)) : nullptr;
+  L.cand = a.in_gmem ? (uint32_t*)take(kCandPerBody * nb) : nullptr;
   // the colouring's lane masks reuse the sorted-manifold words (free until the manifolds are
   // written)
   L.lmlo = L.mab;
   L.lmhi = L.mmeta;
-  if (hot) {
+  if (use_hot) {
     // a pack in device memory keeps its small arrays, and if they fit the arrays its serial
     // walks read, in LDS (the copies in its region stay unused)
     float* h = hot;
@@ -163,7 +167,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, const 
     L.pb = (int32_t*)htake(np); L.ps = (int32_t*)htake(np); L.pn = (int32_t*)htake(np);
     L.pf = htake(3 * np); L.pwd = htake(np); L.px0 = htake(3 * np);
     L.wbox = htake((int)window_words(nb));
-    if (a.hot_bodies) {
+    if (hot_bodies) {
       L.x = htake(3 * nb); L.hm = htake(3 * nb); L.flag = (uint32_t*)htake(nb);
       L.lmlo = (uint32_t*)htake(nb); L.lmhi = (uint32_t*)htake(nb);
     }
@@ -947,12 +951,19 @@ __device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, i
 template <bool kLearned, bool kGlobal>
 constexpr int step_threads() { return (kGlobal && !kLearned) ? kIslandWaves * kWave : kWave; }
 
-template <bool kLearned, bool kGlobal>
-__global__ void __launch_bounds__((step_threads<kLearned, kGlobal>())) step_kernel(StepArgs a) {
+// The plain variants are held to two waves per SIMD (at most 256 registers): occupancy is what
+// hides the latency of the pack's serial phases, and a register count that drifts above 256
+// would halve it.
+// kHot (packs in device memory): the body arrays of the serial walks are in LDS too.  It is a
+// template parameter so that every access has one known address space (a pointer that may be
+// either compiles to flat instructions, which are as slow as device memory even on LDS).
+template <bool kLearned, bool kGlobal, bool kHot>
+__global__ void __launch_bounds__((step_threads<kLearned, kGlobal>()))
+__attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   constexpr int kThreads = step_threads<kLearned, kGlobal>();
   extern __shared__ __align__(16) float smem[];
   float* const dev = a.gmem + a.pack_goff[a.pack_first + blockIdx.x];
-  const Lds L = carve(kGlobal ? dev + kManDevWords * a.pc : smem, dev, kGlobal ? smem : nullptr, a);
+  const Lds L = carve(kGlobal ? dev + kManDevWords * a.pc : smem, dev, smem, kGlobal, kGlobal && kHot, a);
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   if constexpr (kThreads > kWave) {
     if (threadIdx.x >= kWave) {
@@ -1025,6 +1036,8 @@ __global__ void __launch_bounds__((step_threads<kLearned, kGlobal>())) step_kern
   }
   if (lane == 0) {
     L.scal[3] = 0;                                   // error bits
+    // an on-chip pack holds at most kWindows x 64 bodies (the host sizes them so)
+    if (!kGlobal && nb > kWindows * kWave) L.scal[3] = kErrCand;
     L.scal[4] = keep_prev ? a.prev_count[pk] : 0;    // previous-step manifolds
   }
   if constexpr (kLearned) {
@@ -1107,11 +1120,12 @@ __global__ void __launch_bounds__((step_threads<kLearned, kGlobal>())) step_kern
       // body i is broadcast from its window with readlane, so the pair loop touches LDS only
       // to append candidates to the ring.
       int head = 0, tail = 0, nman = 0;
-      if (nb > kWindows * kWave) {
-        // global packs: bounding boxes of 64-body windows let body i skip the windows it cannot
-        // touch (lane = window), then the surviving windows are tested body by body as above,
-        // in ascending order, so candidates still come out in canonical order.  A pack of one tower
-        // (every island in device memory) skips the tower index.
+      if constexpr (kGlobal) {
+        // islands in device memory (one tower each).  Bounding boxes of 64-body windows filter
+        // the pair tests; each lane then walks its own body's candidates j > i in ascending
+        // order, the ground last.  A first walk counts them, a scan gives each body its place
+        // in the canonical list, a second walk writes them there, and the SAT runs on that
+        // list 64 at a time, so the candidates keep their canonical order.
         const int nwin = (nb + kWave - 1) / kWave;
         for (int w = lane; w < nwin; w += kWave) {
           float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
@@ -1128,64 +1142,130 @@ __global__ void __launch_bounds__((step_threads<kLearned, kGlobal>())) step_kern
         }
         wave_sync();
         const float slack = a.margin * 1.01f + 1e-6f;   // a filter: wider than the pair test
-        int cur_t = -1, cand_acc = 0;
-        for (int i = 0; i < nb; ++i) {
-          const uint32_t fi = L.flag[i];
-          if (!(fi & kActive)) continue;
-          const int ti = nt == 1 ? 0 : L.tw[i];
-          float xi[3], hi[3];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) { xi[k] = L.x[k * NB + i]; hi[k] = L.hm[k * NB + i]; }
-          if (ti != cur_t) {
-            if (lane == 0 && cur_t >= 0 && cand_acc) L.tcnt[cur_t * 4 + 0] += (uint32_t)cand_acc;
-            cur_t = ti;
-            cand_acc = 0;
-          }
+        // The candidates of the 64 bodies i = i0 + lane, each lane's in canonical order (j
+        // ascending, the ground last): counted, or written from out + off.  Windows are visited
+        // in order; a window near none of the 64 is skipped, and a near one is loaded into
+        // registers (lane l: body 64 w + l) and broadcast body by body with readlane, so the
+        // tests of one lane wait on no memory.
+        auto walk = [&](int i0, uint32_t* out, int off) -> int {
+          const int i = i0 + lane;
+          const uint32_t fi = i < nb ? L.flag[i] : 0u;
+          const bool act = (fi & kActive) != 0;
           const bool dyni = (fi & kDynamic) != 0;
-          for (int g0 = i / kWave; g0 < nwin; g0 += kWave) {
-            const int w = g0 + lane;
-            bool near = w < nwin;
+          float xi[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+          if (act) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-              near = near && xi[k] - hi[k] <= L.wbox[6 * w + 3 + k] + slack &&
-                     xi[k] + hi[k] + slack >= L.wbox[6 * w + k];
-            uint64_t wb = __ballot(near);
-            while (wb) {
-              const int ww = g0 + __ffsll((unsigned long long)wb) - 1;
-              wb &= wb - 1;
-              const int j = ww * kWave + lane;
-              bool hit = j > i && j < nb;
-              if (hit) {
-                const uint32_t fj = L.flag[j];
-                hit = (nt == 1 || L.tw[j] == ti) && (fj & kActive) && (dyni || (fj & kDynamic)) &&
-                      fabsf(xi[0] - L.x[j]) <= hi[0] + L.hm[j] + a.margin &&
-                      fabsf(xi[1] - L.x[NB + j]) <= hi[1] + L.hm[NB + j] + a.margin &&
-                      fabsf(xi[2] - L.x[2 * NB + j]) <= hi[2] + L.hm[2 * NB + j] + a.margin;
+            for (int k = 0; k < 3; ++k) { xi[k] = L.x[k * NB + i]; hi[k] = L.hm[k * NB + i]; }
+          }
+          int c = 0;
+          const int w0 = i0 / kWave;
+          for (int wb0 = w0 - w0 % kWave; wb0 < nwin; wb0 += kWave) {
+            // lane l holds the box of window wb0 + l
+            float blo[3], bhi[3];
+            const bool inw = wb0 + lane < nwin;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              blo[k] = inw ? L.wbox[6 * (wb0 + lane) + k] : 0.f;
+              bhi[k] = inw ? L.wbox[6 * (wb0 + lane) + 3 + k] : 0.f;
+            }
+            for (int w = max(w0, wb0); w < min(nwin, wb0 + kWave); ++w) {
+              // broadcasts first, then branch-free tests (& rather than &&: no masked regions)
+              float lo[3], hb[3];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                lo[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(blo[k]), w - wb0));
+                hb[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bhi[k]), w - wb0));
               }
-              const uint64_t bal = __ballot(hit);
-              if (hit) L.ring[(tail + __popcll(bal & lane_lt_mask(lane))) & (kRing - 1)] = ((uint32_t)i << 16) | (uint32_t)j;
-              const int cnt = __popcll(bal);
-              cand_acc += cnt;
-              tail += cnt;
-              if (tail - head >= kWave) {
-                wave_sync();
-                nman = narrow_chunk(L, head, kWave, nman, lane);
-                head += kWave;
+              bool near = act;
+#pragma unroll
+              for (int k = 0; k < 3; ++k) near = near & (xi[k] - hi[k] <= hb[k] + slack) & (xi[k] + hi[k] + slack >= lo[k]);
+              if (!__any(near)) continue;
+              const int jl = w * kWave + lane;
+              const bool inj = jl < nb;
+              float xj[3], hj[3];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                xj[k] = inj ? L.x[k * NB + jl] : 0.f;
+                hj[k] = inj ? L.hm[k * NB + jl] : 0.f;
+              }
+              const uint32_t fj = inj ? L.flag[jl] : 0u;
+              const int jn = min(kWave, nb - w * kWave);
+              for (int jj = 0; jj < jn; ++jj) {
+                const int j = w * kWave + jj;
+                const uint32_t f = __builtin_amdgcn_readlane(fj, jj);
+                float d[3], h[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                  d[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xj[k]), jj));
+                  h[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hj[k]), jj));
+                }
+                const bool hit = near & (j > i) & ((f & kActive) != 0) & (dyni | ((f & kDynamic) != 0)) &
+                                 (fabsf(xi[0] - d[0]) <= hi[0] + h[0] + a.margin) &
+                                 (fabsf(xi[1] - d[1]) <= hi[1] + h[1] + a.margin) &
+                                 (fabsf(xi[2] - d[2]) <= hi[2] + h[2] + a.margin);
+                if (hit) {
+                  if (out) out[off + c] = ((uint32_t)i << 16) | (uint32_t)j;
+                  ++c;
+                }
               }
             }
           }
-          if (dyni && (xi[2] - hi[2] <= a.margin)) {
-            if (lane == 0) L.ring[tail & (kRing - 1)] = ((uint32_t)i << 16) | kGround;
-            cand_acc += 1;
-            tail += 1;
-            if (tail - head >= kWave) {
-              wave_sync();
-              nman = narrow_chunk(L, head, kWave, nman, lane);
-              head += kWave;
-            }
+          if (act && dyni && (xi[2] - hi[2] <= a.margin)) {
+            if (out) out[off + c] = ((uint32_t)i << 16) | kGround;
+            ++c;
           }
+          return c;
+        };
+        // counts into the (still unused) colouring lane masks, then an exclusive scan in place
+        uint32_t* const cnt = L.lmlo;
+        for (int i0 = 0; i0 < nb; i0 += kWave) {
+          const int c = walk(i0, nullptr, 0);
+          if (i0 + lane < nb) cnt[i0 + lane] = (uint32_t)c;
         }
-        if (lane == 0 && cur_t >= 0 && cand_acc) L.tcnt[cur_t * 4 + 0] += (uint32_t)cand_acc;
+        wave_sync();
+        uint32_t run = 0;
+        for (int i0 = 0; i0 < nb; i0 += kWave) {
+          const int i = i0 + lane;
+          const uint32_t c = i < nb ? cnt[i] : 0u;
+          uint32_t incl = c;
+#pragma unroll
+          for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(incl, d);
+            if (lane >= d) incl += t;
+          }
+          if (i < nb) cnt[i] = run + incl - c;
+          run += __shfl(incl, kWave - 1);
+        }
+        wave_sync();
+        // the list holds kCandPerBody per body; bodies whose candidates would run past its end are
+        // left out whole (flagged), so the list stays a canonical prefix
+        const int cap = kCandPerBody * nb;
+        int fit = 0;
+        for (int i0 = 0; i0 < nb; i0 += kWave) {
+          const int i = i0 + lane;
+          const int off = i < nb ? (int)cnt[i] : 0;
+          const int end = i + 1 < nb ? (int)cnt[i + 1] : (int)run;
+          const bool keep = i < nb && end <= cap;
+          if (keep) fit = max(fit, end);
+          // lanes whose run does not fit count without writing
+          walk(i0, keep ? L.cand : nullptr, off);
+        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) fit = max(fit, __shfl_xor(fit, d));
+        const int total = fit;
+        if ((int)run > cap && lane == 0) L.scal[3] |= kErrCand;
+        wave_sync();
+        for (int c0 = 0; c0 < total; c0 += kWave) {
+          const int n = min(kWave, total - c0);
+          // narrow_chunk reads the ring: stage the next 64 candidates there
+          if (lane < n) L.ring[(head + lane) & (kRing - 1)] = L.cand[c0 + lane];
+          wave_sync();
+          nman = narrow_chunk(L, head, n, nman, lane);
+          head += n;
+          wave_sync();
+        }
+        tail = head;
+        if (lane == 0) L.tcnt[0] += (uint32_t)run;   // an island is one tower
       } else {
         float wx[kWindows][3], wh[kWindows][3];
         uint32_t wf[kWindows];
@@ -1815,8 +1895,10 @@ __global__ void __launch_bounds__((step_threads<kLearned, kGlobal>())) step_kern
 int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    const void* variants[4] = {(const void*)step_kernel<false, false>, (const void*)step_kernel<true, false>,
-                               (const void*)step_kernel<false, true>, (const void*)step_kernel<true, true>};
+    const void* variants[6] = {(const void*)step_kernel<false, false, false>,
+                               (const void*)step_kernel<true, false, false>,
+                               (const void*)step_kernel<false, true, false>, (const void*)step_kernel<true, true, false>,
+                               (const void*)step_kernel<false, true, true>, (const void*)step_kernel<true, true, true>};
     for (const void* f : variants)
       if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
         return (int)e;
@@ -1826,11 +1908,17 @@ int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   const dim3 grid(a.n_packs), block(kWave);
   hipStream_t s = (hipStream_t)stream;
   if (a.in_gmem) {
-    if (learned) hipLaunchKernelGGL((step_kernel<true, true>), grid, block, lds_bytes, s, a);
-    else hipLaunchKernelGGL((step_kernel<false, true>), grid, dim3(step_threads<false, true>()), lds_bytes, s, a);
+    const dim3 island(step_threads<false, true>());
+    if (a.hot_bodies) {
+      if (learned) hipLaunchKernelGGL((step_kernel<true, true, true>), grid, block, lds_bytes, s, a);
+      else hipLaunchKernelGGL((step_kernel<false, true, true>), grid, island, lds_bytes, s, a);
+    } else {
+      if (learned) hipLaunchKernelGGL((step_kernel<true, true, false>), grid, block, lds_bytes, s, a);
+      else hipLaunchKernelGGL((step_kernel<false, true, false>), grid, island, lds_bytes, s, a);
+    }
   } else {
-    if (learned) hipLaunchKernelGGL((step_kernel<true, false>), grid, block, lds_bytes, s, a);
-    else hipLaunchKernelGGL((step_kernel<false, false>), grid, block, lds_bytes, s, a);
+    if (learned) hipLaunchKernelGGL((step_kernel<true, false, false>), grid, block, lds_bytes, s, a);
+    else hipLaunchKernelGGL((step_kernel<false, false, false>), grid, block, lds_bytes, s, a);
   }
   return (int)hipGetLastError();
 }

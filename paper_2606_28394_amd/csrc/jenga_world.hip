@@ -195,7 +195,9 @@ int32_t build_layout(jg_world* w) {
   auto lds_of = [&](int nb, int towers, int pushes) -> size_t {
     return (size_t)jg::lds_words(nb, pc_of(nb), std::max(1, towers), std::max(1, pushes), mode) * 4;
   };
-  int target = w->prm.pack_bodies > 0 ? w->prm.pack_bodies : 0;
+  // an on-chip pack holds at most kRegBodies bodies (the register broadphase); larger islands
+  // are kept in device memory, one tower each
+  int target = w->prm.pack_bodies > 0 ? std::min(w->prm.pack_bodies, jg::kRegBodies) : 0;
   if (target <= 0) {
     target = 8;
     const size_t budget = (w->prm.warm_start == 2 || w->prm.record_features) ? 40 * 1024 : 20 * 1024;
@@ -326,7 +328,7 @@ int32_t build_layout(jg_world* w) {
         return fail(JG_ECAPACITY, "a pack kept in device memory needs " + std::to_string(c.lds) +
                                   " bytes of LDS for its towers and pushes (max 163840)");
       c.gwords = ((int64_t)jg::kManDevWords * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
-                  jg::window_words(c.nbp) + 3) & ~(int64_t)3;
+                  jg::window_words(c.nbp) + (int64_t)jg::kCandPerBody * c.nbp + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
     } else {
       c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
