@@ -884,6 +884,27 @@ __device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, 
     pmax[p] = mx;
   }
   wave_sync();
+  if (nt == 1) {
+    // one tower (an island): the whole wave reduces its range
+    if (!only || only[0]) {
+      float sum = 0.f, mx = 0.f;
+      for (int p = L.tc0[0] + lane; p < L.tc1[0]; p += kWave) {
+        sum += psum[p];
+        mx = fmaxf(mx, pmax[p]);
+      }
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        sum += __shfl_xor(sum, d);
+        mx = fmaxf(mx, __shfl_xor(mx, d));
+      }
+      const int rows = 3 * L.tpts[0];
+      if (lane == 0) {
+        L.tres[0] = rows ? sqrtf(sum / (float)rows) : 0.f;
+        L.tres[1] = mx;
+      }
+    }
+    return;
+  }
   for (int t = lane; t < nt; t += kWave) {
     if (only && !only[t]) continue;
     float sum = 0.f, mx = 0.f;
@@ -894,6 +915,116 @@ __device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, 
     const int rows = 3 * L.tpts[t];
     L.tres[2 * t] = rows ? sqrtf(sum / (float)rows) : 0.f;
     L.tres[2 * t + 1] = mx;
+  }
+}
+
+// Contact manifolds of the canonical pairs p = first, first + stride, ... < nman, written into
+// their colour-sorted slots (points, normal, depth, and the previous step's impulses when kept).
+// Pairs are independent, so any number of threads can share the list.
+__device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a, int first, int stride, int nman,
+                                                bool keep_prev) {
+  const int NB = L.nbp, PC = L.pc;
+  const int nprev = L.scal[4];
+  for (int p = first; p < nman; p += stride) {
+    const int sidx = L.cpos[p];
+    if (sidx < 0) continue;
+    const uint32_t code = L.cab[p];
+    const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
+    float n[3], t1[3], rA[4][3], depth = 0.f;
+    uint32_t used = 0u, slots = 0u;
+    int npts = 0;
+    float R[9], he[3];
+    body_R(L, i, R);
+    load3(L.he, NB, i, he);
+    if (j == (int)kGround) {
+      // vertices below the ground: the four deepest (ties: lower vertex index), in index order
+      const float xz = L.x[2 * NB + i];
+      float vz[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
+        vz[k] = xz + (R[6] * s0 + R[7] * s1 + R[8] * s2);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        int rank = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rank += (vz[q] < 0.f) && (vz[q] < vz[k] || (vz[q] == vz[k] && q < k));
+        if ((vz[k] < 0.f) && rank < 4) {
+          const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
+          const float rx = R[0] * s0 + R[1] * s1 + R[2] * s2;
+          const float ry = R[3] * s0 + R[4] * s1 + R[5] * s2;
+          const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
+          // r_A = (rx, ry, (rz - xz)/2) in the frame n = -z, t1 = x, t2 = -y
+          mdev(L, sidx)[npts * 3 + 0] = 0.5f * (xz - rz);
+          mdev(L, sidx)[npts * 3 + 1] = rx;
+          mdev(L, sidx)[npts * 3 + 2] = -ry;
+          slots |= (uint32_t)k << (4 * npts);
+          depth = fmaxf(depth, -vz[k]);
+          ++npts;
+        }
+      }
+      n[0] = 0.f; n[1] = 0.f; n[2] = -1.f;
+      t1[0] = 1.f; t1[1] = 0.f; t1[2] = 0.f;
+    } else {
+      float RB[9], heB[3], d[3];
+      body_R(L, j, RB);
+      load3(L.he, NB, j, heB);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
+      sat_boxes(R, he, RB, heB, d, n, depth);   // same inputs as the narrowphase: same normal
+      used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+        if ((used >> s2) & 1u) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) mdev(L, sidx)[npts * 3 + k] = rA[s2][k];
+          slots |= (uint32_t)s2 << (4 * npts);
+          ++npts;
+        }
+    }
+    // warm start: previous step's impulses of the same (pair, slot) if the normal barely turned
+    int found = -1;
+    if (keep_prev && nprev > 0) {
+      int lo = 0, hi = nprev - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint32_t kk = L.pkey[mid];
+        if (kk == code) { found = mid; break; }
+        if (kk < code) lo = mid + 1; else hi = mid - 1;
+      }
+      if (found >= 0) {
+        const float pn[3] = {L.pnrm[found], L.pnrm[PC + found], L.pnrm[2 * PC + found]};
+        if (!(dot3(pn, n) > 0.95f)) found = -1;
+      }
+    }
+    for (int q = 0; q < npts; ++q) {
+      float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+      if (found >= 0) {
+        const uint32_t ps = L.pslot[found];
+        const int pnp = (int)(ps & 15u);
+        const uint32_t sq = (slots >> (4 * q)) & 15u;
+        for (int r = 0; r < pnp; ++r)
+          if (((ps >> (4 + 4 * r)) & 15u) == sq) {
+            l0 = L.plam[(r * 3 + 0) * PC + found];
+            l1 = L.plam[(r * 3 + 1) * PC + found];
+            l2 = L.plam[(r * 3 + 2) * PC + found];
+          }
+      }
+      mdev(L, sidx)[12 + q * 3 + 0] = l0;
+      mdev(L, sidx)[12 + q * 3 + 1] = l1;
+      mdev(L, sidx)[12 + q * 3 + 2] = l2;
+    }
+    L.mab[sidx] = code;
+    L.mmeta[sidx] = (uint32_t)npts | (slots << 12);
+    mdev(L, sidx)[27] = depth;
+    if (keep_prev) L.mcanon[sidx] = p;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mdev(L, sidx)[24 + k] = n[k];
+    const int ti = L.tw[i];
+    atomicAdd(&L.tcnt[ti * 4 + 1], 1u);
+    atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
+    atomicAdd(&L.tpts[ti], npts);
   }
 }
 
@@ -967,10 +1098,14 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   if constexpr (kThreads > kWave) {
     if (threadIdx.x >= kWave) {
-      // helper waves: per substep, the barrier where the first wave enters the sweeps, the
-      // sweeps, the barrier where it leaves them (the same count as the first wave's)
+      // helper waves: per substep they join the first wave in building the manifolds and in
+      // the sweeps, each between a barrier where it enters and one where it leaves (the same
+      // barriers, in the same order, as the first wave's)
       for (int s = 0; s < a.n_steps; ++s)
         for (int sub = 0; sub < a.n_sub; ++sub) {
+          __syncthreads();
+          build_manifolds(L, a, threadIdx.x, kThreads, L.scal[5], keep_prev);
+          __syncthreads();
           __syncthreads();
           pgs_sweeps(L, a.iters, L.scal[2], threadIdx.x, kThreads, a.restitution);
           __syncthreads();
@@ -1459,109 +1594,16 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       const int nkept = L.coloff[ncol];
 
       // ---- 6. manifolds into colour-sorted slots (+ warm start lookup) ----
-      const int nprev = L.scal[4];
-      for (int p = lane; p < nman; p += kWave) {
-        const int sidx = L.cpos[p];
-        if (sidx < 0) continue;
-        const uint32_t code = L.cab[p];
-        const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
-        float n[3], t1[3], rA[4][3], depth = 0.f;
-        uint32_t used = 0u, slots = 0u;
-        int npts = 0;
-        float R[9], he[3];
-        body_R(L, i, R);
-        load3(L.he, NB, i, he);
-        if (j == (int)kGround) {
-          // vertices below the ground: the four deepest (ties: lower vertex index), in index order
-          const float xz = L.x[2 * NB + i];
-          float vz[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
-            vz[k] = xz + (R[6] * s0 + R[7] * s1 + R[8] * s2);
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            int rank = 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) rank += (vz[q] < 0.f) && (vz[q] < vz[k] || (vz[q] == vz[k] && q < k));
-            if ((vz[k] < 0.f) && rank < 4) {
-              const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
-              const float rx = R[0] * s0 + R[1] * s1 + R[2] * s2;
-              const float ry = R[3] * s0 + R[4] * s1 + R[5] * s2;
-              const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
-              // r_A = (rx, ry, (rz - xz)/2) in the frame n = -z, t1 = x, t2 = -y
-              mdev(L, sidx)[npts * 3 + 0] = 0.5f * (xz - rz);
-              mdev(L, sidx)[npts * 3 + 1] = rx;
-              mdev(L, sidx)[npts * 3 + 2] = -ry;
-              slots |= (uint32_t)k << (4 * npts);
-              depth = fmaxf(depth, -vz[k]);
-              ++npts;
-            }
-          }
-          n[0] = 0.f; n[1] = 0.f; n[2] = -1.f;
-          t1[0] = 1.f; t1[1] = 0.f; t1[2] = 0.f;
-        } else {
-          float RB[9], heB[3], d[3];
-          body_R(L, j, RB);
-          load3(L.he, NB, j, heB);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
-          sat_boxes(R, he, RB, heB, d, n, depth);   // same inputs as the narrowphase: same normal
-          used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
-#pragma unroll
-          for (int s2 = 0; s2 < 4; ++s2)
-            if ((used >> s2) & 1u) {
-#pragma unroll
-              for (int k = 0; k < 3; ++k) mdev(L, sidx)[npts * 3 + k] = rA[s2][k];
-              slots |= (uint32_t)s2 << (4 * npts);
-              ++npts;
-            }
-        }
-        // warm start: previous step's impulses of the same (pair, slot) if the normal barely turned
-        int found = -1;
-        if (keep_prev && nprev > 0) {
-          int lo = 0, hi = nprev - 1;
-          while (lo <= hi) {
-            const int mid = (lo + hi) >> 1;
-            const uint32_t kk = L.pkey[mid];
-            if (kk == code) { found = mid; break; }
-            if (kk < code) lo = mid + 1; else hi = mid - 1;
-          }
-          if (found >= 0) {
-            const float pn[3] = {L.pnrm[found], L.pnrm[PC + found], L.pnrm[2 * PC + found]};
-            if (!(dot3(pn, n) > 0.95f)) found = -1;
-          }
-        }
-        for (int q = 0; q < npts; ++q) {
-          float l0 = 0.f, l1 = 0.f, l2 = 0.f;
-          if (found >= 0) {
-            const uint32_t ps = L.pslot[found];
-            const int pnp = (int)(ps & 15u);
-            const uint32_t sq = (slots >> (4 * q)) & 15u;
-            for (int r = 0; r < pnp; ++r)
-              if (((ps >> (4 + 4 * r)) & 15u) == sq) {
-                l0 = L.plam[(r * 3 + 0) * PC + found];
-                l1 = L.plam[(r * 3 + 1) * PC + found];
-                l2 = L.plam[(r * 3 + 2) * PC + found];
-              }
-          }
-          mdev(L, sidx)[12 + q * 3 + 0] = l0;
-          mdev(L, sidx)[12 + q * 3 + 1] = l1;
-          mdev(L, sidx)[12 + q * 3 + 2] = l2;
-        }
-        L.mab[sidx] = code;
-        L.mmeta[sidx] = (uint32_t)npts | (slots << 12);
-        mdev(L, sidx)[27] = depth;
-        if (keep_prev) L.mcanon[sidx] = p;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) mdev(L, sidx)[24 + k] = n[k];
-        const int ti = L.tw[i];
-        atomicAdd(&L.tcnt[ti * 4 + 1], 1u);
-        atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
-        atomicAdd(&L.tpts[ti], npts);
+      // (an island's helper waves join in between the two barriers)
+      if constexpr (kThreads > kWave) {
+        L.scal[5] = nman;
+        __syncthreads();
+        build_manifolds(L, a, threadIdx.x, kThreads, nman, keep_prev);
+        __syncthreads();
+      } else {
+        build_manifolds(L, a, lane, kWave, nman, keep_prev);
+        wave_sync();
       }
-      wave_sync();
       timer.mark(L, lane, 4);
 
       // ---- learned warm start: features, network, initial impulses; feature records ----
