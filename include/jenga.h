@@ -51,7 +51,7 @@ typedef enum {
 } jg_status;
 
 /* Device error-word bits reported by jg_query_stats. */
-#define JG_ERR_CANDIDATES 1u   /* an island in device memory had more than 16 broadphase candidates per body */
+#define JG_ERR_CANDIDATES 1u   /* a body of an island in device memory had more than 16 broadphase candidates */
 #define JG_ERR_MANIFOLDS 2u    /* colliding pairs exceeded the pack capacity */
 #define JG_ERR_COLOURS 4u      /* a manifold needed more than 64 colours (dropped) */
 #define JG_ERR_NAN 8u          /* non-finite body state */

@@ -114,7 +114,7 @@ constexpr int kRegBodies = 256;    // largest pack the LDS path takes (register 
 __host__ __device__ inline int64_t window_words(int nbp) { return 6 * (int64_t)((nbp + 63) / 64); }
 
 // an island in device memory lists its broadphase candidates of a step: at most this many per
-// body (more sets JG_ERR_CANDIDATES)
+// body (more sets JG_ERR_CANDIDATES and keeps the first ones)
 constexpr int kCandPerBody = 16;
 
 // LDS words of a pack kept in device memory: its small arrays (phase counters, colour offsets,

@@ -90,6 +90,7 @@ struct Lds {
   uint32_t *tfb, *tfc;
   float* wbox;        // global packs: per 64-body window, AABB lo[3], hi[3] (broadphase)
   uint32_t* cand;     // global packs: the broadphase candidates of a step, canonical order
+  uint32_t* cslot;    // global packs: kCandPerBody candidate slots per body (the walk's output)
   int nbp, pc;
 };
 
@@ -148,6 +149,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool u
   }
   L.wbox = a.in_gmem ? take((int)window_words(nb)) : nullptr;
   L.cand = a.in_gmem ? (uint32_t*)take(kCandPerBody * nb) : nullptr;
+  L.cslot = a.in_gmem ? (uint32_t*)take(kCandPerBody * nb) : nullptr;
   // the colouring's lane masks reuse the sorted-manifold words (free until the manifolds are
   // written)
   L.lmlo = L.mab;
@@ -1278,11 +1280,12 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
         wave_sync();
         const float slack = a.margin * 1.01f + 1e-6f;   // a filter: wider than the pair test
         // The candidates of the 64 bodies i = i0 + lane, each lane's in canonical order (j
-        // ascending, the ground last): counted, or written from out + off.  Windows are visited
+        // ascending, the ground last): counted, and the first kCandPerBody written from out + off.  Windows are visited
         // in order; a window near none of the 64 is skipped, and a near one is loaded into
         // registers (lane l: body 64 w + l) and broadcast body by body with readlane, so the
         // tests of one lane wait on no memory.
         auto walk = [&](int i0, uint32_t* out, int off) -> int {
+          constexpr int lim = kCandPerBody;
           const int i = i0 + lane;
           const uint32_t fi = i < nb ? L.flag[i] : 0u;
           const bool act = (fi & kActive) != 0;
@@ -1339,24 +1342,31 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
                                  (fabsf(xi[1] - d[1]) <= hi[1] + h[1] + a.margin) &
                                  (fabsf(xi[2] - d[2]) <= hi[2] + h[2] + a.margin);
                 if (hit) {
-                  if (out) out[off + c] = ((uint32_t)i << 16) | (uint32_t)j;
+                  if (c < lim) out[off + c] = ((uint32_t)i << 16) | (uint32_t)j;
                   ++c;
                 }
               }
             }
           }
           if (act && dyni && (xi[2] - hi[2] <= a.margin)) {
-            if (out) out[off + c] = ((uint32_t)i << 16) | kGround;
+            if (c < lim) out[off + c] = ((uint32_t)i << 16) | kGround;
             ++c;
           }
           return c;
         };
-        // counts into the (still unused) colouring lane masks, then an exclusive scan in place
+        // one walk: each body's candidates into its own kCandPerBody slots, counts into the (still
+        // unused) colouring lane masks; an exclusive scan of the counts places each body's run in
+        // the canonical list, and the runs are copied there.  A body with more candidates than
+        // its slots keeps the first kCandPerBody (flagged).
         uint32_t* const cnt = L.lmlo;
+        bool over = false;
         for (int i0 = 0; i0 < nb; i0 += kWave) {
-          const int c = walk(i0, nullptr, 0);
-          if (i0 + lane < nb) cnt[i0 + lane] = (uint32_t)c;
+          const int i = i0 + lane;
+          const int c = walk(i0, L.cslot, i * kCandPerBody);
+          over = over || c > kCandPerBody;
+          if (i < nb) cnt[i] = (uint32_t)min(c, kCandPerBody);
         }
+        if (__any(over) && lane == 0) L.scal[3] |= kErrCand;
         wave_sync();
         uint32_t run = 0;
         for (int i0 = 0; i0 < nb; i0 += kWave) {
@@ -1368,27 +1378,19 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
             const uint32_t t = __shfl_up(incl, d);
             if (lane >= d) incl += t;
           }
-          if (i < nb) cnt[i] = run + incl - c;
+          if (i < nb) {
+            const uint32_t off = run + incl - c;
+            uint32_t v[kCandPerBody];
+#pragma unroll
+            for (int k = 0; k < kCandPerBody; ++k)
+              if (k < (int)c) v[k] = L.cslot[i * kCandPerBody + k];
+#pragma unroll
+            for (int k = 0; k < kCandPerBody; ++k)
+              if (k < (int)c) L.cand[off + k] = v[k];
+          }
           run += __shfl(incl, kWave - 1);
         }
-        wave_sync();
-        // the list holds kCandPerBody per body; bodies whose candidates would run past its end are
-        // left out whole (flagged), so the list stays a canonical prefix
-        const int cap = kCandPerBody * nb;
-        int fit = 0;
-        for (int i0 = 0; i0 < nb; i0 += kWave) {
-          const int i = i0 + lane;
-          const int off = i < nb ? (int)cnt[i] : 0;
-          const int end = i + 1 < nb ? (int)cnt[i + 1] : (int)run;
-          const bool keep = i < nb && end <= cap;
-          if (keep) fit = max(fit, end);
-          // lanes whose run does not fit count without writing
-          walk(i0, keep ? L.cand : nullptr, off);
-        }
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) fit = max(fit, __shfl_xor(fit, d));
-        const int total = fit;
-        if ((int)run > cap && lane == 0) L.scal[3] |= kErrCand;
+        const int total = (int)run;
         wave_sync();
         for (int c0 = 0; c0 < total; c0 += kWave) {
           const int n = min(kWave, total - c0);
@@ -1400,7 +1402,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
           wave_sync();
         }
         tail = head;
-        if (lane == 0) L.tcnt[0] += (uint32_t)run;   // an island is one tower
+        if (lane == 0) L.tcnt[0] += (uint32_t)run;   // an island is one tower (kept candidates)
       } else {
         float wx[kWindows][3], wh[kWindows][3];
         uint32_t wf[kWindows];

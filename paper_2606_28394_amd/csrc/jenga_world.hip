@@ -328,7 +328,7 @@ int32_t build_layout(jg_world* w) {
         return fail(JG_ECAPACITY, "a pack kept in device memory needs " + std::to_string(c.lds) +
                                   " bytes of LDS for its towers and pushes (max 163840)");
       c.gwords = ((int64_t)jg::kManDevWords * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
-                  jg::window_words(c.nbp) + (int64_t)jg::kCandPerBody * c.nbp + 3) & ~(int64_t)3;
+                  jg::window_words(c.nbp) + 2 * (int64_t)jg::kCandPerBody * c.nbp + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
     } else {
       c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
