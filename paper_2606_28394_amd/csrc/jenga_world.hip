@@ -32,16 +32,22 @@ struct DevBuf {
   size_t n = 0;
   hipError_t ensure(size_t count) {
     if (count <= n && p) return hipSuccess;
-    if (p) { hipFree(p); p = nullptr; n = 0; }
+    if (p) {
+      const hipError_t f = hipFree(p);
+      p = nullptr;
+      n = 0;
+      if (f != hipSuccess) return f;
+    }
     size_t c = count ? count : 1;
     hipError_t e = hipMalloc((void**)&p, c * sizeof(T));
     if (e == hipSuccess) n = c;
     return e;
   }
-  void release() {
-    if (p) hipFree(p);
+  hipError_t release() {
+    const hipError_t e = p ? hipFree(p) : hipSuccess;
     p = nullptr;
     n = 0;
+    return e;
   }
 };
 
@@ -552,25 +558,32 @@ int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodi
 
 int32_t jg_destroy_world(jg_world* w) {
   if (!w) return JG_OK;
-  hipSetDevice(w->prm.device);
-  hipStreamSynchronize(w->stream);
-  w->d_x.release(); w->d_q.release(); w->d_v.release(); w->d_w.release(); w->d_he.release();
-  w->d_mass.release(); w->d_flags.release(); w->d_body_tower.release();
-  w->d_pack_body0.release(); w->d_pack_tower0.release(); w->d_pack_push0.release(); w->d_pack_slot0.release();
-  w->d_tower_body0.release();
-  w->d_pack_goff.release(); w->d_gmem.release();
-  w->d_tower_mu.release(); w->d_push_body.release(); w->d_push_start.release(); w->d_push_steps.release();
-  w->d_push_force.release(); w->d_push_withdraw.release(); w->d_push_x0.release();
-  w->d_tower_count.release(); w->d_tower_res.release(); w->d_pack_error.release();
-  w->d_out_ab.release(); w->d_out_meta.release(); w->d_out_geo.release(); w->d_out_pts.release();
-  w->d_out_count.release(); w->d_out_tower.release();
-  w->d_prev_key.release(); w->d_prev_data.release(); w->d_prev_count.release();
-  w->d_phase_cycles.release();
-  w->d_mlp_params.release(); w->d_mlp_packed.release(); w->d_feat.release(); w->d_tower_fallback.release();
-  for (hipStream_t s : w->aux) { hipStreamSynchronize(s); hipStreamDestroy(s); }
-  for (hipEvent_t e : w->aux_done) hipEventDestroy(e);
-  if (w->fork) hipEventDestroy(w->fork);
+  // tear everything down even if a call fails; report the first failure
+  hipError_t first = hipSuccess;
+  auto note = [&](hipError_t e) { if (first == hipSuccess && e != hipSuccess) first = e; };
+  note(hipSetDevice(w->prm.device));
+  note(hipStreamSynchronize(w->stream));
+  for (hipStream_t s : w->aux) note(hipStreamSynchronize(s));
+  note(w->d_x.release()); note(w->d_q.release()); note(w->d_v.release()); note(w->d_w.release());
+  note(w->d_he.release()); note(w->d_mass.release()); note(w->d_flags.release()); note(w->d_body_tower.release());
+  note(w->d_pack_body0.release()); note(w->d_pack_tower0.release()); note(w->d_pack_push0.release());
+  note(w->d_pack_slot0.release()); note(w->d_tower_body0.release());
+  note(w->d_pack_goff.release()); note(w->d_gmem.release());
+  note(w->d_tower_mu.release()); note(w->d_push_body.release()); note(w->d_push_start.release());
+  note(w->d_push_steps.release()); note(w->d_push_force.release()); note(w->d_push_withdraw.release());
+  note(w->d_push_x0.release());
+  note(w->d_tower_count.release()); note(w->d_tower_res.release()); note(w->d_pack_error.release());
+  note(w->d_out_ab.release()); note(w->d_out_meta.release()); note(w->d_out_geo.release());
+  note(w->d_out_pts.release()); note(w->d_out_count.release()); note(w->d_out_tower.release());
+  note(w->d_prev_key.release()); note(w->d_prev_data.release()); note(w->d_prev_count.release());
+  note(w->d_phase_cycles.release());
+  note(w->d_mlp_params.release()); note(w->d_mlp_packed.release()); note(w->d_feat.release());
+  note(w->d_tower_fallback.release());
+  for (hipStream_t s : w->aux) note(hipStreamDestroy(s));
+  for (hipEvent_t e : w->aux_done) note(hipEventDestroy(e));
+  if (w->fork) note(hipEventDestroy(w->fork));
   delete w;
+  if (first != hipSuccess) return fail(JG_EDEVICE, std::string("releasing the world: ") + hipGetErrorString(first));
   return JG_OK;
 }
 
