@@ -577,7 +577,6 @@ __device__ __forceinline__ void manifold_open(const Lds& L, int m, int& a, int& 
 
 __device__ __forceinline__ void load_point(const Lds& L, int m, int j, const float dAB[3], float rA[3], float rB[3],
                                   float lam[3]) {
-  const int pc = L.pc;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     rA[k] = mdev(L, m)[j * 3 + k];
@@ -754,7 +753,7 @@ __device__ __forceinline__ void residual_manifold(const Lds& L, int m, float mu,
 // F r_A, F r_B, F (relative velocity of B with respect to A at the point).  The ground is a
 // body at (x_A, y_A, 0) with the identity orientation.
 __device__ __forceinline__ void point_features(const Lds& L, int m, int j, float gdt, float f[mlp::kFeat]) {
-  const int nb = L.nbp, pc = L.pc;
+  const int nb = L.nbp;
   const uint32_t ab = L.mab[m];
   const int ia = (int)(ab >> 16), ib = (int)(ab & 0xffffu);
   const bool ground = ib == (int)kGround;
@@ -1316,7 +1315,8 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
               }
               bool near = act;
 #pragma unroll
-              for (int k = 0; k < 3; ++k) near = near & (xi[k] - hi[k] <= hb[k] + slack) & (xi[k] + hi[k] + slack >= lo[k]);
+              for (int k = 0; k < 3; ++k)
+                near = ((int)near & (int)(xi[k] - hi[k] <= hb[k] + slack) & (int)(xi[k] + hi[k] + slack >= lo[k])) != 0;
               if (!__any(near)) continue;
               const int jl = w * kWave + lane;
               const bool inj = jl < nb;
@@ -1337,10 +1337,12 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
                   d[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xj[k]), jj));
                   h[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hj[k]), jj));
                 }
-                const bool hit = near & (j > i) & ((f & kActive) != 0) & (dyni | ((f & kDynamic) != 0)) &
-                                 (fabsf(xi[0] - d[0]) <= hi[0] + h[0] + a.margin) &
-                                 (fabsf(xi[1] - d[1]) <= hi[1] + h[1] + a.margin) &
-                                 (fabsf(xi[2] - d[2]) <= hi[2] + h[2] + a.margin);
+                const int hitm = (int)near & (int)(j > i) & (int)((f & kActive) != 0) &
+                                 ((int)dyni | (int)((f & kDynamic) != 0)) &
+                                 (int)(fabsf(xi[0] - d[0]) <= hi[0] + h[0] + a.margin) &
+                                 (int)(fabsf(xi[1] - d[1]) <= hi[1] + h[1] + a.margin) &
+                                 (int)(fabsf(xi[2] - d[2]) <= hi[2] + h[2] + a.margin);
+                const bool hit = hitm != 0;
                 if (hit) {
                   if (c < lim) out[off + c] = ((uint32_t)i << 16) | (uint32_t)j;
                   ++c;

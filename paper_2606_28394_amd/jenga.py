@@ -18,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjenga.so")
 
 JG_OK, JG_EINVAL, JG_ENOMEM, JG_EDEVICE, JG_ECAPACITY, JG_ESTATE, JG_ENAN = 0, -1, -2, -3, -4, -5, -6
+# device error-word bits (jg_stats.error_word)
+JG_ERR_CANDIDATES, JG_ERR_MANIFOLDS, JG_ERR_COLOURS, JG_ERR_NAN = 1, 2, 4, 8
 ERR_CANDIDATES, ERR_MANIFOLDS, ERR_COLOURS, ERR_NAN = 1, 2, 4, 8
 
 EXPORTS = ["jg_default_params", "jg_create_world", "jg_destroy_world", "jg_add_boxes", "jg_set_friction",

@@ -97,3 +97,15 @@ def test_missing_library_fails_loudly(tmp_path):
             J.load_library(str(tmp_path / "libjenga.so"))
     finally:
         J._lib = saved
+
+
+def test_status_codes_and_error_bits_match_header():
+    """The binding's status codes and device error-word bits are the header's."""
+    from paper_2606_28394_amd import jenga as J
+    src = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"\b(JG_[A-Z]+)\s*=\s*(-?\d+)", src))
+    bits = dict((k, int(v)) for k, v in re.findall(r"#define\s+(JG_ERR_[A-Z]+)\s+(\d+)u", src))
+    assert set(codes) >= {"JG_OK", "JG_EINVAL", "JG_ENOMEM", "JG_EDEVICE", "JG_ECAPACITY", "JG_ESTATE", "JG_ENAN"}
+    assert len(bits) == 4
+    for k, v in list(codes.items()) + list(bits.items()):
+        assert getattr(J, k) == v, k

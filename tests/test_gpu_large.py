@@ -173,3 +173,26 @@ def test_device_memory_path_matches_lds_path(J):
             np.testing.assert_array_equal(x, y)
         for w in (lds, dev, again, ref):
             w.close()
+
+
+def test_candidate_overflow_is_flagged(J):
+    """An island body with more than 16 broadphase candidates (a slab under 20 blocks, in a
+    300-body island) is reported with JG_ERR_CANDIDATES, not written past its slots."""
+    n_top, n_fill = 20, 279
+    he = [[1.0, 1.0, 0.05]] + [[0.05, 0.05, 0.05]] * (n_top + n_fill)
+    pos = [[0.0, 0.0, 0.05 - 1e-4]]
+    pos += [[-0.8 + 0.4 * (k % 5), -0.6 + 0.4 * (k // 5), 0.15 - 2e-4] for k in range(n_top)]
+    pos += [[5.0 + 0.2 * (k % 20), 0.2 * (k // 20), 0.05 - 1e-4] for k in range(n_fill)]
+    n = len(pos)
+    sb = W.SceneBuilder(W.default_params(), 1)
+    sb.add_tower(np.array(he), np.full(n, 0.5), np.array(pos), np.tile([1.0, 0, 0, 0], (n, 1)), 0.5,
+                 np.zeros((n, 3)), np.zeros((n, 3)))
+    sc = sb.build()
+    gw = J.World(sc)
+    gw.step(1)
+    assert gw.stats().error_word & J.JG_ERR_CANDIDATES
+    # the blocks far from the slab are unaffected: each rests on the ground with its four points
+    c = gw.contacts(0)
+    far = [k for k in range(1 + n_top, n) if ((c["body_a"] == k) & (c["body_b"] < 0)).sum() == 4]
+    assert len(far) == n_fill
+    gw.close()
