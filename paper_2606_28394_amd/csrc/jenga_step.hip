@@ -1493,10 +1493,14 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       timer.mark(L, lane, 2);
 
       // ---- 5. tower ranges of the canonical list; greedy first-fit colouring ----
-      for (int p = lane; p < nman; p += kWave) {
-        const int t = L.tw[L.cab[p] >> 16];
-        if (p == 0 || L.tw[L.cab[p - 1] >> 16] != t) L.tc0[t] = p;
-        if (p == nman - 1 || L.tw[L.cab[p + 1] >> 16] != t) L.tc1[t] = p + 1;
+      if (nt == 1) {
+        if (lane == 0 && nman > 0) { L.tc0[0] = 0; L.tc1[0] = nman; }
+      } else {
+        for (int p = lane; p < nman; p += kWave) {
+          const int t = L.tw[L.cab[p] >> 16];
+          if (p == 0 || L.tw[L.cab[p - 1] >> 16] != t) L.tc0[t] = p;
+          if (p == nman - 1 || L.tw[L.cab[p + 1] >> 16] != t) L.tc1[t] = p + 1;
+        }
       }
       // per-body lane masks of the current chunk (the sorted-manifold words are free until the
       // manifolds are written): lanes that touch body i, low and high 32 lanes
@@ -1509,10 +1513,13 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       // every earlier manifold of its chunk that shares a dynamic body is coloured.  Lanes
       // coloured in one round share no body, and each sees exactly the colours of all its
       // earlier neighbours, so the result equals the sequential greedy colouring.
+      // (the next chunk's codes are loaded while this one is coloured)
+      uint32_t code_next = lane < nman ? L.cab[lane] : 0u;
       for (int c0 = 0; c0 < nman; c0 += kWave) {
         const int p = c0 + lane;
         const bool valid = p < nman;
-        const uint32_t code = valid ? L.cab[p] : 0u;
+        const uint32_t code = code_next;
+        code_next = p + kWave < nman ? L.cab[p + kWave] : 0u;
         const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
         const bool di = valid && (L.flag[i] & kDynamic);
         const bool dj = valid && j != (int)kGround && (L.flag[j] & kDynamic);
@@ -1572,9 +1579,11 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       }
       wave_sync();
       // colour-sorted positions, canonical order inside each colour
+      int col_next = lane < nman ? L.cpos[lane] : -1;
       for (int c0 = 0; c0 < nman; c0 += kWave) {
         const int p = c0 + lane;
-        const int col = p < nman ? L.cpos[p] : -1;
+        const int col = col_next;
+        col_next = p + kWave < nman ? L.cpos[p + kWave] : -1;
         int pos = -1;
         uint64_t pending = __ballot(col >= 0);
         while (pending) {
@@ -1589,7 +1598,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
         }
         if (p < nman) {
           L.cpos[p] = pos;
-          if (col >= 0) atomicMax(&L.tcnt[L.tw[L.cab[p] >> 16] * 4 + 3], (uint32_t)(col + 1));
+          if (col >= 0) atomicMax(&L.tcnt[(nt == 1 ? 0 : L.tw[L.cab[p] >> 16]) * 4 + 3], (uint32_t)(col + 1));
         }
       }
       wave_sync();
