@@ -28,6 +28,8 @@
 //     omega re-derived from the angular momentum (Eq. (newton_euler), torque free)
 //  10 Baumgarte correction (Eq. (baumgarte)), colour by colour
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <math.h>
 #include <stdint.h>
 
@@ -39,6 +41,7 @@ namespace {
 
 constexpr uint32_t kGround = 0xffffu;
 constexpr int kIslandWaves = 8;   // waves of a workgroup that steps an island in device memory
+constexpr int kMaxDevices = 64;
 
 // A barrier among the lanes of one wave.  Every phase runs on one wave (the workgroup's first),
 // so this is all its steps need: LDS and device-memory accesses of one wave are performed in
@@ -1948,16 +1951,25 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
 }  // namespace
 
 int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    const void* variants[6] = {(const void*)step_kernel<false, false, false>,
-                               (const void*)step_kernel<true, false, false>,
-                               (const void*)step_kernel<false, true, false>, (const void*)step_kernel<true, true, false>,
-                               (const void*)step_kernel<false, true, true>, (const void*)step_kernel<true, true, true>};
-    for (const void* f : variants)
-      if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
-        return (int)e;
-    attr_set = true;
+  // the dynamic-LDS limit of every variant, once per device (the current one), under a lock so
+  // that worlds stepped from several host threads agree
+  static std::mutex attr_mutex;
+  static bool attr_set[kMaxDevices] = {};
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  {
+    std::lock_guard<std::mutex> lock(attr_mutex);
+    if (!attr_set[dev]) {
+      const void* variants[6] = {(const void*)step_kernel<false, false, false>,
+                                 (const void*)step_kernel<true, false, false>,
+                                 (const void*)step_kernel<false, true, false>, (const void*)step_kernel<true, true, false>,
+                                 (const void*)step_kernel<false, true, true>, (const void*)step_kernel<true, true, true>};
+      for (const void* f : variants)
+        if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
+          return (int)e;
+      attr_set[dev] = true;
+    }
   }
   const bool learned = a.warm_start == 2 || a.feat_out;
   const dim3 grid(a.n_packs), block(kWave);
