@@ -232,6 +232,36 @@ def large_island(J, torch, W, steps):
             "error_word": int(s1.error_word)}
 
 
+def single_tower_latency(J, torch, W):
+    """The 18-level tower with one middle block removed: 240 steps in one launch, time per step
+    (one wave on one CU: a latency figure, the GPU is nearly idle)."""
+    scene = W.cfg1(0)
+    stream = torch.cuda.current_stream()
+    world = J.World(scene, stream=stream.cuda_stream)
+    world.step(0)
+    world.sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    world.step(240)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    world.close()
+    log(f"  removal tower: {ms / 240 * 1e3:.1f} us per step")
+    return {"workload": "one 18-level tower (53 blocks after one middle block is removed), 240 steps",
+            "us_per_step": ms / 240 * 1e3}
+
+
+def literal_tilt_rate(J, torch, W, steps):
+    """The throughput batch with tilts of U(0, 3 deg) alone: the towers keep standing (resting
+    contacts throughout)."""
+    scene = W.cfg3(0, n_steps=steps, literal_tilt=True)
+    v, ms, st = _run_timed(J, torch, scene, steps)
+    log(f"  standing towers: {v:.4g} tower-steps/s")
+    return {"workload": f"throughput batch with tilts of U(0, 3 deg): {scene['n_towers']} standing towers, "
+                        f"{steps} steps", "value": v, "kernel_ms": ms, "error_word": int(st.error_word)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +278,8 @@ def main():
     ap.add_argument("--cpu-report", action="store_true",
                     help="also time the oracle single-threaded and on all host threads over samples of "
                          "every workload (a few minutes)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the single-tower latency and standing-tower legs")
     ap.add_argument("--island-steps", type=int, default=100,
                     help="steps of the large-island leg (one 64 x 64 masonry wall); 0 skips it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
@@ -355,6 +387,10 @@ def main():
         "residual_rms_max": s1.residual_rms,
     }
     world.close()
+    if not args.no_extra:
+        log("single-tower latency and standing-tower legs ...")
+        out["single_tower"] = single_tower_latency(J, torch, W)
+        out["standing_towers"] = literal_tilt_rate(J, torch, W, args.steps)
     if args.island_steps > 0:
         log("large-island leg (64 x 64 masonry wall) ...")
         out["large_island"] = large_island(J, torch, W, args.island_steps)
