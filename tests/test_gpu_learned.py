@@ -206,3 +206,41 @@ def test_learned_mode_needs_network(J):
     with pytest.raises(J.JengaError):
         gw.step(1)
     gw.close()
+
+
+def test_learned_and_records_in_device_memory_match_lds(J):
+    """The learned warm start and the feature records with the layout in device memory
+    (pack_bodies = -1) against the LDS path, one step from the same state: the same pairs and
+    fallbacks, state and impulses within the parity tolerances, records close."""
+    sc = _scene(6, seed=3)
+    net = _net(5)
+    G_DT = 9.81 / 240.0
+    for kw in (dict(warm_start=2, mlp=net, mlp_iters=4, fallback_tau=1e30),
+               dict(warm_start=2, mlp=net, mlp_iters=4, fallback_tau=0.0),
+               dict(record_features=True)):
+        lds = J.World(sc, **kw)
+        dev = J.World(sc, pack_bodies=-1, **kw)
+        lds.step(1)
+        dev.step(1)
+        (lx, lq, lv, lw), (dx, dq, dv, dw) = lds.state(), dev.state()
+        ex = float((np.linalg.norm(lx - dx, axis=1) / np.maximum(np.linalg.norm(lx, axis=1), 0.075)).max())
+        ev = float((np.linalg.norm(lv - dv, axis=1) / np.maximum(np.linalg.norm(lv, axis=1), G_DT)).max())
+        ew = float((np.linalg.norm(lw - dw, axis=1) / np.maximum(np.linalg.norm(lw, axis=1), 1.0)).max())
+        _say(sorted(kw), "x", ex, "v", ev, "w", ew, "fallbacks", lds.stats().fallbacks, dev.stats().fallbacks)
+        assert ex <= 1e-5 and float(np.abs(lq - dq).max()) <= 1e-5 and ev <= 1e-4 and ew <= 1e-4
+        assert lds.stats().fallbacks == dev.stats().fallbacks
+        ptr = sc["tower_ptr"]
+        for t in range(sc["n_towers"]):
+            a = int(ptr[t])
+            ca, cb = gpu_manifolds(lds.contacts(t), a), gpu_manifolds(dev.contacts(t), a)
+            assert set(ca) == set(cb)
+            for key in ca:
+                assert ca[key]["colour"] == cb[key]["colour"] and ca[key]["slot"] == cb[key]["slot"]
+                scale = np.maximum(np.abs(ca[key]["lam"]), float(sc["mass"][a + key[0]]) * G_DT / 4.0)
+                assert (np.abs(ca[key]["lam"] - cb[key]["lam"]) / scale).max() <= 2e-4, (t, key)
+            if kw.get("record_features"):
+                fa, fb = lds.features(t), dev.features(t)
+                assert fa.shape == fb.shape
+                np.testing.assert_allclose(fa, fb, rtol=1e-4, atol=1e-6)
+        lds.close()
+        dev.close()
