@@ -371,7 +371,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "towers": T, "bodies": int(scene["tower_ptr"][-1]),
                    "pgs_iters": 20, "dt": 1 / 240, "warm_start": "previous step" if args.warm_start else "zero",
-                   "launch": "one persistent launch of all steps, one 64-lane workgroup per pack of towers"},
+                   "launch": "one persistent launch of all steps, one 64-lane workgroup per pack of towers, "
+                             "packs in four launch classes side by side"},
         "contact_iters_per_s": ci / wall,
         "kernel_ms": kernel_ms,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
