@@ -9,7 +9,9 @@ residual, integration, position correction).
 
 The K timed steps run as one persistent launch (jg_step_batch(world, K)) from the
 batch's initial state, with every input already resident in HBM; W warm-up steps run
-first and the initial state is then restored.  Prints one JSON line.
+first and the initial state is then restored.  Before that, the pack-size tuner
+(paper_2606_28394_amd/autotune.py) times a few pack sizes on the batch and the timed
+world uses its choice.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -56,7 +58,7 @@ def algorithmic_bytes(n_bodies_total, n_points_launch_end):
     return n_bodies_total * (13 * 4 * 2 + 5 * 4) + 32.0 * n_points_launch_end
 
 
-def traffic_from_profile(khash: str, workload: str, steps: int):
+def traffic_from_profile(khash: str, workload: str, steps: int, pack_bodies: int = 0):
     """HBM bytes of one launch of `steps` steps from the committed counter record (FETCH_SIZE +
     WRITE_SIZE of a launch of the same batch).  Nearly all of it is per step (the contact points'
     lever arms and impulses stream through device memory on every sweep), so the record scales
@@ -68,6 +70,8 @@ def traffic_from_profile(khash: str, workload: str, steps: int):
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != khash or not workload.startswith(rec.get("workload", "\0")):
+        return None
+    if int(rec.get("pack_bodies", 0)) != pack_bodies:   # counters taken with another packing
         return None
     return rec["hbm_bytes_per_launch"] * steps / rec["steps"]
 
@@ -282,6 +286,10 @@ def main():
                     help="skip the single-tower latency and standing-tower legs")
     ap.add_argument("--island-steps", type=int, default=100,
                     help="steps of the large-island leg (one 64 x 64 masonry wall); 0 skips it")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's pack size instead of timing candidates on the batch first")
+    ap.add_argument("--tune-steps", type=int, default=40,
+                    help="steps timed per candidate pack size (after a 60-step lead-in)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="first copy MB megabytes device to device once (a known-size reference for "
                          "profiler byte counters)")
@@ -313,7 +321,15 @@ def main():
     scene = W.cfg3(0, n_towers=args.towers, n_steps=args.steps)
     log(f"  {scene['n_towers']} towers, {int(scene['tower_ptr'][-1])} bodies in {time.perf_counter() - t0:.1f} s")
     stream = torch.cuda.current_stream()
-    world = J.World(scene, warm_start=args.warm_start, stream=stream.cuda_stream)
+    pack_bodies, tuned = 0, None
+    if not args.no_autotune:
+        from paper_2606_28394_amd import autotune as A
+        log("pack-size tuner ...")
+        t0 = time.perf_counter()
+        tuned = A.tune_pack_bodies(scene, steps=args.tune_steps, lead_in=60, warm_start=args.warm_start, log=log)
+        pack_bodies = tuned["pack_bodies"]
+        log(f"  chose pack_bodies {pack_bodies} in {time.perf_counter() - t0:.1f} s")
+    world = J.World(scene, warm_start=args.warm_start, stream=stream.cuda_stream, pack_bodies=pack_bodies)
     sizes = np.diff(scene["tower_ptr"]).tolist()
     init = world.state()
 
@@ -353,7 +369,7 @@ def main():
     flops = algorithmic_flops(sizes, args.steps, cand, man, pts, 20)
     achieved_tflops = flops / (kernel_ms * 1e-3) / 1e12
     workload = f"throughput batch: {T} tilted towers, 8-40 levels x 3 boxes, {args.steps} steps"
-    traffic = traffic_from_profile(kernel_hash(), workload, args.steps)
+    traffic = traffic_from_profile(kernel_hash(), workload, args.steps, pack_bodies)
     last_points = pts / max(1, args.steps)
     bytes_launch = algorithmic_bytes(int(scene["tower_ptr"][-1]), last_points)
     out = {
@@ -372,7 +388,11 @@ def main():
         "config": {"workload": workload, "towers": T, "bodies": int(scene["tower_ptr"][-1]),
                    "pgs_iters": 20, "dt": 1 / 240, "warm_start": "previous step" if args.warm_start else "zero",
                    "launch": "one persistent launch of all steps, one 64-lane workgroup per pack of towers, "
-                             "packs in four launch classes side by side"},
+                             "packs in four launch classes side by side",
+                   "pack_bodies": pack_bodies if pack_bodies else "library default",
+                   "pack_tuning": None if tuned is None else
+                   {"tower_steps_per_s": tuned["tower_steps_per_s"], "steps": tuned["steps"],
+                    "lead_in": tuned["lead_in"], "margin": tuned["margin"]}},
         "contact_iters_per_s": ci / wall,
         "kernel_ms": kernel_ms,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
