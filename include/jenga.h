@@ -79,6 +79,10 @@ typedef struct {
                             (pre-solve velocities, zero impulses, iters sweeps); default 1e30 */
   int32_t record_features;   /* 1: keep per-point feature records of each launch's last step
                                 (jg_query_features); default 0 */
+  int32_t use_graph;     /* 1: jg_step_batch replays a HIP graph holding the launch (one graph per step
+                            count, up to 8, built on first use and rebuilt when the layout, a device
+                            buffer or a parameter changes), so that a loop of short calls pays one graph
+                            launch per call; the results are those of the direct launch; default 0 */
 } jg_params;
 
 /* One contact point of the last solved step. */

@@ -147,6 +147,11 @@ inline int64_t lds_words(int nbp, int pc, int tpc, int ppc, int mode) {
 // queues one launch of the step kernel; returns the hipError_t of the launch (0 = success)
 int launch_step(const StepArgs& a, size_t lds_bytes, void* stream);
 
+// the kernel variant and workgroup size launch_step uses for these arguments (one workgroup
+// per pack, dynamic LDS as given to launch_step), for a kernel node of a graph; sets the
+// variants' dynamic-LDS limit on the current device first; returns a hipError_t (0 = success)
+int step_launch_config(const StepArgs& a, const void** func, unsigned* block_threads);
+
 // records the message returned by jg_last_error on this thread; returns code
 int32_t set_error(int32_t code, const std::string& msg);
 

@@ -1951,44 +1951,57 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
 
 }  // namespace
 
-int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
-  // the dynamic-LDS limit of every variant, once per device (the current one), under a lock so
-  // that worlds stepped from several host threads agree
+namespace {
+
+// The dynamic-LDS limit of every variant, once per device (the current one), under a lock so
+// that worlds stepped from several host threads agree.
+int ensure_lds_limit() {
   static std::mutex attr_mutex;
   static bool attr_set[kMaxDevices] = {};
   int dev = 0;
   if (hipError_t e = hipGetDevice(&dev)) return (int)e;
   if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
-  {
-    std::lock_guard<std::mutex> lock(attr_mutex);
-    if (!attr_set[dev]) {
-      const void* variants[6] = {(const void*)step_kernel<false, false, false>,
-                                 (const void*)step_kernel<true, false, false>,
-                                 (const void*)step_kernel<false, true, false>, (const void*)step_kernel<true, true, false>,
-                                 (const void*)step_kernel<false, true, true>, (const void*)step_kernel<true, true, true>};
-      for (const void* f : variants)
-        if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
-          return (int)e;
-      attr_set[dev] = true;
-    }
+  std::lock_guard<std::mutex> lock(attr_mutex);
+  if (!attr_set[dev]) {
+    const void* variants[6] = {(const void*)step_kernel<false, false, false>,
+                               (const void*)step_kernel<true, false, false>,
+                               (const void*)step_kernel<false, true, false>, (const void*)step_kernel<true, true, false>,
+                               (const void*)step_kernel<false, true, true>, (const void*)step_kernel<true, true, true>};
+    for (const void* f : variants)
+      if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
+        return (int)e;
+    attr_set[dev] = true;
   }
+  return 0;
+}
+
+}  // namespace
+
+int step_launch_config(const StepArgs& a, const void** func, unsigned* block_threads) {
+  if (int e = ensure_lds_limit()) return e;
   const bool learned = a.warm_start == 2 || a.feat_out;
-  const dim3 grid(a.n_packs), block(kWave);
-  hipStream_t s = (hipStream_t)stream;
+  const void* f;
+  unsigned threads = kWave;
   if (a.in_gmem) {
-    const dim3 island(step_threads<false, true>());
-    if (a.hot_bodies) {
-      if (learned) hipLaunchKernelGGL((step_kernel<true, true, true>), grid, block, lds_bytes, s, a);
-      else hipLaunchKernelGGL((step_kernel<false, true, true>), grid, island, lds_bytes, s, a);
-    } else {
-      if (learned) hipLaunchKernelGGL((step_kernel<true, true, false>), grid, block, lds_bytes, s, a);
-      else hipLaunchKernelGGL((step_kernel<false, true, false>), grid, island, lds_bytes, s, a);
-    }
+    if (a.hot_bodies)
+      f = learned ? (const void*)step_kernel<true, true, true> : (const void*)step_kernel<false, true, true>;
+    else
+      f = learned ? (const void*)step_kernel<true, true, false> : (const void*)step_kernel<false, true, false>;
+    if (!learned) threads = step_threads<false, true>();
   } else {
-    if (learned) hipLaunchKernelGGL((step_kernel<true, false, false>), grid, block, lds_bytes, s, a);
-    else hipLaunchKernelGGL((step_kernel<false, false, false>), grid, block, lds_bytes, s, a);
+    f = learned ? (const void*)step_kernel<true, false, false> : (const void*)step_kernel<false, false, false>;
   }
-  return (int)hipGetLastError();
+  *func = f;
+  *block_threads = threads;
+  return 0;
+}
+
+int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
+  const void* f = nullptr;
+  unsigned threads = 0;
+  if (int e = step_launch_config(a, &f, &threads)) return e;
+  void* args[1] = {const_cast<StepArgs*>(&a)};
+  return (int)hipLaunchKernel(f, dim3(a.n_packs), dim3(threads), args, lds_bytes, (hipStream_t)stream);
 }
 
 }  // namespace jg

@@ -135,9 +135,32 @@ struct jg_world {
   int64_t launched_points_iters = 0;
   bool stats_pending = false;
   int last_launch_steps = 0;
+  // graphs of the launch (use_graph): one kernel node per launch class, no edges between them
+  struct StepGraph {
+    int n_steps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+    std::vector<jg::StepArgs> args;   // as last set; step0 is rewritten on every replay
+    std::vector<size_t> lds;
+    std::vector<const void*> func;
+    std::vector<unsigned> block;
+  };
+  std::vector<StepGraph> graphs;    // most recently built last
 };
 
 namespace {
+
+hipError_t destroy_graph(jg_world::StepGraph& g) {
+  hipError_t first = hipSuccess;
+  if (g.exec) { first = hipGraphExecDestroy(g.exec); g.exec = nullptr; }
+  if (g.graph) {
+    hipError_t e = hipGraphDestroy(g.graph);
+    if (first == hipSuccess) first = e;
+    g.graph = nullptr;
+  }
+  return first;
+}
 
 int32_t check_world(jg_world* w) {
   if (!w) return fail(JG_EINVAL, "null world");
@@ -493,6 +516,89 @@ int32_t collect_stats(jg_world* w) {
   return JG_OK;
 }
 
+// The launch as a HIP graph: one kernel node per launch class and no edges, so the classes may
+// run side by side as on the forked streams of the direct launch.  A graph is kept per step
+// count and reused while every argument but the first step's index is unchanged (the same
+// layout, buffers and parameters); a replay rewrites that index in each node.  Graphs hold
+// kernel nodes only.
+int32_t launch_graph(jg_world* w, std::vector<jg::StepArgs>& cls, int n_steps) {
+  const size_t nc = cls.size();
+  auto matches = [&](const jg_world::StepGraph& g) {
+    if (g.n_steps != n_steps || g.args.size() != nc) return false;
+    for (size_t k = 0; k < nc; ++k) {
+      jg::StepArgs x = cls[k];
+      x.step0 = g.args[k].step0;
+      if (std::memcmp(&x, &g.args[k], sizeof(x)) != 0 || g.lds[k] != w->classes[k].lds) return false;
+    }
+    return true;
+  };
+  size_t gi = w->graphs.size();
+  for (size_t i = 0; i < w->graphs.size(); ++i)
+    if (w->graphs[i].n_steps == n_steps) { gi = i; break; }
+  const bool stale = gi < w->graphs.size() && !matches(w->graphs[gi]);
+  if (stale || (gi == w->graphs.size() && w->graphs.size() >= 8))
+    HIP_TRY(hipStreamSynchronize(w->stream));   // no launch of a graph in flight when it is destroyed
+  if (stale) {
+    // the layout, a buffer or a parameter changed since it was built
+    hipError_t e = destroy_graph(w->graphs[gi]);
+    w->graphs.erase(w->graphs.begin() + gi);
+    gi = w->graphs.size();
+    if (e != hipSuccess) return fail(JG_EDEVICE, std::string("destroying a stale graph: ") + hipGetErrorString(e));
+  }
+  if (gi == w->graphs.size()) {
+    if (w->graphs.size() >= 8) {
+      hipError_t e = destroy_graph(w->graphs.front());
+      w->graphs.erase(w->graphs.begin());
+      if (e != hipSuccess) return fail(JG_EDEVICE, std::string("destroying a graph: ") + hipGetErrorString(e));
+    }
+    jg_world::StepGraph g;
+    g.n_steps = n_steps;
+    g.args = cls;
+    g.nodes.resize(nc);
+    g.lds.resize(nc);
+    g.func.resize(nc);
+    g.block.resize(nc);
+    hipError_t e = hipGraphCreate(&g.graph, 0);
+    for (size_t k = 0; k < nc && e == hipSuccess; ++k) {
+      g.lds[k] = w->classes[k].lds;
+      if (int r = jg::step_launch_config(g.args[k], &g.func[k], &g.block[k])) { e = (hipError_t)r; break; }
+      void* kp[1] = {&g.args[k]};
+      hipKernelNodeParams p;
+      std::memset(&p, 0, sizeof(p));
+      p.func = const_cast<void*>(g.func[k]);
+      p.gridDim = dim3(g.args[k].n_packs);
+      p.blockDim = dim3(g.block[k]);
+      p.sharedMemBytes = (unsigned)g.lds[k];
+      p.kernelParams = kp;
+      p.extra = nullptr;
+      e = hipGraphAddKernelNode(&g.nodes[k], g.graph, nullptr, 0, &p);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      destroy_graph(g);
+      return fail(JG_EDEVICE, std::string("building the step graph: ") + hipGetErrorString(e));
+    }
+    w->graphs.push_back(std::move(g));
+    gi = w->graphs.size() - 1;
+  }
+  jg_world::StepGraph& g = w->graphs[gi];
+  for (size_t k = 0; k < nc; ++k) {
+    g.args[k].step0 = cls[k].step0;
+    void* kp[1] = {&g.args[k]};
+    hipKernelNodeParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.func = const_cast<void*>(g.func[k]);
+    p.gridDim = dim3(g.args[k].n_packs);
+    p.blockDim = dim3(g.block[k]);
+    p.sharedMemBytes = (unsigned)g.lds[k];
+    p.kernelParams = kp;
+    p.extra = nullptr;
+    HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.nodes[k], &p));
+  }
+  HIP_TRY(hipGraphLaunch(g.exec, w->stream));
+  return JG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -516,6 +622,7 @@ void jg_default_params(jg_params* p) {
   p->mlp_iters = 8;
   p->fallback_tau = 1e30;
   p->record_features = 0;
+  p->use_graph = 0;
 }
 
 const char* jg_last_error(void) { return g_err.c_str(); }
@@ -564,6 +671,7 @@ int32_t jg_destroy_world(jg_world* w) {
   note(hipSetDevice(w->prm.device));
   note(hipStreamSynchronize(w->stream));
   for (hipStream_t s : w->aux) note(hipStreamSynchronize(s));
+  for (auto& g : w->graphs) note(destroy_graph(g));
   note(w->d_x.release()); note(w->d_q.release()); note(w->d_v.release()); note(w->d_w.release());
   note(w->d_he.release()); note(w->d_mass.release()); note(w->d_flags.release()); note(w->d_body_tower.release());
   note(w->d_pack_body0.release()); note(w->d_pack_tower0.release()); note(w->d_pack_push0.release());
@@ -725,37 +833,44 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.tower_fallback = w->d_tower_fallback.p;
   a.mlp_iters = w->prm.mlp_iters;
   a.fallback_tau = (float)std::min(w->prm.fallback_tau, 3.0e38);
-  // Classes are independent (disjoint packs, towers and bodies): run them side by side, so a
-  // small batch fills the GPU and one class's tail overlaps the others.
   const size_t nc = w->classes.size();
-  while (w->aux.size() + 1 < nc) {
-    hipStream_t s;
-    hipEvent_t ev;
-    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    w->aux.push_back(s);
-    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    w->aux_done.push_back(ev);
-  }
-  if (nc > 1) {
-    if (!w->fork) HIP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(w->fork, w->stream));
-  }
+  std::vector<jg::StepArgs> cls(nc, a);
   for (size_t k = 0; k < nc; ++k) {
     const auto& c = w->classes[k];
-    hipStream_t s = k == 0 ? w->stream : w->aux[k - 1];
-    if (k > 0) HIP_TRY(hipStreamWaitEvent(s, w->fork, 0));
-    a.pack_first = c.first;
-    a.n_packs = c.count;
-    a.nbp = c.nbp; a.pc = c.pc; a.tpc = c.tpc; a.ppc = c.ppc;
-    a.gmem = w->d_gmem.p;
-    a.in_gmem = c.global ? 1 : 0;
-    a.hot_bodies = c.hot_bodies ? 1 : 0;
-    a.pack_goff = w->d_pack_goff.p;
-    if (int e = jg::launch_step(a, c.lds, s))
-      return fail(JG_EDEVICE, std::string("step kernel launch: ") + hipGetErrorString((hipError_t)e));
-    if (k > 0) HIP_TRY(hipEventRecord(w->aux_done[k - 1], s));
+    cls[k].pack_first = c.first;
+    cls[k].n_packs = c.count;
+    cls[k].nbp = c.nbp; cls[k].pc = c.pc; cls[k].tpc = c.tpc; cls[k].ppc = c.ppc;
+    cls[k].gmem = w->d_gmem.p;
+    cls[k].in_gmem = c.global ? 1 : 0;
+    cls[k].hot_bodies = c.hot_bodies ? 1 : 0;
+    cls[k].pack_goff = w->d_pack_goff.p;
   }
-  for (size_t k = 1; k < nc; ++k) HIP_TRY(hipStreamWaitEvent(w->stream, w->aux_done[k - 1], 0));
+  if (w->prm.use_graph) {
+    if (int32_t r = launch_graph(w, cls, n_steps)) return r;
+  } else {
+    // Classes are independent (disjoint packs, towers and bodies): run them side by side, so a
+    // small batch fills the GPU and one class's tail overlaps the others.
+    while (w->aux.size() + 1 < nc) {
+      hipStream_t s;
+      hipEvent_t ev;
+      HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      w->aux.push_back(s);
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      w->aux_done.push_back(ev);
+    }
+    if (nc > 1) {
+      if (!w->fork) HIP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(w->fork, w->stream));
+    }
+    for (size_t k = 0; k < nc; ++k) {
+      hipStream_t s = k == 0 ? w->stream : w->aux[k - 1];
+      if (k > 0) HIP_TRY(hipStreamWaitEvent(s, w->fork, 0));
+      if (int e = jg::launch_step(cls[k], w->classes[k].lds, s))
+        return fail(JG_EDEVICE, std::string("step kernel launch: ") + hipGetErrorString((hipError_t)e));
+      if (k > 0) HIP_TRY(hipEventRecord(w->aux_done[k - 1], s));
+    }
+    for (size_t k = 1; k < nc; ++k) HIP_TRY(hipStreamWaitEvent(w->stream, w->aux_done[k - 1], 0));
+  }
   w->step += n_steps;
   w->device_newer = true;
   w->stats_pending = true;

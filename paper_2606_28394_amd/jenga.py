@@ -38,7 +38,8 @@ class jg_params(C.Structure):
                 ("beta", C.c_double), ("slop", C.c_double), ("margin", C.c_double),
                 ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("pack_bodies", C.c_int32), ("manifolds_per_body", C.c_float),
-                ("mlp_iters", C.c_int32), ("fallback_tau", C.c_double), ("record_features", C.c_int32)]
+                ("mlp_iters", C.c_int32), ("fallback_tau", C.c_double), ("record_features", C.c_int32),
+                ("use_graph", C.c_int32)]
 
 
 class jg_contact(C.Structure):
@@ -360,7 +361,7 @@ class World:
 
     def __init__(self, scene: dict, warm_start: int = 0, stream=None, device: int = 0, pack_bodies: int = 0,
                  manifolds_per_body: float = 0.0, params: dict | None = None, mlp=None, mlp_iters: int = 8,
-                 fallback_tau: float = 1e30, record_features: bool = False):
+                 fallback_tau: float = 1e30, record_features: bool = False, use_graph: bool = False):
         pr = params or scene["params"]
         p = jg_default_params()
         p.gravity[:] = [float(g) for g in pr["gravity"]]
@@ -379,6 +380,7 @@ class World:
         p.mlp_iters = int(mlp_iters)
         p.fallback_tau = float(fallback_tau)
         p.record_features = int(bool(record_features))
+        p.use_graph = int(bool(use_graph))
         self.params = p
         T = int(scene["n_towers"])
         ptr = np.asarray(scene["tower_ptr"])
