@@ -212,14 +212,34 @@ __device__ __forceinline__ void store3(float* a, int stride, int i, const float 
   a[i] = o[0]; a[stride + i] = o[1]; a[2 * stride + i] = o[2];
 }
 
+// The contact-frame arithmetic below (basis, rotations into and out of the frame) is written
+// with explicit fused multiply-adds and no other contraction: a PGS visit then gives the same
+// bits whether one lane works both bodies or a lane pair works one body each, whatever the
+// compiler would fuse in either code.
+__device__ __forceinline__ float dot3x(const float a[3], const float b[3]) {
+#pragma clang fp contract(off)
+  return __builtin_fmaf(a[0], b[0], __builtin_fmaf(a[1], b[1], a[2] * b[2]));
+}
+__device__ __forceinline__ void sym_mulx(const float I[6], const float c[3], float o[3]) {
+#pragma clang fp contract(off)
+  o[0] = __builtin_fmaf(I[0], c[0], __builtin_fmaf(I[3], c[1], I[4] * c[2]));
+  o[1] = __builtin_fmaf(I[3], c[0], __builtin_fmaf(I[1], c[1], I[5] * c[2]));
+  o[2] = __builtin_fmaf(I[4], c[0], __builtin_fmaf(I[5], c[1], I[2] * c[2]));
+}
+
 __device__ __forceinline__ void tangent_basis(const float n[3], float t1[3], float t2[3]) {
+#pragma clang fp contract(off)
   float e[3] = {0.f, 0.f, 0.f};
   if (fabsf(n[0]) < 0.9f) e[0] = 1.f; else e[1] = 1.f;
-  const float en = dot3(e, n);
-  float t[3] = {e[0] - en * n[0], e[1] - en * n[1], e[2] - en * n[2]};
-  const float il = __builtin_amdgcn_rsqf(dot3(t, t));   // |t|^2 >= 0.19: no denormal scaling
+  const float en = dot3x(e, n);
+  float t[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[k] = __builtin_fmaf(-en, n[k], e[k]);
+  const float il = __builtin_amdgcn_rsqf(dot3x(t, t));   // |t|^2 >= 0.19: no denormal scaling
   t1[0] = t[0] * il; t1[1] = t[1] * il; t1[2] = t[2] * il;
-  cross3(n, t1, t2);
+  t2[0] = __builtin_fmaf(n[1], t1[2], -(n[2] * t1[1]));
+  t2[1] = __builtin_fmaf(n[2], t1[0], -(n[0] * t1[2]));
+  t2[2] = __builtin_fmaf(n[0], t1[1], -(n[1] * t1[0]));
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -451,11 +471,12 @@ __device__ __forceinline__ void make_frame(const float n[3], Frame& F) {
   tangent_basis(n, F.f[1], F.f[2]);
 }
 __device__ __forceinline__ void to_local(const Frame& F, const float v[3], float o[3]) {
-  o[0] = dot3(F.f[0], v); o[1] = dot3(F.f[1], v); o[2] = dot3(F.f[2], v);
+  o[0] = dot3x(F.f[0], v); o[1] = dot3x(F.f[1], v); o[2] = dot3x(F.f[2], v);
 }
 __device__ __forceinline__ void to_world(const Frame& F, const float o[3], float v[3]) {
+#pragma clang fp contract(off)
 #pragma unroll
-  for (int r = 0; r < 3; ++r) v[r] = F.f[0][r] * o[0] + F.f[1][r] * o[1] + F.f[2][r] * o[2];
+  for (int r = 0; r < 3; ++r) v[r] = __builtin_fmaf(F.f[0][r], o[0], __builtin_fmaf(F.f[1][r], o[1], F.f[2][r] * o[2]));
 }
 
 // body velocities and inverse inertia in the contact frame.  v0, w0 keep the velocities as
@@ -498,9 +519,9 @@ __device__ __forceinline__ void load_local(const Lds& L, int i, const Frame& F, 
   // F Iw F^T
   float g[3][3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) sym_mul(Iw, F.f[j], g[j]);
-  b.I[0] = dot3(F.f[0], g[0]); b.I[1] = dot3(F.f[1], g[1]); b.I[2] = dot3(F.f[2], g[2]);
-  b.I[3] = dot3(F.f[0], g[1]); b.I[4] = dot3(F.f[0], g[2]); b.I[5] = dot3(F.f[1], g[2]);
+  for (int j = 0; j < 3; ++j) sym_mulx(Iw, F.f[j], g[j]);
+  b.I[0] = dot3x(F.f[0], g[0]); b.I[1] = dot3x(F.f[1], g[1]); b.I[2] = dot3x(F.f[2], g[2]);
+  b.I[3] = dot3x(F.f[0], g[1]); b.I[4] = dot3x(F.f[0], g[2]); b.I[5] = dot3x(F.f[1], g[2]);
   b.im = im;
   b.dyn = im > 0.f;
 }
@@ -589,31 +610,103 @@ __device__ __forceinline__ void load_point(const Lds& L, int m, int j, const flo
   }
 }
 
+// One body's share of a PGS row, written out with explicit fused multiply-adds and no other
+// contraction, so that a row gives the same bits whether one lane works both bodies or two
+// lanes work one body each (the partial sums below are then swapped between the lanes).
+template <int K>
+struct SideRow {
+  static constexpr int i1 = (K == 0) ? 1 : 0;
+  static constexpr int i2 = (K == 2) ? 1 : 2;
+  float c1, c2;   // r x e_K
+  float i[3];     // I^-1 (r x e_K)
+  __device__ __forceinline__ void build(const LBody& s, const float r[3]) {
+#pragma clang fp contract(off)
+    axis_cross<K>(r, c1, c2);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) i[q] = __builtin_fmaf(s.I[sym_index(q, i1)], c1, s.I[sym_index(q, i2)] * c2);
+  }
+  // the body's term of the inverse effective mass, Eq. (keff)
+  __device__ __forceinline__ float kpart(const LBody& s) const {
+#pragma clang fp contract(off)
+    return s.im + __builtin_fmaf(c1, i[i1], c2 * i[i2]);
+  }
+  // the velocity of the body's contact point along e_K
+  __device__ __forceinline__ float vpart(const LBody& s) const {
+#pragma clang fp contract(off)
+    return s.v[K] + __builtin_fmaf(c1, s.w[i1], c2 * s.w[i2]);
+  }
+  // impulse sdl along e_K on the body (A takes -dl, B takes +dl)
+  __device__ __forceinline__ void apply(LBody& s, float sdl) const {
+    s.v[K] = __builtin_fmaf(s.im, sdl, s.v[K]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s.w[q] = __builtin_fmaf(sdl, i[q], s.w[q]);
+  }
+};
+
+// the row's new impulse from its relative velocity u and inverse effective mass k:
+// Eq. (lambda_n) with restitution for the normal row, the clipped Eq. (coulomb_pgs) for a tangent
+template <bool kNormal>
+__device__ __forceinline__ float row_lambda(float lam, float u, float k, float bound, float e) {
+#pragma clang fp contract(off)
+  const float rk = __builtin_amdgcn_rcpf(k);
+  if constexpr (kNormal) return fmaxf(__builtin_fmaf(-((1.f + e) * u), rk, lam), 0.f);
+  else return fminf(fmaxf(__builtin_fmaf(-u, rk, lam), -bound), bound);
+}
+
+// one row on one lane, both bodies
+template <int K>
+__device__ __forceinline__ void row_single(LBody& A, LBody& B, const float rA[3], const float rB[3], float& lam,
+                                           float bound, float e) {
+#pragma clang fp contract(off)
+  SideRow<K> ta, tb;
+  ta.build(A, rA);
+  tb.build(B, rB);
+  const float k = ta.kpart(A) + tb.kpart(B);
+  const float u = tb.vpart(B) - ta.vpart(A);
+  const float nl = row_lambda<K == 0>(lam, u, k, bound, e);
+  const float dl = nl - lam;
+  ta.apply(A, -dl);
+  tb.apply(B, dl);
+  lam = nl;
+}
+
+// the partner lane's value (lanes 2p and 2p + 1 swap; both must be active)
+__device__ __forceinline__ float pair_swap(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+
+// one row on a lane pair: this lane holds body S (sg = -1: A, +1: B), its partner the other.
+// k = k_A + k_B and u = v_B - v_A come out bit for bit as in row_single (a sum does not depend
+// on its order of operands, and -(x - y) = y - x exactly).
+template <int K>
+__device__ __forceinline__ void row_pair(LBody& S, const float r[3], float& lam, float bound, float e, float sg) {
+#pragma clang fp contract(off)
+  SideRow<K> t;
+  t.build(S, r);
+  const float kp = t.kpart(S), vp = t.vpart(S);
+  const float k = kp + pair_swap(kp);
+  const float u = sg * (vp - pair_swap(vp));
+  const float nl = row_lambda<K == 0>(lam, u, k, bound, e);
+  const float dl = nl - lam;
+  t.apply(S, sg * dl);
+  lam = nl;
+}
+
 // one point's rows in order: Eq. (lambda_n), then Eq. (coulomb_pgs) on t1 and t2
 __device__ __forceinline__ void solve_point(LBody& A, LBody& B, const float rA[3], const float rB[3], float lam[3],
                                             float mu, float e) {
-  {
-    RowTerms<0> t;
-    t.build(A, B, rA, rB);
-    const float nl = fmaxf(lam[0] - (1.f + e) * t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), 0.f);
-    t.apply(A, B, nl - lam[0]);
-    lam[0] = nl;
-  }
+  row_single<0>(A, B, rA, rB, lam[0], 0.f, e);
   const float bound = mu * lam[0];
-  {
-    RowTerms<1> t;
-    t.build(A, B, rA, rB);
-    const float nl = fminf(fmaxf(lam[1] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
-    t.apply(A, B, nl - lam[1]);
-    lam[1] = nl;
-  }
-  {
-    RowTerms<2> t;
-    t.build(A, B, rA, rB);
-    const float nl = fminf(fmaxf(lam[2] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
-    t.apply(A, B, nl - lam[2]);
-    lam[2] = nl;
-  }
+  row_single<1>(A, B, rA, rB, lam[1], bound, e);
+  row_single<2>(A, B, rA, rB, lam[2], bound, e);
+}
+
+__device__ __forceinline__ void solve_point_pair(LBody& S, const float r[3], float lam[3], float mu, float e,
+                                                 float sg) {
+  row_pair<0>(S, r, lam[0], 0.f, e, sg);
+  const float bound = mu * lam[0];
+  row_pair<1>(S, r, lam[1], bound, e, sg);
+  row_pair<2>(S, r, lam[2], bound, e, sg);
 }
 
 // what one PGS visit of a manifold reads besides the bodies: its pair, point count, friction
@@ -663,33 +756,79 @@ __device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float e,
   for (int c = 0; c < 3; ++c) rec[3 + c] = make_float4(d.l[4 * c], d.l[4 * c + 1], d.l[4 * c + 2], d.l[4 * c + 3]);
 }
 
+// the same visit by a lane pair: lane 2p works body A, lane 2p + 1 body B (the ground: no
+// update); both hold the impulses, the first stores them
+__device__ __forceinline__ void solve_manifold_pair(const Lds& L, int m, float e, ManPoints& d, bool is_b) {
+  const int a = (int)(d.ab >> 16), b = (int)(d.ab & 0xffffu);
+  Frame F;
+  make_frame(d.n, F);
+  const int me = is_b ? b : a;
+  LBody S;
+  load_local<true>(L, me, F, S);
+  float dAB[3] = {0.f, 0.f, 0.f};
+  if (b != (int)kGround) {
+    float dx[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dx[k] = L.x[k * L.nbp + a] - L.x[k * L.nbp + b];
+    to_local(F, dx, dAB);
+  }
+  const float sg = is_b ? 1.f : -1.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < d.np) {
+      float r[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r[k] = is_b ? d.r[3 * j + k] + dAB[k] : d.r[3 * j + k];
+      solve_point_pair(S, r, &d.l[3 * j], d.mu, e, sg);
+    }
+  }
+  store_local(L, me, F, S);
+  if (!is_b) {
+    float4* rec = reinterpret_cast<float4*>(mdev(L, m));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rec[3 + c] = make_float4(d.l[4 * c], d.l[4 * c + 1], d.l[4 * c + 2], d.l[4 * c + 3]);
+  }
+}
+
 __device__ __forceinline__ void solve_manifold(const Lds& L, int m, float e) {
   ManPoints d;
   fetch_points(L, m, d);
   solve_manifold_pts(L, m, e, d);
 }
 
+// A colour of at most nthr / 2 manifolds is worked by lane pairs (pair p = tid / 2 takes
+// manifolds coloff[col] + p + (nthr / 2) k); a larger one by single lanes (tid + nthr k).
+__device__ __forceinline__ bool paired_colour(const Lds& L, int col, int nthr) {
+  return L.coloff[col + 1] - L.coloff[col] <= (nthr >> 1);
+}
+__device__ __forceinline__ int colour_first(const Lds& L, int col, int tid, int nthr) {
+  return L.coloff[col] + (paired_colour(L, col, nthr) ? (tid >> 1) : tid);
+}
+
 // `sweeps` PGS sweeps over the colours by the workgroup's `nthr` threads (thread `tid`).  A
-// thread visits the same manifolds in the same order on every sweep (colour by colour,
-// m = coloff[col] + tid + nthr k), so the points of its next manifold are fetched from device
-// memory while it solves the current one; one with a single manifold keeps it in registers.
-// Every thread passes the same sweeps x ncol barriers.
+// thread visits the same manifolds in the same order on every sweep, so the points of its
+// next manifold are fetched from device memory while it solves the current one; one with a
+// single manifold keeps it in registers.  Every thread passes the same sweeps x ncol barriers.
 __device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, int tid, int nthr, float e) {
   int first = 0;   // the thread's first colour with a manifold (ncol: none)
-  while (first < ncol && L.coloff[first] + tid >= L.coloff[first + 1]) ++first;
+  while (first < ncol && colour_first(L, first, tid, nthr) >= L.coloff[first + 1]) ++first;
   ManPoints cur, nxt;
-  if (first < ncol) fetch_points(L, L.coloff[first] + tid, cur);
+  if (first < ncol) fetch_points(L, colour_first(L, first, tid, nthr), cur);
+  const bool is_b = tid & 1;
   for (int it = 0; it < sweeps; ++it) {
     for (int col = 0; col < ncol; ++col) {
-      for (int m = L.coloff[col] + tid; m < L.coloff[col + 1]; m += nthr) {
-        int n2 = m + nthr, c2 = col;
+      const bool paired = paired_colour(L, col, nthr);
+      const int stride = paired ? (nthr >> 1) : nthr;
+      for (int m = colour_first(L, col, tid, nthr); m < L.coloff[col + 1]; m += stride) {
+        int n2 = m + stride, c2 = col;
         while (n2 >= L.coloff[c2 + 1]) {
-          if (++c2 == ncol) { c2 = first; n2 = L.coloff[first] + tid; break; }
-          n2 = L.coloff[c2] + tid;
+          if (++c2 == ncol) { c2 = first; n2 = colour_first(L, first, tid, nthr); break; }
+          n2 = colour_first(L, c2, tid, nthr);
         }
         const bool other = n2 != m;
         if (other) fetch_points(L, n2, nxt);
-        solve_manifold_pts(L, m, e, cur);
+        if (paired) solve_manifold_pair(L, m, e, cur, is_b);
+        else solve_manifold_pts(L, m, e, cur);
         if (other) cur = nxt;
       }
       __syncthreads();

@@ -575,7 +575,7 @@ int32_t launch_graph(jg_world* w, std::vector<jg::StepArgs>& cls, int n_steps) {
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-      destroy_graph(g);
+      (void)destroy_graph(g);   // the build error is the one reported
       return fail(JG_EDEVICE, std::string("building the step graph: ") + hipGetErrorString(e));
     }
     w->graphs.push_back(std::move(g));

@@ -181,15 +181,17 @@ def test_zero_network_is_previous_step_start_on_gpu(J):
 
 
 def test_zero_threshold_falls_back_to_plain(J, oracle):
-    """tau = 0 redoes every tower's solve plainly: the plain kernel's result (1e-6 relative) and
-    the oracle's within the plain tolerances; fallbacks and sweeps are counted."""
+    """tau = 0 redoes every tower's solve plainly: the plain kernel's result (3e-6 relative; the
+    two kernel instantiations fuse multiply-adds differently outside the solve, so two steps of a
+    falling tower drift apart by a few FP32 roundings) and the oracle's within the plain
+    tolerances; fallbacks and sweeps are counted."""
     sc = _scene(seed=9)
     net = _net(10)
     plain = J.World(sc)
     learned = J.World(sc, warm_start=2, mlp=net, mlp_iters=3, fallback_tau=0.0)
     plain.step(2)
     learned.step(2)
-    _close(plain.state(), learned.state(), "tau0")
+    _close(plain.state(), learned.state(), "tau0", tol=3e-6)
     st, sp = learned.stats(), plain.stats()
     assert st.fallbacks == 2 * sc["n_towers"]
     assert st.contact_iters == sp.contact_iters + 3 * sp.points
