@@ -1,0 +1,100 @@
+"""Trajectories of the removal batch against the oracle, judged by distributions.
+
+A pushed tower collapses chaotically, so FP32 and FP64 trajectories part after a while and
+single towers cannot be compared step by step.  What must agree is what the experiment
+measures over many towers: how many blocks each tower loses to its pushes (a pushed block is
+removed once it has moved its withdrawal distance), and how far the centre of mass of the
+remaining blocks moves in the horizontal plane."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_28394_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 480   # two push windows (steps 60 and 300 of each tower's schedule)
+
+
+@pytest.fixture(scope="module")
+def J():
+    from paper_2606_28394_amd import jenga
+    jenga.load_library()
+    return jenga
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _measures(sc, x, active, x0, active0):
+    ptr = np.asarray(sc["tower_ptr"])
+    removed, drift = [], []
+    for t in range(sc["n_towers"]):
+        a, b = int(ptr[t]), int(ptr[t + 1])
+        removed.append(int((active0[a:b] == 1).sum() - (active[a:b] == 1).sum()))
+        keep = active[a:b] == 1
+        drift.append(float(np.linalg.norm((x[a:b][keep].mean(0) - x0[a:b][keep].mean(0))[:2])))
+    return np.array(removed), np.array(drift)
+
+
+def test_removal_and_drift_distributions_match_oracle(J, oracle):
+    from scipy.stats import ks_2samp
+    sc = W.cfg2(0, n_per_mu=32, n_steps=STEPS)   # 96 towers, 12-24 levels, seeded pushes
+    x0 = np.asarray(sc["pos"], np.float64).reshape(-1, 3)
+    a0 = np.asarray(sc["active"]).astype(np.uint8)
+    _say(f"removal batch: {sc['n_towers']} towers, {STEPS} steps on the GPU")
+    gw = J.World(sc)
+    gw.step(STEPS)
+    g_rem, g_drift = _measures(sc, gw.state()[0], np.asarray(gw.active()), x0, a0)
+    assert gw.stats().error_word == 0
+    gw.close()
+    _say("the same on the oracle")
+    ow = oracle.OracleWorld(sc)
+    ow.step(STEPS, threads=min(16, os.cpu_count() or 1))
+    o_rem, o_drift = _measures(sc, ow.x, ow.active, x0, a0)
+    _say("removals per tower: gpu", np.bincount(g_rem, minlength=3), "oracle", np.bincount(o_rem, minlength=3))
+    _say("drift quartiles [m]: gpu", np.quantile(g_drift, [.25, .5, .75]), "oracle", np.quantile(o_drift, [.25, .5, .75]))
+    # removals are decided by the pushes within a few hundred steps: nearly every tower agrees
+    assert (g_rem == o_rem).mean() >= 0.9
+    assert abs(int(g_rem.sum()) - int(o_rem.sum())) <= 0.05 * max(1, int(o_rem.sum()))
+    # the drift is a chaotic outcome: the two samples must come from one distribution
+    assert ks_2samp(g_drift, o_drift).pvalue > 0.01
+    assert abs(np.median(g_drift) - np.median(o_drift)) <= 0.1 * np.median(o_drift)
+
+
+def test_collapse_distributions_match_oracle(J, oracle):
+    """Tilted towers of the throughput batch's recipe fall for one second (240 steps): the
+    horizontal travel and the drop of each tower's centre of mass, GPU against oracle."""
+    from scipy.stats import ks_2samp
+    steps = 240
+    sc = W.tilted_towers(3, 128, seed=31, n_steps=steps)
+    ptr = np.asarray(sc["tower_ptr"])
+    x0 = np.asarray(sc["pos"], np.float64).reshape(-1, 3)
+
+    def measures(x):
+        travel, drop = [], []
+        for t in range(sc["n_towers"]):
+            a, b = int(ptr[t]), int(ptr[t + 1])
+            d = x[a:b].mean(0) - x0[a:b].mean(0)
+            travel.append(float(np.linalg.norm(d[:2])))
+            drop.append(float(-d[2]))
+        return np.array(travel), np.array(drop)
+
+    _say(f"tilted towers: {sc['n_towers']} towers, {steps} steps on the GPU")
+    gw = J.World(sc)
+    gw.step(steps)
+    g = measures(gw.state()[0])
+    assert gw.stats().error_word == 0
+    gw.close()
+    _say("the same on the oracle")
+    ow = oracle.OracleWorld(sc)
+    ow.step(steps, threads=min(16, os.cpu_count() or 1))
+    o = measures(ow.x)
+    for name, gv, ov in (("travel", g[0], o[0]), ("drop", g[1], o[1])):
+        _say(f"{name} quartiles [m]: gpu", np.quantile(gv, [.25, .5, .75]), "oracle", np.quantile(ov, [.25, .5, .75]))
+        assert ks_2samp(gv, ov).pvalue > 0.01, name
+        assert abs(np.median(gv) - np.median(ov)) <= 0.1 * abs(np.median(ov)), name
