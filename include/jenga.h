@@ -71,8 +71,10 @@ typedef struct {
                             fallback_tau */
   int32_t device;        /* HIP device ordinal */
   void* stream;          /* hipStream_t for all GPU work; NULL = default stream */
-  int32_t pack_bodies;   /* bodies per on-chip pack (at most 256); 0 = automatic; -1 = every tower keeps its
-                            state in device memory (the path of islands over 256 bodies) */
+  int32_t pack_bodies;   /* bodies per on-chip pack (at most 256); 0 = automatic (one tower per pack when
+                            the batch has no more towers than the GPU holds workgroups at once, else the
+                            largest pack that keeps 8, or with features 4, workgroups per CU); -1 = every
+                            tower keeps its state in device memory (the path of islands over 256 bodies) */
   float manifolds_per_body;  /* manifold capacity per body in a pack; 0 = automatic (3.5) */
   int32_t mlp_iters;     /* PGS iterations after a learned warm start; default 8 */
   double fallback_tau;   /* tower residual [m/s] above which a learned solve is redone plainly

@@ -23,10 +23,10 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _one_step_compare(J, oracle, scene, states, warm_start=0, n_check_towers=None, label=""):
+def _one_step_compare(J, oracle, scene, states, warm_start=0, n_check_towers=None, label="", pack_bodies=0):
     """For each oracle state: put it on the GPU, step once on both sides, compare."""
     ow = oracle.OracleWorld(scene, warm_start=warm_start)
-    gw = J.World(scene, warm_start=warm_start)
+    gw = J.World(scene, warm_start=warm_start, pack_bodies=pack_bodies)
     ptr = scene["tower_ptr"]
     towers = range(scene["n_towers"]) if n_check_towers is None else range(min(n_check_towers, scene["n_towers"]))
     reports = []
@@ -101,10 +101,11 @@ def test_tilted_batch_one_step_parity(J, oracle):
 
 
 def test_small_towers_many_per_pack(J, oracle):
-    """Short towers (8-12 levels): several towers share one on-chip pack."""
+    """Short towers (8-12 levels): several towers share one on-chip pack (a small batch gets one
+    tower per pack by default, so the pack size is set)."""
     sc = W.tilted_towers(32, 40, levels_range=(8, 12))
     states = _trajectory_states(oracle, sc, [0, 80])
-    _one_step_compare(J, oracle, sc, states, label="small")
+    _one_step_compare(J, oracle, sc, states, label="small", pack_bodies=120)
 
 
 def test_warm_start_parity(J, oracle):
