@@ -4,8 +4,10 @@
 // depth live in a per-pack block of device memory, read on every PGS visit with
 // the next manifold's record in flight while the current one is solved (this
 // keeps LDS per body small, so more waves share a CU).  The step is bound by
-// the vector ALUs.  An island too large for LDS keeps its layout in device
-// memory, one island per workgroup of eight waves (see step_kernel).
+// the vector ALUs.  A colour with at most half as many manifolds as threads is
+// solved by lane pairs, one body per lane (see pgs_sweeps).  An island too large
+// for LDS keeps its layout in device memory, one island per workgroup of eight
+// waves (see step_kernel).
 //
 // Per step (Secs. "Rigid-Body Foundations", "Physics Engine --- Collision
 // Detection", "Contact Solver --- Projected Gauss-Seidel (PGS)"):
