@@ -1174,6 +1174,105 @@ __device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a,
   }
 }
 
+// Island broadphase (bodies in device memory, one tower per pack).
+// The candidates of the 64 bodies i = i0 + lane, each lane's in canonical order (j
+// ascending, the ground last): counted, and the first kCandPerBody written from out + off.  Windows are visited
+// in order; a window near none of the 64 is skipped, and a near one is loaded into
+// registers (lane l: body 64 w + l) and broadcast body by body with readlane, so the
+// tests of one lane wait on no memory.
+__device__ __forceinline__ int island_walk(const Lds& L, float margin, int nb, int nwin, int i0, int lane, uint32_t* out,
+                                           int off) {
+  const int NB = L.nbp;
+  const float slack = margin * 1.01f + 1e-6f;   // a filter: wider than the pair test
+  constexpr int lim = kCandPerBody;
+  const int i = i0 + lane;
+  const uint32_t fi = i < nb ? L.flag[i] : 0u;
+  const bool act = (fi & kActive) != 0;
+  const bool dyni = (fi & kDynamic) != 0;
+  float xi[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { xi[k] = L.x[k * NB + i]; hi[k] = L.hm[k * NB + i]; }
+  }
+  int c = 0;
+  const int w0 = i0 / kWave;
+  for (int wb0 = w0 - w0 % kWave; wb0 < nwin; wb0 += kWave) {
+    // lane l holds the box of window wb0 + l
+    float blo[3], bhi[3];
+    const bool inw = wb0 + lane < nwin;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      blo[k] = inw ? L.wbox[6 * (wb0 + lane) + k] : 0.f;
+      bhi[k] = inw ? L.wbox[6 * (wb0 + lane) + 3 + k] : 0.f;
+    }
+    for (int w = max(w0, wb0); w < min(nwin, wb0 + kWave); ++w) {
+      // broadcasts first, then branch-free tests (& rather than &&: no masked regions)
+      float lo[3], hb[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(blo[k]), w - wb0));
+        hb[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bhi[k]), w - wb0));
+      }
+      bool near = act;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        near = ((int)near & (int)(xi[k] - hi[k] <= hb[k] + slack) & (int)(xi[k] + hi[k] + slack >= lo[k])) != 0;
+      if (!__any(near)) continue;
+      const int jl = w * kWave + lane;
+      const bool inj = jl < nb;
+      float xj[3], hj[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        xj[k] = inj ? L.x[k * NB + jl] : 0.f;
+        hj[k] = inj ? L.hm[k * NB + jl] : 0.f;
+      }
+      const uint32_t fj = inj ? L.flag[jl] : 0u;
+      const int jn = min(kWave, nb - w * kWave);
+      for (int jj = 0; jj < jn; ++jj) {
+        const int j = w * kWave + jj;
+        const uint32_t f = __builtin_amdgcn_readlane(fj, jj);
+        float d[3], h[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          d[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xj[k]), jj));
+          h[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hj[k]), jj));
+        }
+        const int hitm = (int)near & (int)(j > i) & (int)((f & kActive) != 0) &
+                         ((int)dyni | (int)((f & kDynamic) != 0)) &
+                         (int)(fabsf(xi[0] - d[0]) <= hi[0] + h[0] + margin) &
+                         (int)(fabsf(xi[1] - d[1]) <= hi[1] + h[1] + margin) &
+                         (int)(fabsf(xi[2] - d[2]) <= hi[2] + h[2] + margin);
+        const bool hit = hitm != 0;
+        if (hit) {
+          if (c < lim) out[off + c] = ((uint32_t)i << 16) | (uint32_t)j;
+          ++c;
+        }
+      }
+    }
+  }
+  if (act && dyni && (xi[2] - hi[2] <= margin)) {
+    if (c < lim) out[off + c] = ((uint32_t)i << 16) | kGround;
+    ++c;
+  }
+  return c;
+}
+
+// Walk rounds i0 = 64 (first + k stride) of the island broadphase: each body's candidates into its
+// own kCandPerBody slots and their count (capped) into the colouring lane masks, which are
+// unused until the colouring.  A wave may be one of several sharing the rounds (first, stride in
+// waves): the bodies, slots and counts of distinct rounds are distinct.
+__device__ __forceinline__ void island_walk_rounds(const Lds& L, float margin, int nb, int first, int stride, int lane) {
+  const int nwin = (nb + kWave - 1) / kWave;
+  bool over = false;
+  for (int i0 = first * kWave; i0 < nb; i0 += stride * kWave) {
+    const int i = i0 + lane;
+    const int c = island_walk(L, margin, nb, nwin, i0, lane, L.cslot, i * kCandPerBody);
+    over = over || c > kCandPerBody;
+    if (i < nb) L.lmlo[i] = (uint32_t)min(c, kCandPerBody);
+  }
+  if (__any(over) && lane == 0) atomicOr((uint32_t*)&L.scal[3], kErrCand);
+}
+
 // wave-uniform phase timer: adds the cycles since the previous mark to counter k
 struct PhaseTimer {
   unsigned long long last;
@@ -1244,11 +1343,16 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   if constexpr (kThreads > kWave) {
     if (threadIdx.x >= kWave) {
-      // helper waves: per substep they join the first wave in building the manifolds and in
-      // the sweeps, each between a barrier where it enters and one where it leaves (the same
-      // barriers, in the same order, as the first wave's)
+      // helper waves: per substep they join the first wave in the broadphase walk, in building
+      // the manifolds and in the sweeps, each between a barrier where it enters and one where it
+      // leaves (the same barriers, in the same order, as the first wave's)
+      const int pkh = a.pack_first + blockIdx.x;
+      const int nbh = a.pack_body0[pkh + 1] - a.pack_body0[pkh];
       for (int s = 0; s < a.n_steps; ++s)
         for (int sub = 0; sub < a.n_sub; ++sub) {
+          __syncthreads();
+          island_walk_rounds(L, a.margin, nbh, threadIdx.x / kWave, kThreads / kWave, threadIdx.x % kWave);
+          __syncthreads();
           __syncthreads();
           build_manifolds(L, a, threadIdx.x, kThreads, L.scal[5], keep_prev);
           __syncthreads();
@@ -1404,9 +1508,9 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       if constexpr (kGlobal) {
         // islands in device memory (one tower each).  Bounding boxes of 64-body windows filter
         // the pair tests; each lane then walks its own body's candidates j > i in ascending
-        // order, the ground last.  A first walk counts them, a scan gives each body its place
-        // in the canonical list, a second walk writes them there, and the SAT runs on that
-        // list 64 at a time, so the candidates keep their canonical order.
+        // order, the ground last, into that body's own slots.  A scan of the counts gives each
+        // body its place in the canonical list, the runs are copied there, and the SAT runs on
+        // that list 64 at a time, so the candidates keep their canonical order.
         const int nwin = (nb + kWave - 1) / kWave;
         for (int w = lane; w < nwin; w += kWave) {
           float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
@@ -1422,99 +1526,19 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
           for (int k = 0; k < 3; ++k) { L.wbox[6 * w + k] = lo[k]; L.wbox[6 * w + 3 + k] = hi[k]; }
         }
         wave_sync();
-        const float slack = a.margin * 1.01f + 1e-6f;   // a filter: wider than the pair test
-        // The candidates of the 64 bodies i = i0 + lane, each lane's in canonical order (j
-        // ascending, the ground last): counted, and the first kCandPerBody written from out + off.  Windows are visited
-        // in order; a window near none of the 64 is skipped, and a near one is loaded into
-        // registers (lane l: body 64 w + l) and broadcast body by body with readlane, so the
-        // tests of one lane wait on no memory.
-        auto walk = [&](int i0, uint32_t* out, int off) -> int {
-          constexpr int lim = kCandPerBody;
-          const int i = i0 + lane;
-          const uint32_t fi = i < nb ? L.flag[i] : 0u;
-          const bool act = (fi & kActive) != 0;
-          const bool dyni = (fi & kDynamic) != 0;
-          float xi[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
-          if (act) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) { xi[k] = L.x[k * NB + i]; hi[k] = L.hm[k * NB + i]; }
-          }
-          int c = 0;
-          const int w0 = i0 / kWave;
-          for (int wb0 = w0 - w0 % kWave; wb0 < nwin; wb0 += kWave) {
-            // lane l holds the box of window wb0 + l
-            float blo[3], bhi[3];
-            const bool inw = wb0 + lane < nwin;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              blo[k] = inw ? L.wbox[6 * (wb0 + lane) + k] : 0.f;
-              bhi[k] = inw ? L.wbox[6 * (wb0 + lane) + 3 + k] : 0.f;
-            }
-            for (int w = max(w0, wb0); w < min(nwin, wb0 + kWave); ++w) {
-              // broadcasts first, then branch-free tests (& rather than &&: no masked regions)
-              float lo[3], hb[3];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                lo[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(blo[k]), w - wb0));
-                hb[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bhi[k]), w - wb0));
-              }
-              bool near = act;
-#pragma unroll
-              for (int k = 0; k < 3; ++k)
-                near = ((int)near & (int)(xi[k] - hi[k] <= hb[k] + slack) & (int)(xi[k] + hi[k] + slack >= lo[k])) != 0;
-              if (!__any(near)) continue;
-              const int jl = w * kWave + lane;
-              const bool inj = jl < nb;
-              float xj[3], hj[3];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                xj[k] = inj ? L.x[k * NB + jl] : 0.f;
-                hj[k] = inj ? L.hm[k * NB + jl] : 0.f;
-              }
-              const uint32_t fj = inj ? L.flag[jl] : 0u;
-              const int jn = min(kWave, nb - w * kWave);
-              for (int jj = 0; jj < jn; ++jj) {
-                const int j = w * kWave + jj;
-                const uint32_t f = __builtin_amdgcn_readlane(fj, jj);
-                float d[3], h[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                  d[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xj[k]), jj));
-                  h[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hj[k]), jj));
-                }
-                const int hitm = (int)near & (int)(j > i) & (int)((f & kActive) != 0) &
-                                 ((int)dyni | (int)((f & kDynamic) != 0)) &
-                                 (int)(fabsf(xi[0] - d[0]) <= hi[0] + h[0] + a.margin) &
-                                 (int)(fabsf(xi[1] - d[1]) <= hi[1] + h[1] + a.margin) &
-                                 (int)(fabsf(xi[2] - d[2]) <= hi[2] + h[2] + a.margin);
-                const bool hit = hitm != 0;
-                if (hit) {
-                  if (c < lim) out[off + c] = ((uint32_t)i << 16) | (uint32_t)j;
-                  ++c;
-                }
-              }
-            }
-          }
-          if (act && dyni && (xi[2] - hi[2] <= a.margin)) {
-            if (c < lim) out[off + c] = ((uint32_t)i << 16) | kGround;
-            ++c;
-          }
-          return c;
-        };
         // one walk: each body's candidates into its own kCandPerBody slots, counts into the (still
         // unused) colouring lane masks; an exclusive scan of the counts places each body's run in
         // the canonical list, and the runs are copied there.  A body with more candidates than
-        // its slots keeps the first kCandPerBody (flagged).
+        // its slots keeps the first kCandPerBody (flagged).  The helper waves share the walk.
         uint32_t* const cnt = L.lmlo;
-        bool over = false;
-        for (int i0 = 0; i0 < nb; i0 += kWave) {
-          const int i = i0 + lane;
-          const int c = walk(i0, L.cslot, i * kCandPerBody);
-          over = over || c > kCandPerBody;
-          if (i < nb) cnt[i] = (uint32_t)min(c, kCandPerBody);
+        if constexpr (kThreads > kWave) {
+          __syncthreads();   // window boxes, frames and flags are in place; the helpers enter
+          island_walk_rounds(L, a.margin, nb, 0, kThreads / kWave, lane);
+          __syncthreads();   // every body's candidates are in its slots
+        } else {
+          island_walk_rounds(L, a.margin, nb, 0, 1, lane);
+          wave_sync();
         }
-        if (__any(over) && lane == 0) L.scal[3] |= kErrCand;
-        wave_sync();
         uint32_t run = 0;
         for (int i0 = 0; i0 < nb; i0 += kWave) {
           const int i = i0 + lane;
