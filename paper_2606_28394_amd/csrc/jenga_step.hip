@@ -1707,22 +1707,57 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
         if (dj) { lmlo[j] = 0u; lmhi[j] = 0u; }
         bool done = !valid;
         int col = -1;
-        while (true) {
-          const uint64_t donem = __ballot(done);
-          if (donem == ~0ull) break;
-          if (!done && (dep & ~donem) == 0ull) {
-            uint64_t u = 0ull;
-            if (di) u |= (uint64_t)mask[i] | ((uint64_t)mask[NB + i] << 32);
-            if (dj) u |= (uint64_t)mask[j] | ((uint64_t)mask[NB + j] << 32);
-            if (u != ~0ull) {
-              col = __ffsll((unsigned long long)~u) - 1;
-              const uint64_t bit = 1ull << col;
-              if (di) { mask[i] |= (uint32_t)bit; mask[NB + i] |= (uint32_t)(bit >> 32); }
-              if (dj) { mask[j] |= (uint32_t)bit; mask[NB + j] |= (uint32_t)(bit >> 32); }
+        if constexpr (kGlobal) {
+          // An island's chunks take many rounds (its canonical order runs along chains of
+          // touching stones), so the rounds stay in registers: the colours a lane may not take
+          // are those its bodies got in earlier chunks (read once) and those of the earlier lanes
+          // of this chunk it depends on, folded in (by broadcast) in the round after each is
+          // coloured; the chunk's colours go into the body masks at its end.
+          uint64_t u = 0ull;
+          if (di) u |= (uint64_t)mask[i] | ((uint64_t)mask[NB + i] << 32);
+          if (dj) u |= (uint64_t)mask[j] | ((uint64_t)mask[NB + j] << 32);
+          uint64_t fresh = 0ull;   // lanes coloured in the previous round (wave-uniform)
+          while (true) {
+            for (uint64_t f = fresh; f != 0ull; f &= f - 1ull) {
+              const int k = __ffsll((unsigned long long)f) - 1;
+              const int ck = __builtin_amdgcn_readlane(col, k);
+              if (ck >= 0 && ((dep >> k) & 1ull)) u |= 1ull << ck;
             }
-            done = true;
+            const uint64_t donem = __ballot(done);
+            if (donem == ~0ull) break;
+            const bool ready = !done && (dep & ~donem) == 0ull;
+            if (ready) {
+              if (u != ~0ull) col = __ffsll((unsigned long long)~u) - 1;
+              done = true;
+            }
+            fresh = __ballot(ready);
           }
-          wave_sync();
+          // lanes that share a body set different bits
+          if (valid && col >= 0) {
+            const uint64_t bit = 1ull << col;
+            if (di) { atomicOr(&mask[i], (uint32_t)bit); atomicOr(&mask[NB + i], (uint32_t)(bit >> 32)); }
+            if (dj) { atomicOr(&mask[j], (uint32_t)bit); atomicOr(&mask[NB + j], (uint32_t)(bit >> 32)); }
+          }
+          wave_sync();   // the masks are complete before the next chunk reads them
+        } else {
+          // a pack's chunks take few rounds, each colouring many lanes: the masks stay in LDS
+          while (true) {
+            const uint64_t donem = __ballot(done);
+            if (donem == ~0ull) break;
+            if (!done && (dep & ~donem) == 0ull) {
+              uint64_t u = 0ull;
+              if (di) u |= (uint64_t)mask[i] | ((uint64_t)mask[NB + i] << 32);
+              if (dj) u |= (uint64_t)mask[j] | ((uint64_t)mask[NB + j] << 32);
+              if (u != ~0ull) {
+                col = __ffsll((unsigned long long)~u) - 1;
+                const uint64_t bit = 1ull << col;
+                if (di) { mask[i] |= (uint32_t)bit; mask[NB + i] |= (uint32_t)(bit >> 32); }
+                if (dj) { mask[j] |= (uint32_t)bit; mask[NB + j] |= (uint32_t)(bit >> 32); }
+              }
+              done = true;
+            }
+            wave_sync();
+          }
         }
         if (valid) {
           L.cpos[p] = col;
