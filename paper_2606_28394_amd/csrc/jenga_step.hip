@@ -1017,9 +1017,11 @@ __device__ __forceinline__ void record_solution(const Lds& L, int m, float* rec)
 // canonical pair in psum / pmax (which may alias cab / cpos: each entry is read before it is
 // written), then each tower's contiguous canonical range.  With `only`, towers whose flag is
 // clear keep their residual.
-__device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, int lane, float* psum, float* pmax,
-                                const uint32_t* only) {
-  for (int p = lane; p < nman; p += kWave) {
+// Each canonical pair's residual terms (pairs first, first + stride, ...); psum and pmax may
+// alias the canonical lists (a pair's entry is read before it is overwritten, by one thread).
+__device__ __forceinline__ void residual_parts(const Lds& L, int nman, int first, int stride, float* psum, float* pmax,
+                                               const uint32_t* only) {
+  for (int p = first; p < nman; p += stride) {
     const int m = L.cpos[p];
     float sum = 0.f, mx = 0.f;
     if (m >= 0) {
@@ -1029,7 +1031,16 @@ __device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, 
     psum[p] = sum;
     pmax[p] = mx;
   }
-  wave_sync();
+}
+
+// The towers' residuals from the pairs' terms (fixed summation order); `parts` false when the
+// terms are already in psum and pmax.
+__device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, int lane, float* psum, float* pmax,
+                                const uint32_t* only, bool parts = true) {
+  if (parts) {
+    residual_parts(L, nman, lane, kWave, psum, pmax, only);
+    wave_sync();
+  }
   if (nt == 1) {
     // one tower (an island): the whole wave reduces its range
     if (!only || only[0]) {
@@ -1344,8 +1355,8 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   if constexpr (kThreads > kWave) {
     if (threadIdx.x >= kWave) {
       // helper waves: per substep they join the first wave in the broadphase walk, in building
-      // the manifolds and in the sweeps, each between a barrier where it enters and one where it
-      // leaves (the same barriers, in the same order, as the first wave's)
+      // the manifolds, in the sweeps and in the residual terms, each between a barrier where it
+      // enters and one where it leaves (the same barriers, in the same order, as the first wave's)
       const int pkh = a.pack_first + blockIdx.x;
       const int nbh = a.pack_body0[pkh + 1] - a.pack_body0[pkh];
       for (int s = 0; s < a.n_steps; ++s)
@@ -1358,6 +1369,10 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
           __syncthreads();
           __syncthreads();
           pgs_sweeps(L, a.iters, L.scal[2], threadIdx.x, kThreads, a.restitution);
+          __syncthreads();
+          __syncthreads();
+          residual_parts(L, L.scal[5], threadIdx.x, kThreads, reinterpret_cast<float*>(L.cab),
+                         reinterpret_cast<float*>(L.cpos), nullptr);
           __syncthreads();
         }
       return;
@@ -2009,8 +2024,17 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
 
       // ---- 8. residual (the learned variant took it before the outputs) ----
       if (!learned) {
-        tower_residuals(L, nman, nt, lane, reinterpret_cast<float*>(L.cab), reinterpret_cast<float*>(L.cpos),
-                        nullptr);
+        float* const psum = reinterpret_cast<float*>(L.cab);
+        float* const pmax = reinterpret_cast<float*>(L.cpos);
+        if constexpr (kThreads > kWave) {
+          // an island's helper waves join in the pairs' terms
+          __syncthreads();
+          residual_parts(L, nman, threadIdx.x, kThreads, psum, pmax, nullptr);
+          __syncthreads();
+          tower_residuals(L, nman, nt, lane, psum, pmax, nullptr, false);
+        } else {
+          tower_residuals(L, nman, nt, lane, psum, pmax, nullptr);
+        }
         timer.mark(L, lane, 7);
       }
 
