@@ -159,15 +159,18 @@ def _run_timed(J, torch, scene, steps, **kw):
     return scene["n_towers"] * steps / (ms * 1e-3), ms, st
 
 
-def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(4, 8, 12)):
+def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(4, 8, 12), scene=None, workload=None):
     """The learned warm start against plain PGS at 20 iterations at equal residual, on the
-    450-tower removal batch: R20 = median tower residual of plain-20; each k runs with the
-    fallback threshold tau = R20; the smallest k whose median residual is <= R20 is the
-    equal-residual point.  Rates include inference, residual passes and fallbacks."""
+    450-tower removal batch (or `scene`): R20 = median tower residual of plain-20; each k runs
+    with the fallback threshold tau = R20; the smallest k whose median residual is <= R20 is
+    the equal-residual point.  Rates include inference, residual passes and fallbacks."""
     import numpy as np
     from paper_2606_28394_amd import workloads as W
     net = np.load(weights)
-    scene = W.cfg2(0, n_steps=steps)
+    if scene is None:
+        scene = W.cfg2(0, n_steps=steps)
+        workload = (f"removal batch: {scene['n_towers']} towers, 12-24 levels, 1-8 push removals each, "
+                    f"{steps} steps")
     r20, m20, st20 = _run_residuals(J, scene, steps, chunk)
     v20, ms20, _ = _run_timed(J, torch, scene, steps)
     log(f"plain-20: median residual {r20:.3e} m/s, {v20:.4g} tower-steps/s")
@@ -196,8 +199,7 @@ def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(4, 8, 12)):
     best = min(ok, key=lambda r: r["k"]) if ok else None
     okp = [r for r in prev_rows if r["median_residual"] <= r20]
     bestp = min(okp, key=lambda r: r["k"]) if okp else None
-    return dict(workload=f"removal batch: {scene['n_towers']} towers, 12-24 levels, 1-8 push removals each, "
-                         f"{steps} steps",
+    return dict(workload=workload,
                 plain20=dict(median_residual=r20, mean_residual=m20, value=v20, kernel_ms=ms20),
                 learned=rows, median_residual_other_starts=ctx, previous_step=prev_rows,
                 equal_residual_k=best["k"] if best else None,
@@ -418,6 +420,11 @@ def main():
     if not args.no_learned and os.path.exists(args.learned_weights):
         log("equal-residual leg (learned warm start vs plain-20) ...")
         out["equal_residual"] = equal_residual(J, torch, args.learned_weights)
+        if args.island_steps > 0:
+            log("equal-residual leg on the 64 x 64 masonry wall ...")
+            out["equal_residual_wall"] = equal_residual(
+                J, torch, args.learned_weights, steps=300, ks=(4, 8), scene=W.cfg5(0, n_steps=300),
+                workload="one masonry wall, 64 courses x 64 stones (4096 bodies), steps 1-300")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_towers, args.cpu_steps)
