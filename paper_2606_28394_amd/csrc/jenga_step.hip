@@ -1333,10 +1333,12 @@ __device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, i
 // variant does not carry the network's registers.
 // kGlobal: the pack's layout lives in its region of device memory instead of LDS.  The two are
 // separate instantiations so that the LDS variant's accesses compile to LDS instructions.
-// The plain device-memory variant runs kIslandWaves waves: the first runs every phase, and the
-// others join it for the PGS sweeps only (an island's colours hold hundreds of manifolds).
+// A device-memory variant runs several waves: the first runs every phase, and the others join
+// it where an island's work is wide (the broadphase walk, the manifolds, the sweeps, the residual
+// terms).  The plain variant runs kIslandWaves waves; the one with the network's registers (one
+// wave per SIMD) runs four, one per SIMD of the compute unit.
 template <bool kLearned, bool kGlobal>
-constexpr int step_threads() { return (kGlobal && !kLearned) ? kIslandWaves * kWave : kWave; }
+constexpr int step_threads() { return kGlobal ? (kLearned ? 4 : kIslandWaves) * kWave : kWave; }
 
 // The plain variants are held to two waves per SIMD (at most 256 registers): occupancy is what
 // hides the latency of the pack's serial phases, and a register count that drifts above 256
@@ -1357,8 +1359,11 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       // helper waves: per substep they join the first wave in the broadphase walk, in building
       // the manifolds, in the sweeps and in the residual terms, each between a barrier where it
       // enters and one where it leaves (the same barriers, in the same order, as the first wave's)
+      // (with the learned warm start, the sweeps after it are mlp_iters, and its own residual
+      // and fallback stay with the first wave)
       const int pkh = a.pack_first + blockIdx.x;
       const int nbh = a.pack_body0[pkh + 1] - a.pack_body0[pkh];
+      const bool learned_h = kLearned && a.warm_start == 2;
       for (int s = 0; s < a.n_steps; ++s)
         for (int sub = 0; sub < a.n_sub; ++sub) {
           __syncthreads();
@@ -1368,12 +1373,14 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
           build_manifolds(L, a, threadIdx.x, kThreads, L.scal[5], keep_prev);
           __syncthreads();
           __syncthreads();
-          pgs_sweeps(L, a.iters, L.scal[2], threadIdx.x, kThreads, a.restitution);
+          pgs_sweeps(L, learned_h ? a.mlp_iters : a.iters, L.scal[2], threadIdx.x, kThreads, a.restitution);
           __syncthreads();
-          __syncthreads();
-          residual_parts(L, L.scal[5], threadIdx.x, kThreads, reinterpret_cast<float*>(L.cab),
-                         reinterpret_cast<float*>(L.cpos), nullptr);
-          __syncthreads();
+          if (!learned_h) {
+            __syncthreads();
+            residual_parts(L, L.scal[5], threadIdx.x, kThreads, reinterpret_cast<float*>(L.cab),
+                           reinterpret_cast<float*>(L.cpos), nullptr);
+            __syncthreads();
+          }
         }
       return;
     }
@@ -2211,7 +2218,7 @@ int step_launch_config(const StepArgs& a, const void** func, unsigned* block_thr
       f = learned ? (const void*)step_kernel<true, true, true> : (const void*)step_kernel<false, true, true>;
     else
       f = learned ? (const void*)step_kernel<true, true, false> : (const void*)step_kernel<false, true, false>;
-    if (!learned) threads = step_threads<false, true>();
+    threads = learned ? step_threads<true, true>() : step_threads<false, true>();
   } else {
     f = learned ? (const void*)step_kernel<true, false, false> : (const void*)step_kernel<false, false, false>;
   }
