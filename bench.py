@@ -287,7 +287,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-tower latency and standing-tower legs")
     ap.add_argument("--island-steps", type=int, default=100,
-                    help="steps of the large-island leg (one 64 x 64 masonry wall); 0 skips it")
+                    help="steps of the large-island leg (one 64 x 64 masonry wall); 0 skips it and the "
+                         "wall's equal-residual leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's pack size instead of timing candidates on the batch first")
     ap.add_argument("--tune-steps", type=int, default=40,
