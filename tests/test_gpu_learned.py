@@ -246,3 +246,23 @@ def test_learned_and_records_in_device_memory_match_lds(J):
                 np.testing.assert_allclose(fa, fb, rtol=1e-4, atol=1e-6)
         lds.close()
         dev.close()
+
+
+def test_island_fallback_with_helper_waves(J):
+    """Towers kept in device memory run the learned variant on four waves (the helpers share
+    the walk, manifolds and sweeps; the network and the fallback stay on the first wave).  With
+    tau = 0 every tower falls back, so three steps must give the plain island kernel's result
+    (3e-6 relative, as for on-chip packs), with the fallbacks counted."""
+    sc = _scene(seed=12)
+    net = _net(13)
+    plain = J.World(sc, pack_bodies=-1)
+    learned = J.World(sc, pack_bodies=-1, warm_start=2, mlp=net, mlp_iters=3, fallback_tau=0.0)
+    for w in (plain, learned):
+        w.step(1)
+        w.step(2)
+    _close(plain.state(), learned.state(), "island tau0", tol=3e-6)
+    st = learned.stats()
+    assert st.error_word == 0 and plain.stats().error_word == 0
+    assert st.fallbacks == 3 * sc["n_towers"]
+    plain.close()
+    learned.close()
