@@ -105,6 +105,7 @@ constexpr int kManDevWords = 28;   // r_A 12, lambda 12, n 3, depth per sorted m
                                    // pack's device region
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
 constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
+constexpr int kLearnedIslandWaves = 4;          // waves of a pack in device memory with the network
                                                 // and the chunk's previous dimensionless impulses
 constexpr int kFeatRecord = 30;
 

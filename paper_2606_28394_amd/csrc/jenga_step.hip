@@ -123,6 +123,8 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool u
   const int mode = lds_mode(a);
   L.cyc = (unsigned long long*)take(2 * kPhases);   // first: 8-byte aligned
   L.xs = mode == 2 ? (uint32_t*)take(kStageWords) : nullptr;   // 16-byte aligned (80-byte offset)
+  // an island's other waves stage their network rows right after the first wave's
+  if (use_hot && mode == 2) take((kLearnedIslandWaves - 1) * kStageWords);
   L.x = take(3 * nb); L.q = take(4 * nb); L.v = take(3 * nb); L.w = take(3 * nb);
   L.he = take(3 * nb); L.invm = take(nb); L.invI = take(3 * nb);
   L.flag = (uint32_t*)take(nb); L.tw = (int32_t*)take(nb);
@@ -1284,6 +1286,49 @@ __device__ __forceinline__ void island_walk_rounds(const Lds& L, float margin, i
   if (__any(over) && lane == 0) atomicOr((uint32_t*)&L.scal[3], kErrCand);
 }
 
+// The learned warm start's network inputs, initial impulses and feature records for chunks of 16
+// manifolds x 4 point slots (lane = 4 (m - m0) + j), chunks first, first + stride, ... of the
+// colour-sorted list; xs is the calling wave's staging rows (unused for records alone).
+__device__ __forceinline__ void learned_chunks(const Lds& L, const StepArgs& a, int nkept, int slot0, float gdt,
+                                               bool learned, bool rec, int first, int stride, int lane,
+                                               uint32_t* xs) {
+  const uint4* net = (const uint4*)a.mlp;
+  for (int m0 = first * (kWave / 4); m0 < nkept; m0 += stride * (kWave / 4)) {
+    const int m = m0 + (lane >> 2), j = lane & 3;
+    const bool valid = m < nkept && j < (int)(L.mmeta[m] & 15u);
+    float f[mlp::kFeat];
+    if (valid) point_features(L, m, j, gdt, f);
+    else
+#pragma unroll
+      for (int k = 0; k < mlp::kFeat; ++k) f[k] = 0.f;
+    if (rec && valid) {
+      float* o = a.feat_out + ((size_t)(slot0 + m) * 4 + j) * kFeatRecord;
+#pragma unroll
+      for (int k = 0; k < mlp::kFeat; ++k) o[k] = f[k];
+    }
+    if (learned) {
+      // the network predicts the change from the previous dimensionless impulses
+      float* prevd = reinterpret_cast<float*>(xs + kWave * mlp::kRowWords);
+      mlp::stage_row(net, f, xs + lane * mlp::kRowWords);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) prevd[3 * lane + k] = f[12 + k];
+      wave_sync();
+      mlp::f32x4 y[4];
+      mlp::infer_chunk(net, xs, lane, y);
+      if (lane < 16) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = 16 * t + lane, mm = m0 + (row >> 2), jj = row & 3;
+          if (mm < nkept && jj < (int)(L.mmeta[mm] & 15u))
+#pragma unroll
+            for (int k = 0; k < 3; ++k) mdev(L, mm)[12 + jj * 3 + k] = y[t][k] + prevd[3 * row + k];
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
 // wave-uniform phase timer: adds the cycles since the previous mark to counter k
 struct PhaseTimer {
   unsigned long long last;
@@ -1338,7 +1383,7 @@ __device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, i
 // terms).  The plain variant runs kIslandWaves waves; the one with the network's registers (one
 // wave per SIMD) runs four, one per SIMD of the compute unit.
 template <bool kLearned, bool kGlobal>
-constexpr int step_threads() { return kGlobal ? (kLearned ? 4 : kIslandWaves) * kWave : kWave; }
+constexpr int step_threads() { return kGlobal ? (kLearned ? kLearnedIslandWaves : kIslandWaves) * kWave : kWave; }
 
 // The plain variants are held to two waves per SIMD (at most 256 registers): occupancy is what
 // hides the latency of the pack's serial phases, and a register count that drifts above 256
@@ -1359,11 +1404,13 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       // helper waves: per substep they join the first wave in the broadphase walk, in building
       // the manifolds, in the sweeps and in the residual terms, each between a barrier where it
       // enters and one where it leaves (the same barriers, in the same order, as the first wave's)
-      // (with the learned warm start, the sweeps after it are mlp_iters, and its own residual
-      // and fallback stay with the first wave)
+      // (with the learned warm start they share the network's chunks too; the sweeps after it
+      // are mlp_iters, and its own residual and fallback stay with the first wave)
       const int pkh = a.pack_first + blockIdx.x;
       const int nbh = a.pack_body0[pkh + 1] - a.pack_body0[pkh];
       const bool learned_h = kLearned && a.warm_start == 2;
+      const int slot0h = a.pack_slot0[pkh];
+      const float gdt_h = sqrtf(a.g[0] * a.g[0] + a.g[1] * a.g[1] + a.g[2] * a.g[2]) * a.dt;
       for (int s = 0; s < a.n_steps; ++s)
         for (int sub = 0; sub < a.n_sub; ++sub) {
           __syncthreads();
@@ -1372,6 +1419,16 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
           __syncthreads();
           build_manifolds(L, a, threadIdx.x, kThreads, L.scal[5], keep_prev);
           __syncthreads();
+          if constexpr (kLearned) {
+            const bool rec_h = a.feat_out != nullptr && s == a.n_steps - 1 && sub == a.n_sub - 1;
+            if (learned_h || rec_h) {
+              const int wv = threadIdx.x / kWave;
+              __syncthreads();
+              learned_chunks(L, a, L.coloff[L.scal[2]], slot0h, gdt_h, learned_h, rec_h, wv, kThreads / kWave,
+                             threadIdx.x % kWave, L.xs ? L.xs + wv * kStageWords : nullptr);
+              __syncthreads();
+            }
+          }
           __syncthreads();
           pgs_sweeps(L, learned_h ? a.mlp_iters : a.iters, L.scal[2], threadIdx.x, kThreads, a.restitution);
           __syncthreads();
@@ -1858,42 +1915,14 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
               L.vsave[(3 + k) * NB + i] = L.w[k * NB + i];
             }
         if (learned || rec) {
-          const uint4* net = (const uint4*)a.mlp;
           const float gdt = sqrtf(a.g[0] * a.g[0] + a.g[1] * a.g[1] + a.g[2] * a.g[2]) * dt;
-          // 16 manifolds x 4 point slots per pass: lane = 4 (m - m0) + j
-          for (int m0 = 0; m0 < nkept; m0 += kWave / 4) {
-            const int m = m0 + (lane >> 2), j = lane & 3;
-            const bool valid = m < nkept && j < (int)(L.mmeta[m] & 15u);
-            float f[mlp::kFeat];
-            if (valid) point_features(L, m, j, gdt, f);
-            else
-#pragma unroll
-              for (int k = 0; k < mlp::kFeat; ++k) f[k] = 0.f;
-            if (rec && valid) {
-              float* o = a.feat_out + ((size_t)(slot0 + m) * 4 + j) * kFeatRecord;
-#pragma unroll
-              for (int k = 0; k < mlp::kFeat; ++k) o[k] = f[k];
-            }
-            if (learned) {
-              // the network predicts the change from the previous dimensionless impulses
-              float* prevd = reinterpret_cast<float*>(L.xs + kWave * mlp::kRowWords);
-              mlp::stage_row(net, f, L.xs + lane * mlp::kRowWords);
-#pragma unroll
-              for (int k = 0; k < 3; ++k) prevd[3 * lane + k] = f[12 + k];
-              wave_sync();
-              mlp::f32x4 y[4];
-              mlp::infer_chunk(net, L.xs, lane, y);
-              if (lane < 16) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                  const int row = 16 * t + lane, mm = m0 + (row >> 2), jj = row & 3;
-                  if (mm < nkept && jj < (int)(L.mmeta[mm] & 15u))
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) mdev(L, mm)[12 + jj * 3 + k] = y[t][k] + prevd[3 * row + k];
-                }
-              }
-              wave_sync();
-            }
+          if constexpr (kThreads > kWave) {
+            // an island's helper waves take chunks too, each with its own staging rows
+            __syncthreads();
+            learned_chunks(L, a, nkept, slot0, gdt, learned, rec, 0, kThreads / kWave, lane, L.xs);
+            __syncthreads();
+          } else {
+            learned_chunks(L, a, nkept, slot0, gdt, learned, rec, 0, 1, lane, L.xs);
           }
           wave_sync();
         }
