@@ -7,6 +7,9 @@ Tolerances (one step, FP32 GPU against FP64 oracle):
   impulses     |dl| <= 1e-4 * max(|l|, m g dt / 4)  (m g dt / 4 = 1.72e-4 N s for the benchmark block;
                                                     m of the lighter body of the pair in general)
   points       |dp| <= 1e-5 * max(|p|, 0.075 m)
+  normals      |dn| <= 1e-5 for face and ground normals; <= 1e-3 for an edge-edge (cross) axis,
+               whose direction a_i x b_j / |a_i x b_j| amplifies FP32 rounding by 1 / |a_i x b_j|
+  depths       |dd| <= 1e-5 * max(|p|, 0.075 m)  (face and ground; 1e-3 * 0.075 m on cross axes)
 Contact-pair sets must agree exactly outside the oracle's precision bands;
 colours must agree exactly for towers without a banded pair.
 """
@@ -51,7 +54,8 @@ def compare_contacts(om: dict, gm: dict, masses=None, impulses: bool = True) -> 
     impulses=False skips the impulse comparison (statically indeterminate contact sets, where
     only the bodies' net impulses, fixed by the velocities, are unique)."""
     rep = dict(pairs=len(om), banded=0, missing=[], extra=[], colour_mismatch=[], slot_mismatch=[],
-               point_err=0.0, lam_err=0.0, normal_err=0.0, colours_checked=False)
+               point_err=0.0, lam_err=0.0, normal_err=0.0, normal_err_cross=0.0, depth_err=0.0,
+               depth_err_cross=0.0, colours_checked=False)
     banded = {k for k, m in om.items() if m["band"] & BAND_MASK}
     rep["banded"] = len(banded)
     okeys = set(om) - banded
@@ -66,7 +70,16 @@ def compare_contacts(om: dict, gm: dict, masses=None, impulses: bool = True) -> 
                 rep["colour_mismatch"].append(k)
     for k in okeys & gkeys:
         o, g = om[k], gm[k]
-        rep["normal_err"] = max(rep["normal_err"], float(np.abs(o["normal"] - g["normal"]).max()))
+        cross = o["axis"] >= 6        # an edge-edge axis (the ground has axis -1)
+        en = float(np.abs(o["normal"] - g["normal"]).max())
+        pscale = max(float(np.linalg.norm(o["point"], axis=1).max(initial=0.0)), 0.075)
+        ed = abs(float(o["depth"]) - float(g["depth"])) / pscale
+        if cross:
+            rep["normal_err_cross"] = max(rep["normal_err_cross"], en)
+            rep["depth_err_cross"] = max(rep["depth_err_cross"], ed)
+        else:
+            rep["normal_err"] = max(rep["normal_err"], en)
+            rep["depth_err"] = max(rep["depth_err"], ed)
         if list(o["slot"]) != list(g["slot"]):
             rep["slot_mismatch"].append((k, list(o["slot"]), list(g["slot"])))
             continue
@@ -81,7 +94,9 @@ def compare_contacts(om: dict, gm: dict, masses=None, impulses: bool = True) -> 
         if impulses:
             rep["lam_err"] = max(rep["lam_err"], float((np.abs(o["lam"] - g["lam"]) / lam_scale).max()))
     rep["ok"] = (not rep["missing"] and not rep["extra"] and not rep["colour_mismatch"] and not rep["slot_mismatch"]
-                 and rep["point_err"] <= 1e-5 and rep["lam_err"] <= 1e-4)
+                 and rep["point_err"] <= 1e-5 and rep["lam_err"] <= 1e-4
+                 and rep["normal_err"] <= 1e-5 and rep["depth_err"] <= 1e-5
+                 and rep["normal_err_cross"] <= 1e-3 and rep["depth_err_cross"] <= 1e-3)
     return rep
 
 
