@@ -35,6 +35,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+DEVICE_ERRORS = []   # device error reports (capacity, non-finite state) met by any leg
+
+
+def _synced(J, fn, *a):
+    """A syncing C-ABI query; device error bits it reports (JG_ECAPACITY / JG_ENAN: the call did
+    its work) are noted in the output instead of ending the run."""
+    try:
+        return fn(*a)
+    except J.JengaError as e:
+        if e.code in (J.JG_ECAPACITY, J.JG_ENAN) and e.result is not None:
+            DEVICE_ERRORS.append(str(e))
+            log(f"  device error report: {e}")
+            return e.result
+        raise
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
@@ -135,8 +151,8 @@ def _run_residuals(J, scene, steps, chunk, **kw):
         n = min(chunk, steps - done)
         world.step(n)
         done += n
-        res.extend(world.stats(t).residual_rms for t in range(scene["n_towers"]))
-    st = world.stats()
+        res.extend(_synced(J, world.stats, t).residual_rms for t in range(scene["n_towers"]))
+    st = _synced(J, world.stats)
     world.close()
     res = np.asarray(res)
     return float(np.median(res)), float(res.mean()), st
@@ -154,7 +170,7 @@ def _run_timed(J, torch, scene, steps, **kw):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    st = world.stats()
+    st = _synced(J, world.stats)
     world.close()
     return scene["n_towers"] * steps / (ms * 1e-3), ms, st
 
@@ -215,17 +231,17 @@ def large_island(J, torch, W, steps):
     stream = torch.cuda.current_stream()
     world = J.World(scene, stream=stream.cuda_stream)
     world.step(5)
-    world.sync()
-    s0 = world.stats()
-    J.jg_query_phase_cycles(world.h)
+    _synced(J, world.sync)
+    s0 = _synced(J, world.stats)
+    _synced(J, J.jg_query_phase_cycles, world.h)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     world.step(steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    s1 = world.stats()
-    phases = J.jg_query_phase_cycles(world.h)
+    s1 = _synced(J, world.stats)
+    phases = _synced(J, J.jg_query_phase_cycles, world.h)
     tot = max(1, sum(phases.values()))
     n = int(scene["tower_ptr"][-1])
     world.close()
@@ -338,13 +354,13 @@ def main():
 
     if args.warmup > 0:
         world.step(args.warmup)
-        world.sync()
+        _synced(J, world.sync)
         log(f"warm-up {args.warmup} steps done")
         world.set_state(*init)
     world.step(0)          # make the restored state resident before the timed region
-    world.sync()
-    s0 = world.stats()
-    J.jg_query_phase_cycles(world.h)   # reset the per-phase counters
+    _synced(J, world.sync)
+    s0 = _synced(J, world.stats)
+    _synced(J, J.jg_query_phase_cycles, world.h)   # reset the per-phase counters
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -356,8 +372,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernel_ms = ev0.elapsed_time(ev1)
-    s1 = world.stats()
-    phases = J.jg_query_phase_cycles(world.h)
+    s1 = _synced(J, world.stats)
+    phases = _synced(J, J.jg_query_phase_cycles, world.h)
     total_cyc = max(1, sum(phases.values()))
     log(f"timed {args.steps} steps: wall {wall * 1e3:.1f} ms, kernel (events) {kernel_ms:.1f} ms")
     log("phase share of workgroup cycles: " + ", ".join(f"{k} {100.0 * v / total_cyc:.1f}%" for k, v in phases.items()))
@@ -432,6 +448,7 @@ def main():
     if args.cpu_report:
         log("oracle timing report ...")
         out["cpu_report"] = cpu_report()
+    out["device_error_reports"] = DEVICE_ERRORS
     print(json.dumps(out), flush=True)
 
 

@@ -17,16 +17,26 @@
  *    Angular velocities are world-frame.  Body x is the box's length axis.
  *  - All host arrays are owned by the caller, row-major, double precision:
  *    vec3 arrays are n x 3, quaternion arrays n x 4.  The library copies them.
- *  - The world owns its device memory; it is allocated by jg_create_world and
- *    when towers are added, never inside jg_step_batch.
+ *  - The world owns its device memory.  Host-side changes (bodies, pushes, friction,
+ *    state, activity) are kept on the host until jg_commit, which sizes the packing,
+ *    allocates or resizes device buffers and copies the changes over.  jg_step_batch
+ *    then only queues kernel launches: it allocates no device memory, copies nothing
+ *    and does not wait, and it refuses (JG_ESTATE) while host-side changes are not
+ *    committed.
  *  - Every function returns a jg_status (0 = JG_OK, negative = error) and never
  *    throws.  jg_last_error() gives a thread-local message for the last error.
  *  - Calls on one world are not thread safe.  GPU work is queued on the stream
  *    given in jg_params.stream (NULL = the default stream); jg_step_batch returns
- *    without waiting, the jg_query_* calls wait for the stream.
- *  - Device-side problems (capacity overflow, colour cap, non-finite state) set
- *    an error word; the step drops the excess deterministically and the next
- *    jg_query_stats reports it.
+ *    without waiting; jg_sync and the jg_query_* calls wait for the stream
+ *    ("syncing calls").
+ *  - Device-side problems set bits of an error word (JG_ERR_*) and the step degrades
+ *    deterministically: colliding pairs beyond a pack's capacity and manifolds beyond
+ *    64 colours are dropped (the highest in canonical order first), and a tower whose
+ *    state is non-finite at the start of a step is frozen (its bodies neither move nor
+ *    collide and keep their state; the other towers step on, bit for bit as without it)
+ *    until the host sets a new state.  The next syncing call does its work, then
+ *    returns JG_ENAN (a non-finite state) or JG_ECAPACITY (a capacity bit) once for
+ *    the bits raised since the previous syncing call; jg_query_stats keeps their OR.
  */
 #ifndef JENGA_H
 #define JENGA_H
@@ -85,6 +95,15 @@ typedef struct {
                             count, up to 8, built on first use and rebuilt when the layout, a device
                             buffer or a parameter changes), so that a loop of short calls pays one graph
                             launch per call; the results are those of the direct launch; default 0 */
+  /* episode criteria (Sec. "Stability Detection and Collapse"; used after jg_begin_episodes) */
+  double collapse_fd;    /* f_d of Eq. (collapse): a block moved more than f_d times its length; 0.5 */
+  double collapse_ek;    /* epsilon_k of Eq. (collapse) [J]; 5e-5 */
+  double collapse_theta; /* theta_th of Eq. (collapse) [degrees]; 30 */
+  double rest_ek;        /* kinetic energy below which a collapsed tower is at rest [J]; 1e-7 */
+  double support_eps;    /* eps of Eq. (stability): blocks whose lowest point is this close to the
+                            ground support the tower [m]; 2e-3 */
+  int32_t rest_steps;    /* steps after the collapse after which the tower is held even if not at
+                            rest (Sec. "Full Floor Contact Simulation"); 400 */
 } jg_params;
 
 /* One contact point of the last solved step. */
@@ -118,18 +137,23 @@ typedef struct {
 /* Fill *p with the defaults listed above. */
 void jg_default_params(jg_params* p);
 
-/* Create an empty world on p->device.  max_towers / max_bodies bound what may be
- * added.  *out receives the handle (NULL on failure). */
+/* Create an empty world on p->device (the problem statement of Sec. "Physics Engine": many
+ * independent towers, each a set of rigid boxes on the ground).  max_towers / max_bodies bound
+ * what may be added; the body state arrays are allocated here.  *out receives the handle (NULL
+ * on failure; JG_EINVAL for bad parameters, JG_EDEVICE / JG_ENOMEM for device failures). */
 int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodies, jg_world** out);
 
-/* Release the world and its device memory (waits for queued work). */
+/* Release the world and its device memory (waits for queued work).  NULL is accepted. */
 int32_t jg_destroy_world(jg_world* w);
 
 /* Add n boxes to tower `tower` (0 <= tower < max_towers; towers are numbered
- * densely by first use).  half_extents: n x 3 body-frame half sizes (> 0);
+ * densely by first use).  Each box is a rigid body with the state (x, q, v, omega) of
+ * Sec. "State of a Rigid Body"; its body-frame inertia follows from the mass and the full
+ * sizes by Eq. (inertia).  half_extents: n x 3 body-frame half sizes (> 0);
  * mass: n (> 0, or 0 for a static box); pos: n x 3; quat: n x 4 (normalised by
  * the library); linvel, angvel: n x 3 or NULL (zero).  body_ids_out (n, may be
- * NULL) receives the global body ids, assigned densely in call order. */
+ * NULL) receives the global body ids, assigned densely in call order.  Host side only
+ * (takes effect at jg_commit); JG_ECAPACITY beyond max_bodies, JG_EINVAL for bad values. */
 int32_t jg_add_boxes(jg_world* w, int32_t tower, int32_t n, const double* half_extents, const double* mass,
                      const double* pos, const double* quat, const double* linvel, const double* angvel,
                      int32_t* body_ids_out);
@@ -138,39 +162,62 @@ int32_t jg_add_boxes(jg_world* w, int32_t tower, int32_t n, const double* half_e
  * tower, or for every tower when tower = -1.  Default 0.4. */
 int32_t jg_set_friction(jg_world* w, int32_t tower, double mu);
 
+/* Move types of Tab. ziglar: the centre block and a side block pushed along its length
+ * (no torque, F = 3 mu m g), a side block pushed across it (torque, F = 4 mu m g). */
+#define JG_MOVE_NONE (-1)
+#define JG_MOVE_CENTER_X 0
+#define JG_MOVE_SIDE_Y 1
+#define JG_MOVE_SIDE_X 2
+
 /* Schedule a constant world-frame force at the centre of mass of `body`, acting on
  * steps [start_step, start_step + n_steps) (Ziglar pushes, Eqs. 4 and 8).  When
  * withdraw > 0 the body is deactivated (removed) once its displacement along the
- * force since start_step reaches withdraw metres. */
+ * force since start_step reaches withdraw metres.  move: the push's move type (JG_MOVE_*) for
+ * the episode counts of jg_query_episode, or JG_MOVE_NONE.  In a tower whose collapse has been
+ * declared (jg_begin_episodes) no push acts and no block is withdrawn any more.  Host side only. */
 int32_t jg_set_push(jg_world* w, int32_t body, const double force[3], int32_t start_step, int32_t n_steps,
-                    double withdraw);
+                    double withdraw, int32_t move);
 
-/* Activate (1) or remove (0) a body; inactive bodies neither move nor collide. */
+/* Activate (1) or remove (0) a body, as in the block withdrawal of Sec. "Effect of the
+ * Friction Coefficient"; inactive bodies neither move nor collide.  Host side only. */
 int32_t jg_set_active(jg_world* w, int32_t body, int32_t active);
 
-/* Queue n_steps steps of every tower on the world's stream (one kernel launch).  Changes made
- * on the host since the last call (bodies, pushes, state, friction) are copied to the device
- * first; n_steps = 0 only does that copy.  The on-chip packing is recomputed (and per-pack
- * buffers reallocated) after towers or pushes were added. */
+/* Make the host-side changes since the last commit resident on the device: recompute the
+ * packing and (re)allocate per-pack buffers after towers or pushes were added, copy bodies,
+ * state, friction and pushes, and forget the previous step's impulses after a state change.
+ * Waits for the copies.  A world with no pending change returns at once. */
+int32_t jg_commit(jg_world* w);
+
+/* Queue n_steps steps of every tower on the world's stream: each step is the pipeline of
+ * Secs. "Rigid-Body Foundations", "Physics Engine --- Collision Detection" and "Contact
+ * Solver --- Projected Gauss-Seidel (PGS)" listed at the top of this file, run n_sub times
+ * with dt / n_sub.  Kernel launches only (see the conventions above); JG_ESTATE while
+ * host-side changes wait for jg_commit, or for warm_start 2 without a network. */
 int32_t jg_step_batch(jg_world* w, int32_t n_steps);
 
-/* Copy bodies [first_body, first_body + n) to host arrays (any may be NULL).  Waits. */
+/* Copy the state (x, q, v, omega; Sec. "State of a Rigid Body") of bodies
+ * [first_body, first_body + n) to host arrays (any may be NULL).  Syncing call. */
 int32_t jg_query_state(jg_world* w, int32_t first_body, int32_t n, double* pos, double* quat, double* linvel,
                        double* angvel);
 
-/* Overwrite bodies [first_body, first_body + n) (any array may be NULL = keep). */
+/* Overwrite the state of bodies [first_body, first_body + n) (any array may be NULL = keep;
+ * quaternions are normalised, a zero quaternion is JG_EINVAL).  Host side only: takes effect
+ * at jg_commit, which also unfreezes every tower and forgets the previous step's impulses. */
 int32_t jg_set_state(jg_world* w, int32_t first_body, int32_t n, const double* pos, const double* quat,
                      const double* linvel, const double* angvel);
 
-/* Active flags of bodies [first_body, first_body + n).  Waits. */
+/* Active flags of bodies [first_body, first_body + n) (withdrawn bodies are 0).  Syncing call. */
 int32_t jg_query_active(jg_world* w, int32_t first_body, int32_t n, uint8_t* active);
 
-/* Contact points of one tower's last solved step, in solve order.  Writes at most
- * `capacity` records to out and the total count to *n_out.  Waits. */
+/* Contact points (Sec. "Contact Manifold (Face Clipping)") of one tower's last solved step with
+ * their impulses (Eq. (lambda_n), Eq. (coulomb_pgs)), in solve order.  Writes at most
+ * `capacity` records to out and the total count to *n_out.  Syncing call. */
 int32_t jg_query_contacts(jg_world* w, int32_t tower, jg_contact* out, int32_t capacity, int32_t* n_out);
 
 /* Counters of one tower, or the sum over towers when tower = -1 (then colours is the
- * max, the residuals are the max over towers, error_word the OR).  Waits. */
+ * max, the residuals are the max over towers, error_word the OR).  The residual is the
+ * natural-map residual of the PGS rows after the solve (the complementarity conditions of
+ * Eq. (non_pen) and Eq. (coulomb_pgs)).  Syncing call. */
 int32_t jg_query_stats(jg_world* w, int32_t tower, jg_stats* out);
 
 /* Diagnostics: GPU cycles spent per phase of the step kernel since the last call, summed
@@ -191,11 +238,60 @@ int32_t jg_query_features(jg_world* w, int32_t tower, float* out, int32_t capaci
  * The world keeps a device copy and its packed form; call again to replace it. */
 int32_t jg_set_mlp(jg_world* w, const float* params);
 
-/* Number of towers and bodies added so far. */
+/* Number of towers and bodies added so far (host side). */
 int32_t jg_world_size(jg_world* w, int32_t* n_towers, int32_t* n_bodies);
 
-/* Wait for all queued work of the world. */
+/* Wait for all queued work of the world.  Syncing call. */
 int32_t jg_sync(jg_world* w);
+
+/* Zero-copy views of the device state for a caller that keeps tensors on the GPU (the state
+ * (x, q, v, omega) of Sec. "State of a Rigid Body"): component-major FP32 arrays
+ * x[3][stride], q[4][stride] (w, x, y, z), v[3][stride], angvel[3][stride] in the world's
+ * internal body order (jg_body_slots maps body ids to it); stride = max_bodies.  The world
+ * owns the memory; the pointers stay valid until the next jg_commit that rebuilds the packing
+ * (after towers or pushes were added) or jg_destroy_world.  Between jg_commit and the next
+ * host-side setter the device arrays are authoritative: the caller may read or write them
+ * between launches (ordered on the world's stream), and every setter or query first reads them
+ * back.  A setter makes the host copy authoritative until jg_commit, which then overwrites the
+ * device arrays.  JG_ESTATE while host-side changes wait for jg_commit.  Any output may be NULL. */
+int32_t jg_device_views(jg_world* w, void** x, void** q, void** v, void** angvel, int32_t* stride);
+
+/* One tower's episode (Sec. "Stability Detection and Collapse"), as of the end of the last step. */
+typedef struct {
+  int32_t collapsed;       /* Eq. (collapse) held at the end of some step (then pushes stop) */
+  int32_t done;            /* held after the collapse: at rest (ek < rest_ek) or rest_steps later */
+  int32_t collapse_step;   /* step that declared the collapse, -1 = none */
+  int32_t rest_step;       /* step the tower came to rest after it, -1 = not (yet) */
+  int32_t rounds;          /* moves (pushes with a move type) started by the collapse step, or by the
+                              last step if there was none */
+  int32_t torque_moves;    /* of those, JG_MOVE_SIDE_X moves */
+  int32_t removed;         /* of those, blocks withdrawn */
+  int32_t support_vertices;   /* vertices of the support polygon of Eq. (stability) */
+  float ek;                /* kinetic energy of the tower's active blocks [J] */
+  float dx_max;            /* largest displacement of a block since jg_begin_episodes [m] */
+  float theta_max;         /* largest angle between a block's thickness axis and the vertical [rad] */
+  float margin;            /* Eq. (stability): smallest signed distance of the centre of mass to the
+                              support polygon's edges, positive inside [m]; -inf without a polygon */
+  float imbalance;         /* -margin at the end of the last step before the collapse (or of the last
+                              step) [m]; NaN if the first step collapsed */
+  float com[2];            /* horizontal centre of mass [m] */
+  float _pad;
+} jg_episode;
+
+/* Start an episode in every tower: the current positions become the reference of the displacement
+ * criterion, and no tower is collapsed.  From then on every step evaluates the criteria of
+ * Eq. (collapse) and Eq. (stability) for each tower and applies the episode rules.  Needs a
+ * committed world (JG_ESTATE otherwise); a later jg_commit that rebuilds the packing (after towers or
+ * pushes were added) ends the episodes.  Allocates the episode state on first use; waits. */
+int32_t jg_begin_episodes(jg_world* w);
+
+/* The episode of one tower (JG_ESTATE without jg_begin_episodes).  Syncing call. */
+int32_t jg_query_episode(jg_world* w, int32_t tower, jg_episode* out);
+
+/* Internal slots of bodies [first_body, first_body + n) in the arrays of jg_device_views
+ * (valid until the packing is rebuilt).  JG_ESTATE while added towers or pushes wait for
+ * jg_commit. */
+int32_t jg_body_slots(jg_world* w, int32_t first_body, int32_t n, int32_t* slots);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* jg_last_error(void);

@@ -143,6 +143,46 @@ void or_mlp_forward(const double* mlp, const double f[OR_NFEAT], double y[3]);
 int or_broadphase(int nb, const double* he, const double* mass, const double* x, const double* q,
                   const uint8_t* active, double margin, int32_t* pairs, int cap);
 
+/* ---- episode criteria (Sec. "Stability Detection and Collapse"), episode_oracle.c ---- */
+typedef struct {
+  double fd;            /* f_d of Eq. (collapse): displacement over the block's length, 0.5 */
+  double ek_collapse;   /* epsilon_k of Eq. (collapse), 5e-5 J */
+  double theta_deg;     /* theta_th of Eq. (collapse), 30 degrees */
+  double ek_rest;       /* rest threshold of simulate_until_rest, 1e-7 J */
+  double eps;           /* support epsilon of Eq. (stability), 2 mm */
+  int32_t rest_steps;   /* steps after the collapse at most, 400 */
+  int32_t _pad;
+} or_episode_params;
+
+typedef struct {
+  double ek;            /* kinetic energy of the active dynamic blocks [J] */
+  double dx_max;        /* largest displacement from the episode's start [m] */
+  double theta_max;     /* largest angle between a block's thickness axis and the vertical [rad] */
+  double margin;        /* Eq. (stability) margin [m] (positive inside; -inf without a polygon) */
+  double com[2];        /* horizontal centre of mass [m] */
+  int32_t n_support;    /* support-polygon vertices */
+  int32_t c_d, c_k, c_theta;   /* the three conditions of Eq. (collapse) */
+} or_episode_metrics;
+
+typedef struct {
+  int32_t collapsed, done;          /* collapse declared; at rest (or out of steps) after it */
+  int32_t collapse_step, rest_step; /* -1 = not reached */
+  double imbalance;                 /* -margin at the end of the last step before the collapse [m] */
+  or_episode_metrics last;          /* criteria at the end of the last step */
+} or_episode_state;
+
+/* Criteria of one tower's state; x0: positions at the episode's start. */
+void or_episode_eval(const or_episode_params* E, int nb, const double* he, const double* mass,
+                        const double* x, const double* q, const double* v, const double* w,
+                        const uint8_t* active, const double* x0, or_episode_metrics* out);
+
+/* One step of one tower under the episode rules (see episode_oracle.c); prev/mout as in
+ * or_step_tower (manifolds of the previous and of this step). */
+int or_step_episode(const or_params* p, const or_episode_params* E, int nb, const double* he, const double* mass,
+                    double* x, double* q, double* v, double* w, uint8_t* active, double mu, int npush,
+                    or_push* push, int64_t* step_counter, const double* x0, or_episode_state* es,
+                    const or_manifold* prev, int nprev, or_manifold* mout, int mcap, int* nm_out, or_stats* st);
+
 #ifdef __cplusplus
 }
 #endif

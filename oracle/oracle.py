@@ -16,6 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("JENGA_ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
 SRC = os.path.join(HERE, "jenga_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "episode_oracle.c")]
 
 
 def build(force: bool = True) -> str:
@@ -23,7 +24,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-fno-fast-math", "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
+                               "-fno-fast-math", "-ffp-contract=off", "-o", tmp, *SRCS, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -56,6 +57,31 @@ class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("candidates", C.c_int64), ("manifolds", C.c_int64),
                 ("points", C.c_int64), ("contact_iters", C.c_int64), ("fallbacks", C.c_int64), ("colours", C.c_int32),
                 ("error", C.c_int32), ("res_rms", C.c_double), ("res_max", C.c_double)]
+
+
+class EpisodeParams(C.Structure):
+    _fields_ = [("fd", C.c_double), ("ek_collapse", C.c_double), ("theta_deg", C.c_double),
+                ("ek_rest", C.c_double), ("eps", C.c_double), ("rest_steps", C.c_int32), ("_pad", C.c_int32)]
+
+
+class EpisodeMetrics(C.Structure):
+    _fields_ = [("ek", C.c_double), ("dx_max", C.c_double), ("theta_max", C.c_double), ("margin", C.c_double),
+                ("com", C.c_double * 2), ("n_support", C.c_int32), ("c_d", C.c_int32), ("c_k", C.c_int32),
+                ("c_theta", C.c_int32)]
+
+
+class EpisodeState(C.Structure):
+    _fields_ = [("collapsed", C.c_int32), ("done", C.c_int32), ("collapse_step", C.c_int32),
+                ("rest_step", C.c_int32), ("imbalance", C.c_double), ("last", EpisodeMetrics)]
+
+
+def episode_params(fd=0.5, ek_collapse=5e-5, theta_deg=30.0, ek_rest=1e-7, eps=2e-3, rest_steps=400):
+    """Thresholds of Eq. (collapse), the support epsilon of Eq. (stability) and the rest rule of
+    Sec. "Full Floor Contact Simulation" (the paper's values by default)."""
+    E = EpisodeParams()
+    E.fd, E.ek_collapse, E.theta_deg, E.ek_rest, E.eps, E.rest_steps = fd, ek_collapse, theta_deg, ek_rest, eps, \
+        int(rest_steps)
+    return E
 
 
 class SatResult(C.Structure):
@@ -99,6 +125,14 @@ def lib():
             L.or_mlp_forward.argtypes = [_dp, _dp, _dp]
             L.or_broadphase.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _u8p, C.c_double, _i32p, C.c_int]
             L.or_broadphase.restype = C.c_int
+            L.or_episode_eval.argtypes = [C.POINTER(EpisodeParams), C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _u8p, _dp,
+                                          C.POINTER(EpisodeMetrics)]
+            L.or_step_episode.argtypes = [C.POINTER(Params), C.POINTER(EpisodeParams), C.c_int, _dp, _dp, _dp, _dp,
+                                          _dp, _dp, _u8p, C.c_double, C.c_int, C.POINTER(Push),
+                                          C.POINTER(C.c_int64), _dp, C.POINTER(EpisodeState),
+                                          C.POINTER(Manifold), C.c_int, C.POINTER(Manifold), C.c_int,
+                                          C.POINTER(C.c_int), C.POINTER(Stats)]
+            L.or_step_episode.restype = C.c_int
             _lib = L
     return _lib
 
@@ -197,6 +231,21 @@ def broadphase(he, mass, x, q, active, margin):
     n = lib().or_broadphase(nb, _f64(he, (nb, 3)), _f64(mass, nb), _f64(x, (nb, 3)), _f64(q, (nb, 4)),
                             np.ascontiguousarray(active, np.uint8), float(margin), pairs, cap)
     return pairs[:2 * n].reshape(n, 2)
+
+
+def episode_eval(he, mass, x, q, v, w, active, x0, E: EpisodeParams | None = None) -> dict:
+    """Eq. (stability) margin and the terms of Eq. (collapse) for one tower's state."""
+    nb = len(mass)
+    out = EpisodeMetrics()
+    lib().or_episode_eval(C.byref(E or episode_params()), nb, _f64(he, (nb, 3)), _f64(mass, nb), _f64(x, (nb, 3)),
+                          _f64(q, (nb, 4)), _f64(v, (nb, 3)), _f64(w, (nb, 3)), np.ascontiguousarray(active, np.uint8),
+                          _f64(x0, (nb, 3)), C.byref(out))
+    return metrics_dict(out)
+
+
+def metrics_dict(m: EpisodeMetrics) -> dict:
+    return dict(ek=m.ek, dx_max=m.dx_max, theta_max=m.theta_max, margin=m.margin, com=np.array(m.com[:]),
+                n_support=m.n_support, c_d=bool(m.c_d), c_k=bool(m.c_k), c_theta=bool(m.c_theta))
 
 
 def manifold_dict(m: Manifold) -> dict:
@@ -305,6 +354,56 @@ class OracleWorld:
         else:
             with ThreadPoolExecutor(threads) as ex:
                 list(ex.map(lambda t: self.step_tower(t, n_steps, record), towers))
+
+    # -- episodes (Sec. "Stability Detection and Collapse") --------------------------------------
+
+    def begin_episodes(self, E: EpisodeParams | None = None):
+        """Start an episode in every tower: the current positions are the reference of Eq. (collapse)'s
+        displacement; no tower is collapsed."""
+        self.episode_E = E or episode_params()
+        self.x0 = self.x.copy()
+        self.episodes = [EpisodeState() for _ in range(self.T)]
+        for es in self.episodes:
+            es.collapse_step = es.rest_step = -1
+            es.imbalance = float("nan")
+
+    def step_tower_episode(self, t: int, n_steps: int):
+        a, b = int(self.ptr[t]), int(self.ptr[t + 1])
+        nb = b - a
+        es = self.episodes[t]
+        if nb == 0:
+            self.step_counter[t].value += n_steps
+            return
+        x = self.x[a:b]; q = self.q[a:b]; v = self.v[a:b]; w = self.w[a:b]
+        act = self.active[a:b]
+        cap = 6 * nb + 8
+        for _ in range(n_steps):
+            out = (Manifold * cap)()
+            nout = C.c_int(0)
+            prev = self.contacts[t]
+            lib().or_step_episode(C.byref(self.params), C.byref(self.episode_E), nb, self.he[a:b], self.mass[a:b],
+                                  x, q, v, w, act, float(self.mu[t]), len(self.pushes[t]), self.push_arrays[t],
+                                  C.byref(self.step_counter[t]), self.x0[a:b], C.byref(es),
+                                  prev if prev is not None else None, int(self.ncontacts[t]), out, cap,
+                                  C.byref(nout), C.byref(self.stats[t]))
+            if not es.done or nout.value:
+                self.contacts[t] = out
+                self.ncontacts[t] = min(nout.value, cap)
+
+    def step_episodes(self, n_steps: int = 1, towers=None, threads: int = 1):
+        """Step towers under the episode rules (begin_episodes first)."""
+        towers = range(self.T) if towers is None else towers
+        if threads <= 1:
+            for t in towers:
+                self.step_tower_episode(t, n_steps)
+        else:
+            with ThreadPoolExecutor(threads) as ex:
+                list(ex.map(lambda t: self.step_tower_episode(t, n_steps), towers))
+
+    def episode(self, t: int) -> dict:
+        es = self.episodes[t]
+        return dict(collapsed=bool(es.collapsed), done=bool(es.done), collapse_step=es.collapse_step,
+                    rest_step=es.rest_step, imbalance=es.imbalance, **metrics_dict(es.last))
 
     def manifolds(self, t: int):
         arr = self.contacts[t]

@@ -21,6 +21,8 @@ namespace jg {
 
 constexpr uint32_t kActive = 1u;    // body takes part in the simulation
 constexpr uint32_t kDynamic = 2u;   // mass > 0 (written by the solver)
+constexpr uint32_t kHeld = 4u;      // on chip only: an active body of a frozen tower (treated as
+                                    // inactive; written back as active)
 constexpr int kMaxColours = 64;
 constexpr int kWave = 64;
 constexpr int kRing = 128;          // broadphase -> narrowphase candidate ring
@@ -65,6 +67,13 @@ struct StepArgs {
   uint32_t* tower_count;       // [tower][4]: candidates, manifolds, points, colours(last)
   float* tower_res;            // [tower][2]: rms, max of the last solve
   uint32_t* pack_error;        // [pack]
+  uint32_t* err_flag;          // one word: error bits raised since the host last read it
+  uint32_t* tower_frozen;      // [tower] 1 = the tower's state was found non-finite: it is held
+  // episodes (Sec. "Stability Detection and Collapse"); ep_state null = not tracked
+  uint32_t* ep_state;          // [tower][kEpisodeWords] (see kEp*)
+  const float* ep_x0;          // [3][cap] positions at the episode's start
+  float ep_fd, ep_ek_collapse, ep_cos_theta, ep_ek_rest, ep_eps;
+  int32_t ep_rest_steps;
   // contacts of the last step
   uint32_t* out_ab;            // [slot]  a << 16 | b (pack-local, b = 0xffff ground)
   uint32_t* out_meta;          // npts | colour << 4 | slots << 12 (4 x 4 bits)
@@ -98,7 +107,7 @@ struct StepArgs {
 };
 
 constexpr int kBodyWords = 31;     // x3 q4 v3 w3 he3 invm invI3 flag tower Iw6 aabb/mask3
-constexpr int kTowerWords = 13;    // body range, mu, counters4, residual2, canonical range2, points
+constexpr int kTowerWords = 14;    // body range, mu, counters4, residual2, canonical range2, points, frozen
 constexpr int kPushWords = 10;
 constexpr int kManWords = 4;       // canonical (code, pos) + sorted (code, meta)
 constexpr int kManDevWords = 28;   // r_A 12, lambda 12, n 3, depth per sorted manifold, in the
@@ -108,6 +117,15 @@ constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-
 constexpr int kLearnedIslandWaves = 4;          // waves of a pack in device memory with the network
                                                 // and the chunk's previous dimensionless impulses
 constexpr int kFeatRecord = 30;
+
+// per-tower episode words: flags (kEpCollapsed | kEpDone), collapse step, rest step (-1 = not
+// reached), support-polygon vertices, then floats: kinetic energy, largest displacement, largest
+// tilt, margin of Eq. (stability) at the end of the last step, imbalance (-margin one step before
+// the collapse), centre of mass x, y
+constexpr int kEpisodeWords = 12;
+constexpr uint32_t kEpCollapsed = 1u, kEpDone = 2u;
+enum { kEpFlags = 0, kEpCollapseStep, kEpRestStep, kEpSupport, kEpEk, kEpDx, kEpTheta, kEpMargin, kEpImbalance,
+       kEpComX, kEpComY };
 
 constexpr int kRegBodies = 256;    // largest pack the LDS path takes (register broadphase windows)
 

@@ -70,6 +70,7 @@ struct Lds {
   uint32_t* tcnt;     // [t*4 + k]: candidates, manifolds, points (launch totals), colours (last step)
   float* tres;        // [t*2 + k]
   int32_t *tc0, *tc1, *tpts;   // canonical range and points of the current step
+  uint32_t* tfz;      // [t]: 1 = the tower's state was non-finite at a step's start (held)
   // pushes
   int32_t *pb, *ps, *pn;
   float *pf, *pwd, *px0;
@@ -132,6 +133,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool u
   L.tb0 = (int32_t*)take(nt); L.tb1 = (int32_t*)take(nt); L.mu = take(nt);
   L.tcnt = (uint32_t*)take(4 * nt); L.tres = take(2 * nt);
   L.tc0 = (int32_t*)take(nt); L.tc1 = (int32_t*)take(nt); L.tpts = (int32_t*)take(nt);
+  L.tfz = (uint32_t*)take(nt);
   L.pb = (int32_t*)take(np); L.ps = (int32_t*)take(np); L.pn = (int32_t*)take(np);
   L.pf = take(3 * np); L.pwd = take(np); L.px0 = take(3 * np);
   L.coloff = (int32_t*)take(kMaxColours + 1); L.colcnt = (int32_t*)take(kMaxColours + 1);
@@ -174,6 +176,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool u
     L.tb0 = (int32_t*)htake(nt); L.tb1 = (int32_t*)htake(nt); L.mu = htake(nt);
     L.tcnt = (uint32_t*)htake(4 * nt); L.tres = htake(2 * nt);
     L.tc0 = (int32_t*)htake(nt); L.tc1 = (int32_t*)htake(nt); L.tpts = (int32_t*)htake(nt);
+    L.tfz = (uint32_t*)htake(nt);
     L.pb = (int32_t*)htake(np); L.ps = (int32_t*)htake(np); L.pn = (int32_t*)htake(np);
     L.pf = htake(3 * np); L.pwd = htake(np); L.px0 = htake(3 * np);
     L.wbox = htake((int)window_words(nb));
@@ -1329,6 +1332,144 @@ __device__ __forceinline__ void learned_chunks(const Lds& L, const StepArgs& a, 
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// episodes (Sec. "Stability Detection and Collapse"): at the end of each step, one lane per tower
+// ------------------------------------------------------------------------------------------------
+// The support polygon of Eq. (stability): the horizontal corners of every active block whose lowest
+// point is within eps of the ground, staged in scratch (16 floats per body of the tower), wrapped
+// counter-clockwise from the leftmost-lowest corner (gift wrapping: the next vertex leaves no
+// corner to its right; of collinear corners the farthest); the margin is the smallest signed
+// distance of the centre of mass to the wrapped edges (positive inside; -inf with fewer than three
+// vertices).
+__device__ __forceinline__ float support_margin(const Lds& L, int b0, int b1, float eps, float cx, float cy,
+                                                float* pts, int& nhull) {
+  const int NB = L.nbp;
+  int n = 0;
+  for (int i = b0; i < b1; ++i) {
+    if ((L.flag[i] & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
+    float R[9];
+    body_R(L, i, R);
+    const float he0 = L.he[i], he1 = L.he[NB + i], he2 = L.he[2 * NB + i];
+    const float hz = fabsf(R[6]) * he0 + fabsf(R[7]) * he1 + fabsf(R[8]) * he2;
+    if (!(L.x[2 * NB + i] - hz <= eps)) continue;
+    const float xi = L.x[i], yi = L.x[NB + i];
+    for (int c = 0; c < 8; ++c) {
+      const float s0 = (c & 1) ? he0 : -he0, s1 = (c & 2) ? he1 : -he1, s2 = (c & 4) ? he2 : -he2;
+      pts[2 * n] = xi + (R[0] * s0 + R[1] * s1 + R[2] * s2);
+      pts[2 * n + 1] = yi + (R[3] * s0 + R[4] * s1 + R[5] * s2);
+      ++n;
+    }
+  }
+  nhull = 0;
+  if (n == 0) return -INFINITY;
+  int start = 0;
+  for (int k = 1; k < n; ++k)
+    if (pts[2 * k] < pts[2 * start] || (pts[2 * k] == pts[2 * start] && pts[2 * k + 1] < pts[2 * start + 1])) start = k;
+  const float sx = pts[2 * start], sy = pts[2 * start + 1];
+  float ax = sx, ay = sy;
+  float margin = INFINITY;
+  for (int it = 0; it <= n; ++it) {
+    int nx = -1;
+    float bx = 0.f, by = 0.f, bd = 0.f;
+    for (int k = 0; k < n; ++k) {
+      const float px = pts[2 * k], py = pts[2 * k + 1];
+      if (px == ax && py == ay) continue;
+      const float d2 = (px - ax) * (px - ax) + (py - ay) * (py - ay);
+      if (nx < 0) { nx = k; bx = px; by = py; bd = d2; continue; }
+      const float c = (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+      if (c < 0.f || (c == 0.f && d2 > bd)) { nx = k; bx = px; by = py; bd = d2; }
+    }
+    if (nx < 0) break;                      // every corner at one point
+    const float len = sqrtf(bd);
+    margin = fminf(margin, ((bx - ax) * (cy - ay) - (by - ay) * (cx - ax)) / len);
+    ++nhull;
+    ax = bx;
+    ay = by;
+    if (ax == sx && ay == sy) break;
+  }
+  return nhull >= 3 ? margin : -INFINITY;
+}
+
+// The criteria of Eq. (collapse) for each tower of the pack at the end of step `step`, and the
+// episode rules: a collapse is declared on the first step whose end state meets all three (the
+// imbalance keeps minus the margin of the step before); afterwards the tower is held once its
+// kinetic energy falls below ek_rest or ep_rest_steps steps have passed.  Sums run over the
+// tower's bodies in order (deterministic).  `scratch` holds 16 floats per body of the pack.
+__device__ __forceinline__ void episode_update(const Lds& L, const StepArgs& a, int gt0, int gb0, int nt, int lane,
+                                               int64_t step, float* scratch) {
+  const int NB = L.nbp, CAP = a.cap;
+  for (int t = lane; t < nt; t += kWave) {
+    uint32_t* st = a.ep_state + (size_t)(gt0 + t) * kEpisodeWords;
+    uint32_t flags = st[kEpFlags];
+    if (flags & kEpDone) continue;
+    const int b0 = L.tb0[t], b1 = L.tb1[t];
+    float ek = 0.f, dxmax = 0.f, rzz = 1.f, msum = 0.f, cx = 0.f, cy = 0.f;
+    bool cd = false;
+    for (int i = b0; i < b1; ++i) {
+      if ((L.flag[i] & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
+      const float m = a.mass[gb0 + i];
+      float R[9];
+      body_R(L, i, R);
+      const float l = 2.f * L.he[i], wd = 2.f * L.he[NB + i], hh = 2.f * L.he[2 * NB + i];
+      const float I0 = m / 12.f * (wd * wd + hh * hh), I1 = m / 12.f * (l * l + hh * hh),
+                  I2 = m / 12.f * (l * l + wd * wd);
+      float v[3], w[3];
+      load3(L.v, NB, i, v);
+      load3(L.w, NB, i, w);
+      const float wb0 = R[0] * w[0] + R[3] * w[1] + R[6] * w[2];
+      const float wb1 = R[1] * w[0] + R[4] * w[1] + R[7] * w[2];
+      const float wb2 = R[2] * w[0] + R[5] * w[1] + R[8] * w[2];
+      ek += 0.5f * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      ek += 0.5f * (I0 * wb0 * wb0 + I1 * wb1 * wb1 + I2 * wb2 * wb2);
+      float d2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float d = L.x[k * NB + i] - a.ep_x0[k * CAP + gb0 + i];
+        d2 += d * d;
+      }
+      const float dn = sqrtf(d2);
+      dxmax = fmaxf(dxmax, dn);
+      cd = cd || dn > a.ep_fd * l;
+      rzz = fminf(rzz, R[8]);
+      msum += m;
+      cx += m * L.x[i];
+      cy += m * L.x[NB + i];
+    }
+    if (msum > 0.f) { cx /= msum; cy /= msum; }
+    int nhull = 0;
+    const float margin = support_margin(L, b0, b1, a.ep_eps, cx, cy, scratch + 16 * b0, nhull);
+    const bool ck = ek > a.ep_ek_collapse, ct = rzz < a.ep_cos_theta;
+    st[kEpSupport] = (uint32_t)nhull;
+    st[kEpEk] = __float_as_uint(ek);
+    st[kEpDx] = __float_as_uint(dxmax);
+    st[kEpTheta] = __float_as_uint(acosf(fmaxf(rzz, -1.f)));
+    st[kEpMargin] = __float_as_uint(margin);
+    st[kEpComX] = __float_as_uint(cx);
+    st[kEpComY] = __float_as_uint(cy);
+    if (!(flags & kEpCollapsed)) {
+      if (cd && ck && ct) {
+        flags |= kEpCollapsed;
+        st[kEpCollapseStep] = (uint32_t)(int32_t)step;
+        L.tfz[t] |= 4u;                     // no further push or withdrawal
+      } else {
+        st[kEpImbalance] = __float_as_uint(-margin);
+      }
+    }
+    if (flags & kEpCollapsed) {
+      const int64_t since = step - (int64_t)(int32_t)st[kEpCollapseStep];
+      if (ek < a.ep_ek_rest) {
+        flags |= kEpDone;
+        st[kEpRestStep] = (uint32_t)(int32_t)step;
+      } else if (since >= a.ep_rest_steps) {
+        flags |= kEpDone;
+        st[kEpRestStep] = (uint32_t)(int32_t)-1;
+      }
+      if (flags & kEpDone) L.tfz[t] |= 2u;  // held from the next step on
+    }
+    st[kEpFlags] = flags;
+  }
+}
+
 // wave-uniform phase timer: adds the cycles since the previous mark to counter k
 struct PhaseTimer {
   unsigned long long last;
@@ -1484,6 +1625,13 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     L.tb0[t] = a.tower_body0[gt0 + t] - gb0;
     L.tb1[t] = a.tower_body0[gt0 + t + 1] - gb0;
     L.mu[t] = a.tower_mu[gt0 + t];
+    // bit 1: non-finite state (held); bit 2: episode done (held); bit 4: collapse declared
+    uint32_t fz = a.tower_frozen[gt0 + t] ? 1u : 0u;
+    if (a.ep_state) {
+      const uint32_t ef = a.ep_state[(size_t)(gt0 + t) * kEpisodeWords + kEpFlags];
+      fz |= ((ef & kEpDone) ? 2u : 0u) | ((ef & kEpCollapsed) ? 4u : 0u);
+    }
+    L.tfz[t] = fz;
 #pragma unroll
     for (int k = 0; k < 4; ++k) L.tcnt[t * 4 + k] = 0u;
     L.tres[2 * t] = 0.f;
@@ -1535,6 +1683,27 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     wave_sync();
     for (int sub = 0; sub < a.n_sub; ++sub) {
       const bool last = (s == a.n_steps - 1) && (sub == a.n_sub - 1);
+      // ---- a tower with a non-finite body is frozen: its bodies are held (neither move nor
+      // collide) and keep their state until the host sets a new one ----
+      for (int i = lane; i < nb; i += kWave) {
+        if (!(L.flag[i] & kActive)) continue;
+        bool finite = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          finite = finite && isfinite(L.x[k * NB + i]) && isfinite(L.v[k * NB + i]) && isfinite(L.w[k * NB + i]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) finite = finite && isfinite(L.q[k * NB + i]);
+        if (!finite) {
+          atomicOr(&L.tfz[L.tw[i]], 1u);
+          atomicOr((uint32_t*)&L.scal[3], kErrNan);
+        }
+      }
+      wave_sync();
+      for (int i = lane; i < nb; i += kWave) {
+        const uint32_t f = L.flag[i];
+        if ((f & kActive) && (L.tfz[L.tw[i]] & 3u)) L.flag[i] = (f & ~kActive) | kHeld;
+      }
+      wave_sync();
       // ---- 1. external forces; 2. frames ----
       for (int i = lane; i < nb; i += kWave) {
         const uint32_t f = L.flag[i];
@@ -1545,8 +1714,9 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) vv[k] += dt * a.g[k];
           const float im = L.invm[i];
+          const bool pushes_on = !(L.tfz[L.tw[i]] & 4u);   // none after a declared collapse
           for (int r = 0; r < np; ++r)
-            if (L.pb[r] == i && step >= (int64_t)L.ps[r] && step < (int64_t)L.ps[r] + L.pn[r]) {
+            if (pushes_on && L.pb[r] == i && step >= (int64_t)L.ps[r] && step < (int64_t)L.ps[r] + L.pn[r]) {
 #pragma unroll
               for (int k = 0; k < 3; ++k) vv[k] += dt * L.pf[3 * r + k] * im;
             }
@@ -2107,7 +2277,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
         for (int k = 0; k < 3; ++k) bl[k] = (R[k] * Lw[0] + R[3 + k] * Lw[1] + R[6 + k] * Lw[2]) * iIb[k];
 #pragma unroll
         for (int r = 0; r < 3; ++r) wv[r] = R[3 * r] * bl[0] + R[3 * r + 1] * bl[1] + R[3 * r + 2] * bl[2];
-        bool finite = isfinite(qw);
+        bool finite = isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz);
 #pragma unroll
         for (int k = 0; k < 3; ++k) finite = finite && isfinite(xv[k]) && isfinite(vv[k]) && isfinite(wv[k]);
         if (!finite) atomicOr((uint32_t*)&L.scal[3], kErrNan);
@@ -2142,7 +2312,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     // ---- withdrawal of pushed bodies ----
     for (int r = lane; r < np; r += kWave) {
       const int b = L.pb[r];
-      if (!(L.pwd[r] > 0.f) || step < (int64_t)L.ps[r] || !(L.flag[b] & kActive)) continue;
+      if (!(L.pwd[r] > 0.f) || step < (int64_t)L.ps[r] || !(L.flag[b] & kActive) || (L.tfz[L.tw[b]] & 4u)) continue;
       float dx[3], f[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) { dx[k] = L.x[k * NB + b] - L.px0[3 * r + k]; f[k] = L.pf[3 * r + k]; }
@@ -2153,6 +2323,12 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       }
     }
     wave_sync();
+    // ---- episode criteria at the end of the step (the pack's manifold block is free scratch
+    // until the next step's manifolds) ----
+    if (a.ep_state) {
+      episode_update(L, a, gt0, gb0, nt, lane, step, L.md);
+      wave_sync();
+    }
   }
 
   // ---- write the pack back (a body without mass keeps its stored velocity) ----
@@ -2169,7 +2345,8 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) a.q[k * CAP + g] = L.q[k * NB + i];
-    a.flags[g] = L.flag[i];
+    const uint32_t f = L.flag[i];
+    a.flags[g] = (f & kHeld) ? ((f & ~kHeld) | kActive) : f;
   }
   for (int t = lane; t < nt; t += kWave) {
     const int g = gt0 + t;
@@ -2178,6 +2355,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     a.tower_count[4 * g + 3] = L.tcnt[4 * t + 3];
     a.tower_res[2 * g] = L.tres[2 * t];
     a.tower_res[2 * g + 1] = L.tres[2 * t + 1];
+    a.tower_frozen[g] = L.tfz[t] & 1u;
   }
   for (int r = lane; r < np; r += kWave) {
 #pragma unroll
@@ -2203,7 +2381,10 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     }
     if (lane == 0) a.prev_count[pk] = npv;
   }
-  if (lane == 0) a.pack_error[pk] |= (uint32_t)L.scal[3];
+  if (lane == 0 && L.scal[3]) {
+    a.pack_error[pk] |= (uint32_t)L.scal[3];
+    atomicOr(a.err_flag, (uint32_t)L.scal[3]);
+  }
   timer.mark(L, lane, 0);
   wave_sync();
   if (a.phase_cycles && lane < kPhases) atomicAdd(&a.phase_cycles[lane], L.cyc[lane]);

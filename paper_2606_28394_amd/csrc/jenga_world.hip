@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,7 @@ struct PushRow {
   int start, steps;
   double withdraw;
   double x0[3];
+  int move;        // JG_MOVE_* (episode counts)
 };
 
 }  // namespace
@@ -79,6 +81,8 @@ struct jg_world {
   bool host_dirty = true;     // host mirror newer than the device
   bool device_newer = false;  // device newer than the host mirror
   bool clear_warm = true;     // forget the previous step's impulses before the next launch
+  bool views_out = false;     // jg_device_views was called: device memory may be newer at any time
+  uint32_t err_reported = 0;  // device error bits already returned by a syncing call
   // layout (internal order)
   std::vector<int> int_of_body, body_of_int;
   std::vector<int> tower_order;      // internal tower slot -> tower id
@@ -112,6 +116,12 @@ struct jg_world {
   DevBuf<uint32_t> d_tower_count;
   DevBuf<float> d_tower_res;
   DevBuf<uint32_t> d_pack_error;
+  DevBuf<uint32_t> d_err_flag;      // error bits raised by launches since the host last read them
+  DevBuf<uint32_t> d_tower_frozen;  // [tower slot] frozen (non-finite state) flags
+  // episodes (jg_begin_episodes): per tower slot kEpisodeWords words, reference positions
+  DevBuf<uint32_t> d_ep_state;
+  DevBuf<float> d_ep_x0;
+  bool ep_on = false;
   DevBuf<uint32_t> d_out_ab, d_out_meta;
   DevBuf<float> d_out_geo, d_out_pts;
   DevBuf<int32_t> d_out_count, d_out_tower;
@@ -174,7 +184,7 @@ int32_t set_device(jg_world* w) {
 
 // device -> host mirror
 int32_t download_state(jg_world* w) {
-  if (!w->device_newer) return JG_OK;
+  if (!w->device_newer && !(w->views_out && !w->layout_dirty && !w->host_dirty)) return JG_OK;
   const int n = (int)w->body_of_int.size();
   const int cap = w->max_bodies;
   std::vector<float> buf((size_t)4 * cap);
@@ -219,7 +229,9 @@ int32_t build_layout(jg_world* w) {
     max_tower = std::max(max_tower, (int)w->tower_bodies[t].size());
   }
   if (max_tower > 65534) return fail(JG_ECAPACITY, "a tower has more bodies than one pack can index (65534)");
-  const float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 3.5f;
+  // manifold slots per body: 3.5 in shared packs (sized for LDS); a batch stepped one tower per
+  // workgroup (below) has LDS to spare and gets 6, room for a sinking or collapsing tower's pairs
+  float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 3.5f;
   const int mode = w->prm.warm_start == 2 ? 2 : ((w->prm.warm_start == 1 || w->prm.record_features) ? 1 : 0);
   auto pc_of = [&](int nb) { return std::max(16, (int)std::ceil(mpb * nb)); };
   auto lds_of = [&](int nb, int towers, int pushes) -> size_t {
@@ -238,8 +250,10 @@ int32_t build_layout(jg_world* w) {
     // (the 450-tower removal batch steps 11 % faster so).
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w->prm.device) == hipSuccess && cus > 0 &&
-        (int64_t)order.size() <= (int64_t)cus * (wide ? 4 : 8))
+        (int64_t)order.size() <= (int64_t)cus * (wide ? 4 : 8)) {
       target = 1;
+      if (!(w->prm.manifolds_per_body > 0.f)) mpb = 6.0f;
+    }
   }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return w->tower_bodies[a].size() > w->tower_bodies[b].size();
@@ -395,6 +409,7 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(w->d_tower_count.ensure(4 * nt));
   HIP_TRY(w->d_tower_res.ensure(2 * nt));
   HIP_TRY(w->d_pack_error.ensure(np));
+  HIP_TRY(w->d_tower_frozen.ensure(nt));
   HIP_TRY(w->d_push_body.ensure(npush));
   HIP_TRY(w->d_push_start.ensure(npush));
   HIP_TRY(w->d_push_steps.ensure(npush));
@@ -435,6 +450,7 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(hipMemcpy(w->d_body_tower.p, btw.data(), sizeof(int32_t) * w->max_bodies, hipMemcpyHostToDevice));
   w->layout_dirty = false;
   w->clear_warm = true;
+  w->ep_on = false;   // the episode state is per tower slot of the old layout
   return JG_OK;
 }
 
@@ -468,6 +484,8 @@ int32_t upload_all(jg_world* w) {
   std::vector<float> mu(std::max<size_t>(1, w->tower_order.size()));
   for (size_t s = 0; s < w->tower_order.size(); ++s) mu[s] = (float)w->mu[w->tower_order[s]];
   HIP_TRY(hipMemcpy(w->d_tower_mu.p, mu.data(), sizeof(float) * mu.size(), hipMemcpyHostToDevice));
+  // the host's state replaces the device's: no tower is frozen until a step finds it non-finite
+  HIP_TRY(hipMemset(w->d_tower_frozen.p, 0, sizeof(uint32_t) * mu.size()));
   const size_t P = w->push_order.size();
   if (P) {
     std::vector<int32_t> pb(P), ps(P), pn(P);
@@ -525,6 +543,24 @@ int32_t collect_stats(jg_world* w) {
   if (learned) HIP_TRY(hipMemset(w->d_tower_fallback.p, 0, sizeof(uint32_t) * 2 * T));
   w->stats_pending = false;
   return JG_OK;
+}
+
+// Error bits that launches raised since the last syncing call (the stream has been waited
+// for): JG_ENAN when a state was non-finite, JG_ECAPACITY for a capacity bit, else JG_OK.  Each
+// bit raised by a launch is returned once.
+int32_t report_device_errors(jg_world* w) {
+  uint32_t bits = 0;
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  HIP_TRY(hipMemcpy(&bits, w->d_err_flag.p, sizeof(bits), hipMemcpyDeviceToHost));
+  if (!bits) return JG_OK;
+  HIP_TRY(hipMemset(w->d_err_flag.p, 0, sizeof(uint32_t)));
+  w->err_reported |= bits;
+  std::string what;
+  if (bits & JG_ERR_CANDIDATES) what += " JG_ERR_CANDIDATES (an island body had more than 16 candidates)";
+  if (bits & JG_ERR_MANIFOLDS) what += " JG_ERR_MANIFOLDS (colliding pairs beyond a pack's capacity were dropped)";
+  if (bits & JG_ERR_COLOURS) what += " JG_ERR_COLOURS (manifolds beyond 64 colours were dropped)";
+  if (bits & JG_ERR_NAN) what += " JG_ERR_NAN (a tower's state was non-finite: it is frozen)";
+  return fail((bits & JG_ERR_NAN) ? JG_ENAN : JG_ECAPACITY, "device error bits since the last syncing call:" + what);
 }
 
 // The launch as a HIP graph: one kernel node per launch class and no edges, so the classes may
@@ -634,6 +670,12 @@ void jg_default_params(jg_params* p) {
   p->fallback_tau = 1e30;
   p->record_features = 0;
   p->use_graph = 0;
+  p->collapse_fd = 0.5;
+  p->collapse_ek = 5e-5;
+  p->collapse_theta = 30.0;
+  p->rest_ek = 1e-7;
+  p->support_eps = 2e-3;
+  p->rest_steps = 400;
 }
 
 const char* jg_last_error(void) { return g_err.c_str(); }
@@ -646,6 +688,8 @@ int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodi
   if (p->iters < 0 || p->n_sub < 1 || !(p->dt > 0.0)) return fail(JG_EINVAL, "bad iters, n_sub or dt");
   if (p->warm_start < 0 || p->warm_start > 2) return fail(JG_EINVAL, "warm_start must be 0, 1 or 2");
   if (p->mlp_iters < 0) return fail(JG_EINVAL, "mlp_iters must not be negative");
+  if (p->rest_steps < 0 || !(p->collapse_fd >= 0.0) || !(p->support_eps >= 0.0))
+    return fail(JG_EINVAL, "bad episode parameters");
   jg_world* w = new (std::nothrow) jg_world();
   if (!w) return fail(JG_ENOMEM, "host allocation failed");
   w->prm = *p;
@@ -666,6 +710,8 @@ int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodi
   if (e == hipSuccess) e = w->d_body_tower.ensure(cap);
   if (e == hipSuccess) e = w->d_phase_cycles.ensure(jg::kPhases);
   if (e == hipSuccess) e = hipMemset(w->d_phase_cycles.p, 0, sizeof(unsigned long long) * jg::kPhases);
+  if (e == hipSuccess) e = w->d_err_flag.ensure(1);
+  if (e == hipSuccess) e = hipMemset(w->d_err_flag.p, 0, sizeof(uint32_t));
   if (e != hipSuccess) {
     jg_destroy_world(w);
     return fail(JG_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
@@ -692,6 +738,8 @@ int32_t jg_destroy_world(jg_world* w) {
   note(w->d_push_steps.release()); note(w->d_push_force.release()); note(w->d_push_withdraw.release());
   note(w->d_push_x0.release());
   note(w->d_tower_count.release()); note(w->d_tower_res.release()); note(w->d_pack_error.release());
+  note(w->d_err_flag.release()); note(w->d_tower_frozen.release());
+  note(w->d_ep_state.release()); note(w->d_ep_x0.release());
   note(w->d_out_ab.release()); note(w->d_out_meta.release()); note(w->d_out_geo.release());
   note(w->d_out_pts.release()); note(w->d_out_count.release()); note(w->d_out_tower.release());
   note(w->d_prev_key.release()); note(w->d_prev_data.release()); note(w->d_prev_count.release());
@@ -768,10 +816,11 @@ int32_t jg_set_friction(jg_world* w, int32_t tower, double mu) {
 }
 
 int32_t jg_set_push(jg_world* w, int32_t body, const double force[3], int32_t start_step, int32_t n_steps,
-                    double withdraw) {
+                    double withdraw, int32_t move) {
   if (int32_t r = check_world(w)) return r;
   if (body < 0 || body >= (int)w->mass.size()) return fail(JG_EINVAL, "body index out of range");
   if (!force || n_steps < 0 || !(withdraw >= 0.0)) return fail(JG_EINVAL, "bad push arguments");
+  if (move < JG_MOVE_NONE || move > JG_MOVE_SIDE_X) return fail(JG_EINVAL, "unknown move type");
   if (int32_t r = download_state(w)) return r;
   PushRow pr;
   pr.body = body;
@@ -779,6 +828,7 @@ int32_t jg_set_push(jg_world* w, int32_t body, const double force[3], int32_t st
   pr.start = start_step;
   pr.steps = n_steps;
   pr.withdraw = withdraw;
+  pr.move = move;
   w->pushes.push_back(pr);
   w->layout_dirty = true;
   w->host_dirty = true;
@@ -795,9 +845,8 @@ int32_t jg_set_active(jg_world* w, int32_t body, int32_t active) {
   return JG_OK;
 }
 
-int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
+int32_t jg_commit(jg_world* w) {
   if (int32_t r = check_world(w)) return r;
-  if (n_steps < 0) return fail(JG_EINVAL, "negative step count");
   if (int32_t r = set_device(w)) return r;
   if (w->layout_dirty || w->host_dirty) {
     if (int32_t r = download_state(w)) return r;
@@ -806,11 +855,35 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
       if (int32_t r = build_layout(w)) return r;
     if (int32_t r = upload_all(w)) return r;
   }
-  if (w->clear_warm && w->n_packs > 0) {
-    HIP_TRY(hipMemsetAsync(w->d_prev_count.p, 0, sizeof(int32_t) * w->n_packs, w->stream));
+  if (w->clear_warm) {
+    if (w->n_packs > 0) HIP_TRY(hipMemset(w->d_prev_count.p, 0, sizeof(int32_t) * w->n_packs));
     w->clear_warm = false;
   }
-  if (n_steps == 0) return JG_OK;   // host changes are now resident on the device
+  // one auxiliary stream (and its join event) per launch class after the first
+  const size_t nc = w->classes.size();
+  while (w->aux.size() + 1 < nc) {
+    hipStream_t st;
+    hipEvent_t ev;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    w->aux.push_back(st);
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    w->aux_done.push_back(ev);
+  }
+  if (nc > 1 && !w->fork) HIP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+  // the copies and fills above ran on the null stream and the world's: both are done before
+  // the first launch
+  HIP_TRY(hipStreamSynchronize(nullptr));
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  return JG_OK;
+}
+
+int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
+  if (int32_t r = check_world(w)) return r;
+  if (n_steps < 0) return fail(JG_EINVAL, "negative step count");
+  if (w->layout_dirty || w->host_dirty || w->clear_warm)
+    return fail(JG_ESTATE, "host-side changes are not on the device yet: call jg_commit first");
+  if (int32_t r = set_device(w)) return r;
+  if (n_steps == 0) return JG_OK;
   if (w->prm.warm_start == 2 && !w->mlp_set) return fail(JG_ESTATE, "warm_start 2 needs jg_set_mlp first");
   if (w->n_packs == 0) { w->step += n_steps; return JG_OK; }
   jg::StepArgs a;
@@ -824,6 +897,15 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.push_body = w->d_push_body.p; a.push_start = w->d_push_start.p; a.push_steps = w->d_push_steps.p;
   a.push_force = w->d_push_force.p; a.push_withdraw = w->d_push_withdraw.p; a.push_x0 = w->d_push_x0.p;
   a.tower_count = w->d_tower_count.p; a.tower_res = w->d_tower_res.p; a.pack_error = w->d_pack_error.p;
+  a.err_flag = w->d_err_flag.p; a.tower_frozen = w->d_tower_frozen.p;
+  a.ep_state = w->ep_on ? w->d_ep_state.p : nullptr;
+  a.ep_x0 = w->d_ep_x0.p;
+  a.ep_fd = (float)w->prm.collapse_fd;
+  a.ep_ek_collapse = (float)w->prm.collapse_ek;
+  a.ep_cos_theta = (float)std::cos(w->prm.collapse_theta * 3.14159265358979323846 / 180.0);
+  a.ep_ek_rest = (float)w->prm.rest_ek;
+  a.ep_eps = (float)w->prm.support_eps;
+  a.ep_rest_steps = w->prm.rest_steps;
   a.out_ab = w->d_out_ab.p; a.out_meta = w->d_out_meta.p; a.out_geo = w->d_out_geo.p; a.out_pts = w->d_out_pts.p;
   a.out_count = w->d_out_count.p; a.out_tower = w->d_out_tower.p;
   a.prev_key = w->d_prev_key.p; a.prev_data = w->d_prev_data.p; a.prev_count = w->d_prev_count.p;
@@ -861,18 +943,7 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   } else {
     // Classes are independent (disjoint packs, towers and bodies): run them side by side, so a
     // small batch fills the GPU and one class's tail overlaps the others.
-    while (w->aux.size() + 1 < nc) {
-      hipStream_t s;
-      hipEvent_t ev;
-      HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-      w->aux.push_back(s);
-      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      w->aux_done.push_back(ev);
-    }
-    if (nc > 1) {
-      if (!w->fork) HIP_TRY(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
-      HIP_TRY(hipEventRecord(w->fork, w->stream));
-    }
+    if (nc > 1) HIP_TRY(hipEventRecord(w->fork, w->stream));
     for (size_t k = 0; k < nc; ++k) {
       hipStream_t s = k == 0 ? w->stream : w->aux[k - 1];
       if (k > 0) HIP_TRY(hipStreamWaitEvent(s, w->fork, 0));
@@ -904,7 +975,7 @@ int32_t jg_query_state(jg_world* w, int32_t first_body, int32_t n, double* pos, 
     }
     if (quat) for (int k = 0; k < 4; ++k) quat[4 * i + k] = w->q[4 * id + k];
   }
-  return JG_OK;
+  return report_device_errors(w);
 }
 
 int32_t jg_set_state(jg_world* w, int32_t first_body, int32_t n, const double* pos, const double* quat,
@@ -940,7 +1011,7 @@ int32_t jg_query_active(jg_world* w, int32_t first_body, int32_t n, uint8_t* act
   if (int32_t r = set_device(w)) return r;
   if (int32_t r = download_state(w)) return r;
   for (int i = 0; i < n; ++i) active[i] = w->active[first_body + i];
-  return JG_OK;
+  return report_device_errors(w);
 }
 
 int32_t jg_query_contacts(jg_world* w, int32_t tower, jg_contact* out, int32_t capacity, int32_t* n_out) {
@@ -997,7 +1068,7 @@ int32_t jg_query_contacts(jg_world* w, int32_t tower, jg_contact* out, int32_t c
     ++order;
   }
   *n_out = total;
-  return JG_OK;
+  return report_device_errors(w);
 }
 
 int32_t jg_query_stats(jg_world* w, int32_t tower, jg_stats* out) {
@@ -1021,7 +1092,7 @@ int32_t jg_query_stats(jg_world* w, int32_t tower, jg_stats* out) {
   };
   if (tower >= 0) add(tower);
   else for (int t = 0; t < (int)w->tower_bodies.size(); ++t) add(t);
-  return JG_OK;
+  return report_device_errors(w);
 }
 
 int32_t jg_query_features(jg_world* w, int32_t tower, float* out, int32_t capacity, int32_t* n_out) {
@@ -1062,7 +1133,7 @@ int32_t jg_query_features(jg_world* w, int32_t tower, float* out, int32_t capaci
     }
   }
   *n_out = total;
-  return JG_OK;
+  return report_device_errors(w);
 }
 
 int32_t jg_set_mlp(jg_world* w, const float* params) {
@@ -1096,13 +1167,96 @@ int32_t jg_query_phase_cycles(jg_world* w, uint64_t* cycles, int32_t n) {
   HIP_TRY(hipMemcpy(c, w->d_phase_cycles.p, sizeof(c), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemset(w->d_phase_cycles.p, 0, sizeof(c)));
   for (int k = 0; k < n; ++k) cycles[k] = k < jg::kPhases ? (uint64_t)c[k] : 0u;
-  return JG_OK;
+  return report_device_errors(w);
 }
 
 int32_t jg_sync(jg_world* w) {
   if (int32_t r = check_world(w)) return r;
   if (int32_t r = set_device(w)) return r;
   HIP_TRY(hipStreamSynchronize(w->stream));
+  return report_device_errors(w);
+}
+
+int32_t jg_device_views(jg_world* w, void** x, void** q, void** v, void** angvel, int32_t* stride) {
+  if (int32_t r = check_world(w)) return r;
+  if (w->layout_dirty || w->host_dirty || w->clear_warm)
+    return fail(JG_ESTATE, "host-side changes are not on the device yet: call jg_commit first");
+  if (x) *x = w->d_x.p;
+  if (q) *q = w->d_q.p;
+  if (v) *v = w->d_v.p;
+  if (angvel) *angvel = w->d_w.p;
+  if (stride) *stride = w->max_bodies;
+  w->views_out = true;
+  return JG_OK;
+}
+
+int32_t jg_begin_episodes(jg_world* w) {
+  if (int32_t r = check_world(w)) return r;
+  if (w->layout_dirty || w->host_dirty || w->clear_warm)
+    return fail(JG_ESTATE, "host-side changes are not on the device yet: call jg_commit first");
+  if (int32_t r = set_device(w)) return r;
+  const size_t nt = std::max<size_t>(1, w->tower_order.size());
+  HIP_TRY(w->d_ep_state.ensure(nt * jg::kEpisodeWords));
+  HIP_TRY(w->d_ep_x0.ensure((size_t)3 * w->max_bodies));
+  std::vector<uint32_t> init(nt * jg::kEpisodeWords, 0u);
+  const float qnan = std::numeric_limits<float>::quiet_NaN();
+  uint32_t nan_bits;
+  std::memcpy(&nan_bits, &qnan, sizeof(nan_bits));
+  for (size_t t = 0; t < nt; ++t) {
+    init[t * jg::kEpisodeWords + jg::kEpCollapseStep] = (uint32_t)-1;
+    init[t * jg::kEpisodeWords + jg::kEpRestStep] = (uint32_t)-1;
+    init[t * jg::kEpisodeWords + jg::kEpImbalance] = nan_bits;
+  }
+  HIP_TRY(hipMemcpyAsync(w->d_ep_x0.p, w->d_x.p, sizeof(float) * 3 * w->max_bodies, hipMemcpyDeviceToDevice,
+                         w->stream));
+  HIP_TRY(hipMemcpyAsync(w->d_ep_state.p, init.data(), sizeof(uint32_t) * init.size(), hipMemcpyHostToDevice,
+                         w->stream));
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  w->ep_on = true;
+  return JG_OK;
+}
+
+int32_t jg_query_episode(jg_world* w, int32_t tower, jg_episode* out) {
+  if (int32_t r = check_world(w)) return r;
+  if (!out) return fail(JG_EINVAL, "null output");
+  if (tower < 0 || tower >= (int)w->tower_bodies.size()) return fail(JG_EINVAL, "tower index out of range");
+  if (!w->ep_on) return fail(JG_ESTATE, "no episodes: call jg_begin_episodes first");
+  if (int32_t r = set_device(w)) return r;
+  if (int32_t r = download_state(w)) return r;   // the active flags of withdrawn blocks
+  uint32_t st[jg::kEpisodeWords];
+  HIP_TRY(hipMemcpy(st, w->d_ep_state.p + (size_t)w->tower_slot[tower] * jg::kEpisodeWords, sizeof(st),
+                    hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  auto f = [&](int k) { float v; std::memcpy(&v, &st[k], sizeof(v)); return v; };
+  out->collapsed = (st[jg::kEpFlags] & jg::kEpCollapsed) ? 1 : 0;
+  out->done = (st[jg::kEpFlags] & jg::kEpDone) ? 1 : 0;
+  out->collapse_step = (int32_t)st[jg::kEpCollapseStep];
+  out->rest_step = (int32_t)st[jg::kEpRestStep];
+  out->support_vertices = (int32_t)st[jg::kEpSupport];
+  out->ek = f(jg::kEpEk);
+  out->dx_max = f(jg::kEpDx);
+  out->theta_max = f(jg::kEpTheta);
+  out->margin = f(jg::kEpMargin);
+  out->imbalance = f(jg::kEpImbalance);
+  out->com[0] = f(jg::kEpComX);
+  out->com[1] = f(jg::kEpComY);
+  // the moves started by the collapse step (or by the last step taken)
+  const int64_t last = out->collapsed ? (int64_t)out->collapse_step : w->step - 1;
+  for (const PushRow& pr : w->pushes) {
+    if (pr.move == JG_MOVE_NONE || w->body_tower[pr.body] != tower || (int64_t)pr.start > last) continue;
+    ++out->rounds;
+    if (pr.move == JG_MOVE_SIDE_X) ++out->torque_moves;
+    if (!w->active[pr.body]) ++out->removed;
+  }
+  return report_device_errors(w);
+}
+
+int32_t jg_body_slots(jg_world* w, int32_t first_body, int32_t n, int32_t* slots) {
+  if (int32_t r = check_world(w)) return r;
+  if (!slots || first_body < 0 || n < 0 || first_body + n > (int)w->mass.size())
+    return fail(JG_EINVAL, "bad body range or null output");
+  if (w->layout_dirty) return fail(JG_ESTATE, "the layout changed since the last jg_commit");
+  for (int i = 0; i < n; ++i) slots[i] = w->int_of_body[first_body + i];
   return JG_OK;
 }
 

@@ -23,9 +23,10 @@ JG_ERR_CANDIDATES, JG_ERR_MANIFOLDS, JG_ERR_COLOURS, JG_ERR_NAN = 1, 2, 4, 8
 ERR_CANDIDATES, ERR_MANIFOLDS, ERR_COLOURS, ERR_NAN = 1, 2, 4, 8
 
 EXPORTS = ["jg_default_params", "jg_create_world", "jg_destroy_world", "jg_add_boxes", "jg_set_friction",
-           "jg_set_push", "jg_set_active", "jg_step_batch", "jg_query_state", "jg_set_state", "jg_query_active",
+           "jg_set_push", "jg_set_active", "jg_commit", "jg_step_batch", "jg_query_state", "jg_set_state", "jg_query_active",
            "jg_query_contacts", "jg_query_stats", "jg_query_phase_cycles", "jg_query_features", "jg_set_mlp",
-           "jg_world_size", "jg_sync",
+           "jg_world_size", "jg_sync", "jg_device_views", "jg_body_slots", "jg_begin_episodes",
+           "jg_query_episode",
            "jg_last_error", "jg_mlp_packed_bytes", "jg_mlp_pack", "jg_mlp_forward", "jg_mlp_grad_workspace_bytes",
            "jg_mlp_grad", "jg_mlp_adamw"]
 MLP_PARAMS, MLP_TRAINABLE, MLP_FEATURES, FEAT_RECORD = 20147, 20099, 24, 30
@@ -39,7 +40,9 @@ class jg_params(C.Structure):
                 ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("pack_bodies", C.c_int32), ("manifolds_per_body", C.c_float),
                 ("mlp_iters", C.c_int32), ("fallback_tau", C.c_double), ("record_features", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("collapse_fd", C.c_double), ("collapse_ek", C.c_double),
+                ("collapse_theta", C.c_double), ("rest_ek", C.c_double), ("support_eps", C.c_double),
+                ("rest_steps", C.c_int32)]
 
 
 class jg_contact(C.Structure):
@@ -54,6 +57,16 @@ class jg_stats(C.Structure):
                 ("contact_iters", C.c_int64), ("colours", C.c_int32), ("error_word", C.c_uint32),
                 ("residual_rms", C.c_double), ("residual_max", C.c_double), ("fallbacks", C.c_int64)]
 
+
+class jg_episode(C.Structure):
+    _fields_ = [("collapsed", C.c_int32), ("done", C.c_int32), ("collapse_step", C.c_int32),
+                ("rest_step", C.c_int32), ("rounds", C.c_int32), ("torque_moves", C.c_int32),
+                ("removed", C.c_int32), ("support_vertices", C.c_int32), ("ek", C.c_float), ("dx_max", C.c_float),
+                ("theta_max", C.c_float), ("margin", C.c_float), ("imbalance", C.c_float),
+                ("com", C.c_float * 2), ("_pad", C.c_float)]
+
+
+JG_MOVE_NONE, JG_MOVE_CENTER_X, JG_MOVE_SIDE_Y, JG_MOVE_SIDE_X = -1, 0, 1, 2
 
 CONTACT_DTYPE = np.dtype([("tower", np.int32), ("body_a", np.int32), ("body_b", np.int32), ("slot", np.int32),
                           ("colour", np.int32), ("order", np.int32), ("point", np.float32, 3),
@@ -84,8 +97,9 @@ def load_library(path: str = LIB_PATH):
     L.jg_add_boxes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
                                C.POINTER(C.c_int32)]
     L.jg_set_friction.argtypes = [C.c_void_p, C.c_int32, C.c_double]
-    L.jg_set_push.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, C.c_int32, C.c_double]
+    L.jg_set_push.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, C.c_int32, C.c_double, C.c_int32]
     L.jg_set_active.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    L.jg_commit.argtypes = [C.c_void_p]
     L.jg_step_batch.argtypes = [C.c_void_p, C.c_int32]
     L.jg_query_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
     L.jg_set_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
@@ -97,6 +111,10 @@ def load_library(path: str = LIB_PATH):
     L.jg_set_mlp.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
     L.jg_world_size.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.jg_sync.argtypes = [C.c_void_p]
+    L.jg_device_views.argtypes = [C.c_void_p] + [C.POINTER(C.c_void_p)] * 4 + [C.POINTER(C.c_int32)]
+    L.jg_body_slots.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.jg_begin_episodes.argtypes = [C.c_void_p]
+    L.jg_query_episode.argtypes = [C.c_void_p, C.c_int32, C.POINTER(jg_episode)]
     L.jg_last_error.argtypes = []
     L.jg_last_error.restype = C.c_char_p
     vp, sz = C.c_void_p, C.c_size_t
@@ -114,14 +132,18 @@ def load_library(path: str = LIB_PATH):
 
 
 class JengaError(RuntimeError):
-    def __init__(self, code, msg):
+    """A failed call.  For JG_ECAPACITY / JG_ENAN from a syncing call (device error bits raised
+    by earlier launches) the call did its work: ``result`` holds what it returned."""
+
+    def __init__(self, code, msg, result=None):
         super().__init__(f"jenga error {code}: {msg}")
         self.code = code
+        self.result = result
 
 
-def _check(code):
+def _check(code, result=None):
     if code != JG_OK:
-        raise JengaError(code, load_library().jg_last_error().decode())
+        raise JengaError(code, load_library().jg_last_error().decode(), result)
 
 
 def _ptr(a):
@@ -168,13 +190,18 @@ def jg_set_friction(h, tower, mu):
     _check(load_library().jg_set_friction(h, int(tower), float(mu)))
 
 
-def jg_set_push(h, body, force, start_step, n_steps, withdraw=0.0):
+def jg_set_push(h, body, force, start_step, n_steps, withdraw=0.0, move=JG_MOVE_NONE):
     f = _arr(force, (3,))
-    _check(load_library().jg_set_push(h, int(body), _ptr(f), int(start_step), int(n_steps), float(withdraw)))
+    _check(load_library().jg_set_push(h, int(body), _ptr(f), int(start_step), int(n_steps), float(withdraw),
+                                      int(move)))
 
 
 def jg_set_active(h, body, active):
     _check(load_library().jg_set_active(h, int(body), int(bool(active))))
+
+
+def jg_commit(h):
+    _check(load_library().jg_commit(h))
 
 
 def jg_step_batch(h, n_steps):
@@ -183,7 +210,8 @@ def jg_step_batch(h, n_steps):
 
 def jg_query_state(h, first, n):
     pos = np.zeros((n, 3)); quat = np.zeros((n, 4)); v = np.zeros((n, 3)); w = np.zeros((n, 3))
-    _check(load_library().jg_query_state(h, int(first), int(n), _ptr(pos), _ptr(quat), _ptr(v), _ptr(w)))
+    _check(load_library().jg_query_state(h, int(first), int(n), _ptr(pos), _ptr(quat), _ptr(v), _ptr(w)),
+           (pos, quat, v, w))
     return pos, quat, v, w
 
 
@@ -200,7 +228,7 @@ def jg_set_state(h, first, pos=None, quat=None, linvel=None, angvel=None):
 
 def jg_query_active(h, first, n):
     out = np.zeros(n, np.uint8)
-    _check(load_library().jg_query_active(h, int(first), int(n), out.ctypes.data_as(C.POINTER(C.c_uint8))))
+    _check(load_library().jg_query_active(h, int(first), int(n), out.ctypes.data_as(C.POINTER(C.c_uint8))), out)
     return out
 
 
@@ -208,33 +236,47 @@ def jg_query_contacts(h, tower, capacity=None) -> np.ndarray:
     L = load_library()
     n = C.c_int32(0)
     if capacity is None:
-        _check(L.jg_query_contacts(h, int(tower), None, 0, C.byref(n)))
+        rc = L.jg_query_contacts(h, int(tower), None, 0, C.byref(n))
+        if rc not in (JG_OK, JG_ECAPACITY, JG_ENAN):
+            _check(rc)
         capacity = n.value
+        pending = rc
+    else:
+        pending = JG_OK
     out = np.zeros(max(1, capacity), CONTACT_DTYPE)
-    _check(L.jg_query_contacts(h, int(tower), out.ctypes.data_as(C.c_void_p), int(capacity), C.byref(n)))
-    return out[:min(n.value, capacity)]
+    rc = L.jg_query_contacts(h, int(tower), out.ctypes.data_as(C.c_void_p), int(capacity), C.byref(n))
+    res = out[:min(n.value, capacity)]
+    # the size query may have found the device error bits: report them with the records
+    _check(rc if rc != JG_OK else pending, res)
+    return res
 
 
 def jg_query_stats(h, tower=-1) -> jg_stats:
     s = jg_stats()
-    _check(load_library().jg_query_stats(h, int(tower), C.byref(s)))
+    _check(load_library().jg_query_stats(h, int(tower), C.byref(s)), s)
     return s
 
 
 def jg_query_phase_cycles(h) -> dict:
     out = (C.c_uint64 * len(PHASES))()
-    _check(load_library().jg_query_phase_cycles(h, out, len(PHASES)))
-    return dict(zip(PHASES, [int(v) for v in out]))
+    rc = load_library().jg_query_phase_cycles(h, out, len(PHASES))
+    res = dict(zip(PHASES, [int(v) for v in out]))
+    _check(rc, res)
+    return res
 
 
 def jg_query_features(h, tower=-1) -> np.ndarray:
     """Feature records (n x 30: 24 features, k[3], impulses[3]) of the last step, in contact order."""
     L = load_library()
     n = C.c_int32(0)
-    _check(L.jg_query_features(h, int(tower), None, 0, C.byref(n)))
+    pending = L.jg_query_features(h, int(tower), None, 0, C.byref(n))
+    if pending not in (JG_OK, JG_ECAPACITY, JG_ENAN):
+        _check(pending)
     out = np.zeros((max(1, n.value), FEAT_RECORD), np.float32)
-    _check(L.jg_query_features(h, int(tower), out.ctypes.data_as(C.POINTER(C.c_float)), n.value, C.byref(n)))
-    return out[:n.value]
+    rc = L.jg_query_features(h, int(tower), out.ctypes.data_as(C.POINTER(C.c_float)), n.value, C.byref(n))
+    res = out[:n.value]
+    _check(rc if rc != JG_OK else pending, res)
+    return res
 
 
 def jg_set_mlp(h, params):
@@ -250,6 +292,30 @@ def jg_world_size(h):
 
 def jg_sync(h):
     _check(load_library().jg_sync(h))
+
+
+def jg_device_views(h):
+    """Device pointers (ints) of x, q, v, angvel and the array stride (see include/jenga.h)."""
+    ptrs = [C.c_void_p() for _ in range(4)]
+    stride = C.c_int32(0)
+    _check(load_library().jg_device_views(h, *[C.byref(p) for p in ptrs], C.byref(stride)))
+    return [p.value for p in ptrs], stride.value
+
+
+def jg_begin_episodes(h):
+    _check(load_library().jg_begin_episodes(h))
+
+
+def jg_query_episode(h, tower) -> jg_episode:
+    e = jg_episode()
+    _check(load_library().jg_query_episode(h, int(tower), C.byref(e)), e)
+    return e
+
+
+def jg_body_slots(h, first, n) -> np.ndarray:
+    out = np.zeros(n, np.int32)
+    _check(load_library().jg_body_slots(h, int(first), int(n), out.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out
 
 
 def jg_last_error() -> str:
@@ -396,14 +462,47 @@ class World:
         act = np.asarray(scene["active"])
         for i in np.nonzero(act == 0)[0]:
             jg_set_active(self.h, int(i), 0)
+        moves = scene.get("push_move")
         for i in range(len(scene["push_body"])):
             jg_set_push(self.h, int(scene["push_body"][i]), scene["push_force"][i], int(scene["push_start"][i]),
-                        int(scene["push_steps"][i]), float(scene["push_withdraw"][i]))
+                        int(scene["push_steps"][i]), float(scene["push_withdraw"][i]),
+                        JG_MOVE_NONE if moves is None else int(moves[i]))
         if mlp is not None:
             jg_set_mlp(self.h, mlp)
 
+    def commit(self):
+        jg_commit(self.h)
+
     def step(self, n_steps: int = 1):
+        """Commit pending host-side changes, then queue n_steps steps."""
+        jg_commit(self.h)
         jg_step_batch(self.h, n_steps)
+
+    def device_views(self):
+        """The device state as torch tensors (zero copy): x (3, stride), q (4, stride), v, w
+        (3, stride), in internal body order, and the internal slot of every body."""
+        import torch
+
+        jg_commit(self.h)
+        (px, pq, pv, pw), stride = jg_device_views(self.h)
+        dev = torch.device("cuda", int(self.params.device))
+
+        class _View:
+            def __init__(self, ptr, rows):
+                self.__cuda_array_interface__ = {"shape": (rows, stride), "typestr": "<f4", "data": (ptr, False),
+                                                  "version": 2, "strides": None}
+
+        views = {k: torch.as_tensor(_View(p, r), device=dev)
+                 for k, p, r in (("x", px, 3), ("q", pq, 4), ("v", pv, 3), ("w", pw, 3))}
+        return views, jg_body_slots(self.h, 0, self.n_bodies)
+
+    def begin_episodes(self):
+        """Commit pending changes and start an episode in every tower (jg_begin_episodes)."""
+        jg_commit(self.h)
+        jg_begin_episodes(self.h)
+
+    def episode(self, tower: int) -> jg_episode:
+        return jg_query_episode(self.h, tower)
 
     def state(self):
         return jg_query_state(self.h, 0, self.n_bodies)

@@ -26,6 +26,8 @@ A scene is a dict of numpy arrays:
   push_start (K,)     int32   first step the force acts
   push_steps (K,)     int32   number of steps it acts
   push_withdraw (K,)  f64     displacement along the force that deactivates the body (0 = never)
+  push_move  (K,)     int32   the move a push is (Tab. ziglar): MOVE_CENTER_X, MOVE_SIDE_Y, MOVE_SIDE_X,
+                              or -1 when the push is not a block removal
   params     dict     dt, iters, n_sub, restitution, beta, slop, margin, gravity
   n_steps    int      steps the configuration runs
 """
@@ -47,6 +49,10 @@ PAPER_BLOCK_MASS = 0.0196
 
 G = 9.81
 MU_LEVELS = (0.25, 0.40, 0.60)
+# the move types of Tab. ziglar (which block, which axis), with Ziglar's force factor k
+MOVE_CENTER_X, MOVE_SIDE_Y, MOVE_SIDE_X = 0, 1, 2
+MOVE_NAMES = ("center_xaxis", "side_yaxis", "side_xaxis")
+MOVE_K = (3, 3, 4)
 LAYER_GAP = 1e-3        # in-layer gap between neighbouring blocks
 BED_OVERLAP = 1e-4      # initial vertical overlap (keeps resting contacts active)
 JITTER = 5e-4           # horizontal placement jitter (uniform +-)
@@ -202,9 +208,9 @@ class SceneBuilder:
         self.n_bodies += n
         return first
 
-    def add_push(self, body, force, start, steps, withdraw=0.0):
+    def add_push(self, body, force, start, steps, withdraw=0.0, move=-1):
         self.pushes.append((int(body), np.asarray(force, np.float64).reshape(3), int(start), int(steps),
-                            float(withdraw)))
+                            float(withdraw), int(move)))
 
     def build(self):
         T = len(self.towers)
@@ -223,6 +229,7 @@ class SceneBuilder:
             push_start=np.array([p[2] for p in self.pushes], np.int32).reshape(K),
             push_steps=np.array([p[3] for p in self.pushes], np.int32).reshape(K),
             push_withdraw=np.array([p[4] for p in self.pushes], np.float64).reshape(K),
+            push_move=np.array([p[5] for p in self.pushes], np.int32).reshape(K),
             params=dict(self.params), n_steps=int(self.n_steps))
         return sc
 
@@ -249,7 +256,7 @@ def subset(scene, towers) -> dict:
         b = int(scene["push_body"][i])
         if b in remap:
             sb.add_push(remap[b], scene["push_force"][i], scene["push_start"][i], scene["push_steps"][i],
-                        scene["push_withdraw"][i])
+                        scene["push_withdraw"][i], int(scene["push_move"][i]) if "push_move" in scene else -1)
     return sb.build()
 
 
@@ -286,13 +293,16 @@ def _tower_push_schedule(rng, levels, mu, first_body, sb, n_removals):
         along_x = (l % 2 == 0)
         long_axis = np.array([1.0, 0, 0]) if along_x else np.array([0, 1.0, 0])
         short_axis = np.array([0, 1.0, 0]) if along_x else np.array([1.0, 0, 0])
+        # the centre block leaves along its length ("center_xaxis"); a side block along its length
+        # ("side_yaxis") or outwards across it ("side_xaxis", the torque move)
         if s == 1 or rng.random() < 0.5:
-            k, direction, extent = 3, long_axis * (1 if rng.random() < 0.5 else -1), 2 * BLOCK_HALF[0]
+            move, direction, extent = (MOVE_CENTER_X if s == 1 else MOVE_SIDE_Y), \
+                long_axis * (1 if rng.random() < 0.5 else -1), 2 * BLOCK_HALF[0]
         else:
-            k, direction, extent = 4, short_axis * (1 if s == 2 else -1), 2 * BLOCK_HALF[1]
+            move, direction, extent = MOVE_SIDE_X, short_axis * (1 if s == 2 else -1), 2 * BLOCK_HALF[1]
         scale = rng.uniform(0.9, 1.3)
-        f = scale * k * mu * BLOCK_MASS * G
-        sb.add_push(first_body + 3 * l + s, f * direction, 60 + 240 * r, 180, extent)
+        f = scale * MOVE_K[move] * mu * BLOCK_MASS * G
+        sb.add_push(first_body + 3 * l + s, f * direction, 60 + 240 * r, 180, extent, move)
 
 
 def cfg2(seed: int = 0, n_per_mu: int = 150, n_steps: int = 2000):

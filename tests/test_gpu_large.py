@@ -190,6 +190,10 @@ def test_candidate_overflow_is_flagged(J):
     sc = sb.build()
     gw = J.World(sc)
     gw.step(1)
+    # the next syncing call reports the bit once (JG_ECAPACITY) after doing its work
+    with pytest.raises(J.JengaError) as ei:
+        gw.stats()
+    assert ei.value.code == J.JG_ECAPACITY and ei.value.result.error_word & J.JG_ERR_CANDIDATES
     assert gw.stats().error_word & J.JG_ERR_CANDIDATES
     # the blocks far from the slab are unaffected: each rests on the ground with its four points
     c = gw.contacts(0)

@@ -100,6 +100,16 @@ def test_tilted_batch_one_step_parity(J, oracle):
     _one_step_compare(J, oracle, sc, states, label="tilted")
 
 
+def test_substeps_one_step_parity(J, oracle):
+    """n_sub = 3 substeps of dt / 3 per step and 14 iterations (the paper's own settings): every
+    substep runs the whole pipeline on both sides."""
+    sc = dict(W.tilted_towers(35, 12, levels_range=(8, 24)))
+    sc["params"] = dict(sc["params"], n_sub=3, iters=14)
+    states = _trajectory_states(oracle, sc, [0, 40, 100])
+    reps = _one_step_compare(J, oracle, sc, states, label="n_sub=3")
+    assert all(r["pairs"] > 20 for _, r in reps)
+
+
 def test_small_towers_many_per_pack(J, oracle):
     """Short towers (8-12 levels): several towers share one on-chip pack (a small batch gets one
     tower per pack by default, so the pack size is set)."""
@@ -189,6 +199,7 @@ def test_edge_cases(J, oracle):
     # a world with no towers
     p = J.jg_default_params()
     h = J.jg_create_world(p, 4, 16)
+    J.jg_commit(h)
     J.jg_step_batch(h, 3)
     assert J.jg_query_stats(h).steps == 3
     # one static box with a dynamic box resting on it; one inactive body
@@ -197,6 +208,11 @@ def test_edge_cases(J, oracle):
     J.jg_add_boxes(h, 0, [he, he, he], [0.0, m, m], [[0, 0, 0.2], [0, 0, 0.2 + 0.015 - 1e-4], [0.5, 0, 1.0]],
                    [[1, 0, 0, 0]] * 3)
     J.jg_set_active(h, 2, 0)
+    # host-side changes must be committed before a launch: jg_step_batch only launches
+    with pytest.raises(J.JengaError) as ei:
+        J.jg_step_batch(h, 60)
+    assert ei.value.code == J.JG_ESTATE
+    J.jg_commit(h)
     J.jg_step_batch(h, 60)
     x, q, v, w = J.jg_query_state(h, 0, 3)
     assert np.allclose(x[0], [0, 0, 0.2])              # static never moves
@@ -218,6 +234,7 @@ def test_edge_cases(J, oracle):
     h = J.jg_create_world(p, 2, 300)
     he6, m6, pos6, q6, _, _ = W.jenga_tower(100, None)
     J.jg_add_boxes(h, 0, he6, m6, pos6, q6)
+    J.jg_commit(h)
     J.jg_step_batch(h, 2)
     s = J.jg_query_stats(h)
     assert s.error_word == 0 and s.steps == 2 and s.points > 0
