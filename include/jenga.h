@@ -347,6 +347,15 @@ int32_t jg_mlp_grad_workspace_bytes(int32_t n, size_t* bytes);
 int32_t jg_mlp_grad(const float* params, const void* packed, const float* feats, const float* targets, int32_t n,
                     float* grad, float* loss, void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc): jg_mlp_grad with its workspace replaced by a
+ * static device array of the library (the partial sums of at most 256 workgroups, 20.6 MB per
+ * device, held until the process ends; every n >= 1 fits, a batch that would need more is
+ * JG_ECAPACITY).  Same arguments, kernels and results as jg_mlp_grad; allocates nothing.  Calls
+ * that overlap on one device share the array and race: order them on one stream. */
+int32_t jg_mlp_grad_noalloc(const float* params, const void* packed, const float* feats, const float* targets,
+                            int32_t n, float* grad, float* loss, void* stream);
+
 /* One AdamW step (decoupled weight decay, bias-corrected moments; step counts from 1) on the
  * trainable parameters: p *= 1 - lr wd; m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  m, v: JG_MLP_TRAINABLE floats. */

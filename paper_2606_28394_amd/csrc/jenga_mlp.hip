@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/jenga.h"
@@ -442,12 +443,21 @@ size_t grad_workspace_bytes(int n) { return (size_t)grad_blocks(n) * (kTrainable
 
 hipError_t launch_grad(const float* params, const void* packed, const float* feats, const float* targets, int n,
                        float* grad, float* loss, void* workspace, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)sizeof(TrainLds));
-    if (e != hipSuccess) return e;
-    attr = true;
+  // the kernel's dynamic-LDS limit, once per device (the current one)
+  constexpr int kMaxDevices = 64;
+  static std::mutex attr_mutex;
+  static bool attr[kMaxDevices] = {};
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  {
+    std::lock_guard<std::mutex> lock(attr_mutex);
+    if (!attr[dev]) {
+      hipError_t e = hipFuncSetAttribute((const void*)mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)sizeof(TrainLds));
+      if (e != hipSuccess) return e;
+      attr[dev] = true;
+    }
   }
   const int blocks = grad_blocks(n);
   float* part = (float*)workspace;
@@ -471,6 +481,13 @@ hipError_t launch_adamw(float* params, const float* grad, float* m, float* v, in
 }  // namespace mlp
 }  // namespace jg
 
+// Scratch of jg_mlp_grad_noalloc: the per-workgroup partial gradients of one call, at most
+// kGradScratchParts rows of JG_MLP_TRAINABLE + 1 floats (256 x 20100 x 4 B = 20.6 MB; the
+// gradient launch never uses more workgroups).  Each device the library runs on holds its own
+// copy until the process ends.  Every row a call reads is written earlier in the same call.
+constexpr int kGradScratchParts = 256;
+static __device__ __align__(256) float scratch[(size_t)kGradScratchParts * (JG_MLP_TRAINABLE + 1)];
+
 // ------------------------------------------------------------------------------------------------
 // C ABI
 // ------------------------------------------------------------------------------------------------
@@ -478,6 +495,28 @@ namespace {
 int32_t hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return JG_OK;
   return jg::set_error(JG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// The device address of `scratch` on the current device, looked up on the first call there
+// (the array's name is only a host-side stand-in; kernels get this address).
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kScratchDevices] = {};
+
+int32_t scratch_on_current_device(float** out) {
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return hip_status(e, "jg_mlp_grad_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices) return jg::set_error(JG_EDEVICE, "jg_mlp_grad_noalloc: device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))
+      return hip_status(e, "jg_mlp_grad_noalloc: hipGetSymbolAddress(scratch)");
+    if (!p) return jg::set_error(JG_EDEVICE, "jg_mlp_grad_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return JG_OK;
 }
 }  // namespace
 
@@ -516,6 +555,22 @@ int32_t jg_mlp_grad(const float* params, const void* packed, const float* feats,
     return jg::set_error(JG_EINVAL, "jg_mlp_grad: workspace smaller than jg_mlp_grad_workspace_bytes(n)");
   return hip_status(jg::mlp::launch_grad(params, packed, feats, targets, n, grad, loss, workspace, (hipStream_t)stream),
                     "jg_mlp_grad");
+}
+
+int32_t jg_mlp_grad_noalloc(const float* params, const void* packed, const float* feats, const float* targets,
+                            int32_t n, float* grad, float* loss, void* stream) {
+  if (n <= 0) return jg::set_error(JG_EINVAL, "jg_mlp_grad_noalloc: the batch must hold at least one row");
+  if (!params || !packed || !feats || !targets || !grad)
+    return jg::set_error(JG_EINVAL, "jg_mlp_grad_noalloc: null pointer");
+  if (jg::mlp::grad_workspace_bytes(n) > sizeof(scratch))
+    return jg::set_error(JG_ECAPACITY, "jg_mlp_grad_noalloc: the batch needs " +
+                                       std::to_string(jg::mlp::grad_workspace_bytes(n)) +
+                                       " bytes of partial sums, more than the static scratch holds (" +
+                                       std::to_string(sizeof(scratch)) + ")");
+  float* ws = nullptr;
+  if (int32_t r = scratch_on_current_device(&ws)) return r;
+  return hip_status(jg::mlp::launch_grad(params, packed, feats, targets, n, grad, loss, ws, (hipStream_t)stream),
+                    "jg_mlp_grad_noalloc");
 }
 
 int32_t jg_mlp_adamw(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,

@@ -28,7 +28,7 @@ EXPORTS = ["jg_default_params", "jg_create_world", "jg_destroy_world", "jg_add_b
            "jg_world_size", "jg_sync", "jg_device_views", "jg_body_slots", "jg_begin_episodes",
            "jg_query_episode",
            "jg_last_error", "jg_mlp_packed_bytes", "jg_mlp_pack", "jg_mlp_forward", "jg_mlp_grad_workspace_bytes",
-           "jg_mlp_grad", "jg_mlp_adamw"]
+           "jg_mlp_grad", "jg_mlp_grad_noalloc", "jg_mlp_adamw"]
 MLP_PARAMS, MLP_TRAINABLE, MLP_FEATURES, FEAT_RECORD = 20147, 20099, 24, 30
 PHASES = ["load/store", "forces+frames", "broad+narrow", "colouring", "manifolds", "pgs", "outputs",
           "residual", "integrate", "baumgarte"]
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     L.jg_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp]
     L.jg_mlp_grad_workspace_bytes.argtypes = [C.c_int32, C.POINTER(sz)]
     L.jg_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, sz, vp]
+    L.jg_mlp_grad_noalloc.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp]
     L.jg_mlp_adamw.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     for name in EXPORTS:
         if name not in ("jg_default_params", "jg_last_error"):
@@ -348,6 +349,11 @@ def jg_mlp_grad(params_ptr, packed_ptr, feats_ptr, targets_ptr, n, grad_ptr, los
                 stream=None):
     _check(load_library().jg_mlp_grad(params_ptr, packed_ptr, feats_ptr, targets_ptr, int(n), grad_ptr, loss_ptr,
                                       ws_ptr, int(ws_bytes), stream))
+
+
+def jg_mlp_grad_noalloc(params_ptr, packed_ptr, feats_ptr, targets_ptr, n, grad_ptr, loss_ptr, stream=None):
+    _check(load_library().jg_mlp_grad_noalloc(params_ptr, packed_ptr, feats_ptr, targets_ptr, int(n), grad_ptr,
+                                              loss_ptr, stream))
 
 
 def jg_mlp_adamw(params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, weight_decay, stream=None):
