@@ -175,11 +175,16 @@ def _run_timed(J, torch, scene, steps, **kw):
     return scene["n_towers"] * steps / (ms * 1e-3), ms, st
 
 
-def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(4, 8, 12), scene=None, workload=None):
+def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(1, 2, 4, 8, 12), scene=None, workload=None):
     """The learned warm start against plain PGS at 20 iterations at equal residual, on the
-    450-tower removal batch (or `scene`): R20 = median tower residual of plain-20; each k runs
-    with the fallback threshold tau = R20; the smallest k whose median residual is <= R20 is
-    the equal-residual point.  Rates include inference, residual passes and fallbacks."""
+    450-tower removal batch (or `scene`).  R20 = median tower residual of plain-20.  For each k:
+    - the learned start alone (no fallback, tau = inf): median residual and rate;
+    - the learned start with the fallback at tau = R20 (a tower above it is solved again
+      plainly): median residual, fallback share, sweeps per point, rate;
+    - the previous-step start (no network) at k sweeps: median residual and rate.
+    The learned equal-residual point is the smallest k whose learned-alone median is <= R20; the
+    fallback run counts only where its sweeps per point stay below plain-20's (else the residual
+    is mostly the plain solver's).  Rates include inference, residual passes and fallbacks."""
     import numpy as np
     from paper_2606_28394_amd import workloads as W
     net = np.load(weights)
@@ -187,41 +192,48 @@ def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(4, 8, 12), scene
         scene = W.cfg2(0, n_steps=steps)
         workload = (f"removal batch: {scene['n_towers']} towers, 12-24 levels, 1-8 push removals each, "
                     f"{steps} steps")
+    iters = int(scene["params"]["iters"])
     r20, m20, st20 = _run_residuals(J, scene, steps, chunk)
     v20, ms20, _ = _run_timed(J, torch, scene, steps)
     log(f"plain-20: median residual {r20:.3e} m/s, {v20:.4g} tower-steps/s")
-    rows = []
+    alone, fallback, prev_rows, ctx = [], [], [], {}
     for k in ks:
-        rk, mk, stk = _run_residuals(J, scene, steps, chunk, warm_start=2, mlp=net, mlp_iters=k, fallback_tau=r20)
-        vk, msk, stt = _run_timed(J, torch, scene, steps, warm_start=2, mlp=net, mlp_iters=k, fallback_tau=r20)
-        rows.append(dict(k=k, median_residual=rk, mean_residual=mk, value=vk, kernel_ms=msk,
-                         fallback_rate=stt.fallbacks / (scene["n_towers"] * steps),
-                         contact_iters_per_point=stt.contact_iters / max(1, stt.points)))
-        log(f"learned k={k}: median residual {rk:.3e}, {vk:.4g} tower-steps/s, fallbacks "
-            f"{100 * rows[-1]['fallback_rate']:.1f}%")
-    # zero-start solves at the same k (residual only), and the previous-step start (the impulses
-    # of the previous step, matched by key) with its rate: the warm start without the network
-    ctx, prev_rows = {}, []
-    for k in ks:
+        kw = dict(warm_start=2, mlp=net, mlp_iters=k)
+        rk, mk, _ = _run_residuals(J, scene, steps, chunk, fallback_tau=1e30, **kw)
+        vk, msk, _ = _run_timed(J, torch, scene, steps, fallback_tau=1e30, **kw)
+        alone.append(dict(k=k, median_residual=rk, mean_residual=mk, value=vk, kernel_ms=msk))
+        rf, mf, _ = _run_residuals(J, scene, steps, chunk, fallback_tau=r20, **kw)
+        vf, msf, stf = _run_timed(J, torch, scene, steps, fallback_tau=r20, **kw)
+        fallback.append(dict(k=k, median_residual=rf, mean_residual=mf, value=vf, kernel_ms=msf,
+                             fallback_rate=stf.fallbacks / (scene["n_towers"] * steps),
+                             contact_iters_per_point=stf.contact_iters / max(1, stf.points)))
         p = dict(scene["params"])
         p["iters"] = k
         ctx[f"zero_k{k}"] = _run_residuals(J, scene, steps, chunk, params=p)[0]
-        rk, mk, _ = _run_residuals(J, scene, steps, chunk, params=p, warm_start=1)
-        vk, msk, _ = _run_timed(J, torch, scene, steps, params=p, warm_start=1)
-        ctx[f"previous_k{k}"] = rk
-        prev_rows.append(dict(k=k, median_residual=rk, mean_residual=mk, value=vk, kernel_ms=msk))
-        log(f"previous-step k={k}: median residual {rk:.3e}, {vk:.4g} tower-steps/s")
-    ok = [r for r in rows if r["median_residual"] <= r20]
-    best = min(ok, key=lambda r: r["k"]) if ok else None
-    okp = [r for r in prev_rows if r["median_residual"] <= r20]
-    bestp = min(okp, key=lambda r: r["k"]) if okp else None
+        rp, mp, _ = _run_residuals(J, scene, steps, chunk, params=p, warm_start=1)
+        vp, msp, _ = _run_timed(J, torch, scene, steps, params=p, warm_start=1)
+        prev_rows.append(dict(k=k, median_residual=rp, mean_residual=mp, value=vp, kernel_ms=msp))
+        log(f"k={k}: learned alone {rk:.3e} ({vk:.4g}/s); with fallback {rf:.3e} "
+            f"({100 * fallback[-1]['fallback_rate']:.1f}% fall back, {vf:.4g}/s); previous step {rp:.3e} ({vp:.4g}/s)")
+
+    def first(rows, ok):
+        good = [r for r in rows if ok(r)]
+        return min(good, key=lambda r: r["k"]) if good else None
+
+    best = first(alone, lambda r: r["median_residual"] <= r20)
+    bestf = first(fallback, lambda r: r["median_residual"] <= r20 and r["contact_iters_per_point"] < iters)
+    bestp = first(prev_rows, lambda r: r["median_residual"] <= r20)
     return dict(workload=workload,
                 plain20=dict(median_residual=r20, mean_residual=m20, value=v20, kernel_ms=ms20),
-                learned=rows, median_residual_other_starts=ctx, previous_step=prev_rows,
+                learned_alone=alone, learned_with_fallback=fallback, previous_step=prev_rows,
+                median_residual_zero_start=ctx,
                 equal_residual_k=best["k"] if best else None,
                 learned_vs_plain20=(best["value"] / v20) if best else None,
+                fallback_equal_residual_k=bestf["k"] if bestf else None,
+                fallback_vs_plain20=(bestf["value"] / v20) if bestf else None,
                 previous_step_equal_residual_k=bestp["k"] if bestp else None,
-                previous_step_vs_plain20=(bestp["value"] / v20) if bestp else None)
+                previous_step_vs_plain20=(bestp["value"] / v20) if bestp else None,
+                learned_vs_previous_step=(best["value"] / bestp["value"]) if best and bestp else None)
 
 
 def large_island(J, torch, W, steps):
@@ -254,6 +266,42 @@ def large_island(J, torch, W, steps):
             "error_word": int(s1.error_word)}
 
 
+def grid_wide_islands(J, torch, W, steps=10):
+    """Islands stepped by the whole GPU (one cooperative launch, grid-wide phases): the
+    100,000-stone wall (100 courses x 1,000 stones; the default path for islands of 16,384 bodies or
+    more) and the 4,096-stone wall put on the same path (mega_bodies 1,024) to set beside its
+    one-workgroup figure.  Time per step from HIP events over one launch of `steps` steps after 2."""
+    out = {}
+    for key, scene in (("site_wall_100k", W.masonry_wall(100, 1000, seed=0, n_steps=steps + 2)),
+                       ("wall_4096", W.cfg5(0, n_steps=steps + 2))):
+        if key == "wall_4096":
+            scene = dict(scene, params=dict(scene["params"], mega_bodies=1024))
+        stream = torch.cuda.current_stream()
+        world = J.World(scene, stream=stream.cuda_stream)
+        world.step(2)
+        _synced(J, world.sync)
+        s0 = _synced(J, world.stats)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        world.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        s1 = _synced(J, world.stats)
+        n = int(scene["tower_ptr"][-1])
+        world.close()
+        log(f"  {key}: {ms / steps:.2f} ms per step")
+        out[key] = {"bodies": n, "steps": steps, "ms_per_step": ms / steps,
+                    "body_steps_per_s": n * steps / (ms * 1e-3),
+                    "manifolds_per_step": (s1.manifolds - s0.manifolds) / steps,
+                    "points_per_step": (s1.points - s0.points) / steps,
+                    "contact_iters_per_s": (s1.contact_iters - s0.contact_iters) / (ms * 1e-3),
+                    "colours": int(s1.colours), "error_word": int(s1.error_word)}
+    out["workload"] = ("one island per world, plain PGS-20, zero start, steps 3-" + str(2 + steps) +
+                       "; partitions of 1,024 stones for the colouring")
+    return out
+
+
 def single_tower_latency(J, torch, W):
     """The 18-level tower with one middle block removed: 240 steps in one launch, time per step
     (one wave on one CU: a latency figure, the GPU is nearly idle)."""
@@ -284,6 +332,81 @@ def literal_tilt_rate(J, torch, W, steps):
                         f"{steps} steps", "value": v, "kernel_ms": ms, "error_word": int(st.error_word)}
 
 
+def _mean_or_none(xs):
+    return float(sum(xs) / len(xs)) if xs else None
+
+
+def episodes_table(J, torch, W, steps=2000, warm_starts=(1, 0)):
+    """The 450-episode experiment (Sec. "Effect of the Friction Coefficient", Tab. results) on the
+    removal batch: every tower's episode (collapse criterion of Eq. (collapse), rest rule, moves of
+    Tab. ziglar) on the GPU over one launch of `steps` steps.  Per friction level: collapsed episodes,
+    mean rounds, Ziglar's thresholds F = k mu m g for the paper's block (19.6 g) and the benchmark
+    block, the share of torque moves; and the three validation claims (collapses per move type, the
+    trend with mu).  Run with the previous-step warm start and with the zero start."""
+    import numpy as np
+    scene = W.cfg2(0, n_steps=steps)
+    T = scene["n_towers"]
+    tower = W.tower_of(scene)
+    out = {"workload": f"removal batch: {T} towers (150 per mu), 12-24 levels, 1-8 push removals, {steps} steps"}
+    for ws in warm_starts:
+        stream = torch.cuda.current_stream()
+        world = J.World(scene, warm_start=ws, stream=stream.cuda_stream)
+        world.begin_episodes()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        world.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        eps = [_synced(J, world.episode, t) for t in range(T)]
+        world.close()
+        rows = []
+        by_move = {n: [0, 0] for n in W.MOVE_NAMES}      # collapses during a move of this type, moves
+        for mi, mu in enumerate(W.MU_LEVELS):
+            ts = [t for t in range(T) if abs(scene["mu"][t] - mu) < 1e-12]
+            col = [eps[t] for t in ts if eps[t].collapsed]
+            rounds = [eps[t].rounds for t in ts]
+            torque = sum(eps[t].torque_moves for t in ts)
+            rows.append({"mu": mu, "collapsed": len(col), "episodes": len(ts),
+                         "mean_rounds": float(np.mean(rounds)), "removed": int(sum(eps[t].removed for t in ts)),
+                         "F_min_mN": 3 * mu * W.PAPER_BLOCK_MASS * W.G * 1e3,
+                         "F_tau_mN": 4 * mu * W.PAPER_BLOCK_MASS * W.G * 1e3,
+                         "F_min_mN_benchmark_block": 3 * mu * W.BLOCK_MASS * W.G * 1e3,
+                         "torque_move_pct": 100.0 * torque / max(1, sum(rounds)),
+                         "mean_imbalance_mm": _mean_or_none([1e3 * eps[t].imbalance for t in ts
+                                                            if np.isfinite(eps[t].imbalance)]),
+                         "mean_steps_to_rest": _mean_or_none([e.rest_step - e.collapse_step for e in col
+                                                             if e.rest_step >= 0])})
+        moves_of = {}                                      # tower -> [(start, move)] of its moves
+        for i in range(len(scene["push_body"])):
+            mv = int(scene["push_move"][i])
+            if mv >= 0:
+                moves_of.setdefault(int(tower[int(scene["push_body"][i])]), []).append((int(scene["push_start"][i]), mv))
+        for t, mvs in moves_of.items():
+            e = eps[t]
+            last = e.collapse_step if e.collapsed else steps - 1
+            started = sorted(m for m in mvs if m[0] <= last)
+            for _, mv in started:
+                by_move[W.MOVE_NAMES[mv]][1] += 1
+            # the move during which the collapse came: the last one started by the collapse step
+            if e.collapsed and started:
+                by_move[W.MOVE_NAMES[started[-1][1]]][0] += 1
+        rates = {k: (v[0] / v[1] if v[1] else None) for k, v in by_move.items()}
+        col_rate = [r["collapsed"] / r["episodes"] for r in rows]
+        claims = {"side_yaxis_below_side_xaxis": None if None in (rates["side_yaxis"], rates["side_xaxis"])
+                  else rates["side_yaxis"] < rates["side_xaxis"],
+                  "center_safest": None if None in rates.values() else
+                  rates["center_xaxis"] <= min(rates["side_yaxis"], rates["side_xaxis"]),
+                  "collapse_rate_falls_with_mu": col_rate[0] >= col_rate[1] >= col_rate[2] and col_rate[0] > col_rate[2]}
+        key = "previous_step_start" if ws == 1 else "zero_start"
+        out[key] = {"kernel_ms": ms, "tower_steps_per_s": T * steps / (ms * 1e-3), "rows": rows,
+                    "collapse_rate_by_move": rates, "moves_by_type": {k: v[1] for k, v in by_move.items()},
+                    "ziglar_claims": claims}
+        log(f"  episodes ({key}): collapsed {[r['collapsed'] for r in rows]} of 150, mean rounds "
+            f"{[round(r['mean_rounds'], 2) for r in rows]}, {ms / steps:.3f} ms per step")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +423,8 @@ def main():
     ap.add_argument("--cpu-report", action="store_true",
                     help="also time the oracle single-threaded and on all host threads over samples of "
                          "every workload (a few minutes)")
+    ap.add_argument("--no-episodes", action="store_true",
+                    help="skip the 450-episode table (collapse criterion and labels on the removal batch)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-tower latency and standing-tower legs")
     ap.add_argument("--island-steps", type=int, default=100,
@@ -431,16 +556,21 @@ def main():
         log("single-tower latency and standing-tower legs ...")
         out["single_tower"] = single_tower_latency(J, torch, W)
         out["standing_towers"] = literal_tilt_rate(J, torch, W, args.steps)
+    if not args.no_episodes:
+        log("episode table (removal batch) ...")
+        out["episodes"] = episodes_table(J, torch, W)
     if args.island_steps > 0:
         log("large-island leg (64 x 64 masonry wall) ...")
         out["large_island"] = large_island(J, torch, W, args.island_steps)
+        log("grid-wide islands (100,000-stone wall; the 4,096-stone wall on the same path) ...")
+        out["grid_wide_islands"] = grid_wide_islands(J, torch, W)
     if not args.no_learned and os.path.exists(args.learned_weights):
         log("equal-residual leg (learned warm start vs plain-20) ...")
         out["equal_residual"] = equal_residual(J, torch, args.learned_weights)
         if args.island_steps > 0:
             log("equal-residual leg on the 64 x 64 masonry wall ...")
             out["equal_residual_wall"] = equal_residual(
-                J, torch, args.learned_weights, steps=300, ks=(4, 8), scene=W.cfg5(0, n_steps=300),
+                J, torch, args.learned_weights, steps=300, ks=(1, 2, 3, 4), scene=W.cfg5(0, n_steps=300),
                 workload="one masonry wall, 64 courses x 64 stones (4096 bodies), steps 1-300")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -61,7 +61,8 @@ typedef enum {
 } jg_status;
 
 /* Device error-word bits reported by jg_query_stats. */
-#define JG_ERR_CANDIDATES 1u   /* a body of an island in device memory had more than 16 broadphase candidates */
+#define JG_ERR_CANDIDATES 1u   /* a body of an island in device memory had more than 16 broadphase candidates,
+                                  or a tower stepped by the whole GPU exceeded its candidate capacity */
 #define JG_ERR_MANIFOLDS 2u    /* colliding pairs exceeded the pack capacity */
 #define JG_ERR_COLOURS 4u      /* a manifold needed more than 64 colours (dropped) */
 #define JG_ERR_NAN 8u          /* non-finite body state */
@@ -104,6 +105,33 @@ typedef struct {
                             ground support the tower [m]; 2e-3 */
   int32_t rest_steps;    /* steps after the collapse after which the tower is held even if not at
                             rest (Sec. "Full Floor Contact Simulation"); 400 */
+  /* solver variants (Sec. "Contact Solver --- Projected Gauss-Seidel (PGS)") */
+  int32_t friction_cone; /* 0: each tangent clipped to +-mu lambda_n (Eq. (coulomb_pgs)); 1: the two
+                            tangent rows of a point solved from the same velocities and their impulse
+                            pair projected onto the disc of radius mu lambda_n (the circular cone of the
+                            PGS figure); default 0 */
+  int32_t restitution_bias;  /* 0: Eq. (lambda_n) as printed, (1 + e) times the current normal velocity
+                            in every iteration; 1: the normal row drives the point's normal velocity to
+                            -e v_n-, v_n- its normal velocity before any impulse of the step, when the
+                            point approaches faster than 2 |g| dt (else to 0); default 0 */
+  int32_t manifold_mode; /* 0: the literal silhouettes of Sec. "Contact Manifold (Face Clipping)"
+                            (projected hulls of both boxes, one clipped by the other); 1: reference-face
+                            clipping (the incident face clipped by the reference face's side planes,
+                            points on or below the reference face, one point for an edge-edge axis);
+                            default 0 */
+  /* very large islands (Sec. "Discussion and Implications for Anastylosis": site-scale walls) */
+  int32_t mega_bodies;   /* a tower of at least this many bodies is stepped by the whole GPU: one
+                            cooperative launch whose phases span every CU, a uniform-grid broadphase
+                            with no per-body candidate cap, 32-bit body indices (no 65,534-body
+                            limit) and the partitioned colouring below; such towers take the zero
+                            initial impulses (warm_start 0), no episode criteria, no feature records
+                            and no graph replay; 0 = never; default 16384 */
+  int32_t colour_partition;  /* bodies per colouring partition of such a tower: its pairs are coloured
+                            greedily in four passes, each in canonical order: inside a partition (or
+                            with the ground), between partitions p and p + 1 for even p, then for odd
+                            p, then the rest; default 1024 */
+  float mega_cand_per_body;  /* broadphase candidate capacity of such a tower, per body (the list is cut
+                            at the first body whose candidates do not fit, JG_ERR_CANDIDATES); 16 */
 } jg_params;
 
 /* One contact point of the last solved step. */

@@ -98,8 +98,13 @@ static void box_corner(const double he[3], const double x[3], const double R[9],
 /* SAT (Sec. "Narrowphase: OBB SAT")                                                           */
 /* ------------------------------------------------------------------------------------------ */
 
+/* prefer_face (reference-face manifolds, reading of the usual box-box clipping): a colliding pair
+ * takes its normal and depth from the best face axis (first strict minimum over A0..B2) unless the
+ * best axis overall is a cross axis whose overlap is below 0.95 of the face axis's by more than
+ * 1e-6 m; a cross axis parallel to a face normal then never stands in for the face. */
 static void sat_R(const double heA[3], const double xA[3], const double RA[9],
-                  const double heB[3], const double xB[3], const double RB[9], or_sat_result* out) {
+                  const double heB[3], const double xB[3], const double RB[9], int prefer_face,
+                  or_sat_result* out) {
   double A[3][3], B[3][3], d[3];
   for (int i = 0; i < 3; ++i) { col3(RA, i, A[i]); col3(RB, i, B[i]); }
   for (int k = 0; k < 3; ++k) d[k] = xB[k] - xA[k];
@@ -131,16 +136,31 @@ static void sat_R(const double heA[3], const double xA[3], const double RA[9],
     if (best < 0 || delta[a] < delta[best]) best = a;   /* first strict minimum */
   }
   double dmin = delta[best];
+  const double dsep = dmin;   /* the separation test takes the smallest overlap of all axes */
+  int rivals = 15;            /* axes that compete with the chosen one */
   out->collide = dmin > 0.0;
+  if (prefer_face && best < 6) rivals = 6;
+  if (prefer_face && best >= 6 && dmin > 0.0) {
+    int f = 0;
+    for (int a = 1; a < 6; ++a)
+      if (delta[a] < delta[f]) f = a;
+    const double cut = 0.95 * delta[f] - 1e-6;
+    if (fabs(dmin - cut) < BAND) band |= OR_BAND_NORMAL;   /* the choice sits at its threshold */
+    if (!(dmin < cut)) {
+      best = f;
+      dmin = delta[f];
+      rivals = 6;
+    }
+  }
   out->axis = best;
   out->depth = dmin;
-  out->sigma = -dmin;
+  out->sigma = -dsep;
   double s = dot3(d, axes[best]) < 0.0 ? -1.0 : 1.0;
   for (int k = 0; k < 3; ++k) out->normal[k] = s * axes[best][k];
   if (fabs(out->sigma) < BAND) band |= OR_BAND_SEPARATION;
   /* second best axis that is not parallel to the chosen one (axes closer than ~4e-7 rad give
    * the same normal to single precision; anything further apart changes the contact frame) */
-  for (int a = 0; a < 15; ++a) {
+  for (int a = 0; a < rivals; ++a) {
     if (!tested[a] || a == best) continue;
     if (fabs(dot3(axes[a], axes[best])) > 1.0 - 1e-13) continue;
     if (delta[a] - dmin < BAND) band |= OR_BAND_NORMAL;
@@ -153,7 +173,16 @@ void or_sat(const double heA[3], const double xA[3], const double qA[4],
   double RA[9], RB[9];
   or_quat_to_rot(qA, RA);
   or_quat_to_rot(qB, RB);
-  sat_R(heA, xA, RA, heB, xB, RB, out);
+  sat_R(heA, xA, RA, heB, xB, RB, 0, out);
+}
+
+void or_sat_ex(const double heA[3], const double xA[3], const double qA[4],
+               const double heB[3], const double xB[3], const double qB[4], int32_t prefer_face,
+               or_sat_result* out) {
+  double RA[9], RB[9];
+  or_quat_to_rot(qA, RA);
+  or_quat_to_rot(qB, RB);
+  sat_R(heA, xA, RA, heB, xB, RB, prefer_face != 0, out);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -338,6 +367,181 @@ static int manifold_box_R(const double heA[3], const double xA[3], const double 
   return 1;
 }
 
+/* Reference-face clipping (the alternative to the literal silhouettes): for a face axis the face
+ * of the box that owns it is the reference face (outward normal u: +n for a face of A, -n for a
+ * face of B); the other box's face most opposed to u is the incident face.  The incident face's
+ * quad is clipped by the reference face's four side planes (Sutherland-Hodgman in 3-D); of the
+ * clipped vertices those on or below the reference face (separation s >= 0 along u) are kept, and
+ * each point sits halfway between its vertex and the reference face (v + s u / 2).  The up to four
+ * samples are the kept vertices extreme along the diagonals of (t1, t2), as for the silhouettes.
+ * An edge-edge axis gives one point: the midpoint of the closest points of the two boxes' edges
+ * that support the contact (extreme along +n on A, -n on B).  All points carry the pair's depth. */
+static int clip_plane3(const double (*in)[3], int n, const double pn[3], double off, double (*out)[3], int* band) {
+  int m = 0;
+  for (int i = 0; i < n; ++i) {
+    const double* a = in[(i + n - 1) % n];
+    const double* b = in[i];
+    const double da = dot3(pn, a) - off, db = dot3(pn, b) - off;   /* <= 0 inside */
+    if (fabs(db) < BAND) *band |= OR_BAND_CLIP;
+    const int ia = da <= 0.0, ib = db <= 0.0;
+    if (ib) {
+      if (!ia) {
+        const double t = da / (da - db);
+        for (int k = 0; k < 3; ++k) out[m][k] = a[k] + t * (b[k] - a[k]);
+        ++m;
+      }
+      memcpy(out[m++], b, sizeof(double) * 3);
+    } else if (ia) {
+      const double t = da / (da - db);
+      for (int k = 0; k < 3; ++k) out[m][k] = a[k] + t * (b[k] - a[k]);
+      ++m;
+    }
+  }
+  return m;
+}
+
+static int manifold_refface_R(const double heA[3], const double xA[3], const double RA[9],
+                              const double heB[3], const double xB[3], const double RB[9],
+                              const double n[3], double depth, int axis, or_manifold* m) {
+  double t1[3], t2[3];
+  tangent_basis(n, t1, t2);
+  memcpy(m->normal, n, sizeof(double) * 3);
+  memcpy(m->t1, t1, sizeof(double) * 3);
+  memcpy(m->t2, t2, sizeof(double) * 3);
+  m->depth = depth;
+  m->npts = 0;
+  double A[3][3], B[3][3];
+  for (int i = 0; i < 3; ++i) { col3(RA, i, A[i]); col3(RB, i, B[i]); }
+  if (axis >= 6) {
+    /* edge-edge: the support edges along +n (A) and -n (B) */
+    const int i = (axis - 6) / 3, j = (axis - 6) % 3;
+    double pa[3], pb[3];
+    for (int k = 0; k < 3; ++k) { pa[k] = xA[k]; pb[k] = xB[k]; }
+    for (int q = 0; q < 3; ++q) {
+      if (q != i) {
+        const double sg = dot3(n, A[q]) >= 0.0 ? 1.0 : -1.0;
+        for (int k = 0; k < 3; ++k) pa[k] += sg * heA[q] * A[q][k];
+      }
+      if (q != j) {
+        const double sg = dot3(n, B[q]) >= 0.0 ? -1.0 : 1.0;
+        for (int k = 0; k < 3; ++k) pb[k] += sg * heB[q] * B[q][k];
+      }
+    }
+    /* closest points of the segments pa + s A_i (|s| <= heA_i), pb + t B_j (|t| <= heB_j) */
+    double r[3];
+    for (int k = 0; k < 3; ++k) r[k] = pa[k] - pb[k];
+    const double a11 = 1.0, a22 = 1.0, a12 = dot3(A[i], B[j]);
+    const double b1 = -dot3(A[i], r), b2 = dot3(B[j], r);
+    const double det = a11 * a22 - a12 * a12;
+    double sa = det > 1e-12 ? (b1 * a22 + a12 * b2) / det : 0.0;
+    if (sa > heA[i]) sa = heA[i];
+    if (sa < -heA[i]) sa = -heA[i];
+    /* t minimising |pa + sa A_i - pb - t B_j| for this sa, clamped, then sa again for that t */
+    double tb = dot3(B[j], r) + a12 * sa;
+    if (tb > heB[j]) tb = heB[j];
+    if (tb < -heB[j]) tb = -heB[j];
+    sa = -dot3(A[i], r) + a12 * tb;
+    if (sa > heA[i]) sa = heA[i];
+    if (sa < -heA[i]) sa = -heA[i];
+    for (int k = 0; k < 3; ++k)
+      m->point[0][k] = 0.5 * ((pa[k] + sa * A[i][k]) + (pb[k] + tb * B[j][k]));
+    m->slot[0] = 0;
+    m->npts = 1;
+    return 1;
+  }
+  const int refA = axis < 3;
+  const double(*Rf)[3] = refA ? A : B;
+  const double(*In)[3] = refA ? B : A;
+  const double* heR = refA ? heA : heB;
+  const double* heI = refA ? heB : heA;
+  const double* xR = refA ? xA : xB;
+  const double* xI = refA ? xB : xA;
+  const int fi = refA ? axis : axis - 3;
+  double u[3];
+  for (int k = 0; k < 3; ++k) u[k] = refA ? n[k] : -n[k];
+  /* reference face: centre, its plane offset along u, side axes */
+  double cr[3];
+  const double su = dot3(u, Rf[fi]) >= 0.0 ? 1.0 : -1.0;
+  for (int k = 0; k < 3; ++k) cr[k] = xR[k] + su * heR[fi] * Rf[fi][k];
+  const int s1 = (fi + 1) % 3, s2 = (fi + 2) % 3;
+  /* incident face: most opposed to u */
+  int fk = 0;
+  double best = -1.0;
+  for (int k = 0; k < 3; ++k) {
+    const double d = fabs(dot3(u, In[k]));
+    if (d > best) { best = d; fk = k; }
+  }
+  for (int k = 0; k < 3; ++k)
+    if (k != fk && best - fabs(dot3(u, In[k])) < 1e-9) m->band |= OR_BAND_CLIP;
+  const double sf = dot3(u, In[fk]) >= 0.0 ? -1.0 : 1.0;   /* the face whose normal opposes u */
+  const int g1 = (fk + 1) % 3, g2 = (fk + 2) % 3;
+  double poly[16][3], tmp[16][3];
+  static const double cs[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+  for (int c = 0; c < 4; ++c)
+    for (int k = 0; k < 3; ++k)
+      poly[c][k] = xI[k] + sf * heI[fk] * In[fk][k] + cs[c][0] * heI[g1] * In[g1][k] + cs[c][1] * heI[g2] * In[g2][k];
+  int np = 4;
+  const int sides[4] = {s1, s1, s2, s2};
+  const double sgn[4] = {1.0, -1.0, 1.0, -1.0};
+  for (int e = 0; e < 4 && np > 0; ++e) {
+    double pn[3];
+    for (int k = 0; k < 3; ++k) pn[k] = sgn[e] * Rf[sides[e]][k];
+    const double off = dot3(pn, cr) + heR[sides[e]];
+    np = clip_plane3((const double(*)[3])poly, np, pn, off, tmp, &m->band);
+    memcpy(poly, tmp, sizeof(double) * 3 * (size_t)np);
+  }
+  /* the vertices on or below the reference face, lifted halfway to it */
+  double pts[16][3];
+  int nk = 0;
+  const double h = dot3(u, cr);
+  for (int i = 0; i < np; ++i) {
+    const double sep = h - dot3(u, poly[i]);
+    if (fabs(sep) < BAND) m->band |= OR_BAND_CLIP;
+    if (sep < 0.0) continue;
+    for (int k = 0; k < 3; ++k) pts[nk][k] = poly[i][k] + 0.5 * sep * u[k];
+    ++nk;
+  }
+  if (nk == 0) {
+    /* nothing below the reference face: the silhouettes' empty-clip point */
+    m->band |= OR_BAND_EMPTY;
+    return manifold_box_R(heA, xA, RA, heB, xB, RB, n, depth, m);
+  }
+  static const double diag[4][2] = {{1.0, 1.0}, {-1.0, 1.0}, {-1.0, -1.0}, {1.0, -1.0}};
+  int chosen[4], nchosen = 0;
+  for (int s = 0; s < 4; ++s) {
+    int bi = 0;
+    double bv = diag[s][0] * dot3(pts[0], t1) + diag[s][1] * dot3(pts[0], t2);
+    for (int i = 1; i < nk; ++i) {
+      const double val = diag[s][0] * dot3(pts[i], t1) + diag[s][1] * dot3(pts[i], t2);
+      if (val > bv) { bv = val; bi = i; }
+    }
+    for (int i = 0; i < nk; ++i) {
+      if (i == bi) continue;
+      const double val = diag[s][0] * dot3(pts[i], t1) + diag[s][1] * dot3(pts[i], t2);
+      if (bv - val < BAND) m->band |= OR_BAND_CLIP;
+    }
+    int dup = 0;
+    for (int c = 0; c < nchosen; ++c) dup |= (chosen[c] == bi);
+    if (dup) continue;
+    chosen[nchosen++] = bi;
+    const int j = m->npts++;
+    memcpy(m->point[j], pts[bi], sizeof(double) * 3);
+    m->slot[j] = s;
+  }
+  return 1;
+}
+
+int or_manifold_refface(const double heA[3], const double xA[3], const double qA[4],
+                        const double heB[3], const double xB[3], const double qB[4],
+                        const double normal[3], double depth, int axis, or_manifold* out) {
+  double RA[9], RB[9];
+  or_quat_to_rot(qA, RA);
+  or_quat_to_rot(qB, RB);
+  memset(out, 0, sizeof(*out));
+  out->b = 1;
+  return manifold_refface_R(heA, xA, RA, heB, xB, RB, normal, depth, axis, out);
+}
+
 int or_manifold_box(const double heA[3], const double xA[3], const double qA[4],
                     const double heB[3], const double xB[3], const double qB[4],
                     const double normal[3], double depth, or_manifold* out) {
@@ -495,8 +699,44 @@ static void prep_k(const body_view* bv, or_manifold* ms, int nm) {
   }
 }
 
+/* pre-solve restitution targets: -e v_n- for a point approaching faster than vth (v_n- < -vth, its
+ * normal velocity before any impulse of the step), else 0 (only with the bias option) */
+static void prep_bias(const body_view* bv, or_manifold* ms, int nm, double e, double vth) {
+  for (int c = 0; c < nm; ++c) {
+    or_manifold* m = &ms[c];
+    double invmA, invmB; const double *IA, *IB; double *vA, *wA, *vB, *wB;
+    contact_refs(bv, m, &invmA, &IA, &vA, &wA, &invmB, &IB, &vB, &wB);
+    for (int i = 0; i < m->npts; ++i) {
+      double rA[3], rB[3];
+      lever_arms(bv, m, i, rA, rB);
+      const double vn = rel_vel(vA, wA, vB, wB, rA, rB, m->normal);
+      m->vbias[i] = vn < -vth ? -e * vn : 0.0;
+    }
+  }
+}
+
+/* friction and restitution options of a solve */
+typedef struct {
+  double mu, e;
+  int cone;      /* 0: each tangent clipped to +-mu lambda_n (Eq. (coulomb_pgs)); 1: the tangent pair
+                    projected onto the disc of radius mu lambda_n (the cone of the PGS figure) */
+  int bias;      /* 0: (1 + e) times the current normal velocity every iteration (Eq. (lambda_n) as
+                    printed); 1: a pre-solve target -e min(0, v_n-) per point (m->vbias) */
+} solve_opts;
+
+/* the tangent pair (l1, l2) projected onto the disc of radius b */
+static void disc_project(double* l1, double* l2, double b) {
+  const double s = sqrt(*l1 * *l1 + *l2 * *l2);
+  if (s > b) {
+    const double f = s > 0.0 ? b / s : 0.0;
+    *l1 *= f;
+    *l2 *= f;
+  }
+}
+
 /* one Gauss-Seidel pass over the manifolds in array order */
-static void pgs_sweep(const body_view* bv, or_manifold* ms, int nm, double mu, double e) {
+static void pgs_sweep(const body_view* bv, or_manifold* ms, int nm, const solve_opts* o) {
+  const double mu = o->mu, e = o->e;
   for (int c = 0; c < nm; ++c) {
     or_manifold* m = &ms[c];
     double invmA, invmB; const double *IA, *IB; double *vA, *wA, *vB, *wB;
@@ -506,17 +746,33 @@ static void pgs_sweep(const body_view* bv, or_manifold* ms, int nm, double mu, d
       lever_arms(bv, m, i, rA, rB);
       /* Eq. (lambda_n): normal impulse with restitution, accumulated and clamped at 0 */
       double vn = rel_vel(vA, wA, vB, wB, rA, rB, m->normal);
-      double dl = -(1.0 + e) * vn / m->k[i][0];
+      double dl = o->bias ? (m->vbias[i] - vn) / m->k[i][0] : -(1.0 + e) * vn / m->k[i][0];
       double ln = m->lam[i][0] + dl;
       if (ln < 0.0) ln = 0.0;
       apply_impulse(invmA, IA, vA, wA, invmB, IB, vB, wB, rA, rB, m->normal, ln - m->lam[i][0]);
       m->lam[i][0] = ln;
+      double bound = mu * m->lam[i][0];
+      if (o->cone) {
+        /* both tangent rows from the same velocities, with one inverse effective mass (the
+         * larger of the two) so that the update points against the slip velocity; the pair is
+         * then projected onto the disc */
+        const double kt = m->k[i][1] > m->k[i][2] ? m->k[i][1] : m->k[i][2];
+        double v1 = rel_vel(vA, wA, vB, wB, rA, rB, m->t1);
+        double v2 = rel_vel(vA, wA, vB, wB, rA, rB, m->t2);
+        double l1 = m->lam[i][1] - v1 / kt;
+        double l2 = m->lam[i][2] - v2 / kt;
+        disc_project(&l1, &l2, bound);
+        apply_impulse(invmA, IA, vA, wA, invmB, IB, vB, wB, rA, rB, m->t1, l1 - m->lam[i][1]);
+        apply_impulse(invmA, IA, vA, wA, invmB, IB, vB, wB, rA, rB, m->t2, l2 - m->lam[i][2]);
+        m->lam[i][1] = l1;
+        m->lam[i][2] = l2;
+        continue;
+      }
       /* Eq. (coulomb_pgs): each tangent clipped to +-mu lambda_n */
       for (int t = 1; t <= 2; ++t) {
         const double* d = (t == 1) ? m->t1 : m->t2;
         double vt = rel_vel(vA, wA, vB, wB, rA, rB, d);
         double lt = m->lam[i][t] - vt / m->k[i][t];
-        double bound = mu * m->lam[i][0];
         if (lt < -bound) lt = -bound;
         if (lt > bound) lt = bound;
         apply_impulse(invmA, IA, vA, wA, invmB, IB, vB, wB, rA, rB, d, lt - m->lam[i][t]);
@@ -526,8 +782,10 @@ static void pgs_sweep(const body_view* bv, or_manifold* ms, int nm, double mu, d
   }
 }
 
-/* natural-map residual of every row at the current velocities */
-static void residual(const body_view* bv, const or_manifold* ms, int nm, double mu, double res[2]) {
+/* natural-map residual of every row at the current velocities: normal min(k lambda, w - target);
+ * tangents k (lambda - P(lambda - w / k)) with P the solver's clip (box) or disc projection */
+static void residual(const body_view* bv, const or_manifold* ms, int nm, const solve_opts* o, double res[2]) {
+  const double mu = o->mu;
   double sum = 0.0, mx = 0.0;
   long rows = 0;
   for (int c = 0; c < nm; ++c) {
@@ -537,18 +795,26 @@ static void residual(const body_view* bv, const or_manifold* ms, int nm, double 
     for (int i = 0; i < m->npts; ++i) {
       double rA[3], rB[3];
       lever_arms(bv, m, i, rA, rB);
-      double wn = rel_vel(vA, wA, vB, wB, rA, rB, m->normal);
+      double wn = rel_vel(vA, wA, vB, wB, rA, rB, m->normal) - (o->bias ? m->vbias[i] : 0.0);
       double kl = m->k[i][0] * m->lam[i][0];
       double r = kl < wn ? kl : wn;
       sum += r * r; if (fabs(r) > mx) mx = fabs(r);
+      double bound = mu * m->lam[i][0];
+      double cl[3], kr[3];
+      const double kt = m->k[i][1] > m->k[i][2] ? m->k[i][1] : m->k[i][2];
       for (int t = 1; t <= 2; ++t) {
         const double* d = (t == 1) ? m->t1 : m->t2;
         double wt = rel_vel(vA, wA, vB, wB, rA, rB, d);
-        double bound = mu * m->lam[i][0];
-        double cl = m->lam[i][t] - wt / m->k[i][t];
-        if (cl < -bound) cl = -bound;
-        if (cl > bound) cl = bound;
-        double rt = m->k[i][t] * (m->lam[i][t] - cl);
+        kr[t] = o->cone ? kt : m->k[i][t];
+        cl[t] = m->lam[i][t] - wt / kr[t];
+        if (!o->cone) {
+          if (cl[t] < -bound) cl[t] = -bound;
+          if (cl[t] > bound) cl[t] = bound;
+        }
+      }
+      if (o->cone) disc_project(&cl[1], &cl[2], bound);
+      for (int t = 1; t <= 2; ++t) {
+        double rt = kr[t] * (m->lam[i][t] - cl[t]);
         sum += rt * rt; if (fabs(rt) > mx) mx = fabs(rt);
       }
       rows += 3;
@@ -560,12 +826,20 @@ static void residual(const body_view* bv, const or_manifold* ms, int nm, double 
 
 void or_pgs(int nb, const double* invm, const double* Iinv, const double* x, double* v, double* w,
             int nm, or_manifold* m, double mu, double restitution, int iters, double res[2]) {
+  or_pgs_ex(nb, invm, Iinv, x, v, w, nm, m, mu, restitution, 0, 0, iters, res);
+}
+
+void or_pgs_ex(int nb, const double* invm, const double* Iinv, const double* x, double* v, double* w,
+               int nm, or_manifold* m, double mu, double restitution, int cone, int bias, int iters,
+               double res[2]) {
   uint8_t* dyn = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1));
   for (int i = 0; i < nb; ++i) dyn[i] = invm[i] > 0.0;
   body_view bv = {invm, Iinv, x, v, w, dyn};
+  const solve_opts o = {mu, restitution, cone, bias};
   prep_k(&bv, m, nm);
-  for (int it = 0; it < iters; ++it) pgs_sweep(&bv, m, nm, mu, restitution);
-  residual(&bv, m, nm, mu, res);
+  if (bias) prep_bias(&bv, m, nm, restitution, 0.0);
+  for (int it = 0; it < iters; ++it) pgs_sweep(&bv, m, nm, &o);
+  residual(&bv, m, nm, &o, res);
   free(dyn);
 }
 
@@ -777,9 +1051,16 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
     }
   }
   /* 3. broadphase */
-  int cap = nb * (nb + 1) / 2 + 1;
+  /* room for 16 candidates per body; a denser scene is walked again with room for all */
+  int cap = 16 * nb + 64;
   int32_t* pairs = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap);
   int ncand = broadphase_R(nb, x, h, active, dyn, P->margin, pairs, cap);
+  if (ncand > cap) {
+    free(pairs);
+    cap = ncand;
+    pairs = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap);
+    ncand = broadphase_R(nb, x, h, active, dyn, P->margin, pairs, cap);
+  }
   st->candidates += ncand;
 
   /* 4-5. narrowphase and manifolds, canonical (a, b) order with the ground last per body */
@@ -792,12 +1073,16 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
     m->a = a; m->b = b;
     if (b >= 0) {
       or_sat_result sr;
-      sat_R(he + 3 * a, x + 3 * a, R + 9 * a, he + 3 * b, x + 3 * b, R + 9 * b, &sr);
+      sat_R(he + 3 * a, x + 3 * a, R + 9 * a, he + 3 * b, x + 3 * b, R + 9 * b, P->manifold_mode != 0, &sr);
       if (!sr.collide) continue;
       m->axis = sr.axis;
       m->band = sr.band;
       m->sigma = sr.sigma;
-      manifold_box_R(he + 3 * a, x + 3 * a, R + 9 * a, he + 3 * b, x + 3 * b, R + 9 * b, sr.normal, sr.depth, m);
+      if (P->manifold_mode)
+        manifold_refface_R(he + 3 * a, x + 3 * a, R + 9 * a, he + 3 * b, x + 3 * b, R + 9 * b, sr.normal, sr.depth,
+                           sr.axis, m);
+      else
+        manifold_box_R(he + 3 * a, x + 3 * a, R + 9 * a, he + 3 * b, x + 3 * b, R + 9 * b, sr.normal, sr.depth, m);
     } else {
       m->axis = -1;
       if (!manifold_ground_R(he + 3 * a, x + 3 * a, R + 9 * a, m)) continue;
@@ -807,22 +1092,41 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
   }
   st->manifolds += nm;
 
-  /* 6. greedy colouring in canonical order; conflicts only through dynamic bodies */
+  /* 6. greedy first-fit colouring; conflicts only through dynamic bodies.  A tower below
+   * mega_bodies takes its manifolds in canonical order.  A larger one is cut into partitions of
+   * colour_partition bodies (by tower-local index) and takes them in four passes, each in
+   * canonical order: (1) pairs inside a partition or with the ground; (2) pairs between
+   * partitions p and p + 1 for even p; (3) the same for odd p; (4) pairs between partitions
+   * further apart.  Within a pass, different partitions (or partition pairs) share no body. */
   uint64_t* used = (uint64_t*)calloc(NB, sizeof(uint64_t));
-  int ncol = 0, kept = 0;
+  int ncol = 0;
+  const int parted = P->mega_bodies > 0 && nb >= P->mega_bodies;
+  const int S = P->colour_partition > 0 ? P->colour_partition : 1024;
+  for (int c = 0; c < nm; ++c) ms[c].colour = -1;
+  for (int pass = 0; pass < (parted ? 4 : 1); ++pass) {
+    for (int c = 0; c < nm; ++c) {
+      or_manifold* m = &ms[c];
+      if (parted) {
+        const int pa = m->a / S, pb = m->b < 0 ? pa : m->b / S;
+        const int want = pb == pa ? 0 : (pb == pa + 1 ? 1 + (pa & 1) : 3);
+        if (want != pass) continue;
+      }
+      uint64_t u = 0;
+      if (dyn[m->a]) u |= used[m->a];
+      if (m->b >= 0 && dyn[m->b]) u |= used[m->b];
+      int col = 0;
+      while (col < MAX_COLOURS && (u >> col) & 1ull) ++col;
+      if (col >= MAX_COLOURS) { st->error |= 1; continue; }   /* dropped */
+      m->colour = col;
+      if (dyn[m->a]) used[m->a] |= 1ull << col;
+      if (m->b >= 0 && dyn[m->b]) used[m->b] |= 1ull << col;
+      if (col + 1 > ncol) ncol = col + 1;
+    }
+  }
+  int kept = 0;
   for (int c = 0; c < nm; ++c) {
-    or_manifold* m = &ms[c];
-    uint64_t u = 0;
-    if (dyn[m->a]) u |= used[m->a];
-    if (m->b >= 0 && dyn[m->b]) u |= used[m->b];
-    int col = 0;
-    while (col < MAX_COLOURS && (u >> col) & 1ull) ++col;
-    if (col >= MAX_COLOURS) { st->error |= 1; continue; }   /* dropped */
-    m->colour = col;
-    if (dyn[m->a]) used[m->a] |= 1ull << col;
-    if (m->b >= 0 && dyn[m->b]) used[m->b] |= 1ull << col;
-    if (col + 1 > ncol) ncol = col + 1;
-    if (kept != c) ms[kept] = *m;
+    if (ms[c].colour < 0) continue;
+    if (kept != c) ms[kept] = ms[c];
     ++kept;
   }
   nm = kept;
@@ -838,7 +1142,10 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
 
   /* 7. prep and warm start */
   body_view bv = {invm, Iinv, x, v, w, dyn};
+  const solve_opts so = {mu, P->restitution, P->friction_cone, P->restitution_bias};
   prep_k(&bv, ord, nm);
+  /* a resting contact approaches at about |g| dt per step: twice that is the bounce threshold */
+  if (P->restitution_bias) prep_bias(&bv, ord, nm, P->restitution, 2.0 * norm3(P->gravity) * dt);
   long npts = 0;
   for (int c = 0; c < nm; ++c) npts += ord[c].npts;
   const int learned = P->warm_start == 2 && P->mlp != NULL;
@@ -875,10 +1182,14 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
           double ln = (y[0] > 0.0 ? y[0] : 0.0) * gdt / m->k[i][0];
           double b = mu * ln;
           double l1 = y[1] * gdt / m->k[i][1], l2 = y[2] * gdt / m->k[i][2];
-          if (l1 < -b) l1 = -b;
-          if (l1 > b) l1 = b;
-          if (l2 < -b) l2 = -b;
-          if (l2 > b) l2 = b;
+          if (P->friction_cone) {
+            disc_project(&l1, &l2, b);
+          } else {
+            if (l1 < -b) l1 = -b;
+            if (l1 > b) l1 = b;
+            if (l2 < -b) l2 = -b;
+            if (l2 > b) l2 = b;
+          }
           m->lam[i][0] = ln; m->lam[i][1] = l1; m->lam[i][2] = l2;
         }
       }
@@ -912,19 +1223,19 @@ static int substep(const or_params* P, double dt, int nb, const double* he, cons
   /* 8. PGS; 9. residual.  A learned start runs mlp_iters sweeps; if the residual is still above
    * fallback_tau the solve is redone plainly (pre-solve velocities, zero impulses, iters sweeps). */
   const int iters = learned ? P->mlp_iters : P->iters;
-  for (int it = 0; it < iters; ++it) pgs_sweep(&bv, ord, nm, mu, P->restitution);
+  for (int it = 0; it < iters; ++it) pgs_sweep(&bv, ord, nm, &so);
   st->contact_iters += npts * (int64_t)iters;
   double res[2];
-  residual(&bv, ord, nm, mu, res);
+  residual(&bv, ord, nm, &so, res);
   if (learned && res[0] > P->fallback_tau) {
     memcpy(v, v_save, sizeof(double) * 3 * (size_t)nb);
     memcpy(w, w_save, sizeof(double) * 3 * (size_t)nb);
     for (int c = 0; c < nm; ++c)
       for (int i = 0; i < ord[c].npts; ++i) ord[c].lam[i][0] = ord[c].lam[i][1] = ord[c].lam[i][2] = 0.0;
-    for (int it = 0; it < P->iters; ++it) pgs_sweep(&bv, ord, nm, mu, P->restitution);
+    for (int it = 0; it < P->iters; ++it) pgs_sweep(&bv, ord, nm, &so);
     st->contact_iters += npts * (int64_t)P->iters;
     st->fallbacks += 1;
-    residual(&bv, ord, nm, mu, res);
+    residual(&bv, ord, nm, &so, res);
   }
   free(v_save);
   free(w_save);

@@ -32,6 +32,16 @@ typedef struct {
   int32_t mlp_iters;     /* PGS iterations after the learned warm start */
   double fallback_tau;   /* tower residual [m/s] above which the plain solve is redone */
   const double* mlp;     /* MLP parameters (layout OR_MLP_*), used when warm_start == 2 */
+  int32_t friction_cone; /* 0: per-axis clip of Eq. (coulomb_pgs); 1: the tangent pair projected onto
+                            the disc of radius mu lambda_n (the circular cone of the PGS figure) */
+  int32_t restitution_bias;  /* 0: (1 + e) v_n in every iteration (Eq. (lambda_n) as printed); 1: the
+                            normal row targets -e v_n- (pre-solve normal velocity) when the point
+                            approaches faster than 2 |g| dt, else 0 */
+  int32_t manifold_mode; /* 0: literal silhouettes clipped (Sec. "Contact Manifold (Face Clipping)");
+                            1: reference-face clipping */
+  int32_t mega_bodies;   /* towers of at least this many bodies (0: none) take the partitioned colouring */
+  int32_t colour_partition;  /* bodies per colouring partition (tower-local index / this) */
+  int32_t _pad;
 } or_params;
 
 /* Learned warm start: per-contact MLP 24 -> 128 -> 128 -> 3 with GELU (erf form).  Its outputs
@@ -69,6 +79,7 @@ typedef struct {
   double point[4][3];    /* world contact points */
   double lam[4][3];      /* accumulated impulses (normal, t1, t2) after the solve */
   double k[4][3];        /* inverse effective masses (normal, t1, t2) */
+  double vbias[4];       /* restitution targets of the normal rows (restitution_bias) */
 } or_manifold;
 
 enum {
@@ -106,10 +117,19 @@ void or_box_inertia(double m, const double he[3], double I[3]);
 /* Sec. "Narrowphase: OBB SAT": 15-axis test of boxes A and B. */
 void or_sat(const double heA[3], const double xA[3], const double qA[4],
             const double heB[3], const double xB[3], const double qB[4], or_sat_result* out);
+/* The same with the reference-face preference of the clipping variant: a colliding pair keeps its
+ * best face axis unless a cross axis overlaps less than 0.95 of it minus 1e-6 m. */
+void or_sat_ex(const double heA[3], const double xA[3], const double qA[4],
+               const double heB[3], const double xB[3], const double qB[4], int32_t prefer_face,
+               or_sat_result* out);
 /* Sec. "Contact Manifold (Face Clipping)": manifold of a colliding box pair (normal from A to B). */
 int or_manifold_box(const double heA[3], const double xA[3], const double qA[4],
                     const double heB[3], const double xB[3], const double qB[4],
                     const double normal[3], double depth, or_manifold* out);
+/* The reference-face variant of the same (axis: the SAT axis 0..14 of the pair). */
+int or_manifold_refface(const double heA[3], const double xA[3], const double qA[4],
+                        const double heB[3], const double xB[3], const double qB[4],
+                        const double normal[3], double depth, int axis, or_manifold* out);
 /* Box against the ground half-space z <= 0; returns 1 if it collides. */
 int or_manifold_ground(const double he[3], const double x[3], const double q[4], or_manifold* out);
 
@@ -120,6 +140,10 @@ int or_manifold_ground(const double he[3], const double x[3], const double q[4],
  * Writes k.  Returns the residual (RMS and max) through res[2]. */
 void or_pgs(int nb, const double* invm, const double* Iinv, const double* x, double* v, double* w,
             int nm, or_manifold* m, double mu, double restitution, int iters, double res[2]);
+/* The same with the friction and restitution options of or_params (cone, bias). */
+void or_pgs_ex(int nb, const double* invm, const double* Iinv, const double* x, double* v, double* w,
+               int nm, or_manifold* m, double mu, double restitution, int cone, int bias, int iters,
+               double res[2]);
 
 /* Step one tower n_steps times (state arrays updated in place).
  * prev/nprev: previous step's manifolds for the warm start (may be NULL/0).

@@ -33,7 +33,9 @@ class Params(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("dt", C.c_double), ("restitution", C.c_double),
                 ("beta", C.c_double), ("slop", C.c_double), ("margin", C.c_double),
                 ("n_sub", C.c_int32), ("iters", C.c_int32), ("warm_start", C.c_int32), ("mlp_iters", C.c_int32),
-                ("fallback_tau", C.c_double), ("mlp", C.POINTER(C.c_double))]
+                ("fallback_tau", C.c_double), ("mlp", C.POINTER(C.c_double)), ("friction_cone", C.c_int32),
+                ("restitution_bias", C.c_int32), ("manifold_mode", C.c_int32), ("mega_bodies", C.c_int32),
+                ("colour_partition", C.c_int32), ("_pad", C.c_int32)]
 
 
 NFEAT, HIDDEN, FEAT_RECORD = 24, 128, 30
@@ -50,7 +52,8 @@ class Manifold(C.Structure):
                 ("axis", C.c_int32), ("band", C.c_int32), ("slot", C.c_int32 * 4),
                 ("normal", C.c_double * 3), ("t1", C.c_double * 3), ("t2", C.c_double * 3),
                 ("depth", C.c_double), ("sigma", C.c_double),
-                ("point", (C.c_double * 3) * 4), ("lam", (C.c_double * 3) * 4), ("k", (C.c_double * 3) * 4)]
+                ("point", (C.c_double * 3) * 4), ("lam", (C.c_double * 3) * 4), ("k", (C.c_double * 3) * 4),
+                ("vbias", C.c_double * 4)]
 
 
 class Stats(C.Structure):
@@ -108,12 +111,18 @@ def lib():
             L.or_quat_to_rot.argtypes = [_dp, _dp]
             L.or_box_inertia.argtypes = [C.c_double, _dp, _dp]
             L.or_sat.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.POINTER(SatResult)]
+            L.or_sat_ex.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.c_int32, C.POINTER(SatResult)]
             L.or_manifold_box.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.POINTER(Manifold)]
             L.or_manifold_box.restype = C.c_int
+            L.or_manifold_refface.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_int,
+                                              C.POINTER(Manifold)]
+            L.or_manifold_refface.restype = C.c_int
             L.or_manifold_ground.argtypes = [_dp, _dp, _dp, C.POINTER(Manifold)]
             L.or_manifold_ground.restype = C.c_int
             L.or_pgs.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_int, C.POINTER(Manifold), C.c_double,
                                  C.c_double, C.c_int, _dp]
+            L.or_pgs_ex.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_int, C.POINTER(Manifold), C.c_double,
+                                    C.c_double, C.c_int, C.c_int, C.c_int, _dp]
             L.or_step_tower.argtypes = [C.POINTER(Params), C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _u8p, C.c_double,
                                         C.c_int, C.POINTER(Push), C.POINTER(C.c_int64), C.c_int,
                                         C.POINTER(Manifold), C.c_int, C.POINTER(Manifold), C.c_int,
@@ -158,6 +167,11 @@ def make_params(p: dict, warm_start: int = 0, mlp=None, mlp_iters: int = 0,
     P.warm_start = int(warm_start)
     P.mlp_iters = int(mlp_iters)
     P.fallback_tau = float(fallback_tau)
+    P.friction_cone = int(p.get("friction_cone", 0))
+    P.restitution_bias = int(p.get("restitution_bias", 0))
+    P.manifold_mode = int(p.get("manifold_mode", 0))
+    P.mega_bodies = int(p.get("mega_bodies", 0))
+    P.colour_partition = int(p.get("colour_partition", 0))
     if mlp is not None:
         assert mlp.dtype == np.float64 and mlp.flags.c_contiguous and mlp.size == MLP_SIZE
         P.mlp = mlp.ctypes.data_as(C.POINTER(C.c_double))
@@ -191,9 +205,11 @@ def box_inertia(m, he) -> np.ndarray:
     return I
 
 
-def sat(heA, xA, qA, heB, xB, qB) -> SatResult:
+def sat(heA, xA, qA, heB, xB, qB, prefer_face=False) -> SatResult:
+    """15-axis SAT; prefer_face: the reference-face variant's choice of the normal."""
     r = SatResult()
-    lib().or_sat(_f64(heA, 3), _f64(xA, 3), _f64(qA, 4), _f64(heB, 3), _f64(xB, 3), _f64(qB, 4), C.byref(r))
+    lib().or_sat_ex(_f64(heA, 3), _f64(xA, 3), _f64(qA, 4), _f64(heB, 3), _f64(xB, 3), _f64(qB, 4),
+                    int(bool(prefer_face)), C.byref(r))
     return r
 
 
@@ -204,14 +220,23 @@ def manifold_box(heA, xA, qA, heB, xB, qB, normal, depth) -> Manifold:
     return m
 
 
+def manifold_refface(heA, xA, qA, heB, xB, qB, normal, depth, axis) -> Manifold:
+    """Reference-face clipping manifold of a colliding pair (axis: its SAT axis 0..14)."""
+    m = Manifold()
+    lib().or_manifold_refface(_f64(heA, 3), _f64(xA, 3), _f64(qA, 4), _f64(heB, 3), _f64(xB, 3), _f64(qB, 4),
+                              _f64(normal, 3), float(depth), int(axis), C.byref(m))
+    return m
+
+
 def manifold_ground(he, x, q):
     m = Manifold()
     hit = lib().or_manifold_ground(_f64(he, 3), _f64(x, 3), _f64(q, 4), C.byref(m))
     return m if hit else None
 
 
-def pgs(invm, Iinv, x, v, w, manifolds, mu, restitution, iters):
-    """PGS on explicit manifolds (processed in list order). Returns (v, w, manifolds, residual)."""
+def pgs(invm, Iinv, x, v, w, manifolds, mu, restitution, iters, cone=False, bias=False):
+    """PGS on explicit manifolds (processed in list order). Returns (v, w, manifolds, residual).
+    cone: the tangent pair projected onto the friction disc; bias: pre-solve restitution targets."""
     nb = len(invm)
     v = _f64(v, (nb, 3)).copy()
     w = _f64(w, (nb, 3)).copy()
@@ -219,8 +244,8 @@ def pgs(invm, Iinv, x, v, w, manifolds, mu, restitution, iters):
     for i, m in enumerate(manifolds):
         arr[i] = m
     res = np.zeros(2)
-    lib().or_pgs(nb, _f64(invm, nb), _f64(Iinv, (nb, 9)), _f64(x, (nb, 3)), v, w, len(manifolds), arr,
-                 float(mu), float(restitution), int(iters), res)
+    lib().or_pgs_ex(nb, _f64(invm, nb), _f64(Iinv, (nb, 9)), _f64(x, (nb, 3)), v, w, len(manifolds), arr,
+                    float(mu), float(restitution), int(bool(cone)), int(bool(bias)), int(iters), res)
     return v, w, [arr[i] for i in range(len(manifolds))], res
 
 

@@ -98,6 +98,9 @@ struct StepArgs {
   float dt;                    // substep length
   float restitution, beta, slop, margin;
   int32_t iters, n_sub, n_steps, warm_start;
+  int32_t friction_cone;       // 1: tangent pairs projected onto the disc of radius mu lambda_n
+  int32_t restitution_bias;    // 1: normal rows target -e v_n- (pre-solve velocity) above 2 |g| dt
+  int32_t manifold_mode;       // 0: literal silhouettes; 1: reference-face clipping
   int64_t step0;
   // capacities of this launch (LDS layout)
   int32_t nbp;     // bodies per pack
@@ -110,8 +113,8 @@ constexpr int kBodyWords = 31;     // x3 q4 v3 w3 he3 invm invI3 flag tower Iw6 
 constexpr int kTowerWords = 14;    // body range, mu, counters4, residual2, canonical range2, points, frozen
 constexpr int kPushWords = 10;
 constexpr int kManWords = 4;       // canonical (code, pos) + sorted (code, meta)
-constexpr int kManDevWords = 28;   // r_A 12, lambda 12, n 3, depth per sorted manifold, in the
-                                   // pack's device region
+constexpr int kManDevWords = 32;   // r_A 12, lambda 12, n 3, depth, restitution targets 4 per
+                                   // sorted manifold, in the pack's device region
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
 constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
 constexpr int kLearnedIslandWaves = 4;          // waves of a pack in device memory with the network
@@ -173,5 +176,63 @@ int step_launch_config(const StepArgs& a, const void** func, unsigned* block_thr
 
 // records the message returned by jg_last_error on this thread; returns code
 int32_t set_error(int32_t code, const std::string& msg);
+
+// ------------------------------------------------------------------------------------------------
+// Islands stepped by the whole GPU (towers of at least mega_bodies bodies): one cooperative launch
+// of every step, its phases separated by grid-wide barriers, 32-bit body indices.  The island's
+// bodies are the internal range [g0, g0 + nb) of the world arrays; its pushes the rows [p0, p0 + np)
+// (push_body holds internal indices).  Scratch arrays are sized by the host from nb and cand_cap.
+// ------------------------------------------------------------------------------------------------
+constexpr int kMegaThreads = 256;
+constexpr int kMegaBodyWords = 29;   // x3 q4 v3 w3 he3 invm invI3 Iw6 hm3 (SoA, stride nb)
+constexpr int kMegaBodyU32 = 8;      // flag, tower (0), colour mask lo, hi, cell, candidate count,
+                                     // candidate offset, cell-sorted body (stride nb)
+constexpr int kMegaScal = 256;       // scalar words (counters, colour tables)
+
+struct MegaArgs {
+  float *x, *q, *v, *w;
+  const float *he, *mass;
+  uint32_t* flags;
+  int32_t cap, g0, nb;
+  int32_t tslot;               // tower slot (statistics, frozen flag)
+  float mu;
+  const int32_t *push_body, *push_start, *push_steps;
+  const float *push_force, *push_withdraw;
+  float* push_x0;
+  int32_t p0, np;
+  uint32_t* tower_count;       // [4 * tslot + k]: candidates, manifolds, points (added), colours (last)
+  float* tower_res;            // [2 * tslot + k]: residual RMS, max (last substep)
+  uint32_t* tower_frozen;
+  uint32_t* err_flag;          // the world's error word (reported by the next syncing call)
+  uint32_t* island_err;        // this island's error bits since the host last read them
+  float g[3], dt, restitution, beta, slop, margin;
+  int32_t iters, n_sub, n_steps, friction_cone, restitution_bias, manifold_mode, partition;
+  int64_t step0;
+  // scratch
+  float* body;                 // kMegaBodyWords * nb
+  uint32_t* ubody;             // kMegaBodyU32 * nb
+  int32_t* cells;              // 2 * (ncell_cap + 1): counts, starts
+  int32_t ncell_cap;
+  uint32_t* cand;              // 3 * cand_cap: body a, body b (~0u: the ground), collide flag / position
+  int32_t cand_cap;
+  int32_t* man;                // 7 * cand_cap: canonical a, b, colour, sorted slot; sorted a, b, meta
+  float* md;                   // kManDevWords * cand_cap, colour-sorted records
+  int32_t* part;               // nparts + 1 first canonical manifold of each partition, then nparts far counts
+  int32_t nparts;
+  float* red;                  // 2 * gridDim partial sums (residual)
+  int32_t* ired;               // 2 * gridDim integer partials (scans, counts)
+  int32_t* scal;               // kMegaScal words
+  // contacts of the launch's last step, canonical order (npts 0: a pair dropped by the colouring)
+  int32_t *out_a, *out_b;
+  uint32_t* out_meta;          // npts | colour << 4 | slots << 12
+  float *out_geo, *out_pts;    // 8 and 24 words per pair, as the packs' outputs
+  int32_t* out_count;
+};
+
+// queues the cooperative launch of an island's steps (blocks from mega_blocks); a hipError_t
+int launch_mega(const MegaArgs& a, int blocks, void* stream);
+// the workgroups of the grid-wide kernel: every one resident at once (the occupancy of the
+// current device times its CUs, at most two per CU); a hipError_t
+int mega_blocks(int* blocks);
 
 }  // namespace jg

@@ -30,8 +30,10 @@
 //   9 integration: x += dt v, q from Eq. (quat_int) with world-frame omega,
 //     omega re-derived from the angular momentum (Eq. (newton_euler), torque free)
 //  10 Baumgarte correction (Eq. (baumgarte)), colour by colour
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <math.h>
 #include <stdint.h>
@@ -252,8 +254,12 @@ __device__ __forceinline__ void tangent_basis(const float n[3], float t1[3], flo
 // ------------------------------------------------------------------------------------------------
 // narrowphase: 15-axis SAT in coordinates relative to A's centre (d = xB - xA)
 // ------------------------------------------------------------------------------------------------
+// kPreferFace (reference-face manifolds): of a colliding pair, the normal and depth come from the
+// best face axis unless the best cross axis is smaller than 0.95 of it by more than 1 um, so that
+// a cross axis parallel to a face normal (crossed blocks: x_A x y_B = z) never stands in for it
+template <bool kPreferFace = false>
 __device__ __forceinline__ bool sat_boxes(const float RA[9], const float heA[3], const float RB[9], const float heB[3],
-                          const float d[3], float n[3], float& depth) {
+                          const float d[3], float n[3], float& depth, int* axis_out = nullptr) {
   float A[3][3], B[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -261,19 +267,23 @@ __device__ __forceinline__ bool sat_boxes(const float RA[9], const float heA[3],
     for (int k = 0; k < 3; ++k) { A[i][k] = RA[3 * k + i]; B[i][k] = RB[3 * k + i]; }
   float best = INFINITY;
   float bu[3] = {0.f, 0.f, 1.f};
+  int bi = 0;
   bool sep = false;
-  auto axis = [&](const float u[3]) {
+  auto axis = [&](const float u[3], int idx) {
     const float ra = heA[0] * fabsf(dot3(A[0], u)) + heA[1] * fabsf(dot3(A[1], u)) + heA[2] * fabsf(dot3(A[2], u));
     const float rb = heB[0] * fabsf(dot3(B[0], u)) + heB[1] * fabsf(dot3(B[1], u)) + heB[2] * fabsf(dot3(B[2], u));
     const float dd = ra + rb - fabsf(dot3(d, u));
     sep = sep || !(dd > 0.f);
-    if (dd < best) { best = dd; bu[0] = u[0]; bu[1] = u[1]; bu[2] = u[2]; }
+    if (dd < best) { best = dd; bu[0] = u[0]; bu[1] = u[1]; bu[2] = u[2]; bi = idx; }
   };
 #pragma unroll
-  for (int i = 0; i < 3; ++i) axis(A[i]);
+  for (int i = 0; i < 3; ++i) axis(A[i], i);
 #pragma unroll
-  for (int j = 0; j < 3; ++j) axis(B[j]);
+  for (int j = 0; j < 3; ++j) axis(B[j], 3 + j);
   if (sep) return false;
+  const float best_face = best;
+  const float bu_face[3] = {bu[0], bu[1], bu[2]};
+  const int bi_face = bi;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -284,12 +294,18 @@ __device__ __forceinline__ bool sat_boxes(const float RA[9], const float heA[3],
       if (len2 < 1e-10f) continue;          // |a x b| < 1e-5: not tested
       const float il = rsqrtf(len2);
       c[0] *= il; c[1] *= il; c[2] *= il;
-      axis(c);
+      axis(c, 6 + 3 * i + j);
     }
   if (sep) return false;
+  if (kPreferFace && bi >= 6 && !(best < 0.95f * best_face - 1e-6f)) {
+    best = best_face;
+    bu[0] = bu_face[0]; bu[1] = bu_face[1]; bu[2] = bu_face[2];
+    bi = bi_face;
+  }
   const float s = dot3(d, bu) < 0.f ? -1.f : 1.f;
   n[0] = s * bu[0]; n[1] = s * bu[1]; n[2] = s * bu[2];
   depth = best;
+  if (axis_out) *axis_out = bi;
   return true;
 }
 
@@ -466,6 +482,197 @@ __device__ __forceinline__ uint32_t manifold_boxes(const float RA[9], const floa
   return used;
 }
 
+// Reference-face clipping (the alternative to the literal silhouettes), relative to A's centre in
+// the contact frame.  For a face axis, the face that owns it is the reference face and the other
+// box's face most opposed to it the incident face; both are parallelograms in the (t1, t2) plane
+// (projections along n, which is the reference face's normal).  The clipped polygon's vertices
+// are incident corners inside the reference rectangle, reference corners inside the incident
+// parallelogram and crossings of their edges; each carries the incident face's height along n
+// there, and those on or below the reference face are kept, lifted halfway to it.  The slots are
+// the kept vertices extreme along the four diagonals.  An edge axis gives one point, the midpoint
+// of the closest points of the two supporting edges.  Returns the used-slot bits (0: nothing on or
+// below the reference face; the caller then takes the silhouettes' manifold).
+struct ExtremesZ {
+  float best[4];
+  V2 p[4];
+  float z[4];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { best[s] = -INFINITY; p[s].x = p[s].y = 0.f; z[s] = 0.f; }
+  }
+  __device__ __forceinline__ void consider(V2 q, float zq) {
+    const float a = q.x + q.y, b = q.y - q.x;
+    if (a > best[0]) { best[0] = a; p[0] = q; z[0] = zq; }
+    if (b > best[1]) { best[1] = b; p[1] = q; z[1] = zq; }
+    if (-a > best[2]) { best[2] = -a; p[2] = q; z[2] = zq; }
+    if (-b > best[3]) { best[3] = -b; p[3] = q; z[3] = zq; }
+  }
+};
+
+__device__ __forceinline__ uint32_t manifold_refface(const float RA[9], const float heA[3], const float RB[9],
+                                                     const float heB[3], const float d[3], const float n[3], int axis,
+                                                     float t1[3], float rA[4][3]) {
+  float t2[3];
+  tangent_basis(n, t1, t2);
+  float A[3][3], B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { A[i][k] = RA[3 * k + i]; B[i][k] = RB[3 * k + i]; }
+  if (axis >= 6) {
+    const int i = (axis - 6) / 3, j = (axis - 6) % 3;
+    float pa[3] = {0.f, 0.f, 0.f}, pb[3] = {d[0], d[1], d[2]};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (q != i) {
+        const float sg = dot3(n, A[q]) >= 0.f ? heA[q] : -heA[q];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pa[k] += sg * A[q][k];
+      }
+      if (q != j) {
+        const float sg = dot3(n, B[q]) >= 0.f ? -heB[q] : heB[q];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pb[k] += sg * B[q][k];
+      }
+    }
+    float r[3], c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = pa[k] - pb[k];
+    cross3(A[i], B[j], c);
+    const float det = dot3(c, c), a12 = dot3(A[i], B[j]);
+    const float ar = dot3(A[i], r), br = dot3(B[j], r);
+    float sa = det > 1e-12f ? (a12 * br - ar) / det : 0.f;
+    sa = fminf(fmaxf(sa, -heA[i]), heA[i]);
+    float tb = fminf(fmaxf(br + a12 * sa, -heB[j]), heB[j]);
+    sa = fminf(fmaxf(a12 * tb - ar, -heA[i]), heA[i]);
+    float mid[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mid[k] = 0.5f * ((pa[k] + sa * A[i][k]) + (pb[k] + tb * B[j][k]));
+    rA[0][0] = dot3(mid, n); rA[0][1] = dot3(mid, t1); rA[0][2] = dot3(mid, t2);
+    return 1u;
+  }
+  const bool refA = axis < 3;
+  const int fi = refA ? axis : axis - 3;
+  const int s1 = fi == 0 ? 1 : 0, s2 = fi == 2 ? 1 : 2;
+  const float un = refA ? 1.f : -1.f;           // u = un n, from the reference box to the other
+  // reference face: centre (relative to A) and its two half edges, projected
+  float cr[3], fr[3], e1r[3], e2r[3];
+  float hr1, hr2, hrf;
+  if (refA) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { fr[k] = A[fi][k]; e1r[k] = A[s1][k]; e2r[k] = A[s2][k]; }
+    hrf = heA[fi]; hr1 = heA[s1]; hr2 = heA[s2];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { fr[k] = B[fi][k]; e1r[k] = B[s1][k]; e2r[k] = B[s2][k]; }
+    hrf = heB[fi]; hr1 = heB[s1]; hr2 = heB[s2];
+  }
+  const float su = un * dot3(n, fr) >= 0.f ? hrf : -hrf;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cr[k] = (refA ? 0.f : d[k]) + su * fr[k];
+  const float zr = dot3(cr, n);                 // the reference face's height along n
+  const V2 crc = {dot3(cr, t1), dot3(cr, t2)};
+  const V2 g1 = {hr1 * dot3(e1r, t1), hr1 * dot3(e1r, t2)}, g2 = {hr2 * dot3(e2r, t1), hr2 * dot3(e2r, t2)};
+  // incident face: the other box's face most opposed to u
+  float I[3][3], heI[3], xi[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) I[q][k] = refA ? B[q][k] : A[q][k];
+    heI[q] = refA ? heB[q] : heA[q];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) xi[k] = refA ? d[k] : 0.f;
+  int fk = 0;
+  float bestd = -1.f;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float dq = fabsf(dot3(n, I[q]));
+    if (dq > bestd) { bestd = dq; fk = q; }
+  }
+  const int k1 = fk == 0 ? 1 : 0, k2 = fk == 2 ? 1 : 2;
+  float fI[3], a1[3], a2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { fI[k] = I[fk][k]; a1[k] = I[k1][k]; a2[k] = I[k2][k]; }
+  const float sf = un * dot3(n, fI) >= 0.f ? -heI[fk] : heI[fk];
+  float ci[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ci[k] = xi[k] + sf * fI[k];
+  const V2 cic = {dot3(ci, t1), dot3(ci, t2)};
+  const float zc = dot3(ci, n);
+  const V2 h1 = {heI[k1] * dot3(a1, t1), heI[k1] * dot3(a1, t2)}, h2 = {heI[k2] * dot3(a2, t1), heI[k2] * dot3(a2, t2)};
+  const float dz1 = heI[k1] * dot3(a1, n), dz2 = heI[k2] * dot3(a2, n);
+  // on or below the reference face: u . (p - cr) <= 0, i.e. un (z - zr) <= 0
+  ExtremesZ E;
+  E.init();
+  bool any = false;
+  auto keep = [&](V2 q, float z) {
+    if (un * (z - zr) <= 0.f) {
+      E.consider(q, 0.5f * (z + zr));
+      any = true;
+    }
+  };
+  const float gg1 = g1.x * g1.x + g1.y * g1.y, gg2 = g2.x * g2.x + g2.y * g2.y;
+  const float deth = cr2(h1, h2);
+  V2 ic[4], rc[4];
+  float iz[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float sa = (c == 0 || c == 3) ? 1.f : -1.f, sb = (c < 2) ? 1.f : -1.f;
+    ic[c].x = cic.x + sa * h1.x + sb * h2.x;
+    ic[c].y = cic.y + sa * h1.y + sb * h2.y;
+    iz[c] = zc + sa * dz1 + sb * dz2;
+    rc[c].x = crc.x + sa * g1.x + sb * g2.x;
+    rc[c].y = crc.y + sa * g1.y + sb * g2.y;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    // incident corner inside the reference rectangle (orthogonal half edges)
+    const float px = ic[c].x - crc.x, py = ic[c].y - crc.y;
+    const float a = (px * g1.x + py * g1.y) / gg1, b = (px * g2.x + py * g2.y) / gg2;
+    if (fabsf(a) <= 1.f + 1e-6f && fabsf(b) <= 1.f + 1e-6f) keep(ic[c], iz[c]);
+    // reference corner inside the incident parallelogram, at the incident face's height there
+    const V2 rq = {rc[c].x - cic.x, rc[c].y - cic.y};
+    const float ai = cr2(rq, h2) / deth, bi = cr2(h1, rq) / deth;
+    if (fabsf(ai) <= 1.f + 1e-6f && fabsf(bi) <= 1.f + 1e-6f) keep(rc[c], zc + ai * dz1 + bi * dz2);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const V2 p0 = ic[c], p1 = ic[(c + 1) & 3];
+    const V2 u = {p1.x - p0.x, p1.y - p0.y};
+    const float lu = u.x * u.x + u.y * u.y;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const V2 q0 = rc[e], q1 = rc[(e + 1) & 3];
+      const V2 w = {q1.x - q0.x, q1.y - q0.y};
+      const float den = cr2(u, w);
+      const float lw = w.x * w.x + w.y * w.y;
+      if (lu < 1e-18f || den * den <= 1e-12f * lu * lw) continue;
+      const V2 r = {q0.x - p0.x, q0.y - p0.y};
+      const float idn = 1.f / den;
+      const float t = cr2(r, w) * idn, sv = cr2(r, u) * idn;
+      if (t >= -1e-6f && t <= 1.f + 1e-6f && sv >= -1e-6f && sv <= 1.f + 1e-6f) {
+        const V2 pt = {p0.x + t * u.x, p0.y + t * u.y};
+        keep(pt, iz[c] + t * (iz[(c + 1) & 3] - iz[c]));
+      }
+    }
+  }
+  if (!any) return 0u;
+  uint32_t used = 0u;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    bool ok = E.best[s] != -INFINITY;
+#pragma unroll
+    for (int c = 0; c < s; ++c) {
+      const float dx = E.p[s].x - E.p[c].x, dy = E.p[s].y - E.p[c].y;
+      ok = ok && !(((used >> c) & 1u) && (dx * dx + dy * dy < 1e-12f));
+    }
+    if (ok) used |= 1u << s;
+    rA[s][0] = E.z[s]; rA[s][1] = E.p[s].x; rA[s][2] = E.p[s].y;
+  }
+  return used;
+}
+
 // ------------------------------------------------------------------------------------------------
 // PGS rows (Eq. (lambda_n), Eq. (coulomb_pgs)), worked in the contact frame F = (n, t1, t2).
 // In that frame a row's direction is a unit axis e_K, so r x e_K has two non-zero components
@@ -501,10 +708,8 @@ __device__ constexpr int sym_index(int r, int c) {
 // A body without mass holds zero velocity, inverse mass and inverse inertia in the pack (its
 // stored velocity is left as given), so it needs no case of its own; the ground (i = kGround,
 // only ever the second body of a pair) reads slot 0 and takes zeros.
-template <bool kMayBeGround>
-__device__ __forceinline__ void load_local(const Lds& L, int i, const Frame& F, LBody& b) {
+__device__ __forceinline__ void load_local_g(const Lds& L, int i, bool ground, const Frame& F, LBody& b) {
   const int nb = L.nbp;
-  const bool ground = kMayBeGround && i == (int)kGround;
   const int j = ground ? 0 : i;
   float v[3], w[3], Iw[6];
   load3(L.v, nb, j, v);
@@ -531,6 +736,10 @@ __device__ __forceinline__ void load_local(const Lds& L, int i, const Frame& F, 
   b.I[3] = dot3x(F.f[0], g[1]); b.I[4] = dot3x(F.f[0], g[2]); b.I[5] = dot3x(F.f[1], g[2]);
   b.im = im;
   b.dyn = im > 0.f;
+}
+template <bool kMayBeGround>
+__device__ __forceinline__ void load_local(const Lds& L, int i, const Frame& F, LBody& b) {
+  load_local_g(L, i, kMayBeGround && i == (int)kGround, F, b);
 }
 
 __device__ __forceinline__ void store_local(const Lds& L, int i, const Frame& F, const LBody& b) {
@@ -650,31 +859,77 @@ struct SideRow {
   }
 };
 
+// solver options of a launch: restitution e; cone: the tangent pair projected onto the disc of
+// radius mu lambda_n instead of each tangent clipped; bias: the normal row drives the point's
+// normal velocity to its pre-solve target -e min(0, v_n-) instead of applying (1 + e) to the
+// current velocity
+struct SolveOpts {
+  float e;
+  bool cone, bias;
+};
+
 // the row's new impulse from its relative velocity u and inverse effective mass k:
 // Eq. (lambda_n) with restitution for the normal row, the clipped Eq. (coulomb_pgs) for a tangent
 template <bool kNormal>
-__device__ __forceinline__ float row_lambda(float lam, float u, float k, float bound, float e) {
+__device__ __forceinline__ float row_lambda(float lam, float u, float k, float bound, const SolveOpts& o,
+                                            float target) {
 #pragma clang fp contract(off)
   const float rk = __builtin_amdgcn_rcpf(k);
-  if constexpr (kNormal) return fmaxf(__builtin_fmaf(-((1.f + e) * u), rk, lam), 0.f);
-  else return fminf(fmaxf(__builtin_fmaf(-u, rk, lam), -bound), bound);
+  if constexpr (kNormal) {
+    if (o.bias) return fmaxf(__builtin_fmaf(target - u, rk, lam), 0.f);
+    return fmaxf(__builtin_fmaf(-((1.f + o.e) * u), rk, lam), 0.f);
+  } else {
+    return fminf(fmaxf(__builtin_fmaf(-u, rk, lam), -bound), bound);
+  }
+}
+
+// the tangent pair's unclipped new impulses projected onto the disc of radius b (both lanes of a
+// pair compute it from the same bits)
+__device__ __forceinline__ void disc_project(float& l1, float& l2, float b) {
+#pragma clang fp contract(off)
+  const float s2 = __builtin_fmaf(l1, l1, l2 * l2);
+  if (s2 > b * b) {
+    const float f = b * __builtin_amdgcn_rsqf(s2);
+    l1 *= f;
+    l2 *= f;
+  }
 }
 
 // one row on one lane, both bodies
 template <int K>
 __device__ __forceinline__ void row_single(LBody& A, LBody& B, const float rA[3], const float rB[3], float& lam,
-                                           float bound, float e) {
+                                           float bound, const SolveOpts& o, float target) {
 #pragma clang fp contract(off)
   SideRow<K> ta, tb;
   ta.build(A, rA);
   tb.build(B, rB);
   const float k = ta.kpart(A) + tb.kpart(B);
   const float u = tb.vpart(B) - ta.vpart(A);
-  const float nl = row_lambda<K == 0>(lam, u, k, bound, e);
+  const float nl = row_lambda<K == 0>(lam, u, k, bound, o, target);
   const float dl = nl - lam;
   ta.apply(A, -dl);
   tb.apply(B, dl);
   lam = nl;
+}
+
+// k and the relative velocity of row K on one lane (both bodies), and the impulse dl applied
+template <int K>
+__device__ __forceinline__ void row_ku(const LBody& A, const LBody& B, const float rA[3], const float rB[3], float& k,
+                                       float& u) {
+#pragma clang fp contract(off)
+  SideRow<K> ta, tb;
+  ta.build(A, rA);
+  tb.build(B, rB);
+  k = ta.kpart(A) + tb.kpart(B);
+  u = tb.vpart(B) - ta.vpart(A);
+}
+template <int K>
+__device__ __forceinline__ void row_apply(LBody& A, LBody& B, const float rA[3], const float rB[3], float dl) {
+  SideRow<K> ta, tb;
+  ta.build(A, rA);
+  tb.build(B, rB);
+  ta.apply(A, -dl);
+  tb.apply(B, dl);
 }
 
 // the partner lane's value (lanes 2p and 2p + 1 swap; both must be active)
@@ -686,34 +941,92 @@ __device__ __forceinline__ float pair_swap(float x) {
 // k = k_A + k_B and u = v_B - v_A come out bit for bit as in row_single (a sum does not depend
 // on its order of operands, and -(x - y) = y - x exactly).
 template <int K>
-__device__ __forceinline__ void row_pair(LBody& S, const float r[3], float& lam, float bound, float e, float sg) {
+__device__ __forceinline__ void row_pair(LBody& S, const float r[3], float& lam, float bound, const SolveOpts& o,
+                                         float target, float sg) {
 #pragma clang fp contract(off)
   SideRow<K> t;
   t.build(S, r);
   const float kp = t.kpart(S), vp = t.vpart(S);
   const float k = kp + pair_swap(kp);
   const float u = sg * (vp - pair_swap(vp));
-  const float nl = row_lambda<K == 0>(lam, u, k, bound, e);
+  const float nl = row_lambda<K == 0>(lam, u, k, bound, o, target);
   const float dl = nl - lam;
   t.apply(S, sg * dl);
   lam = nl;
 }
-
-// one point's rows in order: Eq. (lambda_n), then Eq. (coulomb_pgs) on t1 and t2
-__device__ __forceinline__ void solve_point(LBody& A, LBody& B, const float rA[3], const float rB[3], float lam[3],
-                                            float mu, float e) {
-  row_single<0>(A, B, rA, rB, lam[0], 0.f, e);
-  const float bound = mu * lam[0];
-  row_single<1>(A, B, rA, rB, lam[1], bound, e);
-  row_single<2>(A, B, rA, rB, lam[2], bound, e);
+template <int K>
+__device__ __forceinline__ void row_pair_ku(const LBody& S, const float r[3], float sg, float& k, float& u) {
+#pragma clang fp contract(off)
+  SideRow<K> t;
+  t.build(S, r);
+  const float kp = t.kpart(S), vp = t.vpart(S);
+  k = kp + pair_swap(kp);
+  u = sg * (vp - pair_swap(vp));
+}
+template <int K>
+__device__ __forceinline__ void row_pair_apply(LBody& S, const float r[3], float sg, float dl) {
+  SideRow<K> t;
+  t.build(S, r);
+  t.apply(S, sg * dl);
 }
 
-__device__ __forceinline__ void solve_point_pair(LBody& S, const float r[3], float lam[3], float mu, float e,
-                                                 float sg) {
-  row_pair<0>(S, r, lam[0], 0.f, e, sg);
+// the tangent pair of one point on the disc: both rows from the same velocities and with one
+// inverse effective mass (the larger of the two, so that the update points against the slip
+// velocity), the pair of unclipped impulses projected, then both applied
+__device__ __forceinline__ void cone_pair_single(LBody& A, LBody& B, const float rA[3], const float rB[3], float lam[3],
+                                                 float bound) {
+#pragma clang fp contract(off)
+  float k1, u1, k2, u2;
+  row_ku<1>(A, B, rA, rB, k1, u1);
+  row_ku<2>(A, B, rA, rB, k2, u2);
+  const float rk = __builtin_amdgcn_rcpf(fmaxf(k1, k2));
+  float l1 = __builtin_fmaf(-u1, rk, lam[1]);
+  float l2 = __builtin_fmaf(-u2, rk, lam[2]);
+  disc_project(l1, l2, bound);
+  row_apply<1>(A, B, rA, rB, l1 - lam[1]);
+  row_apply<2>(A, B, rA, rB, l2 - lam[2]);
+  lam[1] = l1;
+  lam[2] = l2;
+}
+__device__ __forceinline__ void cone_pair_lanes(LBody& S, const float r[3], float lam[3], float bound, float sg) {
+#pragma clang fp contract(off)
+  float k1, u1, k2, u2;
+  row_pair_ku<1>(S, r, sg, k1, u1);
+  row_pair_ku<2>(S, r, sg, k2, u2);
+  const float rk = __builtin_amdgcn_rcpf(fmaxf(k1, k2));
+  float l1 = __builtin_fmaf(-u1, rk, lam[1]);
+  float l2 = __builtin_fmaf(-u2, rk, lam[2]);
+  disc_project(l1, l2, bound);
+  row_pair_apply<1>(S, r, sg, l1 - lam[1]);
+  row_pair_apply<2>(S, r, sg, l2 - lam[2]);
+  lam[1] = l1;
+  lam[2] = l2;
+}
+
+// one point's rows in order: Eq. (lambda_n), then Eq. (coulomb_pgs) on t1 and t2 (or the pair
+// on the disc)
+__device__ __forceinline__ void solve_point(LBody& A, LBody& B, const float rA[3], const float rB[3], float lam[3],
+                                            float mu, const SolveOpts& o, float target) {
+  row_single<0>(A, B, rA, rB, lam[0], 0.f, o, target);
   const float bound = mu * lam[0];
-  row_pair<1>(S, r, lam[1], bound, e, sg);
-  row_pair<2>(S, r, lam[2], bound, e, sg);
+  if (o.cone) {
+    cone_pair_single(A, B, rA, rB, lam, bound);
+  } else {
+    row_single<1>(A, B, rA, rB, lam[1], bound, o, 0.f);
+    row_single<2>(A, B, rA, rB, lam[2], bound, o, 0.f);
+  }
+}
+
+__device__ __forceinline__ void solve_point_pair(LBody& S, const float r[3], float lam[3], float mu,
+                                                 const SolveOpts& o, float target, float sg) {
+  row_pair<0>(S, r, lam[0], 0.f, o, target, sg);
+  const float bound = mu * lam[0];
+  if (o.cone) {
+    cone_pair_lanes(S, r, lam, bound, sg);
+  } else {
+    row_pair<1>(S, r, lam[1], bound, o, 0.f, sg);
+    row_pair<2>(S, r, lam[2], bound, o, 0.f, sg);
+  }
 }
 
 // what one PGS visit of a manifold reads besides the bodies: its pair, point count, friction
@@ -721,11 +1034,12 @@ __device__ __forceinline__ void solve_point_pair(LBody& S, const float r[3], flo
 // points are unused)
 struct ManPoints {
   float r[12], l[12], n[3], mu;
+  float tb[4];     // restitution targets of the normal rows (with the bias option)
   uint32_t ab;
   int np;
 };
 
-__device__ __forceinline__ void fetch_points(const Lds& L, int m, ManPoints& d) {
+__device__ __forceinline__ void fetch_points(const Lds& L, int m, ManPoints& d, bool bias) {
   d.ab = L.mab[m];
   d.np = (int)(L.mmeta[m] & 15u);
   d.mu = L.mu[L.tw[d.ab >> 16]];
@@ -739,10 +1053,16 @@ __device__ __forceinline__ void fetch_points(const Lds& L, int m, ManPoints& d) 
   }
   const float4 nd = rec[6];
   d.n[0] = nd.x; d.n[1] = nd.y; d.n[2] = nd.z;
+  if (bias) {
+    const float4 tb = rec[7];
+    d.tb[0] = tb.x; d.tb[1] = tb.y; d.tb[2] = tb.z; d.tb[3] = tb.w;
+  } else {
+    d.tb[0] = d.tb[1] = d.tb[2] = d.tb[3] = 0.f;
+  }
 }
 
 // one PGS visit of manifold m with its data already in registers; stores the new impulses
-__device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float e, ManPoints& d) {
+__device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, const SolveOpts& o, ManPoints& d) {
   int a, b;
   Frame F;
   LBody A, B;
@@ -753,7 +1073,7 @@ __device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float e,
     if (j < d.np) {
       const float rA[3] = {d.r[3 * j], d.r[3 * j + 1], d.r[3 * j + 2]};
       const float rB[3] = {rA[0] + dAB[0], rA[1] + dAB[1], rA[2] + dAB[2]};
-      solve_point(A, B, rA, rB, &d.l[3 * j], d.mu, e);
+      solve_point(A, B, rA, rB, &d.l[3 * j], d.mu, o, d.tb[j]);
     }
   }
   store_local(L, a, F, A);
@@ -765,7 +1085,8 @@ __device__ __forceinline__ void solve_manifold_pts(const Lds& L, int m, float e,
 
 // the same visit by a lane pair: lane 2p works body A, lane 2p + 1 body B (the ground: no
 // update); both hold the impulses, the first stores them
-__device__ __forceinline__ void solve_manifold_pair(const Lds& L, int m, float e, ManPoints& d, bool is_b) {
+__device__ __forceinline__ void solve_manifold_pair(const Lds& L, int m, const SolveOpts& o, ManPoints& d,
+                                                    bool is_b) {
   const int a = (int)(d.ab >> 16), b = (int)(d.ab & 0xffffu);
   Frame F;
   make_frame(d.n, F);
@@ -786,7 +1107,7 @@ __device__ __forceinline__ void solve_manifold_pair(const Lds& L, int m, float e
       float r[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) r[k] = is_b ? d.r[3 * j + k] + dAB[k] : d.r[3 * j + k];
-      solve_point_pair(S, r, &d.l[3 * j], d.mu, e, sg);
+      solve_point_pair(S, r, &d.l[3 * j], d.mu, o, d.tb[j], sg);
     }
   }
   store_local(L, me, F, S);
@@ -797,10 +1118,10 @@ __device__ __forceinline__ void solve_manifold_pair(const Lds& L, int m, float e
   }
 }
 
-__device__ __forceinline__ void solve_manifold(const Lds& L, int m, float e) {
+__device__ __forceinline__ void solve_manifold(const Lds& L, int m, const SolveOpts& o) {
   ManPoints d;
-  fetch_points(L, m, d);
-  solve_manifold_pts(L, m, e, d);
+  fetch_points(L, m, d, o.bias);
+  solve_manifold_pts(L, m, o, d);
 }
 
 // A colour of at most nthr / 2 manifolds is worked by lane pairs (pair p = tid / 2 takes
@@ -816,11 +1137,16 @@ __device__ __forceinline__ int colour_first(const Lds& L, int col, int tid, int 
 // thread visits the same manifolds in the same order on every sweep, so the points of its
 // next manifold are fetched from device memory while it solves the current one; one with a
 // single manifold keeps it in registers.  Every thread passes the same sweeps x ncol barriers.
-__device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, int tid, int nthr, float e) {
+// (kVariants false: the literal solver, cone and bias off at compile time, so the default
+// sweep loop carries none of the variants' registers)
+template <bool kVariants>
+__device__ __forceinline__ void pgs_sweeps_impl(const Lds& L, int sweeps, int ncol, int tid, int nthr,
+                                                const SolveOpts& opts) {
+  const SolveOpts o = {opts.e, kVariants && opts.cone, kVariants && opts.bias};
   int first = 0;   // the thread's first colour with a manifold (ncol: none)
   while (first < ncol && colour_first(L, first, tid, nthr) >= L.coloff[first + 1]) ++first;
   ManPoints cur, nxt;
-  if (first < ncol) fetch_points(L, colour_first(L, first, tid, nthr), cur);
+  if (first < ncol) fetch_points(L, colour_first(L, first, tid, nthr), cur, o.bias);
   const bool is_b = tid & 1;
   for (int it = 0; it < sweeps; ++it) {
     for (int col = 0; col < ncol; ++col) {
@@ -833,14 +1159,20 @@ __device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, i
           n2 = colour_first(L, c2, tid, nthr);
         }
         const bool other = n2 != m;
-        if (other) fetch_points(L, n2, nxt);
-        if (paired) solve_manifold_pair(L, m, e, cur, is_b);
-        else solve_manifold_pts(L, m, e, cur);
+        if (other) fetch_points(L, n2, nxt, o.bias);
+        if (paired) solve_manifold_pair(L, m, o, cur, is_b);
+        else solve_manifold_pts(L, m, o, cur);
         if (other) cur = nxt;
       }
       __syncthreads();
     }
   }
+}
+
+__device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, int tid, int nthr,
+                                           const SolveOpts& o) {
+  if (o.cone || o.bias) pgs_sweeps_impl<true>(L, sweeps, ncol, tid, nthr, o);
+  else pgs_sweeps_impl<false>(L, sweeps, ncol, tid, nthr, o);
 }
 
 __device__ __forceinline__ void warm_apply_manifold(const Lds& L, int m) {
@@ -861,37 +1193,75 @@ __device__ __forceinline__ void warm_apply_manifold(const Lds& L, int m) {
   if (b != (int)kGround) store_local(L, b, F, B);
 }
 
-// natural-map residual of one manifold: sum of squares and max |r| over its rows
-__device__ __forceinline__ void residual_manifold(const Lds& L, int m, float mu, float& sum, float& mx) {
-  int a, b;
+// the pair (a, b) of a record opened in its contact frame (b the ground when `ground`)
+__device__ __forceinline__ void pair_open(const Lds& L, int a, int b, bool ground, const float n[3], Frame& F, LBody& A,
+                                          LBody& B, float dAB[3]) {
+  make_frame(n, F);
+  load_local_g(L, a, false, F, A);
+  load_local_g(L, b, ground, F, B);
+  if (!ground) {
+    float d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = L.x[k * L.nbp + a] - L.x[k * L.nbp + b];
+    to_local(F, d, dAB);
+  } else {
+    dAB[0] = dAB[1] = dAB[2] = 0.f;
+  }
+}
+
+// natural-map residual of one pair's record (np points): sum of squares and max |r| over its rows
+__device__ __forceinline__ void residual_rec(const Lds& L, const float* rec, int a, int b, bool ground, int np,
+                                             float mu, const SolveOpts& o, float& sum, float& mx) {
   Frame F;
   LBody A, B;
   float dAB[3];
-  manifold_open(L, m, a, b, F, A, B, dAB);
-  const int np = (int)(L.mmeta[m] & 15u);
+  const float n[3] = {rec[24], rec[25], rec[26]};
+  pair_open(L, a, b, ground, n, F, A, B, dAB);
   sum = 0.f;
   mx = 0.f;
   for (int j = 0; j < np; ++j) {
     float rA[3], rB[3], lam[3];
-    load_point(L, m, j, dAB, rA, rB, lam);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rA[k] = rec[j * 3 + k];
+      rB[k] = rA[k] + dAB[k];
+      lam[k] = rec[12 + j * 3 + k];
+    }
     const float bound = mu * lam[0];
     float res[3];
-    { RowTerms<0> t; t.build(A, B, rA, rB); res[0] = fminf(t.k * lam[0], t.vrel(A, B)); }
     {
-      RowTerms<1> t;
+      RowTerms<0> t;
       t.build(A, B, rA, rB);
-      const float cl = fminf(fmaxf(lam[1] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
-      res[1] = t.k * (lam[1] - cl);
+      const float target = o.bias ? rec[28 + j] : 0.f;
+      res[0] = fminf(t.k * lam[0], t.vrel(A, B) - target);
     }
-    {
-      RowTerms<2> t;
-      t.build(A, B, rA, rB);
-      const float cl = fminf(fmaxf(lam[2] - t.vrel(A, B) * __builtin_amdgcn_rcpf(t.k), -bound), bound);
-      res[2] = t.k * (lam[2] - cl);
+    RowTerms<1> t1;
+    RowTerms<2> t2;
+    t1.build(A, B, rA, rB);
+    t2.build(A, B, rA, rB);
+    const float kt = fmaxf(t1.k, t2.k);
+    const float k1 = o.cone ? kt : t1.k, k2 = o.cone ? kt : t2.k;
+    float cl1 = lam[1] - t1.vrel(A, B) * __builtin_amdgcn_rcpf(k1);
+    float cl2 = lam[2] - t2.vrel(A, B) * __builtin_amdgcn_rcpf(k2);
+    if (o.cone) {
+      disc_project(cl1, cl2, bound);
+    } else {
+      cl1 = fminf(fmaxf(cl1, -bound), bound);
+      cl2 = fminf(fmaxf(cl2, -bound), bound);
     }
+    res[1] = k1 * (lam[1] - cl1);
+    res[2] = k2 * (lam[2] - cl2);
 #pragma unroll
     for (int r = 0; r < 3; ++r) { sum += res[r] * res[r]; mx = fmaxf(mx, fabsf(res[r])); }
   }
+}
+
+// natural-map residual of one manifold: sum of squares and max |r| over its rows
+__device__ __forceinline__ void residual_manifold(const Lds& L, int m, float mu, const SolveOpts& o, float& sum,
+                                                  float& mx) {
+  const uint32_t ab = L.mab[m];
+  const int b = (int)(ab & 0xffffu);
+  residual_rec(L, mdev(L, m), (int)(ab >> 16), b, b == (int)kGround, (int)(L.mmeta[m] & 15u), mu, o, sum, mx);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -964,7 +1334,7 @@ __device__ __forceinline__ void point_features(const Lds& L, int m, int j, float
 // Initial impulses of manifold m from s = network output + previous dimensionless impulses (held
 // in ml), applied like solver impulses: lambda_n = max(0, s_n) |g| dt / k_n,
 // lambda_t = clip(s_t |g| dt / k_t, +-mu lambda_n).
-__device__ __forceinline__ void learned_apply_manifold(const Lds& L, int m, float mu, float gdt) {
+__device__ __forceinline__ void learned_apply_manifold(const Lds& L, int m, float mu, float gdt, bool cone) {
   int a, b;
   Frame F;
   LBody A, B;
@@ -982,8 +1352,13 @@ __device__ __forceinline__ void learned_apply_manifold(const Lds& L, int m, floa
     t2.build(A, B, rA, rB);
     const float ln = fmaxf(y[0], 0.f) * gdt / t0.k;
     const float bound = mu * ln;
-    const float l1 = fminf(fmaxf(y[1] * gdt / t1.k, -bound), bound);
-    const float l2 = fminf(fmaxf(y[2] * gdt / t2.k, -bound), bound);
+    float l1 = y[1] * gdt / t1.k, l2 = y[2] * gdt / t2.k;
+    if (cone) {
+      disc_project(l1, l2, bound);
+    } else {
+      l1 = fminf(fmaxf(l1, -bound), bound);
+      l2 = fminf(fmaxf(l2, -bound), bound);
+    }
     t0.apply(A, B, ln);
     t1.apply(A, B, l1);
     t2.apply(A, B, l2);
@@ -1025,13 +1400,13 @@ __device__ __forceinline__ void record_solution(const Lds& L, int m, float* rec)
 // Each canonical pair's residual terms (pairs first, first + stride, ...); psum and pmax may
 // alias the canonical lists (a pair's entry is read before it is overwritten, by one thread).
 __device__ __forceinline__ void residual_parts(const Lds& L, int nman, int first, int stride, float* psum, float* pmax,
-                                               const uint32_t* only) {
+                                               const uint32_t* only, const SolveOpts& o) {
   for (int p = first; p < nman; p += stride) {
     const int m = L.cpos[p];
     float sum = 0.f, mx = 0.f;
     if (m >= 0) {
       const int t = L.tw[L.mab[m] >> 16];
-      if (!only || only[t]) residual_manifold(L, m, L.mu[t], sum, mx);
+      if (!only || only[t]) residual_manifold(L, m, L.mu[t], o, sum, mx);
     }
     psum[p] = sum;
     pmax[p] = mx;
@@ -1041,9 +1416,9 @@ __device__ __forceinline__ void residual_parts(const Lds& L, int nman, int first
 // The towers' residuals from the pairs' terms (fixed summation order); `parts` false when the
 // terms are already in psum and pmax.
 __device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, int lane, float* psum, float* pmax,
-                                const uint32_t* only, bool parts = true) {
+                                const uint32_t* only, const SolveOpts& o, bool parts = true) {
   if (parts) {
-    residual_parts(L, nman, lane, kWave, psum, pmax, only);
+    residual_parts(L, nman, lane, kWave, psum, pmax, only, o);
     wave_sync();
   }
   if (nt == 1) {
@@ -1083,68 +1458,125 @@ __device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, 
 // Contact manifolds of the canonical pairs p = first, first + stride, ... < nman, written into
 // their colour-sorted slots (points, normal, depth, and the previous step's impulses when kept).
 // Pairs are independent, so any number of threads can share the list.
+// The contact points of colliding pair (i, j) (j the ground when `ground`): lever arms r_A in the
+// contact frame into rec[0..12), the normal (from i to j) and depth; returns the point count and
+// the points' slots (4 bits each).  The ground: Sec. "Narrowphase" reading R18; two boxes: the
+// SAT normal and the silhouette clip (R15, R16), or reference-face clipping (manifold_mode 1).
+template <bool kExt>
+__device__ __forceinline__ int manifold_geometry(const Lds& L, int i, int j, bool ground, int manifold_mode, float* rec,
+                                                 float n[3], float& depth, uint32_t& slots) {
+  const int NB = L.nbp;
+  float t1[3], rA[4][3];
+  uint32_t used = 0u;
+  depth = 0.f;
+  slots = 0u;
+  int npts = 0;
+  float R[9], he[3];
+  body_R(L, i, R);
+  load3(L.he, NB, i, he);
+  if (ground) {
+    // vertices below the ground: the four deepest (ties: lower vertex index), in index order
+    const float xz = L.x[2 * NB + i];
+    float vz[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
+      vz[k] = xz + (R[6] * s0 + R[7] * s1 + R[8] * s2);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int rank = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rank += (vz[q] < 0.f) && (vz[q] < vz[k] || (vz[q] == vz[k] && q < k));
+      if ((vz[k] < 0.f) && rank < 4) {
+        const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
+        const float rx = R[0] * s0 + R[1] * s1 + R[2] * s2;
+        const float ry = R[3] * s0 + R[4] * s1 + R[5] * s2;
+        const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
+        // r_A = (rx, ry, (rz - xz)/2) in the frame n = -z, t1 = x, t2 = -y
+        rec[npts * 3 + 0] = 0.5f * (xz - rz);
+        rec[npts * 3 + 1] = rx;
+        rec[npts * 3 + 2] = -ry;
+        slots |= (uint32_t)k << (4 * npts);
+        depth = fmaxf(depth, -vz[k]);
+        ++npts;
+      }
+    }
+    n[0] = 0.f; n[1] = 0.f; n[2] = -1.f;
+    t1[0] = 1.f; t1[1] = 0.f; t1[2] = 0.f;
+  } else {
+    float RB[9], heB[3], d[3];
+    body_R(L, j, RB);
+    load3(L.he, NB, j, heB);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
+    if (kExt && manifold_mode) {
+      int ax = 0;
+      sat_boxes<true>(R, he, RB, heB, d, n, depth, &ax);   // the narrowphase's inputs: it collides
+      used = manifold_refface(R, he, RB, heB, d, n, ax, t1, rA);
+      if (!used) used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
+    } else {
+      sat_boxes(R, he, RB, heB, d, n, depth);
+      used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+      if ((used >> s2) & 1u) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rec[npts * 3 + k] = rA[s2][k];
+        slots |= (uint32_t)s2 << (4 * npts);
+        ++npts;
+      }
+  }
+  return npts;
+}
+
+// The restitution targets of the pair's normal rows (restitution_bias): rec[28 + q] for its points,
+// -e v_n- from the velocities before any impulse of the step, in the contact frame (n is its first
+// axis), for a point approaching faster than twice |g| dt (a resting contact approaches at about
+// |g| dt per step and does not bounce).
+__device__ __forceinline__ void bias_targets(const Lds& L, int i, int j, bool ground, float* rec, int npts,
+                                             const float n[3], const float g[3], float dt, float e) {
+  const int NB = L.nbp;
+  const float vth = 2.f * sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * dt;
+  Frame F;
+  make_frame(n, F);
+  float tmp[3], vA[3], wA[3], vB[3] = {0.f, 0.f, 0.f}, wB[3] = {0.f, 0.f, 0.f}, dAB[3] = {0.f, 0.f, 0.f};
+  load3(L.v, NB, i, tmp); to_local(F, tmp, vA);
+  load3(L.w, NB, i, tmp); to_local(F, tmp, wA);
+  if (!ground) {
+    load3(L.v, NB, j, tmp); to_local(F, tmp, vB);
+    load3(L.w, NB, j, tmp); to_local(F, tmp, wB);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tmp[k] = L.x[k * NB + i] - L.x[k * NB + j];
+    to_local(F, tmp, dAB);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float tgt = 0.f;
+    if (q < npts) {
+      const float ra[3] = {rec[3 * q], rec[3 * q + 1], rec[3 * q + 2]};
+      const float rb[3] = {ra[0] + dAB[0], ra[1] + dAB[1], ra[2] + dAB[2]};
+      const float vn = (vB[0] + (wB[1] * rb[2] - wB[2] * rb[1])) - (vA[0] + (wA[1] * ra[2] - wA[2] * ra[1]));
+      tgt = vn < -vth ? -e * vn : 0.f;
+    }
+    rec[28 + q] = tgt;
+  }
+}
+
+template <bool kExt>
 __device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a, int first, int stride, int nman,
                                                 bool keep_prev) {
-  const int NB = L.nbp, PC = L.pc;
+  const int PC = L.pc;
   const int nprev = L.scal[4];
   for (int p = first; p < nman; p += stride) {
     const int sidx = L.cpos[p];
     if (sidx < 0) continue;
     const uint32_t code = L.cab[p];
     const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
-    float n[3], t1[3], rA[4][3], depth = 0.f;
-    uint32_t used = 0u, slots = 0u;
-    int npts = 0;
-    float R[9], he[3];
-    body_R(L, i, R);
-    load3(L.he, NB, i, he);
-    if (j == (int)kGround) {
-      // vertices below the ground: the four deepest (ties: lower vertex index), in index order
-      const float xz = L.x[2 * NB + i];
-      float vz[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
-        vz[k] = xz + (R[6] * s0 + R[7] * s1 + R[8] * s2);
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        int rank = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) rank += (vz[q] < 0.f) && (vz[q] < vz[k] || (vz[q] == vz[k] && q < k));
-        if ((vz[k] < 0.f) && rank < 4) {
-          const float s0 = (k & 1) ? he[0] : -he[0], s1 = (k & 2) ? he[1] : -he[1], s2 = (k & 4) ? he[2] : -he[2];
-          const float rx = R[0] * s0 + R[1] * s1 + R[2] * s2;
-          const float ry = R[3] * s0 + R[4] * s1 + R[5] * s2;
-          const float rz = R[6] * s0 + R[7] * s1 + R[8] * s2;
-          // r_A = (rx, ry, (rz - xz)/2) in the frame n = -z, t1 = x, t2 = -y
-          mdev(L, sidx)[npts * 3 + 0] = 0.5f * (xz - rz);
-          mdev(L, sidx)[npts * 3 + 1] = rx;
-          mdev(L, sidx)[npts * 3 + 2] = -ry;
-          slots |= (uint32_t)k << (4 * npts);
-          depth = fmaxf(depth, -vz[k]);
-          ++npts;
-        }
-      }
-      n[0] = 0.f; n[1] = 0.f; n[2] = -1.f;
-      t1[0] = 1.f; t1[1] = 0.f; t1[2] = 0.f;
-    } else {
-      float RB[9], heB[3], d[3];
-      body_R(L, j, RB);
-      load3(L.he, NB, j, heB);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) d[k] = L.x[k * NB + j] - L.x[k * NB + i];
-      sat_boxes(R, he, RB, heB, d, n, depth);   // same inputs as the narrowphase: same normal
-      used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2)
-        if ((used >> s2) & 1u) {
-#pragma unroll
-          for (int k = 0; k < 3; ++k) mdev(L, sidx)[npts * 3 + k] = rA[s2][k];
-          slots |= (uint32_t)s2 << (4 * npts);
-          ++npts;
-        }
-    }
+    float n[3], depth;
+    uint32_t slots;
+    const int npts = manifold_geometry<kExt>(L, i, j, j == (int)kGround, a.manifold_mode, mdev(L, sidx), n, depth, slots);
     // warm start: previous step's impulses of the same (pair, slot) if the normal barely turned
     int found = -1;
     if (keep_prev && nprev > 0) {
@@ -1177,6 +1609,7 @@ __device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a,
       mdev(L, sidx)[12 + q * 3 + 1] = l1;
       mdev(L, sidx)[12 + q * 3 + 2] = l2;
     }
+    if (kExt && a.restitution_bias) bias_targets(L, i, j, j == (int)kGround, mdev(L, sidx), npts, n, a.g, a.dt, a.restitution);
     L.mab[sidx] = code;
     L.mmeta[sidx] = (uint32_t)npts | (slots << 12);
     mdev(L, sidx)[27] = depth;
@@ -1187,6 +1620,69 @@ __device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a,
     atomicAdd(&L.tcnt[ti * 4 + 1], 1u);
     atomicAdd(&L.tcnt[ti * 4 + 2], (uint32_t)npts);
     atomicAdd(&L.tpts[ti], npts);
+  }
+}
+
+// Semi-implicit integration of dynamic body i over dt (Eq. (newton_euler), Eq. (quat_int), R1, R4):
+// x += dt v; q' = normalise(q + dt/2 [0, w] q); w' = I_w(q')^-1 I_w(q) w.  Returns false when the
+// new state is not finite (it is stored all the same).
+__device__ __forceinline__ bool integrate_body(const Lds& L, int i, float dt) {
+  const int NB = L.nbp;
+  float xv[3], vv[3], wv[3], R[9], Ib[3], iIb[3];
+  load3(L.x, NB, i, xv);
+  load3(L.v, NB, i, vv);
+  load3(L.w, NB, i, wv);
+  body_R(L, i, R);
+  load3(L.invI, NB, i, iIb);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { xv[k] += dt * vv[k]; Ib[k] = 1.f / iIb[k]; }
+  // L = R Ib R^T w
+  float bw[3], Lw[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) bw[k] = (R[k] * wv[0] + R[3 + k] * wv[1] + R[6 + k] * wv[2]) * Ib[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) Lw[r] = R[3 * r] * bw[0] + R[3 * r + 1] * bw[1] + R[3 * r + 2] * bw[2];
+  float qw = L.q[i], qx = L.q[NB + i], qy = L.q[2 * NB + i], qz = L.q[3 * NB + i];
+  const float hd = 0.5f * dt;
+  const float dw = -(wv[0] * qx + wv[1] * qy + wv[2] * qz);
+  const float dx = wv[0] * qw + (wv[1] * qz - wv[2] * qy);
+  const float dy = wv[1] * qw + (wv[2] * qx - wv[0] * qz);
+  const float dz = wv[2] * qw + (wv[0] * qy - wv[1] * qx);
+  qw += hd * dw; qx += hd * dx; qy += hd * dy; qz += hd * dz;
+  const float il = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= il; qx *= il; qy *= il; qz *= il;
+  quat_rot(qw, qx, qy, qz, R);
+  float bl[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) bl[k] = (R[k] * Lw[0] + R[3 + k] * Lw[1] + R[6 + k] * Lw[2]) * iIb[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) wv[r] = R[3 * r] * bl[0] + R[3 * r + 1] * bl[1] + R[3 * r + 2] * bl[2];
+  bool finite = isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) finite = finite && isfinite(xv[k]) && isfinite(vv[k]) && isfinite(wv[k]);
+  store3(L.x, NB, i, xv);
+  store3(L.w, NB, i, wv);
+  L.q[i] = qw; L.q[NB + i] = qx; L.q[2 * NB + i] = qy; L.q[3 * NB + i] = qz;
+  return finite;
+}
+
+// Baumgarte position correction of one colliding pair (Eq. (baumgarte), reading R19), from its
+// record's depth and normal: x_A -= beta m_A^-1 c n, x_B += beta m_B^-1 c n with
+// c = max(0, depth - slop) / (m_A^-1 + m_B^-1), dynamic bodies only.
+__device__ __forceinline__ void baumgarte_pair(const Lds& L, int i, int j, bool ground, const float* rec, float beta,
+                                               float slop) {
+  const int NB = L.nbp;
+  const bool di = (L.flag[i] & kDynamic) != 0;
+  const bool dj = !ground && (L.flag[j] & kDynamic);
+  const float ia = di ? L.invm[i] : 0.f, ib = dj ? L.invm[j] : 0.f;
+  float corr = rec[27] - slop;
+  if (ia + ib <= 0.f || corr <= 0.f) return;
+  corr /= (ia + ib);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float nk = rec[24 + k];
+    if (di) L.x[k * NB + i] -= beta * ia * corr * nk;
+    if (dj) L.x[k * NB + j] += beta * ib * corr * nk;
   }
 }
 
@@ -1532,7 +2028,9 @@ constexpr int step_threads() { return kGlobal ? (kLearned ? kLearnedIslandWaves 
 // kHot (packs in device memory): the body arrays of the serial walks are in LDS too.  It is a
 // template parameter so that every access has one known address space (a pointer that may be
 // either compiles to flat instructions, which are as slow as device memory even on LDS).
-template <bool kLearned, bool kGlobal, bool kHot>
+// kExt: the solver variants (disc friction, restitution targets, reference-face clipping) and the
+// episode criteria are compiled in; the default plain kernel carries none of their registers.
+template <bool kLearned, bool kGlobal, bool kHot, bool kExt>
 __global__ void __launch_bounds__((step_threads<kLearned, kGlobal>()))
 __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   constexpr int kThreads = step_threads<kLearned, kGlobal>();
@@ -1552,13 +2050,14 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       const bool learned_h = kLearned && a.warm_start == 2;
       const int slot0h = a.pack_slot0[pkh];
       const float gdt_h = sqrtf(a.g[0] * a.g[0] + a.g[1] * a.g[1] + a.g[2] * a.g[2]) * a.dt;
+      const SolveOpts opts_h = {a.restitution, kExt && a.friction_cone != 0, kExt && a.restitution_bias != 0};
       for (int s = 0; s < a.n_steps; ++s)
         for (int sub = 0; sub < a.n_sub; ++sub) {
           __syncthreads();
           island_walk_rounds(L, a.margin, nbh, threadIdx.x / kWave, kThreads / kWave, threadIdx.x % kWave);
           __syncthreads();
           __syncthreads();
-          build_manifolds(L, a, threadIdx.x, kThreads, L.scal[5], keep_prev);
+          build_manifolds<kExt>(L, a, threadIdx.x, kThreads, L.scal[5], keep_prev);
           __syncthreads();
           if constexpr (kLearned) {
             const bool rec_h = a.feat_out != nullptr && s == a.n_steps - 1 && sub == a.n_sub - 1;
@@ -1571,12 +2070,12 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
             }
           }
           __syncthreads();
-          pgs_sweeps(L, learned_h ? a.mlp_iters : a.iters, L.scal[2], threadIdx.x, kThreads, a.restitution);
+          pgs_sweeps(L, learned_h ? a.mlp_iters : a.iters, L.scal[2], threadIdx.x, kThreads, opts_h);
           __syncthreads();
           if (!learned_h) {
             __syncthreads();
             residual_parts(L, L.scal[5], threadIdx.x, kThreads, reinterpret_cast<float*>(L.cab),
-                           reinterpret_cast<float*>(L.cpos), nullptr);
+                           reinterpret_cast<float*>(L.cpos), nullptr, opts_h);
             __syncthreads();
           }
         }
@@ -1627,7 +2126,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     L.mu[t] = a.tower_mu[gt0 + t];
     // bit 1: non-finite state (held); bit 2: episode done (held); bit 4: collapse declared
     uint32_t fz = a.tower_frozen[gt0 + t] ? 1u : 0u;
-    if (a.ep_state) {
+    if (kExt && a.ep_state) {
       const uint32_t ef = a.ep_state[(size_t)(gt0 + t) * kEpisodeWords + kEpFlags];
       fz |= ((ef & kEpDone) ? 2u : 0u) | ((ef & kEpCollapsed) ? 4u : 0u);
     }
@@ -1669,9 +2168,25 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     }
   }
   wave_sync();
+  // a tower with a non-finite body (state set by the host) is frozen from the first step on
+  for (int i = lane; i < nb; i += kWave) {
+    if (!(L.flag[i] & kActive)) continue;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      finite = finite && isfinite(L.x[k * NB + i]) && isfinite(L.v[k * NB + i]) && isfinite(L.w[k * NB + i]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) finite = finite && isfinite(L.q[k * NB + i]);
+    if (!finite) {
+      atomicOr(&L.tfz[L.tw[i]], 1u);
+      atomicOr((uint32_t*)&L.scal[3], kErrNan);
+    }
+  }
+  wave_sync();
   timer.mark(L, lane, 0);
 
   const float dt = a.dt, e = a.restitution;
+  const SolveOpts opts = {e, kExt && a.friction_cone != 0, kExt && a.restitution_bias != 0};
   for (int s = 0; s < a.n_steps; ++s) {
     const int64_t step = a.step0 + s;
     for (int r = lane; r < np; r += kWave)
@@ -1683,22 +2198,9 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     wave_sync();
     for (int sub = 0; sub < a.n_sub; ++sub) {
       const bool last = (s == a.n_steps - 1) && (sub == a.n_sub - 1);
-      // ---- a tower with a non-finite body is frozen: its bodies are held (neither move nor
-      // collide) and keep their state until the host sets a new one ----
-      for (int i = lane; i < nb; i += kWave) {
-        if (!(L.flag[i] & kActive)) continue;
-        bool finite = true;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          finite = finite && isfinite(L.x[k * NB + i]) && isfinite(L.v[k * NB + i]) && isfinite(L.w[k * NB + i]);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) finite = finite && isfinite(L.q[k * NB + i]);
-        if (!finite) {
-          atomicOr(&L.tfz[L.tw[i]], 1u);
-          atomicOr((uint32_t*)&L.scal[3], kErrNan);
-        }
-      }
-      wave_sync();
+      // ---- the bodies of a frozen tower (non-finite state, found at the launch's start or by
+      // the integration) or of an episode at rest are held: they neither move nor collide and keep
+      // their state ----
       for (int i = lane; i < nb; i += kWave) {
         const uint32_t f = L.flag[i];
         if ((f & kActive) && (L.tfz[L.tw[i]] & 3u)) L.flag[i] = (f & ~kActive) | kHeld;
@@ -2064,10 +2566,10 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       if constexpr (kThreads > kWave) {
         L.scal[5] = nman;
         __syncthreads();
-        build_manifolds(L, a, threadIdx.x, kThreads, nman, keep_prev);
+        build_manifolds<kExt>(L, a, threadIdx.x, kThreads, nman, keep_prev);
         __syncthreads();
       } else {
-        build_manifolds(L, a, lane, kWave, nman, keep_prev);
+        build_manifolds<kExt>(L, a, lane, kWave, nman, keep_prev);
         wave_sync();
       }
       timer.mark(L, lane, 4);
@@ -2119,21 +2621,21 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
           const float gdt = sqrtf(a.g[0] * a.g[0] + a.g[1] * a.g[1] + a.g[2] * a.g[2]) * dt;
           for (int col = 0; col < ncol; ++col) {
             for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave)
-              learned_apply_manifold(L, m, L.mu[L.tw[L.mab[m] >> 16]], gdt);
+              learned_apply_manifold(L, m, L.mu[L.tw[L.mab[m] >> 16]], gdt, opts.cone);
             wave_sync();
           }
           sweeps = a.mlp_iters;
         }
       }
       __syncthreads();   // the helper waves (if any) enter the sweeps with this wave
-      pgs_sweeps(L, sweeps, ncol, threadIdx.x, kThreads, e);
+      pgs_sweeps(L, sweeps, ncol, threadIdx.x, kThreads, opts);
       __syncthreads();
       timer.mark(L, lane, 5);
 
       // ---- learned warm start: residual, and the plain solve again for towers above tau ----
       if constexpr (kLearned) {
         if (learned) {
-          tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, nullptr);
+          tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, nullptr, opts);
           wave_sync();
           int any = 0;
           for (int t = lane; t < nt; t += kWave) {
@@ -2160,14 +2662,14 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
               for (int col = 0; col < ncol; ++col) {
                 for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
                   const int t = L.tw[L.mab[m] >> 16];
-                  if (L.tfb[t]) solve_manifold(L, m, e);
+                  if (L.tfb[t]) solve_manifold(L, m, opts);
                 }
                 wave_sync();
               }
             }
             for (int t = lane; t < nt; t += kWave)
               if (L.tfb[t]) { L.tfc[2 * t] += 1u; L.tfc[2 * t + 1] += (uint32_t)L.tpts[t]; }
-            tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, L.tfb);
+            tower_residuals(L, nman, nt, lane, L.rpart, L.rpart + PC, L.tfb, opts);
           }
           wave_sync();
           timer.mark(L, lane, 7);
@@ -2235,11 +2737,11 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
         if constexpr (kThreads > kWave) {
           // an island's helper waves join in the pairs' terms
           __syncthreads();
-          residual_parts(L, nman, threadIdx.x, kThreads, psum, pmax, nullptr);
+          residual_parts(L, nman, threadIdx.x, kThreads, psum, pmax, nullptr, opts);
           __syncthreads();
-          tower_residuals(L, nman, nt, lane, psum, pmax, nullptr, false);
+          tower_residuals(L, nman, nt, lane, psum, pmax, nullptr, opts, false);
         } else {
-          tower_residuals(L, nman, nt, lane, psum, pmax, nullptr);
+          tower_residuals(L, nman, nt, lane, psum, pmax, nullptr, opts);
         }
         timer.mark(L, lane, 7);
       }
@@ -2248,42 +2750,10 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       for (int i = lane; i < nb; i += kWave) {
         const uint32_t f = L.flag[i];
         if ((f & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
-        float xv[3], vv[3], wv[3], R[9], Ib[3], iIb[3];
-        load3(L.x, NB, i, xv);
-        load3(L.v, NB, i, vv);
-        load3(L.w, NB, i, wv);
-        body_R(L, i, R);
-        load3(L.invI, NB, i, iIb);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) { xv[k] += dt * vv[k]; Ib[k] = 1.f / iIb[k]; }
-        // L = R Ib R^T w
-        float bw[3], Lw[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) bw[k] = (R[k] * wv[0] + R[3 + k] * wv[1] + R[6 + k] * wv[2]) * Ib[k];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) Lw[r] = R[3 * r] * bw[0] + R[3 * r + 1] * bw[1] + R[3 * r + 2] * bw[2];
-        float qw = L.q[i], qx = L.q[NB + i], qy = L.q[2 * NB + i], qz = L.q[3 * NB + i];
-        const float hd = 0.5f * dt;
-        const float dw = -(wv[0] * qx + wv[1] * qy + wv[2] * qz);
-        const float dx = wv[0] * qw + (wv[1] * qz - wv[2] * qy);
-        const float dy = wv[1] * qw + (wv[2] * qx - wv[0] * qz);
-        const float dz = wv[2] * qw + (wv[0] * qy - wv[1] * qx);
-        qw += hd * dw; qx += hd * dx; qy += hd * dy; qz += hd * dz;
-        const float il = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-        qw *= il; qx *= il; qy *= il; qz *= il;
-        quat_rot(qw, qx, qy, qz, R);
-        float bl[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) bl[k] = (R[k] * Lw[0] + R[3 + k] * Lw[1] + R[6 + k] * Lw[2]) * iIb[k];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) wv[r] = R[3 * r] * bl[0] + R[3 * r + 1] * bl[1] + R[3 * r + 2] * bl[2];
-        bool finite = isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) finite = finite && isfinite(xv[k]) && isfinite(vv[k]) && isfinite(wv[k]);
-        if (!finite) atomicOr((uint32_t*)&L.scal[3], kErrNan);
-        store3(L.x, NB, i, xv);
-        store3(L.w, NB, i, wv);
-        L.q[i] = qw; L.q[NB + i] = qx; L.q[2 * NB + i] = qy; L.q[3 * NB + i] = qz;
+        if (!integrate_body(L, i, dt)) {
+          atomicOr((uint32_t*)&L.scal[3], kErrNan);
+          atomicOr(&L.tfz[L.tw[i]], 1u);   // frozen from the next substep on
+        }
       }
       wave_sync();
       timer.mark(L, lane, 8);
@@ -2291,19 +2761,8 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       for (int col = 0; col < ncol; ++col) {
         for (int m = L.coloff[col] + lane; m < L.coloff[col + 1]; m += kWave) {
           const uint32_t ab = L.mab[m];
-          const int i = (int)(ab >> 16), j = (int)(ab & 0xffffu);
-          const bool di = (L.flag[i] & kDynamic) != 0;
-          const bool dj = j != (int)kGround && (L.flag[j] & kDynamic);
-          const float ia = di ? L.invm[i] : 0.f, ib = dj ? L.invm[j] : 0.f;
-          float corr = mdev(L, m)[27] - a.slop;
-          if (ia + ib <= 0.f || corr <= 0.f) continue;
-          corr /= (ia + ib);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const float nk = mdev(L, m)[24 + k];
-            if (di) L.x[k * NB + i] -= a.beta * ia * corr * nk;
-            if (dj) L.x[k * NB + j] += a.beta * ib * corr * nk;
-          }
+          const int j = (int)(ab & 0xffffu);
+          baumgarte_pair(L, (int)(ab >> 16), j, j == (int)kGround, mdev(L, m), a.beta, a.slop);
         }
         wave_sync();
       }
@@ -2325,7 +2784,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     wave_sync();
     // ---- episode criteria at the end of the step (the pack's manifold block is free scratch
     // until the next step's manifolds) ----
-    if (a.ep_state) {
+    if (kExt && a.ep_state) {
       episode_update(L, a, gt0, gb0, nt, lane, step, L.md);
       wave_sync();
     }
@@ -2390,6 +2849,764 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   if (a.phase_cycles && lane < kPhases) atomicAdd(&a.phase_cycles[lane], L.cyc[lane]);
 }
 
+// ------------------------------------------------------------------------------------------------
+// Islands stepped by the whole GPU (Sec. "Discussion and Implications for Anastylosis": site-scale
+// walls).  One cooperative launch runs every step; its phases are separated by grid-wide barriers
+// and every workgroup passes the same barriers in the same order (all loop bounds below are
+// uniform: launch parameters or scalars read after a barrier).  Body indices are 32-bit (the
+// ground is -1).  The stages are those of a pack, grid-wide:
+//   forces, frames -> uniform-grid broadphase (cells of the largest AABB plus the margin, 27
+//   neighbour cells, each body's candidates j > i sorted, the ground last: the canonical list with
+//   no per-body cap) -> SAT -> compaction -> partitioned greedy colouring (four passes: inside
+//   partitions of `partition` bodies, then between neighbouring partitions even / odd, then the
+//   rest, each pass in canonical order; one thread per partition or partition pair) -> colour sort
+//   -> manifolds -> PGS colour by colour -> outputs, residual -> integration -> Baumgarte colour
+//   by colour -> withdrawal at the end of a step.
+// ------------------------------------------------------------------------------------------------
+namespace mega {
+
+enum {
+  sFrozen = 0, sErr, sNcand, sNman, sNcol, sCand, sMans, sPtsAll,
+  sLo = 16, sHi = 19, sHmax = 22,
+  sColOff = 32,          // 65 words
+  sColCnt = 100,         // 64 words
+  sColCur = 168          // 64 words
+};
+
+__device__ __forceinline__ uint32_t ford(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float funord(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ __forceinline__ Lds view(const MegaArgs& a) {
+  Lds L{};
+  const int nb = a.nb;
+  float* p = a.body;
+  L.x = p; L.q = p + 3 * nb; L.v = p + 7 * nb; L.w = p + 10 * nb; L.he = p + 13 * nb;
+  L.invm = p + 16 * nb; L.invI = p + 17 * nb; L.Iw = p + 20 * nb; L.hm = p + 26 * nb;
+  L.flag = a.ubody;
+  L.tw = reinterpret_cast<int32_t*>(a.ubody + nb);
+  L.nbp = nb;
+  L.pc = 0;
+  return L;
+}
+
+// block-wide sums (and a second sum) through LDS; every thread gets the results
+__device__ __forceinline__ void block_sum2(int32_t* sh, int32_t* sh2, int& x, int& y) {
+  sh[threadIdx.x] = x;
+  sh2[threadIdx.x] = y;
+  __syncthreads();
+  for (int d = kMegaThreads / 2; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) {
+      sh[threadIdx.x] += sh[threadIdx.x + d];
+      sh2[threadIdx.x] += sh2[threadIdx.x + d];
+    }
+    __syncthreads();
+  }
+  x = sh[0];
+  y = sh2[0];
+  __syncthreads();
+}
+
+// Exclusive prefix sums of v[0, n) in place over the whole grid; returns the total.  Thread t
+// scans the run [t per, (t + 1) per); the workgroups' sums go through ired (one barrier inside).
+// The caller passes a barrier before anyone reads v.
+__device__ int grid_scan(cooperative_groups::grid_group& grid, int32_t* v, int n, int32_t* ired, int32_t* sh,
+                         int32_t* sh2) {
+  const int T = (int)gridDim.x * kMegaThreads;
+  const int gt = (int)blockIdx.x * kMegaThreads + (int)threadIdx.x;
+  const int per = (n + T - 1) / T;
+  const int lo = min(n, gt * per), hi = min(n, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += v[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int d = 1; d < kMegaThreads; d <<= 1) {
+    const int t = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const int incl = sh[threadIdx.x];
+  if (threadIdx.x == kMegaThreads - 1) ired[blockIdx.x] = incl;
+  __syncthreads();
+  grid.sync();
+  int before = 0, total = 0;
+  for (int b = (int)threadIdx.x; b < (int)gridDim.x; b += kMegaThreads) {
+    const int x = ired[b];
+    total += x;
+    if (b < (int)blockIdx.x) before += x;
+  }
+  block_sum2(sh, sh2, before, total);
+  int run = before + incl - s;
+  for (int i = lo; i < hi; ++i) {
+    const int c = v[i];
+    v[i] = run;
+    run += c;
+  }
+  return total;
+}
+
+// the uniform grid of the active bodies' centres: origin, cell size and cells per axis (the same
+// on every thread: read from the scalars after a barrier)
+struct Grid {
+  float lo[3], h;
+  int n[3];
+  __device__ __forceinline__ int cell_of(const float x[3]) const {
+    int c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = min(n[k] - 1, max(0, (int)floorf((x[k] - lo[k]) / h)));
+    return (c[2] * n[1] + c[1]) * n[0] + c[0];
+  }
+};
+
+__device__ __forceinline__ Grid make_grid(const int32_t* S, float margin, int cap) {
+  Grid G;
+  float hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    G.lo[k] = funord((uint32_t)S[sLo + k]);
+    hi[k] = funord((uint32_t)S[sHi + k]);
+    if (!(hi[k] >= G.lo[k])) { G.lo[k] = 0.f; hi[k] = 0.f; }   // no active body
+  }
+  // two bodies whose AABBs (with the margin) overlap are at most this far apart on every axis
+  G.h = fmaxf(2.f * funord((uint32_t)S[sHmax]) + margin, 1e-6f);
+  bool fits = false;
+  for (int it = 0; it < 16 && !fits; ++it) {
+    double total = 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      G.n[k] = (int)fminf(floorf((hi[k] - G.lo[k]) / G.h) + 1.f, 1.0e6f);
+      total *= (double)G.n[k];
+    }
+    fits = total <= (double)cap;
+    if (!fits) G.h *= (float)fmax(1.01, cbrt(total / (double)cap) * 1.01);
+  }
+  if (!fits) {
+    // one cell (every pair is tested): correct at any size
+    G.n[0] = G.n[1] = G.n[2] = 1;
+    G.h = 3.0e38f;
+  }
+  return G;
+}
+
+// greedy first fit of canonical pair m = (a, b) over the colour masks of its dynamic bodies
+__device__ __forceinline__ void colour_pair(int m, int a, int b, const uint32_t* flag, uint32_t* mlo, uint32_t* mhi,
+                                            int32_t* col_of, int32_t* S) {
+  const bool da = (flag[a] & kDynamic) != 0, db = b >= 0 && (flag[b] & kDynamic);
+  uint64_t u = 0ull;
+  if (da) u |= (uint64_t)mlo[a] | ((uint64_t)mhi[a] << 32);
+  if (db) u |= (uint64_t)mlo[b] | ((uint64_t)mhi[b] << 32);
+  int col = -1;
+  if (u != ~0ull) {
+    col = __ffsll((unsigned long long)~u) - 1;
+    const uint64_t bit = 1ull << col;
+    if (da) { mlo[a] |= (uint32_t)bit; mhi[a] |= (uint32_t)(bit >> 32); }
+    if (db) { mlo[b] |= (uint32_t)bit; mhi[b] |= (uint32_t)(bit >> 32); }
+    atomicAdd(&S[sColCnt + col], 1);
+  } else {
+    atomicOr(&S[sErr], (int)kErrCol);
+  }
+  col_of[m] = col;
+}
+
+// one PGS visit of the record at `rec` (pair a, b; b < 0: the ground), one thread
+__device__ __forceinline__ void solve_rec(const Lds& L, float* rec, int a, int b, int np, float mu,
+                                          const SolveOpts& o) {
+  float r[12], l[12], tb[4];
+  const float4* r4 = reinterpret_cast<const float4*>(rec);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float4 x = r4[c], y = r4[3 + c];
+    r[4 * c] = x.x; r[4 * c + 1] = x.y; r[4 * c + 2] = x.z; r[4 * c + 3] = x.w;
+    l[4 * c] = y.x; l[4 * c + 1] = y.y; l[4 * c + 2] = y.z; l[4 * c + 3] = y.w;
+  }
+  const float4 nd = r4[6], t4 = r4[7];
+  const float n[3] = {nd.x, nd.y, nd.z};
+  tb[0] = o.bias ? t4.x : 0.f; tb[1] = o.bias ? t4.y : 0.f; tb[2] = o.bias ? t4.z : 0.f; tb[3] = o.bias ? t4.w : 0.f;
+  const bool ground = b < 0;
+  Frame F;
+  LBody A, B;
+  float dAB[3];
+  pair_open(L, a, ground ? 0 : b, ground, n, F, A, B, dAB);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < np) {
+      const float rA[3] = {r[3 * j], r[3 * j + 1], r[3 * j + 2]};
+      const float rB[3] = {rA[0] + dAB[0], rA[1] + dAB[1], rA[2] + dAB[2]};
+      solve_point(A, B, rA, rB, &l[3 * j], mu, o, tb[j]);
+    }
+  }
+  store_local(L, a, F, A);
+  if (!ground) store_local(L, b, F, B);
+  float4* w4 = reinterpret_cast<float4*>(rec);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w4[3 + c] = make_float4(l[4 * c], l[4 * c + 1], l[4 * c + 2], l[4 * c + 3]);
+}
+
+}  // namespace mega
+
+__global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
+  namespace cg = cooperative_groups;
+  using namespace mega;
+  cg::grid_group grid = cg::this_grid();
+  __shared__ int32_t sh[kMegaThreads], sh2[kMegaThreads];
+  __shared__ float shf[kMegaThreads], shf2[kMegaThreads];
+  const int NB = a.nb, CAP = a.cap, CC = a.cand_cap;
+  const int gt = (int)blockIdx.x * kMegaThreads + (int)threadIdx.x;
+  const int GS = (int)gridDim.x * kMegaThreads;
+  const Lds L = view(a);
+  int32_t* const S = a.scal;
+  uint32_t* const mlo = a.ubody + 2 * NB;
+  uint32_t* const mhi = a.ubody + 3 * NB;
+  int32_t* const cellof = reinterpret_cast<int32_t*>(a.ubody + 4 * NB);
+  int32_t* const ccount = reinterpret_cast<int32_t*>(a.ubody + 5 * NB);   // counts, then offsets
+  int32_t* const cellbody = reinterpret_cast<int32_t*>(a.ubody + 7 * NB);
+  int32_t* const cstart = a.cells;                     // counts, then first body of each cell
+  int32_t* const cfill = a.cells + a.ncell_cap + 1;
+  uint32_t* const ca = a.cand;
+  uint32_t* const cb = a.cand + CC;
+  int32_t* const chit = reinterpret_cast<int32_t*>(a.cand + 2 * CC);
+  int32_t* const man_a = a.man;
+  int32_t* const man_b = a.man + CC;
+  int32_t* const man_col = a.man + 2 * CC;
+  int32_t* const man_slot = a.man + 3 * CC;
+  int32_t* const s_a = a.man + 4 * CC;
+  int32_t* const s_b = a.man + 5 * CC;
+  uint32_t* const s_meta = reinterpret_cast<uint32_t*>(a.man + 6 * CC);
+  int32_t* const far = a.part + a.nparts + 1;
+  const float dt = a.dt;
+  const SolveOpts opts = {a.restitution, a.friction_cone != 0, a.restitution_bias != 0};
+  const int PS = a.partition;
+
+  // ---- load the island (inverse mass and inertia of Eq. (inertia) with the full sizes) ----
+  for (int i = gt; i < NB; i += GS) {
+    const int g = a.g0 + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      L.x[k * NB + i] = a.x[k * CAP + g];
+      L.v[k * NB + i] = a.v[k * CAP + g];
+      L.w[k * NB + i] = a.w[k * CAP + g];
+      L.he[k * NB + i] = a.he[k * CAP + g];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.q[k * NB + i] = a.q[k * CAP + g];
+    const float m = a.mass[g];
+    const float l = 2.f * a.he[g], wd = 2.f * a.he[CAP + g], hh = 2.f * a.he[2 * CAP + g];
+    const bool dyn = m > 0.f;
+    L.invm[i] = dyn ? 1.f / m : 0.f;
+    L.invI[i] = dyn ? 1.f / (m / 12.f * (wd * wd + hh * hh)) : 0.f;
+    L.invI[NB + i] = dyn ? 1.f / (m / 12.f * (l * l + hh * hh)) : 0.f;
+    L.invI[2 * NB + i] = dyn ? 1.f / (m / 12.f * (l * l + wd * wd)) : 0.f;
+    L.flag[i] = a.flags[g];
+    L.tw[i] = 0;
+    if (!dyn) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { L.v[k * NB + i] = 0.f; L.w[k * NB + i] = 0.f; }
+    }
+  }
+  if (gt == 0) {
+    S[sFrozen] = a.tower_frozen[a.tslot] ? 1 : 0;
+    S[sErr] = 0;
+    S[sCand] = 0; S[sMans] = 0; S[sPtsAll] = 0;
+    S[sNcol] = 0;
+  }
+  grid.sync();
+  // a non-finite state freezes the island from the first step on
+  for (int i = gt; i < NB; i += GS) {
+    if (!(L.flag[i] & kActive)) continue;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      finite = finite && isfinite(L.x[k * NB + i]) && isfinite(L.v[k * NB + i]) && isfinite(L.w[k * NB + i]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) finite = finite && isfinite(L.q[k * NB + i]);
+    if (!finite) {
+      atomicOr(&S[sFrozen], 1);
+      atomicOr(&S[sErr], (int)kErrNan);
+    }
+  }
+  grid.sync();
+
+  for (int s = 0; s < a.n_steps; ++s) {
+    const int64_t step = a.step0 + s;
+    for (int r = gt; r < a.np; r += GS) {
+      const int row = a.p0 + r;
+      if ((int64_t)a.push_start[row] == step) {
+        const int b = a.push_body[row] - a.g0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.push_x0[3 * row + k] = L.x[k * NB + b];
+      }
+    }
+    grid.sync();
+    for (int sub = 0; sub < a.n_sub; ++sub) {
+      if (S[sFrozen]) continue;   // uniform: written before the last barrier only
+      const bool last = (s == a.n_steps - 1) && (sub == a.n_sub - 1);
+      // ---- 1. external forces and pushes; 2. frames; colour masks cleared ----
+      for (int i = gt; i < NB; i += GS) {
+        const uint32_t f = L.flag[i];
+        const bool moving = (f & (kActive | kDynamic)) == (kActive | kDynamic);
+        if (moving) {
+          float vv[3];
+          load3(L.v, NB, i, vv);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) vv[k] += dt * a.g[k];
+          store3(L.v, NB, i, vv);
+        }
+        float R[9];
+        body_R(L, i, R);
+        const float he0 = L.he[i], he1 = L.he[NB + i], he2 = L.he[2 * NB + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          L.hm[k * NB + i] = fabsf(R[3 * k]) * he0 + fabsf(R[3 * k + 1]) * he1 + fabsf(R[3 * k + 2]) * he2;
+        float d[3];
+        if (moving) load3(L.invI, NB, i, d);
+        else d[0] = d[1] = d[2] = 0.f;
+        L.Iw[i] = R[0] * d[0] * R[0] + R[1] * d[1] * R[1] + R[2] * d[2] * R[2];
+        L.Iw[NB + i] = R[3] * d[0] * R[3] + R[4] * d[1] * R[4] + R[5] * d[2] * R[5];
+        L.Iw[2 * NB + i] = R[6] * d[0] * R[6] + R[7] * d[1] * R[7] + R[8] * d[2] * R[8];
+        L.Iw[3 * NB + i] = R[0] * d[0] * R[3] + R[1] * d[1] * R[4] + R[2] * d[2] * R[5];
+        L.Iw[4 * NB + i] = R[0] * d[0] * R[6] + R[1] * d[1] * R[7] + R[2] * d[2] * R[8];
+        L.Iw[5 * NB + i] = R[3] * d[0] * R[6] + R[4] * d[1] * R[7] + R[5] * d[2] * R[8];
+        mlo[i] = 0u;
+        mhi[i] = 0u;
+      }
+      // pushes (rows in order; a body's pushes add in row order, as on a pack)
+      for (int i = gt; i < NB; i += GS) {
+        if ((L.flag[i] & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
+        const int g = a.g0 + i;
+        for (int r = 0; r < a.np; ++r) {
+          const int row = a.p0 + r;
+          if (a.push_body[row] == g && step >= (int64_t)a.push_start[row] &&
+              step < (int64_t)a.push_start[row] + a.push_steps[row]) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.v[k * NB + i] += dt * a.push_force[3 * row + k] * L.invm[i];
+          }
+        }
+      }
+      if (gt == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { S[sLo + k] = (int32_t)ford(3.0e38f); S[sHi + k] = (int32_t)ford(-3.0e38f); }
+        S[sHmax] = (int32_t)ford(0.f);
+        S[sNcol] = 0;
+      }
+      if (gt < kMaxColours) S[sColCnt + gt] = 0;
+      for (int c = gt; c <= a.ncell_cap; c += GS) { cstart[c] = 0; cfill[c] = 0; }
+      grid.sync();
+      // ---- 3. uniform grid: bounds of the active centres, largest AABB half size ----
+      {
+        float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f}, hmax = 0.f;
+        for (int i = gt; i < NB; i += GS) {
+          if (!(L.flag[i] & kActive)) continue;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const float x = L.x[k * NB + i];
+            lo[k] = fminf(lo[k], x);
+            hi[k] = fmaxf(hi[k], x);
+            hmax = fmaxf(hmax, L.hm[k * NB + i]);
+          }
+        }
+        // wave reductions, then one atomic per wave
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], __shfl_xor(lo[k], d));
+            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], d));
+          }
+          hmax = fmaxf(hmax, __shfl_xor(hmax, d));
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            atomicMin(reinterpret_cast<uint32_t*>(&S[sLo + k]), ford(lo[k]));
+            atomicMax(reinterpret_cast<uint32_t*>(&S[sHi + k]), ford(hi[k]));
+          }
+          atomicMax(reinterpret_cast<uint32_t*>(&S[sHmax]), ford(hmax));
+        }
+      }
+      grid.sync();
+      const Grid G = make_grid(S, a.margin, a.ncell_cap);
+      const int ncell = G.n[0] * G.n[1] * G.n[2];
+      for (int i = gt; i < NB; i += GS) {
+        int c = -1;
+        if (L.flag[i] & kActive) {
+          float x[3];
+          load3(L.x, NB, i, x);
+          c = G.cell_of(x);
+          atomicAdd(&cstart[c], 1);
+        }
+        cellof[i] = c;
+      }
+      grid.sync();
+      const int nin = grid_scan(grid, cstart, ncell, a.ired, sh, sh2);
+      if (gt == 0) cstart[ncell] = nin;
+      grid.sync();
+      for (int i = gt; i < NB; i += GS) {
+        const int c = cellof[i];
+        if (c >= 0) cellbody[cstart[c] + atomicAdd(&cfill[c], 1)] = i;
+      }
+      grid.sync();
+      // ---- candidates: per body i, the bodies j > i of the 27 neighbour cells that pass
+      // Eq. (aabb) with the margin (inclusive), then the ground; counted, placed, written ----
+      auto walk = [&](int i, uint32_t* out, int room) -> int {
+        int cnt = 0;
+        const uint32_t fi = L.flag[i];
+        if (!(fi & kActive)) return 0;
+        const bool dyni = (fi & kDynamic) != 0;
+        float xi[3], hi[3];
+        load3(L.x, NB, i, xi);
+        load3(L.hm, NB, i, hi);
+        int ci[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ci[k] = min(G.n[k] - 1, max(0, (int)floorf((xi[k] - G.lo[k]) / G.h)));
+        for (int dz = -1; dz <= 1; ++dz) {
+          const int cz = ci[2] + dz;
+          if (cz < 0 || cz >= G.n[2]) continue;
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int cy = ci[1] + dy;
+            if (cy < 0 || cy >= G.n[1]) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int cx = ci[0] + dx;
+              if (cx < 0 || cx >= G.n[0]) continue;
+              const int c = (cz * G.n[1] + cy) * G.n[0] + cx;
+              for (int k = cstart[c]; k < cstart[c + 1]; ++k) {
+                const int j = cellbody[k];
+                if (j <= i) continue;
+                const uint32_t fj = L.flag[j];
+                if (!(fj & kActive) || !(dyni || (fj & kDynamic))) continue;
+                if (fabsf(xi[0] - L.x[j]) <= hi[0] + L.hm[j] + a.margin &&
+                    fabsf(xi[1] - L.x[NB + j]) <= hi[1] + L.hm[NB + j] + a.margin &&
+                    fabsf(xi[2] - L.x[2 * NB + j]) <= hi[2] + L.hm[2 * NB + j] + a.margin) {
+                  if (out && cnt < room) out[cnt] = (uint32_t)j;
+                  ++cnt;
+                }
+              }
+            }
+          }
+        }
+        if (out) {
+          // ascending j (insertion sort of the body's own run)
+          const int n = min(cnt, room);
+          for (int p = 1; p < n; ++p) {
+            const uint32_t v = out[p];
+            int q = p - 1;
+            while (q >= 0 && out[q] > v) { out[q + 1] = out[q]; --q; }
+            out[q + 1] = v;
+          }
+        }
+        if (dyni && (xi[2] - hi[2] <= a.margin)) {
+          if (out && cnt < room) out[cnt] = ~0u;
+          ++cnt;
+        }
+        return cnt;
+      };
+      for (int i = gt; i < NB; i += GS) ccount[i] = walk(i, nullptr, 0);
+      grid.sync();
+      const int ncand_all = grid_scan(grid, ccount, NB, a.ired, sh, sh2);
+      if (gt == 0) S[sNcand] = min(ncand_all, CC);
+      grid.sync();
+      // a body whose run does not fit the candidate capacity ends the list before its run
+      for (int i = gt; i < NB; i += GS) {
+        const int off = ccount[i], end = i + 1 < NB ? ccount[i + 1] : ncand_all;
+        if (end > CC && off <= CC) {
+          atomicMin(&S[sNcand], off);
+          atomicOr(&S[sErr], (int)kErrCand);
+        }
+      }
+      grid.sync();
+      const int ncand = S[sNcand];
+      for (int i = gt; i < NB; i += GS) {
+        const int off = ccount[i], end = i + 1 < NB ? ccount[i + 1] : ncand_all;
+        if (end > ncand || end == off) continue;
+        walk(i, cb + off, end - off);
+        for (int k = off; k < end; ++k) ca[k] = (uint32_t)i;
+      }
+      grid.sync();
+      // ---- 4. narrowphase (SAT, Sec. "Narrowphase: OBB SAT"; the ground: a vertex below z = 0) ----
+      for (int k = gt; k < ncand; k += GS) {
+        const int i = (int)ca[k];
+        const uint32_t jb = cb[k];
+        bool hit;
+        if (jb == ~0u) {
+          hit = L.x[2 * NB + i] - L.hm[2 * NB + i] < 0.f;
+        } else {
+          const int j = (int)jb;
+          float RA[9], RB[9], heA[3], heB[3], d[3], n[3], depth;
+          body_R(L, i, RA);
+          body_R(L, j, RB);
+          load3(L.he, NB, i, heA);
+          load3(L.he, NB, j, heB);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) d[q] = L.x[q * NB + j] - L.x[q * NB + i];
+          hit = sat_boxes(RA, heA, RB, heB, d, n, depth);
+        }
+        chit[k] = hit ? 1 : 0;
+      }
+      grid.sync();
+      const int nman = grid_scan(grid, chit, ncand, a.ired, sh, sh2);
+      if (gt == 0) S[sNman] = nman;
+      grid.sync();
+      for (int k = gt; k < ncand; k += GS) {
+        const int pos = chit[k], nxt = k + 1 < ncand ? chit[k + 1] : nman;
+        if (nxt > pos) {
+          man_a[pos] = (int32_t)ca[k];
+          man_b[pos] = cb[k] == ~0u ? -1 : (int32_t)cb[k];
+          man_col[pos] = -1;
+        }
+      }
+      grid.sync();
+      // ---- 5. partitioned greedy colouring ----
+      for (int p = gt; p <= a.nparts; p += GS) {
+        // the first canonical pair whose first body is in partition p or later
+        const int key = (int)min((int64_t)p * PS, (int64_t)NB);
+        int lo = 0, hi = nman;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (man_a[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        a.part[p] = lo;
+        if (p < a.nparts) far[p] = 0;
+      }
+      grid.sync();
+      for (int pass = 0; pass < 3; ++pass) {
+        for (int p = gt; p < a.nparts; p += GS) {
+          if (pass > 0 && (p & 1) != pass - 1) continue;
+          for (int m = a.part[p]; m < a.part[p + 1]; ++m) {
+            const int i = man_a[m], j = man_b[m];
+            const int pj = j < 0 ? p : j / PS;
+            if (pass == 0 && pj > p + 1) ++far[p];
+            if ((pass == 0 && pj == p) || (pass > 0 && pj == p + 1)) colour_pair(m, i, j, L.flag, mlo, mhi, man_col, S);
+          }
+        }
+        grid.sync();
+      }
+      // the pairs between partitions further apart: one thread, canonical order
+      if (gt == 0) {
+        for (int p = 0; p < a.nparts; ++p) {
+          if (far[p] == 0) continue;
+          for (int m = a.part[p]; m < a.part[p + 1]; ++m) {
+            const int i = man_a[m], j = man_b[m];
+            if (j >= 0 && j / PS > p + 1) colour_pair(m, i, j, L.flag, mlo, mhi, man_col, S);
+          }
+        }
+        int off = 0, ncol = 0;
+        for (int c = 0; c < kMaxColours; ++c) {
+          const int n = S[sColCnt + c];
+          S[sColOff + c] = off;
+          S[sColCur + c] = 0;
+          off += n;
+          if (n > 0) ncol = c + 1;
+        }
+        S[sColOff + kMaxColours] = off;
+        S[sNcol] = ncol;
+      }
+      grid.sync();
+      const int ncol = S[sNcol];
+      // colour-sorted slots (the order inside a colour is free: its pairs share no dynamic body)
+      for (int m = gt; m < nman; m += GS) {
+        const int c = man_col[m];
+        int slot = -1;
+        if (c >= 0) {
+          slot = S[sColOff + c] + atomicAdd(&S[sColCur + c], 1);
+          s_a[slot] = man_a[m];
+          s_b[slot] = man_b[m];
+        }
+        man_slot[m] = slot;
+      }
+      grid.sync();
+      // ---- 6. manifolds into the colour-sorted slots (zero initial impulses) ----
+      {
+        int pts = 0, kept = 0;
+        for (int m = gt; m < nman; m += GS) {
+          const int slot = man_slot[m];
+          if (slot < 0) continue;
+          const int i = man_a[m], j = man_b[m];
+          const bool ground = j < 0;
+          float* rec = a.md + (size_t)slot * kManDevWords;
+          float n[3], depth;
+          uint32_t slots;
+          const int np = manifold_geometry<true>(L, i, ground ? 0 : j, ground, a.manifold_mode, rec, n, depth, slots);
+#pragma unroll
+          for (int k = 0; k < 12; ++k) rec[12 + k] = 0.f;
+          if (a.restitution_bias) bias_targets(L, i, ground ? 0 : j, ground, rec, np, n, a.g, dt, a.restitution);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) rec[24 + k] = n[k];
+          rec[27] = depth;
+          s_meta[slot] = (uint32_t)np | (slots << 12);
+          pts += np;
+          kept += 1;
+        }
+        block_sum2(sh, sh2, pts, kept);
+        if (threadIdx.x == 0 && (pts || kept)) {
+          atomicAdd(&S[sPtsAll], pts);
+          atomicAdd(&S[sMans], kept);
+        }
+        if (gt == 0) atomicAdd(&S[sCand], ncand);
+      }
+      grid.sync();
+      // ---- 7. PGS sweeps, colour by colour (Sec. "Contact Solver --- Projected Gauss-Seidel") ----
+      for (int it = 0; it < a.iters; ++it) {
+        for (int c = 0; c < ncol; ++c) {
+          const int c1 = S[sColOff + c + 1];
+          for (int slot = S[sColOff + c] + gt; slot < c1; slot += GS)
+            solve_rec(L, a.md + (size_t)slot * kManDevWords, s_a[slot], s_b[slot], (int)(s_meta[slot] & 15u), a.mu,
+                      opts);
+          grid.sync();
+        }
+      }
+      // ---- contacts of the launch's last step (canonical order) ----
+      if (last) {
+        for (int m = gt; m < nman; m += GS) {
+          const int slot = man_slot[m];
+          a.out_a[m] = man_a[m];
+          a.out_b[m] = man_b[m];
+          if (slot < 0) {
+            a.out_meta[m] = 0u;
+            continue;
+          }
+          const float* rec = a.md + (size_t)slot * kManDevWords;
+          const uint32_t meta = s_meta[slot];
+          const int np = (int)(meta & 15u);
+          a.out_meta[m] = (meta & 0x0ffff00fu) | ((uint32_t)man_col[m] << 4);
+          const float nn[3] = {rec[24], rec[25], rec[26]};
+          Frame F;
+          make_frame(nn, F);
+          for (int k = 0; k < 3; ++k) {
+            a.out_geo[8 * (size_t)m + k] = nn[k];
+            a.out_geo[8 * (size_t)m + 3 + k] = F.f[1][k];
+          }
+          a.out_geo[8 * (size_t)m + 6] = rec[27];
+          a.out_geo[8 * (size_t)m + 7] = 0.f;
+          const int ia = man_a[m];
+          for (int q = 0; q < 4; ++q) {
+            float rl[3] = {0.f, 0.f, 0.f}, rw[3];
+            if (q < np)
+              for (int k = 0; k < 3; ++k) rl[k] = rec[q * 3 + k];
+            to_world(F, rl, rw);
+            for (int k = 0; k < 3; ++k) {
+              a.out_pts[24 * (size_t)m + 6 * q + k] = L.x[k * NB + ia] + rw[k];
+              a.out_pts[24 * (size_t)m + 6 * q + 3 + k] = q < np ? rec[12 + q * 3 + k] : 0.f;
+            }
+          }
+        }
+        if (gt == 0) *a.out_count = nman;
+      }
+      // ---- 8. residual (R21): canonical order, a fixed summation order for a grid size ----
+      {
+        float sum = 0.f, mx = 0.f;
+        int pts = 0, unused = 0;
+        for (int m = gt; m < nman; m += GS) {
+          const int slot = man_slot[m];
+          if (slot < 0) continue;
+          float s2, m2;
+          const int j = man_b[m];
+          const int np = (int)(s_meta[slot] & 15u);
+          residual_rec(L, a.md + (size_t)slot * kManDevWords, man_a[m], j < 0 ? 0 : j, j < 0, np, a.mu, opts, s2, m2);
+          sum += s2;
+          mx = fmaxf(mx, m2);
+          pts += np;
+        }
+        shf[threadIdx.x] = sum;
+        shf2[threadIdx.x] = mx;
+        __syncthreads();
+        for (int d = kMegaThreads / 2; d > 0; d >>= 1) {
+          if ((int)threadIdx.x < d) {
+            shf[threadIdx.x] += shf[threadIdx.x + d];
+            shf2[threadIdx.x] = fmaxf(shf2[threadIdx.x], shf2[threadIdx.x + d]);
+          }
+          __syncthreads();
+        }
+        block_sum2(sh, sh2, pts, unused);
+        if (threadIdx.x == 0) {
+          a.red[2 * blockIdx.x] = shf[0];
+          a.red[2 * blockIdx.x + 1] = shf2[0];
+          a.ired[blockIdx.x] = pts;
+        }
+      }
+      grid.sync();
+      if (gt == 0) {
+        float sum = 0.f, mx = 0.f;
+        int pts = 0;
+        for (int b = 0; b < (int)gridDim.x; ++b) {
+          sum += a.red[2 * b];
+          mx = fmaxf(mx, a.red[2 * b + 1]);
+          pts += a.ired[b];
+        }
+        const int rows = 3 * pts;
+        a.tower_res[2 * a.tslot] = rows ? sqrtf(sum / (float)rows) : 0.f;
+        a.tower_res[2 * a.tslot + 1] = mx;
+        a.tower_count[4 * a.tslot + 3] = (uint32_t)ncol;
+      }
+      // ---- 9. integration ----
+      for (int i = gt; i < NB; i += GS) {
+        if ((L.flag[i] & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
+        if (!integrate_body(L, i, dt)) {
+          atomicOr(&S[sErr], (int)kErrNan);
+          atomicOr(&S[sFrozen], 1);   // frozen from the next substep on
+        }
+      }
+      grid.sync();
+      // ---- 10. Baumgarte position correction (Eq. (baumgarte)), colour by colour ----
+      for (int c = 0; c < ncol; ++c) {
+        const int c1 = S[sColOff + c + 1];
+        for (int slot = S[sColOff + c] + gt; slot < c1; slot += GS) {
+          const int j = s_b[slot];
+          baumgarte_pair(L, s_a[slot], j < 0 ? 0 : j, j < 0, a.md + (size_t)slot * kManDevWords, a.beta, a.slop);
+        }
+        grid.sync();
+      }
+    }
+    // ---- withdrawal of pushed bodies at the end of the step ----
+    if (!S[sFrozen]) {
+      for (int r = gt; r < a.np; r += GS) {
+        const int row = a.p0 + r;
+        const int b = a.push_body[row] - a.g0;
+        if (!(a.push_withdraw[row] > 0.f) || step < (int64_t)a.push_start[row] || !(L.flag[b] & kActive)) continue;
+        float dx[3], f[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { dx[k] = L.x[k * NB + b] - a.push_x0[3 * row + k]; f[k] = a.push_force[3 * row + k]; }
+        if (dot3(dx, f) >= a.push_withdraw[row] * sqrtf(dot3(f, f))) {
+          atomicAnd(&L.flag[b], ~kActive);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) { L.v[k * NB + b] = 0.f; L.w[k * NB + b] = 0.f; }
+        }
+      }
+    }
+    grid.sync();
+  }
+
+  // ---- write the island back (a body without mass keeps its stored velocity) ----
+  for (int i = gt; i < NB; i += GS) {
+    const int g = a.g0 + i;
+    const bool dyn = (L.flag[i] & kDynamic) != 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a.x[k * CAP + g] = L.x[k * NB + i];
+      if (dyn) {
+        a.v[k * CAP + g] = L.v[k * NB + i];
+        a.w[k * CAP + g] = L.w[k * NB + i];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.q[k * CAP + g] = L.q[k * NB + i];
+    a.flags[g] = L.flag[i];
+  }
+  if (gt == 0) {
+    a.tower_count[4 * a.tslot + 0] += (uint32_t)S[sCand];
+    a.tower_count[4 * a.tslot + 1] += (uint32_t)S[sMans];
+    a.tower_count[4 * a.tslot + 2] += (uint32_t)S[sPtsAll];
+    a.tower_frozen[a.tslot] = S[sFrozen] ? 1u : 0u;
+    if (S[sErr]) {
+      atomicOr(a.err_flag, (uint32_t)S[sErr]);
+      atomicOr(a.island_err, (uint32_t)S[sErr]);
+    }
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -2404,10 +3621,12 @@ int ensure_lds_limit() {
   if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
   std::lock_guard<std::mutex> lock(attr_mutex);
   if (!attr_set[dev]) {
-    const void* variants[6] = {(const void*)step_kernel<false, false, false>,
-                               (const void*)step_kernel<true, false, false>,
-                               (const void*)step_kernel<false, true, false>, (const void*)step_kernel<true, true, false>,
-                               (const void*)step_kernel<false, true, true>, (const void*)step_kernel<true, true, true>};
+    const void* variants[9] = {
+        (const void*)step_kernel<false, false, false, false>, (const void*)step_kernel<false, false, false, true>,
+        (const void*)step_kernel<true, false, false, true>,   (const void*)step_kernel<false, true, false, false>,
+        (const void*)step_kernel<false, true, false, true>,   (const void*)step_kernel<true, true, false, true>,
+        (const void*)step_kernel<false, true, true, false>,   (const void*)step_kernel<false, true, true, true>,
+        (const void*)step_kernel<true, true, true, true>};
     for (const void* f : variants)
       if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
         return (int)e;
@@ -2421,16 +3640,22 @@ int ensure_lds_limit() {
 int step_launch_config(const StepArgs& a, const void** func, unsigned* block_threads) {
   if (int e = ensure_lds_limit()) return e;
   const bool learned = a.warm_start == 2 || a.feat_out;
+  // the variants and the episode criteria run in their own instantiations (the network's kernel
+  // always carries them)
+  const bool ext = a.friction_cone || a.restitution_bias || a.manifold_mode || a.ep_state;
   const void* f;
   unsigned threads = kWave;
   if (a.in_gmem) {
     if (a.hot_bodies)
-      f = learned ? (const void*)step_kernel<true, true, true> : (const void*)step_kernel<false, true, true>;
+      f = learned ? (const void*)step_kernel<true, true, true, true>
+                  : (ext ? (const void*)step_kernel<false, true, true, true> : (const void*)step_kernel<false, true, true, false>);
     else
-      f = learned ? (const void*)step_kernel<true, true, false> : (const void*)step_kernel<false, true, false>;
+      f = learned ? (const void*)step_kernel<true, true, false, true>
+                  : (ext ? (const void*)step_kernel<false, true, false, true> : (const void*)step_kernel<false, true, false, false>);
     threads = learned ? step_threads<true, true>() : step_threads<false, true>();
   } else {
-    f = learned ? (const void*)step_kernel<true, false, false> : (const void*)step_kernel<false, false, false>;
+    f = learned ? (const void*)step_kernel<true, false, false, true>
+                : (ext ? (const void*)step_kernel<false, false, false, true> : (const void*)step_kernel<false, false, false, false>);
   }
   *func = f;
   *block_threads = threads;
@@ -2443,6 +3668,27 @@ int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
   if (int e = step_launch_config(a, &f, &threads)) return e;
   void* args[1] = {const_cast<StepArgs*>(&a)};
   return (int)hipLaunchKernel(f, dim3(a.n_packs), dim3(threads), args, lds_bytes, (hipStream_t)stream);
+}
+
+}  // namespace jg
+
+namespace jg {
+
+int mega_blocks(int* blocks) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mega_kernel, kMegaThreads, 0);
+  if (e != hipSuccess) return (int)e;
+  *blocks = std::max(1, std::min(per, 2)) * std::max(1, cus);
+  return 0;
+}
+
+int launch_mega(const MegaArgs& a, int blocks, void* stream) {
+  MegaArgs args = a;
+  void* params[] = {(void*)&args};
+  return (int)hipLaunchCooperativeKernel((const void*)mega_kernel, dim3((unsigned)blocks), dim3(kMegaThreads), params, 0,
+                                         (hipStream_t)stream);
 }
 
 }  // namespace jg

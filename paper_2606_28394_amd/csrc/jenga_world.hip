@@ -157,6 +157,27 @@ struct jg_world {
     std::vector<unsigned> block;
   };
   std::vector<StepGraph> graphs;    // most recently built last
+  // towers stepped by the whole GPU (at least mega_bodies bodies): after every pack in internal
+  // order, each with its own scratch
+  struct Mega {
+    int tower = -1, g0 = 0, nb = 0, tslot = 0, p0 = 0, np = 0;
+    int ncell_cap = 0, cand_cap = 0, nparts = 0;
+    DevBuf<float> body, md, red, out_geo, out_pts;
+    DevBuf<uint32_t> ubody, cand, out_meta, err;
+    DevBuf<int32_t> cells, man, part, ired, scal, out_a, out_b, out_count;
+    hipError_t release() {
+      hipError_t first = hipSuccess;
+      for (hipError_t e : {body.release(), md.release(), red.release(), out_geo.release(), out_pts.release(),
+                           ubody.release(), cand.release(), out_meta.release(), err.release(), cells.release(),
+                           man.release(), part.release(), ired.release(), scal.release(), out_a.release(),
+                           out_b.release(), out_count.release()})
+        if (first == hipSuccess) first = e;
+      return first;
+    }
+  };
+  std::vector<Mega> megas;
+  std::vector<int> mega_of_tower;   // tower id -> index in megas (-1: in a pack)
+  int mega_grid = 0;                // workgroups of their cooperative launches
 };
 
 namespace {
@@ -222,13 +243,25 @@ int32_t download_state(jg_world* w) {
 // classes of equal workgroups-per-CU, each launched with the LDS its largest pack needs.
 int32_t build_layout(jg_world* w) {
   const int T = (int)w->tower_bodies.size();
-  std::vector<int> order;
+  std::vector<int> order, mega_towers;
   int max_tower = 1;
   for (int t = 0; t < T; ++t) {
-    if (!w->tower_bodies[t].empty()) order.push_back(t);
-    max_tower = std::max(max_tower, (int)w->tower_bodies[t].size());
+    const int n = (int)w->tower_bodies[t].size();
+    if (n == 0) continue;
+    if (w->prm.mega_bodies > 0 && n >= w->prm.mega_bodies) {
+      mega_towers.push_back(t);
+      continue;
+    }
+    order.push_back(t);
+    max_tower = std::max(max_tower, n);
   }
   if (max_tower > 65534) return fail(JG_ECAPACITY, "a tower has more bodies than one pack can index (65534)");
+  if (!mega_towers.empty() && (w->prm.warm_start != 0 || w->prm.use_graph || w->prm.record_features))
+    return fail(JG_EINVAL, "towers of mega_bodies bodies or more are stepped with warm_start 0, without graphs "
+                           "or feature records");
+  for (auto& m : w->megas) HIP_TRY(m.release());
+  w->megas.clear();
+  w->mega_of_tower.assign(T, -1);
   // manifold slots per body: 3.5 in shared packs (sized for LDS); a batch stepped one tower per
   // workgroup (below) has LDS to spare and gets 6, room for a sinking or collapsing tower's pairs
   float mpb = w->prm.manifolds_per_body > 0.f ? w->prm.manifolds_per_body : 3.5f;
@@ -348,6 +381,26 @@ int32_t build_layout(jg_world* w) {
     c.tpc = std::max(c.tpc, (int)bins[b].towers.size());
     c.ppc = std::max(c.ppc, std::max(1, pushes));
   }
+  // towers stepped by the whole GPU: their bodies, slots and push rows after every pack's
+  for (int t : mega_towers) {
+    jg_world::Mega m;
+    m.tower = t;
+    m.tslot = (int)w->tower_order.size();
+    w->tower_slot[t] = m.tslot;
+    w->tower_order.push_back(t);
+    m.g0 = (int)w->body_of_int.size();
+    for (int id : w->tower_bodies[t]) {
+      w->int_of_body[id] = (int)w->body_of_int.size();
+      w->body_of_int.push_back(id);
+    }
+    m.nb = (int)w->body_of_int.size() - m.g0;
+    m.p0 = (int)w->push_order.size();
+    for (int id : w->tower_bodies[t])
+      for (int r : push_of_body[id]) w->push_order.push_back(r);
+    m.np = (int)w->push_order.size() - m.p0;
+    w->mega_of_tower[t] = (int)w->megas.size();
+    w->megas.push_back(m);
+  }
   // at most four classes (the hardware queues a process gets by default): fold the smallest class
   // into its neighbour with the larger LDS (its packs then run at that neighbour's occupancy)
   auto lds_classes = [&]() {
@@ -448,6 +501,40 @@ int32_t build_layout(jg_world* w) {
   for (int s = 0; s < (int)w->tower_order.size(); ++s)
     for (int k = tb0[s]; k < tb0[s + 1]; ++k) btw[k] = s;
   HIP_TRY(hipMemcpy(w->d_body_tower.p, btw.data(), sizeof(int32_t) * w->max_bodies, hipMemcpyHostToDevice));
+  // scratch of the towers stepped by the whole GPU
+  if (!w->megas.empty()) {
+    if (int e = jg::mega_blocks(&w->mega_grid))
+      return fail(JG_EDEVICE, std::string("sizing the grid-wide launch: ") + hipGetErrorString((hipError_t)e));
+    const size_t G = (size_t)w->mega_grid;
+    for (auto& m : w->megas) {
+      const size_t nb = (size_t)m.nb;
+      m.ncell_cap = (int)std::min<size_t>(2 * nb + 64, (size_t)1 << 30);
+      const double cc = std::ceil((double)w->prm.mega_cand_per_body * (double)nb);
+      if (cc > 2.0e9) return fail(JG_ECAPACITY, "candidate capacity of a large island beyond 2e9");
+      m.cand_cap = std::max(64, (int)cc);
+      m.nparts = (int)((nb + (size_t)w->prm.colour_partition - 1) / (size_t)w->prm.colour_partition);
+      const size_t C = (size_t)m.cand_cap;
+      HIP_TRY(m.body.ensure(jg::kMegaBodyWords * nb));
+      HIP_TRY(m.ubody.ensure(jg::kMegaBodyU32 * nb));
+      HIP_TRY(m.cells.ensure(2 * ((size_t)m.ncell_cap + 1)));
+      HIP_TRY(m.cand.ensure(3 * C));
+      HIP_TRY(m.man.ensure(7 * C));
+      HIP_TRY(m.md.ensure((size_t)jg::kManDevWords * C));
+      HIP_TRY(m.part.ensure(2 * (size_t)m.nparts + 1));
+      HIP_TRY(m.red.ensure(2 * G + 2));
+      HIP_TRY(m.ired.ensure(G + 1));
+      HIP_TRY(m.scal.ensure(jg::kMegaScal));
+      HIP_TRY(m.out_a.ensure(C));
+      HIP_TRY(m.out_b.ensure(C));
+      HIP_TRY(m.out_meta.ensure(C));
+      HIP_TRY(m.out_geo.ensure(8 * C));
+      HIP_TRY(m.out_pts.ensure(24 * C));
+      HIP_TRY(m.out_count.ensure(1));
+      HIP_TRY(m.err.ensure(1));
+      HIP_TRY(hipMemsetAsync(m.out_count.p, 0, sizeof(int32_t), w->stream));
+      HIP_TRY(hipMemsetAsync(m.err.p, 0, sizeof(uint32_t), w->stream));
+    }
+  }
   w->layout_dirty = false;
   w->clear_warm = true;
   w->ep_on = false;   // the episode state is per tower slot of the old layout
@@ -536,7 +623,12 @@ int32_t collect_stats(jg_world* w) {
     w->st_col[t] = (int32_t)cnt[4 * s + 3];
     w->st_rms[t] = res[2 * s];
     w->st_max[t] = res[2 * s + 1];
-    w->st_err[t] |= perr[w->pack_of_tower[t]];
+    if (w->pack_of_tower[t] >= 0) w->st_err[t] |= perr[w->pack_of_tower[t]];
+  }
+  for (auto& m : w->megas) {
+    uint32_t e = 0;
+    HIP_TRY(hipMemcpy(&e, m.err.p, sizeof(e), hipMemcpyDeviceToHost));
+    w->st_err[m.tower] |= e;
   }
   for (int k = 0; k < 4 * T; k += 4) { cnt[k] = cnt[k + 1] = cnt[k + 2] = 0; }
   HIP_TRY(hipMemcpy(w->d_tower_count.p, cnt.data(), sizeof(uint32_t) * 4 * T, hipMemcpyHostToDevice));
@@ -676,6 +768,12 @@ void jg_default_params(jg_params* p) {
   p->rest_ek = 1e-7;
   p->support_eps = 2e-3;
   p->rest_steps = 400;
+  p->friction_cone = 0;
+  p->restitution_bias = 0;
+  p->manifold_mode = 0;
+  p->mega_bodies = 16384;
+  p->colour_partition = 1024;
+  p->mega_cand_per_body = 16.f;
 }
 
 const char* jg_last_error(void) { return g_err.c_str(); }
@@ -690,6 +788,11 @@ int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodi
   if (p->mlp_iters < 0) return fail(JG_EINVAL, "mlp_iters must not be negative");
   if (p->rest_steps < 0 || !(p->collapse_fd >= 0.0) || !(p->support_eps >= 0.0))
     return fail(JG_EINVAL, "bad episode parameters");
+  if (p->friction_cone < 0 || p->friction_cone > 1 || p->restitution_bias < 0 || p->restitution_bias > 1 ||
+      p->manifold_mode < 0 || p->manifold_mode > 1)
+    return fail(JG_EINVAL, "friction_cone, restitution_bias and manifold_mode are 0 or 1");
+  if (p->mega_bodies < 0 || p->colour_partition < 1 || !(p->mega_cand_per_body >= 1.f))
+    return fail(JG_EINVAL, "mega_bodies >= 0, colour_partition >= 1 and mega_cand_per_body >= 1");
   jg_world* w = new (std::nothrow) jg_world();
   if (!w) return fail(JG_ENOMEM, "host allocation failed");
   w->prm = *p;
@@ -746,6 +849,7 @@ int32_t jg_destroy_world(jg_world* w) {
   note(w->d_phase_cycles.release());
   note(w->d_mlp_params.release()); note(w->d_mlp_packed.release()); note(w->d_feat.release());
   note(w->d_tower_fallback.release());
+  for (auto& m : w->megas) note(m.release());
   for (hipStream_t s : w->aux) note(hipStreamDestroy(s));
   for (hipEvent_t e : w->aux_done) note(hipEventDestroy(e));
   if (w->fork) note(hipEventDestroy(w->fork));
@@ -885,7 +989,7 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   if (int32_t r = set_device(w)) return r;
   if (n_steps == 0) return JG_OK;
   if (w->prm.warm_start == 2 && !w->mlp_set) return fail(JG_ESTATE, "warm_start 2 needs jg_set_mlp first");
-  if (w->n_packs == 0) { w->step += n_steps; return JG_OK; }
+  if (w->n_packs == 0 && w->megas.empty()) { w->step += n_steps; return JG_OK; }
   jg::StepArgs a;
   std::memset(&a, 0, sizeof(a));
   a.x = w->d_x.p; a.q = w->d_q.p; a.v = w->d_v.p; a.w = w->d_w.p;
@@ -918,6 +1022,9 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
   a.margin = (float)w->prm.margin;
   a.iters = w->prm.iters;
   a.n_sub = w->prm.n_sub;
+  a.friction_cone = w->prm.friction_cone;
+  a.restitution_bias = w->prm.restitution_bias;
+  a.manifold_mode = w->prm.manifold_mode;
   a.n_steps = n_steps;
   a.warm_start = w->prm.warm_start;
   a.step0 = w->step;
@@ -952,6 +1059,33 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
       if (k > 0) HIP_TRY(hipEventRecord(w->aux_done[k - 1], s));
     }
     for (size_t k = 1; k < nc; ++k) HIP_TRY(hipStreamWaitEvent(w->stream, w->aux_done[k - 1], 0));
+  }
+  // towers stepped by the whole GPU, one cooperative launch each (after the packs on the stream)
+  for (auto& m : w->megas) {
+    jg::MegaArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.x = w->d_x.p; g.q = w->d_q.p; g.v = w->d_v.p; g.w = w->d_w.p;
+    g.he = w->d_he.p; g.mass = w->d_mass.p; g.flags = w->d_flags.p;
+    g.cap = w->max_bodies; g.g0 = m.g0; g.nb = m.nb; g.tslot = m.tslot;
+    g.mu = (float)w->mu[m.tower];
+    g.push_body = w->d_push_body.p; g.push_start = w->d_push_start.p; g.push_steps = w->d_push_steps.p;
+    g.push_force = w->d_push_force.p; g.push_withdraw = w->d_push_withdraw.p; g.push_x0 = w->d_push_x0.p;
+    g.p0 = m.p0; g.np = m.np;
+    g.tower_count = w->d_tower_count.p; g.tower_res = w->d_tower_res.p; g.tower_frozen = w->d_tower_frozen.p;
+    g.err_flag = w->d_err_flag.p; g.island_err = m.err.p;
+    for (int k = 0; k < 3; ++k) g.g[k] = a.g[k];
+    g.dt = a.dt; g.restitution = a.restitution; g.beta = a.beta; g.slop = a.slop; g.margin = a.margin;
+    g.iters = a.iters; g.n_sub = a.n_sub; g.n_steps = n_steps;
+    g.friction_cone = a.friction_cone; g.restitution_bias = a.restitution_bias; g.manifold_mode = a.manifold_mode;
+    g.partition = w->prm.colour_partition;
+    g.step0 = w->step;
+    g.body = m.body.p; g.ubody = m.ubody.p; g.cells = m.cells.p; g.ncell_cap = m.ncell_cap;
+    g.cand = m.cand.p; g.cand_cap = m.cand_cap; g.man = m.man.p; g.md = m.md.p;
+    g.part = m.part.p; g.nparts = m.nparts; g.red = m.red.p; g.ired = m.ired.p; g.scal = m.scal.p;
+    g.out_a = m.out_a.p; g.out_b = m.out_b.p; g.out_meta = m.out_meta.p; g.out_geo = m.out_geo.p;
+    g.out_pts = m.out_pts.p; g.out_count = m.out_count.p;
+    if (int e = jg::launch_mega(g, w->mega_grid, w->stream))
+      return fail(JG_EDEVICE, std::string("grid-wide island launch: ") + hipGetErrorString((hipError_t)e));
   }
   w->step += n_steps;
   w->device_newer = true;
@@ -1019,9 +1153,53 @@ int32_t jg_query_contacts(jg_world* w, int32_t tower, jg_contact* out, int32_t c
   if (!n_out || capacity < 0 || (capacity > 0 && !out)) return fail(JG_EINVAL, "bad output buffer");
   if (tower < 0 || tower >= (int)w->tower_bodies.size()) return fail(JG_EINVAL, "tower index out of range");
   *n_out = 0;
-  if (w->layout_dirty || w->n_packs == 0) return JG_OK;
+  if (w->layout_dirty || (w->n_packs == 0 && w->megas.empty())) return JG_OK;
   if (int32_t r = set_device(w)) return r;
   HIP_TRY(hipStreamSynchronize(w->stream));
+  if (w->mega_of_tower[tower] >= 0) {
+    // a tower stepped by the whole GPU: its pairs in canonical order, 32-bit indices
+    const auto& m = w->megas[w->mega_of_tower[tower]];
+    int32_t cnt = 0;
+    HIP_TRY(hipMemcpy(&cnt, m.out_count.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (cnt <= 0) return report_device_errors(w);
+    std::vector<int32_t> ia(cnt), ib(cnt);
+    std::vector<uint32_t> meta(cnt);
+    std::vector<float> geo(8 * (size_t)cnt), pts(24 * (size_t)cnt);
+    HIP_TRY(hipMemcpy(ia.data(), m.out_a.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ib.data(), m.out_b.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(meta.data(), m.out_meta.p, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(geo.data(), m.out_geo.p, sizeof(float) * 8 * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pts.data(), m.out_pts.p, sizeof(float) * 24 * cnt, hipMemcpyDeviceToHost));
+    int total = 0, order = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int npts = (int)(meta[k] & 15u);
+      if (npts == 0) continue;
+      for (int q = 0; q < npts; ++q) {
+        if (total < capacity) {
+          jg_contact& c = out[total];
+          c.tower = tower;
+          c.body_a = w->body_of_int[m.g0 + ia[k]];
+          c.body_b = ib[k] < 0 ? -1 : w->body_of_int[m.g0 + ib[k]];
+          c.slot = (int)((meta[k] >> (12 + 4 * q)) & 15u);
+          c.colour = (int)((meta[k] >> 4) & 255u);
+          c.order = order;
+          for (int j = 0; j < 3; ++j) {
+            c.point[j] = pts[24 * (size_t)k + 6 * q + j];
+            c.normal[j] = geo[8 * (size_t)k + j];
+            c.t1[j] = geo[8 * (size_t)k + 3 + j];
+          }
+          c.depth = geo[8 * (size_t)k + 6];
+          c.lambda_n = pts[24 * (size_t)k + 6 * q + 3];
+          c.lambda_t1 = pts[24 * (size_t)k + 6 * q + 4];
+          c.lambda_t2 = pts[24 * (size_t)k + 6 * q + 5];
+        }
+        ++total;
+      }
+      ++order;
+    }
+    *n_out = total;
+    return report_device_errors(w);
+  }
   const int pk = w->pack_of_tower[tower];
   if (pk < 0) return JG_OK;
   int32_t cnt = 0;

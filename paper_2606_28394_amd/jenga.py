@@ -42,7 +42,9 @@ class jg_params(C.Structure):
                 ("mlp_iters", C.c_int32), ("fallback_tau", C.c_double), ("record_features", C.c_int32),
                 ("use_graph", C.c_int32), ("collapse_fd", C.c_double), ("collapse_ek", C.c_double),
                 ("collapse_theta", C.c_double), ("rest_ek", C.c_double), ("support_eps", C.c_double),
-                ("rest_steps", C.c_int32)]
+                ("rest_steps", C.c_int32), ("friction_cone", C.c_int32), ("restitution_bias", C.c_int32),
+                ("manifold_mode", C.c_int32), ("mega_bodies", C.c_int32), ("colour_partition", C.c_int32),
+                ("mega_cand_per_body", C.c_float)]
 
 
 class jg_contact(C.Structure):
@@ -433,7 +435,8 @@ class World:
 
     def __init__(self, scene: dict, warm_start: int = 0, stream=None, device: int = 0, pack_bodies: int = 0,
                  manifolds_per_body: float = 0.0, params: dict | None = None, mlp=None, mlp_iters: int = 8,
-                 fallback_tau: float = 1e30, record_features: bool = False, use_graph: bool = False):
+                 fallback_tau: float = 1e30, record_features: bool = False, use_graph: bool = False,
+                 episode: dict | None = None):
         pr = params or scene["params"]
         p = jg_default_params()
         p.gravity[:] = [float(g) for g in pr["gravity"]]
@@ -444,6 +447,12 @@ class World:
         p.margin = float(pr["margin"])
         p.n_sub = int(pr["n_sub"])
         p.iters = int(pr["iters"])
+        p.friction_cone = int(pr.get("friction_cone", 0))
+        p.restitution_bias = int(pr.get("restitution_bias", 0))
+        p.manifold_mode = int(pr.get("manifold_mode", 0))
+        p.mega_bodies = int(pr.get("mega_bodies", 16384))
+        p.colour_partition = int(pr.get("colour_partition", 1024))
+        p.mega_cand_per_body = float(pr.get("mega_cand_per_body", 16.0))
         p.warm_start = int(warm_start)
         p.device = int(device)
         p.stream = stream if stream is not None else current_stream_handle()
@@ -453,6 +462,8 @@ class World:
         p.fallback_tau = float(fallback_tau)
         p.record_features = int(bool(record_features))
         p.use_graph = int(bool(use_graph))
+        for k, v in (episode or {}).items():     # collapse_fd, collapse_ek, ..., rest_steps
+            setattr(p, k, type(getattr(p, k))(v))
         self.params = p
         T = int(scene["n_towers"])
         ptr = np.asarray(scene["tower_ptr"])

@@ -28,7 +28,9 @@ A scene is a dict of numpy arrays:
   push_withdraw (K,)  f64     displacement along the force that deactivates the body (0 = never)
   push_move  (K,)     int32   the move a push is (Tab. ziglar): MOVE_CENTER_X, MOVE_SIDE_Y, MOVE_SIDE_X,
                               or -1 when the push is not a block removal
-  params     dict     dt, iters, n_sub, restitution, beta, slop, margin, gravity
+  params     dict     dt, iters, n_sub, restitution, beta, slop, margin, gravity, friction_cone (0 per-axis
+                      clip, 1 disc), restitution_bias (0 as printed, 1 pre-solve target), manifold_mode
+                      (0 literal silhouettes, 1 reference-face clipping)
   n_steps    int      steps the configuration runs
 """
 from __future__ import annotations
@@ -60,7 +62,8 @@ JITTER = 5e-4           # horizontal placement jitter (uniform +-)
 
 def default_params(**over):
     p = dict(dt=1.0 / 240.0, iters=20, n_sub=1, restitution=0.10, beta=0.35,
-             slop=4e-4, margin=2e-3, gravity=(0.0, 0.0, -G))
+             slop=4e-4, margin=2e-3, gravity=(0.0, 0.0, -G), friction_cone=0, restitution_bias=0,
+             manifold_mode=0, mega_bodies=16384, colour_partition=1024)
     p.update(over)
     return p
 
@@ -263,6 +266,17 @@ def subset(scene, towers) -> dict:
 # ----------------------------------------------------------------------------------------------
 # Benchmark configurations
 # ----------------------------------------------------------------------------------------------
+
+def paper_preset_params(**over):
+    """The paper's own simulator settings (appendix "Physical Parameters"): 14 PGS iterations and
+    three substeps of a 1/240 s step."""
+    return default_params(iters=14, n_sub=3, **over)
+
+
+def paper_tower(levels: int, rng: np.random.Generator | None):
+    """A tower of the paper's block (81 x 26 x 18 mm, 19.6 g), same layout recipe."""
+    return jenga_tower(levels, rng, half=PAPER_BLOCK_HALF, mass=PAPER_BLOCK_MASS)
+
 
 def cfg1(seed: int = 0):
     """One 18-level tower (54 blocks), one seeded middle block removed at t = 0.

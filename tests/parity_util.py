@@ -47,12 +47,14 @@ def oracle_manifolds(ow, t: int) -> dict:
     return {(m["a"], m["b"]): m for m in ow.manifolds(t)}
 
 
-def compare_contacts(om: dict, gm: dict, masses=None, impulses: bool = True) -> dict:
+def compare_contacts(om: dict, gm: dict, masses=None, impulses: bool = True, lam_tol: float = 1e-4,
+                     point_tol: float = 1e-5) -> dict:
     """Returns a report; 'ok' is True when every check inside the tolerances passes.
     masses (tower-local, optional): the impulse floor of a pair is then m g dt / 4 of its lighter
     body (the ground counts as infinitely heavy) instead of the benchmark block's.
     impulses=False skips the impulse comparison (statically indeterminate contact sets, where
-    only the bodies' net impulses, fixed by the velocities, are unique)."""
+    only the bodies' net impulses, fixed by the velocities, are unique); lam_tol, point_tol: the
+    impulse and point tolerances (1e-4 and 1e-5 by default)."""
     rep = dict(pairs=len(om), banded=0, missing=[], extra=[], colour_mismatch=[], slot_mismatch=[],
                point_err=0.0, lam_err=0.0, normal_err=0.0, normal_err_cross=0.0, depth_err=0.0,
                depth_err_cross=0.0, colours_checked=False)
@@ -94,7 +96,7 @@ def compare_contacts(om: dict, gm: dict, masses=None, impulses: bool = True) -> 
         if impulses:
             rep["lam_err"] = max(rep["lam_err"], float((np.abs(o["lam"] - g["lam"]) / lam_scale).max()))
     rep["ok"] = (not rep["missing"] and not rep["extra"] and not rep["colour_mismatch"] and not rep["slot_mismatch"]
-                 and rep["point_err"] <= 1e-5 and rep["lam_err"] <= 1e-4
+                 and rep["point_err"] <= point_tol and rep["lam_err"] <= lam_tol
                  and rep["normal_err"] <= 1e-5 and rep["depth_err"] <= 1e-5
                  and rep["normal_err_cross"] <= 1e-3 and rep["depth_err_cross"] <= 1e-3)
     return rep

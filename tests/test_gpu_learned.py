@@ -127,14 +127,18 @@ def test_all_tower_records_match_per_tower_queries(J):
     gw.close()
 
 
+@pytest.mark.parametrize("pack", [0, -1], ids=["lds", "device"])
 @pytest.mark.parametrize("steps", [1, 3])
-def test_constant_network_parity(J, oracle, steps):
-    """A network with constant outputs makes the initial impulses exact functions of k and mu:
-    the learned start, mlp_iters sweeps and the records then meet the plain tolerances."""
+def test_constant_network_parity(J, oracle, steps, pack):
+    """A network with constant outputs makes the initial impulses exact functions of k and mu and
+    of the previous step's impulses (added back to the predicted change): the learned start,
+    mlp_iters sweeps and the records then meet the plain tolerances, for on-chip packs and for
+    towers kept in device memory (whose network chunks are split over four waves)."""
     sc = _scene(seed=4)
     net = _net(5, const=[0.3, 0.05, -0.02])
     kw = dict(warm_start=2, mlp=net, mlp_iters=4)
-    ow, gw = _pair(J, oracle, sc, dict(kw, fallback_tau=1e30), dict(kw, fallback_tau=float("inf")), steps=steps)
+    ow, gw = _pair(J, oracle, sc, dict(kw, fallback_tau=1e30, pack_bodies=pack), dict(kw, fallback_tau=float("inf")),
+                   steps=steps)
     assert gw.stats().fallbacks == 0
     _check_records(sc, ow, gw, label=f"const{steps}")
     _check_step(sc, ow, gw, label=f"const{steps}")
@@ -248,11 +252,45 @@ def test_learned_and_records_in_device_memory_match_lds(J):
         dev.close()
 
 
+def test_learned_multi_step_device_matches_lds(J):
+    """Four steps of the learned start (a random network, no fallback) with the towers kept in
+    device memory against on-chip packs: from the second step on the previous impulses enter the
+    network's inputs and are added back to its output, on the four waves' own staging rows.  The
+    same pairs every step, no fallbacks, each tower's sweeps counted as mlp_iters, and states
+    within the one-step parity tolerances times the steps."""
+    sc = _scene(6, seed=14)
+    net = _net(15)
+    kw = dict(warm_start=2, mlp=net, mlp_iters=4, fallback_tau=1e30)
+    lds = J.World(sc, **kw)
+    dev = J.World(sc, pack_bodies=-1, **kw)
+    G_DT = 9.81 / 240.0
+    ptr = sc["tower_ptr"]
+    for step in range(4):
+        lds.step(1)
+        dev.step(1)
+        (lx, lq, lv, lw), (dx, dq, dv, dw) = lds.state(), dev.state()
+        ex = float((np.linalg.norm(lx - dx, axis=1) / np.maximum(np.linalg.norm(lx, axis=1), 0.075)).max())
+        ev = float((np.linalg.norm(lv - dv, axis=1) / np.maximum(np.linalg.norm(lv, axis=1), G_DT)).max())
+        _say("learned device vs lds, step", step, "x", ex, "v", ev)
+        assert ex <= 1e-5 * (step + 1) and float(np.abs(lq - dq).max()) <= 1e-5 * (step + 1)
+        assert ev <= 1e-4 * (step + 1)
+        for t in range(sc["n_towers"]):
+            a = int(ptr[t])
+            assert set(gpu_manifolds(lds.contacts(t), a)) == set(gpu_manifolds(dev.contacts(t), a)), (step, t)
+    for w in (lds, dev):
+        st = w.stats()
+        assert st.fallbacks == 0 and st.error_word == 0
+        assert st.contact_iters == 4 * st.points
+    lds.close()
+    dev.close()
+
+
 def test_island_fallback_with_helper_waves(J):
-    """Towers kept in device memory run the learned variant on four waves (the helpers share
-    the walk, manifolds and sweeps; the network and the fallback stay on the first wave).  With
-    tau = 0 every tower falls back, so three steps must give the plain island kernel's result
-    (3e-6 relative, as for on-chip packs), with the fallbacks counted."""
+    """Towers kept in device memory run the learned variant on four waves (the helpers share the
+    walk, the manifolds, the network's chunks and the sweeps; the residual and the fallback solve
+    stay on the first wave).  With tau = 0 every tower falls back, so three steps must give the
+    plain island kernel's result (3e-6 relative, as for on-chip packs), with the fallbacks
+    counted."""
     sc = _scene(seed=12)
     net = _net(13)
     plain = J.World(sc, pack_bodies=-1)

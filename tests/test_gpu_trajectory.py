@@ -2,9 +2,10 @@
 
 A pushed tower collapses chaotically, so FP32 and FP64 trajectories part after a while and
 single towers cannot be compared step by step.  What must agree is what the experiment
-measures over many towers: how many blocks each tower loses to its pushes (a pushed block is
-removed once it has moved its withdrawal distance), and how far the centre of mass of the
-remaining blocks moves in the horizontal plane."""
+measures over many towers: when the towers collapse (Eq. (collapse)), how many blocks each
+tower loses to its pushes (a pushed block is removed once it has moved its withdrawal
+distance), and how far the centre of mass of the remaining blocks moves in the horizontal
+plane."""
 import os
 import sys
 
@@ -15,7 +16,8 @@ from paper_2606_28394_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-STEPS = 480   # two push windows (steps 60 and 300 of each tower's schedule)
+STEPS = 2000   # the removal episodes' full length (pushes from step 60 on, 1-8 per tower)
+PER_MU = 50    # 150 towers
 
 
 @pytest.fixture(scope="module")
@@ -41,29 +43,49 @@ def _measures(sc, x, active, x0, active0):
     return np.array(removed), np.array(drift)
 
 
-def test_removal_and_drift_distributions_match_oracle(J, oracle):
+@pytest.mark.parametrize("warm_start", [0, 1], ids=["zero_start", "previous_step_start"])
+def test_removal_and_drift_distributions_match_oracle(J, oracle, warm_start):
+    """150 towers of the removal batch over the whole episode (collapse criterion, no pushes after
+    a collapse, held at rest).  With the zero start the towers lean over and collapse early: the
+    collapse steps and the final drifts must come from one distribution.  With the previous-step
+    start they stand through their removals: removal counts agree tower by tower."""
     from scipy.stats import ks_2samp
-    sc = W.cfg2(0, n_per_mu=32, n_steps=STEPS)   # 96 towers, 12-24 levels, seeded pushes
+    sc = W.cfg2(0, n_per_mu=PER_MU, n_steps=STEPS)
     x0 = np.asarray(sc["pos"], np.float64).reshape(-1, 3)
     a0 = np.asarray(sc["active"]).astype(np.uint8)
-    _say(f"removal batch: {sc['n_towers']} towers, {STEPS} steps on the GPU")
-    gw = J.World(sc)
+    _say(f"removal batch: {sc['n_towers']} towers, {STEPS} steps on the GPU (warm start {warm_start})")
+    gw = J.World(sc, warm_start=warm_start)
+    gw.begin_episodes()
     gw.step(STEPS)
     g_rem, g_drift = _measures(sc, gw.state()[0], np.asarray(gw.active()), x0, a0)
+    g_ep = [gw.episode(t) for t in range(sc["n_towers"])]
     assert gw.stats().error_word == 0
     gw.close()
     _say("the same on the oracle")
-    ow = oracle.OracleWorld(sc)
-    ow.step(STEPS, threads=min(16, os.cpu_count() or 1))
+    ow = oracle.OracleWorld(sc, warm_start=warm_start)
+    ow.begin_episodes()
+    ow.step_episodes(STEPS, threads=min(16, os.cpu_count() or 1))
     o_rem, o_drift = _measures(sc, ow.x, ow.active, x0, a0)
+    o_ep = [ow.episode(t) for t in range(sc["n_towers"])]
+    g_col = np.array([e.collapse_step for e in g_ep if e.collapsed])
+    o_col = np.array([e["collapse_step"] for e in o_ep if e["collapsed"]])
+    _say("collapsed: gpu", len(g_col), "oracle", len(o_col))
     _say("removals per tower: gpu", np.bincount(g_rem, minlength=3), "oracle", np.bincount(o_rem, minlength=3))
     _say("drift quartiles [m]: gpu", np.quantile(g_drift, [.25, .5, .75]), "oracle", np.quantile(o_drift, [.25, .5, .75]))
-    # removals are decided by the pushes within a few hundred steps: nearly every tower agrees
+    n = sc["n_towers"]
+    assert abs(len(g_col) - len(o_col)) <= 0.05 * n
+    if len(o_col) >= 0.5 * n:
+        _say("collapse step quartiles: gpu", np.quantile(g_col, [.25, .5, .75]), "oracle",
+             np.quantile(o_col, [.25, .5, .75]))
+        assert ks_2samp(g_col, o_col).pvalue > 0.01
+        assert abs(np.median(g_col) - np.median(o_col)) <= 0.05 * np.median(o_col)
+    # removals are decided by the pushes before any collapse: nearly every tower agrees
     assert (g_rem == o_rem).mean() >= 0.9
-    assert abs(int(g_rem.sum()) - int(o_rem.sum())) <= 0.05 * max(1, int(o_rem.sum()))
-    # the drift is a chaotic outcome: the two samples must come from one distribution
+    assert abs(int(g_rem.sum()) - int(o_rem.sum())) <= 0.05 * max(20, int(o_rem.sum()))
+    # the drift is a chaotic outcome: the two samples must come from one distribution (standing
+    # towers move by fractions of a millimetre: 0.1 mm is the floor)
     assert ks_2samp(g_drift, o_drift).pvalue > 0.01
-    assert abs(np.median(g_drift) - np.median(o_drift)) <= 0.1 * np.median(o_drift)
+    assert abs(np.median(g_drift) - np.median(o_drift)) <= 0.1 * np.median(o_drift) + 1e-4
 
 
 def test_collapse_distributions_match_oracle(J, oracle):

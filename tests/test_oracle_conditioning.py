@@ -98,3 +98,39 @@ def test_tower_spread_stays_small(oracle, oracle32):
         ri, f32 = _spread(oracle, oracle32, sc, S)
         print("tower: rounded inputs", ri, "fp32", f32, flush=True)
         assert f32["v"] < 1e-4 and f32["w"] < 1e-4
+
+
+def _lam_spread(O, O32, sc, S):
+    """Impulse and point spread (compare_contacts measures) of one step, FP32 oracle against FP64."""
+    from parity_util import compare_contacts, oracle_manifolds
+    a = O.OracleWorld(sc)
+    a.set_state(*S)
+    a.step(1)
+    b = O32.OracleWorld(sc)
+    b.set_state(*[z.astype(np.float32) for z in S])
+    b.step(1)
+    ptr = sc["tower_ptr"]
+    lam = pts = 0.0
+    for t in range(sc["n_towers"]):
+        lo, hi = int(ptr[t]), int(ptr[t + 1])
+        bm = {k: dict(v, point=np.asarray(v["point"], np.float64), lam=np.asarray(v["lam"], np.float64),
+                      normal=np.asarray(v["normal"], np.float64)) for k, v in oracle_manifolds(b, t).items()}
+        rep = compare_contacts(oracle_manifolds(a, t), bm, sc["mass"][lo:hi])
+        lam, pts = max(lam, rep["lam_err"]), max(pts, rep["point_err"])
+    return lam, pts
+
+
+@pytest.mark.slow
+def test_refface_spread_is_fp32_arithmetic(oracle, oracle32):
+    """Reference-face clipping is the FP32-sensitive manifold: on falling towers (step 150 of the
+    tilted batch) the single-precision oracle's impulses are more than 1e-4 off its FP64 self, the
+    silhouette manifolds' stay within 1e-4; both within 1e-3."""
+    spread = {}
+    for mode in (0, 1):
+        sc = W.tilted_towers(44, 10, levels_range=(8, 24))
+        sc["params"] = dict(sc["params"], manifold_mode=mode)
+        (S,) = _states(oracle, sc, [150])
+        spread[mode] = _lam_spread(oracle, oracle32, sc, S)
+        print("manifold_mode", mode, "impulse and point spread", spread[mode], flush=True)
+    assert spread[0][0] < 1e-4 and 1e-4 < spread[1][0] < 1e-3
+    assert spread[1][1] > 3 * spread[0][1] and spread[1][1] < 5e-5
