@@ -310,16 +310,20 @@ def single_tower_latency(J, torch, W):
     world = J.World(scene, stream=stream.cuda_stream)
     world.step(0)
     world.sync()
+    _synced(J, J.jg_query_phase_cycles, world.h)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     world.step(240)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    phases = _synced(J, J.jg_query_phase_cycles, world.h)
+    tot = max(1, sum(phases.values()))
     world.close()
     log(f"  removal tower: {ms / 240 * 1e3:.1f} us per step")
     return {"workload": "one 18-level tower (53 blocks after one middle block is removed), 240 steps",
-            "us_per_step": ms / 240 * 1e3}
+            "us_per_step": ms / 240 * 1e3,
+            "phase_cycle_share": {k: round(v / tot, 4) for k, v in phases.items()}}
 
 
 def literal_tilt_rate(J, torch, W, steps):

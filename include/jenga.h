@@ -129,7 +129,9 @@ typedef struct {
   int32_t colour_partition;  /* bodies per colouring partition of such a tower: its pairs are coloured
                             greedily in four passes, each in canonical order: inside a partition (or
                             with the ground), between partitions p and p + 1 for even p, then for odd
-                            p, then the rest; default 1024 */
+                            p, then the rest; partitions of up to 2,048 bodies are walked in LDS; a
+                            partition should span a course of a wall, so that a pair with the course
+                            above joins the next partition; default 1024 */
   float mega_cand_per_body;  /* broadphase candidate capacity of such a tower, per body (the list is cut
                             at the first body whose candidates do not fit, JG_ERR_CANDIDATES); 16 */
 } jg_params;

@@ -48,7 +48,8 @@ struct StepArgs {
   const int32_t* pack_slot0;
   const int64_t* pack_goff;    // [pack] word offset of the pack's region in gmem
   float* gmem;                 // per-pack regions: the contact points' lever arms and impulses
-                               // (kManDevWords per manifold slot), then, for a pack whose layout
+                               // (kManDevWords per manifold slot), their restitution targets
+                               // (kManBiasWords per slot), then, for a pack whose layout
                                // lives in device memory, the whole layout
   int32_t in_gmem;             // 1: this launch's packs keep their whole layout in gmem
   int32_t hot_bodies;          // in_gmem packs: 1 = the arrays of the serial walks also in LDS
@@ -113,8 +114,10 @@ constexpr int kBodyWords = 31;     // x3 q4 v3 w3 he3 invm invI3 flag tower Iw6 
 constexpr int kTowerWords = 14;    // body range, mu, counters4, residual2, canonical range2, points, frozen
 constexpr int kPushWords = 10;
 constexpr int kManWords = 4;       // canonical (code, pos) + sorted (code, meta)
-constexpr int kManDevWords = 32;   // r_A 12, lambda 12, n 3, depth, restitution targets 4 per
-                                   // sorted manifold, in the pack's device region
+constexpr int kManDevWords = 28;   // r_A 12, lambda 12, n 3, depth per sorted manifold, in the
+                                   // pack's device region
+constexpr int kManBiasWords = 4;   // restitution targets of a sorted manifold's points (after all
+                                   // of the pack's records; used with restitution_bias only)
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
 constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
 constexpr int kLearnedIslandWaves = 4;          // waves of a pack in device memory with the network
@@ -188,6 +191,8 @@ constexpr int kMegaBodyWords = 29;   // x3 q4 v3 w3 he3 invm invI3 Iw6 hm3 (SoA,
 constexpr int kMegaBodyU32 = 8;      // flag, tower (0), colour mask lo, hi, cell, candidate count,
                                      // candidate offset, cell-sorted body (stride nb)
 constexpr int kMegaScal = 256;       // scalar words (counters, colour tables)
+constexpr int kMegaStagedPartition = 2048;  // colouring partitions up to this size are walked in LDS
+constexpr int kMegaChunk = 1024;            // pairs staged in LDS per walk chunk
 
 struct MegaArgs {
   float *x, *q, *v, *w;
@@ -217,6 +222,7 @@ struct MegaArgs {
   int32_t cand_cap;
   int32_t* man;                // 7 * cand_cap: canonical a, b, colour, sorted slot; sorted a, b, meta
   float* md;                   // kManDevWords * cand_cap, colour-sorted records
+  float* mtb;                  // kManBiasWords * cand_cap, their restitution targets
   int32_t* part;               // nparts + 1 first canonical manifold of each partition, then nparts far counts
   int32_t nparts;
   float* red;                  // 2 * gridDim partial sums (residual)
@@ -231,8 +237,8 @@ struct MegaArgs {
 
 // queues the cooperative launch of an island's steps (blocks from mega_blocks); a hipError_t
 int launch_mega(const MegaArgs& a, int blocks, void* stream);
-// the workgroups of the grid-wide kernel: every one resident at once (the occupancy of the
-// current device times its CUs, at most two per CU); a hipError_t
-int mega_blocks(int* blocks);
+// the workgroups of the grid-wide kernel for an island of `bodies` bodies: every one resident at
+// once (at most the occupancy of the current device times its CUs, two per CU); a hipError_t
+int mega_blocks(int bodies, int* blocks);
 
 }  // namespace jg

@@ -86,6 +86,7 @@ struct Lds {
   // colour-sorted manifolds
   uint32_t *mab, *mmeta;
   uint32_t *lmlo, *lmhi;   // colouring: per-body lane masks of the current chunk (low, high lanes)
+  float* mtb;         // device block after the records: restitution targets, 4 per sorted manifold
   float* md;          // device block, kManDevWords per sorted manifold: r_A [12] (contact frame
                       // (n, t1, t2)), lambda [12], n [3], depth (see mdev)
   // warm start: sorted -> canonical, previous step store (canonical order)
@@ -144,6 +145,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool u
   L.cab = (uint32_t*)take(pc); L.cpos = (int32_t*)take(pc);
   L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc);
   L.md = dev;
+  L.mtb = dev + (size_t)kManDevWords * pc;
   if (mode >= 1) {
     L.mcanon = (int32_t*)take(pc);
     L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
@@ -1054,7 +1056,7 @@ __device__ __forceinline__ void fetch_points(const Lds& L, int m, ManPoints& d, 
   const float4 nd = rec[6];
   d.n[0] = nd.x; d.n[1] = nd.y; d.n[2] = nd.z;
   if (bias) {
-    const float4 tb = rec[7];
+    const float4 tb = *reinterpret_cast<const float4*>(L.mtb + 4 * (size_t)m);
     d.tb[0] = tb.x; d.tb[1] = tb.y; d.tb[2] = tb.z; d.tb[3] = tb.w;
   } else {
     d.tb[0] = d.tb[1] = d.tb[2] = d.tb[3] = 0.f;
@@ -1210,8 +1212,8 @@ __device__ __forceinline__ void pair_open(const Lds& L, int a, int b, bool groun
 }
 
 // natural-map residual of one pair's record (np points): sum of squares and max |r| over its rows
-__device__ __forceinline__ void residual_rec(const Lds& L, const float* rec, int a, int b, bool ground, int np,
-                                             float mu, const SolveOpts& o, float& sum, float& mx) {
+__device__ __forceinline__ void residual_rec(const Lds& L, const float* rec, const float* tb, int a, int b, bool ground,
+                                             int np, float mu, const SolveOpts& o, float& sum, float& mx) {
   Frame F;
   LBody A, B;
   float dAB[3];
@@ -1232,7 +1234,7 @@ __device__ __forceinline__ void residual_rec(const Lds& L, const float* rec, int
     {
       RowTerms<0> t;
       t.build(A, B, rA, rB);
-      const float target = o.bias ? rec[28 + j] : 0.f;
+      const float target = o.bias ? tb[j] : 0.f;
       res[0] = fminf(t.k * lam[0], t.vrel(A, B) - target);
     }
     RowTerms<1> t1;
@@ -1261,7 +1263,8 @@ __device__ __forceinline__ void residual_manifold(const Lds& L, int m, float mu,
                                                   float& mx) {
   const uint32_t ab = L.mab[m];
   const int b = (int)(ab & 0xffffu);
-  residual_rec(L, mdev(L, m), (int)(ab >> 16), b, b == (int)kGround, (int)(L.mmeta[m] & 15u), mu, o, sum, mx);
+  residual_rec(L, mdev(L, m), L.mtb + 4 * (size_t)m, (int)(ab >> 16), b, b == (int)kGround, (int)(L.mmeta[m] & 15u),
+               mu, o, sum, mx);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1531,12 +1534,12 @@ __device__ __forceinline__ int manifold_geometry(const Lds& L, int i, int j, boo
   return npts;
 }
 
-// The restitution targets of the pair's normal rows (restitution_bias): rec[28 + q] for its points,
+// The restitution targets of the pair's normal rows (restitution_bias): tb[q] for its points,
 // -e v_n- from the velocities before any impulse of the step, in the contact frame (n is its first
 // axis), for a point approaching faster than twice |g| dt (a resting contact approaches at about
 // |g| dt per step and does not bounce).
-__device__ __forceinline__ void bias_targets(const Lds& L, int i, int j, bool ground, float* rec, int npts,
-                                             const float n[3], const float g[3], float dt, float e) {
+__device__ __forceinline__ void bias_targets(const Lds& L, int i, int j, bool ground, const float* rec, float* tb,
+                                             int npts, const float n[3], const float g[3], float dt, float e) {
   const int NB = L.nbp;
   const float vth = 2.f * sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * dt;
   Frame F;
@@ -1560,7 +1563,7 @@ __device__ __forceinline__ void bias_targets(const Lds& L, int i, int j, bool gr
       const float vn = (vB[0] + (wB[1] * rb[2] - wB[2] * rb[1])) - (vA[0] + (wA[1] * ra[2] - wA[2] * ra[1]));
       tgt = vn < -vth ? -e * vn : 0.f;
     }
-    rec[28 + q] = tgt;
+    tb[q] = tgt;
   }
 }
 
@@ -1609,7 +1612,8 @@ __device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a,
       mdev(L, sidx)[12 + q * 3 + 1] = l1;
       mdev(L, sidx)[12 + q * 3 + 2] = l2;
     }
-    if (kExt && a.restitution_bias) bias_targets(L, i, j, j == (int)kGround, mdev(L, sidx), npts, n, a.g, a.dt, a.restitution);
+    if (kExt && a.restitution_bias)
+      bias_targets(L, i, j, j == (int)kGround, mdev(L, sidx), L.mtb + 4 * (size_t)sidx, npts, n, a.g, a.dt, a.restitution);
     L.mab[sidx] = code;
     L.mmeta[sidx] = (uint32_t)npts | (slots << 12);
     mdev(L, sidx)[27] = depth;
@@ -2036,7 +2040,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   constexpr int kThreads = step_threads<kLearned, kGlobal>();
   extern __shared__ __align__(16) float smem[];
   float* const dev = a.gmem + a.pack_goff[a.pack_first + blockIdx.x];
-  const Lds L = carve(kGlobal ? dev + kManDevWords * a.pc : smem, dev, smem, kGlobal, kGlobal && kHot, a);
+  const Lds L = carve(kGlobal ? dev + (kManDevWords + kManBiasWords) * a.pc : smem, dev, smem, kGlobal, kGlobal && kHot, a);
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   if constexpr (kThreads > kWave) {
     if (threadIdx.x >= kWave) {
@@ -3006,7 +3010,6 @@ __device__ __forceinline__ void colour_pair(int m, int a, int b, const uint32_t*
     const uint64_t bit = 1ull << col;
     if (da) { mlo[a] |= (uint32_t)bit; mhi[a] |= (uint32_t)(bit >> 32); }
     if (db) { mlo[b] |= (uint32_t)bit; mhi[b] |= (uint32_t)(bit >> 32); }
-    atomicAdd(&S[sColCnt + col], 1);
   } else {
     atomicOr(&S[sErr], (int)kErrCol);
   }
@@ -3014,7 +3017,7 @@ __device__ __forceinline__ void colour_pair(int m, int a, int b, const uint32_t*
 }
 
 // one PGS visit of the record at `rec` (pair a, b; b < 0: the ground), one thread
-__device__ __forceinline__ void solve_rec(const Lds& L, float* rec, int a, int b, int np, float mu,
+__device__ __forceinline__ void solve_rec(const Lds& L, float* rec, const float* tbp, int a, int b, int np, float mu,
                                           const SolveOpts& o) {
   float r[12], l[12], tb[4];
   const float4* r4 = reinterpret_cast<const float4*>(rec);
@@ -3024,7 +3027,8 @@ __device__ __forceinline__ void solve_rec(const Lds& L, float* rec, int a, int b
     r[4 * c] = x.x; r[4 * c + 1] = x.y; r[4 * c + 2] = x.z; r[4 * c + 3] = x.w;
     l[4 * c] = y.x; l[4 * c + 1] = y.y; l[4 * c + 2] = y.z; l[4 * c + 3] = y.w;
   }
-  const float4 nd = r4[6], t4 = r4[7];
+  const float4 nd = r4[6];
+  const float4 t4 = o.bias ? *reinterpret_cast<const float4*>(tbp) : make_float4(0.f, 0.f, 0.f, 0.f);
   const float n[3] = {nd.x, nd.y, nd.z};
   tb[0] = o.bias ? t4.x : 0.f; tb[1] = o.bias ? t4.y : 0.f; tb[2] = o.bias ? t4.z : 0.f; tb[3] = o.bias ? t4.w : 0.f;
   const bool ground = b < 0;
@@ -3055,6 +3059,10 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
   cg::grid_group grid = cg::this_grid();
   __shared__ int32_t sh[kMegaThreads], sh2[kMegaThreads];
   __shared__ float shf[kMegaThreads], shf2[kMegaThreads];
+  // partition walks: colour masks (2 words) and dynamic flags of up to two partitions, pairs
+  __shared__ uint32_t lmask[4 * kMegaStagedPartition];
+  __shared__ uint8_t ldyn[2 * kMegaStagedPartition];
+  __shared__ int32_t lpair[2 * kMegaChunk];
   const int NB = a.nb, CAP = a.cap, CC = a.cand_cap;
   const int gt = (int)blockIdx.x * kMegaThreads + (int)threadIdx.x;
   const int GS = (int)gridDim.x * kMegaThreads;
@@ -3219,14 +3227,24 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
           }
           hmax = fmaxf(hmax, __shfl_xor(hmax, d));
         }
+        // then across the block's waves in LDS, one atomic per block and quantity
+        const int wv = (int)threadIdx.x / kWave;
         if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            atomicMin(reinterpret_cast<uint32_t*>(&S[sLo + k]), ford(lo[k]));
-            atomicMax(reinterpret_cast<uint32_t*>(&S[sHi + k]), ford(hi[k]));
-          }
-          atomicMax(reinterpret_cast<uint32_t*>(&S[sHmax]), ford(hmax));
+          for (int k = 0; k < 3; ++k) { shf[8 * wv + k] = lo[k]; shf[8 * wv + 3 + k] = hi[k]; }
+          shf[8 * wv + 6] = hmax;
         }
+        __syncthreads();
+        if (threadIdx.x < 7) {
+          const int q = (int)threadIdx.x;
+          float v = shf[q];
+          for (int w2 = 1; w2 < kMegaThreads / kWave; ++w2)
+            v = (q < 3) ? fminf(v, shf[8 * w2 + q]) : fmaxf(v, shf[8 * w2 + q]);
+          if (q < 3) atomicMin(reinterpret_cast<uint32_t*>(&S[sLo + q]), ford(v));
+          else if (q < 6) atomicMax(reinterpret_cast<uint32_t*>(&S[sHi + q - 3]), ford(v));
+          else atomicMax(reinterpret_cast<uint32_t*>(&S[sHmax]), ford(v));
+        }
+        __syncthreads();
       }
       grid.sync();
       const Grid G = make_grid(S, a.margin, a.ncell_cap);
@@ -3372,17 +3390,76 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
         if (p < a.nparts) far[p] = 0;
       }
       grid.sync();
-      for (int pass = 0; pass < 3; ++pass) {
-        for (int p = gt; p < a.nparts; p += GS) {
-          if (pass > 0 && (p & 1) != pass - 1) continue;
-          for (int m = a.part[p]; m < a.part[p + 1]; ++m) {
-            const int i = man_a[m], j = man_b[m];
-            const int pj = j < 0 ? p : j / PS;
-            if (pass == 0 && pj > p + 1) ++far[p];
-            if ((pass == 0 && pj == p) || (pass > 0 && pj == p + 1)) colour_pair(m, i, j, L.flag, mlo, mhi, man_col, S);
+      if (PS <= kMegaStagedPartition) {
+        // one workgroup per partition (pass 1) or partition pair (passes 2, 3): the bodies' colour
+        // masks and dynamic flags and the pairs, in chunks, staged in LDS; its first thread walks them
+        for (int pass = 0; pass < 3; ++pass) {
+          for (int p = (int)blockIdx.x; p < a.nparts; p += (int)gridDim.x) {
+            if (pass > 0 && (p & 1) != pass - 1) continue;
+            const int b0 = p * PS, nbp = min((pass == 0 ? 1 : 2) * PS, NB - b0);
+            for (int i = (int)threadIdx.x; i < nbp; i += kMegaThreads) {
+              lmask[2 * i] = mlo[b0 + i];
+              lmask[2 * i + 1] = mhi[b0 + i];
+              ldyn[i] = (L.flag[b0 + i] & kDynamic) ? 1 : 0;
+            }
+            int nfar = 0;
+            for (int c0 = a.part[p]; c0 < a.part[p + 1]; c0 += kMegaChunk) {
+              const int n = min(kMegaChunk, a.part[p + 1] - c0);
+              __syncthreads();
+              for (int k = (int)threadIdx.x; k < n; k += kMegaThreads) {
+                lpair[2 * k] = man_a[c0 + k] - b0;
+                lpair[2 * k + 1] = man_b[c0 + k];
+              }
+              __syncthreads();
+              if (threadIdx.x == 0) {
+                for (int k = 0; k < n; ++k) {
+                  // the second body's place: the ground or this partition (0), the next (1), further (2)
+                  const int i = lpair[2 * k], jg = lpair[2 * k + 1];
+                  const int j = jg < 0 ? -1 : jg - b0;
+                  const int where = j < PS ? 0 : (j < 2 * PS ? 1 : 2);
+                  if (pass == 0 && where == 2) ++nfar;
+                  if (where != (pass == 0 ? 0 : 1)) continue;
+                  const bool da = ldyn[i] != 0, db = j >= 0 && ldyn[j] != 0;
+                  uint64_t u = 0ull;
+                  if (da) u |= (uint64_t)lmask[2 * i] | ((uint64_t)lmask[2 * i + 1] << 32);
+                  if (db) u |= (uint64_t)lmask[2 * j] | ((uint64_t)lmask[2 * j + 1] << 32);
+                  int col = -1;
+                  if (u != ~0ull) {
+                    col = __ffsll((unsigned long long)~u) - 1;
+                    const uint64_t bit = 1ull << col;
+                    if (da) { lmask[2 * i] |= (uint32_t)bit; lmask[2 * i + 1] |= (uint32_t)(bit >> 32); }
+                    if (db) { lmask[2 * j] |= (uint32_t)bit; lmask[2 * j + 1] |= (uint32_t)(bit >> 32); }
+                  } else {
+                    atomicOr(&S[sErr], (int)kErrCol);
+                  }
+                  man_col[c0 + k] = col;
+                }
+              }
+            }
+            __syncthreads();
+            for (int i = (int)threadIdx.x; i < nbp; i += kMegaThreads) {
+              mlo[b0 + i] = lmask[2 * i];
+              mhi[b0 + i] = lmask[2 * i + 1];
+            }
+            if (pass == 0 && threadIdx.x == 0) far[p] = nfar;
+            __syncthreads();
           }
+          grid.sync();
         }
-        grid.sync();
+      } else {
+        // partitions too large to stage: one thread per partition (pair), from device memory
+        for (int pass = 0; pass < 3; ++pass) {
+          for (int p = gt; p < a.nparts; p += GS) {
+            if (pass > 0 && (p & 1) != pass - 1) continue;
+            for (int m = a.part[p]; m < a.part[p + 1]; ++m) {
+              const int i = man_a[m], j = man_b[m];
+              const int pj = j < 0 ? p : j / PS;
+              if (pass == 0 && pj > p + 1) ++far[p];
+              if ((pass == 0 && pj == p) || (pass > 0 && pj == p + 1)) colour_pair(m, i, j, L.flag, mlo, mhi, man_col, S);
+            }
+          }
+          grid.sync();
+        }
       }
       // the pairs between partitions further apart: one thread, canonical order
       if (gt == 0) {
@@ -3393,6 +3470,23 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
             if (j >= 0 && j / PS > p + 1) colour_pair(m, i, j, L.flag, mlo, mhi, man_col, S);
           }
         }
+      }
+      grid.sync();
+      // colour-sorted slots (the order inside a colour is free: its pairs share no dynamic body):
+      // each workgroup counts the colours of a contiguous run of the canonical list in LDS (ranks
+      // from LDS atomics), adds its counts once per colour, and takes a range of every colour
+      const int chunk = (nman + (int)gridDim.x - 1) / (int)gridDim.x;
+      const int cm0 = min(nman, (int)blockIdx.x * chunk), cm1 = min(nman, cm0 + chunk);
+      if (threadIdx.x < kMaxColours) sh[threadIdx.x] = 0;
+      __syncthreads();
+      for (int m = cm0 + (int)threadIdx.x; m < cm1; m += kMegaThreads) {
+        const int c = man_col[m];
+        man_slot[m] = c >= 0 ? atomicAdd(&sh[c], 1) : -1;
+      }
+      __syncthreads();
+      if (threadIdx.x < kMaxColours && sh[threadIdx.x] > 0) atomicAdd(&S[sColCnt + threadIdx.x], sh[threadIdx.x]);
+      grid.sync();
+      if (gt == 0) {
         int off = 0, ncol = 0;
         for (int c = 0; c < kMaxColours; ++c) {
           const int n = S[sColCnt + c];
@@ -3406,12 +3500,15 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
       }
       grid.sync();
       const int ncol = S[sNcol];
-      // colour-sorted slots (the order inside a colour is free: its pairs share no dynamic body)
-      for (int m = gt; m < nman; m += GS) {
+      if (threadIdx.x < kMaxColours)
+        sh2[threadIdx.x] = sh[threadIdx.x] > 0 ? S[sColOff + threadIdx.x] + atomicAdd(&S[sColCur + threadIdx.x], sh[threadIdx.x])
+                                               : 0;
+      __syncthreads();
+      for (int m = cm0 + (int)threadIdx.x; m < cm1; m += kMegaThreads) {
         const int c = man_col[m];
         int slot = -1;
         if (c >= 0) {
-          slot = S[sColOff + c] + atomicAdd(&S[sColCur + c], 1);
+          slot = sh2[c] + man_slot[m];
           s_a[slot] = man_a[m];
           s_b[slot] = man_b[m];
         }
@@ -3432,7 +3529,8 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
           const int np = manifold_geometry<true>(L, i, ground ? 0 : j, ground, a.manifold_mode, rec, n, depth, slots);
 #pragma unroll
           for (int k = 0; k < 12; ++k) rec[12 + k] = 0.f;
-          if (a.restitution_bias) bias_targets(L, i, ground ? 0 : j, ground, rec, np, n, a.g, dt, a.restitution);
+          if (a.restitution_bias)
+            bias_targets(L, i, ground ? 0 : j, ground, rec, a.mtb + 4 * (size_t)slot, np, n, a.g, dt, a.restitution);
 #pragma unroll
           for (int k = 0; k < 3; ++k) rec[24 + k] = n[k];
           rec[27] = depth;
@@ -3453,8 +3551,8 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
         for (int c = 0; c < ncol; ++c) {
           const int c1 = S[sColOff + c + 1];
           for (int slot = S[sColOff + c] + gt; slot < c1; slot += GS)
-            solve_rec(L, a.md + (size_t)slot * kManDevWords, s_a[slot], s_b[slot], (int)(s_meta[slot] & 15u), a.mu,
-                      opts);
+            solve_rec(L, a.md + (size_t)slot * kManDevWords, a.mtb + 4 * (size_t)slot, s_a[slot], s_b[slot],
+                      (int)(s_meta[slot] & 15u), a.mu, opts);
           grid.sync();
         }
       }
@@ -3505,7 +3603,8 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
           float s2, m2;
           const int j = man_b[m];
           const int np = (int)(s_meta[slot] & 15u);
-          residual_rec(L, a.md + (size_t)slot * kManDevWords, man_a[m], j < 0 ? 0 : j, j < 0, np, a.mu, opts, s2, m2);
+          residual_rec(L, a.md + (size_t)slot * kManDevWords, a.mtb + 4 * (size_t)slot, man_a[m], j < 0 ? 0 : j, j < 0,
+                       np, a.mu, opts, s2, m2);
           sum += s2;
           mx = fmaxf(mx, m2);
           pts += np;
@@ -3674,13 +3773,17 @@ int launch_step(const StepArgs& a, size_t lds_bytes, void* stream) {
 
 namespace jg {
 
-int mega_blocks(int* blocks) {
+int mega_blocks(int bodies, int* blocks) {
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mega_kernel, kMegaThreads, 0);
   if (e != hipSuccess) return (int)e;
-  *blocks = std::max(1, std::min(per, 2)) * std::max(1, cus);
+  const int most = std::max(1, std::min(per, 2)) * std::max(1, cus);
+  // a grid-wide barrier costs about 0.1 us per workgroup (their arrivals are serialised), a colour
+  // of the sweeps about 1.4 us per round of visits: about one workgroup per 3,072 bodies keeps
+  // a colour (about a quarter of the bodies in pairs) to a few rounds
+  *blocks = std::min(most, std::max(4, (bodies + 3071) / 3072));
   return 0;
 }
 

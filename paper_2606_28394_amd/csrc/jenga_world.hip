@@ -161,7 +161,7 @@ struct jg_world {
   // order, each with its own scratch
   struct Mega {
     int tower = -1, g0 = 0, nb = 0, tslot = 0, p0 = 0, np = 0;
-    int ncell_cap = 0, cand_cap = 0, nparts = 0;
+    int ncell_cap = 0, cand_cap = 0, nparts = 0, grid = 0;
     DevBuf<float> body, md, red, out_geo, out_pts;
     DevBuf<uint32_t> ubody, cand, out_meta, err;
     DevBuf<int32_t> cells, man, part, ired, scal, out_a, out_b, out_count;
@@ -177,7 +177,6 @@ struct jg_world {
   };
   std::vector<Mega> megas;
   std::vector<int> mega_of_tower;   // tower id -> index in megas (-1: in a pack)
-  int mega_grid = 0;                // workgroups of their cooperative launches
 };
 
 namespace {
@@ -433,7 +432,7 @@ int32_t build_layout(jg_world* w) {
         return fail(JG_ECAPACITY, "a pack kept in device memory needs " + std::to_string(c.lds) +
                                   " bytes of LDS for its towers and pushes (max 163840)");
       // (with the network, every wave of the island has its own staging rows)
-      c.gwords = ((int64_t)jg::kManDevWords * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
+      c.gwords = ((int64_t)(jg::kManDevWords + jg::kManBiasWords) * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
                   (mode == 2 ? (int64_t)(jg::kLearnedIslandWaves - 1) * jg::kStageWords : 0) +
                   jg::window_words(c.nbp) + 2 * (int64_t)jg::kCandPerBody * c.nbp + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
@@ -441,7 +440,7 @@ int32_t build_layout(jg_world* w) {
       c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
       if (c.lds > 160 * 1024)
         return fail(JG_ECAPACITY, "a launch class needs " + std::to_string(c.lds) + " bytes of LDS (max 163840)");
-      c.gwords = ((int64_t)jg::kManDevWords * c.pc + 3) & ~(int64_t)3;
+      c.gwords = ((int64_t)(jg::kManDevWords + jg::kManBiasWords) * c.pc + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
     }
     for (int k = 0; k < c.count; ++k) w->pack_slot0.push_back(w->pack_slot0.back() + c.pc);
@@ -503,10 +502,10 @@ int32_t build_layout(jg_world* w) {
   HIP_TRY(hipMemcpy(w->d_body_tower.p, btw.data(), sizeof(int32_t) * w->max_bodies, hipMemcpyHostToDevice));
   // scratch of the towers stepped by the whole GPU
   if (!w->megas.empty()) {
-    if (int e = jg::mega_blocks(&w->mega_grid))
-      return fail(JG_EDEVICE, std::string("sizing the grid-wide launch: ") + hipGetErrorString((hipError_t)e));
-    const size_t G = (size_t)w->mega_grid;
     for (auto& m : w->megas) {
+      if (int e = jg::mega_blocks(m.nb, &m.grid))
+        return fail(JG_EDEVICE, std::string("sizing the grid-wide launch: ") + hipGetErrorString((hipError_t)e));
+      const size_t G = (size_t)m.grid;
       const size_t nb = (size_t)m.nb;
       m.ncell_cap = (int)std::min<size_t>(2 * nb + 64, (size_t)1 << 30);
       const double cc = std::ceil((double)w->prm.mega_cand_per_body * (double)nb);
@@ -519,7 +518,7 @@ int32_t build_layout(jg_world* w) {
       HIP_TRY(m.cells.ensure(2 * ((size_t)m.ncell_cap + 1)));
       HIP_TRY(m.cand.ensure(3 * C));
       HIP_TRY(m.man.ensure(7 * C));
-      HIP_TRY(m.md.ensure((size_t)jg::kManDevWords * C));
+      HIP_TRY(m.md.ensure((size_t)(jg::kManDevWords + jg::kManBiasWords) * C));
       HIP_TRY(m.part.ensure(2 * (size_t)m.nparts + 1));
       HIP_TRY(m.red.ensure(2 * G + 2));
       HIP_TRY(m.ired.ensure(G + 1));
@@ -1081,10 +1080,11 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
     g.step0 = w->step;
     g.body = m.body.p; g.ubody = m.ubody.p; g.cells = m.cells.p; g.ncell_cap = m.ncell_cap;
     g.cand = m.cand.p; g.cand_cap = m.cand_cap; g.man = m.man.p; g.md = m.md.p;
+    g.mtb = m.md.p + (size_t)jg::kManDevWords * m.cand_cap;
     g.part = m.part.p; g.nparts = m.nparts; g.red = m.red.p; g.ired = m.ired.p; g.scal = m.scal.p;
     g.out_a = m.out_a.p; g.out_b = m.out_b.p; g.out_meta = m.out_meta.p; g.out_geo = m.out_geo.p;
     g.out_pts = m.out_pts.p; g.out_count = m.out_count.p;
-    if (int e = jg::launch_mega(g, w->mega_grid, w->stream))
+    if (int e = jg::launch_mega(g, m.grid, w->stream))
       return fail(JG_EDEVICE, std::string("grid-wide island launch: ") + hipGetErrorString((hipError_t)e));
   }
   w->step += n_steps;
