@@ -555,6 +555,23 @@ def main():
         "error_word": int(s1.error_word),
         "residual_rms_max": s1.residual_rms,
     }
+    # the same batch while it collapses (dense dynamic contacts): untimed steps up to step 200 after
+    # the timed window, then the same number of timed steps again
+    lead = max(0, 200 - args.steps)
+    if lead:
+        world.step(lead)
+        _synced(J, world.sync)
+    n2 = max(20, args.steps)
+    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev2.record(stream)
+    world.step(n2)
+    ev3.record(stream)
+    torch.cuda.synchronize()
+    ms2 = ev2.elapsed_time(ev3)
+    first = args.steps + lead + 1
+    out["collapse_phase"] = {"steps": f"{first}-{first + n2 - 1}", "tower_steps_per_s": T * n2 / (ms2 * 1e-3),
+                             "kernel_ms": ms2, "error_word": int(_synced(J, world.stats).error_word)}
+    log(f"collapse phase (steps {first}-{first + n2 - 1}): {T * n2 / (ms2 * 1e-3):.4g} tower-steps/s")
     world.close()
     if not args.no_extra:
         log("single-tower latency and standing-tower legs ...")
