@@ -107,9 +107,10 @@ typedef struct {
                             rest (Sec. "Full Floor Contact Simulation"); 400 */
   /* solver variants (Sec. "Contact Solver --- Projected Gauss-Seidel (PGS)") */
   int32_t friction_cone; /* 0: each tangent clipped to +-mu lambda_n (Eq. (coulomb_pgs)); 1: the two
-                            tangent rows of a point solved from the same velocities and their impulse
-                            pair projected onto the disc of radius mu lambda_n (the circular cone of the
-                            PGS figure); default 0 */
+                            tangent rows of a point solved from the same velocities with one inverse
+                            effective mass (the larger eigenvalue of their 2 x 2 block) and their
+                            impulse pair projected onto the disc of radius mu lambda_n (the circular
+                            cone of the PGS figure); default 0 */
   int32_t restitution_bias;  /* 0: Eq. (lambda_n) as printed, (1 + e) times the current normal velocity
                             in every iteration; 1: the normal row drives the point's normal velocity to
                             -e v_n-, v_n- its normal velocity before any impulse of the step, when the
@@ -134,6 +135,12 @@ typedef struct {
                             above joins the next partition; default 1024 */
   float mega_cand_per_body;  /* broadphase candidate capacity of such a tower, per body (the list is cut
                             at the first body whose candidates do not fit, JG_ERR_CANDIDATES); 16 */
+  int32_t small_batch;   /* 0: a batch with at most two towers per CU, stepped with the zero or the
+                            previous-step start and no feature records, gets one workgroup of four
+                            waves per tower: the first steps it, all four build its manifolds, solve
+                            it (each lane pair keeping one manifold's row terms in registers for the
+                            whole solve) and sum its residual; the results are bit for bit those of
+                            one wave per tower; -1: never; default 0 */
 } jg_params;
 
 /* One contact point of the last solved step. */

@@ -639,6 +639,30 @@ static double eff_inv_mass(double invmA, const double* IA, double invmB, const d
   return k;
 }
 
+/* the coupling of two rows d1, d2 of one point: the off-diagonal entry J1 M^-1 J2^T of the
+ * contact's inverse effective mass matrix, (m_A^-1 + m_B^-1) d1.d2 + sum (r x d1).I^-1 (r x d2) */
+static double eff_inv_mass_cross(double invmA, const double* IA, double invmB, const double* IB,
+                                 const double rA[3], const double rB[3], const double d1[3], const double d2[3]) {
+  double k = (invmA + invmB) * dot3(d1, d2);
+  double c1[3], c2[3], ic[3];
+  if (IA) {
+    cross3(rA, d1, c1); cross3(rA, d2, c2); mat_vec(IA, c2, ic);
+    k += dot3(c1, ic);
+  }
+  if (IB) {
+    cross3(rB, d1, c1); cross3(rB, d2, c2); mat_vec(IB, c2, ic);
+    k += dot3(c1, ic);
+  }
+  return k;
+}
+
+/* the larger eigenvalue of the tangent block [[k1, k12], [k12, k2]] of a point: the step 1 / kt
+ * along the slip never overshoots in any direction of the pair */
+static double tangent_block_max(double k1, double k2, double k12) {
+  const double h = 0.5 * (k1 - k2);
+  return 0.5 * (k1 + k2) + sqrt(h * h + k12 * k12);
+}
+
 /* apply impulse P (along d, magnitude dl): A gets -P, B gets +P */
 static void apply_impulse(double invmA, const double* IA, double* vA, double* wA,
                           double invmB, const double* IB, double* vB, double* wB,
@@ -695,6 +719,7 @@ static void prep_k(const body_view* bv, or_manifold* ms, int nm) {
       m->k[i][0] = eff_inv_mass(invmA, IA, invmB, IB, rA, rB, m->normal);
       m->k[i][1] = eff_inv_mass(invmA, IA, invmB, IB, rA, rB, m->t1);
       m->k[i][2] = eff_inv_mass(invmA, IA, invmB, IB, rA, rB, m->t2);
+      m->k12[i] = eff_inv_mass_cross(invmA, IA, invmB, IB, rA, rB, m->t1, m->t2);
     }
   }
 }
@@ -753,10 +778,10 @@ static void pgs_sweep(const body_view* bv, or_manifold* ms, int nm, const solve_
       m->lam[i][0] = ln;
       double bound = mu * m->lam[i][0];
       if (o->cone) {
-        /* both tangent rows from the same velocities, with one inverse effective mass (the
-         * larger of the two) so that the update points against the slip velocity; the pair is
-         * then projected onto the disc */
-        const double kt = m->k[i][1] > m->k[i][2] ? m->k[i][1] : m->k[i][2];
+        /* both tangent rows from the same velocities, with one inverse effective mass (the larger
+         * eigenvalue of the pair's 2 x 2 block) so that the update points against the slip
+         * velocity and overshoots in no direction; the pair is then projected onto the disc */
+        const double kt = tangent_block_max(m->k[i][1], m->k[i][2], m->k12[i]);
         double v1 = rel_vel(vA, wA, vB, wB, rA, rB, m->t1);
         double v2 = rel_vel(vA, wA, vB, wB, rA, rB, m->t2);
         double l1 = m->lam[i][1] - v1 / kt;
@@ -801,7 +826,7 @@ static void residual(const body_view* bv, const or_manifold* ms, int nm, const s
       sum += r * r; if (fabs(r) > mx) mx = fabs(r);
       double bound = mu * m->lam[i][0];
       double cl[3], kr[3];
-      const double kt = m->k[i][1] > m->k[i][2] ? m->k[i][1] : m->k[i][2];
+      const double kt = tangent_block_max(m->k[i][1], m->k[i][2], m->k12[i]);
       for (int t = 1; t <= 2; ++t) {
         const double* d = (t == 1) ? m->t1 : m->t2;
         double wt = rel_vel(vA, wA, vB, wB, rA, rB, d);

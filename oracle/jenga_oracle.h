@@ -80,6 +80,7 @@ typedef struct {
   double lam[4][3];      /* accumulated impulses (normal, t1, t2) after the solve */
   double k[4][3];        /* inverse effective masses (normal, t1, t2) */
   double vbias[4];       /* restitution targets of the normal rows (restitution_bias) */
+  double k12[4];         /* coupling of the two tangent rows (t1 and t2) of a point (disc friction) */
 } or_manifold;
 
 enum {

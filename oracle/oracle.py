@@ -53,7 +53,7 @@ class Manifold(C.Structure):
                 ("normal", C.c_double * 3), ("t1", C.c_double * 3), ("t2", C.c_double * 3),
                 ("depth", C.c_double), ("sigma", C.c_double),
                 ("point", (C.c_double * 3) * 4), ("lam", (C.c_double * 3) * 4), ("k", (C.c_double * 3) * 4),
-                ("vbias", C.c_double * 4)]
+                ("vbias", C.c_double * 4), ("k12", C.c_double * 4)]
 
 
 class Stats(C.Structure):

@@ -104,6 +104,7 @@ struct StepArgs {
   int32_t manifold_mode;       // 0: literal silhouettes; 1: reference-face clipping
   int64_t step0;
   // capacities of this launch (LDS layout)
+  int32_t lat;     // 1: one tower per 256-thread workgroup (small batches), sweeps from registers
   int32_t nbp;     // bodies per pack
   int32_t pc;      // manifolds per pack
   int32_t tpc;     // towers per pack

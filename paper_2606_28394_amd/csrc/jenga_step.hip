@@ -46,6 +46,7 @@ namespace {
 
 constexpr uint32_t kGround = 0xffffu;
 constexpr int kIslandWaves = 8;   // waves of a workgroup that steps an island in device memory
+constexpr int kLatencyWaves = 4;  // waves of a workgroup that steps one tower of a small batch
 constexpr int kMaxDevices = 64;
 
 // A barrier among the lanes of one wave.  Every phase runs on one wave (the workgroup's first),
@@ -870,19 +871,24 @@ struct SolveOpts {
   bool cone, bias;
 };
 
-// the row's new impulse from its relative velocity u and inverse effective mass k:
-// Eq. (lambda_n) with restitution for the normal row, the clipped Eq. (coulomb_pgs) for a tangent
+// the row's new impulse from its relative velocity u and the reciprocal rk of its inverse
+// effective mass k: Eq. (lambda_n) with restitution for the normal row, the clipped
+// Eq. (coulomb_pgs) for a tangent
 template <bool kNormal>
-__device__ __forceinline__ float row_lambda(float lam, float u, float k, float bound, const SolveOpts& o,
-                                            float target) {
+__device__ __forceinline__ float row_lambda_rk(float lam, float u, float rk, float bound, const SolveOpts& o,
+                                               float target) {
 #pragma clang fp contract(off)
-  const float rk = __builtin_amdgcn_rcpf(k);
   if constexpr (kNormal) {
     if (o.bias) return fmaxf(__builtin_fmaf(target - u, rk, lam), 0.f);
     return fmaxf(__builtin_fmaf(-((1.f + o.e) * u), rk, lam), 0.f);
   } else {
     return fminf(fmaxf(__builtin_fmaf(-u, rk, lam), -bound), bound);
   }
+}
+template <bool kNormal>
+__device__ __forceinline__ float row_lambda(float lam, float u, float k, float bound, const SolveOpts& o,
+                                            float target) {
+  return row_lambda_rk<kNormal>(lam, u, __builtin_amdgcn_rcpf(k), bound, o, target);
 }
 
 // the tangent pair's unclipped new impulses projected onto the disc of radius b (both lanes of a
@@ -914,26 +920,6 @@ __device__ __forceinline__ void row_single(LBody& A, LBody& B, const float rA[3]
   lam = nl;
 }
 
-// k and the relative velocity of row K on one lane (both bodies), and the impulse dl applied
-template <int K>
-__device__ __forceinline__ void row_ku(const LBody& A, const LBody& B, const float rA[3], const float rB[3], float& k,
-                                       float& u) {
-#pragma clang fp contract(off)
-  SideRow<K> ta, tb;
-  ta.build(A, rA);
-  tb.build(B, rB);
-  k = ta.kpart(A) + tb.kpart(B);
-  u = tb.vpart(B) - ta.vpart(A);
-}
-template <int K>
-__device__ __forceinline__ void row_apply(LBody& A, LBody& B, const float rA[3], const float rB[3], float dl) {
-  SideRow<K> ta, tb;
-  ta.build(A, rA);
-  tb.build(B, rB);
-  ta.apply(A, -dl);
-  tb.apply(B, dl);
-}
-
 // the partner lane's value (lanes 2p and 2p + 1 swap; both must be active)
 __device__ __forceinline__ float pair_swap(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
@@ -956,51 +942,64 @@ __device__ __forceinline__ void row_pair(LBody& S, const float r[3], float& lam,
   t.apply(S, sg * dl);
   lam = nl;
 }
-template <int K>
-__device__ __forceinline__ void row_pair_ku(const LBody& S, const float r[3], float sg, float& k, float& u) {
+// one body's share of the coupling of a point's two tangent rows: (r x e_1) . I^-1 (r x e_2)
+__device__ __forceinline__ float tangent_cross(const SideRow<1>& t1, const SideRow<2>& t2) {
 #pragma clang fp contract(off)
-  SideRow<K> t;
-  t.build(S, r);
-  const float kp = t.kpart(S), vp = t.vpart(S);
-  k = kp + pair_swap(kp);
-  u = sg * (vp - pair_swap(vp));
+  return __builtin_fmaf(t1.c1, t2.i[SideRow<1>::i1], t1.c2 * t2.i[SideRow<1>::i2]);
 }
-template <int K>
-__device__ __forceinline__ void row_pair_apply(LBody& S, const float r[3], float sg, float dl) {
-  SideRow<K> t;
-  t.build(S, r);
-  t.apply(S, sg * dl);
+
+// the larger eigenvalue of the tangent block [[k1, k12], [k12, k2]]: a step 1 / kt along the slip
+// overshoots in no direction of the pair
+__device__ __forceinline__ float tangent_block_max(float k1, float k2, float k12) {
+#pragma clang fp contract(off)
+  const float h = 0.5f * (k1 - k2);
+  return 0.5f * (k1 + k2) + __builtin_sqrtf(__builtin_fmaf(h, h, k12 * k12));
 }
 
 // the tangent pair of one point on the disc: both rows from the same velocities and with one
-// inverse effective mass (the larger of the two, so that the update points against the slip
-// velocity), the pair of unclipped impulses projected, then both applied
+// inverse effective mass (the larger eigenvalue of the pair's block, so that the update points
+// against the slip velocity), the pair of unclipped impulses projected, then both applied
 __device__ __forceinline__ void cone_pair_single(LBody& A, LBody& B, const float rA[3], const float rB[3], float lam[3],
                                                  float bound) {
 #pragma clang fp contract(off)
-  float k1, u1, k2, u2;
-  row_ku<1>(A, B, rA, rB, k1, u1);
-  row_ku<2>(A, B, rA, rB, k2, u2);
-  const float rk = __builtin_amdgcn_rcpf(fmaxf(k1, k2));
+  SideRow<1> a1, b1;
+  SideRow<2> a2, b2;
+  a1.build(A, rA);
+  b1.build(B, rB);
+  a2.build(A, rA);
+  b2.build(B, rB);
+  const float k1 = a1.kpart(A) + b1.kpart(B), u1 = b1.vpart(B) - a1.vpart(A);
+  const float k2 = a2.kpart(A) + b2.kpart(B), u2 = b2.vpart(B) - a2.vpart(A);
+  const float k12 = tangent_cross(a1, a2) + tangent_cross(b1, b2);
+  const float rk = __builtin_amdgcn_rcpf(tangent_block_max(k1, k2, k12));
   float l1 = __builtin_fmaf(-u1, rk, lam[1]);
   float l2 = __builtin_fmaf(-u2, rk, lam[2]);
   disc_project(l1, l2, bound);
-  row_apply<1>(A, B, rA, rB, l1 - lam[1]);
-  row_apply<2>(A, B, rA, rB, l2 - lam[2]);
+  const float d1 = l1 - lam[1], d2 = l2 - lam[2];
+  a1.apply(A, -d1);
+  b1.apply(B, d1);
+  a2.apply(A, -d2);
+  b2.apply(B, d2);
   lam[1] = l1;
   lam[2] = l2;
 }
 __device__ __forceinline__ void cone_pair_lanes(LBody& S, const float r[3], float lam[3], float bound, float sg) {
 #pragma clang fp contract(off)
-  float k1, u1, k2, u2;
-  row_pair_ku<1>(S, r, sg, k1, u1);
-  row_pair_ku<2>(S, r, sg, k2, u2);
-  const float rk = __builtin_amdgcn_rcpf(fmaxf(k1, k2));
+  SideRow<1> t1;
+  SideRow<2> t2;
+  t1.build(S, r);
+  t2.build(S, r);
+  const float kp1 = t1.kpart(S), vp1 = t1.vpart(S), kp2 = t2.kpart(S), vp2 = t2.vpart(S);
+  const float kx = tangent_cross(t1, t2);
+  const float k1 = kp1 + pair_swap(kp1), u1 = sg * (vp1 - pair_swap(vp1));
+  const float k2 = kp2 + pair_swap(kp2), u2 = sg * (vp2 - pair_swap(vp2));
+  const float k12 = kx + pair_swap(kx);
+  const float rk = __builtin_amdgcn_rcpf(tangent_block_max(k1, k2, k12));
   float l1 = __builtin_fmaf(-u1, rk, lam[1]);
   float l2 = __builtin_fmaf(-u2, rk, lam[2]);
   disc_project(l1, l2, bound);
-  row_pair_apply<1>(S, r, sg, l1 - lam[1]);
-  row_pair_apply<2>(S, r, sg, l2 - lam[2]);
+  t1.apply(S, sg * (l1 - lam[1]));
+  t2.apply(S, sg * (l2 - lam[2]));
   lam[1] = l1;
   lam[2] = l2;
 }
@@ -1177,6 +1176,123 @@ __device__ __forceinline__ void pgs_sweeps(const Lds& L, int sweeps, int ncol, i
   else pgs_sweeps_impl<false>(L, sweeps, ncol, tid, nthr, o);
 }
 
+// One row of a visit by a lane pair from the cached share of the row (r x e_K, I^-1 (r x e_K) in
+// t, the reciprocal rk of the pair's k): what row_pair computes, with the terms that do not change
+// during the sweeps taken from registers.
+template <int K>
+__device__ __forceinline__ void row_pair_cached(LBody& S, const SideRow<K>& t, float rk, float& lam, float bound,
+                                                const SolveOpts& o, float target, float sg) {
+#pragma clang fp contract(off)
+  const float vp = t.vpart(S);
+  const float u = sg * (vp - pair_swap(vp));
+  const float nl = row_lambda_rk<K == 0>(lam, u, rk, bound, o, target);
+  const float dl = nl - lam;
+  t.apply(S, sg * dl);
+  lam = nl;
+}
+
+// The sweeps of a tower stepped by a workgroup of kNthr threads (small batches).  Lane pair
+// p = tid / 2 owns colour-sorted manifold p for the whole solve: its body's share of every row
+// (r x e_K, I^-1 (r x e_K)) and the rows' 1 / k are computed once, by the arithmetic of a visit,
+// and kept in registers, so a visit only reads and writes its body's velocities.  The bits are
+// those of pgs_sweeps (the pair mode, which single lanes match bit for bit).  A tower with more
+// manifolds than lane pairs, or the disc friction variant, takes pgs_sweeps.  Every thread
+// passes the same sweeps x ncol barriers.
+template <int kNthr>
+__device__ __forceinline__ void pgs_sweeps_lat(const Lds& L, int sweeps, int ncol, int tid, const SolveOpts& o) {
+  const int nkept = L.coloff[ncol];
+  if (nkept > kNthr / 2 || o.cone) {
+    pgs_sweeps(L, sweeps, ncol, tid, kNthr, o);
+    return;
+  }
+  const int p = tid >> 1;
+  const bool is_b = (tid & 1) != 0;
+  const bool mine = p < nkept;   // the same for both lanes of a pair
+  SideRow<0> t0[4];
+  SideRow<1> t1[4];
+  SideRow<2> t2[4];
+  float rk[4][3], lam[12], tb[4];
+  Frame F;
+  LBody S;
+  int me = 0, np = 0, col = -1;
+  float mu = 0.f, sg = 0.f;
+  bool ground_me = false;
+  if (mine) {
+    ManPoints d;
+    fetch_points(L, p, d, o.bias);
+    np = d.np;
+    mu = d.mu;
+    const int a_ = (int)(d.ab >> 16), b_ = (int)(d.ab & 0xffffu);
+    make_frame(d.n, F);
+    me = is_b ? b_ : a_;
+    ground_me = is_b && b_ == (int)kGround;
+    load_local_g(L, me, ground_me, F, S);
+    float dAB[3] = {0.f, 0.f, 0.f};
+    if (b_ != (int)kGround) {
+      float dx[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dx[k] = L.x[k * L.nbp + a_] - L.x[k * L.nbp + b_];
+      to_local(F, dx, dAB);
+    }
+    sg = is_b ? 1.f : -1.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float r[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) r[k] = is_b ? d.r[3 * j + k] + dAB[k] : d.r[3 * j + k];
+      t0[j].build(S, r);
+      t1[j].build(S, r);
+      t2[j].build(S, r);
+      if (j < np) {
+        const float k0 = t0[j].kpart(S), k1 = t1[j].kpart(S), k2 = t2[j].kpart(S);
+        rk[j][0] = __builtin_amdgcn_rcpf(k0 + pair_swap(k0));
+        rk[j][1] = __builtin_amdgcn_rcpf(k1 + pair_swap(k1));
+        rk[j][2] = __builtin_amdgcn_rcpf(k2 + pair_swap(k2));
+      } else {
+        rk[j][0] = rk[j][1] = rk[j][2] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) lam[k] = d.l[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tb[k] = d.tb[k];
+    col = 0;
+    while (L.coloff[col + 1] <= p) ++col;
+  }
+  for (int it = 0; it < sweeps; ++it) {
+    for (int c = 0; c < ncol; ++c) {
+      if (mine && c == col) {
+        // the body's velocities in the frame, as load_local_g reads them
+        float v[3] = {0.f, 0.f, 0.f}, w[3] = {0.f, 0.f, 0.f};
+        if (!ground_me) {
+          load3(L.v, L.nbp, me, v);
+          load3(L.w, L.nbp, me, w);
+        }
+        to_local(F, v, S.v);
+        to_local(F, w, S.w);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { S.v0[k] = S.v[k]; S.w0[k] = S.w[k]; }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j < np) {
+            row_pair_cached<0>(S, t0[j], rk[j][0], lam[3 * j], 0.f, o, tb[j], sg);
+            const float bound = mu * lam[3 * j];
+            row_pair_cached<1>(S, t1[j], rk[j][1], lam[3 * j + 1], bound, o, 0.f, sg);
+            row_pair_cached<2>(S, t2[j], rk[j][2], lam[3 * j + 2], bound, o, 0.f, sg);
+          }
+        }
+        store_local(L, me, F, S);
+      }
+      __syncthreads();
+    }
+  }
+  if (mine && !is_b) {
+    float4* rec = reinterpret_cast<float4*>(mdev(L, p));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rec[3 + c] = make_float4(lam[4 * c], lam[4 * c + 1], lam[4 * c + 2], lam[4 * c + 3]);
+  }
+}
+
 __device__ __forceinline__ void warm_apply_manifold(const Lds& L, int m) {
   int a, b;
   Frame F;
@@ -1241,7 +1357,12 @@ __device__ __forceinline__ void residual_rec(const Lds& L, const float* rec, con
     RowTerms<2> t2;
     t1.build(A, B, rA, rB);
     t2.build(A, B, rA, rB);
-    const float kt = fmaxf(t1.k, t2.k);
+    // disc friction: one inverse effective mass, the larger eigenvalue of the tangent block
+    const float kt = o.cone ? tangent_block_max(
+                                  t1.k, t2.k,
+                                  (t1.a1 * t2.iA[RowTerms<1>::i1] + t1.a2 * t2.iA[RowTerms<1>::i2]) +
+                                      (t1.b1 * t2.iB[RowTerms<1>::i1] + t1.b2 * t2.iB[RowTerms<1>::i2]))
+                            : 0.f;
     const float k1 = o.cone ? kt : t1.k, k2 = o.cone ? kt : t2.k;
     float cl1 = lam[1] - t1.vrel(A, B) * __builtin_amdgcn_rcpf(k1);
     float cl2 = lam[2] - t2.vrel(A, B) * __builtin_amdgcn_rcpf(k2);
@@ -2023,8 +2144,10 @@ __device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, i
 // it where an island's work is wide (the broadphase walk, the manifolds, the sweeps, the residual
 // terms).  The plain variant runs kIslandWaves waves; the one with the network's registers (one
 // wave per SIMD) runs four, one per SIMD of the compute unit.
-template <bool kLearned, bool kGlobal>
-constexpr int step_threads() { return kGlobal ? (kLearned ? kLearnedIslandWaves : kIslandWaves) * kWave : kWave; }
+template <bool kLearned, bool kGlobal, bool kLat = false>
+constexpr int step_threads() {
+  return kGlobal ? (kLearned ? kLearnedIslandWaves : kIslandWaves) * kWave : (kLat ? kLatencyWaves * kWave : kWave);
+}
 
 // The plain variants are held to two waves per SIMD (at most 256 registers): occupancy is what
 // hides the latency of the pack's serial phases, and a register count that drifts above 256
@@ -2034,21 +2157,25 @@ constexpr int step_threads() { return kGlobal ? (kLearned ? kLearnedIslandWaves 
 // either compiles to flat instructions, which are as slow as device memory even on LDS).
 // kExt: the solver variants (disc friction, restitution targets, reference-face clipping) and the
 // episode criteria are compiled in; the default plain kernel carries none of their registers.
-template <bool kLearned, bool kGlobal, bool kHot, bool kExt>
-__global__ void __launch_bounds__((step_threads<kLearned, kGlobal>()))
+// kLat (small batches): one tower per workgroup of kLatencyWaves waves; the first wave steps it as
+// a pack, the others join it in building the manifolds, in the sweeps (register-resident lane
+// pairs, pgs_sweeps_lat) and in the residual terms.
+template <bool kLearned, bool kGlobal, bool kHot, bool kExt, bool kLat = false>
+__global__ void __launch_bounds__((step_threads<kLearned, kGlobal, kLat>()))
 __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
-  constexpr int kThreads = step_threads<kLearned, kGlobal>();
+  constexpr int kThreads = step_threads<kLearned, kGlobal, kLat>();
   extern __shared__ __align__(16) float smem[];
   float* const dev = a.gmem + a.pack_goff[a.pack_first + blockIdx.x];
   const Lds L = carve(kGlobal ? dev + (kManDevWords + kManBiasWords) * a.pc : smem, dev, smem, kGlobal, kGlobal && kHot, a);
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   if constexpr (kThreads > kWave) {
     if (threadIdx.x >= kWave) {
-      // helper waves: per substep they join the first wave in the broadphase walk, in building
-      // the manifolds, in the sweeps and in the residual terms, each between a barrier where it
-      // enters and one where it leaves (the same barriers, in the same order, as the first wave's)
-      // (with the learned warm start they share the network's chunks too; the sweeps after it
-      // are mlp_iters, and its own residual and fallback stay with the first wave)
+      // helper waves: per substep they join the first wave in the broadphase walk (islands in
+      // device memory), in building the manifolds, in the sweeps and in the residual terms, each
+      // between a barrier where it enters and one where it leaves (the same barriers, in the
+      // same order, as the first wave's) (with the learned warm start they share the network's
+      // chunks too; the sweeps after it are mlp_iters, and its own residual and fallback stay
+      // with the first wave)
       const int pkh = a.pack_first + blockIdx.x;
       const int nbh = a.pack_body0[pkh + 1] - a.pack_body0[pkh];
       const bool learned_h = kLearned && a.warm_start == 2;
@@ -2057,9 +2184,11 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       const SolveOpts opts_h = {a.restitution, kExt && a.friction_cone != 0, kExt && a.restitution_bias != 0};
       for (int s = 0; s < a.n_steps; ++s)
         for (int sub = 0; sub < a.n_sub; ++sub) {
-          __syncthreads();
-          island_walk_rounds(L, a.margin, nbh, threadIdx.x / kWave, kThreads / kWave, threadIdx.x % kWave);
-          __syncthreads();
+          if constexpr (kGlobal) {
+            __syncthreads();
+            island_walk_rounds(L, a.margin, nbh, threadIdx.x / kWave, kThreads / kWave, threadIdx.x % kWave);
+            __syncthreads();
+          }
           __syncthreads();
           build_manifolds<kExt>(L, a, threadIdx.x, kThreads, L.scal[5], keep_prev);
           __syncthreads();
@@ -2074,7 +2203,8 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
             }
           }
           __syncthreads();
-          pgs_sweeps(L, learned_h ? a.mlp_iters : a.iters, L.scal[2], threadIdx.x, kThreads, opts_h);
+          if constexpr (kLat) pgs_sweeps_lat<kThreads>(L, a.iters, L.scal[2], threadIdx.x, opts_h);
+          else pgs_sweeps(L, learned_h ? a.mlp_iters : a.iters, L.scal[2], threadIdx.x, kThreads, opts_h);
           __syncthreads();
           if (!learned_h) {
             __syncthreads();
@@ -2632,7 +2762,8 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
         }
       }
       __syncthreads();   // the helper waves (if any) enter the sweeps with this wave
-      pgs_sweeps(L, sweeps, ncol, threadIdx.x, kThreads, opts);
+      if constexpr (kLat) pgs_sweeps_lat<kThreads>(L, sweeps, ncol, threadIdx.x, opts);
+      else pgs_sweeps(L, sweeps, ncol, threadIdx.x, kThreads, opts);
       __syncthreads();
       timer.mark(L, lane, 5);
 
@@ -3720,12 +3851,14 @@ int ensure_lds_limit() {
   if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
   std::lock_guard<std::mutex> lock(attr_mutex);
   if (!attr_set[dev]) {
-    const void* variants[9] = {
+    const void* variants[11] = {
         (const void*)step_kernel<false, false, false, false>, (const void*)step_kernel<false, false, false, true>,
         (const void*)step_kernel<true, false, false, true>,   (const void*)step_kernel<false, true, false, false>,
         (const void*)step_kernel<false, true, false, true>,   (const void*)step_kernel<true, true, false, true>,
         (const void*)step_kernel<false, true, true, false>,   (const void*)step_kernel<false, true, true, true>,
-        (const void*)step_kernel<true, true, true, true>};
+        (const void*)step_kernel<true, true, true, true>,
+        (const void*)step_kernel<false, false, false, false, true>,
+        (const void*)step_kernel<false, false, false, true, true>};
     for (const void* f : variants)
       if (hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))
         return (int)e;
@@ -3752,6 +3885,9 @@ int step_launch_config(const StepArgs& a, const void** func, unsigned* block_thr
       f = learned ? (const void*)step_kernel<true, true, false, true>
                   : (ext ? (const void*)step_kernel<false, true, false, true> : (const void*)step_kernel<false, true, false, false>);
     threads = learned ? step_threads<true, true>() : step_threads<false, true>();
+  } else if (a.lat && !learned) {
+    f = ext ? (const void*)step_kernel<false, false, false, true, true> : (const void*)step_kernel<false, false, false, false, true>;
+    threads = step_threads<false, false, true>();
   } else {
     f = learned ? (const void*)step_kernel<true, false, false, true>
                 : (ext ? (const void*)step_kernel<false, false, false, true> : (const void*)step_kernel<false, false, false, false>);

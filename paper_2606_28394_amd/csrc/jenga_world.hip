@@ -93,6 +93,7 @@ struct jg_world {
     size_t lds = 0;
     bool global = false;     // packs keep their state in device memory (islands too large for LDS)
     bool hot_bodies = false; // global packs: the serial walks' body arrays in LDS
+    bool lat = false;        // one tower per workgroup of four waves (small batches)
     int64_t gwords = 0;      // words of one pack's device region
   };
   std::vector<PackClass> classes;   // launch classes, in pack order
@@ -272,6 +273,7 @@ int32_t build_layout(jg_world* w) {
   // an on-chip pack holds at most kRegBodies bodies (the register broadphase); larger islands
   // are kept in device memory, one tower each
   int target = w->prm.pack_bodies > 0 ? std::min(w->prm.pack_bodies, jg::kRegBodies) : 0;
+  bool lat = false;
   if (target <= 0) {
     const bool wide = w->prm.warm_start == 2 || w->prm.record_features;
     const size_t budget = wide ? 40 * 1024 : 20 * 1024;
@@ -285,6 +287,9 @@ int32_t build_layout(jg_world* w) {
         (int64_t)order.size() <= (int64_t)cus * (wide ? 4 : 8)) {
       target = 1;
       if (!(w->prm.manifolds_per_body > 0.f)) mpb = 6.0f;
+      // at most two towers per CU: each gets a workgroup of four waves (two per CU at two waves
+      // per SIMD), which share its manifolds, sweeps and residual
+      lat = w->prm.small_batch >= 0 && !wide && (int64_t)order.size() <= 2 * (int64_t)cus;
     }
   }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -372,6 +377,7 @@ int32_t build_layout(jg_world* w) {
       c.first = (int)b;
       c.per_cu = per_cu;
       c.global = bins[b].global;
+      c.lat = lat && !bins[b].global;
       w->classes.push_back(c);
     }
     jg_world::PackClass& c = w->classes.back();
@@ -773,6 +779,7 @@ void jg_default_params(jg_params* p) {
   p->mega_bodies = 16384;
   p->colour_partition = 1024;
   p->mega_cand_per_body = 16.f;
+  p->small_batch = 0;
 }
 
 const char* jg_last_error(void) { return g_err.c_str(); }
@@ -1042,6 +1049,7 @@ int32_t jg_step_batch(jg_world* w, int32_t n_steps) {
     cls[k].gmem = w->d_gmem.p;
     cls[k].in_gmem = c.global ? 1 : 0;
     cls[k].hot_bodies = c.hot_bodies ? 1 : 0;
+    cls[k].lat = c.lat ? 1 : 0;
     cls[k].pack_goff = w->d_pack_goff.p;
   }
   if (w->prm.use_graph) {

@@ -44,7 +44,7 @@ class jg_params(C.Structure):
                 ("collapse_theta", C.c_double), ("rest_ek", C.c_double), ("support_eps", C.c_double),
                 ("rest_steps", C.c_int32), ("friction_cone", C.c_int32), ("restitution_bias", C.c_int32),
                 ("manifold_mode", C.c_int32), ("mega_bodies", C.c_int32), ("colour_partition", C.c_int32),
-                ("mega_cand_per_body", C.c_float)]
+                ("mega_cand_per_body", C.c_float), ("small_batch", C.c_int32)]
 
 
 class jg_contact(C.Structure):
@@ -436,6 +436,7 @@ class World:
     def __init__(self, scene: dict, warm_start: int = 0, stream=None, device: int = 0, pack_bodies: int = 0,
                  manifolds_per_body: float = 0.0, params: dict | None = None, mlp=None, mlp_iters: int = 8,
                  fallback_tau: float = 1e30, record_features: bool = False, use_graph: bool = False,
+                 small_batch: int = 0,
                  episode: dict | None = None):
         pr = params or scene["params"]
         p = jg_default_params()
@@ -462,6 +463,7 @@ class World:
         p.fallback_tau = float(fallback_tau)
         p.record_features = int(bool(record_features))
         p.use_graph = int(bool(use_graph))
+        p.small_batch = int(small_batch)
         for k, v in (episode or {}).items():     # collapse_fd, collapse_ek, ..., rest_steps
             setattr(p, k, type(getattr(p, k))(v))
         self.params = p
