@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2606_28394_amd/csrc/jenga_step.hip", "paper_2606_28394_amd/csrc/jenga_device.h"]
+KERNEL_SOURCES = ["paper_2606_28394_amd/csrc/jenga_step.hip", "paper_2606_28394_amd/csrc/jenga_device.h",
+                  "paper_2606_28394_amd/csrc/jenga_world.hip"]   # the kernels and the launch layout
 
 
 def log(*a):

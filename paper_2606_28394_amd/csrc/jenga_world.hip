@@ -406,6 +406,29 @@ int32_t build_layout(jg_world* w) {
     w->mega_of_tower[t] = (int)w->megas.size();
     w->megas.push_back(m);
   }
+  // neighbouring classes whose LDS would fit more workgroups per CU than the kernel's registers
+  // allow run at the same occupancy: one launch holds them all (with the largest pack's LDS, as
+  // long as that still fits the register-bound count), so that they share one launch tail
+  {
+    const int reg_cap = lat ? 2 : ((w->prm.warm_start == 2 || w->prm.record_features) ? 4 : 8);
+    for (size_t k = 1; k < w->classes.size();) {
+      jg_world::PackClass& into = w->classes[k - 1];
+      const jg_world::PackClass& from = w->classes[k];
+      const bool same = !into.global && !from.global && into.lat == from.lat && into.per_cu >= reg_cap &&
+                        from.per_cu >= reg_cap;
+      const int nbp = std::max(into.nbp, from.nbp), tpc = std::max(into.tpc, from.tpc),
+                ppc = std::max(into.ppc, from.ppc);
+      if (same && (int)((160 * 1024) / lds_of(nbp, tpc, ppc)) >= reg_cap) {
+        into.count += from.count;
+        into.nbp = nbp;
+        into.tpc = tpc;
+        into.ppc = ppc;
+        w->classes.erase(w->classes.begin() + (long)k);
+      } else {
+        ++k;
+      }
+    }
+  }
   // at most four classes (the hardware queues a process gets by default): fold the smallest class
   // into its neighbour with the larger LDS (its packs then run at that neighbour's occupancy)
   auto lds_classes = [&]() {
