@@ -2206,7 +2206,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
           if constexpr (kLat) pgs_sweeps_lat<kThreads>(L, a.iters, L.scal[2], threadIdx.x, opts_h);
           else pgs_sweeps(L, learned_h ? a.mlp_iters : a.iters, L.scal[2], threadIdx.x, kThreads, opts_h);
           __syncthreads();
-          if (!learned_h) {
+          if (!learned_h && s == a.n_steps - 1 && sub == a.n_sub - 1) {
             __syncthreads();
             residual_parts(L, L.scal[5], threadIdx.x, kThreads, reinterpret_cast<float*>(L.cab),
                            reinterpret_cast<float*>(L.cpos), nullptr, opts_h);
@@ -2865,8 +2865,9 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       wave_sync();
       timer.mark(L, lane, 6);
 
-      // ---- 8. residual (the learned variant took it before the outputs) ----
-      if (!learned) {
+      // ---- 8. residual of the launch's last solve, the one the outputs report (the learned
+      // variant took it before the outputs, for its fallback) ----
+      if (!learned && last) {
         float* const psum = reinterpret_cast<float*>(L.cab);
         float* const pmax = reinterpret_cast<float*>(L.cpos);
         if constexpr (kThreads > kWave) {
