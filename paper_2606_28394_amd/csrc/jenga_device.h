@@ -49,7 +49,8 @@ struct StepArgs {
   const int64_t* pack_goff;    // [pack] word offset of the pack's region in gmem
   float* gmem;                 // per-pack regions: the contact points' lever arms and impulses
                                // (kManDevWords per manifold slot), their restitution targets
-                               // (kManBiasWords per slot), then, for a pack whose layout
+                               // (kManBiasWords per slot), the narrowphase's normals and
+                               // depths (kManSatWords per slot), then, for a pack whose layout
                                // lives in device memory, the whole layout
   int32_t in_gmem;             // 1: this launch's packs keep their whole layout in gmem
   int32_t hot_bodies;          // in_gmem packs: 1 = the arrays of the serial walks also in LDS
@@ -119,6 +120,9 @@ constexpr int kManDevWords = 28;   // r_A 12, lambda 12, n 3, depth per sorted m
                                    // pack's device region
 constexpr int kManBiasWords = 4;   // restitution targets of a sorted manifold's points (after all
                                    // of the pack's records; used with restitution_bias only)
+constexpr int kManSatWords = 4;    // the narrowphase's normal and depth of a canonical colliding
+                                   // pair (after the targets), reused to build its manifold
+constexpr int kManPackWords = kManDevWords + kManBiasWords + kManSatWords;   // per slot of a pack
 constexpr int kWarmWords = 18;     // sorted -> canonical map + previous step store (17)
 constexpr int kStageWords = 64 * 16 + 64 * 3;   // network input rows of one 64-point chunk (bf16)
 constexpr int kLearnedIslandWaves = 4;          // waves of a pack in device memory with the network

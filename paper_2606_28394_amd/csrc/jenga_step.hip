@@ -90,6 +90,8 @@ struct Lds {
   float* mtb;         // device block after the records: restitution targets, 4 per sorted manifold
   float* md;          // device block, kManDevWords per sorted manifold: r_A [12] (contact frame
                       // (n, t1, t2)), lambda [12], n [3], depth (see mdev)
+  float* msat;        // device block after the targets: the narrowphase's normal [3] and depth of
+                      // canonical colliding pair p at [4 p]
   // warm start: sorted -> canonical, previous step store (canonical order)
   int32_t* mcanon;
   uint32_t *pkey, *pslot;
@@ -147,6 +149,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool u
   L.mab = (uint32_t*)take(pc); L.mmeta = (uint32_t*)take(pc);
   L.md = dev;
   L.mtb = dev + (size_t)kManDevWords * pc;
+  L.msat = dev + (size_t)(kManDevWords + kManBiasWords) * pc;
   if (mode >= 1) {
     L.mcanon = (int32_t*)take(pc);
     L.pkey = (uint32_t*)take(pc); L.pslot = (uint32_t*)take(pc); L.pnrm = take(3 * pc); L.plam = take(12 * pc);
@@ -1586,9 +1589,11 @@ __device__ __forceinline__ void tower_residuals(const Lds& L, int nman, int nt, 
 // contact frame into rec[0..12), the normal (from i to j) and depth; returns the point count and
 // the points' slots (4 bits each).  The ground: Sec. "Narrowphase" reading R18; two boxes: the
 // SAT normal and the silhouette clip (R15, R16), or reference-face clipping (manifold_mode 1).
+// sat: the narrowphase's normal and depth of the pair (n [3], depth), or null to take them again
+// here (both come from sat_boxes on the same inputs)
 template <bool kExt>
 __device__ __forceinline__ int manifold_geometry(const Lds& L, int i, int j, bool ground, int manifold_mode, float* rec,
-                                                 float n[3], float& depth, uint32_t& slots) {
+                                                 float n[3], float& depth, uint32_t& slots, const float* sat) {
   const int NB = L.nbp;
   float t1[3], rA[4][3];
   uint32_t used = 0u;
@@ -1640,7 +1645,13 @@ __device__ __forceinline__ int manifold_geometry(const Lds& L, int i, int j, boo
       used = manifold_refface(R, he, RB, heB, d, n, ax, t1, rA);
       if (!used) used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
     } else {
-      sat_boxes(R, he, RB, heB, d, n, depth);
+      if (sat) {
+        const float4 nd = *reinterpret_cast<const float4*>(sat);
+        n[0] = nd.x; n[1] = nd.y; n[2] = nd.z;
+        depth = nd.w;
+      } else {
+        sat_boxes(R, he, RB, heB, d, n, depth);
+      }
       used = manifold_boxes(R, he, RB, heB, d, n, t1, rA);
     }
 #pragma unroll
@@ -1700,7 +1711,8 @@ __device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a,
     const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
     float n[3], depth;
     uint32_t slots;
-    const int npts = manifold_geometry<kExt>(L, i, j, j == (int)kGround, a.manifold_mode, mdev(L, sidx), n, depth, slots);
+    const int npts = manifold_geometry<kExt>(L, i, j, j == (int)kGround, a.manifold_mode, mdev(L, sidx), n, depth, slots,
+                                             L.msat + 4 * (size_t)p);
     // warm start: previous step's impulses of the same (pair, slot) if the normal barely turned
     int found = -1;
     if (keep_prev && nprev > 0) {
@@ -2104,18 +2116,21 @@ struct PhaseTimer {
 __device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane ? ((~0ull) >> (64 - lane)) : 0ull; }
 
 // SAT on up to 64 ring entries starting at `head`; colliding pairs are appended (in order)
-// to the canonical list.  Returns the new list length.
+// to the canonical list, a box pair's normal and depth beside it (msat), for its manifold.
+// Returns the new list length.
 __device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, int nman, int lane) {
   const int NB = L.nbp;
-  bool hit = false;
+  bool hit = false, ground = true;
   uint32_t code = 0;
+  float n[3] = {0.f, 0.f, 0.f}, depth = 0.f;
   if (lane < count) {
     code = L.ring[(head + lane) & (kRing - 1)];
     const int i = (int)(code >> 16), j = (int)(code & 0xffffu);
-    if (j == (int)kGround) {
+    ground = j == (int)kGround;
+    if (ground) {
       hit = L.x[2 * NB + i] - L.hm[2 * NB + i] < 0.f;
     } else {
-      float RA[9], RB[9], heA[3], heB[3], d[3], n[3], depth;
+      float RA[9], RB[9], heA[3], heB[3], d[3];
       body_R(L, i, RA);
       body_R(L, j, RB);
       load3(L.he, NB, i, heA);
@@ -2128,7 +2143,10 @@ __device__ __forceinline__ int narrow_chunk(const Lds& L, int head, int count, i
   const uint64_t bal = __ballot(hit);
   if (hit) {
     const int idx = nman + __popcll(bal & lane_lt_mask(lane));
-    if (idx < L.pc) L.cab[idx] = code;
+    if (idx < L.pc) {
+      L.cab[idx] = code;
+      if (!ground) *reinterpret_cast<float4*>(L.msat + 4 * (size_t)idx) = make_float4(n[0], n[1], n[2], depth);
+    }
   }
   return nman + __popcll(bal);
 }
@@ -2166,7 +2184,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
   constexpr int kThreads = step_threads<kLearned, kGlobal, kLat>();
   extern __shared__ __align__(16) float smem[];
   float* const dev = a.gmem + a.pack_goff[a.pack_first + blockIdx.x];
-  const Lds L = carve(kGlobal ? dev + (kManDevWords + kManBiasWords) * a.pc : smem, dev, smem, kGlobal, kGlobal && kHot, a);
+  const Lds L = carve(kGlobal ? dev + kManPackWords * a.pc : smem, dev, smem, kGlobal, kGlobal && kHot, a);
   const bool keep_prev = lds_mode(a) >= 1;   // previous-step store kept (warm start or records)
   if constexpr (kThreads > kWave) {
     if (threadIdx.x >= kWave) {
@@ -3658,7 +3676,8 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
           float* rec = a.md + (size_t)slot * kManDevWords;
           float n[3], depth;
           uint32_t slots;
-          const int np = manifold_geometry<true>(L, i, ground ? 0 : j, ground, a.manifold_mode, rec, n, depth, slots);
+          const int np = manifold_geometry<true>(L, i, ground ? 0 : j, ground, a.manifold_mode, rec, n, depth, slots,
+                                                 nullptr);
 #pragma unroll
           for (int k = 0; k < 12; ++k) rec[12 + k] = 0.f;
           if (a.restitution_bias)

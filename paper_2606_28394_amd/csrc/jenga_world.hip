@@ -461,7 +461,7 @@ int32_t build_layout(jg_world* w) {
         return fail(JG_ECAPACITY, "a pack kept in device memory needs " + std::to_string(c.lds) +
                                   " bytes of LDS for its towers and pushes (max 163840)");
       // (with the network, every wave of the island has its own staging rows)
-      c.gwords = ((int64_t)(jg::kManDevWords + jg::kManBiasWords) * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
+      c.gwords = ((int64_t)jg::kManPackWords * c.pc + jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) +
                   (mode == 2 ? (int64_t)(jg::kLearnedIslandWaves - 1) * jg::kStageWords : 0) +
                   jg::window_words(c.nbp) + 2 * (int64_t)jg::kCandPerBody * c.nbp + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
@@ -469,7 +469,7 @@ int32_t build_layout(jg_world* w) {
       c.lds = (size_t)jg::lds_words(c.nbp, c.pc, c.tpc, c.ppc, mode) * 4;
       if (c.lds > 160 * 1024)
         return fail(JG_ECAPACITY, "a launch class needs " + std::to_string(c.lds) + " bytes of LDS (max 163840)");
-      c.gwords = ((int64_t)(jg::kManDevWords + jg::kManBiasWords) * c.pc + 3) & ~(int64_t)3;
+      c.gwords = ((int64_t)jg::kManPackWords * c.pc + 3) & ~(int64_t)3;
       for (int k = 0; k < c.count; ++k) { goff.push_back(gtotal); gtotal += c.gwords; }
     }
     for (int k = 0; k < c.count; ++k) w->pack_slot0.push_back(w->pack_slot0.back() + c.pc);
