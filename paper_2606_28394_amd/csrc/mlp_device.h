@@ -58,28 +58,30 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // layer's result tiles 2kb (j < 4) and 2kb + 1 (j >= 4)
 __host__ __device__ constexpr int kappa(int kb, int g, int j) { return 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3); }
 
-// round to nearest even bfloat16, returned as the raw 16 bits
-__device__ inline uint32_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-__device__ inline uint32_t pack2(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-// GELU x Phi(x) with Phi(x) = erfc(-x / sqrt 2) / 2, erfc from Abramowitz and Stegun 7.1.26
-// (|error| <= 1.5e-7 on erf): erfc(a) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-a^2},
-// t = 1 / (1 + p a), a >= 0.
+// round to nearest even bfloat16, returned as the raw 16 bits: the conversion instruction of
+// gfx950 (v_cvt_pk_bf16_f32), one for two values in pack2
+__device__ inline uint32_t bf16_bits(float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ inline uint32_t pack2(float lo, float hi) {
+  const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// GELU x Phi(x), written as max(x, 0) - |x| Phi(-|x|) (the two agree for either sign of x), with
+// Phi(-s) = erfc(s / sqrt 2) / 2 and erfc from Abramowitz and Stegun 7.1.26 (|error| <= 1.5e-7 on
+// erf): erfc(a) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-a^2}, t = 1 / (1 + p a), a >= 0.  The
+// halving is folded into the coefficients and 1 / sqrt 2 into p and the exponent.
 __device__ inline float gelu(float x) {
-  const float a = fabsf(x) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.f));
-  float poly = fmaf(t, 1.061405429f, -1.453152027f);
-  poly = fmaf(t, poly, 1.421413741f);
-  poly = fmaf(t, poly, -0.284496736f);
-  poly = fmaf(t, poly, 0.254829592f);
-  poly *= t;
-  const float half_erfc = 0.5f * poly * __builtin_amdgcn_exp2f(-1.4426950408889634f * a * a);
-  const float phi = x >= 0.f ? 1.f - half_erfc : half_erfc;
-  return x * phi;
+  const float s = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, s, 1.f));
+  float poly = fmaf(t, 0.5f * 1.061405429f, 0.5f * -1.453152027f);
+  poly = fmaf(t, poly, 0.5f * 1.421413741f);
+  poly = fmaf(t, poly, 0.5f * -0.284496736f);
+  poly = fmaf(t, poly, 0.5f * 0.254829592f);
+  // e^{-s^2 / 2} = 2^{-s^2 log2(e) / 2}
+  const float q = (poly * t) * __builtin_amdgcn_exp2f((-0.72134752044448170f * s) * s);
+  return fmaf(-s, q, fmaxf(x, 0.f));
 }
 
 // dGELU/dx = Phi(x) + x phi(x)
