@@ -68,35 +68,34 @@ __device__ inline uint32_t pack2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, v);
 }
 
-// GELU x Phi(x), written as max(x, 0) - |x| Phi(-|x|) (the two agree for either sign of x), with
-// Phi(-s) = erfc(s / sqrt 2) / 2 and erfc from Abramowitz and Stegun 7.1.26 (|error| <= 1.5e-7 on
-// erf): erfc(a) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-a^2}, t = 1 / (1 + p a), a >= 0.  The
-// halving is folded into the coefficients and 1 / sqrt 2 into p and the exponent.
-__device__ inline float gelu(float x) {
-  const float s = fabsf(x);
+// Phi(-s) = erfc(s / sqrt 2) / 2 for s >= 0, with erfc from Abramowitz and Stegun 7.1.26
+// (|error| <= 1.5e-7 on erf): erfc(a) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-a^2},
+// t = 1 / (1 + p a).  The halving is folded into the coefficients and 1 / sqrt 2 into p and the
+// exponent; e returns e^{-s^2 / 2}.  GELU and its derivative share it.
+__device__ inline float phi_tail(float s, float& e) {
   const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, s, 1.f));
   float poly = fmaf(t, 0.5f * 1.061405429f, 0.5f * -1.453152027f);
   poly = fmaf(t, poly, 0.5f * 1.421413741f);
   poly = fmaf(t, poly, 0.5f * -0.284496736f);
   poly = fmaf(t, poly, 0.5f * 0.254829592f);
-  // e^{-s^2 / 2} = 2^{-s^2 log2(e) / 2}
-  const float q = (poly * t) * __builtin_amdgcn_exp2f((-0.72134752044448170f * s) * s);
+  e = __builtin_amdgcn_exp2f((-0.72134752044448170f * s) * s);   // 2^{-s^2 log2(e) / 2}
+  return (poly * t) * e;
+}
+
+// GELU x Phi(x), written as max(x, 0) - |x| Phi(-|x|) (the two agree for either sign of x)
+__device__ inline float gelu(float x) {
+  const float s = fabsf(x);
+  float e;
+  const float q = phi_tail(s, e);
   return fmaf(-s, q, fmaxf(x, 0.f));
 }
 
-// dGELU/dx = Phi(x) + x phi(x)
+// dGELU/dx = Phi(x) + x phi(x), phi(x) = e^{-x^2 / 2} / sqrt(2 pi)
 __device__ inline float gelu_grad(float x) {
-  const float a = fabsf(x) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.f));
-  float poly = fmaf(t, 1.061405429f, -1.453152027f);
-  poly = fmaf(t, poly, 1.421413741f);
-  poly = fmaf(t, poly, -0.284496736f);
-  poly = fmaf(t, poly, 0.254829592f);
-  poly *= t;
-  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * a * a);
-  const float half_erfc = 0.5f * poly * e;
-  const float phi = x >= 0.f ? 1.f - half_erfc : half_erfc;
-  return phi + x * 0.3989422804014327f * e;
+  float e;
+  const float q = phi_tail(fabsf(x), e);
+  const float phi = x >= 0.f ? 1.f - q : q;
+  return fmaf(x * 0.3989422804014327f, e, phi);
 }
 
 __device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
