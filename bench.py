@@ -337,11 +337,7 @@ def literal_tilt_rate(J, torch, W, steps):
                         f"{steps} steps", "value": v, "kernel_ms": ms, "error_word": int(st.error_word)}
 
 
-def _mean_or_none(xs):
-    return float(sum(xs) / len(xs)) if xs else None
-
-
-def episodes_table(J, torch, W, steps=2000, warm_starts=(1, 0)):
+def episodes_table(J, torch, W, steps=2000, warm_starts=(1, 0), out_dir=None):
     """The 450-episode experiment (Sec. "Effect of the Friction Coefficient", Tab. results) on the
     removal batch: every tower's episode (collapse criterion of Eq. (collapse), rest rule, moves of
     Tab. ziglar) on the GPU over one launch of `steps` steps.  Per friction level: collapsed episodes,
@@ -349,6 +345,7 @@ def episodes_table(J, torch, W, steps=2000, warm_starts=(1, 0)):
     block, the share of torque moves; and the three validation claims (collapses per move type, the
     trend with mu).  Run with the previous-step warm start and with the zero start."""
     import numpy as np
+    from paper_2606_28394_amd import episodes as E
     scene = W.cfg2(0, n_steps=steps)
     T = scene["n_towers"]
     tower = W.tower_of(scene)
@@ -364,24 +361,12 @@ def episodes_table(J, torch, W, steps=2000, warm_starts=(1, 0)):
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
         eps = [_synced(J, world.episode, t) for t in range(T)]
+        records = E.world_records(world, scene)
         world.close()
-        rows = []
+        rows = E.summary(records)   # Tab. results, one row per friction level
+        if out_dir:
+            E.write_json(records, out_dir, tag=f"_{'previous_step' if ws == 1 else 'zero'}_start")
         by_move = {n: [0, 0] for n in W.MOVE_NAMES}      # collapses during a move of this type, moves
-        for mi, mu in enumerate(W.MU_LEVELS):
-            ts = [t for t in range(T) if abs(scene["mu"][t] - mu) < 1e-12]
-            col = [eps[t] for t in ts if eps[t].collapsed]
-            rounds = [eps[t].rounds for t in ts]
-            torque = sum(eps[t].torque_moves for t in ts)
-            rows.append({"mu": mu, "collapsed": len(col), "episodes": len(ts),
-                         "mean_rounds": float(np.mean(rounds)), "removed": int(sum(eps[t].removed for t in ts)),
-                         "F_min_mN": 3 * mu * W.PAPER_BLOCK_MASS * W.G * 1e3,
-                         "F_tau_mN": 4 * mu * W.PAPER_BLOCK_MASS * W.G * 1e3,
-                         "F_min_mN_benchmark_block": 3 * mu * W.BLOCK_MASS * W.G * 1e3,
-                         "torque_move_pct": 100.0 * torque / max(1, sum(rounds)),
-                         "mean_imbalance_mm": _mean_or_none([1e3 * eps[t].imbalance for t in ts
-                                                            if np.isfinite(eps[t].imbalance)]),
-                         "mean_steps_to_rest": _mean_or_none([e.rest_step - e.collapse_step for e in col
-                                                             if e.rest_step >= 0])})
         moves_of = {}                                      # tower -> [(start, move)] of its moves
         for i in range(len(scene["push_body"])):
             mv = int(scene["push_move"][i])
@@ -428,6 +413,8 @@ def main():
     ap.add_argument("--cpu-report", action="store_true",
                     help="also time the oracle single-threaded and on all host threads over samples of "
                          "every workload (a few minutes)")
+    ap.add_argument("--episodes-json", default=None, metavar="DIR",
+                    help="write the episode records and per-friction summaries of the episode leg as JSON")
     ap.add_argument("--no-episodes", action="store_true",
                     help="skip the 450-episode table (collapse criterion and labels on the removal batch)")
     ap.add_argument("--no-extra", action="store_true",
@@ -580,7 +567,7 @@ def main():
         out["standing_towers"] = literal_tilt_rate(J, torch, W, args.steps)
     if not args.no_episodes:
         log("episode table (removal batch) ...")
-        out["episodes"] = episodes_table(J, torch, W)
+        out["episodes"] = episodes_table(J, torch, W, out_dir=args.episodes_json)
     if args.island_steps > 0:
         log("large-island leg (64 x 64 masonry wall) ...")
         out["large_island"] = large_island(J, torch, W, args.island_steps)

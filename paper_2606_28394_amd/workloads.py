@@ -196,7 +196,9 @@ class SceneBuilder:
         self.pushes = []     # (global body, force, start, steps, withdraw)
         self.n_bodies = 0
 
-    def add_tower(self, he, m, pos, quat, mu, linvel=None, angvel=None, active=None):
+    def add_tower(self, he, m, pos, quat, mu, linvel=None, angvel=None, active=None, level=None, slot=None):
+        """level, slot: each block's layer and position in it (a tower built by jenga_tower), kept
+        for the episode labels' map of removed positions; -1 where not given."""
         n = len(m)
         t = dict(he=np.asarray(he, np.float64).reshape(n, 3),
                  m=np.asarray(m, np.float64).reshape(n),
@@ -204,7 +206,9 @@ class SceneBuilder:
                  quat=np.asarray(quat, np.float64).reshape(n, 4),
                  v=np.zeros((n, 3)) if linvel is None else np.asarray(linvel, np.float64).reshape(n, 3),
                  w=np.zeros((n, 3)) if angvel is None else np.asarray(angvel, np.float64).reshape(n, 3),
-                 active=np.ones(n, np.uint8) if active is None else np.asarray(active, np.uint8).reshape(n))
+                 active=np.ones(n, np.uint8) if active is None else np.asarray(active, np.uint8).reshape(n),
+                 level=np.full(n, -1, np.int32) if level is None else np.asarray(level, np.int32).reshape(n),
+                 slot=np.full(n, -1, np.int32) if slot is None else np.asarray(slot, np.int32).reshape(n))
         first = self.n_bodies
         self.towers.append(t)
         self.mu.append(float(mu))
@@ -227,6 +231,7 @@ class SceneBuilder:
             half_extents=cat("he").reshape(-1, 3), mass=cat("m"), pos=cat("pos").reshape(-1, 3),
             quat=cat("quat").reshape(-1, 4), linvel=cat("v").reshape(-1, 3), angvel=cat("w").reshape(-1, 3),
             active=cat("active").astype(np.uint8), mu=np.asarray(self.mu, np.float64),
+            body_level=cat("level").astype(np.int32), body_slot=cat("slot").astype(np.int32),
             push_body=np.array([p[0] for p in self.pushes], np.int32).reshape(K),
             push_force=np.array([p[1] for p in self.pushes], np.float64).reshape(K, 3),
             push_start=np.array([p[2] for p in self.pushes], np.int32).reshape(K),
@@ -252,7 +257,9 @@ def subset(scene, towers) -> dict:
         a, b = int(ptr[t]), int(ptr[t + 1])
         first = sb.add_tower(scene["half_extents"][a:b], scene["mass"][a:b], scene["pos"][a:b],
                              scene["quat"][a:b], scene["mu"][t], scene["linvel"][a:b],
-                             scene["angvel"][a:b], scene["active"][a:b])
+                             scene["angvel"][a:b], scene["active"][a:b],
+                             scene["body_level"][a:b] if "body_level" in scene else None,
+                             scene["body_slot"][a:b] if "body_slot" in scene else None)
         for k in range(a, b):
             remap[k] = first + (k - a)
     for i in range(len(scene["push_body"])):
@@ -290,7 +297,7 @@ def cfg1(seed: int = 0):
     s = int(rng.integers(0, 3))
     active[3 * level + s] = 0
     sb = SceneBuilder(default_params(), n_steps=240)
-    sb.add_tower(he, m, pos, quat, 0.40, active=active)
+    sb.add_tower(he, m, pos, quat, 0.40, active=active, level=lev, slot=slot)
     return sb.build()
 
 
@@ -328,7 +335,7 @@ def cfg2(seed: int = 0, n_per_mu: int = 150, n_steps: int = 2000):
             rng = rng_for(2, seed * 100000 + idx)
             levels = int(rng.integers(12, 25))
             he, m, pos, quat, lev, slot = jenga_tower(levels, rng)
-            first = sb.add_tower(he, m, pos, quat, mu)
+            first = sb.add_tower(he, m, pos, quat, mu, level=lev, slot=slot)
             _tower_push_schedule(rng, levels, mu, first, sb, int(rng.integers(1, 9)))
             idx += 1
     return sb.build()

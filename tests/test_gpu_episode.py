@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+from paper_2606_28394_amd import episodes as E
 from paper_2606_28394_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -143,6 +144,7 @@ def test_removal_episodes_match_oracle(J, oracle, warm_start):
     gw.begin_episodes()
     gw.step(2000)
     ge = [gw.episode(t) for t in range(sc["n_towers"])]
+    grec = E.world_records(gw, sc)
     _say(f"gpu episodes done (warm_start {warm_start})")
     ow = oracle.OracleWorld(sc, warm_start=warm_start)
     ow.begin_episodes()
@@ -156,6 +158,13 @@ def test_removal_episodes_match_oracle(J, oracle, warm_start):
         rounds, torque, o["removed"] = oracle_labels(sc, t, o, ow)
         if bool(g.collapsed) == o["collapsed"] and (not o["collapsed"] or g.collapse_step == o["collapse_step"]):
             assert g.rounds == rounds and g.torque_moves == torque, t
+    # the labels' map of removed positions: one entry per withdrawn block, the same positions as
+    # the oracle's wherever the withdrawn counts agree
+    for t, (g, o) in enumerate(zip(grec, oe)):
+        assert np.array(g["removed_locs"]).sum() == g["num_removed"], t
+        orec = E.episode_record(sc, t, dict(o, rounds=0, torque_moves=0), ow.active)
+        if g["num_removed"] == o["removed"]:
+            assert g["removed_locs"] == orec["removed_locs"], t
     same_rem = sum(g.removed == o["removed"] for g, o in zip(ge, oe))
     _say("withdrawn blocks gpu", sum(g.removed for g in ge), "oracle", sum(o["removed"] for o in oe),
          "same count", same_rem, "/", n)
