@@ -159,8 +159,9 @@ def _run_residuals(J, scene, steps, chunk, **kw):
     return float(np.median(res)), float(res.mean()), st
 
 
-def _run_timed(J, torch, scene, steps, **kw):
-    """One persistent launch of `steps` steps from the initial state; tower-steps/s from HIP events."""
+def _run_timed(J, torch, scene, steps, keep=False, **kw):
+    """One persistent launch of `steps` steps from the initial state; tower-steps/s from HIP events.
+    keep: return the open world with the stats, (world, stats), instead of closing it."""
     stream = torch.cuda.current_stream()
     world = J.World(scene, stream=stream.cuda_stream, **kw)
     world.step(0)
@@ -172,6 +173,8 @@ def _run_timed(J, torch, scene, steps, **kw):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     st = _synced(J, world.stats)
+    if keep:
+        return scene["n_towers"] * steps / (ms * 1e-3), ms, (world, st)
     world.close()
     return scene["n_towers"] * steps / (ms * 1e-3), ms, st
 
@@ -335,6 +338,60 @@ def literal_tilt_rate(J, torch, W, steps):
     log(f"  standing towers: {v:.4g} tower-steps/s")
     return {"workload": f"throughput batch with tilts of U(0, 3 deg): {scene['n_towers']} standing towers, "
                         f"{steps} steps", "value": v, "kernel_ms": ms, "error_word": int(st.error_word)}
+
+
+def variants_ab(J, torch, W, towers=4096, steps=240, episode_steps=2000):
+    """The solver variants against the literal solver (R36-R39):
+    - disc friction;
+    - restitution targets;
+    - reference-face manifolds;
+    - the paper's solver setting (14 sweeps, 3 substeps), on the same towers.
+
+    Each variant runs two workloads:
+    - the first `towers` towers of the throughput batch's recipe falling for `steps` steps: the
+      rate, and the quartiles of each tower's centre-of-mass travel and drop (the collapse
+      distributions);
+    - the removal batch's episodes with the previous-step start: collapsed towers and withdrawn
+      blocks per friction level.
+    """
+    import numpy as np
+    from paper_2606_28394_amd import episodes as E
+    fall = W.tilted_towers(3, towers, seed=31, n_steps=steps)
+    ptr = np.asarray(fall["tower_ptr"])
+    x0 = np.asarray(fall["pos"], np.float64).reshape(-1, 3)
+    removal = W.cfg2(0, n_steps=episode_steps)
+    # (name, solver parameters, world options); reference-face manifolds make collapsing towers
+    # press more pairs together than the default 3.5 slots per body hold
+    variants = (("literal", {}, {}), ("disc_friction", {"friction_cone": 1}, {}),
+                ("restitution_targets", {"restitution_bias": 1}, {}),
+                ("reference_face", {"manifold_mode": 1}, {"manifolds_per_body": 6.0}),
+                ("paper_solver_14x3", {"iters": 14, "n_sub": 3}, {}))
+    rows = []
+    for name, over, kw in variants:
+        sc = dict(fall, params=dict(fall["params"], **over))
+        v, ms, st = _run_timed(J, torch, sc, steps, keep=True, **kw)
+        world, st = st
+        x = _synced(J, world.state)[0]
+        world.close()
+        d = np.stack([x[ptr[t]:ptr[t + 1]].mean(0) - x0[ptr[t]:ptr[t + 1]].mean(0) for t in range(len(ptr) - 1)])
+        travel, drop = np.linalg.norm(d[:, :2], axis=1), -d[:, 2]
+        rs = dict(removal, params=dict(removal["params"], **over))
+        stream = torch.cuda.current_stream()
+        ew = J.World(rs, warm_start=1, stream=stream.cuda_stream, **kw)
+        ew.begin_episodes()
+        ew.step(episode_steps)
+        summ = E.summary(E.world_records(ew, rs))
+        ew.close()
+        row = {"variant": name, "tower_steps_per_s": v, "error_word": int(st.error_word),
+               "travel_quartiles_m": [float(q) for q in np.quantile(travel, [.25, .5, .75])],
+               "drop_quartiles_m": [float(q) for q in np.quantile(drop, [.25, .5, .75])],
+               "episodes_collapsed": [r["collapsed"] for r in summ], "episodes_withdrawn": [r["removed"] for r in summ]}
+        log(f"  {name}: {v:.4g} tower-steps/s, median travel {row['travel_quartiles_m'][1]:.3f} m, median drop "
+            f"{row['drop_quartiles_m'][1]:.3f} m, collapsed {row['episodes_collapsed']}, withdrawn {row['episodes_withdrawn']}")
+        rows.append(row)
+    return {"workload": f"{towers} towers of the throughput batch's recipe falling {steps} steps; the removal batch's "
+                        f"450 episodes ({episode_steps} steps, previous-step start; per mu {list(W.MU_LEVELS)})",
+            "rows": rows}
 
 
 def episodes_table(J, torch, W, steps=2000, warm_starts=(1, 0), out_dir=None):
@@ -565,6 +622,8 @@ def main():
         log("single-tower latency and standing-tower legs ...")
         out["single_tower"] = single_tower_latency(J, torch, W)
         out["standing_towers"] = literal_tilt_rate(J, torch, W, args.steps)
+        log("solver variants A/B ...")
+        out["variants_ab"] = variants_ab(J, torch, W)
     if not args.no_episodes:
         log("episode table (removal batch) ...")
         out["episodes"] = episodes_table(J, torch, W, out_dir=args.episodes_json)
