@@ -141,7 +141,13 @@ typedef struct {
                             it (each lane pair keeping one manifold's row terms in registers for the
                             whole solve) and sum its residual; the results are bit for bit those of
                             one wave per tower; -1: never; default 0 */
+  int32_t precision;     /* arithmetic of the step kernels: JG_FP32 (the only one built; default).
+                            JG_FP64 makes jg_create_world return JG_EINVAL: an FP64 instantiation
+                            would double every kernel's LDS and registers, and is not built */
 } jg_params;
+
+#define JG_FP32 0
+#define JG_FP64 1
 
 /* One contact point of the last solved step. */
 typedef struct {

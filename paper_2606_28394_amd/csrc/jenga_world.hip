@@ -803,6 +803,7 @@ void jg_default_params(jg_params* p) {
   p->colour_partition = 1024;
   p->mega_cand_per_body = 16.f;
   p->small_batch = 0;
+  p->precision = JG_FP32;
 }
 
 const char* jg_last_error(void) { return g_err.c_str(); }
@@ -822,6 +823,8 @@ int32_t jg_create_world(const jg_params* p, int32_t max_towers, int32_t max_bodi
     return fail(JG_EINVAL, "friction_cone, restitution_bias and manifold_mode are 0 or 1");
   if (p->mega_bodies < 0 || p->colour_partition < 1 || !(p->mega_cand_per_body >= 1.f))
     return fail(JG_EINVAL, "mega_bodies >= 0, colour_partition >= 1 and mega_cand_per_body >= 1");
+  if (p->precision == JG_FP64) return fail(JG_EINVAL, "FP64 stepping is not built: the step kernels compute in FP32");
+  if (p->precision != JG_FP32) return fail(JG_EINVAL, "precision is JG_FP32 or JG_FP64");
   jg_world* w = new (std::nothrow) jg_world();
   if (!w) return fail(JG_ENOMEM, "host allocation failed");
   w->prm = *p;

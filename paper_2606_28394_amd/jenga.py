@@ -44,7 +44,7 @@ class jg_params(C.Structure):
                 ("collapse_theta", C.c_double), ("rest_ek", C.c_double), ("support_eps", C.c_double),
                 ("rest_steps", C.c_int32), ("friction_cone", C.c_int32), ("restitution_bias", C.c_int32),
                 ("manifold_mode", C.c_int32), ("mega_bodies", C.c_int32), ("colour_partition", C.c_int32),
-                ("mega_cand_per_body", C.c_float), ("small_batch", C.c_int32)]
+                ("mega_cand_per_body", C.c_float), ("small_batch", C.c_int32), ("precision", C.c_int32)]
 
 
 class jg_contact(C.Structure):
@@ -69,6 +69,7 @@ class jg_episode(C.Structure):
 
 
 JG_MOVE_NONE, JG_MOVE_CENTER_X, JG_MOVE_SIDE_Y, JG_MOVE_SIDE_X = -1, 0, 1, 2
+JG_FP32, JG_FP64 = 0, 1
 
 CONTACT_DTYPE = np.dtype([("tower", np.int32), ("body_a", np.int32), ("body_b", np.int32), ("slot", np.int32),
                           ("colour", np.int32), ("order", np.int32), ("point", np.float32, 3),

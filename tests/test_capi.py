@@ -72,6 +72,19 @@ def test_default_params(lib):
     assert abs(p.restitution - 0.10) < 1e-15 and abs(p.beta - 0.35) < 1e-15
     assert abs(p.slop - 4e-4) < 1e-15 and abs(p.margin - 2e-3) < 1e-15
     assert tuple(p.gravity) == (0.0, 0.0, -9.81)
+    assert p.precision == 0   # JG_FP32
+
+
+def test_fp64_precision_is_rejected(lib):
+    """Only FP32 step kernels are built: asking for FP64 fails before any device call."""
+    from paper_2606_28394_amd import jenga as J
+    for prec in (1, 7):
+        p = J.jg_default_params()
+        p.precision = prec
+        with pytest.raises(J.JengaError) as e:
+            J.jg_create_world(p, 1, 8)
+        assert e.value.code == J.JG_EINVAL
+        assert ("not built" in str(e.value)) == (prec == 1)
 
 
 def test_calls_without_gpu_fail_cleanly(lib):
