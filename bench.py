@@ -581,7 +581,7 @@ def main():
         "config": {"workload": workload, "towers": T, "bodies": int(scene["tower_ptr"][-1]),
                    "pgs_iters": 20, "dt": 1 / 240, "warm_start": "previous step" if args.warm_start else "zero",
                    "launch": "one persistent launch of all steps, one 64-lane workgroup per pack of towers, "
-                             "packs in four launch classes side by side",
+                             "packs grouped by workgroups per CU into launch classes that run side by side",
                    "pack_bodies": pack_bodies if pack_bodies else "library default",
                    "pack_tuning": None if tuned is None else
                    {"tower_steps_per_s": tuned["tower_steps_per_s"], "steps": tuned["steps"],
