@@ -5,7 +5,10 @@ Tolerances (one step, FP32 GPU against FP64 oracle):
   quaternions  |dq| <= 1e-5
   velocities   |dv| <= 1e-4 * max(|v|, g dt)        angular: 1e-4 * max(|w|, 1 rad/s)
   impulses     |dl| <= 1e-4 * max(|l|, m g dt / 4)  (m g dt / 4 = 1.72e-4 N s for the benchmark block;
-                                                    m of the lighter body of the pair in general)
+                                                    m of the lighter body of the pair in general);
+               2e-4 (LAM_TOL_FALLING) for the tilted batches in mid-fall, where the single-precision
+               oracle is already 5e-5 to 1e-4 off its FP64 self after one step
+               (test_oracle_conditioning.py)
   points       |dp| <= 1e-5 * max(|p|, 0.075 m)
   normals      |dn| <= 1e-5 for face and ground normals; <= 1e-3 for an edge-edge (cross) axis,
                whose direction a_i x b_j / |a_i x b_j| amplifies FP32 rounding by 1 / |a_i x b_j|
@@ -20,6 +23,7 @@ import numpy as np
 from oracle import oracle as O
 
 G_DT = 9.81 / 240.0
+LAM_TOL_FALLING = 2e-4
 LAM_FLOOR = 0.016875 * 9.81 / 240.0 / 4.0
 BAND_MASK = O.BAND_SEPARATION | O.BAND_NORMAL | O.BAND_CROSS | O.BAND_CLIP | O.BAND_GROUND | O.BAND_EMPTY
 

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2606_28394_amd import workloads as W
-from parity_util import compare_contacts, compare_state, fmt, gpu_manifolds, oracle_manifolds
+from parity_util import LAM_TOL_FALLING, compare_contacts, compare_state, fmt, gpu_manifolds, oracle_manifolds
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +29,10 @@ def _say(*a):
 RES_TOL = 1e-4
 
 
-def _one_step_compare(J, oracle, scene, states, warm_start=0, n_check_towers=None, label="", pack_bodies=0):
-    """For each oracle state: put it on the GPU, step once on both sides, compare."""
+def _one_step_compare(J, oracle, scene, states, warm_start=0, n_check_towers=None, label="", pack_bodies=0,
+                      lam_tol=1e-4):
+    """For each oracle state: put it on the GPU, step once on both sides, compare (impulses to
+    lam_tol, relative with the m g dt / 4 floor)."""
     ow = oracle.OracleWorld(scene, warm_start=warm_start)
     gw = J.World(scene, warm_start=warm_start, pack_bodies=pack_bodies)
     ptr = scene["tower_ptr"]
@@ -50,7 +52,8 @@ def _one_step_compare(J, oracle, scene, states, warm_start=0, n_check_towers=Non
         st = compare_state(ow, gx, gq, gv, gww)
         worst = 0.0
         for t in towers:
-            rep = compare_contacts(oracle_manifolds(ow, t), gpu_manifolds(gw.contacts(t), int(ptr[t])))
+            rep = compare_contacts(oracle_manifolds(ow, t), gpu_manifolds(gw.contacts(t), int(ptr[t])),
+                                   lam_tol=lam_tol)
             reports.append((t, rep))
             assert rep["ok"], f"{label} tower {t}: {fmt(rep)}"
             # the residual of the solve (natural map of every PGS row, RMS and max over rows)
@@ -107,9 +110,12 @@ def test_cfg1_tower_one_step_parity_along_trajectory(J, oracle):
 
 
 def test_tilted_batch_one_step_parity(J, oracle):
+    """Towers of up to 40 levels in mid-fall: the impulses are held to 2e-4, twice the bound on the
+    single-precision oracle's spread against its FP64 self on this batch (pinned on the CPU by
+    test_falling_impulse_spread_is_fp32_arithmetic)."""
     sc = W.tilted_towers(31, 24, levels_range=(8, 40))
     states = _trajectory_states(oracle, sc, [0, 60, 150])
-    _one_step_compare(J, oracle, sc, states, label="tilted")
+    _one_step_compare(J, oracle, sc, states, label="tilted", lam_tol=LAM_TOL_FALLING)
 
 
 def test_substeps_one_step_parity(J, oracle):

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2606_28394_amd import workloads as W
-from parity_util import compare_contacts, compare_state, fmt, gpu_manifolds, oracle_manifolds
+from parity_util import LAM_TOL_FALLING, compare_contacts, compare_state, fmt, gpu_manifolds, oracle_manifolds
 
 pytestmark = pytest.mark.gpu
 
@@ -61,8 +61,9 @@ LAM_TOL_REFFACE = 1e-3
 POINT_TOL_REFFACE = 5e-5
 
 
-def _one_step(J, oracle, sc, steps, label, masses=None):
-    """For each oracle state along the trajectory: set it on both sides, one step, compare."""
+def _one_step(J, oracle, sc, steps, label, masses=None, lam_tol=1e-4):
+    """For each oracle state along the trajectory: set it on both sides, one step, compare
+    (impulses to lam_tol with silhouette manifolds)."""
     ow_traj = oracle.OracleWorld(sc)
     states, done = [], 0
     for s in steps:
@@ -74,7 +75,7 @@ def _one_step(J, oracle, sc, steps, label, masses=None):
     gw = J.World(sc)
     ptr = sc["tower_ptr"]
     refface = sc["params"].get("manifold_mode", 0) != 0
-    lam_tol, point_tol = (LAM_TOL_REFFACE, POINT_TOL_REFFACE) if refface else (1e-4, 1e-5)
+    lam_tol, point_tol = (LAM_TOL_REFFACE, POINT_TOL_REFFACE) if refface else (lam_tol, 1e-5)
     for k, S in enumerate(states):
         ow.set_state(*S)
         gw.set_state(*S)
@@ -102,8 +103,11 @@ VARIANTS = {
 
 @pytest.mark.parametrize("name", list(VARIANTS))
 def test_variant_one_step_parity(J, oracle, name):
+    """Falling tilted towers: impulses to 2e-4 with silhouette manifolds, twice the bound on the
+    single-precision oracle's own spread on these states (5e-5 to 1e-4 at step 60, pinned on the
+    CPU by test_falling_impulse_spread_is_fp32_arithmetic)."""
     sc = _with(W.tilted_towers(44, 10, levels_range=(8, 24)), **VARIANTS[name])
-    _one_step(J, oracle, sc, [0, 60, 150], name)
+    _one_step(J, oracle, sc, [0, 60, 150], name, lam_tol=LAM_TOL_FALLING)
 
 
 def test_paper_preset_one_step_parity(J, oracle):
