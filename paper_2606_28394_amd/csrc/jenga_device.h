@@ -112,7 +112,7 @@ struct StepArgs {
   int32_t ppc;     // push rows per pack
 };
 
-constexpr int kBodyWords = 31;     // x3 q4 v3 w3 he3 invm invI3 flag tower Iw6 aabb/mask3
+constexpr int kBodyWords = 28;     // x3 q4 v3 w3 he3 invm flag tower Iw6 aabb/mask3
 constexpr int kTowerWords = 14;    // body range, mu, counters4, residual2, canonical range2, points, frozen
 constexpr int kPushWords = 10;
 constexpr int kManWords = 4;       // canonical (code, pos) + sorted (code, meta)
@@ -192,7 +192,7 @@ int32_t set_error(int32_t code, const std::string& msg);
 // (push_body holds internal indices).  Scratch arrays are sized by the host from nb and cand_cap.
 // ------------------------------------------------------------------------------------------------
 constexpr int kMegaThreads = 256;
-constexpr int kMegaBodyWords = 29;   // x3 q4 v3 w3 he3 invm invI3 Iw6 hm3 (SoA, stride nb)
+constexpr int kMegaBodyWords = 26;   // x3 q4 v3 w3 he3 invm Iw6 hm3 (SoA, stride nb)
 constexpr int kMegaBodyU32 = 8;      // flag, tower (0), colour mask lo, hi, cell, candidate count,
                                      // candidate offset, cell-sorted body (stride nb)
 constexpr int kMegaScal = 256;       // scalar words (counters, colour tables)

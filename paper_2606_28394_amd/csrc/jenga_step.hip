@@ -63,7 +63,7 @@ constexpr uint32_t kErrCand = 1u, kErrMan = 2u, kErrCol = 4u, kErrNan = 8u;
 
 struct Lds {
   // bodies [comp * nbp + i]
-  float *x, *q, *v, *w, *he, *invm, *invI, *Iw;
+  float *x, *q, *v, *w, *he, *invm, *Iw;
   float* hm;          // AABB half sizes during the broadphase, then colour masks (2 words)
   uint32_t* flag;
   int32_t* tw;
@@ -133,7 +133,7 @@ __device__ __forceinline__ Lds carve(float* base, float* dev, float* hot, bool u
   // an island's other waves stage their network rows right after the first wave's
   if (use_hot && mode == 2) take((kLearnedIslandWaves - 1) * kStageWords);
   L.x = take(3 * nb); L.q = take(4 * nb); L.v = take(3 * nb); L.w = take(3 * nb);
-  L.he = take(3 * nb); L.invm = take(nb); L.invI = take(3 * nb);
+  L.he = take(3 * nb); L.invm = take(nb);
   L.flag = (uint32_t*)take(nb); L.tw = (int32_t*)take(nb);
   L.Iw = take(6 * nb); L.hm = take(3 * nb);
   L.tb0 = (int32_t*)take(nt); L.tb1 = (int32_t*)take(nt); L.mu = take(nt);
@@ -761,6 +761,19 @@ __device__ __forceinline__ void store_local(const Lds& L, int i, const Frame& F,
   for (int k = 0; k < 3; ++k) { v[k] += gv[k]; w[k] += gw[k]; }
   store3(L.v, L.nbp, i, v);
   store3(L.w, L.nbp, i, w);
+}
+
+// The inverse body-frame inertia of box i of mass m (as given), Eq. (inertia) with l, w, h the
+// full sizes (2 h_k): 1 / (m (w^2 + h^2) / 12) about the length axis and likewise about the
+// others; zero for a body without mass.  Taken where it is needed (the mass from device memory),
+// so the pack holds no copy of it.
+__device__ __forceinline__ void inv_body_inertia(const Lds& L, int i, float m, float o[3]) {
+  const int NB = L.nbp;
+  const float l = 2.f * L.he[i], wd = 2.f * L.he[NB + i], hh = 2.f * L.he[2 * NB + i];
+  const bool dyn = m > 0.f;
+  o[0] = dyn ? 1.f / (m / 12.f * (wd * wd + hh * hh)) : 0.f;
+  o[1] = dyn ? 1.f / (m / 12.f * (l * l + hh * hh)) : 0.f;
+  o[2] = dyn ? 1.f / (m / 12.f * (l * l + wd * wd)) : 0.f;
 }
 
 // the two non-zero components (at i1 < i2) of a x e_K
@@ -1763,14 +1776,14 @@ __device__ __forceinline__ void build_manifolds(const Lds& L, const StepArgs& a,
 // Semi-implicit integration of dynamic body i over dt (Eq. (newton_euler), Eq. (quat_int), R1, R4):
 // x += dt v; q' = normalise(q + dt/2 [0, w] q); w' = I_w(q')^-1 I_w(q) w.  Returns false when the
 // new state is not finite (it is stored all the same).
-__device__ __forceinline__ bool integrate_body(const Lds& L, int i, float dt) {
+__device__ __forceinline__ bool integrate_body(const Lds& L, int i, float m, float dt) {
   const int NB = L.nbp;
   float xv[3], vv[3], wv[3], R[9], Ib[3], iIb[3];
   load3(L.x, NB, i, xv);
   load3(L.v, NB, i, vv);
   load3(L.w, NB, i, wv);
   body_R(L, i, R);
-  load3(L.invI, NB, i, iIb);
+  inv_body_inertia(L, i, m, iIb);
 #pragma unroll
   for (int k = 0; k < 3; ++k) { xv[k] += dt * vv[k]; Ib[k] = 1.f / iIb[k]; }
   // L = R Ib R^T w
@@ -2257,14 +2270,10 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) L.q[k * NB + i] = a.q[k * CAP + g];
-    // inverse mass and inverse body inertia, Eq. (inertia) with l, w, h the full sizes
+    // inverse mass (the inverse body inertia is taken from the mass and the sizes where needed)
     const float m = a.mass[g];
-    const float l = 2.f * a.he[g], wd = 2.f * a.he[CAP + g], hh = 2.f * a.he[2 * CAP + g];
     const bool dyn = m > 0.f;
     L.invm[i] = dyn ? 1.f / m : 0.f;
-    L.invI[i] = dyn ? 1.f / (m / 12.f * (wd * wd + hh * hh)) : 0.f;
-    L.invI[NB + i] = dyn ? 1.f / (m / 12.f * (l * l + hh * hh)) : 0.f;
-    L.invI[2 * NB + i] = dyn ? 1.f / (m / 12.f * (l * l + wd * wd)) : 0.f;
     L.flag[i] = a.flags[g];
     L.tw[i] = a.body_tower[g] - gt0;
     if (!dyn) {
@@ -2383,7 +2392,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
         for (int k = 0; k < 3; ++k)
           L.hm[k * NB + i] = fabsf(R[3 * k]) * he0 + fabsf(R[3 * k + 1]) * he1 + fabsf(R[3 * k + 2]) * he2;
         float d[3];
-        if (moving) load3(L.invI, NB, i, d);
+        if (moving) inv_body_inertia(L, i, a.mass[gb0 + i], d);
         else d[0] = d[1] = d[2] = 0.f;
         // R diag(d) R^T
         L.Iw[i] = R[0] * d[0] * R[0] + R[1] * d[1] * R[1] + R[2] * d[2] * R[2];
@@ -2904,7 +2913,7 @@ __attribute__((amdgpu_waves_per_eu(kLearned ? 1 : 2))) step_kernel(StepArgs a) {
       for (int i = lane; i < nb; i += kWave) {
         const uint32_t f = L.flag[i];
         if ((f & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
-        if (!integrate_body(L, i, dt)) {
+        if (!integrate_body(L, i, a.mass[gb0 + i], dt)) {
           atomicOr((uint32_t*)&L.scal[3], kErrNan);
           atomicOr(&L.tfz[L.tw[i]], 1u);   // frozen from the next substep on
         }
@@ -3040,7 +3049,7 @@ __device__ __forceinline__ Lds view(const MegaArgs& a) {
   const int nb = a.nb;
   float* p = a.body;
   L.x = p; L.q = p + 3 * nb; L.v = p + 7 * nb; L.w = p + 10 * nb; L.he = p + 13 * nb;
-  L.invm = p + 16 * nb; L.invI = p + 17 * nb; L.Iw = p + 20 * nb; L.hm = p + 26 * nb;
+  L.invm = p + 16 * nb; L.Iw = p + 17 * nb; L.hm = p + 23 * nb;
   L.flag = a.ubody;
   L.tw = reinterpret_cast<int32_t*>(a.ubody + nb);
   L.nbp = nb;
@@ -3240,7 +3249,7 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
   const SolveOpts opts = {a.restitution, a.friction_cone != 0, a.restitution_bias != 0};
   const int PS = a.partition;
 
-  // ---- load the island (inverse mass and inertia of Eq. (inertia) with the full sizes) ----
+  // ---- load the island (inverse mass; the inverse inertia is taken where needed) ----
   for (int i = gt; i < NB; i += GS) {
     const int g = a.g0 + i;
 #pragma unroll
@@ -3253,12 +3262,8 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) L.q[k * NB + i] = a.q[k * CAP + g];
     const float m = a.mass[g];
-    const float l = 2.f * a.he[g], wd = 2.f * a.he[CAP + g], hh = 2.f * a.he[2 * CAP + g];
     const bool dyn = m > 0.f;
     L.invm[i] = dyn ? 1.f / m : 0.f;
-    L.invI[i] = dyn ? 1.f / (m / 12.f * (wd * wd + hh * hh)) : 0.f;
-    L.invI[NB + i] = dyn ? 1.f / (m / 12.f * (l * l + hh * hh)) : 0.f;
-    L.invI[2 * NB + i] = dyn ? 1.f / (m / 12.f * (l * l + wd * wd)) : 0.f;
     L.flag[i] = a.flags[g];
     L.tw[i] = 0;
     if (!dyn) {
@@ -3321,7 +3326,7 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
         for (int k = 0; k < 3; ++k)
           L.hm[k * NB + i] = fabsf(R[3 * k]) * he0 + fabsf(R[3 * k + 1]) * he1 + fabsf(R[3 * k + 2]) * he2;
         float d[3];
-        if (moving) load3(L.invI, NB, i, d);
+        if (moving) inv_body_inertia(L, i, a.mass[a.g0 + i], d);
         else d[0] = d[1] = d[2] = 0.f;
         L.Iw[i] = R[0] * d[0] * R[0] + R[1] * d[1] * R[1] + R[2] * d[2] * R[2];
         L.Iw[NB + i] = R[3] * d[0] * R[3] + R[4] * d[1] * R[4] + R[5] * d[2] * R[5];
@@ -3794,7 +3799,7 @@ __global__ void __launch_bounds__(kMegaThreads) mega_kernel(MegaArgs a) {
       // ---- 9. integration ----
       for (int i = gt; i < NB; i += GS) {
         if ((L.flag[i] & (kActive | kDynamic)) != (kActive | kDynamic)) continue;
-        if (!integrate_body(L, i, dt)) {
+        if (!integrate_body(L, i, a.mass[a.g0 + i], dt)) {
           atomicOr(&S[sErr], (int)kErrNan);
           atomicOr(&S[sFrozen], 1);   // frozen from the next substep on
         }
