@@ -37,6 +37,7 @@ def log(*a):
 
 
 DEVICE_ERRORS = []   # device error reports (capacity, non-finite state) met by any leg
+RUN = [""]           # the run the next syncing call belongs to, named in its report
 
 
 def _synced(J, fn, *a):
@@ -46,7 +47,7 @@ def _synced(J, fn, *a):
         return fn(*a)
     except J.JengaError as e:
         if e.code in (J.JG_ECAPACITY, J.JG_ENAN) and e.result is not None:
-            DEVICE_ERRORS.append(str(e))
+            DEVICE_ERRORS.append(f"{RUN[0]}: {e}" if RUN[0] else str(e))
             log(f"  device error report: {e}")
             return e.result
         raise
@@ -141,10 +142,12 @@ def cpu_report(threads=None):
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2606_28394_amd", "data", "warmstart_mlp.npy")
 
 
-def _run_residuals(J, scene, steps, chunk, **kw):
+def _run_residuals(J, scene, steps, chunk, run="", **kw):
     """Step a fresh world `steps` steps in launches of `chunk`; median and mean of the per-tower
-    residual (RMS over rows) at each launch end, and the counters."""
+    residual (RMS over rows) at each launch end, and the counters.  run: names the run in device
+    error reports."""
     import numpy as np
+    RUN[0] = run
     world = J.World(scene, **kw)
     res = []
     done = 0
@@ -159,9 +162,11 @@ def _run_residuals(J, scene, steps, chunk, **kw):
     return float(np.median(res)), float(res.mean()), st
 
 
-def _run_timed(J, torch, scene, steps, keep=False, **kw):
+def _run_timed(J, torch, scene, steps, keep=False, run="", **kw):
     """One persistent launch of `steps` steps from the initial state; tower-steps/s from HIP events.
-    keep: return the open world with the stats, (world, stats), instead of closing it."""
+    keep: return the open world with the stats, (world, stats), instead of closing it.  run: names
+    the run in device error reports."""
+    RUN[0] = run
     stream = torch.cuda.current_stream()
     world = J.World(scene, stream=stream.cuda_stream, **kw)
     world.step(0)
@@ -197,25 +202,29 @@ def equal_residual(J, torch, weights, steps=2000, chunk=50, ks=(1, 2, 4, 8, 12),
         workload = (f"removal batch: {scene['n_towers']} towers, 12-24 levels, 1-8 push removals each, "
                     f"{steps} steps")
     iters = int(scene["params"]["iters"])
-    r20, m20, st20 = _run_residuals(J, scene, steps, chunk)
-    v20, ms20, _ = _run_timed(J, torch, scene, steps)
+    tag = workload.split(":")[0].split(",")[0]
+    r20, m20, st20 = _run_residuals(J, scene, steps, chunk, run=f"{tag}, plain-20")
+    v20, ms20, _ = _run_timed(J, torch, scene, steps, run=f"{tag}, plain-20")
     log(f"plain-20: median residual {r20:.3e} m/s, {v20:.4g} tower-steps/s")
     alone, fallback, prev_rows, ctx = [], [], [], {}
     for k in ks:
         kw = dict(warm_start=2, mlp=net, mlp_iters=k)
-        rk, mk, _ = _run_residuals(J, scene, steps, chunk, fallback_tau=1e30, **kw)
-        vk, msk, _ = _run_timed(J, torch, scene, steps, fallback_tau=1e30, **kw)
+        run = f"{tag}, learned start alone, k={k}"
+        rk, mk, _ = _run_residuals(J, scene, steps, chunk, fallback_tau=1e30, run=run, **kw)
+        vk, msk, _ = _run_timed(J, torch, scene, steps, fallback_tau=1e30, run=run, **kw)
         alone.append(dict(k=k, median_residual=rk, mean_residual=mk, value=vk, kernel_ms=msk))
-        rf, mf, _ = _run_residuals(J, scene, steps, chunk, fallback_tau=r20, **kw)
-        vf, msf, stf = _run_timed(J, torch, scene, steps, fallback_tau=r20, **kw)
+        run = f"{tag}, learned start with fallback, k={k}"
+        rf, mf, _ = _run_residuals(J, scene, steps, chunk, fallback_tau=r20, run=run, **kw)
+        vf, msf, stf = _run_timed(J, torch, scene, steps, fallback_tau=r20, run=run, **kw)
         fallback.append(dict(k=k, median_residual=rf, mean_residual=mf, value=vf, kernel_ms=msf,
                              fallback_rate=stf.fallbacks / (scene["n_towers"] * steps),
                              contact_iters_per_point=stf.contact_iters / max(1, stf.points)))
         p = dict(scene["params"])
         p["iters"] = k
-        ctx[f"zero_k{k}"] = _run_residuals(J, scene, steps, chunk, params=p)[0]
-        rp, mp, _ = _run_residuals(J, scene, steps, chunk, params=p, warm_start=1)
-        vp, msp, _ = _run_timed(J, torch, scene, steps, params=p, warm_start=1)
+        ctx[f"zero_k{k}"] = _run_residuals(J, scene, steps, chunk, params=p, run=f"{tag}, zero start, k={k}")[0]
+        run = f"{tag}, previous-step start, k={k}"
+        rp, mp, _ = _run_residuals(J, scene, steps, chunk, params=p, warm_start=1, run=run)
+        vp, msp, _ = _run_timed(J, torch, scene, steps, params=p, warm_start=1, run=run)
         prev_rows.append(dict(k=k, median_residual=rp, mean_residual=mp, value=vp, kernel_ms=msp))
         log(f"k={k}: learned alone {rk:.3e} ({vk:.4g}/s); with fallback {rf:.3e} "
             f"({100 * fallback[-1]['fallback_rate']:.1f}% fall back, {vf:.4g}/s); previous step {rp:.3e} ({vp:.4g}/s)")
@@ -334,7 +343,7 @@ def literal_tilt_rate(J, torch, W, steps):
     """The throughput batch with tilts of U(0, 3 deg) alone: the towers keep standing (resting
     contacts throughout)."""
     scene = W.cfg3(0, n_steps=steps, literal_tilt=True)
-    v, ms, st = _run_timed(J, torch, scene, steps)
+    v, ms, st = _run_timed(J, torch, scene, steps, run=RUN[0])
     log(f"  standing towers: {v:.4g} tower-steps/s")
     return {"workload": f"throughput batch with tilts of U(0, 3 deg): {scene['n_towers']} standing towers, "
                         f"{steps} steps", "value": v, "kernel_ms": ms, "error_word": int(st.error_word)}
@@ -369,7 +378,7 @@ def variants_ab(J, torch, W, towers=4096, steps=240, episode_steps=2000):
     rows = []
     for name, over, kw in variants:
         sc = dict(fall, params=dict(fall["params"], **over))
-        v, ms, st = _run_timed(J, torch, sc, steps, keep=True, **kw)
+        v, ms, st = _run_timed(J, torch, sc, steps, keep=True, run=RUN[0], **kw)
         world, st = st
         x = _synced(J, world.state)[0]
         world.close()
@@ -620,17 +629,23 @@ def main():
     world.close()
     if not args.no_extra:
         log("single-tower latency and standing-tower legs ...")
+        RUN[0] = "single tower"
         out["single_tower"] = single_tower_latency(J, torch, W)
+        RUN[0] = "standing towers"
         out["standing_towers"] = literal_tilt_rate(J, torch, W, args.steps)
         log("solver variants A/B ...")
+        RUN[0] = "variants A/B"
         out["variants_ab"] = variants_ab(J, torch, W)
     if not args.no_episodes:
         log("episode table (removal batch) ...")
+        RUN[0] = "episodes"
         out["episodes"] = episodes_table(J, torch, W, out_dir=args.episodes_json)
     if args.island_steps > 0:
         log("large-island leg (64 x 64 masonry wall) ...")
+        RUN[0] = "large island"
         out["large_island"] = large_island(J, torch, W, args.island_steps)
         log("grid-wide islands (100,000-stone wall; the 4,096-stone wall on the same path) ...")
+        RUN[0] = "grid-wide islands"
         out["grid_wide_islands"] = grid_wide_islands(J, torch, W)
     if not args.no_learned and os.path.exists(args.learned_weights):
         log("equal-residual leg (learned warm start vs plain-20) ...")
