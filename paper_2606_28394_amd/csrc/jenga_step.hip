@@ -863,12 +863,12 @@ struct SideRow {
   // the body's term of the inverse effective mass, Eq. (keff)
   __device__ __forceinline__ float kpart(const LBody& s) const {
 #pragma clang fp contract(off)
-    return s.im + __builtin_fmaf(c1, i[i1], c2 * i[i2]);
+    return __builtin_fmaf(c1, i[i1], __builtin_fmaf(c2, i[i2], s.im));
   }
   // the velocity of the body's contact point along e_K
   __device__ __forceinline__ float vpart(const LBody& s) const {
 #pragma clang fp contract(off)
-    return s.v[K] + __builtin_fmaf(c1, s.w[i1], c2 * s.w[i2]);
+    return __builtin_fmaf(c1, s.w[i1], __builtin_fmaf(c2, s.w[i2], s.v[K]));
   }
   // impulse sdl along e_K on the body (A takes -dl, B takes +dl)
   __device__ __forceinline__ void apply(LBody& s, float sdl) const {
